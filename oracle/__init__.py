@@ -1,0 +1,216 @@
+"""FP64 CPU oracle for the NNFFT (Algorithm 2.2) and the fast sinc transform
+(Algorithm 6.1) of Kircheis, Potts, Tasche (arXiv 2107.02671).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the CPU-baseline
+leg of the benchmark are the only users.  It shares no code with the GPU
+library and never imports it.
+
+The arithmetic lives in ``oracle.c`` (plain C, IEEE double, OpenMP only for
+parallel loops); this module marshals numpy arrays and holds the closed-form
+error bounds, which are one-line formulas from the paper.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_lib = None
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_long), ("N_star", ctypes.c_long), ("N1", ctypes.c_long),
+                ("G1", ctypes.c_long), ("N2", ctypes.c_long), ("m1", ctypes.c_int),
+                ("m2", ctypes.c_int), ("sigma1", ctypes.c_double), ("sigma2", ctypes.c_double),
+                ("sigma1_eff", ctypes.c_double), ("sigma2_eff", ctypes.c_double),
+                ("a", ctypes.c_double), ("beta1", ctypes.c_double), ("beta2", ctypes.c_double)]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        from . import build as _build
+        path = _build.build(force=False)
+        L = ctypes.CDLL(path)
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.orc_params.argtypes = [ctypes.c_long, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                 ctypes.c_int, ctypes.POINTER(_Params)]
+        L.orc_omega.argtypes = [ctypes.c_double, ctypes.c_double]
+        L.orc_omega.restype = ctypes.c_double
+        L.orc_omega_hat.argtypes = [ctypes.c_double, ctypes.c_double]
+        L.orc_omega_hat.restype = ctypes.c_double
+        L.orc_sinc_pi.argtypes = [ctypes.c_double]
+        L.orc_sinc_pi.restype = ctypes.c_double
+        L.orc_direct.argtypes = [ctypes.c_long, ctypes.c_long, dp, dp, ctypes.c_long, dp, dp]
+        L.orc_sinc_direct.argtypes = [ctypes.c_long, ctypes.c_long, dp, dp, ctypes.c_long, dp, dp]
+        L.orc_nnfft.argtypes = [ctypes.c_long, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                ctypes.c_int, ctypes.c_long, dp, dp, ctypes.c_long, dp, dp, dp, dp]
+        L.orc_gauss_legendre.argtypes = [ctypes.c_long, dp, dp]
+        L.orc_clenshaw_curtis.argtypes = [ctypes.c_long, dp, dp]
+        L.orc_sinc_fast.argtypes = [ctypes.c_long, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                    ctypes.c_int, ctypes.c_int, ctypes.c_long, ctypes.c_long, dp, dp,
+                                    ctypes.c_long, dp, dp]
+        L.orc_num_threads.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _real(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _cplx(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.complex128))
+
+
+@dataclass(frozen=True)
+class Params:
+    N: int
+    N_star: int
+    N1: int
+    G1: int
+    N2: int
+    m1: int
+    m2: int
+    sigma1: float
+    sigma2: float
+    sigma1_eff: float
+    sigma2_eff: float
+    a: float
+    beta1: float
+    beta2: float
+
+
+def params(N, sigma1, sigma2, m1, m2) -> Params:
+    p = _Params()
+    rc = lib().orc_params(int(N), float(sigma1), float(sigma2), int(m1), int(m2), ctypes.byref(p))
+    if rc:
+        raise ValueError(f"invalid NNFFT parameters N={N} sigma=({sigma1},{sigma2}) m=({m1},{m2})")
+    return Params(**{f: getattr(p, f) for f, _ in _Params._fields_})
+
+
+def omega(u, beta) -> np.ndarray:
+    u = np.asarray(u, dtype=np.float64)
+    return np.vectorize(lambda t: lib().orc_omega(float(t), float(beta)), otypes=[float])(u)
+
+
+def omega_hat(v, beta) -> np.ndarray:
+    v = np.asarray(v, dtype=np.float64)
+    return np.vectorize(lambda t: lib().orc_omega_hat(float(t), float(beta)), otypes=[float])(v)
+
+
+def sinc_pi(d) -> np.ndarray:
+    d = np.asarray(d, dtype=np.float64)
+    return np.vectorize(lambda t: lib().orc_sinc_pi(float(t)), otypes=[float])(d)
+
+
+def direct(N, v, f, x) -> np.ndarray:
+    """(1.2): y_j = sum_k f_k exp(-2 pi i N v_k x_j), FP64, compensated sums."""
+    v, x, f = _real(v), _real(x), _cplx(f)
+    y = np.zeros(len(x), dtype=np.complex128)
+    lib().orc_direct(int(N), len(v), _dp(v), _dp(f.view(np.float64)), len(x), _dp(x),
+                     _dp(y.view(np.float64)))
+    return y
+
+
+def nnfft(N, v, f, x, sigma1=2.0, sigma2=2.0, m1=4, m2=4, return_steps=False):
+    """Algorithm 2.2 in FP64 with a direct DFT for step 3.
+
+    return_steps=True also returns g (step 1, length G1, index l + G1/2) and
+    h (step 3, length N2, index s + N2/2)."""
+    v, x, f = _real(v), _real(x), _cplx(f)
+    P = params(N, sigma1, sigma2, m1, m2)
+    y = np.zeros(len(x), dtype=np.complex128)
+    g = np.zeros(P.G1, dtype=np.complex128)
+    h = np.zeros(P.N2, dtype=np.complex128)
+    rc = lib().orc_nnfft(int(N), float(sigma1), float(sigma2), int(m1), int(m2), len(v), _dp(v),
+                         _dp(f.view(np.float64)), len(x), _dp(x), _dp(y.view(np.float64)),
+                         _dp(g.view(np.float64)), _dp(h.view(np.float64)))
+    if rc == 2:
+        raise ValueError("node outside [-1/2, 1/2]")
+    if rc:
+        raise RuntimeError(f"orc_nnfft failed with code {rc}")
+    return (y, g, h) if return_steps else y
+
+
+def sinc_direct(N, a, c, b) -> np.ndarray:
+    """(6.2): h(b_l) = sum_k c_k sinc(N pi (b_l - a_k)); complex output."""
+    a, b, c = _real(a), _real(b), _cplx(c)
+    h = np.zeros(len(b), dtype=np.complex128)
+    lib().orc_sinc_direct(int(N), len(a), _dp(a), _dp(c.view(np.float64)), len(b), _dp(b),
+                          _dp(h.view(np.float64)))
+    return h
+
+
+def gauss_legendre(n):
+    """Gauss-Legendre nodes (decreasing) and halved weights (sum = 1)."""
+    z = np.zeros(n)
+    w = np.zeros(n)
+    if lib().orc_gauss_legendre(int(n), _dp(z), _dp(w)):
+        raise ValueError("n must be >= 1")
+    return z, w
+
+
+def clenshaw_curtis(n):
+    """Chebyshev points z_k = cos(k pi/n), k = 0..n, and the weights of (5.4)."""
+    z = np.zeros(n + 1)
+    w = np.zeros(n + 1)
+    if lib().orc_clenshaw_curtis(int(n), _dp(z), _dp(w)):
+        raise ValueError("n must be >= 1")
+    return z, w
+
+
+QUAD_GAUSS_LEGENDRE = 0
+QUAD_CLENSHAW_CURTIS = 1
+
+
+def sinc_fast(N, a, c, b, nq, quad=QUAD_GAUSS_LEGENDRE, sigma1=2.0, sigma2=2.0, m1=6, m2=6):
+    """Algorithm 6.1 built from two FP64 oracle NNFFTs."""
+    a, b, c = _real(a), _real(b), _cplx(c)
+    h = np.zeros(len(b), dtype=np.complex128)
+    rc = lib().orc_sinc_fast(int(N), float(sigma1), float(sigma2), int(m1), int(m2), int(quad),
+                             int(nq), len(a), _dp(a), _dp(c.view(np.float64)), len(b), _dp(b),
+                             _dp(h.view(np.float64)))
+    if rc:
+        raise RuntimeError(f"orc_sinc_fast failed with code {rc}")
+    return h
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
+
+
+# --------------------------------------------------------------------------
+# Closed-form error bounds (formulas transcribed from the theorems)
+# --------------------------------------------------------------------------
+
+def bound_thm41(N1, m1, m2, sigma1, sigma2) -> float:
+    """E(phi_sinh) of (4.2), Theorem 4.1: bound on E_paper for sinh windows."""
+    t1 = (24 * m1 ** 1.5 + 10) * math.exp(-2 * math.pi * m1 * math.sqrt(1 - 1 / sigma1))
+    t2 = ((24 * m2 ** 1.5 + 10) * (2 * N1 + 4 * m1) / math.sqrt(2 * m1 * math.pi)
+          * math.exp(2 * math.pi * m1 * (1 - math.sqrt(1 - 1 / sigma1) - 1 / (2 * sigma1)))
+          * math.exp(-2 * math.pi * m2 * math.sqrt(1 - 1 / sigma2)))
+    return t1 + t2
+
+
+CC_C = math.pi * (math.e ** 2 - 1) / (2 * math.e)   # C of Theorem 5.3
+
+
+def bound_thm53(N, nu) -> float:
+    """(5.6), Theorem 5.3: Clenshaw-Curtis sinc error bound for n = nu N."""
+    return (36 * (1 + math.exp(-2 * CC_C * N)) / (35 * (math.e ** 2 - 1))
+            * math.exp(-N * (nu - CC_C)))
+
+
+def bound_thm62(eps, E) -> float:
+    """(6.7), Theorem 6.2: fast sinc error factor (eps + 2E + E^2) times sum |c_k|,
+    where E is the NNFFT error constant of Theorem 3.5."""
+    return eps + 2 * E + E * E

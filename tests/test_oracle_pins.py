@@ -1,0 +1,423 @@
+"""Pins for the FP64 CPU oracle, against facts that do not come from the oracle
+itself: closed forms, library routines (numpy FFT, scipy quadrature, scipy
+Bessel functions, scipy Gauss-Legendre), brute force on tiny inputs, the
+error bounds of Theorems 4.1, 5.3 and 6.2, and numbers printed in the paper
+(tests/golden/paper_values.json).
+
+Each test is chosen so that a plausible slip in the oracle (a dropped factor,
+a wrong sign or index, a transposed operand) makes it fail.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.fft
+import scipy.integrate
+import scipy.special
+
+import oracle
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+# Theorem 4.1 slip: the proof's lower bound for I_1 holds with the constant
+# sqrt(x0) e^{-x0} I_1(x0) = 0.3705 at x0 = 4 pi / sqrt 5, not 2/5, so the
+# second term of (4.2) is scaled by 0.4 / 0.3705 = 1.08 when used as a gate.
+THM41_SLIP = 1.08
+
+
+def _rng(seed):
+    return np.random.default_rng(seed)
+
+
+def _cgauss(rng, n):
+    return rng.standard_normal(n) + 1j * rng.standard_normal(n)
+
+
+def _bound(P):
+    return THM41_SLIP * oracle.bound_thm41(P.N1, P.m1, P.m2, P.sigma1_eff, P.sigma2_eff)
+
+
+# --------------------------------------------------------------------------
+# windows
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("beta", [9.42477796, 18.8495559, 28.2743339, 56.5486678])
+def test_omega_closed_form_properties(beta):
+    # Example 2.1: even, support [-1, 1], omega(0) = 1, decreasing on [0, 1]
+    u = np.linspace(0, 1, 2001)
+    w = oracle.omega(u, beta)
+    assert w[0] == pytest.approx(1.0, abs=1e-15)
+    assert w[-1] == 0.0
+    assert np.all(np.diff(w) <= 1e-18)
+    np.testing.assert_array_equal(oracle.omega(-u, beta), w)
+    assert oracle.omega(np.array([1.5, -3.0]), beta).tolist() == [0.0, 0.0]
+    ref = np.sinh(beta * np.sqrt(1 - u[:-1] ** 2)) / np.sinh(beta)
+    np.testing.assert_allclose(w[:-1], ref, rtol=1e-13, atol=1e-300)
+
+
+@pytest.mark.parametrize("beta", [9.42477796, 18.8495559, 28.2743339, 37.6991118, 56.5486678])
+def test_omega_hat_matches_numerical_fourier_integral(beta):
+    # (2.1) against 2 int_0^1 omega(x) cos(2 pi v x) dx by adaptive quadrature,
+    # on both sides of the branch point v = beta / (2 pi).
+    vb = beta / (2 * np.pi)
+    for v in [0.0, 0.13 * vb, 0.5 * vb, 0.9 * vb, vb, 1.3 * vb, 2.1 * vb]:
+        f = lambda x: 2 * np.sinh(beta * np.sqrt(1 - x * x)) / np.sinh(beta) * np.cos(2 * np.pi * v * x)
+        ref, err = scipy.integrate.quad(f, 0, 1, epsabs=1e-15, epsrel=1e-13, limit=400)
+        got = float(oracle.omega_hat(v, beta))
+        scale = float(oracle.omega_hat(0.0, beta))
+        assert abs(got - ref) <= 1e-11 * scale, (v, got, ref)
+
+
+@pytest.mark.parametrize("beta", [9.42477796, 28.2743339, 56.5486678, 75.398])
+def test_omega_hat_matches_scipy_bessel_i1(beta):
+    v = np.linspace(0, 0.99 * beta / (2 * np.pi), 50)
+    z = np.sqrt(beta ** 2 - 4 * np.pi ** 2 * v ** 2)
+    ref = np.pi * beta / np.sinh(beta) * scipy.special.i1(z) / z
+    np.testing.assert_allclose(oracle.omega_hat(v, beta), ref, rtol=5e-14)
+
+
+# --------------------------------------------------------------------------
+# parameter derivation (sizes worked out by hand from the readings)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("N,sigma,m,expect", [
+    # N* = N + ceil(2m/sigma); N1 = 2 ceil(sigma N*/2); G1 = N1 + 2m;
+    # N2 = largest even 2^p 3^q 5^r <= sigma G1.
+    (64, 2.0, 4, (68, 136, 144, 288)),          # 64+4; 136; 144; 288 = 2^5 3^2
+    (4096, 2.0, 6, (4102, 8204, 8216, 16384)),  # 16432 -> 16384 = 2^14
+    (1024, 2.0, 6, (1030, 2060, 2072, 4096)),   # 4144 -> 4096
+    (64, 2.0, 6, (70, 140, 152, 300)),          # 304 -> 300 = 2^2 3 5^2
+    (8192, 2.0, 12, (8204, 16408, 16432, 32768)),
+    (16384, 2.0, 8, (16392, 32784, 32800, 65536)),
+    (1200, 1.25, 6, (1210, 1514, 1526, 1920)),  # N*=1200+ceil(9.6)=1210; 1.25*1210=1512.5 -> 1514
+])
+def test_param_sizes(N, sigma, m, expect):
+    P = oracle.params(N, sigma, sigma, m, m)
+    assert (P.N_star, P.N1, P.G1, P.N2) == expect
+    assert P.a == pytest.approx(P.G1 / P.N1)
+    assert P.beta1 == pytest.approx(2 * math.pi * m * (1 - 1 / (2 * P.N1 / P.N_star)))
+    # Algorithm 2.2 input requirement 2 m2 <= (1 - 1/sigma1) N2
+    assert 2 * m <= (1 - 1 / P.sigma1_eff) * P.N2
+
+
+def test_param_rejects_invalid():
+    for args in [(0, 2, 2, 4, 4), (64, 1.0, 2, 4, 4), (64, 2, 0.9, 4, 4), (64, 2, 2, 1, 4)]:
+        with pytest.raises(ValueError):
+            oracle.params(*args)
+
+
+# --------------------------------------------------------------------------
+# direct sum (1.2)
+# --------------------------------------------------------------------------
+
+def test_direct_single_exponential_closed_form():
+    rng = _rng(11)
+    N = 1000
+    v = rng.uniform(-0.5, 0.5, 37)
+    x = np.concatenate([rng.uniform(-0.5, 0.5, 50), [-0.5, 0.5, 0.0]])
+    for k0 in [0, 17, 36]:
+        f = np.zeros(37, complex)
+        f[k0] = 0.7 - 0.2j
+        y = oracle.direct(N, v, f, x)
+        ref = f[k0] * np.exp(-2j * np.pi * N * v[k0] * x)
+        np.testing.assert_allclose(y, ref, rtol=0, atol=2e-13)
+
+
+def test_direct_equals_numpy_dft_on_equispaced_nodes():
+    # v_k = k/n, x_j = j/n, N = n: exp(-2 pi i N v_k x_j) = exp(-2 pi i k j / n)
+    n = 96
+    lab = np.arange(-n // 2, n // 2)
+    rng = _rng(12)
+    f = _cgauss(rng, n)
+    y = oracle.direct(n, lab / n, f, lab / n)
+    Y = np.fft.fft(np.fft.ifftshift(f))       # index k mod n
+    ref = Y[lab % n]
+    np.testing.assert_allclose(y, ref, rtol=0, atol=1e-11 * np.abs(ref).max())
+
+
+def test_direct_brute_force_tiny():
+    rng = _rng(13)
+    v = rng.uniform(-0.5, 0.5, 5)
+    x = rng.uniform(-0.5, 0.5, 4)
+    f = _cgauss(rng, 5)
+    N = 7
+    ref = [sum(f[k] * complex(math.cos(2 * math.pi * N * v[k] * x[j]),
+                              -math.sin(2 * math.pi * N * v[k] * x[j])) for k in range(5))
+           for j in range(4)]
+    np.testing.assert_allclose(oracle.direct(N, v, f, x), ref, atol=1e-13)
+
+
+# --------------------------------------------------------------------------
+# NNFFT (Algorithm 2.2)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("N,M1,M2,sigma,m", [
+    (64, 256, 256, 2.0, 4),      # the smallest workload: checked against brute force
+    (64, 256, 256, 2.0, 2),
+    (64, 256, 256, 2.0, 6),
+    (100, 333, 301, 1.5, 5),     # odd node counts, sigma1 N* not an integer
+    (200, 500, 400, 1.25, 7),
+    (128, 1000, 777, 2.0, 8),
+])
+def test_nnfft_within_theorem_4_1(N, M1, M2, sigma, m):
+    rng = _rng(N + M1 + m)
+    v = rng.uniform(-0.5, 0.5, M1)
+    x = rng.uniform(-0.5, 0.5, M2)
+    f = _cgauss(rng, M1)
+    P = oracle.params(N, sigma, sigma, m, m)
+    y = oracle.nnfft(N, v, f, x, sigma, sigma, m, m)
+    ex = oracle.direct(N, v, f, x)
+    e_paper = np.abs(y - ex).max() / np.abs(f).sum()
+    assert e_paper <= _bound(P), (e_paper, _bound(P))
+
+
+def test_nnfft_error_decays_exponentially_in_m():
+    rng = _rng(21)
+    N, M = 64, 256
+    v = rng.uniform(-0.5, 0.5, M)
+    x = rng.uniform(-0.5, 0.5, M)
+    f = _cgauss(rng, M)
+    ex = oracle.direct(N, v, f, x)
+    errs = []
+    for m in [2, 3, 4, 5, 6, 7]:
+        y = oracle.nnfft(N, v, f, x, 2.0, 2.0, m, m)
+        errs.append(np.abs(y - ex).max() / np.abs(f).sum())
+    # each step in m gains more than a factor 10 (the bound (4.2) gains
+    # e^{2 pi sqrt(1/2)} ~ 85 per step for sigma = 2)
+    for a, b in zip(errs, errs[1:]):
+        assert b < a / 10, errs
+    assert errs[-1] < 1e-12
+
+
+@pytest.mark.parametrize("v0", [0.0, 0.49, -0.5, 0.5, 0.123456789])
+def test_nnfft_single_exponential(v0):
+    rng = _rng(22)
+    N = 80
+    x = np.concatenate([rng.uniform(-0.5, 0.5, 300), [-0.5, 0.5]])
+    for m in [4, 6]:
+        P = oracle.params(N, 2.0, 2.0, m, m)
+        y = oracle.nnfft(N, np.array([v0]), np.array([1.0 + 0j]), x, 2.0, 2.0, m, m)
+        err = np.abs(y - np.exp(-2j * np.pi * N * v0 * x)).max()
+        assert err <= _bound(P)
+
+
+def test_nnfft_edge_nodes():
+    rng = _rng(23)
+    N = 64
+    v = np.concatenate([[-0.5, 0.5, 0.0], rng.uniform(-0.5, 0.5, 60)])
+    x = np.concatenate([[-0.5, 0.5, 0.0], rng.uniform(-0.5, 0.5, 40)])
+    f = _cgauss(rng, len(v))
+    P = oracle.params(N, 2.0, 2.0, 6, 6)
+    y = oracle.nnfft(N, v, f, x, 2.0, 2.0, 6, 6)
+    ex = oracle.direct(N, v, f, x)
+    assert np.abs(y - ex).max() / np.abs(f).sum() <= _bound(P)
+
+
+def test_nnfft_rejects_nodes_outside_domain():
+    with pytest.raises(ValueError):
+        oracle.nnfft(64, np.array([0.6]), np.array([1 + 0j]), np.array([0.0]))
+    with pytest.raises(ValueError):
+        oracle.nnfft(64, np.array([0.1]), np.array([1 + 0j]), np.array([-0.50001]))
+
+
+def test_nnfft_step3_matches_numpy_fft():
+    # step 3 of the oracle is a direct DFT; compare with numpy's FFT applied to
+    # the deconvolved step-1 output.
+    rng = _rng(24)
+    N, m = 64, 4
+    P = oracle.params(N, 2.0, 2.0, m, m)
+    v = rng.uniform(-0.5, 0.5, 200)
+    f = _cgauss(rng, 200)
+    _, g, h = oracle.nnfft(N, v, f, np.array([0.0]), 2.0, 2.0, m, m, return_steps=True)
+    ell = np.arange(P.G1) - P.G1 // 2
+    phi2 = (P.m2 / P.N2) * oracle.omega_hat(P.m2 * ell / P.N2, P.beta2)
+    X = np.zeros(P.N2, complex)
+    X[ell % P.N2] = g / phi2
+    Y = np.fft.fft(X) / P.N2
+    s = np.arange(P.N2) - P.N2 // 2
+    np.testing.assert_allclose(h, Y[s % P.N2], rtol=0, atol=1e-12 * np.abs(Y).max())
+
+
+def test_nnfft_step1_total_mass():
+    # sum_l phi_1(l/N1 - v) / N1 is a rectangular rule for int phi_1 = phi_1_hat(0)
+    # (Sec. 2, (2.10) at x = 0); so sum_l g_l ~ phi_1_hat(0) sum_k f_k.
+    rng = _rng(25)
+    N, m = 64, 6
+    P = oracle.params(N, 2.0, 2.0, m, m)
+    v = rng.uniform(-0.5, 0.5, 50)
+    f = _cgauss(rng, 50)
+    _, g, _ = oracle.nnfft(N, v, f, np.array([0.0]), 2.0, 2.0, m, m, return_steps=True)
+    phi1_hat0 = (P.m1 / P.N1) * float(oracle.omega_hat(0.0, P.beta1))
+    np.testing.assert_allclose(g.sum(), phi1_hat0 * f.sum(), rtol=1e-8)
+
+
+def test_nnfft_linearity():
+    rng = _rng(26)
+    N = 50
+    v = rng.uniform(-0.5, 0.5, 90)
+    x = rng.uniform(-0.5, 0.5, 70)
+    f1, f2 = _cgauss(rng, 90), _cgauss(rng, 90)
+    a, b = 0.3 - 1.1j, -2.0 + 0.5j
+    lhs = oracle.nnfft(N, v, a * f1 + b * f2, x, 2, 2, 5, 5)
+    rhs = a * oracle.nnfft(N, v, f1, x, 2, 2, 5, 5) + b * oracle.nnfft(N, v, f2, x, 2, 2, 5, 5)
+    np.testing.assert_allclose(lhs, rhs, rtol=0, atol=1e-12 * np.abs(lhs).max())
+
+
+# --------------------------------------------------------------------------
+# quadrature rules
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [1, 2, 5, 64, 2048])
+def test_gauss_legendre_matches_scipy(n):
+    z, w = oracle.gauss_legendre(n)
+    zr, wr = scipy.special.roots_legendre(n)
+    order = np.argsort(-zr)
+    np.testing.assert_allclose(z, zr[order], rtol=0, atol=1e-14)
+    # scipy's weights lose ~1e-7 relative accuracy at the end nodes for large n
+    np.testing.assert_allclose(w, wr[order] / 2, rtol=5e-7, atol=5e-15)
+    assert w.sum() == pytest.approx(1.0, abs=1e-13)
+    # independent recomputation in extended precision: Newton-polish the nodes
+    # with the Legendre recurrence in long double and use W = 2/((1-t^2) P_n'^2)
+    t = z.astype(np.longdouble)
+
+    def legendre(t):
+        p0, p1 = np.ones_like(t), t.copy()
+        for k in range(1, n):
+            p0, p1 = p1, ((2 * k + 1) * t * p1 - k * p0) / (k + 1)
+        return p1, n * (t * p1 - p0) / (t * t - 1)
+
+    if n > 1:
+        for _ in range(3):
+            p, dp = legendre(t)
+            t = t - p / dp
+        p, dp = legendre(t)
+        wl = (1 / ((1 - t * t) * dp * dp)).astype(np.float64)
+        np.testing.assert_allclose(w, wl, rtol=1e-9)
+
+
+def test_gauss_legendre_exact_on_polynomials():
+    n = 9
+    z, w = oracle.gauss_legendre(n)
+    for p in range(2 * n):
+        exact = 0.0 if p % 2 else 1.0 / (p + 1)   # (1/2) int_{-1}^{1} t^p dt
+        assert np.dot(w, z ** p) == pytest.approx(exact, abs=1e-14)
+
+
+def test_clenshaw_curtis_small_and_structure():
+    z, w = oracle.clenshaw_curtis(2)
+    np.testing.assert_allclose(w, [1 / 6, 2 / 3, 1 / 6], atol=1e-15)   # Simpson's rule, halved
+    for n in [2, 3, 4, 8, 64, 1024]:
+        z, w = oracle.clenshaw_curtis(n)
+        assert w.sum() == pytest.approx(1.0, abs=1e-13)                # (5.5)
+        np.testing.assert_array_equal(z, -z[::-1])                       # z_k = -z_{n-k}
+        np.testing.assert_allclose(w, w[::-1], rtol=0, atol=1e-15)       # w_k = w_{n-k}
+        assert np.all(w > 0)
+        np.testing.assert_allclose(z, np.cos(np.arange(n + 1) * np.pi / n), atol=1e-15)
+
+
+@pytest.mark.parametrize("n", [4, 16, 64])
+def test_clenshaw_curtis_exact_on_polynomials(n):
+    z, w = oracle.clenshaw_curtis(n)
+    for p in range(n + 1):
+        exact = 0.0 if p % 2 else 1.0 / (p + 1)
+        assert np.dot(w, z ** p) == pytest.approx(exact, abs=1e-13)
+
+
+@pytest.mark.parametrize("t", [2, 3, 6, 10])
+def test_clenshaw_curtis_weights_match_algorithm_5_4(t):
+    # Algorithm 5.4: the same weights from an orthogonal DCT-I (scipy.fft)
+    n = 2 ** t
+    eps = np.ones(n + 1)
+    eps[0] = eps[n] = math.sqrt(2) / 2
+    a = np.zeros(n + 1)
+    j = np.arange(n // 2 + 1)
+    a[2 * j] = eps[2 * j] * 2.0 / (1.0 - 4.0 * j * j)
+    ahat = scipy.fft.dct(a, type=1, norm="ortho")
+    w54 = eps * ahat / math.sqrt(2 * n)
+    _, w = oracle.clenshaw_curtis(n)
+    np.testing.assert_allclose(w, w54, rtol=0, atol=1e-15)
+
+
+def test_theorem_5_3_printed_values():
+    gold = json.load(open(os.path.join(GOLDEN, "paper_values.json")))
+    c = gold["clenshaw_curtis_C"]
+    assert oracle.CC_C == pytest.approx(c["value"], abs=c["abs_tol"])
+    assert oracle.CC_C == pytest.approx(math.pi * math.sinh(1.0), rel=1e-15)
+    g = gold["cc_eps_1e-8_nu_4_min_N"]
+    nmin = g["value"]
+    assert oracle.bound_thm53(nmin, g["nu"]) < g["eps"] < oracle.bound_thm53(nmin - 1, g["nu"])
+
+
+@pytest.mark.parametrize("N", [16, 64, 200])
+def test_clenshaw_curtis_sinc_error_within_theorem_5_3(N):
+    nu = 4
+    z, w = oracle.clenshaw_curtis(nu * N)
+    x = np.linspace(-1, 1, 4001)
+    approx = (w[None, :] * np.exp(-1j * np.pi * N * np.outer(x, z))).sum(axis=1)
+    err = np.abs(approx - np.sinc(N * x)).max()
+    assert err <= oracle.bound_thm53(N, nu) + 1e-14
+
+
+@pytest.mark.parametrize("N", [64, 256, 1024])
+def test_gauss_legendre_2N_sinc_error(N):
+    # 2N Gauss-Legendre nodes integrate (1/2) e^{-pi i N t x} on [-1, 1] for
+    # |x| <= 1 to better than 1e-11 once N >= 64 (at N = 16 the error is still
+    # ~1e-4: the rule needs n well above pi N / 2 plus a margin that only
+    # becomes small relative to N for larger N).
+    z, w = oracle.gauss_legendre(2 * N)
+    x = np.linspace(-1, 1, 3001)
+    approx = (w[None, :] * np.exp(-1j * np.pi * N * np.outer(x, z))).sum(axis=1)
+    assert np.abs(approx - np.sinc(N * x)).max() < 1e-11
+
+
+# --------------------------------------------------------------------------
+# discrete sinc transform (6.2) and Algorithm 6.1
+# --------------------------------------------------------------------------
+
+def test_sinc_direct_matches_numpy_sinc():
+    rng = _rng(31)
+    N = 128
+    a = rng.uniform(-0.5, 0.5, 70)
+    b = np.concatenate([rng.uniform(-0.5, 0.5, 60), a[:5]])   # include b = a (sinc(0) = 1)
+    c = _cgauss(rng, 70)
+    ref = (np.sinc(N * (b[:, None] - a[None, :])) * c[None, :]).sum(axis=1)
+    np.testing.assert_allclose(oracle.sinc_direct(N, a, c, b), ref, rtol=0, atol=1e-12)
+
+
+def test_sinc_direct_shannon_cardinality():
+    # sinc(N pi (a0 + l/N - a0)) = delta_{l0}
+    N = 64
+    a0 = 0.0123
+    ell = np.arange(-20, 21)
+    b = a0 + ell / N
+    h = oracle.sinc_direct(N, np.array([a0]), np.array([1.0 + 0j]), b)
+    np.testing.assert_allclose(h, (ell == 0).astype(float), atol=1e-13)
+    assert float(oracle.sinc_pi(0.0)) == 1.0
+
+
+@pytest.mark.parametrize("quad,nq_of_N", [(oracle.QUAD_GAUSS_LEGENDRE, lambda N: 2 * N),
+                                          (oracle.QUAD_CLENSHAW_CURTIS, lambda N: 4 * N)])
+def test_sinc_fast_within_theorem_6_2(quad, nq_of_N):
+    rng = _rng(32)
+    N, m = 64, 6
+    L1, L2 = 200, 180
+    a = 0.5 * np.cos(rng.uniform(0, np.pi, L1))     # Chebyshev-distributed nodes
+    b = 0.5 * np.cos(rng.uniform(0, np.pi, L2))
+    c = rng.standard_normal(L1) + 0j
+    h = oracle.sinc_fast(N, a, c, b, nq_of_N(N), quad, 2.0, 2.0, m, m)
+    ref = oracle.sinc_direct(N, a, c, b)
+    P = oracle.params(N, 2.0, 2.0, m, m)
+    if quad == oracle.QUAD_CLENSHAW_CURTIS:
+        eps = oracle.bound_thm53(N, 4)
+    else:
+        z, w = oracle.gauss_legendre(2 * N)
+        xs = np.linspace(-1, 1, 4001)
+        eps = np.abs((w[None, :] * np.exp(-1j * np.pi * N * np.outer(xs, z))).sum(1) - np.sinc(N * xs)).max()
+    bound = oracle.bound_thm62(eps, _bound(P)) * np.abs(c).sum()
+    err = np.abs(h - ref).max()
+    assert err <= bound, (err, bound)
+    assert err < 1e-6 * np.abs(ref).max()
+    # real coefficients give a real transform
+    assert np.abs(h.imag).max() < 1e-9 * np.abs(h).max()
