@@ -1,0 +1,191 @@
+/*
+ * nnfft.h - C ABI of the MI355X (gfx950) NNFFT / fast sinc transform library.
+ *
+ * Method: Kircheis, Potts, Tasche, "Nonuniform fast Fourier transforms with
+ * nonequispaced spatial and frequency data and fast sinc transforms"
+ * (arXiv 2107.02671).
+ *
+ *   NNFFT (Algorithm 2.2): approximates, for frequencies v_k and spatial nodes
+ *   x_j in [-1/2, 1/2],
+ *        y_j = f(x_j) = sum_{k=0}^{M1-1} f_k exp(-2 pi i N v_k x_j)    (1.2)
+ *   by sinh-type window spreading (step 1, (2.12)), division by phi_hat_2
+ *   (step 2), a length-N2 FFT (step 3), phi_2 interpolation (step 4) and the
+ *   final division by phi_hat_1(N x_j) (Algorithm 2.2, output line).  The
+ *   substitution N -> N* = N + ceil(2 m1 / sigma1) of Sec. 2 (after (2.7)) is
+ *   always applied, so v_k may fill all of [-1/2, 1/2].
+ *
+ *   Fast sinc transform (Algorithm 6.1): approximates
+ *        h_l = sum_{k=0}^{L1-1} c_k sinc(N pi (b_l - a_k))              (6.2)
+ *   by the quadrature sinc(N pi x) = (1/2) int_{-1}^{1} e^{-pi i N t x} dt
+ *   (Sec. 5), an NNFFT, a multiplication by the quadrature weights and a
+ *   second NNFFT.
+ *
+ * Conventions for every entry point:
+ *   - Complex arrays are interleaved (re, im): c64 = 2 x float, c128 = 2 x
+ *     double.  NNFFT_FP32_COMP plans take and return c64, NNFFT_FP64_PLAIN
+ *     plans c128.
+ *   - Node arrays (v, x, a, b) are FP64 DEVICE pointers; coefficient and
+ *     result arrays (f, y, c, h) are DEVICE pointers.  Index k of an array is
+ *     the paper's label k - M/2 (any M >= 1 is accepted).
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream).  exec is
+ *     asynchronous on that stream and never synchronizes the host; plan
+ *     creation synchronizes `stream` once.
+ *   - The caller owns every pointer it passes.  A plan copies what it needs
+ *     from v and x; they may be freed once the plan call has returned.
+ *   - A plan owns its device scratch, so one plan serves one exec at a time:
+ *     two execs of the same plan on different streams race.
+ *   - Errors are returned as nnfft_status; nothing throws across the ABI.
+ *     nnfft_last_error() returns a thread-local message for the last failure.
+ *   - Precision: NNFFT_FP64_PLAIN evaluates the windows exactly in FP64 and
+ *     accumulates in FP64 (the plain comparator).  NNFFT_FP32_COMP streams,
+ *     transforms and interpolates in FP32 with compensated (two-sum)
+ *     accumulation of the grid cells; the correction factors phi_hat_1,
+ *     phi_hat_2, the FFT twiddles and the quadrature nodes and weights are
+ *     computed in FP64.
+ */
+#ifndef NNFFT_H
+#define NNFFT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nnfft_plan_s *nnfft_plan_t;
+typedef struct sinc_plan_s *sinc_plan_t;
+
+typedef enum {
+    NNFFT_OK = 0,
+    NNFFT_ERR_ARG = 1,          /* invalid size or parameter (see below)           */
+    NNFFT_ERR_DOMAIN = 2,       /* a node outside [-1/2, 1/2] or not finite        */
+    NNFFT_ERR_NOMEM = 3,        /* device or host allocation failed                */
+    NNFFT_ERR_DEVICE = 4,       /* a HIP call failed                               */
+    NNFFT_ERR_UNSUPPORTED = 5,  /* parameters outside what the kernels implement   */
+    NNFFT_ERR_BUSY = 6          /* resource in use (serving layer)                 */
+} nnfft_status;
+
+typedef enum {
+    NNFFT_FP64_PLAIN = 0,       /* FP64 windows, FP64 accumulation, FP64 FFT       */
+    NNFFT_FP32_COMP = 1         /* FP32 data path, compensated grid accumulation   */
+} nnfft_precision;
+
+typedef enum {
+    SINC_QUAD_GAUSS_LEGENDRE = 0,   /* n_quad Gauss-Legendre nodes (e.g. 2N)         */
+    SINC_QUAD_CLENSHAW_CURTIS = 1   /* Chebyshev points, n_quad + 1 nodes, (5.4)     */
+} sinc_quad;
+
+/* Derived sizes and diagnostics of a plan (host struct, filled by the library). */
+typedef struct {
+    int64_t N, N_star, N1, G1, N2;  /* bandwidth, N*, N1, G1 = N1 + 2 m1, FFT length */
+    int64_t M1, M2;                 /* node counts                                   */
+    int32_t m1, m2;                 /* truncation parameters                         */
+    int32_t precision;              /* nnfft_precision                               */
+    double sigma1, sigma2;          /* requested oversampling factors                */
+    double sigma1_eff, sigma2_eff;  /* N1 / N*, N2 / G1 (used in beta and the bound) */
+    double a;                       /* (2.6): 1 + 2 m1 / N1                          */
+    double beta1, beta2;            /* 2 pi m_j (1 - 1/(2 sigma_j_eff))              */
+    double bound_thm41;             /* E(phi_sinh) of (4.2) at the effective sigmas  */
+    int32_t thm41_applies;          /* 1 if sigma_eff in [5/4, 2] and m2 >= m1       */
+    int32_t window_degree;          /* FP32: degree of the per-tap window polynomials*/
+    double window_fit_err;          /* FP32: max abs error of those polynomials      */
+    int32_t corr_degree;            /* degree of the 1/phi_hat_1 Chebyshev series     */
+    double corr_fit_err;            /* its max relative error                        */
+    int64_t device_bytes;           /* device memory owned by the plan               */
+    int64_t block_points;           /* points per node block (XCD locality unit)     */
+    int32_t items_points;           /* max points per work item                      */
+    int32_t spread_workgroups;      /* workgroups of the spreading launch            */
+    int32_t interp_workgroups;      /* workgroups of the interpolation launch        */
+    int32_t fft_n1, fft_n2;         /* FFT factorization N2 = n1 * n2 (n1 = 1: one WG)*/
+} nnfft_info_t;
+
+/*
+ * Parameter derivation only (no device work); used to size requests.
+ * Sizes of Algorithm 2.2 with these readings: N* = N + ceil(2 m1/sigma1);
+ * N1 = 2 ceil(sigma1 N* / 2); G1 = N1 + 2 m1; N2 = the largest even integer
+ * with prime factors 2, 3, 5 not above sigma2 G1 (if that drops below
+ * min(sigma2, 5/4) G1: the smallest such integer >= sigma2 G1);
+ * beta_j from the effective sigmas.
+ * Errors: NNFFT_ERR_ARG if N < 1, m < 2, sigma <= 1, 2 m1 >= N1 or
+ * 2 m2 > (1 - 1/sigma1_eff) N2 (the requirement of Algorithm 2.2).
+ */
+nnfft_status nnfft_derive_params(int64_t N, double sigma1, double sigma2, int m1, int m2,
+                                 nnfft_info_t *out);
+
+/*
+ * Creates a plan for Algorithm 2.2 (step 0 "precompute" and the node
+ * preprocessing): node records (grid cell + fractional offset, computed in
+ * FP64), a stable sort of the nodes into cell bins inside blocks of
+ * consecutive indices, the work items and the workgroup schedule, the FP64
+ * table 1/(N1 N2 phi_hat_2(l)), the FFT twiddles (FP64, rounded for FP32),
+ * and for FP32 the Chebyshev fits of the window taps and of 1/phi_hat_1.
+ *   v[M1], x[M2]  FP64 device arrays of frequencies and spatial nodes.
+ * Errors: ARG (sizes as in nnfft_derive_params, M1 < 1, M2 < 1, M > 2^30),
+ * DOMAIN (|v_k| > 1/2 or |x_j| > 1/2 or NaN), UNSUPPORTED (m > 16, FP32 with
+ * m < 4, or a window / correction fit that misses its tolerance), NOMEM,
+ * DEVICE.  On error *out is set to NULL.
+ */
+nnfft_status nnfft_plan(nnfft_plan_t *out, int64_t N, int64_t M1, int64_t M2,
+                        double sigma1, double sigma2, int m1, int m2, nnfft_precision prec,
+                        const double *v, const double *x, void *stream);
+
+/*
+ * Runs Algorithm 2.2 on `stream`: f[M1] -> y[M2] (c64 or c128 per the plan's
+ * precision; y in the caller's node order).  f and y must not overlap.
+ */
+nnfft_status nnfft_exec(nnfft_plan_t p, const void *f, void *y, void *stream);
+
+/*
+ * Batched form: runs n independent plans in one launch per stage (spreading,
+ * transform, interpolation), each with its own sizes and precision.  Plans
+ * must be distinct.  Results are bitwise those of nnfft_exec on each plan.
+ */
+nnfft_status nnfft_exec_batch(int n, const nnfft_plan_t *plans, const void *const *f,
+                              void *const *y, void *stream);
+
+nnfft_status nnfft_info(nnfft_plan_t p, nnfft_info_t *out);
+nnfft_status nnfft_destroy(nnfft_plan_t p);
+
+/*
+ * Fast sinc transform plan (Algorithm 6.1).  Quadrature nodes z_j and weights
+ * w_j (sum w_j = 1) are computed on the host in FP64: Gauss-Legendre with
+ * n_quad nodes, or Clenshaw-Curtis (5.4) with n_quad + 1 Chebyshev points.
+ * The first NNFFT uses v = a_k, x = z_j / 2, the second v = -z_j / 2,
+ * x = b_l, both with bandwidth N and the given sigma, m, precision.
+ *   a[L1], b[L2]: FP64 device arrays in [-1/2, 1/2].
+ * Errors: as nnfft_plan, plus ARG for n_quad < 1 or an unknown rule.
+ */
+nnfft_status sinc_plan(sinc_plan_t *out, int64_t N, int64_t L1, int64_t L2, sinc_quad quad,
+                       int64_t n_quad, double sigma1, double sigma2, int m1, int m2,
+                       nnfft_precision prec, const double *a, const double *b, void *stream);
+
+/* c[L1] -> h[L2] (complex, c64/c128 per precision); real c gives real h up to
+ * the transform's error.  Asynchronous on `stream`. */
+nnfft_status sinc_exec(sinc_plan_t p, const void *c, void *h, void *stream);
+
+/* Info of the two NNFFT plans inside (which = 0: step 1, which = 1: step 3). */
+nnfft_status sinc_info(sinc_plan_t p, int which, nnfft_info_t *out);
+nnfft_status sinc_destroy(sinc_plan_t p);
+
+/*
+ * The quadrature rule sinc_plan uses, on the host (no device work):
+ * z[n_nodes], w[n_nodes] HOST arrays with n_nodes = n_quad (Gauss-Legendre)
+ * or n_quad + 1 (Clenshaw-Curtis); weights sum to 1 (sinc(N pi x) is half the
+ * integral of e^{-pi i N t x} over [-1, 1], Sec. 5).  Gauss-Legendre by
+ * Newton's method on the Legendre recurrence; Clenshaw-Curtis by Algorithm
+ * 5.4 (DCT-I of length n_quad + 1).  Errors: ARG for n_quad < 1, an unknown
+ * rule or null arrays.
+ */
+nnfft_status nnfft_quadrature(sinc_quad quad, int64_t n_quad, double *z, double *w);
+
+/* Thread-local description of the last error in this thread ("" if none). */
+const char *nnfft_last_error(void);
+
+/* Library version string. */
+const char *nnfft_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NNFFT_H */

@@ -1,0 +1,285 @@
+"""ctypes binding of include/nnfft.h (argument marshalling only).
+
+Every function has the name of the C entry point it calls.  Device arrays
+are torch tensors on the GPU (their data_ptr() is passed); the stream is the
+current torch stream unless one is given.  All compute happens in the HIP
+library; nothing here falls back to another implementation: if the library
+is missing the import-time loader raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnnfft.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "nnfft.h")
+
+NNFFT_OK = 0
+NNFFT_ERR_ARG = 1
+NNFFT_ERR_DOMAIN = 2
+NNFFT_ERR_NOMEM = 3
+NNFFT_ERR_DEVICE = 4
+NNFFT_ERR_UNSUPPORTED = 5
+NNFFT_ERR_BUSY = 6
+STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_DOMAIN", 3: "ERR_NOMEM", 4: "ERR_DEVICE",
+                5: "ERR_UNSUPPORTED", 6: "ERR_BUSY"}
+
+NNFFT_FP64_PLAIN = 0
+NNFFT_FP32_COMP = 1
+SINC_QUAD_GAUSS_LEGENDRE = 0
+SINC_QUAD_CLENSHAW_CURTIS = 1
+
+
+class NnfftInfo(ctypes.Structure):
+    _fields_ = [
+        ("N", ctypes.c_int64), ("N_star", ctypes.c_int64), ("N1", ctypes.c_int64),
+        ("G1", ctypes.c_int64), ("N2", ctypes.c_int64),
+        ("M1", ctypes.c_int64), ("M2", ctypes.c_int64),
+        ("m1", ctypes.c_int32), ("m2", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("sigma1", ctypes.c_double), ("sigma2", ctypes.c_double),
+        ("sigma1_eff", ctypes.c_double), ("sigma2_eff", ctypes.c_double),
+        ("a", ctypes.c_double), ("beta1", ctypes.c_double), ("beta2", ctypes.c_double),
+        ("bound_thm41", ctypes.c_double), ("thm41_applies", ctypes.c_int32),
+        ("window_degree", ctypes.c_int32), ("window_fit_err", ctypes.c_double),
+        ("corr_degree", ctypes.c_int32), ("corr_fit_err", ctypes.c_double),
+        ("device_bytes", ctypes.c_int64), ("block_points", ctypes.c_int64),
+        ("items_points", ctypes.c_int32), ("spread_workgroups", ctypes.c_int32),
+        ("interp_workgroups", ctypes.c_int32), ("fft_n1", ctypes.c_int32),
+        ("fft_n2", ctypes.c_int32),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class NnfftError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Loads libnnfft.so (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() or "
+                          f"python paper_2107_02671_amd/build.py")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, dbl, ci = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int
+    L.nnfft_derive_params.argtypes = [i64, dbl, dbl, ci, ci, ctypes.POINTER(NnfftInfo)]
+    L.nnfft_plan.argtypes = [ctypes.POINTER(vp), i64, i64, i64, dbl, dbl, ci, ci, ci, vp, vp, vp]
+    L.nnfft_exec.argtypes = [vp, vp, vp, vp]
+    L.nnfft_exec_batch.argtypes = [ci, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
+    L.nnfft_info.argtypes = [vp, ctypes.POINTER(NnfftInfo)]
+    L.nnfft_destroy.argtypes = [vp]
+    L.sinc_plan.argtypes = [ctypes.POINTER(vp), i64, i64, i64, ci, i64, dbl, dbl, ci, ci, ci, vp, vp, vp]
+    L.sinc_exec.argtypes = [vp, vp, vp, vp]
+    L.sinc_info.argtypes = [vp, ci, ctypes.POINTER(NnfftInfo)]
+    L.sinc_destroy.argtypes = [vp]
+    dptr = ctypes.POINTER(ctypes.c_double)
+    L.nnfft_quadrature.argtypes = [ci, i64, dptr, dptr]
+    L.nnfft_last_error.restype = ctypes.c_char_p
+    L.nnfft_version.restype = ctypes.c_char_p
+    for name in ["nnfft_quadrature", "nnfft_derive_params", "nnfft_plan", "nnfft_exec", "nnfft_exec_batch", "nnfft_info",
+                 "nnfft_destroy", "sinc_plan", "sinc_exec", "sinc_info", "sinc_destroy"]:
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def header_functions():
+    """Names of the functions declared in include/nnfft.h."""
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(nnfft_\w+|sinc_\w+)\s*\(", src)))
+
+
+def _check(status):
+    if status != NNFFT_OK:
+        raise NnfftError(status, nnfft_last_error())
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def nnfft_last_error() -> str:
+    return lib().nnfft_last_error().decode()
+
+
+def nnfft_version() -> str:
+    return lib().nnfft_version().decode()
+
+
+def nnfft_derive_params(N, sigma1, sigma2, m1, m2) -> dict:
+    info = NnfftInfo()
+    _check(lib().nnfft_derive_params(int(N), float(sigma1), float(sigma2), int(m1), int(m2),
+                                     ctypes.byref(info)))
+    return info.as_dict()
+
+
+def nnfft_quadrature(quad, n_quad):
+    """Host-side quadrature rule of sinc_plan: (z, w) numpy arrays."""
+    import numpy as np
+    n = int(n_quad) + (1 if quad == SINC_QUAD_CLENSHAW_CURTIS else 0)
+    z = np.zeros(n)
+    w = np.zeros(n)
+    dptr = ctypes.POINTER(ctypes.c_double)
+    _check(lib().nnfft_quadrature(int(quad), int(n_quad), z.ctypes.data_as(dptr), w.ctypes.data_as(dptr)))
+    return z, w
+
+
+def _require(t, dtype, n, name):
+    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous() or t.numel() != n:
+        raise ValueError(f"{name}: need a contiguous {dtype} CUDA tensor of {n} elements, "
+                         f"got {t.dtype} {tuple(t.shape)} on {t.device}")
+
+
+def nnfft_plan(N, v, x, sigma1=2.0, sigma2=2.0, m1=6, m2=6, prec=NNFFT_FP32_COMP, stream=None):
+    """v, x: float64 CUDA tensors.  Returns an opaque plan handle (c_void_p)."""
+    import torch
+    _require(v, torch.float64, v.numel(), "v")
+    _require(x, torch.float64, x.numel(), "x")
+    h = ctypes.c_void_p()
+    _check(lib().nnfft_plan(ctypes.byref(h), int(N), v.numel(), x.numel(), float(sigma1), float(sigma2),
+                            int(m1), int(m2), int(prec), _ptr(v), _ptr(x), _stream(stream)))
+    return h
+
+
+def nnfft_info(plan) -> dict:
+    info = NnfftInfo()
+    _check(lib().nnfft_info(plan, ctypes.byref(info)))
+    return info.as_dict()
+
+
+def _cdtype(prec):
+    import torch
+    return torch.complex64 if prec == NNFFT_FP32_COMP else torch.complex128
+
+
+def nnfft_exec(plan, f, y, stream=None):
+    info = nnfft_info(plan)
+    dt = _cdtype(info["precision"])
+    _require(f, dt, info["M1"], "f")
+    _require(y, dt, info["M2"], "y")
+    _check(lib().nnfft_exec(plan, _ptr(f), _ptr(y), _stream(stream)))
+
+
+def nnfft_exec_batch(plans, fs, ys, stream=None):
+    n = len(plans)
+    for p, f, y in zip(plans, fs, ys):
+        info = nnfft_info(p)
+        dt = _cdtype(info["precision"])
+        _require(f, dt, info["M1"], "f")
+        _require(y, dt, info["M2"], "y")
+    P = (ctypes.c_void_p * n)(*[p.value for p in plans])
+    F = (ctypes.c_void_p * n)(*[f.data_ptr() for f in fs])
+    Y = (ctypes.c_void_p * n)(*[y.data_ptr() for y in ys])
+    _check(lib().nnfft_exec_batch(n, P, F, Y, _stream(stream)))
+
+
+def nnfft_destroy(plan):
+    _check(lib().nnfft_destroy(plan))
+
+
+def sinc_plan(N, a, b, n_quad, quad=SINC_QUAD_GAUSS_LEGENDRE, sigma1=2.0, sigma2=2.0, m1=6, m2=6,
+              prec=NNFFT_FP32_COMP, stream=None):
+    import torch
+    _require(a, torch.float64, a.numel(), "a")
+    _require(b, torch.float64, b.numel(), "b")
+    h = ctypes.c_void_p()
+    _check(lib().sinc_plan(ctypes.byref(h), int(N), a.numel(), b.numel(), int(quad), int(n_quad),
+                           float(sigma1), float(sigma2), int(m1), int(m2), int(prec), _ptr(a), _ptr(b),
+                           _stream(stream)))
+    return h
+
+
+def sinc_info(plan, which=0) -> dict:
+    info = NnfftInfo()
+    _check(lib().sinc_info(plan, int(which), ctypes.byref(info)))
+    return info.as_dict()
+
+
+def sinc_exec(plan, c, h, stream=None):
+    i0, i1 = sinc_info(plan, 0), sinc_info(plan, 1)
+    dt = _cdtype(i0["precision"])
+    _require(c, dt, i0["M1"], "c")
+    _require(h, dt, i1["M2"], "h")
+    _check(lib().sinc_exec(plan, _ptr(c), _ptr(h), _stream(stream)))
+
+
+def sinc_destroy(plan):
+    _check(lib().sinc_destroy(plan))
+
+
+class Plan:
+    """Owning wrapper: Plan(N, v, x, ...) ; plan(f) -> y ; closed on exit/GC."""
+
+    def __init__(self, N, v, x, sigma1=2.0, sigma2=2.0, m1=6, m2=6, prec=NNFFT_FP32_COMP, stream=None):
+        self.handle = nnfft_plan(N, v, x, sigma1, sigma2, m1, m2, prec, stream)
+        self.info = nnfft_info(self.handle)
+
+    def __call__(self, f, y=None, stream=None):
+        import torch
+        if y is None:
+            y = torch.empty(self.info["M2"], dtype=_cdtype(self.info["precision"]), device=f.device)
+        nnfft_exec(self.handle, f, y, stream)
+        return y
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            nnfft_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class SincPlan:
+    def __init__(self, N, a, b, n_quad, quad=SINC_QUAD_GAUSS_LEGENDRE, sigma1=2.0, sigma2=2.0, m1=6,
+                 m2=6, prec=NNFFT_FP32_COMP, stream=None):
+        self.handle = sinc_plan(N, a, b, n_quad, quad, sigma1, sigma2, m1, m2, prec, stream)
+        self.info = [sinc_info(self.handle, 0), sinc_info(self.handle, 1)]
+
+    def __call__(self, c, h=None, stream=None):
+        import torch
+        if h is None:
+            h = torch.empty(self.info[1]["M2"], dtype=_cdtype(self.info[0]["precision"]), device=c.device)
+        sinc_exec(self.handle, c, h, stream)
+        return h
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            sinc_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,352 @@
+// Host-side FP64 mathematics of the NNFFT plan.
+#include "host_math.h"
+
+#include <cmath>
+#include <complex>
+#include <cstring>
+
+#include "internal.h"
+
+namespace nnfft {
+
+namespace {
+
+constexpr double kPi = 3.141592653589793238462643383279502884;
+
+int64_t ceil_with_slack(double x) { return (int64_t)std::ceil(x - 1e-9); }
+
+bool only_235(int64_t n)
+{
+    if (n < 1) return false;
+    for (int p : {2, 3, 5})
+        while (n % p == 0) n /= p;
+    return n == 1;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Sizes (Algorithm 2.2 input list, N* substitution of Sec. 2)
+// ---------------------------------------------------------------------------
+nnfft_status derive_params(int64_t N, double sigma1, double sigma2, int m1, int m2,
+                           nnfft_info_t *out)
+{
+    std::memset(out, 0, sizeof(*out));
+    if (N < 1 || m1 < 2 || m2 < 2 || !(sigma1 > 1.0) || !(sigma2 > 1.0) ||
+        !std::isfinite(sigma1) || !std::isfinite(sigma2))
+        return NNFFT_ERR_ARG;
+    nnfft_info_t &P = *out;
+    P.N = N;
+    P.m1 = m1;
+    P.m2 = m2;
+    P.sigma1 = sigma1;
+    P.sigma2 = sigma2;
+    P.N_star = N + ceil_with_slack(2.0 * m1 / sigma1);
+    P.N1 = 2 * ceil_with_slack(0.5 * sigma1 * (double)P.N_star);
+    P.G1 = P.N1 + 2 * m1;
+    // N2: even, only prime factors 2, 3, 5; largest not above sigma2 G1,
+    // unless that leaves too little oversampling.
+    const double want = sigma2 * (double)P.G1;
+    int64_t down = (int64_t)std::floor(want + 1e-9) & ~(int64_t)1;
+    while (down > 0 && !only_235(down)) down -= 2;
+    const double floor_ok = std::min(sigma2, 1.25) * (double)P.G1;
+    int64_t n2 = down;
+    if (down <= P.G1 || (double)down < floor_ok - 1e-9) {
+        int64_t up = ceil_with_slack(want);
+        up += (up & 1);
+        while (!only_235(up)) up += 2;
+        n2 = up;
+    }
+    P.N2 = n2;
+    P.sigma1_eff = (double)P.N1 / (double)P.N_star;
+    P.sigma2_eff = (double)P.N2 / (double)P.G1;
+    P.a = (double)P.G1 / (double)P.N1;
+    P.beta1 = 2.0 * kPi * m1 * (1.0 - 0.5 / P.sigma1_eff);
+    P.beta2 = 2.0 * kPi * m2 * (1.0 - 0.5 / P.sigma2_eff);
+    if (2 * m1 >= P.N1) return NNFFT_ERR_ARG;
+    if (2.0 * m2 > (1.0 - 1.0 / P.sigma1_eff) * (double)P.N2 + 1e-9) return NNFFT_ERR_ARG;
+    // (4.2), Theorem 4.1, evaluated at the effective oversampling factors
+    {
+        const double s1 = P.sigma1_eff, s2 = P.sigma2_eff;
+        const double a1 = (24.0 * std::pow((double)m1, 1.5) + 10.0);
+        const double a2 = (24.0 * std::pow((double)m2, 1.5) + 10.0);
+        const double e1 = std::exp(-2.0 * kPi * m1 * std::sqrt(1.0 - 1.0 / s1));
+        const double grow = std::exp(2.0 * kPi * m1 * (1.0 - std::sqrt(1.0 - 1.0 / s1) - 0.5 / s1));
+        const double e2 = std::exp(-2.0 * kPi * m2 * std::sqrt(1.0 - 1.0 / s2));
+        P.bound_thm41 = a1 * e1 + a2 * (2.0 * P.N1 + 4.0 * m1) / std::sqrt(2.0 * m1 * kPi) * grow * e2;
+        P.thm41_applies = (s1 >= 1.25 - 1e-12 && s1 <= 2.0 + 1e-12 && s2 >= 1.25 - 1e-12 &&
+                           s2 <= 2.0 + 1e-12 && m2 >= m1) ? 1 : 0;
+    }
+    return NNFFT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Window and window transform
+// ---------------------------------------------------------------------------
+double window_sinh(double u, double beta)
+{
+    const double q = (1.0 - u) * (1.0 + u);
+    if (!(q > 0.0)) return 0.0;
+    return std::sinh(beta * std::sqrt(q)) / std::sinh(beta);
+}
+
+// I_1(z)/z for y = z^2 >= 0 from its Taylor series (1/2) sum y^k/(4^k k!(k+1)!)
+// evaluated in nested (Horner) form from the last kept term down.
+static double i1_over_z(double y)
+{
+    const double q = 0.25 * y;
+    // the terms peak near k = sqrt(q); past ~e sqrt(q) + 40 they are < 1e-20
+    const int K = 40 + (int)(2.72 * std::sqrt(q));
+    double acc = 1.0;
+    for (int k = K; k >= 1; --k) acc = 1.0 + acc * q / ((double)k * (double)(k + 1));
+    return 0.5 * acc;
+}
+
+double window_sinh_hat(double v, double beta)
+{
+    const double y = beta * beta - 4.0 * kPi * kPi * v * v;
+    const double pre = kPi * beta / std::sinh(beta);
+    if (y >= 0.0) return pre * i1_over_z(y);
+    const double z = std::sqrt(-y);
+    return pre * ::j1(z) / z;
+}
+
+// ---------------------------------------------------------------------------
+// Chebyshev fits
+// ---------------------------------------------------------------------------
+std::vector<double> cheb_nodes(int deg)
+{
+    std::vector<double> t(deg + 1);
+    for (int j = 0; j <= deg; ++j) t[j] = std::cos(kPi * (j + 0.5) / (deg + 1));
+    return t;
+}
+
+std::vector<double> cheb_fit(int deg, const std::vector<double> &f)
+{
+    std::vector<double> c(deg + 1, 0.0);
+    for (int k = 0; k <= deg; ++k) {
+        double s = 0.0;
+        for (int j = 0; j <= deg; ++j) s += f[j] * std::cos(kPi * k * (j + 0.5) / (deg + 1));
+        c[k] = 2.0 * s / (deg + 1);
+    }
+    c[0] *= 0.5;
+    return c;
+}
+
+double cheb_eval(const double *c, int deg, double t)
+{
+    double b1 = 0.0, b2 = 0.0;
+    for (int k = deg; k >= 1; --k) {
+        const double b0 = c[k] + 2.0 * t * b1 - b2;
+        b2 = b1;
+        b1 = b0;
+    }
+    return c[0] + t * b1 - b2;
+}
+
+std::vector<double> fit_window_taps(int m, double beta, int deg, double *max_err)
+{
+    std::vector<double> out((size_t)(2 * m) * (deg + 1));
+    const std::vector<double> tn = cheb_nodes(deg);
+    double worst = 0.0;
+    for (int r = 0; r < 2 * m; ++r) {
+        std::vector<double> f(deg + 1);
+        for (int j = 0; j <= deg; ++j) {
+            const double x = 0.5 * (tn[j] + 1.0);
+            f[j] = window_sinh((r - m + 1 - x) / m, beta);
+        }
+        std::vector<double> c = cheb_fit(deg, f);
+        for (int k = 0; k <= deg; ++k) out[(size_t)r * (deg + 1) + k] = c[k];
+        for (int i = 0; i <= 2000; ++i) {
+            const double x = i / 2000.0;
+            const double e = std::fabs(cheb_eval(c.data(), deg, 2.0 * x - 1.0) -
+                                       window_sinh((r - m + 1 - x) / m, beta));
+            worst = std::max(worst, e);
+        }
+    }
+    *max_err = worst;
+    return out;
+}
+
+std::vector<double> fit_inverse_phi1(const nnfft_info_t &P, double tol, int max_deg,
+                                     double *max_rel_err)
+{
+    // phi_hat_1(N* x) = (m1/N1) omega_hat_1(m1 N* x / N1)
+    auto inv = [&](double x) {
+        const double v = (double)P.m1 * (double)P.N_star * x / (double)P.N1;
+        return 1.0 / ((double)P.m1 / (double)P.N1 * window_sinh_hat(v, P.beta1));
+    };
+    std::vector<double> best;
+    double best_err = 1e300;
+    for (int deg = 4; deg <= max_deg; deg += 2) {
+        const std::vector<double> tn = cheb_nodes(deg);
+        std::vector<double> f(deg + 1);
+        for (int j = 0; j <= deg; ++j) f[j] = inv(std::sqrt((tn[j] + 1.0) / 8.0));
+        std::vector<double> c = cheb_fit(deg, f);
+        double err = 0.0;
+        for (int i = 0; i <= 4000; ++i) {
+            const double x = 0.5 * i / 4000.0;
+            const double ref = inv(x);
+            err = std::max(err, std::fabs(cheb_eval(c.data(), deg, 8.0 * x * x - 1.0) / ref - 1.0));
+        }
+        if (err < best_err) {
+            best_err = err;
+            best = c;
+        }
+        if (err <= tol) break;
+    }
+    *max_rel_err = best_err;
+    return best;
+}
+
+// ---------------------------------------------------------------------------
+// Twiddles: exp(-2 pi i q / n), exact at multiples of a quarter turn
+// ---------------------------------------------------------------------------
+std::vector<double> twiddles(int64_t n)
+{
+    std::vector<double> tw((size_t)(2 * n));
+    for (int64_t q = 0; q < n; ++q) {
+        const int64_t q4 = 4 * q;
+        const int64_t quad = q4 / n;          // 0..3
+        const int64_t rem = q4 - quad * n;    // angle in the quadrant = (pi/2) rem / n
+        const double th = 0.5 * kPi * (double)rem / (double)n;
+        double c = std::cos(th), s = std::sin(th);
+        // exp(-i (quad pi/2 + th))
+        double re, im;
+        switch (quad) {
+        case 0: re = c; im = -s; break;
+        case 1: re = -s; im = -c; break;
+        case 2: re = -c; im = s; break;
+        default: re = s; im = c; break;
+        }
+        tw[2 * q] = re;
+        tw[2 * q + 1] = im;
+    }
+    return tw;
+}
+
+// ---------------------------------------------------------------------------
+// Quadrature rules for sinc(N pi x) = (1/2) int e^{-pi i N t x} dt (Sec. 5)
+// ---------------------------------------------------------------------------
+void gauss_legendre_rule(int64_t n, std::vector<double> &z, std::vector<double> &w)
+{
+    // Newton's method on P_n from Tricomi's asymptotic node estimate, with
+    // (1 - t^2) P_n'(t) = n (P_{n-1}(t) - t P_n(t)); the weight
+    // W = 2 / ((1 - t^2) P_n'(t)^2) is evaluated with that derivative at the
+    // final node, which keeps it accurate where 1 - t^2 is small.
+    z.assign((size_t)n, 0.0);
+    w.assign((size_t)n, 0.0);
+    const double nn = (double)n;
+    auto legendre = [&](double t, double &p, double &pm) {
+        pm = 1.0;
+        p = t;
+        for (int64_t k = 2; k <= n; ++k) {
+            const double pk = ((2.0 * k - 1.0) * t * p - (k - 1.0) * pm) / (double)k;
+            pm = p;
+            p = pk;
+        }
+    };
+    for (int64_t i = 1; i <= (n + 1) / 2; ++i) {
+        const double th = kPi * (4.0 * i - 1.0) / (4.0 * nn + 2.0);
+        double t = (1.0 - (nn - 1.0) / (8.0 * nn * nn * nn)) * std::cos(th);
+        double p, pm;
+        for (int it = 0; it < 60; ++it) {
+            legendre(t, p, pm);
+            const double dp = nn * (pm - t * p) / ((1.0 - t) * (1.0 + t));
+            const double step = p / dp;
+            t -= step;
+            if (std::fabs(step) <= 1e-17) break;
+        }
+        legendre(t, p, pm);
+        const double omt2 = (1.0 - t) * (1.0 + t);
+        const double dp = nn * (pm - t * p) / omt2;
+        const double W = 2.0 / (omt2 * dp * dp);
+        z[(size_t)(i - 1)] = t;
+        z[(size_t)(n - i)] = -t;
+        w[(size_t)(i - 1)] = 0.5 * W;
+        w[(size_t)(n - i)] = 0.5 * W;
+    }
+    if (n % 2) z[(size_t)(n / 2)] = 0.0;
+}
+
+namespace {
+// in-place iterative radix-2 complex FFT (forward), n a power of two
+void fft_pow2(std::vector<std::complex<double>> &a)
+{
+    const size_t n = a.size();
+    for (size_t i = 1, j = 0; i < n; ++i) {
+        size_t bit = n >> 1;
+        for (; j & bit; bit >>= 1) j ^= bit;
+        j ^= bit;
+        if (i < j) std::swap(a[i], a[j]);
+    }
+    for (size_t len = 2; len <= n; len <<= 1) {
+        const double ang = -2.0 * kPi / (double)len;
+        for (size_t i = 0; i < n; i += len)
+            for (size_t k = 0; k < len / 2; ++k) {
+                const std::complex<double> wk(std::cos(ang * k), std::sin(ang * k));
+                const std::complex<double> u = a[i + k], v = a[i + k + len / 2] * wk;
+                a[i + k] = u + v;
+                a[i + k + len / 2] = u - v;
+            }
+    }
+}
+}  // namespace
+
+void clenshaw_curtis_rule(int64_t n, std::vector<double> &z, std::vector<double> &w)
+{
+    // Chebyshev points z_k = cos(k pi / n) and the weights of Algorithm 5.4:
+    // a_{2j} = eps(2j) 2/(1 - 4 j^2), a_odd = 0; a_hat = C^I_{n+1} a (DCT-I);
+    // w_k = eps(k) a_hat_k / sqrt(2n).  The DCT-I is done through a length-2n
+    // FFT of the even extension when n is a power of two, directly otherwise.
+    z.assign((size_t)(n + 1), 0.0);
+    w.assign((size_t)(n + 1), 0.0);
+    const double r2 = std::sqrt(0.5);
+    auto eps = [&](int64_t j) { return (j == 0 || j == n) ? r2 : 1.0; };
+    std::vector<double> a((size_t)(n + 1), 0.0);
+    for (int64_t j = 0; 2 * j <= n; ++j)
+        a[(size_t)(2 * j)] = eps(2 * j) * 2.0 / (1.0 - 4.0 * (double)j * (double)j);
+    // b_j = eps(j) a_j ; DCT-I core: S_k = sum_j b_j cos(j k pi / n)
+    std::vector<double> S((size_t)(n + 1), 0.0);
+    if (n >= 2 && (n & (n - 1)) == 0) {
+        std::vector<std::complex<double>> e((size_t)(2 * n));
+        for (int64_t j = 0; j <= n; ++j) e[(size_t)j] = eps(j) * a[(size_t)j];
+        for (int64_t j = 1; j < n; ++j) e[(size_t)(2 * n - j)] = e[(size_t)j];
+        fft_pow2(e);
+        // E_k = b_0 + (-1)^k b_n + 2 sum_{0<j<n} b_j cos(j k pi / n), so
+        // S_k = (E_k + b_0 + (-1)^k b_n) / 2
+        for (int64_t k = 0; k <= n; ++k)
+            S[(size_t)k] = 0.5 * (e[(size_t)k].real() + eps(0) * a[0] +
+                                  ((k % 2) ? -1.0 : 1.0) * eps(n) * a[(size_t)n]);
+    } else {
+        for (int64_t k = 0; k <= n; ++k) {
+            double s = 0.0;
+            for (int64_t j = 0; j <= n; ++j) {
+                const int64_t q = (j * k) % (2 * n);
+                s += eps(j) * a[(size_t)j] * std::cos(kPi * (double)q / (double)n);
+            }
+            S[(size_t)k] = s;
+        }
+    }
+    const double scale = std::sqrt(2.0 / (double)n);
+    for (int64_t k = 0; k <= n; ++k) {
+        const double ahat = scale * eps(k) * S[(size_t)k];
+        w[(size_t)k] = eps(k) * ahat / std::sqrt(2.0 * (double)n);
+        z[(size_t)k] = std::sin(kPi * (double)(n - 2 * k) / (2.0 * (double)n));
+    }
+}
+
+std::vector<int> radix_passes(int64_t n)
+{
+    std::vector<int> r;
+    if (n < 1) return {};
+    while (n % 8 == 0 && n > 4) { r.push_back(8); n /= 8; }
+    while (n % 4 == 0) { r.push_back(4); n /= 4; }
+    while (n % 2 == 0) { r.push_back(2); n /= 2; }
+    while (n % 5 == 0) { r.push_back(5); n /= 5; }
+    while (n % 3 == 0) { r.push_back(3); n /= 3; }
+    if (n != 1) return {};
+    return r;
+}
+
+}  // namespace nnfft

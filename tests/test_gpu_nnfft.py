@@ -1,0 +1,188 @@
+"""GPU parity of the NNFFT (Algorithm 2.2) against the FP64 CPU oracle.
+
+Tolerances (relative l-infinity error E_inf = max|y_gpu - y_oracle| / max|y_oracle|):
+  FP64 plain path  <= 1e-12  (same algorithm, FP64 arithmetic; differences are
+                              summation order and exp/sqrt rounding)
+  FP32 path        <= 1e-5 * max(1, kappa / 4.62), where
+                   kappa = max_j omega_hat_j(0) / omega_hat_j(m_j / (2 sigma_j))
+                   is the largest amplification of the two divisions by
+                   phi_hat (steps 2 and output): the FFT's absolute FP32
+                   rounding is divided by phi_hat_1(N x_j), which is kappa
+                   times smaller at |x_j| = 1/2 than at 0.  1e-5 is the stated
+                   FP32 requirement at m = 6, sigma = 2, where kappa = 4.62.
+Cases span several workgroups and node blocks with ragged tails, the FFT in
+one workgroup and in four-step form, radix 3/5 transform lengths, unequal
+sigma and m, edge and clustered nodes, and single-node inputs.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2107_02671_amd as P
+from paper_2107_02671_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FP64, FP32 = P.NNFFT_FP64_PLAIN, P.NNFFT_FP32_COMP
+TOL = {FP64: 1e-12, FP32: 1e-5}
+DEV = "cuda:0"
+KAPPA_REF = 4.62   # kappa at m = 6, sigma = 2
+
+
+def kappa(N, s1, s2, m1, m2):
+    Pp = oracle.params(N, s1, s2, m1, m2)
+    k1 = oracle.omega_hat(0.0, Pp.beta1) / oracle.omega_hat(m1 / (2 * Pp.sigma1_eff), Pp.beta1)
+    k2 = oracle.omega_hat(0.0, Pp.beta2) / oracle.omega_hat(m2 / (2 * Pp.sigma2_eff), Pp.beta2)
+    return float(max(k1, k2))
+
+
+def tol(prec, N, s1, s2, m1, m2):
+    if prec == FP64:
+        return TOL[FP64]
+    return TOL[FP32] * max(1.0, kappa(N, s1, s2, m1, m2) / KAPPA_REF)
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_nnfft(N, v, x, f, s1, s2, m1, m2, prec):
+    _say(f"[gpu] nnfft N={N} M1={len(v)} M2={len(x)} sigma=({s1},{s2}) m=({m1},{m2}) prec={prec}")
+    tv = torch.tensor(v, dtype=torch.float64, device=DEV)
+    tx = torch.tensor(x, dtype=torch.float64, device=DEV)
+    cdt = torch.complex64 if prec == FP32 else torch.complex128
+    tf = torch.tensor(f, dtype=cdt, device=DEV)
+    with P.Plan(N, tv, tx, s1, s2, m1, m2, prec) as pl:
+        y = pl(tf)
+        torch.cuda.synchronize()
+        info = pl.info
+    return y.cpu().numpy().astype(np.complex128), info
+
+
+def einf(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+CASES = [
+    # N, M1, M2, sigma1, sigma2, m1, m2, nodes
+    (64, 256, 256, 2.0, 2.0, 4, 4, "uniform"),
+    (200, 12345, 9999, 2.0, 2.0, 5, 5, "uniform"),
+    (200, 12345, 9999, 2.0, 2.0, 8, 8, "uniform"),
+    (333, 20001, 7777, 2.0, 2.0, 12, 12, "uniform"),
+    (150, 5000, 5001, 2.0, 2.0, 16, 16, "uniform"),
+    (4096, 1 << 17, 1 << 17, 2.0, 2.0, 6, 6, "uniform"),
+    (1200, 2400, 1600, 1.25, 1.25, 6, 6, "uniform"),
+    (100, 777, 501, 1.5, 2.0, 5, 7, "uniform"),
+    (8192, 50000, 40000, 2.0, 2.0, 6, 6, "uniform"),
+    (1024, 30000, 30000, 2.0, 2.0, 6, 6, "chebyshev"),
+    (2048, 1 << 16, 1 << 16, 2.0, 2.0, 8, 8, "clustered"),
+]
+
+
+def _nodes(kind, g, n):
+    return {"uniform": W.uniform_nodes, "chebyshev": W.chebyshev_nodes,
+            "clustered": W.clustered_nodes}[kind](g, n)
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"N{c[0]}-M{c[1]}x{c[2]}-s{c[3]}-{c[4]}-m{c[5]}-{c[6]}-{c[7]}")
+def test_nnfft_parity(case, prec):
+    N, M1, M2, s1, s2, m1, m2, kind = case
+    if prec == FP32 and min(m1, m2) < 4:
+        pytest.skip("FP32 path needs m >= 4")
+    g = W.rng(N + M1 + 7 * m1)
+    v, x = _nodes(kind, g, M1), _nodes(kind, g, M2)
+    f = W.complex_gaussian(g, M1)
+    y, info = gpu_nnfft(N, v, x, f, s1, s2, m1, m2, prec)
+    yo = oracle.nnfft(N, v, f, x, s1, s2, m1, m2)
+    e = einf(y, yo)
+    t = tol(prec, N, s1, s2, m1, m2)
+    _say(f"    E_inf vs oracle = {e:.3e} (tol {t:.2e}), N2={info['N2']} fft=({info['fft_n1']},{info['fft_n2']})")
+    assert e <= t
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_small_workload_against_direct_sum(prec):
+    # N=64, M1=M2=256, sigma=2, m=4: against the oracle NNFFT and the direct sum
+    N, v, x, f, w = W.nnfft_inputs("small")
+    y, info = gpu_nnfft(N, v, x, f, 2.0, 2.0, 4, 4, prec)
+    yo = oracle.nnfft(N, v, f, x, 2.0, 2.0, 4, 4)
+    ex = oracle.direct(N, v, f, x)
+    assert einf(y, yo) <= TOL[prec]
+    e_paper = np.abs(y - ex).max() / np.abs(f).sum()
+    assert e_paper <= 1.08 * info["bound_thm41"]
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_large_workload(prec):
+    # N=4096, M1=M2=2^20, sigma=2, m=6 (the benchmarked configuration), all
+    # outputs against the oracle NNFFT, 256 sampled outputs against the direct sum
+    N, v, x, f, w = W.nnfft_inputs("large")
+    y, info = gpu_nnfft(N, v, x, f, 2.0, 2.0, 6, 6, prec)
+    yo = oracle.nnfft(N, v, f, x, 2.0, 2.0, 6, 6)
+    e = einf(y, yo)
+    _say(f"    large E_inf vs oracle NNFFT = {e:.3e}")
+    assert e <= TOL[prec]
+    idx = W.rng(99).choice(len(x), 256, replace=False)
+    ex = oracle.direct(N, v, f, x[idx])
+    e_direct = float(np.abs(y[idx] - ex).max() / np.abs(ex).max())
+    _say(f"    large E_inf vs direct sum (256 samples) = {e_direct:.3e}")
+    assert e_direct <= 1e-5
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_edge_and_single_nodes(prec):
+    g = W.rng(5)
+    N, m = 64, 6
+    v = np.concatenate([[-0.5, 0.5, 0.0, -0.25, 0.25], W.uniform_nodes(g, 60)])
+    x = np.concatenate([[-0.5, 0.5, 0.0], W.uniform_nodes(g, 40)])
+    f = W.complex_gaussian(g, len(v))
+    y, _ = gpu_nnfft(N, v, x, f, 2.0, 2.0, m, m, prec)
+    assert einf(y, oracle.nnfft(N, v, f, x, 2.0, 2.0, m, m)) <= TOL[prec]
+    # one node on each side
+    for v1, x1 in [(0.5, -0.5), (-0.5, 0.5), (0.1234, 0.4321)]:
+        y, _ = gpu_nnfft(N, np.array([v1]), np.array([x1]), np.array([1.0 - 2.0j]), 2.0, 2.0, m, m, prec)
+        yo = oracle.nnfft(N, np.array([v1]), np.array([1.0 - 2.0j]), np.array([x1]), 2.0, 2.0, m, m)
+        assert abs(y[0] - yo[0]) <= TOL[prec] * abs(yo[0])
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_repeatable_bitwise(prec):
+    g = W.rng(6)
+    N, M = 512, 40000
+    v, x, f = W.uniform_nodes(g, M), W.uniform_nodes(g, M), W.complex_gaussian(g, M)
+    _say(f"[gpu] repeat N={N} M={M} prec={prec}")
+    cdt = torch.complex64 if prec == FP32 else torch.complex128
+    tv = torch.tensor(v, device=DEV)
+    tx = torch.tensor(x, device=DEV)
+    tf = torch.tensor(f, dtype=cdt, device=DEV)
+    with P.Plan(N, tv, tx, 2.0, 2.0, 6, 6, prec) as p1, P.Plan(N, tv, tx, 2.0, 2.0, 6, 6, prec) as p2:
+        a = p1(tf).clone()
+        b = p1(tf).clone()
+        c = p2(tf).clone()
+        torch.cuda.synchronize()
+    assert torch.equal(a, b) and torch.equal(a, c)
+
+
+def test_plan_errors():
+    _say("[gpu] plan error paths")
+    dev_v = torch.tensor([0.1, 0.6], dtype=torch.float64, device=DEV)
+    dev_x = torch.tensor([0.0], dtype=torch.float64, device=DEV)
+    with pytest.raises(P.NnfftError) as e:
+        P.nnfft_plan(64, dev_v, dev_x, 2.0, 2.0, 6, 6, FP64)
+    assert e.value.status == P.binding.NNFFT_ERR_DOMAIN
+    ok_v = torch.tensor([0.1, 0.2], dtype=torch.float64, device=DEV)
+    with pytest.raises(P.NnfftError) as e:
+        P.nnfft_plan(64, ok_v, dev_x, 2.0, 2.0, 3, 3, FP32)
+    assert e.value.status == P.binding.NNFFT_ERR_UNSUPPORTED
+    with pytest.raises(P.NnfftError) as e:
+        P.nnfft_plan(64, ok_v, dev_x, 2.0, 2.0, 17, 17, FP64)
+    assert e.value.status == P.binding.NNFFT_ERR_UNSUPPORTED
+    nan_x = torch.tensor([float("nan")], dtype=torch.float64, device=DEV)
+    with pytest.raises(P.NnfftError) as e:
+        P.nnfft_plan(64, ok_v, nan_x, 2.0, 2.0, 6, 6, FP64)
+    assert e.value.status == P.binding.NNFFT_ERR_DOMAIN
