@@ -144,6 +144,18 @@ nnfft_status nnfft_exec_batch(int n, const nnfft_plan_t *plans, const void *cons
                               void *const *y, void *stream);
 
 nnfft_status nnfft_info(nnfft_plan_t p, nnfft_info_t *out);
+
+/*
+ * Stage timing.  nnfft_profile_start makes the next `max_execs` execs of the
+ * plan record HIP events on their stream at the stage boundaries (before
+ * spreading, after spreading, after the FFT, after interpolation);
+ * nnfft_profile_stop waits for the last of them and returns the average
+ * duration in milliseconds of each stage over the recorded execs in
+ * stage_ms[0..2] = {spreading, FFT (with merge and deconvolution),
+ * interpolation} and their count in *nexecs.  Errors: ARG, NOMEM, DEVICE.
+ */
+nnfft_status nnfft_profile_start(nnfft_plan_t p, int max_execs);
+nnfft_status nnfft_profile_stop(nnfft_plan_t p, double *stage_ms, int *nexecs);
 nnfft_status nnfft_destroy(nnfft_plan_t p);
 
 /*

@@ -85,9 +85,11 @@ def lib():
     L.sinc_destroy.argtypes = [vp]
     dptr = ctypes.POINTER(ctypes.c_double)
     L.nnfft_quadrature.argtypes = [ci, i64, dptr, dptr]
+    L.nnfft_profile_start.argtypes = [vp, ci]
+    L.nnfft_profile_stop.argtypes = [vp, dptr, ctypes.POINTER(ci)]
     L.nnfft_last_error.restype = ctypes.c_char_p
     L.nnfft_version.restype = ctypes.c_char_p
-    for name in ["nnfft_quadrature", "nnfft_derive_params", "nnfft_plan", "nnfft_exec", "nnfft_exec_batch", "nnfft_info",
+    for name in ["nnfft_profile_start", "nnfft_profile_stop", "nnfft_quadrature", "nnfft_derive_params", "nnfft_plan", "nnfft_exec", "nnfft_exec_batch", "nnfft_info",
                  "nnfft_destroy", "sinc_plan", "sinc_exec", "sinc_info", "sinc_destroy"]:
         getattr(L, name).restype = ctypes.c_int
     _lib = L
@@ -192,6 +194,18 @@ def nnfft_exec_batch(plans, fs, ys, stream=None):
     F = (ctypes.c_void_p * n)(*[f.data_ptr() for f in fs])
     Y = (ctypes.c_void_p * n)(*[y.data_ptr() for y in ys])
     _check(lib().nnfft_exec_batch(n, P, F, Y, _stream(stream)))
+
+
+def nnfft_profile_start(plan, max_execs):
+    _check(lib().nnfft_profile_start(plan, int(max_execs)))
+
+
+def nnfft_profile_stop(plan):
+    """Average stage durations (ms) over the profiled execs: (spread, fft, interp), count."""
+    ms = (ctypes.c_double * 3)()
+    n = ctypes.c_int()
+    _check(lib().nnfft_profile_stop(plan, ms, ctypes.byref(n)))
+    return (ms[0], ms[1], ms[2]), n.value
 
 
 def nnfft_destroy(plan):

@@ -99,60 +99,104 @@ __device__ __forceinline__ double cheb64(const double *__restrict__ c, int deg, 
     return fma(t, b1, c[0] - b2);
 }
 
-// 1/phi_hat_1(N* x_j) for the bin label `lab` and offset `fr` of a node
-__device__ __forceinline__ double inv_phi1(const PlanDesc &P, int lab, double fr)
+// 1/phi_hat_1(N* x_j) from its FP64 Chebyshev series in t = 8 x^2 - 1, with
+// x_j reconstructed in FP64 from the bin label and the cell offset.
+template <int CD>
+__device__ __forceinline__ double inv_phi1_fixed(const double *__restrict__ c, double u_to_x, int lab,
+                                                 double fr)
 {
-    const double x = ((double)lab + fr) * P.u_to_x;
-    return cheb64(P.corr, P.corr_deg, fma(8.0 * x, x, -1.0));
+    const double x = ((double)lab + fr) * u_to_x;
+    const double t = fma(8.0 * x, x, -1.0);
+    const double t2 = t + t;
+    double b1 = 0.0, b2 = 0.0;
+#pragma unroll
+    for (int k = CD; k >= 1; --k) {
+        const double b0 = fma(t2, b1, c[k] - b2);
+        b2 = b1;
+        b1 = b0;
+    }
+    return fma(t, b1, c[0] - b2);
 }
 
 // ===========================================================================
 // Spreading, FP32 path
 // ===========================================================================
-template <int TM>   // TM >= 2 m1
+template <int TM>   // TM >= 2 m
 struct Spread32Lds {
-    cx<float> mom[256 * (kDeg + 1)];
-    cx<float> sbin[256 * TM];
-    int ibin[256];
-    int runS[256];
-    int runE[256];
+    cx<float> mom[kItemsPerWg * (kDeg + 1)];   // Chebyshev moments of each item
+    cx<float> sbin[kItemsPerWg * TM];          // 2m taps of each bin
+    float C[TM * (kDeg + 1)];                  // tap coefficients, staged once per workgroup
+    int ibin[kItemsPerWg];
+    int runS[kItemsPerWg];
+    int runE[kItemsPerWg];
 };
 
-template <int TM>
-__device__ void spread32_wg(const PlanDesc &P, int cid, const cx<float> *__restrict__ f,
-                            Spread32Lds<TM> &L)
+// Copies the [2m][kDeg + 1] tap coefficients into LDS once per workgroup.
+__device__ __forceinline__ void stage_taps(float *dst, const float *__restrict__ src, int tm)
+{
+    for (int i = threadIdx.x; i < tm * (kDeg + 1); i += blockDim.x) dst[i] = src[i];
+}
+
+// Chebyshev moments mu_k += f * T_k(y), k = 0..kDeg
+__device__ __forceinline__ void add_moments(float *mr, float *mi, cx<float> fv, float y)
 {
     constexpr int D = kDeg;
-    const Chunk ch = P.sp.chunks[cid];
-    const int m = P.m1, tm = 2 * m;
-    const int t = threadIdx.x, nt = blockDim.x;
-    for (int b = t; b < ch.nbin; b += nt) {
-        L.runS[b] = -1;
-        L.runE[b] = 0;
+    const float y2 = y + y;
+    float T0 = 1.f, T1 = y;
+    mr[0] += fv.re;
+    mi[0] += fv.im;
+    mr[1] = fmaf(fv.re, y, mr[1]);
+    mi[1] = fmaf(fv.im, y, mi[1]);
+#pragma unroll
+    for (int k = 2; k <= D; ++k) {
+        const float T2 = fmaf(y2, T1, -T0);
+        mr[k] = fmaf(fv.re, T2, mr[k]);
+        mi[k] = fmaf(fv.im, T2, mi[k]);
+        T0 = T1;
+        T1 = T2;
     }
-    // Phase A: Chebyshev moments of each item
-    if (t < ch.nitem) {
-        const Item it = P.sp.items[ch.item0 + t];
+}
+
+constexpr int kPtBatch = 16;   // point records loaded per batch
+
+// One wavefront per chunk of up to 64 items.
+//  A: thread = item: Chebyshev moments of its points (coalesced record loads
+//     from the chunk's transposed block, then the coefficient gathers, then
+//     the arithmetic) into LDS;
+//  B: thread = bin: two-sum of the moments of the bin's items, then the bin's
+//     2m taps sum_k C[r][k] M_k;
+//  C: window cell w (grid cell bin_lo - m + 1 + w) = two-sum over r of tap r
+//     of bin w - r, stored as (hi.re, hi.im, lo.re, lo.im).
+template <int TM>
+__device__ void spread32_slot(const SpreadArgs &A, const cx<float> *__restrict__ f, int g, Spread32Lds<TM> &L)
+{
+    constexpr int D = kDeg;
+    const int t = threadIdx.x;
+    const Item it = A.items[g * kItemsPerWg + t];    // independent of the chunk load
+    const Chunk ch = A.chunks[g];
+    if (ch.nitem == 0) return;
+    const int m = A.m, tm = 2 * m;
+    if (t < ch.nbin) {
+        L.runS[t] = -1;
+        L.runE[t] = 0;
+    }
+    if (it.n > 0) {
         float mr[D + 1], mi[D + 1];
 #pragma unroll
         for (int k = 0; k <= D; ++k) mr[k] = mi[k] = 0.f;
-        for (int p = it.p0; p < it.p0 + it.n; ++p) {
-            const float y = fmaf(2.f, P.sp.frac32[p], -1.f);
-            const cx<float> fv = f[P.sp.perm[p]];
-            const float y2 = y + y;
-            float T0 = 1.f, T1 = y;
-            mr[0] += fv.re;
-            mi[0] += fv.im;
-            mr[1] = fmaf(fv.re, y, mr[1]);
-            mi[1] = fmaf(fv.im, y, mi[1]);
+        const PtRec *__restrict__ rec = A.rec32 + ch.rec_off + t;
+        for (int q0 = 0; q0 < it.n; q0 += kPtBatch) {
+            // unconditional loads (slot index clamped into the item) so that
+            // all of them are in flight together
+            PtRec r[kPtBatch];
+            cx<float> fv[kPtBatch];
 #pragma unroll
-            for (int k = 2; k <= D; ++k) {
-                const float T2 = fmaf(y2, T1, -T0);
-                mr[k] = fmaf(fv.re, T2, mr[k]);
-                mi[k] = fmaf(fv.im, T2, mi[k]);
-                T0 = T1;
-                T1 = T2;
-            }
+            for (int q = 0; q < kPtBatch; ++q) r[q] = rec[min(q0 + q, it.n - 1) * kItemsPerWg];
+#pragma unroll
+            for (int q = 0; q < kPtBatch; ++q) fv[q] = f[r[q].perm];
+#pragma unroll
+            for (int q = 0; q < kPtBatch; ++q)
+                if (q0 + q < it.n) add_moments(mr, mi, fv[q], fmaf(2.f, r[q].frac, -1.f));
         }
 #pragma unroll
         for (int k = 0; k <= D; ++k) L.mom[t * (D + 1) + k] = cxmk(mr[k], mi[k]);
@@ -165,24 +209,12 @@ __device__ void spread32_wg(const PlanDesc &P, int cid, const cx<float> *__restr
         if (t == ch.nitem - 1 || L.ibin[t + 1] != b) L.runE[b] = t + 1;
     }
     __syncthreads();
-    // Phase B: per bin, compensated sum of its items' moments, then the 2m taps
-    for (int b = t; b < ch.nbin; b += nt) {
-        cx<float> *out = L.sbin + b * TM;
-        const int s = L.runS[b];
-        if (s < 0) {
-            for (int r = 0; r < tm; ++r) out[r] = cxmk(0.f, 0.f);
-            continue;
-        }
-        const int e = L.runE[b];
+    if (t < ch.nbin) {
+        const int s = L.runS[t], e = L.runE[t];
         float hr[D + 1], hi[D + 1], lr[D + 1], li[D + 1];
 #pragma unroll
-        for (int k = 0; k <= D; ++k) {
-            const cx<float> v = L.mom[s * (D + 1) + k];
-            hr[k] = v.re;
-            hi[k] = v.im;
-            lr[k] = li[k] = 0.f;
-        }
-        for (int i = s + 1; i < e; ++i) {
+        for (int k = 0; k <= D; ++k) hr[k] = hi[k] = lr[k] = li[k] = 0.f;
+        for (int i = s; i < e; ++i) {   // s = -1, e = 0 for a bin without items
 #pragma unroll
             for (int k = 0; k <= D; ++k) {
                 const cx<float> v = L.mom[i * (D + 1) + k];
@@ -195,79 +227,90 @@ __device__ void spread32_wg(const PlanDesc &P, int cid, const cx<float> *__restr
             hr[k] += lr[k];
             hi[k] += li[k];
         }
-        for (int r = 0; r < tm; ++r) {
-            const float *c = P.C1 + r * (D + 1);
-            float ar = 0.f, ai = 0.f;
+        cx<float> *out = L.sbin + t * TM;
 #pragma unroll
-            for (int k = 0; k <= D; ++k) {
-                ar = fmaf(c[k], hr[k], ar);
-                ai = fmaf(c[k], hi[k], ai);
+        for (int r = 0; r < TM; ++r) {
+            if (r < tm) {
+                const float *c = L.C + r * (D + 1);
+                float ar = 0.f, ai = 0.f;
+#pragma unroll
+                for (int k = 0; k <= D; ++k) {
+                    ar = fmaf(c[k], hr[k], ar);
+                    ai = fmaf(c[k], hi[k], ai);
+                }
+                out[r] = cxmk(ar, ai);
             }
-            out[r] = cxmk(ar, ai);
         }
     }
     __syncthreads();
-    // Phase C: window cell w (cell bin_lo - m + 1 + w) collects tap w - b of
-    // bin b; compensated, stored as (hi.re, hi.im, lo.re, lo.im)
     const int W = ch.nbin + tm - 1;
-    float4 *part = reinterpret_cast<float4 *>(P.partial) + ch.part_off;
-    for (int w = t; w < W; w += nt) {
-        const int blo = max(0, w - tm + 1), bhi = min(ch.nbin - 1, w);
+    float4 *part = reinterpret_cast<float4 *>(A.partial) + ch.part_off;
+    for (int w = t; w < W; w += blockDim.x) {
+        cx<float> v[TM];
+#pragma unroll
+        for (int r = 0; r < TM; ++r) {
+            const int b = min(max(w - r, 0), ch.nbin - 1);
+            v[r] = L.sbin[b * TM + r];
+        }
         float hr = 0.f, hi = 0.f, lr = 0.f, li = 0.f;
-        for (int b = blo; b <= bhi; ++b) {
-            const cx<float> v = L.sbin[b * TM + (w - b)];
-            comp_add(hr, lr, v.re);
-            comp_add(hi, li, v.im);
+#pragma unroll
+        for (int r = 0; r < TM; ++r) {
+            const int b = w - r;
+            if (r < tm && b >= 0 && b < ch.nbin) {
+                comp_add(hr, lr, v[r].re);
+                comp_add(hi, li, v[r].im);
+            }
         }
         part[w] = make_float4(hr, hi, lr, li);
     }
 }
 
+// Launch slots g = blockIdx.x + j gridDim.x; gridDim.x is a multiple of 8 (or
+// the slot count), so every slot a workgroup takes maps to the same XCD.
 template <int TM>
-__global__ __launch_bounds__(256) void k_spread32(PlanDesc P, const cx<float> *__restrict__ f)
+__global__ __launch_bounds__(64) void k_spread32(SpreadArgs A, const cx<float> *__restrict__ f)
 {
     __shared__ Spread32Lds<TM> L;
-    const int cid = P.sp.sched[blockIdx.x];
-    if (cid < 0) return;
-    spread32_wg<TM>(P, cid, f, L);
+    stage_taps(L.C, A.C, 2 * A.m);
+    __syncthreads();
+    for (int g = blockIdx.x; g < A.ngrid; g += gridDim.x) {
+        spread32_slot<TM>(A, f, g, L);
+        __syncthreads();   // LDS reuse by the next slot
+    }
 }
 
 // ===========================================================================
-// Spreading, FP64 plain path (64 threads, items of up to Q64 points)
+// Spreading, FP64 plain path (items of up to Q64 points)
 // ===========================================================================
 constexpr int Q64 = 8;
 
 struct Spread64Lds {
-    cx<double> sitem[64 * 2 * kMaxM];
-    int ibin[64];
-    int runS[64];
-    int runE[64];
+    cx<double> sitem[kItemsPerWg * 2 * kMaxM];
+    int ibin[kItemsPerWg];
+    int runS[kItemsPerWg];
+    int runE[kItemsPerWg];
 };
 
-__device__ void spread64_wg(const PlanDesc &P, int cid, const cx<double> *__restrict__ f,
-                            Spread64Lds &L)
+__global__ __launch_bounds__(64) void k_spread64(SpreadArgs A, const cx<double> *__restrict__ f)
 {
-    const Chunk ch = P.sp.chunks[cid];
-    const int m = P.m1, tm = 2 * m;
-    const int t = threadIdx.x, nt = blockDim.x;
-    for (int b = t; b < ch.nbin; b += nt) {
-        L.runS[b] = -1;
-        L.runE[b] = 0;
+    __shared__ Spread64Lds L;
+    const int g = blockIdx.x, t = threadIdx.x;
+    const Item it = A.items[g * kItemsPerWg + t];
+    const Chunk ch = A.chunks[g];
+    if (ch.nitem == 0) return;
+    const int m = A.m, tm = 2 * m;
+    if (t < ch.nbin) {
+        L.runS[t] = -1;
+        L.runE[t] = 0;
     }
-    if (t < ch.nitem) {
-        const Item it = P.sp.items[ch.item0 + t];
+    if (it.n > 0) {
         double xf[Q64];
         cx<double> fv[Q64];
 #pragma unroll
         for (int q = 0; q < Q64; ++q) {
-            if (q < it.n) {
-                const int p = it.p0 + q;
-                xf[q] = P.sp.frac64[p];
-                fv[q] = f[P.sp.perm[p]];
-            } else {
-                xf[q] = 0.0;
-                fv[q] = cxmk(0.0, 0.0);
-            }
+            const int p = it.p0 + (q < it.n ? q : 0);
+            xf[q] = A.frac64[p];
+            fv[q] = (q < it.n) ? f[A.perm[p]] : cxmk(0.0, 0.0);
         }
         const double inv_m = 1.0 / (double)m;
         for (int r = 0; r < tm; ++r) {
@@ -275,7 +318,7 @@ __device__ void spread64_wg(const PlanDesc &P, int cid, const cx<double> *__rest
 #pragma unroll
             for (int q = 0; q < Q64; ++q) {
                 if (q < it.n) {
-                    const double w = omega64(((double)(r - m + 1) - xf[q]) * inv_m, P.beta1, P.inv_den1);
+                    const double w = omega64(((double)(r - m + 1) - xf[q]) * inv_m, A.beta, A.inv_den);
                     ar = fma(fv[q].re, w, ar);
                     ai = fma(fv[q].im, w, ai);
                 }
@@ -292,8 +335,8 @@ __device__ void spread64_wg(const PlanDesc &P, int cid, const cx<double> *__rest
     }
     __syncthreads();
     const int W = ch.nbin + tm - 1;
-    double2 *part = reinterpret_cast<double2 *>(P.partial) + ch.part_off;
-    for (int w = t; w < W; w += nt) {
+    double2 *part = reinterpret_cast<double2 *>(A.partial) + ch.part_off;
+    for (int w = t; w < W; w += blockDim.x) {
         const int blo = max(0, w - tm + 1), bhi = min(ch.nbin - 1, w);
         double ar = 0.0, ai = 0.0;
         for (int b = blo; b <= bhi; ++b) {
@@ -310,157 +353,127 @@ __device__ void spread64_wg(const PlanDesc &P, int cid, const cx<double> *__rest
     }
 }
 
-__global__ __launch_bounds__(64) void k_spread64(PlanDesc P, const cx<double> *__restrict__ f)
-{
-    __shared__ Spread64Lds L;
-    const int cid = P.sp.sched[blockIdx.x];
-    if (cid < 0) return;
-    spread64_wg(P, cid, f, L);
-}
-
 // ===========================================================================
 // Interpolation
 // ===========================================================================
-struct Interp32Lds {
-    cx<float> Hb[256 * (kDeg + 1)];
-    int ibin[256];
-    int used[256];
-};
-
-__device__ void interp32_wg(const PlanDesc &P, int cid, cx<float> *__restrict__ y, Interp32Lds &L)
+// One thread per item, no barrier: the item's bin coefficients
+// H_k = sum_r C[r][k] h_{c - m + 1 + r} (the transpose of the spreading taps),
+// then y_j = (sum_k H_k T_k(t_j)) / phi_hat_1(N* x_j) for each of its points.
+__device__ void interp32_item(const InterpArgs &A, cx<float> *__restrict__ y, const Item &it,
+                              const float *Cs, const PtRec *__restrict__ rec)
 {
     constexpr int D = kDeg;
-    const Chunk ch = P.ip.chunks[cid];
-    const int m = P.m2, tm = 2 * m;
-    const int t = threadIdx.x, nt = blockDim.x;
-    for (int b = t; b < ch.nbin; b += nt) L.used[b] = 0;
-    __syncthreads();
-    Item it;
-    it.n = 0;
-    if (t < ch.nitem) {
-        it = P.ip.items[ch.item0 + t];
-        const int b = it.bin - ch.bin_lo;
-        L.ibin[t] = b;
-        L.used[b] = 1;
-    }
-    __syncthreads();
-    // Phase B: per used bin, H_k = sum_r C2[r][k] h_{c - m + 1 + r}
-    const cx<float> *h = reinterpret_cast<const cx<float> *>(P.hlin);
-    for (int b = t; b < ch.nbin; b += nt) {
-        if (!L.used[b]) continue;
-        const int lab = ch.bin_lo + b - P.ip_off;
-        const int s0 = lab - m + 1 + P.N2 / 2;
-        float Hr[D + 1], Hi[D + 1];
+    const int m = A.m, tm = 2 * m;
+    const int lab = it.bin - A.ip_off;
+    // the first batch of point records is in flight while H is formed
+    PtRec r[kPtBatch];
 #pragma unroll
-        for (int k = 0; k <= D; ++k) Hr[k] = Hi[k] = 0.f;
-        for (int r = 0; r < tm; ++r) {
-            const cx<float> hv = h[s0 + r];
-            const float *c = P.C2 + r * (D + 1);
+    for (int q = 0; q < kPtBatch; ++q) r[q] = rec[min(q, it.n - 1) * kItemsPerWg];
+    double c[kCorr32 + 1];
 #pragma unroll
-            for (int k = 0; k <= D; ++k) {
-                Hr[k] = fmaf(c[k], hv.re, Hr[k]);
-                Hi[k] = fmaf(c[k], hv.im, Hi[k]);
-            }
-        }
+    for (int k = 0; k <= kCorr32; ++k) c[k] = A.corr[k];
+    const cx<float> *h = reinterpret_cast<const cx<float> *>(A.hlin) + (lab - m + 1 + A.N2 / 2);
+    float Hr[D + 1], Hi[D + 1];
 #pragma unroll
-        for (int k = 0; k <= D; ++k) L.Hb[b * (D + 1) + k] = cxmk(Hr[k], Hi[k]);
-    }
-    __syncthreads();
-    // Phase C: per point, y = (sum_k H_k T_k(t)) / phi_hat_1(N* x)
-    if (t < ch.nitem) {
-        const int b = L.ibin[t];
-        const int lab = ch.bin_lo + b - P.ip_off;
-        float Hr[D + 1], Hi[D + 1];
+    for (int k = 0; k <= D; ++k) Hr[k] = Hi[k] = 0.f;
+    for (int rr = 0; rr < tm; ++rr) {
+        const cx<float> hv = h[rr];
+        const float *cc = Cs + rr * (D + 1);
 #pragma unroll
         for (int k = 0; k <= D; ++k) {
-            const cx<float> v = L.Hb[b * (D + 1) + k];
-            Hr[k] = v.re;
-            Hi[k] = v.im;
+            Hr[k] = fmaf(cc[k], hv.re, Hr[k]);
+            Hi[k] = fmaf(cc[k], hv.im, Hi[k]);
         }
-        for (int p = it.p0; p < it.p0 + it.n; ++p) {
-            const float fr = P.ip.frac32[p];
-            const float yv = fmaf(2.f, fr, -1.f);
-            const float y2 = yv + yv;
-            float T0 = 1.f, T1 = yv;
-            float sr = fmaf(Hr[1], yv, Hr[0]);
-            float si = fmaf(Hi[1], yv, Hi[0]);
+    }
+    for (int q0 = 0; q0 < it.n; q0 += kPtBatch) {
+        if (q0 > 0) {
 #pragma unroll
-            for (int k = 2; k <= D; ++k) {
-                const float T2 = fmaf(y2, T1, -T0);
-                sr = fmaf(Hr[k], T2, sr);
-                si = fmaf(Hi[k], T2, si);
-                T0 = T1;
-                T1 = T2;
+            for (int q = 0; q < kPtBatch; ++q) r[q] = rec[min(q0 + q, it.n - 1) * kItemsPerWg];
+        }
+#pragma unroll
+        for (int q = 0; q < kPtBatch; ++q) {
+            if (q0 + q < it.n) {
+                const float yv = fmaf(2.f, r[q].frac, -1.f);
+                const float y2 = yv + yv;
+                float T0 = 1.f, T1 = yv;
+                float sr = fmaf(Hr[1], yv, Hr[0]);
+                float si = fmaf(Hi[1], yv, Hi[0]);
+#pragma unroll
+                for (int k = 2; k <= D; ++k) {
+                    const float T2 = fmaf(y2, T1, -T0);
+                    sr = fmaf(Hr[k], T2, sr);
+                    si = fmaf(Hi[k], T2, si);
+                    T0 = T1;
+                    T1 = T2;
+                }
+                const double corr = inv_phi1_fixed<kCorr32>(c, A.u_to_x, lab, (double)r[q].frac);
+                y[r[q].perm] = cxmk((float)((double)sr * corr), (float)((double)si * corr));
             }
-            const double corr = inv_phi1(P, lab, (double)fr);
-            y[P.ip.perm[p]] = cxmk((float)((double)sr * corr), (float)((double)si * corr));
         }
     }
 }
 
-__global__ __launch_bounds__(256) void k_interp32(PlanDesc P, cx<float> *__restrict__ y)
+__global__ __launch_bounds__(64) void k_interp32(InterpArgs A, cx<float> *__restrict__ y)
 {
-    __shared__ Interp32Lds L;
-    const int cid = P.ip.sched[blockIdx.x];
-    if (cid < 0) return;
-    interp32_wg(P, cid, y, L);
+    __shared__ float Cs[2 * kMaxM * (kDeg + 1)];
+    stage_taps(Cs, A.C, 2 * A.m);
+    __syncthreads();
+    for (int g = blockIdx.x; g < A.ngrid; g += gridDim.x) {
+        const Item it = A.items[g * kItemsPerWg + threadIdx.x];
+        if (it.n > 0) {
+            const int rec_off = A.chunks[g].rec_off;
+            interp32_item(A, y, it, Cs, A.rec32 + rec_off + threadIdx.x);
+        }
+    }
 }
 
 struct Interp64Lds {
-    cx<double> hw[64 * 2 * kMaxM];
-    int ibin[64];
-    int used[64];
+    cx<double> hw[kItemsPerWg * 2 * kMaxM];
+    int ibin[kItemsPerWg];
+    int used[kItemsPerWg];
 };
 
-__device__ void interp64_wg(const PlanDesc &P, int cid, cx<double> *__restrict__ y, Interp64Lds &L)
+__global__ __launch_bounds__(64) void k_interp64(InterpArgs A, cx<double> *__restrict__ y)
 {
-    const Chunk ch = P.ip.chunks[cid];
-    const int m = P.m2, tm = 2 * m;
-    const int t = threadIdx.x, nt = blockDim.x;
-    for (int b = t; b < ch.nbin; b += nt) L.used[b] = 0;
+    __shared__ Interp64Lds L;
+    const int g = blockIdx.x, t = threadIdx.x;
+    const Item it = A.items[g * kItemsPerWg + t];
+    const Chunk ch = A.chunks[g];
+    if (ch.nitem == 0) return;
+    const int m = A.m, tm = 2 * m;
+    if (t < ch.nbin) L.used[t] = 0;
     __syncthreads();
-    Item it;
-    it.n = 0;
-    if (t < ch.nitem) {
-        it = P.ip.items[ch.item0 + t];
+    if (it.n > 0) {
         const int b = it.bin - ch.bin_lo;
         L.ibin[t] = b;
         L.used[b] = 1;
     }
     __syncthreads();
-    const cx<double> *h = reinterpret_cast<const cx<double> *>(P.hlin);
-    for (int b = t; b < ch.nbin; b += nt) {
-        if (!L.used[b]) continue;
-        const int lab = ch.bin_lo + b - P.ip_off;
-        const int s0 = lab - m + 1 + P.N2 / 2;
-        for (int r = 0; r < tm; ++r) L.hw[b * tm + r] = h[s0 + r];
+    const cx<double> *h = reinterpret_cast<const cx<double> *>(A.hlin);
+    if (t < ch.nbin && L.used[t]) {
+        const int lab = ch.bin_lo + t - A.ip_off;
+        const int s0 = lab - m + 1 + A.N2 / 2;
+        for (int r = 0; r < tm; ++r) L.hw[t * tm + r] = h[s0 + r];
     }
     __syncthreads();
-    if (t < ch.nitem) {
+    if (it.n > 0) {
         const int b = L.ibin[t];
-        const int lab = ch.bin_lo + b - P.ip_off;
+        const int lab = ch.bin_lo + b - A.ip_off;
         const double inv_m = 1.0 / (double)m;
         for (int p = it.p0; p < it.p0 + it.n; ++p) {
-            const double fr = P.ip.frac64[p];
+            const double fr = A.frac64[p];
             double sr = 0.0, si = 0.0;
             for (int r = 0; r < tm; ++r) {
-                const double w = omega64((fr + (double)(m - 1 - r)) * inv_m, P.beta2, P.inv_den2);
+                const double w = omega64((fr + (double)(m - 1 - r)) * inv_m, A.beta, A.inv_den);
                 const cx<double> hv = L.hw[b * tm + r];
                 sr = fma(hv.re, w, sr);
                 si = fma(hv.im, w, si);
             }
-            const double corr = inv_phi1(P, lab, fr);
-            y[P.ip.perm[p]] = cxmk(sr * corr, si * corr);
+            const double x = ((double)lab + fr) * A.u_to_x;
+            const double corr = cheb64(A.corr, A.corr_deg, fma(8.0 * x, x, -1.0));
+            y[A.perm[p]] = cxmk(sr * corr, si * corr);
         }
     }
-}
-
-__global__ __launch_bounds__(64) void k_interp64(PlanDesc P, cx<double> *__restrict__ y)
-{
-    __shared__ Interp64Lds L;
-    const int cid = P.ip.sched[blockIdx.x];
-    if (cid < 0) return;
-    interp64_wg(P, cid, y, L);
 }
 
 // ===========================================================================
@@ -470,48 +483,59 @@ constexpr int kFftVals = 4096;   // complex values per FFT workgroup
 
 // FFT input element q (index mod N2) = merged, deconvolved step-1 output:
 // label l = q (q < N2/2) or q - N2; zero outside I_{G1}.
-__device__ __forceinline__ cx<float> fft_input32(const PlanDesc &P, int q)
+__device__ __forceinline__ cx<float> fft_input32(const FftArgs &A, int q)
 {
-    const int lab = (q < P.N2 / 2) ? q : q - P.N2;
-    if (lab < -P.G1 / 2 || lab >= P.G1 / 2) return cxmk(0.f, 0.f);
-    const int cell = lab + P.G1 / 2;
-    const float4 *part = reinterpret_cast<const float4 *>(P.partial);
+    const int lab = (q < A.N2 / 2) ? q : q - A.N2;
+    if (lab < -A.G1 / 2 || lab >= A.G1 / 2) return cxmk(0.f, 0.f);
+    const int cell = lab + A.G1 / 2;
+    const float4 *part = reinterpret_cast<const float4 *>(A.partial);
     float hr = 0.f, hi = 0.f, lr = 0.f, li = 0.f;
-    const int e1 = P.merge_off[cell + 1];
-    for (int e = P.merge_off[cell]; e < e1; ++e) {
-        const float4 v = part[P.merge_idx[e]];
-        comp_add(hr, lr, v.x);
-        comp_add(hi, li, v.y);
-        lr += v.z;
-        li += v.w;
+    const int e0 = A.merge_off[cell], e1 = A.merge_off[cell + 1];
+    // eight entries at a time: all index loads, then all partial loads
+    for (int e = e0; e < e1; e += 8) {
+        int idx[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) idx[q] = A.merge_idx[(e + q < e1) ? e + q : e0];
+        float4 v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = part[idx[q]];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            if (e + q < e1) {
+                comp_add(hr, lr, v[q].x);
+                comp_add(hi, li, v[q].y);
+                lr += v[q].z;
+                li += v[q].w;
+            }
+        }
     }
-    const double sc = P.deconv[cell];
+    const double sc = A.deconv[cell];
     return cxmk((float)((double)(hr + lr) * sc), (float)((double)(hi + li) * sc));
 }
 
-__device__ __forceinline__ cx<double> fft_input64(const PlanDesc &P, int q)
+__device__ __forceinline__ cx<double> fft_input64(const FftArgs &A, int q)
 {
-    const int lab = (q < P.N2 / 2) ? q : q - P.N2;
-    if (lab < -P.G1 / 2 || lab >= P.G1 / 2) return cxmk(0.0, 0.0);
-    const int cell = lab + P.G1 / 2;
-    const double2 *part = reinterpret_cast<const double2 *>(P.partial);
+    const int lab = (q < A.N2 / 2) ? q : q - A.N2;
+    if (lab < -A.G1 / 2 || lab >= A.G1 / 2) return cxmk(0.0, 0.0);
+    const int cell = lab + A.G1 / 2;
+    const double2 *part = reinterpret_cast<const double2 *>(A.partial);
     double ar = 0.0, ai = 0.0;
-    const int e1 = P.merge_off[cell + 1];
-    for (int e = P.merge_off[cell]; e < e1; ++e) {
-        const double2 v = part[P.merge_idx[e]];
+    const int e1 = A.merge_off[cell + 1];
+    for (int e = A.merge_off[cell]; e < e1; ++e) {
+        const double2 v = part[A.merge_idx[e]];
         ar += v.x;
         ai += v.y;
     }
-    const double sc = P.deconv[cell];
+    const double sc = A.deconv[cell];
     return cxmk(ar * sc, ai * sc);
 }
 
 template <typename T>
-__device__ __forceinline__ cx<T> fft_input(const PlanDesc &P, int q);
+__device__ __forceinline__ cx<T> fft_input(const FftArgs &A, int q);
 template <>
-__device__ __forceinline__ cx<float> fft_input<float>(const PlanDesc &P, int q) { return fft_input32(P, q); }
+__device__ __forceinline__ cx<float> fft_input<float>(const FftArgs &A, int q) { return fft_input32(A, q); }
 template <>
-__device__ __forceinline__ cx<double> fft_input<double>(const PlanDesc &P, int q) { return fft_input64(P, q); }
+__device__ __forceinline__ cx<double> fft_input<double>(const FftArgs &A, int q) { return fft_input64(A, q); }
 
 // forward DFT of size R in registers: X_q = sum_r a_r exp(-2 pi i r q / R)
 template <typename T, int R>
@@ -628,7 +652,7 @@ __device__ void stockham_pass(const cx<T> *src, cx<T> *dst, int Lsub, int B, int
 // Transforms the B length-Lsub sequences in buf[0] in place (result ends up in
 // buf[0] or buf[1]; the returned pointer tells which).
 template <typename T>
-__device__ cx<T> *stockham(cx<T> *buf0, cx<T> *buf1, int Lsub, int B, const int *rad, int npass,
+__device__ cx<T> *stockham(cx<T> *buf0, cx<T> *buf1, int Lsub, int B, const int8_t *rad, int npass,
                            const cx<T> *__restrict__ tw, int tstride)
 {
     cx<T> *src = buf0, *dst = buf1;
@@ -653,14 +677,13 @@ __device__ cx<T> *stockham(cx<T> *buf0, cx<T> *buf1, int Lsub, int B, const int 
 
 // write output k (index mod N2) of the length-N2 transform into hlin if consumed
 template <typename T>
-__device__ __forceinline__ void fft_store(const PlanDesc &P, int k, cx<T> v)
+__device__ __forceinline__ void fft_store(const FftArgs &A, int k, cx<T> v)
 {
-    cx<T> *h = reinterpret_cast<cx<T> *>(P.hlin);
-    const int half = P.N2 / 2;
-    const int s = (k < half) ? k : k - P.N2;
-    const int S = P.fft.S;
-    if (s >= -S && s <= S) h[s + half] = v;
-    if (k == half && half <= S) h[P.N2] = v;   // label +N2/2 equals label -N2/2
+    cx<T> *h = reinterpret_cast<cx<T> *>(A.hlin);
+    const int half = A.N2 / 2;
+    const int s = (k < half) ? k : k - A.N2;
+    if (s >= -A.S && s <= A.S) h[s + half] = v;
+    if (k == half && half <= A.S) h[A.N2] = v;   // label +N2/2 equals label -N2/2
 }
 
 template <typename T>
@@ -670,34 +693,34 @@ struct FftLds {
 
 // Whole transform in one workgroup (N2 <= kFftVals)
 template <typename T>
-__global__ __launch_bounds__(256) void k_fft_single(PlanDesc P)
+__global__ __launch_bounds__(256) void k_fft_single(FftArgs A)
 {
     __shared__ FftLds<T> L;
-    const int N2 = P.N2;
-    for (int q = threadIdx.x; q < N2; q += blockDim.x) L.buf[0][q] = fft_input<T>(P, q);
+    const int N2 = A.N2;
+    for (int q = threadIdx.x; q < N2; q += blockDim.x) L.buf[0][q] = fft_input<T>(A, q);
     __syncthreads();
-    const cx<T> *tw = reinterpret_cast<const cx<T> *>(P.tw);
-    cx<T> *res = stockham<T>(L.buf[0], L.buf[1], N2, 1, P.fft.radA, P.fft.npassA, tw, 1);
-    for (int k = threadIdx.x; k < N2; k += blockDim.x) fft_store<T>(P, k, res[k]);
+    const cx<T> *tw = reinterpret_cast<const cx<T> *>(A.tw);
+    cx<T> *res = stockham<T>(L.buf[0], L.buf[1], N2, 1, A.radA, A.npassA, tw, 1);
+    for (int k = threadIdx.x; k < N2; k += blockDim.x) fft_store<T>(A, k, res[k]);
 }
 
 // Four-step stage A: for columns j1, length-n2 transforms over j2 of
 // x[j1 + n1 j2], times exp(-2 pi i j1 k2 / N2), stored to Y[j1 n2 + k2].
 template <typename T>
-__global__ __launch_bounds__(256) void k_fft_stageA(PlanDesc P)
+__global__ __launch_bounds__(256) void k_fft_stageA(FftArgs A)
 {
     __shared__ FftLds<T> L;
-    const int n1 = P.fft.n1, n2 = P.fft.n2, B = P.fft.batchA;
+    const int n1 = A.n1, n2 = A.n2, B = A.batchA;
     const int j1_0 = blockIdx.x * B;
     const int nb = min(B, n1 - j1_0);
     for (int idx = threadIdx.x; idx < nb * n2; idx += blockDim.x) {
         const int j2 = idx / nb, bl = idx - j2 * nb;
-        L.buf[0][bl * n2 + j2] = fft_input<T>(P, j1_0 + bl + n1 * j2);
+        L.buf[0][bl * n2 + j2] = fft_input<T>(A, j1_0 + bl + n1 * j2);
     }
     __syncthreads();
-    const cx<T> *tw = reinterpret_cast<const cx<T> *>(P.tw);
-    cx<T> *res = stockham<T>(L.buf[0], L.buf[1], n2, nb, P.fft.radA, P.fft.npassA, tw, n1);
-    cx<T> *Y = reinterpret_cast<cx<T> *>(P.Y);
+    const cx<T> *tw = reinterpret_cast<const cx<T> *>(A.tw);
+    cx<T> *res = stockham<T>(L.buf[0], L.buf[1], n2, nb, A.radA, A.npassA, tw, n1);
+    cx<T> *Y = reinterpret_cast<cx<T> *>(A.Y);
     for (int idx = threadIdx.x; idx < nb * n2; idx += blockDim.x) {
         const int bl = idx / n2, k2 = idx - bl * n2;
         const int j1 = j1_0 + bl;
@@ -708,23 +731,23 @@ __global__ __launch_bounds__(256) void k_fft_stageA(PlanDesc P)
 // Four-step stage B: for columns k2, length-n1 transforms over j1 of
 // Y[j1 n2 + k2]; output k1 is X[k2 + n2 k1].
 template <typename T>
-__global__ __launch_bounds__(256) void k_fft_stageB(PlanDesc P)
+__global__ __launch_bounds__(256) void k_fft_stageB(FftArgs A)
 {
     __shared__ FftLds<T> L;
-    const int n1 = P.fft.n1, n2 = P.fft.n2, B = P.fft.batchB;
+    const int n1 = A.n1, n2 = A.n2, B = A.batchB;
     const int k2_0 = blockIdx.x * B;
     const int nb = min(B, n2 - k2_0);
-    const cx<T> *Y = reinterpret_cast<const cx<T> *>(P.Y);
+    const cx<T> *Y = reinterpret_cast<const cx<T> *>(A.Y);
     for (int idx = threadIdx.x; idx < nb * n1; idx += blockDim.x) {
         const int j1 = idx / nb, bl = idx - j1 * nb;
         L.buf[0][bl * n1 + j1] = Y[(size_t)j1 * n2 + k2_0 + bl];
     }
     __syncthreads();
-    const cx<T> *tw = reinterpret_cast<const cx<T> *>(P.tw);
-    cx<T> *res = stockham<T>(L.buf[0], L.buf[1], n1, nb, P.fft.radB, P.fft.npassB, tw, n2);
+    const cx<T> *tw = reinterpret_cast<const cx<T> *>(A.tw);
+    cx<T> *res = stockham<T>(L.buf[0], L.buf[1], n1, nb, A.radB, A.npassB, tw, n2);
     for (int idx = threadIdx.x; idx < nb * n1; idx += blockDim.x) {
         const int bl = idx / n1, k1 = idx - bl * n1;
-        fft_store<T>(P, k2_0 + bl + n2 * k1, res[bl * n1 + k1]);
+        fft_store<T>(A, k2_0 + bl + n2 * k1, res[bl * n1 + k1]);
     }
 }
 
@@ -732,36 +755,50 @@ __global__ __launch_bounds__(256) void k_fft_stageB(PlanDesc P)
 // Launchers
 // ===========================================================================
 template <typename T>
-static void launch_fft(const PlanDesc &P, hipStream_t s)
+static void launch_fft(const FftArgs &A, hipStream_t s)
 {
-    if (P.fft.n1 == 1) {
-        hipLaunchKernelGGL((k_fft_single<T>), dim3(1), dim3(kFftThreads), 0, s, P);
+    if (A.n1 == 1) {
+        hipLaunchKernelGGL((k_fft_single<T>), dim3(1), dim3(A.threadsA), 0, s, A);
     } else {
-        const int gA = (P.fft.n1 + P.fft.batchA - 1) / P.fft.batchA;
-        const int gB = (P.fft.n2 + P.fft.batchB - 1) / P.fft.batchB;
-        hipLaunchKernelGGL((k_fft_stageA<T>), dim3(gA), dim3(kFftThreads), 0, s, P);
-        hipLaunchKernelGGL((k_fft_stageB<T>), dim3(gB), dim3(kFftThreads), 0, s, P);
+        const int gA = (A.n1 + A.batchA - 1) / A.batchA;
+        const int gB = (A.n2 + A.batchB - 1) / A.batchB;
+        hipLaunchKernelGGL((k_fft_stageA<T>), dim3(gA), dim3(A.threadsA), 0, s, A);
+        hipLaunchKernelGGL((k_fft_stageB<T>), dim3(gB), dim3(A.threadsB), 0, s, A);
     }
 }
 
-hipError_t launch_exec(const PlanDesc &P, const void *f, void *y, hipStream_t s)
+// grid of a slot-looping launch: all slots, or a multiple of 8 below the cap
+static int grid_of(int nslots, int cap)
 {
+    if (cap <= 0 || nslots <= cap) return nslots;
+    return std::max(8, cap / 8 * 8);
+}
+
+hipError_t launch_exec(const PlanDev &P, const void *f, void *y, hipStream_t s, hipEvent_t *ev)
+{
+    if (ev) (void)hipEventRecord(ev[0], s);
     if (P.prec == NNFFT_FP32_COMP) {
         const cx<float> *fin = reinterpret_cast<const cx<float> *>(f);
-        if (2 * P.m1 <= 16)
-            hipLaunchKernelGGL((k_spread32<16>), dim3(P.sp.ngrid), dim3(P.items_per_wg), 0, s, P, fin);
+        const int gs = grid_of(P.sp.ngrid, P.sp_grid_max), gi = grid_of(P.ip.ngrid, P.ip_grid_max);
+        if (2 * P.sp.m <= 16)
+            hipLaunchKernelGGL((k_spread32<16>), dim3(gs), dim3(kItemsPerWg), 0, s, P.sp, fin);
         else
-            hipLaunchKernelGGL((k_spread32<32>), dim3(P.sp.ngrid), dim3(P.items_per_wg), 0, s, P, fin);
-        launch_fft<float>(P, s);
-        hipLaunchKernelGGL(k_interp32, dim3(P.ip.ngrid), dim3(P.items_per_wg), 0, s, P,
+            hipLaunchKernelGGL((k_spread32<32>), dim3(gs), dim3(kItemsPerWg), 0, s, P.sp, fin);
+        if (ev) (void)hipEventRecord(ev[1], s);
+        launch_fft<float>(P.fft, s);
+        if (ev) (void)hipEventRecord(ev[2], s);
+        hipLaunchKernelGGL(k_interp32, dim3(gi), dim3(kItemsPerWg), 0, s, P.ip,
                            reinterpret_cast<cx<float> *>(y));
     } else {
-        hipLaunchKernelGGL(k_spread64, dim3(P.sp.ngrid), dim3(P.items_per_wg), 0, s, P,
+        hipLaunchKernelGGL(k_spread64, dim3(P.sp.ngrid), dim3(kItemsPerWg), 0, s, P.sp,
                            reinterpret_cast<const cx<double> *>(f));
-        launch_fft<double>(P, s);
-        hipLaunchKernelGGL(k_interp64, dim3(P.ip.ngrid), dim3(P.items_per_wg), 0, s, P,
+        if (ev) (void)hipEventRecord(ev[1], s);
+        launch_fft<double>(P.fft, s);
+        if (ev) (void)hipEventRecord(ev[2], s);
+        hipLaunchKernelGGL(k_interp64, dim3(P.ip.ngrid), dim3(kItemsPerWg), 0, s, P.ip,
                            reinterpret_cast<cx<double> *>(y));
     }
+    if (ev) (void)hipEventRecord(ev[3], s);
     return hipGetLastError();
 }
 

@@ -37,12 +37,15 @@ void hip_check(hipError_t e, const char *what)
 // Node layout of one side, built on the host.
 struct SideHost {
     std::vector<int32_t> perm;
-    std::vector<float> frac32;
+    std::vector<PtRec> rec32;
     std::vector<double> frac64;
     std::vector<Item> items;
     std::vector<Chunk> chunks;
     std::vector<int32_t> chunk_block;
-    std::vector<int32_t> sched;
+    std::vector<int32_t> chunk_item0;   // first item of each chunk
+    std::vector<Chunk> launch;          // chunks in launch order, empty ones pad
+    std::vector<Item> launch_items;     // 64 items per launch slot, n = 0 pads
+    std::vector<PtRec> trec32;          // FP32: records in per-chunk transposed blocks
     int64_t part_cells = 0;
     int64_t nblocks = 0;
 };
@@ -54,28 +57,31 @@ struct Layout {
     int IW;             // items per workgroup (= threads)
 };
 
-// Rule table measured on MI355X: items of ~4 points for FP32 at 2^20 nodes,
-// growing with the node count so that a launch has a few workgroups per CU;
+// Rule table measured on MI355X: one-wavefront workgroups of 64 items; items
+// of up to Q points with Q growing with the node count (16 at 2^20 nodes,
+// 32 at most on the FP32 path, 8 on the FP64 path) so that a launch keeps a
+// few workgroups per CU;
 // blocks of 2^17 nodes (1 MB of c64 coefficients, well inside one XCD's L2),
 // split into 8 when that keeps them >= 2^14 nodes so every XCD has a block.
 Layout choose_layout(int64_t M, bool fp32)
 {
     Layout L;
-    L.IW = fp32 ? 256 : 64;
+    L.IW = kItemsPerWg;
     const int64_t cus = 256;
     const int64_t target_wg = 4 * cus;
     int64_t q = M / (L.IW * target_wg);
-    int Q = 1;
-    while (Q < q && Q < (fp32 ? 16 : 8)) Q *= 2;
-    L.Q = std::max(1, Q);
-    if (!fp32) L.Q = std::min(L.Q, 8);
+    int Q = 2;
+    while (Q < q && Q < (fp32 ? 32 : 8)) Q *= 2;
+    L.Q = Q;
     const int64_t bmax = fp32 ? (int64_t)1 << 17 : (int64_t)1 << 16;
     const int64_t bmin = (int64_t)1 << 14;
     int64_t nblk = (M + bmax - 1) / bmax;
     if (nblk < 8 && M >= 8 * bmin) nblk = 8;
     if (nblk < 1) nblk = 1;
     L.block = (M + nblk - 1) / nblk;
+    // overrides for tuning sweeps
     if (const char *e = std::getenv("NNFFT_ITEM_POINTS")) L.Q = std::max(1, std::min(fp32 ? 64 : 8, atoi(e)));
+    if (const char *e = std::getenv("NNFFT_BLOCK_POINTS")) L.block = std::max<int64_t>(1, atoll(e));
     return L;
 }
 
@@ -100,7 +106,7 @@ bool build_side(const std::vector<double> &nodes, double scale, int64_t off, int
         fr[k] = t - c;
     }
     S.perm.assign(M, 0);
-    if (fp32) S.frac32.assign(M, 0.f);
+    if (fp32) S.rec32.assign(M, PtRec{0, 0.f});
     else S.frac64.assign(M, 0.0);
     std::vector<int32_t> sbin(M);
     std::vector<int64_t> cnt(nbins + 1);
@@ -119,7 +125,7 @@ bool build_side(const std::vector<double> &nodes, double scale, int64_t off, int
             if (fp32) {
                 float f = (float)fr[k];
                 if (!(f < 1.0f)) f = 0.99999994f;   // keep the offset inside [0, 1)
-                S.frac32[pos] = f;
+                S.rec32[pos] = PtRec{(int32_t)k, f};
             } else {
                 S.frac64[pos] = fr[k];
             }
@@ -147,7 +153,6 @@ bool build_side(const std::vector<double> &nodes, double scale, int64_t off, int
             size_t cj = ci;
             while (cj < it1 && (int)(cj - ci) < L.IW && S.items[cj].bin - blo < L.IW) ++cj;
             Chunk c{};
-            c.item0 = (int32_t)ci;
             c.nitem = (int32_t)(cj - ci);
             c.bin_lo = blo;
             c.nbin = S.items[cj - 1].bin - blo + 1;
@@ -155,6 +160,7 @@ bool build_side(const std::vector<double> &nodes, double scale, int64_t off, int
             if (m > 0) part += c.nbin + 2 * m - 1;
             S.chunks.push_back(c);
             S.chunk_block.push_back((int32_t)blk);
+            S.chunk_item0.push_back((int32_t)ci);
             ci = cj;
         }
     }
@@ -163,20 +169,60 @@ bool build_side(const std::vector<double> &nodes, double scale, int64_t off, int
     // so the chunks of block b go to slots with w % 8 == b % 8 and all
     // gathers/scatters of a block stay in one XCD's L2.
     const int nx = 8;
+    std::vector<int32_t> order;   // launch slot -> chunk id (-1: empty)
     if (S.nblocks >= nx) {
         std::vector<std::vector<int32_t>> lists(nx);
         for (size_t c = 0; c < S.chunks.size(); ++c) lists[S.chunk_block[c] % nx].push_back((int32_t)c);
         size_t mx = 0;
         for (auto &l : lists) mx = std::max(mx, l.size());
-        S.sched.assign(mx * nx, -1);
+        order.assign(mx * nx, -1);
         for (int x = 0; x < nx; ++x)
-            for (size_t j = 0; j < lists[x].size(); ++j) S.sched[j * nx + x] = lists[x][j];
+            for (size_t j = 0; j < lists[x].size(); ++j) order[j * nx + x] = lists[x][j];
     } else {
-        S.sched.resize(S.chunks.size());
-        for (size_t c = 0; c < S.chunks.size(); ++c) S.sched[c] = (int32_t)c;
+        order.resize(S.chunks.size());
+        for (size_t c = 0; c < S.chunks.size(); ++c) order[c] = (int32_t)c;
+    }
+    const Chunk empty{0, 0, 0, 0, 0, 0, 0, 0};
+    const Item pad_item{0, 0, 0, 0};
+    S.launch.assign(order.size(), empty);
+    S.launch_items.assign(order.size() * kItemsPerWg, pad_item);
+    int64_t roff = 0;
+    for (size_t g = 0; g < order.size(); ++g) {
+        if (order[g] < 0) continue;
+        Chunk c = S.chunks[order[g]];
+        const int32_t i0 = S.chunk_item0[order[g]];
+        int qmax = 0;
+        for (int i = 0; i < c.nitem; ++i) {
+            S.launch_items[g * kItemsPerWg + i] = S.items[i0 + i];
+            qmax = std::max(qmax, (int)S.items[i0 + i].n);
+        }
+        c.qmax = qmax;
+        c.rec_off = (int32_t)roff;
+        if (fp32) {
+            // transposed block: point q of item t at rec_off + 64 q + t
+            S.trec32.resize((size_t)(roff + (int64_t)qmax * kItemsPerWg), PtRec{0, 0.f});
+            for (int i = 0; i < c.nitem; ++i) {
+                const Item &it = S.items[i0 + i];
+                for (int q = 0; q < it.n; ++q)
+                    S.trec32[(size_t)(roff + (int64_t)q * kItemsPerWg + i)] = S.rec32[(size_t)(it.p0 + q)];
+            }
+            roff += (int64_t)qmax * kItemsPerWg;
+        }
+        S.launch[g] = c;
+    }
+    if (roff >= ((int64_t)1 << 31)) {
+        err = "too many padded records";
+        return false;
     }
     return true;
 }
+
+// FFT factorization chosen at plan time (copied into FftArgs)
+struct FftPlan {
+    int32_t N2 = 0, n1 = 0, n2 = 0, npassA = 0, npassB = 0;
+    int radA[kMaxPasses] = {}, radB[kMaxPasses] = {};
+    int32_t batchA = 0, batchB = 0, threadsA = 0, threadsB = 0, S = 0;
+};
 
 // largest-square-ish factorization N2 = n1 * n2 with both parts <= limit
 bool fft_factor(int64_t N2, int64_t limit, int64_t &n1, int64_t &n2)
@@ -204,12 +250,21 @@ bool fft_factor(int64_t N2, int64_t limit, int64_t &n1, int64_t &n2)
 // ---------------------------------------------------------------------------
 struct nnfft_plan_s {
     nnfft_info_t info{};
-    PlanDesc desc{};
+    PlanDev desc{};
     std::vector<void *> allocs;
     int64_t bytes = 0;
+    std::vector<hipEvent_t> prof_ev;   // 4 events per profiled exec
+    int prof_max = 0, prof_used = 0;
 
+    void drop_events()
+    {
+        for (hipEvent_t e : prof_ev) (void)hipEventDestroy(e);
+        prof_ev.clear();
+        prof_max = prof_used = 0;
+    }
     ~nnfft_plan_s()
     {
+        drop_events();
         for (void *p : allocs) (void)hipFree(p);
     }
     template <typename T>
@@ -308,11 +363,12 @@ static nnfft_status plan_impl(nnfft_plan_t *out, int64_t N, int64_t M1, int64_t 
             return fail(NNFFT_ERR_UNSUPPORTED, "window polynomial misses FP32 accuracy for these sigma, m");
     }
     double corr_err = 0.0;
-    std::vector<double> corr = fit_inverse_phi1(P, fp32 ? 1e-9 : 1e-14, kMaxCorrDeg, &corr_err);
+    std::vector<double> corr = fit_inverse_phi1(P, fp32 ? 1e-9 : 1e-14, fp32 ? kCorr32 : kMaxCorrDeg, &corr_err);
     P.corr_degree = (int32_t)corr.size() - 1;
     P.corr_fit_err = corr_err;
     if (corr_err > (fp32 ? 1e-8 : 1e-12))
         return fail(NNFFT_ERR_UNSUPPORTED, "1/phi_hat_1 series does not converge for this sigma1");
+    if (fp32) corr.resize(kCorr32 + 1, 0.0);   // zero-padded to the unrolled length
 
     std::vector<double> deconv(P.G1);
     for (int64_t c = 0; c < P.G1; ++c) {
@@ -359,10 +415,17 @@ static nnfft_status plan_impl(nnfft_plan_t *out, int64_t N, int64_t M1, int64_t 
     }
 
     // FFT factorization -----------------------------------------------------
-    FftDesc fd{};
+    FftPlan fd{};
     fd.N2 = (int32_t)P.N2;
-    const int64_t single_max = 4096;
+    // one workgroup for short transforms; longer ones as two launches of
+    // many workgroups (one or two columns each) so that the partial merge in
+    // the first stage's load runs with enough workgroups in flight
+    const int64_t single_max = 1024;
     const int kvals = 4096;
+    auto threads_for = [](int64_t vals) {
+        int64_t t = (vals + 63) / 64 * 64;
+        return (int32_t)std::max<int64_t>(64, std::min<int64_t>(256, t));
+    };
     if (P.N2 <= single_max) {
         const std::vector<int> r = radix_passes(P.N2);
         if (r.empty() || (int)r.size() > kMaxPasses) return fail(NNFFT_ERR_UNSUPPORTED, "FFT length not 2,3,5-smooth");
@@ -370,6 +433,7 @@ static nnfft_status plan_impl(nnfft_plan_t *out, int64_t N, int64_t M1, int64_t 
         fd.n2 = (int32_t)P.N2;
         fd.npassA = (int32_t)r.size();
         std::copy(r.begin(), r.end(), fd.radA);
+        fd.threadsA = 256;
     } else {
         int64_t n1, n2;
         if (!fft_factor(P.N2, kvals, n1, n2)) return fail(NNFFT_ERR_UNSUPPORTED, "FFT length cannot be split");
@@ -381,8 +445,10 @@ static nnfft_status plan_impl(nnfft_plan_t *out, int64_t N, int64_t M1, int64_t 
         fd.npassB = (int32_t)rB.size();
         std::copy(rA.begin(), rA.end(), fd.radA);
         std::copy(rB.begin(), rB.end(), fd.radB);
-        fd.batchA = (int32_t)std::max<int64_t>(1, std::min<int64_t>(n1, kvals / n2));
-        fd.batchB = (int32_t)std::max<int64_t>(1, std::min<int64_t>(n2, kvals / n1));
+        fd.batchA = (int32_t)std::max<int64_t>(1, std::min<int64_t>(n1 / 128, kvals / n2));
+        fd.batchB = (int32_t)std::max<int64_t>(1, std::min<int64_t>(n2 / 128, kvals / n1));
+        fd.threadsA = threads_for((int64_t)fd.batchA * n2);
+        fd.threadsB = threads_for((int64_t)fd.batchB * n1);
     }
     {
         const double U = (double)P.N2 * (double)P.N_star / (2.0 * (double)P.N1);
@@ -393,53 +459,71 @@ static nnfft_status plan_impl(nnfft_plan_t *out, int64_t N, int64_t M1, int64_t 
     // device upload -----------------------------------------------------------
     nnfft_plan_s *pl = new nnfft_plan_s();
     try {
-        PlanDesc &D = pl->desc;
+        PlanDev &D = pl->desc;
         D.prec = prec;
-        D.m1 = m1;
-        D.m2 = m2;
-        D.G1 = (int32_t)P.G1;
-        D.N2 = (int32_t)P.N2;
-        D.corr_deg = P.corr_degree;
-        D.ip_off = (int32_t)(P.N2 / 2);
-        D.items_per_wg = lay1.IW;
-        D.beta1 = P.beta1;
-        D.beta2 = P.beta2;
-        D.inv_den1 = 1.0 / (1.0 - std::exp(-2.0 * P.beta1));
-        D.inv_den2 = 1.0 / (1.0 - std::exp(-2.0 * P.beta2));
-        D.u_to_x = (double)P.N1 / ((double)P.N2 * (double)P.N_star);
-        D.fft = fd;
-        auto side = [&](SideHost &S, SideDesc &SD) {
-            SD.items = pl->upload(S.items, s);
-            SD.chunks = pl->upload(S.chunks, s);
-            SD.sched = pl->upload(S.sched, s);
-            SD.perm = pl->upload(S.perm, s);
-            if (fp32) SD.frac32 = pl->upload(S.frac32, s);
-            else SD.frac64 = pl->upload(S.frac64, s);
-            SD.ngrid = (int32_t)S.sched.size();
-            SD.nchunks = (int32_t)S.chunks.size();
-        };
-        side(sp, D.sp);
-        side(ip, D.ip);
+        if (const char *e = std::getenv("NNFFT_GRID_MAX")) D.sp_grid_max = D.ip_grid_max = atoi(e);
+        SpreadArgs &SA = D.sp;
+        InterpArgs &IA = D.ip;
+        FftArgs &FA = D.fft;
+        SA.items = pl->upload(sp.launch_items, s);
+        SA.chunks = pl->upload(sp.launch, s);
+        SA.ngrid = (int32_t)sp.launch.size();
+        SA.m = m1;
+        SA.beta = P.beta1;
+        SA.inv_den = 1.0 / (1.0 - std::exp(-2.0 * P.beta1));
+        IA.items = pl->upload(ip.launch_items, s);
+        IA.chunks = pl->upload(ip.launch, s);
+        IA.ngrid = (int32_t)ip.launch.size();
+        IA.m = m2;
+        IA.beta = P.beta2;
+        IA.inv_den = 1.0 / (1.0 - std::exp(-2.0 * P.beta2));
+        IA.N2 = (int32_t)P.N2;
+        IA.ip_off = (int32_t)(P.N2 / 2);
+        IA.u_to_x = (double)P.N1 / ((double)P.N2 * (double)P.N_star);
+        IA.corr = pl->upload(corr, s);
+        IA.corr_deg = P.corr_degree;
         if (fp32) {
+            SA.rec32 = pl->upload(sp.trec32, s);
+            IA.rec32 = pl->upload(ip.trec32, s);
             std::vector<float> c1(C1d.begin(), C1d.end()), c2(C2d.begin(), C2d.end());
-            D.C1 = pl->upload(c1, s);
-            D.C2 = pl->upload(c2, s);
+            SA.C = pl->upload(c1, s);
+            IA.C = pl->upload(c2, s);
+        } else {
+            SA.perm = pl->upload(sp.perm, s);
+            SA.frac64 = pl->upload(sp.frac64, s);
+            IA.perm = pl->upload(ip.perm, s);
+            IA.frac64 = pl->upload(ip.frac64, s);
         }
-        D.corr = pl->upload(corr, s);
-        D.deconv = pl->upload(deconv, s);
-        D.merge_off = pl->upload(moff, s);
-        D.merge_idx = pl->upload(midx, s);
         const size_t csz = fp32 ? 8 : 16;
+        SA.partial = pl->scratch((size_t)sp.part_cells * 16);
+        FA.partial = SA.partial;
+        FA.merge_off = pl->upload(moff, s);
+        FA.merge_idx = pl->upload(midx, s);
+        FA.deconv = pl->upload(deconv, s);
         if (fp32) {
             std::vector<float> tw32(tw.begin(), tw.end());
-            D.tw = pl->upload(tw32, s);
+            FA.tw = pl->upload(tw32, s);
         } else {
-            D.tw = pl->upload(tw, s);
+            FA.tw = pl->upload(tw, s);
         }
-        D.partial = pl->scratch((size_t)sp.part_cells * 16);
-        D.X = nullptr;
-        D.Y = pl->scratch((size_t)P.N2 * csz);
-        D.hlin = pl->scratch((size_t)(P.N2 + 1) * csz);
+        FA.Y = pl->scratch((size_t)P.N2 * csz);
+        FA.hlin = pl->scratch((size_t)(P.N2 + 1) * csz);
+        IA.hlin = FA.hlin;
+        FA.N2 = (int32_t)P.N2;
+        FA.G1 = (int32_t)P.G1;
+        FA.n1 = fd.n1;
+        FA.n2 = fd.n2;
+        FA.batchA = fd.batchA;
+        FA.batchB = fd.batchB;
+        FA.threadsA = fd.threadsA;
+        FA.threadsB = fd.threadsB;
+        FA.S = fd.S;
+        FA.npassA = fd.npassA;
+        FA.npassB = fd.npassB;
+        for (int i = 0; i < kMaxPasses; ++i) {
+            FA.radA[i] = (int8_t)fd.radA[i];
+            FA.radB[i] = (int8_t)fd.radB[i];
+        }
         hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
         P.device_bytes = pl->bytes;
         P.block_points = lay1.block;
@@ -494,7 +578,9 @@ nnfft_status nnfft_plan(nnfft_plan_t *out, int64_t N, int64_t M1, int64_t M2, do
 nnfft_status nnfft_exec(nnfft_plan_t p, const void *f, void *y, void *stream)
 {
     if (!p || !f || !y) return fail(NNFFT_ERR_ARG, "null argument");
-    const hipError_t e = launch_exec(p->desc, f, y, static_cast<hipStream_t>(stream));
+    hipEvent_t *ev = nullptr;
+    if (p->prof_used < p->prof_max) ev = &p->prof_ev[4 * (size_t)p->prof_used++];
+    const hipError_t e = launch_exec(p->desc, f, y, static_cast<hipStream_t>(stream), ev);
     if (e != hipSuccess) return fail(NNFFT_ERR_DEVICE, std::string("launch: ") + hipGetErrorString(e));
     return NNFFT_OK;
 }
@@ -514,6 +600,48 @@ nnfft_status nnfft_info(nnfft_plan_t p, nnfft_info_t *out)
 {
     if (!p || !out) return fail(NNFFT_ERR_ARG, "null argument");
     *out = p->info;
+    return NNFFT_OK;
+}
+
+nnfft_status nnfft_profile_start(nnfft_plan_t p, int max_execs)
+{
+    if (!p || max_execs < 1) return fail(NNFFT_ERR_ARG, "bad argument");
+    p->drop_events();
+    p->prof_ev.resize(4 * (size_t)max_execs);
+    for (auto &e : p->prof_ev) {
+        if (hipEventCreate(&e) != hipSuccess) {
+            e = nullptr;
+            p->drop_events();
+            return fail(NNFFT_ERR_DEVICE, "hipEventCreate failed");
+        }
+    }
+    p->prof_max = max_execs;
+    p->prof_used = 0;
+    return NNFFT_OK;
+}
+
+nnfft_status nnfft_profile_stop(nnfft_plan_t p, double *stage_ms, int *nexecs)
+{
+    if (!p || !stage_ms) return fail(NNFFT_ERR_ARG, "bad argument");
+    const int n = p->prof_used;
+    double acc[3] = {0.0, 0.0, 0.0};
+    if (n > 0 && hipEventSynchronize(p->prof_ev[4 * (size_t)(n - 1) + 3]) != hipSuccess) {
+        p->drop_events();
+        return fail(NNFFT_ERR_DEVICE, "hipEventSynchronize failed");
+    }
+    for (int i = 0; i < n; ++i)
+        for (int s = 0; s < 3; ++s) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, p->prof_ev[4 * (size_t)i + s], p->prof_ev[4 * (size_t)i + s + 1]) !=
+                hipSuccess) {
+                p->drop_events();
+                return fail(NNFFT_ERR_DEVICE, "hipEventElapsedTime failed");
+            }
+            acc[s] += ms;
+        }
+    for (int s = 0; s < 3; ++s) stage_ms[s] = n > 0 ? acc[s] / n : 0.0;
+    if (nexecs) *nexecs = n;
+    p->drop_events();
     return NNFFT_OK;
 }
 
