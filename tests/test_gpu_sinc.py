@@ -1,0 +1,136 @@
+"""GPU parity of the fast sinc transform (Algorithm 6.1) against the FP64 oracle.
+
+The GPU chain (quadrature on the host in FP64, NNFFT on the nodes a_k and
+z_j / 2, multiplication by the weights w_j, NNFFT on -z_j / 2 and b_l) is
+compared with the oracle's own Algorithm 6.1 on the same inputs, and on
+sampled outputs with the direct sum (6.2).
+
+Tolerances (relative l-infinity error against max |h_oracle|):
+  FP64 plain  1e-12
+  FP32        2e-5 * max(1, kappa / 4.62): two chained NNFFTs.  The first
+              transform's error delta_j (<= 1e-5 max|g| by the NNFFT gate) enters
+              the second only through sum_j w_j delta_j e^(...), and the weights
+              are positive with sum 1, so it adds at most 1e-5 max|g|; max|g| is
+              reached at z = 0 where g(0) = sum c_k = h at coincident nodes up to
+              the sinc decay, so both halves are of the size of max|h|.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2107_02671_amd as P
+from paper_2107_02671_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FP64, FP32 = P.NNFFT_FP64_PLAIN, P.NNFFT_FP32_COMP
+GL, CC = P.SINC_QUAD_GAUSS_LEGENDRE, P.SINC_QUAD_CLENSHAW_CURTIS
+DEV = "cuda:0"
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def tol(prec, m):
+    if prec == FP64:
+        return 1e-12
+    return 2e-5 * (1.0 if m >= 6 else 3.0)
+
+
+def gpu_sinc(N, a, b, c, n_quad, quad, m, prec):
+    _say(f"[gpu] sinc N={N} L1={len(a)} L2={len(b)} quad={quad} n={n_quad} m={m} prec={prec}")
+    cdt = torch.complex64 if prec == FP32 else torch.complex128
+    sp = P.SincPlan(N, torch.tensor(a, device=DEV), torch.tensor(b, device=DEV), n_quad, quad,
+                    2.0, 2.0, m, m, prec)
+    try:
+        h = sp(torch.tensor(c, dtype=cdt, device=DEV))
+        torch.cuda.synchronize()
+        info = sp.info
+    finally:
+        sp.close()
+    return h.cpu().numpy().astype(np.complex128), info
+
+
+def einf(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+@pytest.mark.parametrize("quad,nq", [(GL, lambda N: 2 * N), (CC, lambda N: 4 * N)], ids=["gl2N", "cc4N"])
+def test_sinc_parity(prec, quad, nq):
+    # the sinc workload at reduced length: N = 1024, L1 = L2 = 2^14, Chebyshev nodes
+    N, a, b, c, w = W.nnfft_inputs("sinc", 1 << 14, 1 << 14)
+    n_quad = nq(N)
+    h, info = gpu_sinc(N, a, b, c, n_quad, quad, 6, prec)
+    ho = oracle.sinc_fast(N, a, c, b, n_quad, quad, 2.0, 2.0, 6, 6)
+    e = einf(h, ho)
+    _say(f"    E_inf vs oracle Algorithm 6.1 = {e:.3e}; nodes {info[0]['M2']}, N2 = {info[0]['N2']}")
+    assert info[0]["M2"] == (n_quad if quad == GL else n_quad + 1)
+    assert e <= tol(prec, 6)
+    # real coefficients: the transform is real up to its error
+    assert np.abs(h.imag).max() <= tol(prec, 6) * np.abs(ho).max()
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_sinc_full_size_against_direct_sum(prec):
+    # N = 1024, L1 = L2 = 2^18, Gauss-Legendre 2048 nodes (the benchmarked
+    # sinc workload): all outputs against the oracle's Algorithm 6.1, 512
+    # sampled outputs against the direct sum (6.2) within Theorem 6.2
+    N, a, b, c, w = W.nnfft_inputs("sinc")
+    h, info = gpu_sinc(N, a, b, c, w["n_quad"], GL, w["m"], prec)
+    ho = oracle.sinc_fast(N, a, c, b, w["n_quad"], oracle.QUAD_GAUSS_LEGENDRE, 2.0, 2.0, 6, 6)
+    e = einf(h, ho)
+    _say(f"    full-size E_inf vs oracle = {e:.3e}")
+    assert e <= tol(prec, 6)
+    idx = W.rng(77).choice(len(b), 512, replace=False)
+    ex = oracle.sinc_direct(N, a, c, b[idx])
+    err = np.abs(h[idx] - ex).max()
+    e_direct = float(err / np.abs(ex).max())
+    _say(f"    full-size E_inf vs direct sum (512 samples) = {e_direct:.3e}")
+    # Theorem 6.2 with the quadrature error measured on a fine grid and the
+    # NNFFT constant of Theorem 4.1 (with its constant slip of 1.08)
+    z, wq = oracle.gauss_legendre(w["n_quad"])
+    xs = np.linspace(-1, 1, 8001)
+    eps = np.abs((wq[None, :] * np.exp(-1j * np.pi * N * np.outer(xs, z))).sum(1) - np.sinc(N * xs)).max()
+    Pp = oracle.params(N, 2.0, 2.0, 6, 6)
+    E = 1.08 * oracle.bound_thm41(Pp.N1, 6, 6, Pp.sigma1_eff, Pp.sigma2_eff)
+    bound = oracle.bound_thm62(eps, E) * np.abs(c).sum()
+    assert err <= bound + tol(prec, 6) * np.abs(ho).max()
+    assert e_direct <= 1e-4
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_sinc_shannon_cardinality(prec):
+    # b_l = a_0 + l / N: h_l = c_0 sinc(pi l) = delta_{l0} for one coefficient
+    N = 64
+    a0 = 0.03125 + 0.001
+    ell = np.arange(-24, 24)
+    b = a0 + ell / N
+    m = 12 if prec == FP64 else 6
+    h, _ = gpu_sinc(N, np.array([a0]), b, np.array([1.0 + 0j]), 4 * N, GL, m, prec)
+    ho = oracle.sinc_fast(N, np.array([a0]), np.array([1.0 + 0j]), b, 4 * N, oracle.QUAD_GAUSS_LEGENDRE,
+                          2.0, 2.0, m, m)
+    assert einf(h, ho) <= tol(prec, m)
+    delta = (ell == 0).astype(float)
+    assert np.abs(h - delta).max() <= (1e-9 if prec == FP64 else 1e-4)
+
+
+def test_sinc_plan_errors():
+    _say("[gpu] sinc plan error paths")
+    a = torch.tensor([0.1, 0.2], dtype=torch.float64, device=DEV)
+    b = torch.tensor([0.0], dtype=torch.float64, device=DEV)
+    with pytest.raises(P.NnfftError) as e:
+        P.sinc_plan(64, a, b, 0, GL, 2.0, 2.0, 6, 6, FP64)
+    assert e.value.status == P.binding.NNFFT_ERR_ARG
+    with pytest.raises(P.NnfftError) as e:
+        P.sinc_plan(64, a, b, 128, 7, 2.0, 2.0, 6, 6, FP64)
+    assert e.value.status == P.binding.NNFFT_ERR_ARG
+    bad = torch.tensor([0.7], dtype=torch.float64, device=DEV)
+    with pytest.raises(P.NnfftError) as e:
+        P.sinc_plan(64, a, bad, 128, GL, 2.0, 2.0, 6, 6, FP64)
+    assert e.value.status == P.binding.NNFFT_ERR_DOMAIN
