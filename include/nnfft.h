@@ -136,9 +136,16 @@ nnfft_status nnfft_plan(nnfft_plan_t *out, int64_t N, int64_t M1, int64_t M2,
 nnfft_status nnfft_exec(nnfft_plan_t p, const void *f, void *y, void *stream);
 
 /*
- * Batched form: runs n independent plans in one launch per stage (spreading,
- * transform, interpolation), each with its own sizes and precision.  Plans
- * must be distinct.  Results are bitwise those of nnfft_exec on each plan.
+ * Batched form (Algorithm 2.2 on many plans at once): runs n independent
+ * plans of any sizes N, M1, M2, sigma, m with one launch per stage for all
+ * plans of one precision -- spreading, FFT stage A (whole transforms of
+ * short plans), FFT stage B, interpolation -- up to 32 plans per launch
+ * (longer lists are cut into groups of 32).  FP32 and FP64 plans form
+ * separate groups.  f[i], y[i] are the device arrays of plans[i] (c64 for
+ * FP32 plans, c128 for FP64).  Each workgroup runs the same code on the same
+ * data as nnfft_exec, so every y[i] is bitwise equal to nnfft_exec on that
+ * plan.  Errors: ARG (n < 0, a null plan or array, or a plan listed twice:
+ * plans own their scratch), DEVICE.  Asynchronous on `stream`.
  */
 nnfft_status nnfft_exec_batch(int n, const nnfft_plan_t *plans, const void *const *f,
                               void *const *y, void *stream);

@@ -108,9 +108,25 @@ struct PlanDev {
     InterpArgs ip;
 };
 
+// Batched launches: up to kMaxBatch plans of one precision per launch.  The
+// table travels as the kernel argument; workgroups [start[p], start[p + 1])
+// belong to plan p (start[p] is a multiple of 8, so a plan's local workgroup
+// index has the same XCD residue as in a launch of its own).
+constexpr int kMaxBatch = 32;
+struct BatchTable {
+    const PlanDev *desc[kMaxBatch];   // device copies of the plans' descriptors
+    const void *in[kMaxBatch];        // f of each plan
+    void *out[kMaxBatch];             // y of each plan
+    int32_t start[kMaxBatch + 1];
+    int32_t n;
+};
+
 // Kernel launchers (kernels.hip).  ev: null, or 4 events recorded before
 // spreading, after spreading, after the FFT and after interpolation.
 hipError_t launch_exec(const PlanDev &P, const void *f, void *y, hipStream_t s, hipEvent_t *ev);
+// n plans of one precision: host descriptors (sizes) and their device copies
+hipError_t launch_exec_batch(int n, const PlanDev *const *host, const PlanDev *const *dev,
+                             const void *const *f, void *const *y, hipStream_t s);
 hipError_t launch_scale_by_weights(int prec, const double *w, const void *src, void *dst, int64_t n,
                                    hipStream_t s);
 

@@ -291,10 +291,9 @@ struct Spread64Lds {
     int runE[kItemsPerWg];
 };
 
-__global__ __launch_bounds__(64) void k_spread64(SpreadArgs A, const cx<double> *__restrict__ f)
+__device__ void spread64_slot(const SpreadArgs &A, const cx<double> *__restrict__ f, int g, Spread64Lds &L)
 {
-    __shared__ Spread64Lds L;
-    const int g = blockIdx.x, t = threadIdx.x;
+    const int t = threadIdx.x;
     const Item it = A.items[g * kItemsPerWg + t];
     const Chunk ch = A.chunks[g];
     if (ch.nitem == 0) return;
@@ -351,6 +350,12 @@ __global__ __launch_bounds__(64) void k_spread64(SpreadArgs A, const cx<double> 
         }
         part[w] = make_double2(ar, ai);
     }
+}
+
+__global__ __launch_bounds__(64) void k_spread64(SpreadArgs A, const cx<double> *__restrict__ f)
+{
+    __shared__ Spread64Lds L;
+    spread64_slot(A, f, blockIdx.x, L);
 }
 
 // ===========================================================================
@@ -413,18 +418,22 @@ __device__ void interp32_item(const InterpArgs &A, cx<float> *__restrict__ y, co
     }
 }
 
+__device__ __forceinline__ void interp32_slot(const InterpArgs &A, cx<float> *__restrict__ y, int g,
+                                              const float *Cs)
+{
+    const Item it = A.items[g * kItemsPerWg + threadIdx.x];
+    if (it.n > 0) {
+        const int rec_off = A.chunks[g].rec_off;
+        interp32_item(A, y, it, Cs, A.rec32 + rec_off + threadIdx.x);
+    }
+}
+
 __global__ __launch_bounds__(64) void k_interp32(InterpArgs A, cx<float> *__restrict__ y)
 {
     __shared__ float Cs[2 * kMaxM * (kDeg + 1)];
     stage_taps(Cs, A.C, 2 * A.m);
     __syncthreads();
-    for (int g = blockIdx.x; g < A.ngrid; g += gridDim.x) {
-        const Item it = A.items[g * kItemsPerWg + threadIdx.x];
-        if (it.n > 0) {
-            const int rec_off = A.chunks[g].rec_off;
-            interp32_item(A, y, it, Cs, A.rec32 + rec_off + threadIdx.x);
-        }
-    }
+    for (int g = blockIdx.x; g < A.ngrid; g += gridDim.x) interp32_slot(A, y, g, Cs);
 }
 
 struct Interp64Lds {
@@ -433,10 +442,9 @@ struct Interp64Lds {
     int used[kItemsPerWg];
 };
 
-__global__ __launch_bounds__(64) void k_interp64(InterpArgs A, cx<double> *__restrict__ y)
+__device__ void interp64_slot(const InterpArgs &A, cx<double> *__restrict__ y, int g, Interp64Lds &L)
 {
-    __shared__ Interp64Lds L;
-    const int g = blockIdx.x, t = threadIdx.x;
+    const int t = threadIdx.x;
     const Item it = A.items[g * kItemsPerWg + t];
     const Chunk ch = A.chunks[g];
     if (ch.nitem == 0) return;
@@ -474,6 +482,12 @@ __global__ __launch_bounds__(64) void k_interp64(InterpArgs A, cx<double> *__res
             y[A.perm[p]] = cxmk(sr * corr, si * corr);
         }
     }
+}
+
+__global__ __launch_bounds__(64) void k_interp64(InterpArgs A, cx<double> *__restrict__ y)
+{
+    __shared__ Interp64Lds L;
+    interp64_slot(A, y, blockIdx.x, L);
 }
 
 // ===========================================================================
@@ -691,11 +705,20 @@ struct FftLds {
     cx<T> buf[2][kFftVals];
 };
 
+// Column block handled by local workgroup w of a launch of 8 ceil(ng / 8)
+// workgroups: XCD x = w mod 8 takes the contiguous blocks [x per, (x + 1) per),
+// so neighbouring columns, which share cache lines of the strided loads and
+// stores, meet in one L2.  Blocks >= ng are idle.
+__device__ __forceinline__ int xcd_block(int w, int ng)
+{
+    const int per = (ng + 7) / 8;
+    return (w & 7) * per + (w >> 3);
+}
+
 // Whole transform in one workgroup (N2 <= kFftVals)
 template <typename T>
-__global__ __launch_bounds__(256) void k_fft_single(FftArgs A)
+__device__ void fft_single_body(const FftArgs &A, FftLds<T> &L)
 {
-    __shared__ FftLds<T> L;
     const int N2 = A.N2;
     for (int q = threadIdx.x; q < N2; q += blockDim.x) L.buf[0][q] = fft_input<T>(A, q);
     __syncthreads();
@@ -704,14 +727,23 @@ __global__ __launch_bounds__(256) void k_fft_single(FftArgs A)
     for (int k = threadIdx.x; k < N2; k += blockDim.x) fft_store<T>(A, k, res[k]);
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void k_fft_single(FftArgs A)
+{
+    __shared__ FftLds<T> L;
+    fft_single_body<T>(A, L);
+}
+
 // Four-step stage A: for columns j1, length-n2 transforms over j2 of
 // x[j1 + n1 j2], times exp(-2 pi i j1 k2 / N2), stored to Y[j1 n2 + k2].
 template <typename T>
-__global__ __launch_bounds__(256) void k_fft_stageA(FftArgs A)
+__device__ void fft_stageA_body(const FftArgs &A, int w, FftLds<T> &L)
 {
-    __shared__ FftLds<T> L;
     const int n1 = A.n1, n2 = A.n2, B = A.batchA;
-    const int j1_0 = blockIdx.x * B;
+    const int ng = (n1 + B - 1) / B;
+    const int blk = xcd_block(w, ng);
+    if (blk >= ng) return;
+    const int j1_0 = blk * B;
     const int nb = min(B, n1 - j1_0);
     for (int idx = threadIdx.x; idx < nb * n2; idx += blockDim.x) {
         const int j2 = idx / nb, bl = idx - j2 * nb;
@@ -728,14 +760,23 @@ __global__ __launch_bounds__(256) void k_fft_stageA(FftArgs A)
     }
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void k_fft_stageA(FftArgs A)
+{
+    __shared__ FftLds<T> L;
+    fft_stageA_body<T>(A, blockIdx.x, L);
+}
+
 // Four-step stage B: for columns k2, length-n1 transforms over j1 of
 // Y[j1 n2 + k2]; output k1 is X[k2 + n2 k1].
 template <typename T>
-__global__ __launch_bounds__(256) void k_fft_stageB(FftArgs A)
+__device__ void fft_stageB_body(const FftArgs &A, int w, FftLds<T> &L)
 {
-    __shared__ FftLds<T> L;
     const int n1 = A.n1, n2 = A.n2, B = A.batchB;
-    const int k2_0 = blockIdx.x * B;
+    const int ng = (n2 + B - 1) / B;
+    const int blk = xcd_block(w, ng);
+    if (blk >= ng) return;
+    const int k2_0 = blk * B;
     const int nb = min(B, n2 - k2_0);
     const cx<T> *Y = reinterpret_cast<const cx<T> *>(A.Y);
     for (int idx = threadIdx.x; idx < nb * n1; idx += blockDim.x) {
@@ -751,17 +792,110 @@ __global__ __launch_bounds__(256) void k_fft_stageB(FftArgs A)
     }
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void k_fft_stageB(FftArgs A)
+{
+    __shared__ FftLds<T> L;
+    fft_stageB_body<T>(A, blockIdx.x, L);
+}
+
+// ===========================================================================
+// Batched kernels: one launch per stage for up to kMaxBatch plans of one
+// precision.  Each workgroup finds its plan in the table and runs the same
+// slot / column code as the plan's own launch, so results are bitwise equal.
+// ===========================================================================
+__device__ __forceinline__ int batch_plan(const BatchTable &T, int g)
+{
+    int p = 0;
+    while (p + 1 < T.n && T.start[p + 1] <= g) ++p;
+    return p;
+}
+
+template <int TM>
+__global__ __launch_bounds__(64) void k_spread32_batch(BatchTable T)
+{
+    __shared__ Spread32Lds<TM> L;
+    const int p = batch_plan(T, blockIdx.x);
+    const SpreadArgs A = T.desc[p]->sp;
+    const int g = blockIdx.x - T.start[p];
+    if (g >= A.ngrid) return;
+    stage_taps(L.C, A.C, 2 * A.m);
+    __syncthreads();
+    spread32_slot<TM>(A, static_cast<const cx<float> *>(T.in[p]), g, L);
+}
+
+__global__ __launch_bounds__(64) void k_spread64_batch(BatchTable T)
+{
+    __shared__ Spread64Lds L;
+    const int p = batch_plan(T, blockIdx.x);
+    const SpreadArgs A = T.desc[p]->sp;
+    const int g = blockIdx.x - T.start[p];
+    if (g >= A.ngrid) return;
+    spread64_slot(A, static_cast<const cx<double> *>(T.in[p]), g, L);
+}
+
+__global__ __launch_bounds__(64) void k_interp32_batch(BatchTable T)
+{
+    __shared__ float Cs[2 * kMaxM * (kDeg + 1)];
+    const int p = batch_plan(T, blockIdx.x);
+    const InterpArgs A = T.desc[p]->ip;
+    const int g = blockIdx.x - T.start[p];
+    if (g >= A.ngrid) return;
+    stage_taps(Cs, A.C, 2 * A.m);
+    __syncthreads();
+    interp32_slot(A, static_cast<cx<float> *>(T.out[p]), g, Cs);
+}
+
+__global__ __launch_bounds__(64) void k_interp64_batch(BatchTable T)
+{
+    __shared__ Interp64Lds L;
+    const int p = batch_plan(T, blockIdx.x);
+    const InterpArgs A = T.desc[p]->ip;
+    const int g = blockIdx.x - T.start[p];
+    if (g >= A.ngrid) return;
+    interp64_slot(A, static_cast<cx<double> *>(T.out[p]), g, L);
+}
+
+// stage A of four-step plans and the whole transform of one-workgroup plans
+template <typename T>
+__global__ __launch_bounds__(256) void k_fftA_batch(BatchTable Tb)
+{
+    __shared__ FftLds<T> L;
+    const int p = batch_plan(Tb, blockIdx.x);
+    const FftArgs &A = Tb.desc[p]->fft;
+    const int w = blockIdx.x - Tb.start[p];
+    if (A.n1 == 1) {
+        if (w == 0) fft_single_body<T>(A, L);
+    } else {
+        fft_stageA_body<T>(A, w, L);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_fftB_batch(BatchTable Tb)
+{
+    __shared__ FftLds<T> L;
+    const int p = batch_plan(Tb, blockIdx.x);
+    const FftArgs &A = Tb.desc[p]->fft;
+    fft_stageB_body<T>(A, blockIdx.x - Tb.start[p], L);
+}
+
 // ===========================================================================
 // Launchers
 // ===========================================================================
+// workgroups of a four-step stage: column blocks rounded up to a multiple of 8
+static int fft_groups(int ncol, int batch)
+{
+    return ((ncol + batch - 1) / batch + 7) / 8 * 8;
+}
+
 template <typename T>
 static void launch_fft(const FftArgs &A, hipStream_t s)
 {
     if (A.n1 == 1) {
         hipLaunchKernelGGL((k_fft_single<T>), dim3(1), dim3(A.threadsA), 0, s, A);
     } else {
-        const int gA = (A.n1 + A.batchA - 1) / A.batchA;
-        const int gB = (A.n2 + A.batchB - 1) / A.batchB;
+        const int gA = fft_groups(A.n1, A.batchA), gB = fft_groups(A.n2, A.batchB);
         hipLaunchKernelGGL((k_fft_stageA<T>), dim3(gA), dim3(A.threadsA), 0, s, A);
         hipLaunchKernelGGL((k_fft_stageB<T>), dim3(gB), dim3(A.threadsB), 0, s, A);
     }
@@ -800,6 +934,64 @@ hipError_t launch_exec(const PlanDev &P, const void *f, void *y, hipStream_t s, 
     }
     if (ev) (void)hipEventRecord(ev[3], s);
     return hipGetLastError();
+}
+
+hipError_t launch_exec_batch(int n, const PlanDev *const *host, const PlanDev *const *dev,
+                             const void *const *f, void *const *y, hipStream_t s)
+{
+    auto rnd8 = [](int x) { return (x + 7) / 8 * 8; };
+    for (int b0 = 0; b0 < n; b0 += kMaxBatch) {
+        const int nb = std::min(kMaxBatch, n - b0);
+        BatchTable Tsp{}, Tip{}, TA{}, TB{};
+        int ssp = 0, sip = 0, sA = 0, sB = 0, thrA = 64, thrB = 64;
+        bool long_window = false;
+        for (int i = 0; i < nb; ++i) {
+            const PlanDev &P = *host[b0 + i];
+            for (BatchTable *T : {&Tsp, &Tip, &TA, &TB}) {
+                T->desc[i] = dev[b0 + i];
+                T->in[i] = f[b0 + i];
+                T->out[i] = y[b0 + i];
+            }
+            Tsp.start[i] = ssp;
+            ssp += rnd8(P.sp.ngrid);
+            Tip.start[i] = sip;
+            sip += rnd8(P.ip.ngrid);
+            TA.start[i] = sA;
+            TB.start[i] = sB;
+            if (P.fft.n1 == 1) {
+                sA += 8;
+                thrA = std::max(thrA, P.fft.threadsA);
+            } else {
+                sA += fft_groups(P.fft.n1, P.fft.batchA);
+                sB += fft_groups(P.fft.n2, P.fft.batchB);
+                thrA = std::max(thrA, P.fft.threadsA);
+                thrB = std::max(thrB, P.fft.threadsB);
+            }
+            long_window = long_window || 2 * P.sp.m > 16;
+        }
+        Tsp.start[nb] = ssp;
+        Tip.start[nb] = sip;
+        TA.start[nb] = sA;
+        TB.start[nb] = sB;
+        Tsp.n = Tip.n = TA.n = TB.n = nb;
+        if (host[b0]->prec == NNFFT_FP32_COMP) {
+            if (long_window)
+                hipLaunchKernelGGL((k_spread32_batch<32>), dim3(ssp), dim3(kItemsPerWg), 0, s, Tsp);
+            else
+                hipLaunchKernelGGL((k_spread32_batch<16>), dim3(ssp), dim3(kItemsPerWg), 0, s, Tsp);
+            hipLaunchKernelGGL((k_fftA_batch<float>), dim3(sA), dim3(thrA), 0, s, TA);
+            if (sB > 0) hipLaunchKernelGGL((k_fftB_batch<float>), dim3(sB), dim3(thrB), 0, s, TB);
+            hipLaunchKernelGGL(k_interp32_batch, dim3(sip), dim3(kItemsPerWg), 0, s, Tip);
+        } else {
+            hipLaunchKernelGGL(k_spread64_batch, dim3(ssp), dim3(kItemsPerWg), 0, s, Tsp);
+            hipLaunchKernelGGL((k_fftA_batch<double>), dim3(sA), dim3(thrA), 0, s, TA);
+            if (sB > 0) hipLaunchKernelGGL((k_fftB_batch<double>), dim3(sB), dim3(thrB), 0, s, TB);
+            hipLaunchKernelGGL(k_interp64_batch, dim3(sip), dim3(kItemsPerWg), 0, s, Tip);
+        }
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 // ===========================================================================

@@ -251,6 +251,7 @@ bool fft_factor(int64_t N2, int64_t limit, int64_t &n1, int64_t &n2)
 struct nnfft_plan_s {
     nnfft_info_t info{};
     PlanDev desc{};
+    PlanDev *ddesc = nullptr;          // device copy of desc (batched launches)
     std::vector<void *> allocs;
     int64_t bytes = 0;
     std::vector<hipEvent_t> prof_ev;   // 4 events per profiled exec
@@ -524,6 +525,9 @@ static nnfft_status plan_impl(nnfft_plan_t *out, int64_t N, int64_t M1, int64_t 
             FA.radA[i] = (int8_t)fd.radA[i];
             FA.radB[i] = (int8_t)fd.radB[i];
         }
+        pl->ddesc = static_cast<PlanDev *>(pl->scratch(sizeof(PlanDev)));
+        hip_check(hipMemcpyAsync(pl->ddesc, &pl->desc, sizeof(PlanDev), hipMemcpyHostToDevice, s),
+                  "hipMemcpyAsync");
         hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
         P.device_bytes = pl->bytes;
         P.block_points = lay1.block;
@@ -589,9 +593,35 @@ nnfft_status nnfft_exec_batch(int n, const nnfft_plan_t *plans, const void *cons
                               void *stream)
 {
     if (n < 0 || (n > 0 && (!plans || !f || !y))) return fail(NNFFT_ERR_ARG, "null argument");
-    for (int i = 0; i < n; ++i) {
-        const nnfft_status st = nnfft_exec(plans[i], f[i], y[i], stream);
-        if (st != NNFFT_OK) return st;
+    try {
+        std::vector<nnfft_plan_t> seen;
+        seen.reserve(n);
+        for (int i = 0; i < n; ++i) {
+            if (!plans[i] || !f[i] || !y[i]) return fail(NNFFT_ERR_ARG, "null plan or array in the batch");
+            seen.push_back(plans[i]);
+        }
+        std::sort(seen.begin(), seen.end());
+        if (std::adjacent_find(seen.begin(), seen.end()) != seen.end())
+            return fail(NNFFT_ERR_ARG, "a plan appears twice in the batch");
+        // one group per precision, each in the callers' order
+        for (int prec : {(int)NNFFT_FP32_COMP, (int)NNFFT_FP64_PLAIN}) {
+            std::vector<const PlanDev *> host, dev;
+            std::vector<const void *> fi;
+            std::vector<void *> yi;
+            for (int i = 0; i < n; ++i) {
+                if (plans[i]->desc.prec != prec) continue;
+                host.push_back(&plans[i]->desc);
+                dev.push_back(plans[i]->ddesc);
+                fi.push_back(f[i]);
+                yi.push_back(y[i]);
+            }
+            if (host.empty()) continue;
+            const hipError_t e = launch_exec_batch((int)host.size(), host.data(), dev.data(), fi.data(),
+                                                   yi.data(), static_cast<hipStream_t>(stream));
+            if (e != hipSuccess) return fail(NNFFT_ERR_DEVICE, std::string("batched launch: ") + hipGetErrorString(e));
+        }
+    } catch (const std::bad_alloc &) {
+        return fail(NNFFT_ERR_NOMEM, "host allocation failed");
     }
     return NNFFT_OK;
 }

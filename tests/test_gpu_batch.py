@@ -1,0 +1,102 @@
+"""Batched execution (nnfft_exec_batch): many plans of uneven N, M1, M2, m
+and precision in one launch per stage, bitwise equal to one exec per plan,
+and within the parity tolerance of the FP64 oracle."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2107_02671_amd as P
+from paper_2107_02671_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FP64, FP32 = P.NNFFT_FP64_PLAIN, P.NNFFT_FP32_COMP
+DEV = "cuda:0"
+
+
+def _tol(prec, N, m):
+    # the NNFFT parity rule: FP64 1e-12; FP32 1e-5 scaled by the phi_hat ratio kappa
+    if prec == FP64:
+        return 1e-12
+    Pp = oracle.params(N, 2.0, 2.0, m, m)
+    k = max(oracle.omega_hat(0.0, b) / oracle.omega_hat(m / (2 * s), b)
+            for b, s in ((Pp.beta1, Pp.sigma1_eff), (Pp.beta2, Pp.sigma2_eff)))
+    return 1e-5 * max(1.0, float(k) / 4.62)
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _requests(n, seed, max_log2_m=17):
+    g = W.rng(seed)
+    out = []
+    for i in range(n):
+        N = int(np.rint(np.exp(g.uniform(np.log(64), np.log(8192)))))
+        M1 = int(np.rint(np.exp(g.uniform(np.log(2 ** 10), np.log(2 ** max_log2_m)))))
+        M2 = int(np.rint(np.exp(g.uniform(np.log(2 ** 10), np.log(2 ** max_log2_m)))))
+        kind = i % 4
+        prec, m = [(FP32, 6), (FP64, 12), (FP32, 10), (FP64, 5)][kind]
+        v, x, f = W.uniform_nodes(g, M1), W.uniform_nodes(g, M2), W.complex_gaussian(g, M1)
+        out.append(dict(N=N, M1=M1, M2=M2, prec=prec, m=m, v=v, x=x, f=f))
+    return out
+
+
+def _plans(reqs):
+    plans, fs = [], []
+    for r in reqs:
+        cdt = torch.complex64 if r["prec"] == FP32 else torch.complex128
+        plans.append(P.Plan(r["N"], torch.tensor(r["v"], device=DEV), torch.tensor(r["x"], device=DEV),
+                            2.0, 2.0, r["m"], r["m"], r["prec"]))
+        fs.append(torch.tensor(r["f"], dtype=cdt, device=DEV))
+    return plans, fs
+
+
+def test_batch_bitwise_equals_single_execs():
+    reqs = _requests(40, seed=11)     # more than one group of 32, both precisions
+    _say(f"[gpu] batch of {len(reqs)} plans, N in [{min(r['N'] for r in reqs)}, {max(r['N'] for r in reqs)}]")
+    plans, fs = _plans(reqs)
+    try:
+        singles = [p(f).clone() for p, f in zip(plans, fs)]
+        ys = [torch.full_like(s, float("nan")) for s in singles]
+        P.nnfft_exec_batch([p.handle for p in plans], fs, ys)
+        torch.cuda.synchronize()
+        for i, (a, b) in enumerate(zip(singles, ys)):
+            assert torch.equal(a, b), f"plan {i} differs from its single exec"
+        # a second batch in another order gives the same bits again
+        order = list(reversed(range(len(plans))))
+        ys2 = [torch.full_like(singles[i], float("nan")) for i in order]
+        P.nnfft_exec_batch([plans[i].handle for i in order], [fs[i] for i in order], ys2)
+        torch.cuda.synchronize()
+        for k, i in enumerate(order):
+            assert torch.equal(singles[i], ys2[k])
+        # parity of a few batch results with the oracle
+        for i in (0, 1, 2, 3):
+            r = reqs[i]
+            yo = oracle.nnfft(r["N"], r["v"], r["f"], r["x"], 2.0, 2.0, r["m"], r["m"])
+            e = np.abs(ys[i].cpu().numpy() - yo).max() / np.abs(yo).max()
+            _say(f"    plan {i} N={r['N']} M=({r['M1']},{r['M2']}) m={r['m']} prec={r['prec']}: E_inf {e:.2e}")
+            assert e <= _tol(r["prec"], r["N"], r["m"])
+    finally:
+        for p in plans:
+            p.close()
+
+
+def test_batch_errors_and_empty():
+    _say("[gpu] batch error paths")
+    reqs = _requests(2, seed=12, max_log2_m=11)
+    plans, fs = _plans(reqs)
+    try:
+        ys = [torch.empty(r["M2"], dtype=f.dtype, device=DEV) for r, f in zip(reqs, fs)]
+        with pytest.raises(P.NnfftError) as e:
+            P.nnfft_exec_batch([plans[0].handle, plans[0].handle], [fs[0], fs[0]], [ys[0], ys[0]])
+        assert e.value.status == P.binding.NNFFT_ERR_ARG
+        P.nnfft_exec_batch([], [], [])
+        torch.cuda.synchronize()
+    finally:
+        for p in plans:
+            p.close()
