@@ -14,6 +14,13 @@ Reported (one JSON line):
   roofline       the slowest kernel's algorithmic bytes per launch / its average
                  duration, from HIP events recorded on the library's stream
   cpu_baseline   the FP64 CPU oracle NNFFT on the same workload
+  batched        the served request mix (N log-uniform in [64, 8192], M1, M2
+                 log-uniform in [2^10, 2^20]) as resident plans run by
+                 nnfft_exec_batch: FP32 (m=6) against FP64 plain (m=12) pts/s
+  served         the same mix through the serving layer (plans built per
+                 request, admitted by HBM footprint, continuous batching):
+                 closed-loop capacity, then Poisson arrivals at 0.5, 0.8 and
+                 1.0 times that rate with p50 / p99 latency (submit to done)
 """
 from __future__ import annotations
 
@@ -68,6 +75,102 @@ def time_steps(fn, steps, warmup, torch, before=None):
     return (time.perf_counter() - t0) / steps
 
 
+def request_inputs(torch, req, fp32, dev):
+    """Seeded device inputs of one served request: uniform nodes, complex Gaussian f."""
+    g = torch.Generator(device=dev)
+    g.manual_seed(4_000_000 + req["id"])
+    v = torch.rand(req["M1"], dtype=torch.float64, device=dev, generator=g) - 0.5
+    x = torch.rand(req["M2"], dtype=torch.float64, device=dev, generator=g) - 0.5
+    cdt = torch.complex64 if fp32 else torch.complex128
+    f = torch.randn(req["M1"], dtype=cdt, device=dev, generator=g)
+    y = torch.empty(req["M2"], dtype=cdt, device=dev)
+    return v, x, f, y
+
+
+def batched_benchmark(P, W, torch, nplans, reps=20):
+    """Resident plans of the served mix, one nnfft_exec_batch per step."""
+    import numpy as np
+    dev = torch.device("cuda:0")
+    reqs = W.served_requests(nplans * 4, seed=4)
+    out = {}
+    for name, fp32, prec, m in [("fp32", True, P.NNFFT_FP32_COMP, 6), ("fp64", False, P.NNFFT_FP64_PLAIN, 12)]:
+        sel = [r for r in reqs if r["fp32"] == fp32][:nplans]
+        plans, fs, ys, pts = [], [], [], 0
+        for r in sel:
+            v, x, f, y = request_inputs(torch, r, fp32, dev)
+            plans.append(P.Plan(r["N"], v, x, 2.0, 2.0, m, m, prec))
+            fs.append(f)
+            ys.append(y)
+            pts += r["M1"] + r["M2"]
+        handles = [p.handle for p in plans]
+        t = time_steps(lambda: P.nnfft_exec_batch(handles, fs, ys), reps, 3, torch)
+        out[name] = {"plans": len(plans), "points_per_step": pts, "ms_per_step": t * 1e3,
+                     "value": pts / t, "unit": "pts/s", "m": m}
+        for p in plans:
+            p.close()
+    out["speedup_fp32_over_fp64"] = out["fp32"]["value"] / out["fp64"]["value"]
+    return out
+
+
+def served_benchmark(P, W, torch, n_req, planners=12, budget=16 << 30):
+    """The served request stream: closed loop for capacity, then Poisson arrivals."""
+    import threading
+
+    import numpy as np
+    dev = torch.device("cuda:0")
+    reqs = W.served_requests(10000, seed=4)[:n_req]
+
+    def run(rate):
+        srv = P.Server(hbm_budget_bytes=budget, planner_threads=planners, streams=2)
+        results = [None] * len(reqs)
+        tickets = [None] * len(reqs)
+        ready = threading.Semaphore(0)
+        window = threading.Semaphore(256)      # at most 256 outstanding (input memory)
+
+        def collect():
+            for i in range(len(reqs)):
+                ready.acquire()
+                results[i] = srv.wait(tickets[i])
+                window.release()
+
+        th = threading.Thread(target=collect)
+        th.start()
+        t0 = time.perf_counter()
+        arrival = 0.0
+        for i, r in enumerate(reqs):
+            if rate is not None:
+                arrival += r["gap"] / rate
+                while time.perf_counter() - t0 < arrival:
+                    time.sleep(min(1e-3, max(0.0, arrival - (time.perf_counter() - t0))))
+            window.acquire()
+            v, x, f, y = request_inputs(torch, r, r["fp32"], dev)
+            torch.cuda.current_stream().synchronize()
+            prec = P.NNFFT_FP32_COMP if r["fp32"] else P.NNFFT_FP64_PLAIN
+            tickets[i] = srv.submit(r["N"], v, x, f, y, sigma1=2.0, sigma2=2.0, m1=r["m"], m2=r["m"], prec=prec)
+            ready.release()
+        th.join()
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+        srv.close()
+        lat = np.array([res["done_ms"] - res["submit_ms"] for res in results])
+        ok = sum(res["status"] == 0 for res in results)
+        pts = sum(r["M1"] + r["M2"] for r in reqs)
+        return {"requests": len(reqs), "ok": ok, "wall_s": wall, "req_per_s": len(reqs) / wall,
+                "value": pts / wall, "unit": "pts/s", "p50_ms": float(np.percentile(lat, 50)),
+                "p99_ms": float(np.percentile(lat, 99)),
+                "mean_group": float(np.mean([res["group_size"] for res in results])),
+                "admission_waits": st["admission_waits"], "arena_peak_bytes": st["arena_peak"]}
+
+    closed = run(None)
+    out = {"closed_loop": closed, "planner_threads": planners, "hbm_budget_bytes": budget,
+           "mix": "N logU[64,8192], M1,M2 logU[2^10,2^20], FP32 m=6 / FP64 m=12 (1:1), uniform nodes"}
+    cap = closed["req_per_s"]
+    for frac in (0.5, 0.8, 1.0):
+        print(f"[bench] served, Poisson arrivals at {frac} x {cap:.0f} req/s", file=sys.stderr, flush=True)
+        out[f"poisson_{frac}"] = run(frac * cap)
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -78,6 +181,10 @@ def main() -> int:
     ap.add_argument("--fp32-only", action="store_true", help="skip the FP64 plain comparator")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 256 MiB device copy (counter calibration runs)")
+    ap.add_argument("--serve-requests", type=int, default=2000,
+                    help="requests per served run (the full request stream has 10000; 0 skips)")
+    ap.add_argument("--batch-plans", type=int, default=48,
+                    help="resident plans per precision in the batched measurement (0 skips)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -223,6 +330,12 @@ def main() -> int:
                                "cores": oracle.num_threads(), "kind": "oracle",
                                "sample": f"full workload (M1=M2=2^20, N=4096, m=6), {reps} runs of "
                                          f"the FP64 oracle NNFFT (plan + all steps), {tot:.1f} s"}
+    if args.batch_plans > 0:
+        print("[bench] batched resident plans", file=sys.stderr, flush=True)
+        out["batched"] = batched_benchmark(P, W, torch, args.batch_plans)
+    if args.serve_requests > 0:
+        print("[bench] served request stream", file=sys.stderr, flush=True)
+        out["served"] = served_benchmark(P, W, torch, args.serve_requests)
     if args.calibrate_copy:
         a = torch.empty(1 << 26, dtype=torch.float32, device=dev).fill_(1.0)
         b = torch.empty_like(a)

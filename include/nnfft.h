@@ -166,6 +166,52 @@ nnfft_status nnfft_profile_stop(nnfft_plan_t p, double *stage_ms, int *nexecs);
 nnfft_status nnfft_destroy(nnfft_plan_t p);
 
 /*
+ * Layout tuning.  A plan sorts each node side into blocks of consecutive
+ * caller indices (one XCD's share of the gathers and scatters), bins of one
+ * grid cell, work items of at most items_points points of one bin, and
+ * one-wavefront workgroups of 64 items.  FP32 spreading and interpolation
+ * launches may cap their grid at grid_max workgroups that loop over the
+ * slots (0: one workgroup per slot; FP64 launches are always one per slot).
+ * These knobs change speed, and the summation order of the FP32 cell sums,
+ * never the algorithm.  Plans take them from a process-wide table keyed by
+ * precision and ceil(log2 M) of each side, else from a built-in rule.
+ */
+typedef struct {
+    int32_t items_points;           /* max points per work item (FP64: <= 8)         */
+    int32_t grid_max;               /* FP32 launch cap, 0 = one workgroup per slot   */
+    int64_t block_points;           /* points per node block                         */
+    double exec_ms;                 /* nnfft_autotune: measured exec time            */
+    int32_t candidates;             /* nnfft_autotune: layouts timed                 */
+    int32_t tuned;                  /* nnfft_get_tuning: 1 if from the table         */
+} nnfft_tuning_t;
+
+/*
+ * Autotuner: times nnfft_exec of an N, M1 = M2 = M, m1 = m2 = m, sigma = 2
+ * plan on synthetic uniform nodes (a fixed seed) for a set of candidate
+ * layouts (items_points {4, 8, 16, 32} (FP64 {2, 4, 8}) x block_points
+ * {2^13 .. 2^17} x grid_max {0, 1024} (FP64 0), after the clamping rules,
+ * and the built-in rule's layout), `reps` timed execs each
+ * after 2 untimed ones, on `stream`, and installs the fastest in the table
+ * for M's size class and precision (it then applies to both sides of later
+ * plans of that class).  Allocates and frees its own device memory; blocks
+ * until done.  *best receives the layout and its time.
+ * Errors: ARG, UNSUPPORTED (as nnfft_plan), NOMEM, DEVICE.
+ */
+nnfft_status nnfft_autotune(int64_t N, int64_t M, int m, nnfft_precision prec, int reps, void *stream,
+                            nnfft_tuning_t *best);
+
+/* Installs a layout for plans of precision prec whose side has M's size class
+ * (ceil(log2 M)).  Errors: ARG for items_points < 1, block_points < 1,
+ * grid_max < 0.  Out-of-range values are clamped when a plan uses them. */
+nnfft_status nnfft_set_tuning(nnfft_precision prec, int64_t M, const nnfft_tuning_t *t);
+
+/* The layout a plan side of M nodes would use now (tuned = 1 if from the table). */
+nnfft_status nnfft_get_tuning(nnfft_precision prec, int64_t M, nnfft_tuning_t *out);
+
+/* Empties the table (plans fall back to the built-in rule). */
+nnfft_status nnfft_clear_tuning(void);
+
+/*
  * Fast sinc transform plan (Algorithm 6.1).  Quadrature nodes z_j and weights
  * w_j (sum w_j = 1) are computed on the host in FP64: Gauss-Legendre with
  * n_quad nodes, or Clenshaw-Curtis (5.4) with n_quad + 1 Chebyshev points.

@@ -14,7 +14,8 @@ import re
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libnnfft.so")
-HEADER = os.path.join(os.path.dirname(HERE), "include", "nnfft.h")
+INCLUDE = os.path.join(os.path.dirname(HERE), "include")
+HEADERS = [os.path.join(INCLUDE, "nnfft.h"), os.path.join(INCLUDE, "nnfft_serve.h")]
 
 NNFFT_OK = 0
 NNFFT_ERR_ARG = 1
@@ -54,6 +55,55 @@ class NnfftInfo(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class NnfftTuning(ctypes.Structure):
+    _fields_ = [("items_points", ctypes.c_int32), ("grid_max", ctypes.c_int32),
+                ("block_points", ctypes.c_int64), ("exec_ms", ctypes.c_double),
+                ("candidates", ctypes.c_int32), ("tuned", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+NNFFT_REQ_NNFFT = 0
+NNFFT_REQ_SINC = 1
+
+
+class NnfftRequest(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("precision", ctypes.c_int32), ("N", ctypes.c_int64),
+                ("M1", ctypes.c_int64), ("M2", ctypes.c_int64),
+                ("sigma1", ctypes.c_double), ("sigma2", ctypes.c_double),
+                ("m1", ctypes.c_int32), ("m2", ctypes.c_int32), ("quad", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("n_quad", ctypes.c_int64),
+                ("v", ctypes.c_void_p), ("x", ctypes.c_void_p), ("f", ctypes.c_void_p), ("y", ctypes.c_void_p),
+                ("plan_key", ctypes.c_uint64)]
+
+
+class NnfftResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("group_size", ctypes.c_int32),
+                ("footprint_bytes", ctypes.c_int64), ("plan_reused", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("submit_ms", ctypes.c_double), ("admit_ms", ctypes.c_double),
+                ("launch_ms", ctypes.c_double), ("done_ms", ctypes.c_double), ("message", ctypes.c_char * 160)]
+
+    def as_dict(self):
+        d = {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+        d["message"] = self.message.decode(errors="replace")
+        return d
+
+
+class NnfftServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("planner_threads", ctypes.c_int32),
+                ("streams", ctypes.c_int32), ("max_batch", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class NnfftServerStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in ("submitted", "completed", "failed", "groups", "admission_waits",
+                                             "evictions", "arena_bytes", "arena_in_use", "arena_peak",
+                                             "resident_plans")]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 class NnfftError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
@@ -87,20 +137,39 @@ def lib():
     L.nnfft_quadrature.argtypes = [ci, i64, dptr, dptr]
     L.nnfft_profile_start.argtypes = [vp, ci]
     L.nnfft_profile_stop.argtypes = [vp, dptr, ctypes.POINTER(ci)]
+    tp = ctypes.POINTER(NnfftTuning)
+    L.nnfft_autotune.argtypes = [i64, i64, ci, ci, ci, vp, tp]
+    L.nnfft_set_tuning.argtypes = [ci, i64, tp]
+    L.nnfft_get_tuning.argtypes = [ci, i64, tp]
+    L.nnfft_clear_tuning.argtypes = []
+    u64 = ctypes.c_uint64
+    L.nnfft_server_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(NnfftServerConfig)]
+    L.nnfft_server_submit.argtypes = [vp, ctypes.POINTER(NnfftRequest), ctypes.POINTER(u64)]
+    L.nnfft_server_wait.argtypes = [vp, u64, ctypes.POINTER(NnfftResult)]
+    L.nnfft_server_poll.argtypes = [vp, u64, ctypes.POINTER(NnfftResult)]
+    L.nnfft_server_stats.argtypes = [vp, ctypes.POINTER(NnfftServerStats)]
+    L.nnfft_server_evict.argtypes = [vp, u64]
+    L.nnfft_server_destroy.argtypes = [vp]
     L.nnfft_last_error.restype = ctypes.c_char_p
     L.nnfft_version.restype = ctypes.c_char_p
-    for name in ["nnfft_profile_start", "nnfft_profile_stop", "nnfft_quadrature", "nnfft_derive_params", "nnfft_plan", "nnfft_exec", "nnfft_exec_batch", "nnfft_info",
-                 "nnfft_destroy", "sinc_plan", "sinc_exec", "sinc_info", "sinc_destroy"]:
+    for name in ["nnfft_profile_start", "nnfft_profile_stop", "nnfft_quadrature", "nnfft_derive_params",
+                 "nnfft_plan", "nnfft_exec", "nnfft_exec_batch", "nnfft_info", "nnfft_destroy", "sinc_plan",
+                 "sinc_exec", "sinc_info", "sinc_destroy", "nnfft_autotune", "nnfft_set_tuning",
+                 "nnfft_get_tuning", "nnfft_clear_tuning", "nnfft_server_create", "nnfft_server_submit",
+                 "nnfft_server_wait", "nnfft_server_poll", "nnfft_server_stats", "nnfft_server_evict",
+                 "nnfft_server_destroy"]:
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
 
 
 def header_functions():
-    """Names of the functions declared in include/nnfft.h."""
-    src = open(HEADER).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(nnfft_\w+|sinc_\w+)\s*\(", src)))
+    """Names of the functions declared in include/*.h."""
+    names = set()
+    for h in HEADERS:
+        src = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names.update(re.findall(r"\b(nnfft_\w+|sinc_\w+)\s*\(", src))
+    return sorted(names)
 
 
 def _check(status):
@@ -297,3 +366,135 @@ class SincPlan:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------------------
+# layout tuning
+# ---------------------------------------------------------------------------
+def nnfft_autotune(N, M, m, prec, reps=10, stream=None) -> dict:
+    t = NnfftTuning()
+    _check(lib().nnfft_autotune(int(N), int(M), int(m), int(prec), int(reps), _stream(stream), ctypes.byref(t)))
+    return t.as_dict()
+
+
+def nnfft_set_tuning(prec, M, items_points, block_points, grid_max=0):
+    t = NnfftTuning(int(items_points), int(grid_max), int(block_points), 0.0, 0, 0)
+    _check(lib().nnfft_set_tuning(int(prec), int(M), ctypes.byref(t)))
+
+
+def nnfft_get_tuning(prec, M) -> dict:
+    t = NnfftTuning()
+    _check(lib().nnfft_get_tuning(int(prec), int(M), ctypes.byref(t)))
+    return t.as_dict()
+
+
+def nnfft_clear_tuning():
+    _check(lib().nnfft_clear_tuning())
+
+
+# ---------------------------------------------------------------------------
+# serving (include/nnfft_serve.h)
+# ---------------------------------------------------------------------------
+def nnfft_server_create(hbm_budget_bytes=0, planner_threads=0, streams=0, max_batch=0):
+    cfg = NnfftServerConfig(int(hbm_budget_bytes), int(planner_threads), int(streams), int(max_batch), 0)
+    h = ctypes.c_void_p()
+    _check(lib().nnfft_server_create(ctypes.byref(h), ctypes.byref(cfg)))
+    return h
+
+
+def nnfft_server_submit(server, N, v, x, f, y, sigma1=2.0, sigma2=2.0, m1=6, m2=6, prec=NNFFT_FP32_COMP,
+                        kind=NNFFT_REQ_NNFFT, quad=SINC_QUAD_GAUSS_LEGENDRE, n_quad=0, plan_key=0) -> int:
+    """v, x: float64 CUDA tensors; f, y: complex CUDA tensors of the plan's
+    precision.  The tensors must stay alive until the result is taken."""
+    import torch
+    _require(v, torch.float64, v.numel(), "v")
+    _require(x, torch.float64, x.numel(), "x")
+    dt = _cdtype(prec)
+    _require(f, dt, v.numel(), "f")
+    _require(y, dt, x.numel(), "y")
+    r = NnfftRequest(int(kind), int(prec), int(N), v.numel(), x.numel(), float(sigma1), float(sigma2),
+                     int(m1), int(m2), int(quad), 0, int(n_quad), v.data_ptr(), x.data_ptr(), f.data_ptr(),
+                     y.data_ptr(), int(plan_key))
+    t = ctypes.c_uint64()
+    _check(lib().nnfft_server_submit(server, ctypes.byref(r), ctypes.byref(t)))
+    return t.value
+
+
+def nnfft_server_wait(server, ticket) -> dict:
+    r = NnfftResult()
+    _check(lib().nnfft_server_wait(server, ctypes.c_uint64(ticket), ctypes.byref(r)))
+    return r.as_dict()
+
+
+def nnfft_server_poll(server, ticket):
+    """The result dict if finished, else None."""
+    r = NnfftResult()
+    st = lib().nnfft_server_poll(server, ctypes.c_uint64(ticket), ctypes.byref(r))
+    if st == NNFFT_ERR_BUSY:
+        return None
+    _check(st)
+    return r.as_dict()
+
+
+def nnfft_server_stats(server) -> dict:
+    s = NnfftServerStats()
+    _check(lib().nnfft_server_stats(server, ctypes.byref(s)))
+    return s.as_dict()
+
+
+def nnfft_server_evict(server, plan_key):
+    _check(lib().nnfft_server_evict(server, ctypes.c_uint64(plan_key)))
+
+
+def nnfft_server_destroy(server):
+    _check(lib().nnfft_server_destroy(server))
+
+
+class Server:
+    """Owning wrapper of a server; submit() keeps the request's tensors alive
+    until wait()/poll() has returned its result."""
+
+    def __init__(self, hbm_budget_bytes=0, planner_threads=0, streams=0, max_batch=0):
+        self.handle = nnfft_server_create(hbm_budget_bytes, planner_threads, streams, max_batch)
+        self._keep = {}
+
+    def submit(self, N, v, x, f, y, **kw):
+        t = nnfft_server_submit(self.handle, N, v, x, f, y, **kw)
+        self._keep[t] = (v, x, f, y)
+        return t
+
+    def wait(self, ticket):
+        try:
+            return nnfft_server_wait(self.handle, ticket)
+        finally:
+            self._keep.pop(ticket, None)
+
+    def poll(self, ticket):
+        r = nnfft_server_poll(self.handle, ticket)
+        if r is not None:
+            self._keep.pop(ticket, None)
+        return r
+
+    def stats(self):
+        return nnfft_server_stats(self.handle)
+
+    def evict(self, plan_key):
+        nnfft_server_evict(self.handle, plan_key)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            nnfft_server_destroy(self.handle)
+            self.handle = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

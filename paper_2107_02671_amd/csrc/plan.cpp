@@ -1,28 +1,27 @@
-// NNFFT plans (Algorithm 2.2 step 0) and the C ABI of include/nnfft.h.
+// NNFFT plans (Algorithm 2.2 step 0), the tuning table, the fast sinc
+// transform plan (Algorithm 6.1) and the C ABI of include/nnfft.h.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/nnfft.h"
 #include "host_math.h"
 #include "internal.h"
+#include "plan.h"
 
 using namespace nnfft;
 
 namespace {
 
 thread_local std::string g_last_error;
-
-nnfft_status fail(nnfft_status st, const std::string &msg)
-{
-    g_last_error = msg;
-    return st;
-}
 
 struct HipError {
     hipError_t err;
@@ -34,56 +33,107 @@ void hip_check(hipError_t e, const char *what)
     if (e != hipSuccess) throw HipError{e, what};
 }
 
-// Node layout of one side, built on the host.
-struct SideHost {
-    std::vector<int32_t> perm;
-    std::vector<PtRec> rec32;
-    std::vector<double> frac64;
-    std::vector<Item> items;
-    std::vector<Chunk> chunks;
-    std::vector<int32_t> chunk_block;
-    std::vector<int32_t> chunk_item0;   // first item of each chunk
-    std::vector<Chunk> launch;          // chunks in launch order, empty ones pad
-    std::vector<Item> launch_items;     // 64 items per launch slot, n = 0 pads
-    std::vector<PtRec> trec32;          // FP32: records in per-chunk transposed blocks
-    int64_t part_cells = 0;
-    int64_t nblocks = 0;
-};
+void *hip_alloc(void *, size_t bytes)
+{
+    void *p = nullptr;
+    return hipMalloc(&p, bytes) == hipSuccess ? p : nullptr;
+}
 
-// Tunables chosen per plan (the "autotuner" table; see choose_layout).
-struct Layout {
-    int64_t block;      // points per node block
-    int Q;              // max points per work item
-    int IW;             // items per workgroup (= threads)
-};
+void hip_release(void *, void *p)
+{
+    if (p) (void)hipFree(p);
+}
 
-// Rule table measured on MI355X: one-wavefront workgroups of 64 items; items
-// of up to Q points with Q growing with the node count (16 at 2^20 nodes,
-// 32 at most on the FP32 path, 8 on the FP64 path) so that a launch keeps a
-// few workgroups per CU;
-// blocks of 2^17 nodes (1 MB of c64 coefficients, well inside one XCD's L2),
-// split into 8 when that keeps them >= 2^14 nodes so every XCD has a block.
-Layout choose_layout(int64_t M, bool fp32)
+// Tuning table: (precision, ceil(log2 M)) -> layout.
+std::mutex g_tune_mu;
+std::map<std::pair<int, int>, Layout> g_tune;
+
+int size_class(int64_t M)
+{
+    int c = 0;
+    while (((int64_t)1 << c) < M) ++c;
+    return c;
+}
+
+}  // namespace
+
+namespace nnfft {
+
+const DevMem &hip_mem()
+{
+    static const DevMem m = {hip_alloc, hip_release, nullptr};
+    return m;
+}
+
+nnfft_status fail(nnfft_status st, const std::string &msg)
+{
+    g_last_error = msg;
+    return st;
+}
+
+// Rule measured on MI355X: one-wavefront workgroups of 64 items; items of up
+// to Q points with Q growing with the node count (16 at 2^20 nodes, 32 at
+// most on the FP32 path, 8 on the FP64 path) so that a launch keeps a few
+// workgroups per CU; blocks of 2^17 nodes (FP32; 1 MB of c64 coefficients,
+// well inside one XCD's 4 MB L2) or 2^16 (FP64), split into 8 when that keeps
+// them >= 2^14 nodes so that every XCD has a block.
+Layout rule_layout(int64_t M, bool fp32)
 {
     Layout L;
-    L.IW = kItemsPerWg;
-    const int64_t cus = 256;
-    const int64_t target_wg = 4 * cus;
-    int64_t q = M / (L.IW * target_wg);
+    const int64_t target_wg = 4 * 256;
+    const int64_t q = M / (kItemsPerWg * target_wg);
     int Q = 2;
     while (Q < q && Q < (fp32 ? 32 : 8)) Q *= 2;
     L.Q = Q;
     const int64_t bmax = fp32 ? (int64_t)1 << 17 : (int64_t)1 << 16;
+    L.block = bmax;
+    L.grid_max = 0;
+    return sanitize_layout(L, M, fp32);
+}
+
+Layout sanitize_layout(Layout L, int64_t M, bool fp32)
+{
+    L.Q = std::max(1, std::min(L.Q, fp32 ? 64 : 8));   // the FP64 kernels hold 8 points per item
+    if (!fp32) L.grid_max = 0;                           // FP64 launches are one workgroup per slot
+    L.grid_max = std::max(0, L.grid_max);
     const int64_t bmin = (int64_t)1 << 14;
-    int64_t nblk = (M + bmax - 1) / bmax;
+    int64_t block = std::max<int64_t>(1, L.block);
+    int64_t nblk = (M + block - 1) / block;
     if (nblk < 8 && M >= 8 * bmin) nblk = 8;
     if (nblk < 1) nblk = 1;
-    L.block = (M + nblk - 1) / nblk;
-    // overrides for tuning sweeps
-    if (const char *e = std::getenv("NNFFT_ITEM_POINTS")) L.Q = std::max(1, std::min(fp32 ? 64 : 8, atoi(e)));
-    if (const char *e = std::getenv("NNFFT_BLOCK_POINTS")) L.block = std::max<int64_t>(1, atoll(e));
+    L.block = std::max<int64_t>(1, (M + nblk - 1) / nblk);
     return L;
 }
+
+Layout choose_layout(int64_t M, bool fp32)
+{
+    Layout L;
+    if (get_tuned_layout(fp32, M, L)) return sanitize_layout(L, M, fp32);
+    return rule_layout(M, fp32);
+}
+
+void set_tuned_layout(bool fp32, int64_t M, const Layout &L)
+{
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune[{fp32 ? 1 : 0, size_class(M)}] = L;
+}
+
+bool get_tuned_layout(bool fp32, int64_t M, Layout &L)
+{
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = g_tune.find({fp32 ? 1 : 0, size_class(M)});
+    if (it == g_tune.end()) return false;
+    L = it->second;
+    return true;
+}
+
+void clear_tuned_layouts()
+{
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune.clear();
+}
+
+namespace {
 
 // Builds the sorted records, items, chunks and schedule of one side.
 // t_k = scale * node_k (grid units); bin = floor(t_k) + off in [0, nbins).
@@ -151,7 +201,7 @@ bool build_side(const std::vector<double> &nodes, double scale, int64_t off, int
         for (size_t ci = it0; ci < it1;) {
             const int32_t blo = S.items[ci].bin;
             size_t cj = ci;
-            while (cj < it1 && (int)(cj - ci) < L.IW && S.items[cj].bin - blo < L.IW) ++cj;
+            while (cj < it1 && (int)(cj - ci) < kItemsPerWg && S.items[cj].bin - blo < kItemsPerWg) ++cj;
             Chunk c{};
             c.nitem = (int32_t)(cj - ci);
             c.bin_lo = blo;
@@ -217,13 +267,6 @@ bool build_side(const std::vector<double> &nodes, double scale, int64_t off, int
     return true;
 }
 
-// FFT factorization chosen at plan time (copied into FftArgs)
-struct FftPlan {
-    int32_t N2 = 0, n1 = 0, n2 = 0, npassA = 0, npassB = 0;
-    int radA[kMaxPasses] = {}, radB[kMaxPasses] = {};
-    int32_t batchA = 0, batchB = 0, threadsA = 0, threadsB = 0, S = 0;
-};
-
 // largest-square-ish factorization N2 = n1 * n2 with both parts <= limit
 bool fft_factor(int64_t N2, int64_t limit, int64_t &n1, int64_t &n2)
 {
@@ -247,95 +290,118 @@ bool fft_factor(int64_t N2, int64_t limit, int64_t &n1, int64_t &n2)
 
 }  // namespace
 
-// ---------------------------------------------------------------------------
-struct nnfft_plan_s {
-    nnfft_info_t info{};
-    PlanDev desc{};
-    PlanDev *ddesc = nullptr;          // device copy of desc (batched launches)
-    std::vector<void *> allocs;
-    int64_t bytes = 0;
-    std::vector<hipEvent_t> prof_ev;   // 4 events per profiled exec
-    int prof_max = 0, prof_used = 0;
-
-    void drop_events()
-    {
-        for (hipEvent_t e : prof_ev) (void)hipEventDestroy(e);
-        prof_ev.clear();
-        prof_max = prof_used = 0;
-    }
-    ~nnfft_plan_s()
-    {
-        drop_events();
-        for (void *p : allocs) (void)hipFree(p);
-    }
+// Device block of a plan: every array at a 256-byte aligned offset, the
+// uploaded tables first (one host-to-device copy), the scratch after them.
+struct Carver {
+    uintptr_t base;
+    size_t off = 0;
+    std::vector<char> *stage;   // host image of the uploaded part (null: sizing pass)
+    explicit Carver(uintptr_t b, std::vector<char> *st) : base(b), stage(st) {}
     template <typename T>
-    T *upload(const std::vector<T> &v, hipStream_t s)
+    T *put(const std::vector<T> &v)
     {
-        const size_t n = std::max<size_t>(1, v.size());
-        void *p = nullptr;
-        hip_check(hipMalloc(&p, n * sizeof(T)), "hipMalloc");
-        allocs.push_back(p);
-        bytes += (int64_t)(n * sizeof(T));
-        if (!v.empty()) hip_check(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s),
-                                  "hipMemcpyAsync");
-        return static_cast<T *>(p);
+        off = (off + 255) & ~(size_t)255;
+        const size_t nb = std::max<size_t>(1, v.size()) * sizeof(T);
+        if (stage) {
+            if (stage->size() < off + nb) stage->resize(off + nb);
+            if (!v.empty()) std::memcpy(stage->data() + off, v.data(), v.size() * sizeof(T));
+        }
+        T *p = reinterpret_cast<T *>(base + off);
+        off += nb;
+        return p;
     }
-    void *scratch(size_t nbytes)
+    void *scratch(size_t nb)
     {
-        void *p = nullptr;
-        hip_check(hipMalloc(&p, std::max<size_t>(nbytes, 16)), "hipMalloc");
-        allocs.push_back(p);
-        bytes += (int64_t)nbytes;
+        off = (off + 255) & ~(size_t)255;
+        void *p = reinterpret_cast<void *>(base + off);
+        off += std::max<size_t>(nb, 16);
         return p;
     }
 };
 
-struct sinc_plan_s {
-    nnfft_plan_t p1 = nullptr, p2 = nullptr;
-    double *w = nullptr;      // [n_nodes] quadrature weights (FP64, device)
-    void *g = nullptr;        // [n_nodes] complex intermediate
-    int64_t n_nodes = 0;
-    int32_t prec = 0;
-    ~sinc_plan_s()
-    {
-        if (p1) nnfft_destroy(p1);
-        if (p2) nnfft_destroy(p2);
-        if (w) (void)hipFree(w);
-        if (g) (void)hipFree(g);
-    }
-};
-
-namespace nnfft {
-// sinc weight multiply (kernels_sinc.hip)
-hipError_t launch_scale_by_weights(int prec, const double *w, const void *src, void *dst, int64_t n,
-                                   hipStream_t s);
-}
-
-// ---------------------------------------------------------------------------
-extern "C" {
-
-const char *nnfft_last_error(void) { return g_last_error.c_str(); }
-
-const char *nnfft_version(void) { return "nnfft-mi355x 0.1 (gfx950)"; }
-
-nnfft_status nnfft_derive_params(int64_t N, double sigma1, double sigma2, int m1, int m2,
-                                 nnfft_info_t *out)
+// Lays the plan out in its device block (base 0: sizing pass) and fills the
+// kernel descriptors.  Returns the end of the uploaded part in *upload_end.
+void layout_plan(const HostPlan &H, Carver &C, PlanDev &D, size_t *upload_end, PlanDev **ddesc)
 {
-    if (!out) return fail(NNFFT_ERR_ARG, "null output");
-    const nnfft_status st = derive_params(N, sigma1, sigma2, m1, m2, out);
-    if (st != NNFFT_OK) return fail(st, "invalid NNFFT parameters (N >= 1, m >= 2, sigma > 1, "
-                                        "2 m1 < N1 and 2 m2 <= (1 - 1/sigma1) N2 are required)");
-    return NNFFT_OK;
+    const nnfft_info_t &P = H.info;
+    const bool fp32 = H.fp32;
+    D = PlanDev{};
+    D.prec = P.precision;
+    D.sp_grid_max = H.lay1.grid_max;
+    D.ip_grid_max = H.lay2.grid_max;
+    SpreadArgs &SA = D.sp;
+    InterpArgs &IA = D.ip;
+    FftArgs &FA = D.fft;
+    SA.items = C.put(H.sp.launch_items);
+    SA.chunks = C.put(H.sp.launch);
+    SA.ngrid = (int32_t)H.sp.launch.size();
+    SA.m = P.m1;
+    SA.beta = P.beta1;
+    SA.inv_den = 1.0 / (1.0 - std::exp(-2.0 * P.beta1));
+    IA.items = C.put(H.ip.launch_items);
+    IA.chunks = C.put(H.ip.launch);
+    IA.ngrid = (int32_t)H.ip.launch.size();
+    IA.m = P.m2;
+    IA.beta = P.beta2;
+    IA.inv_den = 1.0 / (1.0 - std::exp(-2.0 * P.beta2));
+    IA.N2 = (int32_t)P.N2;
+    IA.ip_off = (int32_t)(P.N2 / 2);
+    IA.u_to_x = (double)P.N1 / ((double)P.N2 * (double)P.N_star);
+    IA.corr = C.put(H.corr);
+    IA.corr_deg = P.corr_degree;
+    if (fp32) {
+        SA.rec32 = C.put(H.sp.trec32);
+        IA.rec32 = C.put(H.ip.trec32);
+        SA.C = C.put(H.C1);
+        IA.C = C.put(H.C2);
+    } else {
+        SA.perm = C.put(H.sp.perm);
+        SA.frac64 = C.put(H.sp.frac64);
+        IA.perm = C.put(H.ip.perm);
+        IA.frac64 = C.put(H.ip.frac64);
+    }
+    FA.merge_off = C.put(H.moff);
+    FA.merge_idx = C.put(H.midx);
+    FA.deconv = C.put(H.deconv);
+    if (fp32) FA.tw = C.put(H.tw32);
+    else FA.tw = C.put(H.tw64);
+    *upload_end = C.off;
+    const size_t csz = fp32 ? 8 : 16;
+    SA.partial = C.scratch((size_t)H.sp.part_cells * 16);
+    FA.partial = SA.partial;
+    FA.Y = C.scratch((size_t)P.N2 * csz);
+    FA.hlin = C.scratch((size_t)(P.N2 + 1) * csz);
+    IA.hlin = FA.hlin;
+    FA.N2 = (int32_t)P.N2;
+    FA.G1 = (int32_t)P.G1;
+    FA.n1 = H.fd.n1;
+    FA.n2 = H.fd.n2;
+    FA.batchA = H.fd.batchA;
+    FA.batchB = H.fd.batchB;
+    FA.threadsA = H.fd.threadsA;
+    FA.threadsB = H.fd.threadsB;
+    FA.S = H.fd.S;
+    FA.npassA = H.fd.npassA;
+    FA.npassB = H.fd.npassB;
+    for (int i = 0; i < kMaxPasses; ++i) {
+        FA.radA[i] = (int8_t)H.fd.radA[i];
+        FA.radB[i] = (int8_t)H.fd.radB[i];
+    }
+    *ddesc = static_cast<PlanDev *>(C.scratch(sizeof(PlanDev)));   // the descriptor's device copy
 }
 
-static nnfft_status plan_impl(nnfft_plan_t *out, int64_t N, int64_t M1, int64_t M2, double sigma1,
-                              double sigma2, int m1, int m2, nnfft_precision prec,
-                              const std::vector<double> &v, const std::vector<double> &x,
-                              hipStream_t s)
+nnfft_status plan_host(HostPlan &H, int64_t N, int64_t M1, int64_t M2, double sigma1, double sigma2,
+                       int m1, int m2, nnfft_precision prec, const std::vector<double> &v,
+                       const std::vector<double> &x, const Layout *lay1, const Layout *lay2)
 {
     nnfft_info_t P;
     nnfft_status st = derive_params(N, sigma1, sigma2, m1, m2, &P);
-    if (st != NNFFT_OK) return fail(st, "invalid NNFFT parameters");
+    if (st != NNFFT_OK) return fail(st, "invalid NNFFT parameters (N >= 1, m >= 2, sigma > 1, "
+                                        "2 m1 < N1 and 2 m2 <= (1 - 1/sigma1) N2 are required)");
+    if (M1 < 1 || M2 < 1 || M1 > ((int64_t)1 << 30) || M2 > ((int64_t)1 << 30))
+        return fail(NNFFT_ERR_ARG, "node counts must be in [1, 2^30]");
+    if (prec != NNFFT_FP64_PLAIN && prec != NNFFT_FP32_COMP) return fail(NNFFT_ERR_ARG, "unknown precision");
+    if ((int64_t)v.size() != M1 || (int64_t)x.size() != M2) return fail(NNFFT_ERR_ARG, "node array sizes");
     if (m1 > kMaxM || m2 > kMaxM) return fail(NNFFT_ERR_UNSUPPORTED, "m > 16 is not implemented");
     const bool fp32 = (prec == NNFFT_FP32_COMP);
     if (fp32 && (m1 < 4 || m2 < 4))
@@ -351,72 +417,86 @@ static nnfft_status plan_impl(nnfft_plan_t *out, int64_t N, int64_t M1, int64_t 
     P.M1 = M1;
     P.M2 = M2;
     P.precision = prec;
+    H.fp32 = fp32;
 
     // tables in FP64 -----------------------------------------------------
-    std::vector<double> C1d, C2d;
     double e1 = 0.0, e2 = 0.0;
     if (fp32) {
-        C1d = fit_window_taps(m1, P.beta1, kDeg, &e1);
-        C2d = fit_window_taps(m2, P.beta2, kDeg, &e2);
+        const std::vector<double> c1 = fit_window_taps(m1, P.beta1, kDeg, &e1);
+        const std::vector<double> c2 = fit_window_taps(m2, P.beta2, kDeg, &e2);
         P.window_degree = kDeg;
         P.window_fit_err = std::max(e1, e2);
         if (P.window_fit_err > 5e-8)
             return fail(NNFFT_ERR_UNSUPPORTED, "window polynomial misses FP32 accuracy for these sigma, m");
+        H.C1.assign(c1.begin(), c1.end());
+        H.C2.assign(c2.begin(), c2.end());
     }
     double corr_err = 0.0;
-    std::vector<double> corr = fit_inverse_phi1(P, fp32 ? 1e-9 : 1e-14, fp32 ? kCorr32 : kMaxCorrDeg, &corr_err);
-    P.corr_degree = (int32_t)corr.size() - 1;
+    H.corr = fit_inverse_phi1(P, fp32 ? 1e-9 : 1e-14, fp32 ? kCorr32 : kMaxCorrDeg, &corr_err);
+    P.corr_degree = (int32_t)H.corr.size() - 1;
     P.corr_fit_err = corr_err;
     if (corr_err > (fp32 ? 1e-8 : 1e-12))
         return fail(NNFFT_ERR_UNSUPPORTED, "1/phi_hat_1 series does not converge for this sigma1");
-    if (fp32) corr.resize(kCorr32 + 1, 0.0);   // zero-padded to the unrolled length
+    if (fp32) H.corr.resize(kCorr32 + 1, 0.0);   // zero-padded to the unrolled length
 
-    std::vector<double> deconv(P.G1);
+    H.deconv.resize(P.G1);
     for (int64_t c = 0; c < P.G1; ++c) {
         const double l = (double)(c - P.G1 / 2);
         const double phi2 = (double)m2 / (double)P.N2 * window_sinh_hat(m2 * l / (double)P.N2, P.beta2);
-        deconv[c] = 1.0 / ((double)P.N1 * (double)P.N2 * phi2);
+        H.deconv[c] = 1.0 / ((double)P.N1 * (double)P.N2 * phi2);
     }
-    const std::vector<double> tw = twiddles(P.N2);
+    H.tw64 = twiddles(P.N2);
+    if (fp32) {
+        H.tw32.assign(H.tw64.begin(), H.tw64.end());
+        H.tw64.clear();
+    }
 
     // node layouts ----------------------------------------------------------
-    const Layout lay1 = choose_layout(M1, fp32), lay2 = choose_layout(M2, fp32);
-    SideHost sp, ip;
+    H.lay1 = lay1 ? sanitize_layout(*lay1, M1, fp32) : choose_layout(M1, fp32);
+    H.lay2 = lay2 ? sanitize_layout(*lay2, M2, fp32) : choose_layout(M2, fp32);
     std::string err;
     // spreading: t_k = N1 v*_k = N1 N v_k / N*, bin = floor(t_k) + G1/2
-    if (!build_side(v, (double)P.N1 * (double)N / (double)P.N_star, P.G1 / 2, P.G1, lay1, fp32, m1, sp, err))
+    if (!build_side(v, (double)P.N1 * (double)N / (double)P.N_star, P.G1 / 2, P.G1, H.lay1, fp32, m1, H.sp, err))
         return fail(NNFFT_ERR_ARG, err);
     // interpolation: u_j = N2 N* x_j / N1, bin = floor(u_j) + N2/2
-    if (!build_side(x, (double)P.N2 * (double)P.N_star / (double)P.N1, P.N2 / 2, P.N2 + 1, lay2, fp32, 0,
-                    ip, err))
+    if (!build_side(x, (double)P.N2 * (double)P.N_star / (double)P.N1, P.N2 / 2, P.N2 + 1, H.lay2, fp32, 0,
+                    H.ip, err))
         return fail(NNFFT_ERR_ARG, err);
-    if (sp.part_cells >= ((int64_t)1 << 31)) return fail(NNFFT_ERR_UNSUPPORTED, "too many partial cells");
+    if (H.sp.part_cells >= ((int64_t)1 << 31)) return fail(NNFFT_ERR_UNSUPPORTED, "too many partial cells");
+    // the sorted copies are only needed by the FP64 kernels
+    if (fp32) {
+        std::vector<int32_t>().swap(H.sp.perm);
+        std::vector<int32_t>().swap(H.ip.perm);
+    }
+    std::vector<PtRec>().swap(H.sp.rec32);
+    std::vector<PtRec>().swap(H.ip.rec32);
 
     // merge lists: for each grid cell the partial cells of the chunks covering it
-    std::vector<int32_t> moff(P.G1 + 1, 0), midx;
-    for (const Chunk &c : sp.chunks) {
+    H.moff.assign(P.G1 + 1, 0);
+    for (const Chunk &c : H.sp.chunks) {
         const int W = c.nbin + 2 * m1 - 1;
         for (int w = 0; w < W; ++w) {
             const int64_t cell = (int64_t)c.bin_lo - m1 + 1 + w;
             if (cell < 0 || cell >= P.G1) return fail(NNFFT_ERR_ARG, "internal: window outside the grid");
-            moff[cell + 1]++;
+            H.moff[cell + 1]++;
         }
     }
-    for (int64_t c = 0; c < P.G1; ++c) moff[c + 1] += moff[c];
-    midx.resize(moff[P.G1]);
+    for (int64_t c = 0; c < P.G1; ++c) H.moff[c + 1] += H.moff[c];
+    H.midx.resize(H.moff[P.G1]);
     {
-        std::vector<int32_t> cur(moff.begin(), moff.end() - 1);
-        for (const Chunk &c : sp.chunks) {
+        std::vector<int32_t> cur(H.moff.begin(), H.moff.end() - 1);
+        for (const Chunk &c : H.sp.chunks) {
             const int W = c.nbin + 2 * m1 - 1;
             for (int w = 0; w < W; ++w) {
                 const int64_t cell = (int64_t)c.bin_lo - m1 + 1 + w;
-                midx[cur[cell]++] = c.part_off + w;
+                H.midx[cur[cell]++] = c.part_off + w;
             }
         }
     }
 
     // FFT factorization -----------------------------------------------------
-    FftPlan fd{};
+    FftPlan &fd = H.fd;
+    fd = FftPlan{};
     fd.N2 = (int32_t)P.N2;
     // one workgroup for short transforms; longer ones as two launches of
     // many workgroups (one or two columns each) so that the partial merge in
@@ -439,7 +519,8 @@ static nnfft_status plan_impl(nnfft_plan_t *out, int64_t N, int64_t M1, int64_t 
         int64_t n1, n2;
         if (!fft_factor(P.N2, kvals, n1, n2)) return fail(NNFFT_ERR_UNSUPPORTED, "FFT length cannot be split");
         const std::vector<int> rA = radix_passes(n2), rB = radix_passes(n1);
-        if (rA.empty() || rB.empty()) return fail(NNFFT_ERR_UNSUPPORTED, "FFT length not 2,3,5-smooth");
+        if (rA.empty() || rB.empty() || (int)rA.size() > kMaxPasses || (int)rB.size() > kMaxPasses)
+            return fail(NNFFT_ERR_UNSUPPORTED, "FFT length not 2,3,5-smooth");
         fd.n1 = (int32_t)n1;
         fd.n2 = (int32_t)n2;
         fd.npassA = (int32_t)rA.size();
@@ -453,106 +534,166 @@ static nnfft_status plan_impl(nnfft_plan_t *out, int64_t N, int64_t M1, int64_t 
     }
     {
         const double U = (double)P.N2 * (double)P.N_star / (2.0 * (double)P.N1);
-        int64_t S = (int64_t)std::ceil(U) + m2;
+        const int64_t S = (int64_t)std::ceil(U) + m2;
         fd.S = (int32_t)std::min<int64_t>(S, P.N2 / 2);
     }
 
-    // device upload -----------------------------------------------------------
-    nnfft_plan_s *pl = new nnfft_plan_s();
+    // device block size -------------------------------------------------------
+    PlanDev D, *dd = nullptr;
+    Carver C(0, nullptr);
+    size_t upload_end = 0;
+    H.info = P;
+    layout_plan(H, C, D, &upload_end, &dd);
+    H.total_bytes = C.off;
+    H.info.device_bytes = (int64_t)C.off;
+    H.info.block_points = H.lay1.block;
+    H.info.items_points = H.lay1.Q;
+    H.info.spread_workgroups = D.sp.ngrid;
+    H.info.interp_workgroups = D.ip.ngrid;
+    H.info.fft_n1 = fd.n1;
+    H.info.fft_n2 = fd.n2;
+    return NNFFT_OK;
+}
+
+nnfft_status plan_create(const HostPlan &H, const DevMem &mem, hipStream_t s, nnfft_plan_t *out)
+{
+    *out = nullptr;
+    void *base = mem.alloc(mem.ctx, H.total_bytes);
+    if (!base) return fail(NNFFT_ERR_NOMEM, "device memory for the plan (" + std::to_string(H.total_bytes) +
+                                                " bytes) is not available");
+    nnfft_plan_s *pl = new (std::nothrow) nnfft_plan_s();
+    if (!pl) {
+        mem.release(mem.ctx, base);
+        return fail(NNFFT_ERR_NOMEM, "host allocation failed");
+    }
+    pl->base = base;
+    pl->mem = mem;
+    pl->info = H.info;
     try {
-        PlanDev &D = pl->desc;
-        D.prec = prec;
-        if (const char *e = std::getenv("NNFFT_GRID_MAX")) D.sp_grid_max = D.ip_grid_max = atoi(e);
-        SpreadArgs &SA = D.sp;
-        InterpArgs &IA = D.ip;
-        FftArgs &FA = D.fft;
-        SA.items = pl->upload(sp.launch_items, s);
-        SA.chunks = pl->upload(sp.launch, s);
-        SA.ngrid = (int32_t)sp.launch.size();
-        SA.m = m1;
-        SA.beta = P.beta1;
-        SA.inv_den = 1.0 / (1.0 - std::exp(-2.0 * P.beta1));
-        IA.items = pl->upload(ip.launch_items, s);
-        IA.chunks = pl->upload(ip.launch, s);
-        IA.ngrid = (int32_t)ip.launch.size();
-        IA.m = m2;
-        IA.beta = P.beta2;
-        IA.inv_den = 1.0 / (1.0 - std::exp(-2.0 * P.beta2));
-        IA.N2 = (int32_t)P.N2;
-        IA.ip_off = (int32_t)(P.N2 / 2);
-        IA.u_to_x = (double)P.N1 / ((double)P.N2 * (double)P.N_star);
-        IA.corr = pl->upload(corr, s);
-        IA.corr_deg = P.corr_degree;
-        if (fp32) {
-            SA.rec32 = pl->upload(sp.trec32, s);
-            IA.rec32 = pl->upload(ip.trec32, s);
-            std::vector<float> c1(C1d.begin(), C1d.end()), c2(C2d.begin(), C2d.end());
-            SA.C = pl->upload(c1, s);
-            IA.C = pl->upload(c2, s);
-        } else {
-            SA.perm = pl->upload(sp.perm, s);
-            SA.frac64 = pl->upload(sp.frac64, s);
-            IA.perm = pl->upload(ip.perm, s);
-            IA.frac64 = pl->upload(ip.frac64, s);
-        }
-        const size_t csz = fp32 ? 8 : 16;
-        SA.partial = pl->scratch((size_t)sp.part_cells * 16);
-        FA.partial = SA.partial;
-        FA.merge_off = pl->upload(moff, s);
-        FA.merge_idx = pl->upload(midx, s);
-        FA.deconv = pl->upload(deconv, s);
-        if (fp32) {
-            std::vector<float> tw32(tw.begin(), tw.end());
-            FA.tw = pl->upload(tw32, s);
-        } else {
-            FA.tw = pl->upload(tw, s);
-        }
-        FA.Y = pl->scratch((size_t)P.N2 * csz);
-        FA.hlin = pl->scratch((size_t)(P.N2 + 1) * csz);
-        IA.hlin = FA.hlin;
-        FA.N2 = (int32_t)P.N2;
-        FA.G1 = (int32_t)P.G1;
-        FA.n1 = fd.n1;
-        FA.n2 = fd.n2;
-        FA.batchA = fd.batchA;
-        FA.batchB = fd.batchB;
-        FA.threadsA = fd.threadsA;
-        FA.threadsB = fd.threadsB;
-        FA.S = fd.S;
-        FA.npassA = fd.npassA;
-        FA.npassB = fd.npassB;
-        for (int i = 0; i < kMaxPasses; ++i) {
-            FA.radA[i] = (int8_t)fd.radA[i];
-            FA.radB[i] = (int8_t)fd.radB[i];
-        }
-        pl->ddesc = static_cast<PlanDev *>(pl->scratch(sizeof(PlanDev)));
+        std::vector<char> stage;
+        Carver C((uintptr_t)base, &stage);
+        size_t upload_end = 0;
+        layout_plan(H, C, pl->desc, &upload_end, &pl->ddesc);
+        hip_check(hipMemcpyAsync(base, stage.data(), upload_end, hipMemcpyHostToDevice, s), "hipMemcpyAsync");
         hip_check(hipMemcpyAsync(pl->ddesc, &pl->desc, sizeof(PlanDev), hipMemcpyHostToDevice, s),
                   "hipMemcpyAsync");
         hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
-        P.device_bytes = pl->bytes;
-        P.block_points = lay1.block;
-        P.items_points = lay1.Q;
-        P.spread_workgroups = D.sp.ngrid;
-        P.interp_workgroups = D.ip.ngrid;
-        P.fft_n1 = fd.n1;
-        P.fft_n2 = fd.n2;
-        pl->info = P;
     } catch (const HipError &e) {
         delete pl;
-        return fail(e.err == hipErrorOutOfMemory ? NNFFT_ERR_NOMEM : NNFFT_ERR_DEVICE,
-                    std::string(e.what) + ": " + hipGetErrorString(e.err));
+        return fail(NNFFT_ERR_DEVICE, std::string(e.what) + ": " + hipGetErrorString(e.err));
+    } catch (const std::bad_alloc &) {
+        delete pl;
+        return fail(NNFFT_ERR_NOMEM, "host allocation failed");
     }
     *out = pl;
     return NNFFT_OK;
 }
 
-static nnfft_status copy_nodes(const double *d, int64_t n, std::vector<double> &h, hipStream_t s)
+nnfft_status copy_nodes(const double *d, int64_t n, std::vector<double> &h, hipStream_t s)
 {
     h.resize(n);
     if (n == 0) return NNFFT_OK;
     hipError_t e = hipMemcpyAsync(h.data(), d, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return fail(NNFFT_ERR_DEVICE, std::string("copying nodes: ") + hipGetErrorString(e));
+    return NNFFT_OK;
+}
+
+nnfft_status sinc_host(SincHostPlan &S, int64_t N, int64_t L1, int64_t L2, sinc_quad quad, int64_t n_quad,
+                       double sigma1, double sigma2, int m1, int m2, nnfft_precision prec,
+                       const std::vector<double> &a, const std::vector<double> &b)
+{
+    if (n_quad < 1 || n_quad > ((int64_t)1 << 24)) return fail(NNFFT_ERR_ARG, "n_quad out of range");
+    if (quad != SINC_QUAD_GAUSS_LEGENDRE && quad != SINC_QUAD_CLENSHAW_CURTIS)
+        return fail(NNFFT_ERR_ARG, "unknown quadrature rule");
+    std::vector<double> z;
+    if (quad == SINC_QUAD_GAUSS_LEGENDRE) gauss_legendre_rule(n_quad, z, S.w);
+    else clenshaw_curtis_rule(n_quad, z, S.w);
+    const int64_t nn = (int64_t)z.size();
+    std::vector<double> xs(nn), vs(nn);
+    for (int64_t j = 0; j < nn; ++j) {
+        xs[j] = 0.5 * z[j];    // step 1: spatial nodes z_j / 2
+        vs[j] = -0.5 * z[j];   // step 3: frequencies -z_j / 2
+    }
+    nnfft_status st = plan_host(S.h1, N, L1, nn, sigma1, sigma2, m1, m2, prec, a, xs);
+    if (st == NNFFT_OK) st = plan_host(S.h2, N, nn, L2, sigma1, sigma2, m1, m2, prec, vs, b);
+    if (st != NNFFT_OK) return st;
+    S.n_nodes = nn;
+    S.prec = prec;
+    const size_t csz = (prec == NNFFT_FP32_COMP) ? 8 : 16;
+    S.wg_bytes = ((size_t)nn * sizeof(double) + 255) / 256 * 256 + (size_t)nn * csz;
+    S.total_bytes = S.h1.total_bytes + S.h2.total_bytes + S.wg_bytes;
+    return NNFFT_OK;
+}
+
+nnfft_status sinc_create(const SincHostPlan &S, const DevMem &mem, hipStream_t s, sinc_plan_t *out)
+{
+    *out = nullptr;
+    sinc_plan_s *sp = new (std::nothrow) sinc_plan_s();
+    if (!sp) return fail(NNFFT_ERR_NOMEM, "host allocation failed");
+    sp->mem = mem;
+    sp->n_nodes = S.n_nodes;
+    sp->prec = S.prec;
+    nnfft_status st = plan_create(S.h1, mem, s, &sp->p1);
+    if (st == NNFFT_OK) st = plan_create(S.h2, mem, s, &sp->p2);
+    if (st != NNFFT_OK) {
+        delete sp;
+        return st;
+    }
+    sp->wg_base = mem.alloc(mem.ctx, S.wg_bytes);
+    if (!sp->wg_base) {
+        delete sp;
+        return fail(NNFFT_ERR_NOMEM, "device memory for the quadrature weights is not available");
+    }
+    sp->w = static_cast<double *>(sp->wg_base);
+    sp->g = static_cast<char *>(sp->wg_base) + ((size_t)S.n_nodes * sizeof(double) + 255) / 256 * 256;
+    hipError_t e = hipMemcpyAsync(sp->w, S.w.data(), (size_t)S.n_nodes * sizeof(double), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        delete sp;
+        return fail(NNFFT_ERR_DEVICE, hipGetErrorString(e));
+    }
+    *out = sp;
+    return NNFFT_OK;
+}
+
+}  // namespace nnfft
+
+void nnfft_plan_s::drop_events()
+{
+    for (hipEvent_t e : prof_ev)
+        if (e) (void)hipEventDestroy(e);
+    prof_ev.clear();
+    prof_max = prof_used = 0;
+}
+
+nnfft_plan_s::~nnfft_plan_s()
+{
+    drop_events();
+    if (base) mem.release(mem.ctx, base);
+}
+
+sinc_plan_s::~sinc_plan_s()
+{
+    if (p1) nnfft_destroy(p1);
+    if (p2) nnfft_destroy(p2);
+    if (wg_base) mem.release(mem.ctx, wg_base);
+}
+
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char *nnfft_last_error(void) { return g_last_error.c_str(); }
+
+const char *nnfft_version(void) { return "nnfft-mi355x 0.2 (gfx950)"; }
+
+nnfft_status nnfft_derive_params(int64_t N, double sigma1, double sigma2, int m1, int m2,
+                                 nnfft_info_t *out)
+{
+    if (!out) return fail(NNFFT_ERR_ARG, "null output");
+    const nnfft_status st = derive_params(N, sigma1, sigma2, m1, m2, out);
+    if (st != NNFFT_OK) return fail(st, "invalid NNFFT parameters (N >= 1, m >= 2, sigma > 1, "
+                                        "2 m1 < N1 and 2 m2 <= (1 - 1/sigma1) N2 are required)");
     return NNFFT_OK;
 }
 
@@ -573,7 +714,10 @@ nnfft_status nnfft_plan(nnfft_plan_t *out, int64_t N, int64_t M1, int64_t M2, do
         if (st != NNFFT_OK) return st;
         st = copy_nodes(x, M2, hx, s);
         if (st != NNFFT_OK) return st;
-        return plan_impl(out, N, M1, M2, sigma1, sigma2, m1, m2, prec, hv, hx, s);
+        HostPlan H;
+        st = plan_host(H, N, M1, M2, sigma1, sigma2, m1, m2, prec, hv, hx);
+        if (st != NNFFT_OK) return st;
+        return plan_create(H, hip_mem(), s, out);
     } catch (const std::bad_alloc &) {
         return fail(NNFFT_ERR_NOMEM, "host allocation failed");
     }
@@ -618,7 +762,8 @@ nnfft_status nnfft_exec_batch(int n, const nnfft_plan_t *plans, const void *cons
             if (host.empty()) continue;
             const hipError_t e = launch_exec_batch((int)host.size(), host.data(), dev.data(), fi.data(),
                                                    yi.data(), static_cast<hipStream_t>(stream));
-            if (e != hipSuccess) return fail(NNFFT_ERR_DEVICE, std::string("batched launch: ") + hipGetErrorString(e));
+            if (e != hipSuccess)
+                return fail(NNFFT_ERR_DEVICE, std::string("batched launch: ") + hipGetErrorString(e));
         }
     } catch (const std::bad_alloc &) {
         return fail(NNFFT_ERR_NOMEM, "host allocation failed");
@@ -637,7 +782,7 @@ nnfft_status nnfft_profile_start(nnfft_plan_t p, int max_execs)
 {
     if (!p || max_execs < 1) return fail(NNFFT_ERR_ARG, "bad argument");
     p->drop_events();
-    p->prof_ev.resize(4 * (size_t)max_execs);
+    p->prof_ev.assign(4 * (size_t)max_execs, nullptr);
     for (auto &e : p->prof_ev) {
         if (hipEventCreate(&e) != hipSuccess) {
             e = nullptr;
@@ -683,6 +828,44 @@ nnfft_status nnfft_destroy(nnfft_plan_t p)
 }
 
 // ---------------------------------------------------------------------------
+// Tuning table
+// ---------------------------------------------------------------------------
+nnfft_status nnfft_set_tuning(nnfft_precision prec, int64_t M, const nnfft_tuning_t *t)
+{
+    if (!t || M < 1 || (prec != NNFFT_FP64_PLAIN && prec != NNFFT_FP32_COMP) || t->items_points < 1 ||
+        t->block_points < 1 || t->grid_max < 0)
+        return fail(NNFFT_ERR_ARG, "bad tuning");
+    Layout L;
+    L.Q = t->items_points;
+    L.block = t->block_points;
+    L.grid_max = t->grid_max;
+    set_tuned_layout(prec == NNFFT_FP32_COMP, M, L);
+    return NNFFT_OK;
+}
+
+nnfft_status nnfft_get_tuning(nnfft_precision prec, int64_t M, nnfft_tuning_t *out)
+{
+    if (!out || M < 1 || (prec != NNFFT_FP64_PLAIN && prec != NNFFT_FP32_COMP))
+        return fail(NNFFT_ERR_ARG, "bad argument");
+    Layout L;
+    const bool fp32 = prec == NNFFT_FP32_COMP;
+    const bool tuned = get_tuned_layout(fp32, M, L);
+    L = choose_layout(M, fp32);
+    *out = nnfft_tuning_t{};
+    out->items_points = L.Q;
+    out->grid_max = L.grid_max;
+    out->block_points = L.block;
+    out->tuned = tuned ? 1 : 0;
+    return NNFFT_OK;
+}
+
+nnfft_status nnfft_clear_tuning(void)
+{
+    clear_tuned_layouts();
+    return NNFFT_OK;
+}
+
+// ---------------------------------------------------------------------------
 // Fast sinc transform (Algorithm 6.1)
 // ---------------------------------------------------------------------------
 nnfft_status sinc_plan(sinc_plan_t *out, int64_t N, int64_t L1, int64_t L2, sinc_quad quad,
@@ -699,40 +882,15 @@ nnfft_status sinc_plan(sinc_plan_t *out, int64_t N, int64_t L1, int64_t L2, sinc
     if (!a || !b) return fail(NNFFT_ERR_ARG, "null node array");
     try {
         hipStream_t s = static_cast<hipStream_t>(stream);
-        std::vector<double> z, w;
-        if (quad == SINC_QUAD_GAUSS_LEGENDRE) gauss_legendre_rule(n_quad, z, w);
-        else clenshaw_curtis_rule(n_quad, z, w);
-        const int64_t nn = (int64_t)z.size();
-        std::vector<double> xs(nn), vs(nn);
-        for (int64_t j = 0; j < nn; ++j) {
-            xs[j] = 0.5 * z[j];    // step 1: spatial nodes z_j / 2
-            vs[j] = -0.5 * z[j];   // step 3: frequencies -z_j / 2
-        }
         std::vector<double> ha, hb;
         nnfft_status st = copy_nodes(a, L1, ha, s);
         if (st != NNFFT_OK) return st;
         st = copy_nodes(b, L2, hb, s);
         if (st != NNFFT_OK) return st;
-        sinc_plan_s *sp = new sinc_plan_s();
-        sp->n_nodes = nn;
-        sp->prec = prec;
-        st = plan_impl(&sp->p1, N, L1, nn, sigma1, sigma2, m1, m2, prec, ha, xs, s);
-        if (st == NNFFT_OK) st = plan_impl(&sp->p2, N, nn, L2, sigma1, sigma2, m1, m2, prec, vs, hb, s);
-        if (st != NNFFT_OK) {
-            delete sp;
-            return st;
-        }
-        const size_t csz = (prec == NNFFT_FP32_COMP) ? 8 : 16;
-        hipError_t e = hipMalloc(&sp->w, (size_t)nn * sizeof(double));
-        if (e == hipSuccess) e = hipMalloc(&sp->g, (size_t)nn * csz);
-        if (e == hipSuccess) e = hipMemcpyAsync(sp->w, w.data(), (size_t)nn * sizeof(double), hipMemcpyHostToDevice, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e != hipSuccess) {
-            delete sp;
-            return fail(e == hipErrorOutOfMemory ? NNFFT_ERR_NOMEM : NNFFT_ERR_DEVICE, hipGetErrorString(e));
-        }
-        *out = sp;
-        return NNFFT_OK;
+        SincHostPlan S;
+        st = sinc_host(S, N, L1, L2, quad, n_quad, sigma1, sigma2, m1, m2, prec, ha, hb);
+        if (st != NNFFT_OK) return st;
+        return sinc_create(S, hip_mem(), s, out);
     } catch (const std::bad_alloc &) {
         return fail(NNFFT_ERR_NOMEM, "host allocation failed");
     }

@@ -1,0 +1,140 @@
+// Host-side plan construction shared by the plan, autotuning and serving
+// entry points (Algorithm 2.2 step 0 and the node preprocessing).  Not part
+// of the public C ABI.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/nnfft.h"
+#include "internal.h"
+
+namespace nnfft {
+
+// Records the message for nnfft_last_error (thread-local) and returns st.
+nnfft_status fail(nnfft_status st, const std::string &msg);
+
+// Layout knobs of one node side: what the autotuner chooses.
+struct Layout {
+    int64_t block = 0;   // points per node block (consecutive caller indices)
+    int Q = 0;           // max points per work item
+    int grid_max = 0;    // FP32: workgroups of a slot-looping launch (0: one per slot)
+};
+
+// The tuned layout for M nodes if the table has one, else the rule.
+Layout choose_layout(int64_t M, bool fp32);
+Layout rule_layout(int64_t M, bool fp32);
+void set_tuned_layout(bool fp32, int64_t M, const Layout &L);
+bool get_tuned_layout(bool fp32, int64_t M, Layout &L);
+void clear_tuned_layouts();
+// Clamps a requested layout to what the kernels implement.
+Layout sanitize_layout(Layout L, int64_t M, bool fp32);
+
+// Node layout of one side, built on the host.
+struct SideHost {
+    std::vector<int32_t> perm;          // FP64: caller's index of each sorted point
+    std::vector<PtRec> rec32;           // FP32: (index, offset) of each sorted point
+    std::vector<double> frac64;         // FP64: offset of each sorted point
+    std::vector<Item> items;
+    std::vector<Chunk> chunks;
+    std::vector<int32_t> chunk_block;
+    std::vector<int32_t> chunk_item0;   // first item of each chunk
+    std::vector<Chunk> launch;          // chunks in launch order, empty ones pad
+    std::vector<Item> launch_items;     // 64 items per launch slot, n = 0 pads
+    std::vector<PtRec> trec32;          // FP32: records in per-chunk transposed blocks
+    int64_t part_cells = 0;
+    int64_t nblocks = 0;
+};
+
+// FFT factorization chosen at plan time (copied into FftArgs).
+struct FftPlan {
+    int32_t N2 = 0, n1 = 0, n2 = 0, npassA = 0, npassB = 0;
+    int radA[kMaxPasses] = {}, radB[kMaxPasses] = {};
+    int32_t batchA = 0, batchB = 0, threadsA = 0, threadsB = 0, S = 0;
+};
+
+// Everything of one plan that is computed on the host, and the size of the
+// single device block it needs.
+struct HostPlan {
+    nnfft_info_t info{};
+    bool fp32 = false;
+    Layout lay1{}, lay2{};
+    SideHost sp, ip;
+    std::vector<float> C1, C2;         // FP32: window tap series of both sides
+    std::vector<double> corr;          // series of 1/phi_hat_1
+    std::vector<double> deconv;        // 1 / (N1 N2 phi_hat_2(l))
+    std::vector<double> tw64;          // FFT twiddles
+    std::vector<float> tw32;
+    std::vector<int32_t> moff, midx;   // merge lists of the spreading windows
+    FftPlan fd{};
+    size_t total_bytes = 0;            // device bytes of the plan (one block)
+};
+
+// Provider of the plan's device block.
+struct DevMem {
+    void *(*alloc)(void *ctx, size_t bytes);   // null on failure
+    void (*release)(void *ctx, void *p);
+    void *ctx;
+};
+const DevMem &hip_mem();                       // hipMalloc / hipFree
+
+}  // namespace nnfft
+
+// Public handles (opaque in nnfft.h).
+struct nnfft_plan_s {
+    nnfft_info_t info{};
+    nnfft::PlanDev desc{};
+    nnfft::PlanDev *ddesc = nullptr;   // device copy of desc (batched launches)
+    void *base = nullptr;              // the plan's device block
+    nnfft::DevMem mem{};
+    std::vector<hipEvent_t> prof_ev;   // 4 events per profiled exec
+    int prof_max = 0, prof_used = 0;
+
+    void drop_events();
+    ~nnfft_plan_s();
+};
+
+struct sinc_plan_s {
+    nnfft_plan_t p1 = nullptr, p2 = nullptr;
+    double *w = nullptr;      // [n_nodes] quadrature weights (FP64, device)
+    void *g = nullptr;        // [n_nodes] complex intermediate
+    void *wg_base = nullptr;  // device block of w and g
+    nnfft::DevMem mem{};
+    int64_t n_nodes = 0;
+    int32_t prec = 0;
+    ~sinc_plan_s();
+};
+
+namespace nnfft {
+
+// Validations, tables and node layouts of Algorithm 2.2 step 0 from host
+// copies of the nodes.  lay1 / lay2: null = choose_layout.
+nnfft_status plan_host(HostPlan &H, int64_t N, int64_t M1, int64_t M2, double sigma1, double sigma2,
+                       int m1, int m2, nnfft_precision prec, const std::vector<double> &v,
+                       const std::vector<double> &x, const Layout *lay1 = nullptr,
+                       const Layout *lay2 = nullptr);
+
+// Allocates H.total_bytes from mem, uploads (one copy, synchronizes s) and
+// returns the handle, which releases the block to mem when destroyed.
+nnfft_status plan_create(const HostPlan &H, const DevMem &mem, hipStream_t s, nnfft_plan_t *out);
+
+// Fast sinc transform (Algorithm 6.1) on the host: quadrature and both plans.
+struct SincHostPlan {
+    HostPlan h1, h2;
+    std::vector<double> w;
+    int64_t n_nodes = 0;
+    int32_t prec = 0;
+    size_t wg_bytes = 0;
+    size_t total_bytes = 0;   // both plans plus weights and intermediate
+};
+nnfft_status sinc_host(SincHostPlan &S, int64_t N, int64_t L1, int64_t L2, sinc_quad quad, int64_t n_quad,
+                       double sigma1, double sigma2, int m1, int m2, nnfft_precision prec,
+                       const std::vector<double> &a, const std::vector<double> &b);
+nnfft_status sinc_create(const SincHostPlan &S, const DevMem &mem, hipStream_t s, sinc_plan_t *out);
+
+// Device-to-host copy of n FP64 nodes (synchronizes s).
+nnfft_status copy_nodes(const double *d, int64_t n, std::vector<double> &h, hipStream_t s);
+
+}  // namespace nnfft

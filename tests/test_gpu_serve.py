@@ -1,0 +1,211 @@
+"""Layout autotuning and the serving layer (include/nnfft_serve.h) on the GPU.
+
+Served results are compared bitwise with the same plan run alone
+(nnfft_exec / sinc_exec): continuous batching may group a request with any
+others, on any stream, in arena memory, and must not change a bit of it."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2107_02671_amd as P
+from paper_2107_02671_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FP64, FP32 = P.NNFFT_FP64_PLAIN, P.NNFFT_FP32_COMP
+DEV = "cuda:0"
+GL = P.SINC_QUAD_GAUSS_LEGENDRE
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _req(g, i, max_log2_m=15, sinc_every=0):
+    N = int(np.rint(np.exp(g.uniform(np.log(64), np.log(2048)))))
+    M1 = int(np.rint(np.exp(g.uniform(np.log(2 ** 10), np.log(2 ** max_log2_m)))))
+    M2 = int(np.rint(np.exp(g.uniform(np.log(2 ** 10), np.log(2 ** max_log2_m)))))
+    prec, m = (FP32, 6) if i % 2 == 0 else (FP64, 12)
+    kind = P.NNFFT_REQ_SINC if sinc_every and i % sinc_every == sinc_every - 1 else P.NNFFT_REQ_NNFFT
+    if kind == P.NNFFT_REQ_SINC:
+        v, x = W.chebyshev_nodes(g, M1), W.chebyshev_nodes(g, M2)
+        f = g.standard_normal(M1) + 0j
+    else:
+        v, x, f = W.uniform_nodes(g, M1), W.uniform_nodes(g, M2), W.complex_gaussian(g, M1)
+    cdt = torch.complex64 if prec == FP32 else torch.complex128
+    return dict(N=N, prec=prec, m=m, kind=kind, n_quad=2 * N,
+                v=torch.tensor(v, device=DEV), x=torch.tensor(x, device=DEV),
+                f=torch.tensor(f, dtype=cdt, device=DEV), hv=v, hx=x, hf=f)
+
+
+def _alone(r):
+    if r["kind"] == P.NNFFT_REQ_SINC:
+        sp = P.SincPlan(r["N"], r["v"], r["x"], r["n_quad"], GL, 2.0, 2.0, r["m"], r["m"], r["prec"])
+        try:
+            return sp(r["f"]).clone()
+        finally:
+            torch.cuda.synchronize()
+            sp.close()
+    with P.Plan(r["N"], r["v"], r["x"], 2.0, 2.0, r["m"], r["m"], r["prec"]) as pl:
+        y = pl(r["f"]).clone()
+        torch.cuda.synchronize()
+    return y
+
+
+def _submit(srv, r, key=0, f=None):
+    y = torch.full((r["x"].numel(),), float("nan"), dtype=r["f"].dtype, device=DEV)
+    t = srv.submit(r["N"], r["v"], r["x"], r["f"] if f is None else f, y, sigma1=2.0, sigma2=2.0,
+                   m1=r["m"], m2=r["m"], prec=r["prec"], kind=r["kind"], quad=GL, n_quad=r["n_quad"],
+                   plan_key=key)
+    return t, y
+
+
+def test_autotune_installs_layout():
+    P.nnfft_clear_tuning()
+    M = 1 << 17
+    _say(f"[gpu] autotune N=4096 M={M} FP32")
+    best = P.nnfft_autotune(4096, M, 6, FP32, reps=3)
+    _say(f"    best {best}")
+    assert best["candidates"] >= 8 and best["exec_ms"] > 0
+    got = P.nnfft_get_tuning(FP32, M)
+    assert got["tuned"] == 1
+    assert (got["items_points"], got["block_points"], got["grid_max"]) == \
+        (best["items_points"], best["block_points"], best["grid_max"])
+    g = W.rng(21)
+    v, x, f = W.uniform_nodes(g, M), W.uniform_nodes(g, M), W.complex_gaussian(g, M)
+    with P.Plan(4096, torch.tensor(v, device=DEV), torch.tensor(x, device=DEV), 2.0, 2.0, 6, 6, FP32) as pl:
+        assert pl.info["items_points"] == best["items_points"]
+        y = pl(torch.tensor(f, dtype=torch.complex64, device=DEV))
+        torch.cuda.synchronize()
+    yo = oracle.nnfft(4096, v, f, x, 2.0, 2.0, 6, 6)
+    assert np.abs(y.cpu().numpy() - yo).max() / np.abs(yo).max() <= 1e-5
+    P.nnfft_clear_tuning()
+
+
+def test_server_mix_equals_alone():
+    g = W.rng(31)
+    reqs = [_req(g, i, sinc_every=6) for i in range(26)]
+    _say(f"[gpu] server: {len(reqs)} mixed requests ({sum(r['kind'] for r in reqs)} sinc)")
+    torch.cuda.synchronize()
+    with P.Server(hbm_budget_bytes=1 << 30, planner_threads=4, streams=2) as srv:
+        sub = [_submit(srv, r) for r in reqs]
+        res = [srv.wait(t) for t, _ in sub]
+        st = srv.stats()
+    _say(f"    stats {st}")
+    assert all(r["status"] == 0 for r in res), [r["message"] for r in res if r["status"]]
+    assert st["completed"] == len(reqs) and st["failed"] == 0 and st["arena_in_use"] == 0
+    assert max(r["group_size"] for r in res) >= 1
+    for i, (r, (_, y)) in enumerate(zip(reqs, sub)):
+        assert torch.equal(y, _alone(r)), f"request {i} differs from its plan run alone"
+        assert res[i]["submit_ms"] <= res[i]["admit_ms"] <= res[i]["launch_ms"] <= res[i]["done_ms"]
+    # parity with the oracle for one request of each kind and precision
+    seen = set()
+    for r, (_, y) in zip(reqs, sub):
+        k = (r["kind"], r["prec"])
+        if k in seen:
+            continue
+        seen.add(k)
+        if r["kind"] == P.NNFFT_REQ_SINC:
+            yo = oracle.sinc_fast(r["N"], r["hv"], r["hf"], r["hx"], r["n_quad"], oracle.QUAD_GAUSS_LEGENDRE,
+                                  2.0, 2.0, r["m"], r["m"])
+            tol = 1e-12 if r["prec"] == FP64 else 2e-5
+        else:
+            yo = oracle.nnfft(r["N"], r["hv"], r["hf"], r["hx"], 2.0, 2.0, r["m"], r["m"])
+            tol = 1e-12 if r["prec"] == FP64 else 1e-5
+        e = np.abs(y.cpu().numpy() - yo).max() / np.abs(yo).max()
+        _say(f"    kind {r['kind']} prec {r['prec']} N={r['N']}: E_inf vs oracle {e:.2e}")
+        assert e <= tol
+
+
+def test_server_admission_and_errors():
+    g = W.rng(41)
+    reqs = [_req(g, 2 * i, max_log2_m=16) for i in range(12)]    # FP32 requests
+
+    def nbytes(r):
+        with P.Plan(r["N"], r["v"], r["x"], 2.0, 2.0, 6, 6, FP32) as pl:
+            return (pl.info["device_bytes"] + 255) // 256 * 256
+
+    sizes = [nbytes(r) for r in reqs]
+    # room for the two largest plans together, not for the two largest plus a resident one
+    a, b = sorted(sizes)[-2:]
+    budget = a + b
+    keyed = reqs[int(np.argmax(sizes))]
+    _say(f"[gpu] server admission: budget {budget} bytes, plan sizes {min(sizes)}..{max(sizes)}")
+    torch.cuda.synchronize()
+    with P.Server(hbm_budget_bytes=budget, planner_threads=6, streams=2, max_batch=4) as srv:
+        # a resident plan fills part of the arena ...
+        t, yk = _submit(srv, keyed, key=9)
+        assert srv.wait(t)["status"] == 0
+        assert srv.stats()["resident_plans"] == 1
+        # ... and is evicted when the stream of other plans needs the space
+        sub = [_submit(srv, r) for r in reqs]
+        # a plan larger than the whole arena is refused, not queued forever
+        Mbig = 1 << 21
+        bv = torch.zeros(Mbig, dtype=torch.float64, device=DEV)
+        bf = torch.zeros(Mbig, dtype=torch.complex64, device=DEV)
+        by = torch.empty(Mbig, dtype=torch.complex64, device=DEV)
+        tb = srv.submit(4096, bv, bv, bf, by, prec=FP32)
+        # parameter errors come back in the result
+        bad = _req(W.rng(43), 0, max_log2_m=10)
+        te, _ = _submit(srv, dict(bad, m=3))
+        res = [srv.wait(t) for t, _ in sub]
+        rb, re_ = srv.wait(tb), srv.wait(te)
+        st = srv.stats()
+    _say(f"    stats {st}; refused: {rb['message']}")
+    assert all(r["status"] == 0 for r in res)
+    assert st["arena_peak"] <= budget
+    assert st["evictions"] >= 1
+    assert rb["status"] == P.binding.NNFFT_ERR_NOMEM
+    assert re_["status"] == P.binding.NNFFT_ERR_UNSUPPORTED
+    assert torch.equal(yk, _alone(keyed))
+    for r, (_, y) in zip(reqs, sub):
+        assert torch.equal(y, _alone(r))
+
+
+def test_server_resident_plans():
+    g = W.rng(51)
+    r = _req(g, 0, max_log2_m=14)
+    fs = [r["f"]] + [torch.tensor(W.complex_gaussian(g, r["v"].numel()), dtype=torch.complex64, device=DEV)
+                     for _ in range(3)]
+    _say("[gpu] server resident plan reuse")
+    torch.cuda.synchronize()
+    with P.Server(hbm_budget_bytes=256 << 20, planner_threads=2, streams=2) as srv:
+        sub = [_submit(srv, r, key=77, f=f) for f in fs]
+        res = [srv.wait(t) for t, _ in sub]
+        assert srv.stats()["resident_plans"] == 1
+        # same key with other parameters is an error
+        t, _ = _submit(srv, dict(r, m=8), key=77)
+        assert srv.wait(t)["status"] == P.binding.NNFFT_ERR_ARG
+        srv.evict(77)
+        assert srv.stats()["resident_plans"] == 0
+    assert [x["plan_reused"] for x in res] == [0, 1, 1, 1]
+    assert all(x["status"] == 0 for x in res)
+    with P.Plan(r["N"], r["v"], r["x"], 2.0, 2.0, 6, 6, FP32) as pl:
+        for f, (_, y) in zip(fs, sub):
+            assert torch.equal(y, pl(f))
+
+
+def test_server_groups_resident_requests():
+    # requests on resident plans need no planning: they reach the executor
+    # faster than single launches drain, so launch groups form
+    g = W.rng(61)
+    reqs = [_req(g, i, max_log2_m=13) for i in range(8)]
+    _say("[gpu] server launch groups over 8 resident plans")
+    torch.cuda.synchronize()
+    with P.Server(hbm_budget_bytes=256 << 20, planner_threads=4, streams=1, max_batch=32) as srv:
+        first = [_submit(srv, r, key=100 + i) for i, r in enumerate(reqs)]
+        for t, _ in first:
+            assert srv.wait(t)["status"] == 0
+        sub = [(i, _submit(srv, r, key=100 + i)) for rep in range(6) for i, r in enumerate(reqs)]
+        res = [srv.wait(t) for _, (t, _) in sub]
+        st = srv.stats()
+    sizes = [r["group_size"] for r in res]
+    _say(f"    group sizes: max {max(sizes)}, mean {np.mean(sizes):.2f}; stats {st}")
+    assert all(r["status"] == 0 and r["plan_reused"] == 1 for r in res)
+    alone = [_alone(r) for r in reqs]
+    for i, (_, y) in sub:
+        assert torch.equal(y, alone[i])

@@ -1,5 +1,5 @@
 """CPU checks of the HIP library: it loads, exports every entry point that
-include/nnfft.h declares, and its host-side logic (size derivation, error
+include/nnfft.h and include/nnfft_serve.h declare, and its host-side logic (size derivation, error
 codes, quadrature rules) agrees with the oracle.  No device work."""
 import ctypes
 
@@ -15,6 +15,7 @@ def test_library_loads_and_exports_header_symbols():
     L = binding.lib()
     names = binding.header_functions()
     assert len(names) >= 12
+    assert {"nnfft_exec_batch", "nnfft_autotune", "nnfft_server_create", "nnfft_server_submit"} <= set(names)
     for n in names:
         assert hasattr(L, n), n
         assert ctypes.cast(getattr(L, n), ctypes.c_void_p).value
@@ -71,3 +72,33 @@ def test_quadrature_rejects():
         P.nnfft_quadrature(P.SINC_QUAD_GAUSS_LEGENDRE, 0)
     with pytest.raises(P.NnfftError):
         P.nnfft_quadrature(7, 4)
+
+
+# ---------------------------------------------------------------------------
+# layout tuning table (host only)
+# ---------------------------------------------------------------------------
+def test_tuning_table_rule_set_clear():
+    L = binding.lib()
+    binding.nnfft_clear_tuning()
+    FP32, FP64 = binding.NNFFT_FP32_COMP, binding.NNFFT_FP64_PLAIN
+    r = binding.nnfft_get_tuning(FP32, 1 << 20)
+    # built-in rule: 16 points per item at 2^20 nodes, 2^17-point blocks, no grid cap
+    assert (r["items_points"], r["block_points"], r["grid_max"], r["tuned"]) == (16, 1 << 17, 0, 0)
+    r = binding.nnfft_get_tuning(FP64, 1 << 20)
+    assert (r["items_points"], r["block_points"], r["tuned"]) == (8, 1 << 16, 0)
+    # small sides keep one block; 8 blocks once every XCD can get 2^14 points
+    assert binding.nnfft_get_tuning(FP32, 1000)["block_points"] == 1000
+    assert binding.nnfft_get_tuning(FP32, 8 << 14)["block_points"] == 1 << 14
+    binding.nnfft_set_tuning(FP32, 1 << 20, 8, 1 << 16, 2048)
+    r = binding.nnfft_get_tuning(FP32, (1 << 19) + 1)     # same size class ceil(log2 M) = 20
+    assert (r["items_points"], r["grid_max"], r["tuned"]) == (8, 2048, 1)
+    assert binding.nnfft_get_tuning(FP32, 1 << 19)["tuned"] == 0
+    # FP64 kernels hold at most 8 points per item and never loop over slots
+    binding.nnfft_set_tuning(FP64, 1 << 20, 32, 1 << 16, 512)
+    r = binding.nnfft_get_tuning(FP64, 1 << 20)
+    assert (r["items_points"], r["grid_max"], r["tuned"]) == (8, 0, 1)
+    with pytest.raises(binding.NnfftError):
+        binding.nnfft_set_tuning(FP32, 1 << 20, 0, 1 << 16)
+    binding.nnfft_clear_tuning()
+    assert binding.nnfft_get_tuning(FP32, 1 << 20)["tuned"] == 0
+    assert L is binding.lib()
