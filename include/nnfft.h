@@ -130,6 +130,18 @@ nnfft_status nnfft_plan(nnfft_plan_t *out, int64_t N, int64_t M1, int64_t M2,
                         const double *v, const double *x, void *stream);
 
 /*
+ * Host-only dry run of nnfft_plan on HOST node arrays v[M1], x[M2]: the same
+ * validations, tables and node layout, then a check of the layout invariants
+ * the kernels rely on (every point in exactly one work item, record blocks,
+ * spreading windows inside the grid, no two windows writing one partial
+ * cell, merge lists).  No device work, no device memory.  *out receives the
+ * plan's info, device_bytes included (its exact device footprint).
+ * Errors: as nnfft_plan; ARG with an "internal:" message if an invariant fails.
+ */
+nnfft_status nnfft_plan_dry_run(int64_t N, int64_t M1, int64_t M2, double sigma1, double sigma2, int m1, int m2,
+                                nnfft_precision prec, const double *v, const double *x, nnfft_info_t *out);
+
+/*
  * Runs Algorithm 2.2 on `stream`: f[M1] -> y[M2] (c64 or c128 per the plan's
  * precision; y in the caller's node order).  f and y must not overlap.
  */
@@ -169,16 +181,14 @@ nnfft_status nnfft_destroy(nnfft_plan_t p);
  * Layout tuning.  A plan sorts each node side into blocks of consecutive
  * caller indices (one XCD's share of the gathers and scatters), bins of one
  * grid cell, work items of at most items_points points of one bin, and
- * one-wavefront workgroups of 64 items.  FP32 spreading and interpolation
- * launches may cap their grid at grid_max workgroups that loop over the
- * slots (0: one workgroup per slot; FP64 launches are always one per slot).
+ * workgroups of 64 items (one workgroup per launch slot).
  * These knobs change speed, and the summation order of the FP32 cell sums,
  * never the algorithm.  Plans take them from a process-wide table keyed by
  * precision and ceil(log2 M) of each side, else from a built-in rule.
  */
 typedef struct {
     int32_t items_points;           /* max points per work item (FP64: <= 8)         */
-    int32_t grid_max;               /* FP32 launch cap, 0 = one workgroup per slot   */
+    int32_t reserved;               /* 0                                             */
     int64_t block_points;           /* points per node block                         */
     double exec_ms;                 /* nnfft_autotune: measured exec time            */
     int32_t candidates;             /* nnfft_autotune: layouts timed                 */
@@ -189,7 +199,7 @@ typedef struct {
  * Autotuner: times nnfft_exec of an N, M1 = M2 = M, m1 = m2 = m, sigma = 2
  * plan on synthetic uniform nodes (a fixed seed) for a set of candidate
  * layouts (items_points {4, 8, 16, 32} (FP64 {2, 4, 8}) x block_points
- * {2^13 .. 2^17} x grid_max {0, 1024} (FP64 0), after the clamping rules,
+ * {2^13 .. 2^17}, after the clamping rules,
  * and the built-in rule's layout), `reps` timed execs each
  * after 2 untimed ones, on `stream`, and installs the fastest in the table
  * for M's size class and precision (it then applies to both sides of later
@@ -201,8 +211,8 @@ nnfft_status nnfft_autotune(int64_t N, int64_t M, int m, nnfft_precision prec, i
                             nnfft_tuning_t *best);
 
 /* Installs a layout for plans of precision prec whose side has M's size class
- * (ceil(log2 M)).  Errors: ARG for items_points < 1, block_points < 1,
- * grid_max < 0.  Out-of-range values are clamped when a plan uses them. */
+ * (ceil(log2 M)).  Errors: ARG for items_points < 1 or block_points < 1.
+ * Out-of-range values are clamped when a plan uses them. */
 nnfft_status nnfft_set_tuning(nnfft_precision prec, int64_t M, const nnfft_tuning_t *t);
 
 /* The layout a plan side of M nodes would use now (tuned = 1 if from the table). */

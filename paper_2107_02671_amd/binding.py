@@ -56,7 +56,7 @@ class NnfftInfo(ctypes.Structure):
 
 
 class NnfftTuning(ctypes.Structure):
-    _fields_ = [("items_points", ctypes.c_int32), ("grid_max", ctypes.c_int32),
+    _fields_ = [("items_points", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("block_points", ctypes.c_int64), ("exec_ms", ctypes.c_double),
                 ("candidates", ctypes.c_int32), ("tuned", ctypes.c_int32)]
 
@@ -126,6 +126,8 @@ def lib():
     L.nnfft_derive_params.argtypes = [i64, dbl, dbl, ci, ci, ctypes.POINTER(NnfftInfo)]
     L.nnfft_plan.argtypes = [ctypes.POINTER(vp), i64, i64, i64, dbl, dbl, ci, ci, ci, vp, vp, vp]
     L.nnfft_exec.argtypes = [vp, vp, vp, vp]
+    L.nnfft_plan_dry_run.argtypes = [i64, i64, i64, dbl, dbl, ci, ci, ci, ctypes.POINTER(dbl), ctypes.POINTER(dbl),
+                                     ctypes.POINTER(NnfftInfo)]
     L.nnfft_exec_batch.argtypes = [ci, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
     L.nnfft_info.argtypes = [vp, ctypes.POINTER(NnfftInfo)]
     L.nnfft_destroy.argtypes = [vp]
@@ -152,7 +154,7 @@ def lib():
     L.nnfft_server_destroy.argtypes = [vp]
     L.nnfft_last_error.restype = ctypes.c_char_p
     L.nnfft_version.restype = ctypes.c_char_p
-    for name in ["nnfft_profile_start", "nnfft_profile_stop", "nnfft_quadrature", "nnfft_derive_params",
+    for name in ["nnfft_plan_dry_run", "nnfft_profile_start", "nnfft_profile_stop", "nnfft_quadrature", "nnfft_derive_params",
                  "nnfft_plan", "nnfft_exec", "nnfft_exec_batch", "nnfft_info", "nnfft_destroy", "sinc_plan",
                  "sinc_exec", "sinc_info", "sinc_destroy", "nnfft_autotune", "nnfft_set_tuning",
                  "nnfft_get_tuning", "nnfft_clear_tuning", "nnfft_server_create", "nnfft_server_submit",
@@ -231,6 +233,18 @@ def nnfft_plan(N, v, x, sigma1=2.0, sigma2=2.0, m1=6, m2=6, prec=NNFFT_FP32_COMP
     _check(lib().nnfft_plan(ctypes.byref(h), int(N), v.numel(), x.numel(), float(sigma1), float(sigma2),
                             int(m1), int(m2), int(prec), _ptr(v), _ptr(x), _stream(stream)))
     return h
+
+
+def nnfft_plan_dry_run(N, v, x, sigma1=2.0, sigma2=2.0, m1=6, m2=6, prec=NNFFT_FP32_COMP) -> dict:
+    """Host-only plan construction and layout check on numpy float64 node arrays."""
+    import numpy as np
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    info = NnfftInfo()
+    dptr = ctypes.POINTER(ctypes.c_double)
+    _check(lib().nnfft_plan_dry_run(int(N), v.size, x.size, float(sigma1), float(sigma2), int(m1), int(m2),
+                                    int(prec), v.ctypes.data_as(dptr), x.ctypes.data_as(dptr), ctypes.byref(info)))
+    return info.as_dict()
 
 
 def nnfft_info(plan) -> dict:
@@ -377,8 +391,8 @@ def nnfft_autotune(N, M, m, prec, reps=10, stream=None) -> dict:
     return t.as_dict()
 
 
-def nnfft_set_tuning(prec, M, items_points, block_points, grid_max=0):
-    t = NnfftTuning(int(items_points), int(grid_max), int(block_points), 0.0, 0, 0)
+def nnfft_set_tuning(prec, M, items_points, block_points):
+    t = NnfftTuning(int(items_points), 0, int(block_points), 0.0, 0, 0)
     _check(lib().nnfft_set_tuning(int(prec), int(M), ctypes.byref(t)))
 
 

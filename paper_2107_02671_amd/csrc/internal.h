@@ -16,6 +16,7 @@ constexpr int kMaxCorrDeg = 48;     // largest degree of the 1/phi_hat_1 series
 constexpr int kCorr32 = 16;         // FP32 path: the series is zero-padded to this degree
 constexpr int kMaxPasses = 20;      // radix passes of one sub-transform
 constexpr int kItemsPerWg = 64;     // items (= threads) of a spreading / interpolation workgroup
+constexpr int kMaxPlanes = 16;      // colours of spreading windows with fixed offsets
 
 // One work item: up to Q consecutive sorted points of one cell bin.
 struct Item {
@@ -32,17 +33,15 @@ struct Chunk {
     int32_t nitem;
     int32_t bin_lo;
     int32_t nbin;
-    int32_t part_off;   // spreading side: first partial cell of this chunk
-    int32_t rec_off;    // FP32 path: first record of the chunk's transposed block
-    int32_t qmax;       // FP32 path: largest item size in the chunk
-    int32_t pad0, pad1;
+    int32_t part_off;   // spreading side: partial cell of the window's first cell
 };
 
 // FP32 point record: the caller's index and the fractional offset of the
-// node in its cell, read with one 8-byte load.  Records are stored per chunk
-// transposed: point q of item t of the chunk is at rec_off + 64 q + t, so a
-// wavefront's record load for one q is contiguous (slots q >= n of an item
-// are padding).
+// node in its cell, read with one 8-byte load.  Records are stored per launch
+// slot transposed, `rows` rows per slot: point q of item t of slot g is at
+// (g rows + q) 64 + t, so a wavefront's load of one row is contiguous and its
+// address does not depend on any other load (rows q >= n of an item repeat
+// its last record).
 struct alignas(8) PtRec {
     int32_t perm;
     float frac;
@@ -59,12 +58,13 @@ struct SpreadArgs {
     void *partial;            // chunk windows: float4 (hi, lo) or double2
     double beta, inv_den;     // FP64 path window: beta, 1 / (1 - exp(-2 beta))
     int32_t m, ngrid;
+    int32_t rows, pad;        // FP32 path: record rows per slot (max points per item)
 };
 
 // Steps 2-3 (merge, 1/phi_hat_2, FFT) arguments of one plan.
 struct FftArgs {
-    const void *partial;
-    const int32_t *merge_off; // [G1 + 1] CSR over grid cells of partial indices
+    const void *partial;      // nplanes planes of G1 cells, then overflow windows
+    const int32_t *merge_off; // [G1 + 1] CSR over grid cells of overflow partial indices
     const int32_t *merge_idx;
     const double *deconv;     // [G1] 1 / (N1 N2 phi_hat_2(l)), l = cell - G1/2
     const void *tw;           // [N2] exp(-2 pi i q / N2) (float2 or double2)
@@ -76,7 +76,7 @@ struct FftArgs {
     int32_t threadsA, threadsB;
     int32_t S;                // outputs with |s| <= S are consumed by step 4
     int32_t npassA, npassB;
-    int32_t pad;
+    int32_t nplanes;          // planes of spreading windows summed for every cell
     int8_t radA[kMaxPasses];  // radices of the length-n2 transform (or of N2)
     int8_t radB[kMaxPasses];  // radices of the length-n1 transform
 };
@@ -96,13 +96,12 @@ struct InterpArgs {
     int32_t m, ngrid;
     int32_t N2, ip_off;       // bin storage index = floor(u_j) + ip_off
     int32_t corr_deg;
-    int32_t pad;
+    int32_t rows;             // FP32 path: record rows per slot
 };
 
 struct PlanDev {
     int32_t prec;             // nnfft_precision
-    int32_t sp_grid_max;      // FP32 spreading / interpolation launches: at most this many
-    int32_t ip_grid_max;      // workgroups, each looping over launch slots (0: one per slot)
+    int32_t pad0, pad1;
     SpreadArgs sp;
     FftArgs fft;
     InterpArgs ip;

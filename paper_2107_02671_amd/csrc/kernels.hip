@@ -121,17 +121,31 @@ __device__ __forceinline__ double inv_phi1_fixed(const double *__restrict__ c, d
 // ===========================================================================
 // Spreading, FP32 path
 // ===========================================================================
+// FP32 spreading and interpolation run four wavefronts per 64-item chunk: each
+// wave takes a quarter of every item's points, so a CU holds four times as
+// many waves as chunks and hides the latency of the loads and of the
+// dependent FMA chains.
+constexpr int kWaves32 = 4;
+constexpr int kThreads32 = kWaves32 * kItemsPerWg;
+constexpr int kRowsPerWave = 8;   // record rows a wave loads in one batch
+
+// LDS arrays are indexed [moment or tap][item or bin] so that the lanes of a
+// wave (consecutive items or bins) touch consecutive 8-byte words: no bank
+// conflicts in any phase.
 template <int TM>   // TM >= 2 m
 struct Spread32Lds {
-    cx<float> mom[kItemsPerWg * (kDeg + 1)];   // Chebyshev moments of each item
-    cx<float> sbin[kItemsPerWg * TM];          // 2m taps of each bin
-    float C[TM * (kDeg + 1)];                  // tap coefficients, staged once per workgroup
+    union {
+        cx<float> mom[kWaves32][kDeg + 1][kItemsPerWg];   // each wave's share of the item moments (A, B1)
+        cx<float> sbin[TM][kItemsPerWg];                  // 2m taps of each bin (B2, C)
+    };
+    cx<float> bmom[kDeg + 1][kItemsPerWg];                // moments of each bin
+    float C[TM * (kDeg + 1)];                         // tap coefficients
     int ibin[kItemsPerWg];
     int runS[kItemsPerWg];
     int runE[kItemsPerWg];
 };
 
-// Copies the [2m][kDeg + 1] tap coefficients into LDS once per workgroup.
+// Copies the [2m][kDeg + 1] tap coefficients into LDS.
 __device__ __forceinline__ void stage_taps(float *dst, const float *__restrict__ src, int tm)
 {
     for (int i = threadIdx.x; i < tm * (kDeg + 1); i += blockDim.x) dst[i] = src[i];
@@ -157,126 +171,135 @@ __device__ __forceinline__ void add_moments(float *mr, float *mi, cx<float> fv, 
     }
 }
 
-constexpr int kPtBatch = 16;   // point records loaded per batch
-
-// One wavefront per chunk of up to 64 items.
-//  A: thread = item: Chebyshev moments of its points (coalesced record loads
-//     from the chunk's transposed block, then the coefficient gathers, then
-//     the arithmetic) into LDS;
-//  B: thread = bin: two-sum of the moments of the bin's items, then the bin's
-//     2m taps sum_k C[r][k] M_k;
-//  C: window cell w (grid cell bin_lo - m + 1 + w) = two-sum over r of tap r
-//     of bin w - r, stored as (hi.re, hi.im, lo.re, lo.im).
+// One chunk of up to 64 items (4 waves, lane t = item t):
+//  A: wave w accumulates the Chebyshev moments of its rows of each item
+//     (record loads and coefficient gathers first, then the arithmetic);
+//  B1: thread (w, bin) forms the bin moments M_k, k = w, w + 4, w + 8: the
+//     item moment is the plain sum of the four wave shares, items of a bin are
+//     added with two-sum;
+//  B2: thread (w, bin) forms taps r = w, w + 4, ...: sum_k C[r][k] M_k;
+//  C: window cell c (grid cell bin_lo - m + 1 + c) = two-sum over r of tap r
+//     of bin c - r, stored as (hi.re, hi.im, lo.re, lo.im).
 template <int TM>
 __device__ void spread32_slot(const SpreadArgs &A, const cx<float> *__restrict__ f, int g, Spread32Lds<TM> &L)
 {
     constexpr int D = kDeg;
-    const int t = threadIdx.x;
-    const Item it = A.items[g * kItemsPerWg + t];    // independent of the chunk load
+    const int t = threadIdx.x & (kItemsPerWg - 1), w = threadIdx.x / kItemsPerWg;
+    const int rows = A.rows, rpw = (rows + kWaves32 - 1) / kWaves32, row0 = w * rpw;
+    // this wave's record rows and their coefficient gathers are issued first:
+    // their addresses depend on no other load (rows past an item's end repeat
+    // its last record, empty items point at coefficient 0)
+    const PtRec *__restrict__ rec = A.rec32 + (size_t)g * rows * kItemsPerWg + t;
+    PtRec r[kRowsPerWave];
+    cx<float> fv[kRowsPerWave];
+#pragma unroll
+    for (int j = 0; j < kRowsPerWave; ++j) r[j] = rec[min(row0 + j, rows - 1) * kItemsPerWg];
+#pragma unroll
+    for (int j = 0; j < kRowsPerWave; ++j) fv[j] = f[r[j].perm];
+    const Item it = A.items[g * kItemsPerWg + t];
     const Chunk ch = A.chunks[g];
     if (ch.nitem == 0) return;
     const int m = A.m, tm = 2 * m;
-    if (t < ch.nbin) {
-        L.runS[t] = -1;
+    stage_taps(L.C, A.C, tm);   // read after the barriers below
+    if (w == 0 && t < ch.nbin) {   // empty run unless an item of the bin sets it
+        L.runS[t] = 0;
         L.runE[t] = 0;
     }
-    if (it.n > 0) {
+    {
         float mr[D + 1], mi[D + 1];
 #pragma unroll
         for (int k = 0; k <= D; ++k) mr[k] = mi[k] = 0.f;
-        const PtRec *__restrict__ rec = A.rec32 + ch.rec_off + t;
-        for (int q0 = 0; q0 < it.n; q0 += kPtBatch) {
-            // unconditional loads (slot index clamped into the item) so that
-            // all of them are in flight together
-            PtRec r[kPtBatch];
-            cx<float> fv[kPtBatch];
+        const int nq = min(rpw, it.n - row0);   // this wave's points of the item
+        for (int j0 = 0; j0 < nq; j0 += kRowsPerWave) {
+            if (j0 > 0) {
 #pragma unroll
-            for (int q = 0; q < kPtBatch; ++q) r[q] = rec[min(q0 + q, it.n - 1) * kItemsPerWg];
+                for (int j = 0; j < kRowsPerWave; ++j) r[j] = rec[min(row0 + j0 + j, rows - 1) * kItemsPerWg];
 #pragma unroll
-            for (int q = 0; q < kPtBatch; ++q) fv[q] = f[r[q].perm];
+                for (int j = 0; j < kRowsPerWave; ++j) fv[j] = f[r[j].perm];
+            }
 #pragma unroll
-            for (int q = 0; q < kPtBatch; ++q)
-                if (q0 + q < it.n) add_moments(mr, mi, fv[q], fmaf(2.f, r[q].frac, -1.f));
+            for (int j = 0; j < kRowsPerWave; ++j)
+                if (j0 + j < nq) add_moments(mr, mi, fv[j], fmaf(2.f, r[j].frac, -1.f));
         }
 #pragma unroll
-        for (int k = 0; k <= D; ++k) L.mom[t * (D + 1) + k] = cxmk(mr[k], mi[k]);
-        L.ibin[t] = it.bin - ch.bin_lo;
+        for (int k = 0; k <= D; ++k) L.mom[w][k][t] = cxmk(mr[k], mi[k]);
+        if (w == 0 && it.n > 0) L.ibin[t] = it.bin - ch.bin_lo;
     }
     __syncthreads();
-    if (t < ch.nitem) {
+    if (w == 0 && t < ch.nitem) {
         const int b = L.ibin[t];
         if (t == 0 || L.ibin[t - 1] != b) L.runS[b] = t;
         if (t == ch.nitem - 1 || L.ibin[t + 1] != b) L.runE[b] = t + 1;
     }
     __syncthreads();
     if (t < ch.nbin) {
-        const int s = L.runS[t], e = L.runE[t];
-        float hr[D + 1], hi[D + 1], lr[D + 1], li[D + 1];
+        const int s = L.runS[t], e = L.runE[t];   // s = e for a bin without items
+        for (int k = w; k <= D; k += kWaves32) {
+            float hr = 0.f, hi = 0.f, lr = 0.f, li = 0.f;
+            for (int i = s; i < e; ++i) {
+                cx<float> v = L.mom[0][k][i];
 #pragma unroll
-        for (int k = 0; k <= D; ++k) hr[k] = hi[k] = lr[k] = li[k] = 0.f;
-        for (int i = s; i < e; ++i) {   // s = -1, e = 0 for a bin without items
-#pragma unroll
-            for (int k = 0; k <= D; ++k) {
-                const cx<float> v = L.mom[i * (D + 1) + k];
-                comp_add(hr[k], lr[k], v.re);
-                comp_add(hi[k], li[k], v.im);
+                for (int ww = 1; ww < kWaves32; ++ww) {
+                    v.re += L.mom[ww][k][i].re;
+                    v.im += L.mom[ww][k][i].im;
+                }
+                comp_add(hr, lr, v.re);
+                comp_add(hi, li, v.im);
             }
+            L.bmom[k][t] = cxmk(hr + lr, hi + li);
         }
+    }
+    __syncthreads();
+    if (t < ch.nbin) {
+        float Mr[D + 1], Mi[D + 1];
 #pragma unroll
         for (int k = 0; k <= D; ++k) {
-            hr[k] += lr[k];
-            hi[k] += li[k];
+            const cx<float> v = L.bmom[k][t];
+            Mr[k] = v.re;
+            Mi[k] = v.im;
         }
-        cx<float> *out = L.sbin + t * TM;
+        for (int r0 = w; r0 < tm; r0 += kWaves32) {
+            const float *c = L.C + r0 * (D + 1);
+            float ar = 0.f, ai = 0.f;
 #pragma unroll
-        for (int r = 0; r < TM; ++r) {
-            if (r < tm) {
-                const float *c = L.C + r * (D + 1);
-                float ar = 0.f, ai = 0.f;
-#pragma unroll
-                for (int k = 0; k <= D; ++k) {
-                    ar = fmaf(c[k], hr[k], ar);
-                    ai = fmaf(c[k], hi[k], ai);
-                }
-                out[r] = cxmk(ar, ai);
+            for (int k = 0; k <= D; ++k) {
+                ar = fmaf(c[k], Mr[k], ar);
+                ai = fmaf(c[k], Mi[k], ai);
             }
+            L.sbin[r0][t] = cxmk(ar, ai);
         }
     }
     __syncthreads();
     const int W = ch.nbin + tm - 1;
     float4 *part = reinterpret_cast<float4 *>(A.partial) + ch.part_off;
-    for (int w = t; w < W; w += blockDim.x) {
+    for (int wc = threadIdx.x; wc < W; wc += blockDim.x) {
         cx<float> v[TM];
 #pragma unroll
-        for (int r = 0; r < TM; ++r) {
-            const int b = min(max(w - r, 0), ch.nbin - 1);
-            v[r] = L.sbin[b * TM + r];
+        for (int rr = 0; rr < TM; ++rr) {
+            const int b = min(max(wc - rr, 0), ch.nbin - 1);
+            v[rr] = L.sbin[rr][b];
         }
         float hr = 0.f, hi = 0.f, lr = 0.f, li = 0.f;
 #pragma unroll
-        for (int r = 0; r < TM; ++r) {
-            const int b = w - r;
-            if (r < tm && b >= 0 && b < ch.nbin) {
-                comp_add(hr, lr, v[r].re);
-                comp_add(hi, li, v[r].im);
+        for (int rr = 0; rr < TM; ++rr) {
+            const int b = wc - rr;
+            if (rr < tm && b >= 0 && b < ch.nbin) {
+                comp_add(hr, lr, v[rr].re);
+                comp_add(hi, li, v[rr].im);
             }
         }
-        part[w] = make_float4(hr, hi, lr, li);
+        part[wc] = make_float4(hr, hi, lr, li);
     }
 }
 
-// Launch slots g = blockIdx.x + j gridDim.x; gridDim.x is a multiple of 8 (or
-// the slot count), so every slot a workgroup takes maps to the same XCD.
+// One workgroup per launch slot (slot g runs on XCD g mod 8).  At least 6
+// waves per SIMD for short windows: then 1536 workgroups are resident at once.
 template <int TM>
-__global__ __launch_bounds__(64) void k_spread32(SpreadArgs A, const cx<float> *__restrict__ f)
+__global__ __launch_bounds__(kThreads32, TM <= 16 ? 6 : 4) void k_spread32(SpreadArgs A,
+                                                                        const cx<float> *__restrict__ f)
 {
     __shared__ Spread32Lds<TM> L;
-    stage_taps(L.C, A.C, 2 * A.m);
-    __syncthreads();
-    for (int g = blockIdx.x; g < A.ngrid; g += gridDim.x) {
-        spread32_slot<TM>(A, f, g, L);
-        __syncthreads();   // LDS reuse by the next slot
-    }
+    spread32_slot<TM>(A, f, blockIdx.x, L);
 }
 
 // ===========================================================================
@@ -322,7 +345,7 @@ __device__ void spread64_slot(const SpreadArgs &A, const cx<double> *__restrict_
                     ai = fma(fv[q].im, w, ai);
                 }
             }
-            L.sitem[t * tm + r] = cxmk(ar, ai);
+            L.sitem[r * kItemsPerWg + t] = cxmk(ar, ai);
         }
         L.ibin[t] = it.bin - ch.bin_lo;
     }
@@ -343,7 +366,7 @@ __device__ void spread64_slot(const SpreadArgs &A, const cx<double> *__restrict_
             if (s < 0) continue;
             const int e = L.runE[b];
             for (int i = s; i < e; ++i) {
-                const cx<double> v = L.sitem[i * tm + (w - b)];
+                const cx<double> v = L.sitem[(w - b) * kItemsPerWg + i];
                 ar += v.re;
                 ai += v.im;
             }
@@ -361,79 +384,104 @@ __global__ __launch_bounds__(64) void k_spread64(SpreadArgs A, const cx<double> 
 // ===========================================================================
 // Interpolation
 // ===========================================================================
-// One thread per item, no barrier: the item's bin coefficients
-// H_k = sum_r C[r][k] h_{c - m + 1 + r} (the transpose of the spreading taps),
-// then y_j = (sum_k H_k T_k(t_j)) / phi_hat_1(N* x_j) for each of its points.
-__device__ void interp32_item(const InterpArgs &A, cx<float> *__restrict__ y, const Item &it,
-                              const float *Cs, const PtRec *__restrict__ rec)
+// Four waves per chunk of 64 items (lane t = item t).  The item's bin
+// coefficients H_k = sum_r C[r][k] h_{c - m + 1 + r} (the transpose of the
+// spreading taps) are formed by wave w for k = w, w + 4, w + 8 and shared in
+// LDS; then wave w evaluates y_j = (sum_k H_k T_k(t_j)) / phi_hat_1(N* x_j)
+// for its rows of the item's points.
+struct Interp32Lds {
+    cx<float> H[kDeg + 1][kItemsPerWg];
+};
+
+template <int CD>
+__device__ __forceinline__ void interp32_slot(const InterpArgs &A, cx<float> *__restrict__ y, int g,
+                                              Interp32Lds &L)
 {
     constexpr int D = kDeg;
+    const int t = threadIdx.x & (kItemsPerWg - 1), w = threadIdx.x / kItemsPerWg;
+    const int rows = A.rows, rpw = (rows + kWaves32 - 1) / kWaves32, row0 = w * rpw;
+    // this wave's first record rows are in flight together with the item load
+    const PtRec *__restrict__ rec = A.rec32 + (size_t)g * rows * kItemsPerWg + t;
+    PtRec r[kRowsPerWave];
+#pragma unroll
+    for (int j = 0; j < kRowsPerWave; ++j) r[j] = rec[min(row0 + j, rows - 1) * kItemsPerWg];
+    const Item it = A.items[g * kItemsPerWg + t];
     const int m = A.m, tm = 2 * m;
     const int lab = it.bin - A.ip_off;
-    // the first batch of point records is in flight while H is formed
-    PtRec r[kPtBatch];
+    if (it.n > 0) {
+        const float *__restrict__ Cs = A.C;   // same address in every lane: scalar loads
+        const cx<float> *h = reinterpret_cast<const cx<float> *>(A.hlin) + (lab - m + 1 + A.N2 / 2);
+        constexpr int KW = (D + kWaves32) / kWaves32;   // moments per wave (3)
+        float ar[KW], ai[KW];
 #pragma unroll
-    for (int q = 0; q < kPtBatch; ++q) r[q] = rec[min(q, it.n - 1) * kItemsPerWg];
-    double c[kCorr32 + 1];
+        for (int j = 0; j < KW; ++j) ar[j] = ai[j] = 0.f;
+        for (int rr = 0; rr < tm; ++rr) {
+            const cx<float> hv = h[rr];
 #pragma unroll
-    for (int k = 0; k <= kCorr32; ++k) c[k] = A.corr[k];
-    const cx<float> *h = reinterpret_cast<const cx<float> *>(A.hlin) + (lab - m + 1 + A.N2 / 2);
-    float Hr[D + 1], Hi[D + 1];
+            for (int j = 0; j < KW; ++j) {
+                const int k = w + kWaves32 * j;
+                if (k <= D) {
+                    const float c = Cs[rr * (D + 1) + k];
+                    ar[j] = fmaf(c, hv.re, ar[j]);
+                    ai[j] = fmaf(c, hv.im, ai[j]);
+                }
+            }
+        }
 #pragma unroll
-    for (int k = 0; k <= D; ++k) Hr[k] = Hi[k] = 0.f;
-    for (int rr = 0; rr < tm; ++rr) {
-        const cx<float> hv = h[rr];
-        const float *cc = Cs + rr * (D + 1);
-#pragma unroll
-        for (int k = 0; k <= D; ++k) {
-            Hr[k] = fmaf(cc[k], hv.re, Hr[k]);
-            Hi[k] = fmaf(cc[k], hv.im, Hi[k]);
+        for (int j = 0; j < KW; ++j) {
+            const int k = w + kWaves32 * j;
+            if (k <= D) L.H[k][t] = cxmk(ar[j], ai[j]);
         }
     }
-    for (int q0 = 0; q0 < it.n; q0 += kPtBatch) {
-        if (q0 > 0) {
+    __syncthreads();
+    if (it.n > 0) {
+        float Hr[D + 1], Hi[D + 1];
 #pragma unroll
-            for (int q = 0; q < kPtBatch; ++q) r[q] = rec[min(q0 + q, it.n - 1) * kItemsPerWg];
+        for (int k = 0; k <= D; ++k) {
+            const cx<float> v = L.H[k][t];
+            Hr[k] = v.re;
+            Hi[k] = v.im;
         }
+        double c[CD + 1];
 #pragma unroll
-        for (int q = 0; q < kPtBatch; ++q) {
-            if (q0 + q < it.n) {
-                const float yv = fmaf(2.f, r[q].frac, -1.f);
-                const float y2 = yv + yv;
-                float T0 = 1.f, T1 = yv;
-                float sr = fmaf(Hr[1], yv, Hr[0]);
-                float si = fmaf(Hi[1], yv, Hi[0]);
+        for (int k = 0; k <= CD; ++k) c[k] = A.corr[k];
+        const int nq = min(rpw, it.n - row0);
+        for (int j0 = 0; j0 < nq; j0 += kRowsPerWave) {
+            if (j0 > 0) {
 #pragma unroll
-                for (int k = 2; k <= D; ++k) {
-                    const float T2 = fmaf(y2, T1, -T0);
-                    sr = fmaf(Hr[k], T2, sr);
-                    si = fmaf(Hi[k], T2, si);
-                    T0 = T1;
-                    T1 = T2;
+                for (int j = 0; j < kRowsPerWave; ++j) r[j] = rec[min(row0 + j0 + j, rows - 1) * kItemsPerWg];
+            }
+#pragma unroll
+            for (int j = 0; j < kRowsPerWave; ++j) {
+                if (j0 + j < nq) {
+                    const float yv = fmaf(2.f, r[j].frac, -1.f);
+                    const float y2 = yv + yv;
+                    float T0 = 1.f, T1 = yv;
+                    float sr = fmaf(Hr[1], yv, Hr[0]);
+                    float si = fmaf(Hi[1], yv, Hi[0]);
+#pragma unroll
+                    for (int k = 2; k <= D; ++k) {
+                        const float T2 = fmaf(y2, T1, -T0);
+                        sr = fmaf(Hr[k], T2, sr);
+                        si = fmaf(Hi[k], T2, si);
+                        T0 = T1;
+                        T1 = T2;
+                    }
+                    const double corr = inv_phi1_fixed<CD>(c, A.u_to_x, lab, (double)r[j].frac);
+                    y[r[j].perm] = cxmk((float)((double)sr * corr), (float)((double)si * corr));
                 }
-                const double corr = inv_phi1_fixed<kCorr32>(c, A.u_to_x, lab, (double)r[q].frac);
-                y[r[q].perm] = cxmk((float)((double)sr * corr), (float)((double)si * corr));
             }
         }
     }
 }
 
-__device__ __forceinline__ void interp32_slot(const InterpArgs &A, cx<float> *__restrict__ y, int g,
-                                              const float *Cs)
+// CD: degree of the 1/phi_hat_1 series as evaluated (the plan's series
+// zero-padded to CD; leading zero terms leave the result bit for bit unchanged)
+template <int CD>
+__global__ __launch_bounds__(kThreads32) void k_interp32(InterpArgs A, cx<float> *__restrict__ y)
 {
-    const Item it = A.items[g * kItemsPerWg + threadIdx.x];
-    if (it.n > 0) {
-        const int rec_off = A.chunks[g].rec_off;
-        interp32_item(A, y, it, Cs, A.rec32 + rec_off + threadIdx.x);
-    }
-}
-
-__global__ __launch_bounds__(64) void k_interp32(InterpArgs A, cx<float> *__restrict__ y)
-{
-    __shared__ float Cs[2 * kMaxM * (kDeg + 1)];
-    stage_taps(Cs, A.C, 2 * A.m);
-    __syncthreads();
-    for (int g = blockIdx.x; g < A.ngrid; g += gridDim.x) interp32_slot(A, y, g, Cs);
+    __shared__ Interp32Lds L;
+    interp32_slot<CD>(A, y, blockIdx.x, L);
 }
 
 struct Interp64Lds {
@@ -461,7 +509,7 @@ __device__ void interp64_slot(const InterpArgs &A, cx<double> *__restrict__ y, i
     if (t < ch.nbin && L.used[t]) {
         const int lab = ch.bin_lo + t - A.ip_off;
         const int s0 = lab - m + 1 + A.N2 / 2;
-        for (int r = 0; r < tm; ++r) L.hw[t * tm + r] = h[s0 + r];
+        for (int r = 0; r < tm; ++r) L.hw[r * kItemsPerWg + t] = h[s0 + r];
     }
     __syncthreads();
     if (it.n > 0) {
@@ -473,7 +521,7 @@ __device__ void interp64_slot(const InterpArgs &A, cx<double> *__restrict__ y, i
             double sr = 0.0, si = 0.0;
             for (int r = 0; r < tm; ++r) {
                 const double w = omega64((fr + (double)(m - 1 - r)) * inv_m, A.beta, A.inv_den);
-                const cx<double> hv = L.hw[b * tm + r];
+                const cx<double> hv = L.hw[r * kItemsPerWg + b];
                 sr = fma(hv.re, w, sr);
                 si = fma(hv.im, w, si);
             }
@@ -493,7 +541,17 @@ __global__ __launch_bounds__(64) void k_interp64(InterpArgs A, cx<double> *__res
 // ===========================================================================
 // FFT (steps 2-3)
 // ===========================================================================
-constexpr int kFftVals = 4096;   // complex values per FFT workgroup
+// complex values per FFT workgroup (sub-transform length x batch)
+template <typename T>
+struct FftCfg;
+template <>
+struct FftCfg<float> {
+    static constexpr int vals = 4096;
+};
+template <>
+struct FftCfg<double> {
+    static constexpr int vals = 2048;
+};
 
 // FFT input element q (index mod N2) = merged, deconvolved step-1 output:
 // label l = q (q < N2/2) or q - N2; zero outside I_{G1}.
@@ -505,7 +563,23 @@ __device__ __forceinline__ cx<float> fft_input32(const FftArgs &A, int q)
     const float4 *part = reinterpret_cast<const float4 *>(A.partial);
     float hr = 0.f, hi = 0.f, lr = 0.f, li = 0.f;
     const int e0 = A.merge_off[cell], e1 = A.merge_off[cell + 1];
-    // eight entries at a time: all index loads, then all partial loads
+    // the planes: fixed offsets s G1 + cell, eight loads in flight at a time
+    const int np = A.nplanes;
+    for (int s0 = 0; s0 < np; s0 += 8) {
+        float4 v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = part[(size_t)min(s0 + q, np - 1) * A.G1 + cell];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            if (s0 + q < np) {
+                comp_add(hr, lr, v[q].x);
+                comp_add(hi, li, v[q].y);
+                lr += v[q].z;
+                li += v[q].w;
+            }
+        }
+    }
+    // overflow windows through their index lists: eight entries at a time
     for (int e = e0; e < e1; e += 8) {
         int idx[8];
 #pragma unroll
@@ -535,6 +609,19 @@ __device__ __forceinline__ cx<double> fft_input64(const FftArgs &A, int q)
     const double2 *part = reinterpret_cast<const double2 *>(A.partial);
     double ar = 0.0, ai = 0.0;
     const int e1 = A.merge_off[cell + 1];
+    const int np = A.nplanes;
+    for (int s0 = 0; s0 < np; s0 += 8) {
+        double2 v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = part[(size_t)min(s0 + q, np - 1) * A.G1 + cell];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            if (s0 + q < np) {
+                ar += v[q].x;
+                ai += v[q].y;
+            }
+        }
+    }
     for (int e = A.merge_off[cell]; e < e1; ++e) {
         const double2 v = part[A.merge_idx[e]];
         ar += v.x;
@@ -635,7 +722,8 @@ struct Dft<T, 5> {
 };
 
 // One Stockham pass of radix R on B transforms of length Lsub held in LDS
-// (src[b * Lsub + j]) into dst.  Twiddle exp(-2 pi i e / Lsub) = tw[e * tstride].
+// (src[b * Lsub + j]) into dst.  Twiddle exp(-2 pi i e / Lsub) = tw[e * tstride]
+// (an LDS table of the sub-transform length, tstride = 1).
 template <typename T, int R>
 __device__ void stockham_pass(const cx<T> *src, cx<T> *dst, int Lsub, int B, int Ns,
                               const cx<T> *__restrict__ tw, int tstride)
@@ -702,7 +790,9 @@ __device__ __forceinline__ void fft_store(const FftArgs &A, int k, cx<T> v)
 
 template <typename T>
 struct FftLds {
-    cx<T> buf[2][kFftVals];
+    cx<T> buf[2][FftCfg<T>::vals];
+    cx<T> tw[FftCfg<T>::vals];    // exp(-2 pi i e / L) of the sub-transform length L
+    cx<T> otw[FftCfg<T>::vals];   // stage A: the four-step twiddles of this workgroup's columns
 };
 
 // Column block handled by local workgroup w of a launch of 8 ceil(ng / 8)
@@ -715,15 +805,19 @@ __device__ __forceinline__ int xcd_block(int w, int ng)
     return (w & 7) * per + (w >> 3);
 }
 
-// Whole transform in one workgroup (N2 <= kFftVals)
+// Whole transform in one workgroup (N2 <= 1024)
 template <typename T>
 __device__ void fft_single_body(const FftArgs &A, FftLds<T> &L)
 {
     const int N2 = A.N2;
-    for (int q = threadIdx.x; q < N2; q += blockDim.x) L.buf[0][q] = fft_input<T>(A, q);
+    const cx<T> *gtw = reinterpret_cast<const cx<T> *>(A.tw);
+    // data and twiddles in one round of loads; all passes then run from LDS
+    for (int q = threadIdx.x; q < N2; q += blockDim.x) {
+        L.tw[q] = gtw[q];
+        L.buf[0][q] = fft_input<T>(A, q);
+    }
     __syncthreads();
-    const cx<T> *tw = reinterpret_cast<const cx<T> *>(A.tw);
-    cx<T> *res = stockham<T>(L.buf[0], L.buf[1], N2, 1, A.radA, A.npassA, tw, 1);
+    cx<T> *res = stockham<T>(L.buf[0], L.buf[1], N2, 1, A.radA, A.npassA, L.tw, 1);
     for (int k = threadIdx.x; k < N2; k += blockDim.x) fft_store<T>(A, k, res[k]);
 }
 
@@ -745,18 +839,23 @@ __device__ void fft_stageA_body(const FftArgs &A, int w, FftLds<T> &L)
     if (blk >= ng) return;
     const int j1_0 = blk * B;
     const int nb = min(B, n1 - j1_0);
+    const cx<T> *gtw = reinterpret_cast<const cx<T> *>(A.tw);
+    // one round of loads: the merged input, the length-n2 twiddles and the
+    // four-step twiddles exp(-2 pi i j1 k2 / N2) of these columns
     for (int idx = threadIdx.x; idx < nb * n2; idx += blockDim.x) {
         const int j2 = idx / nb, bl = idx - j2 * nb;
+        const int k2 = idx - (idx / n2) * n2, bo = idx / n2;
+        if (idx < n2) L.tw[idx] = gtw[idx * n1];
+        L.otw[idx] = gtw[(j1_0 + bo) * k2];
         L.buf[0][bl * n2 + j2] = fft_input<T>(A, j1_0 + bl + n1 * j2);
     }
     __syncthreads();
-    const cx<T> *tw = reinterpret_cast<const cx<T> *>(A.tw);
-    cx<T> *res = stockham<T>(L.buf[0], L.buf[1], n2, nb, A.radA, A.npassA, tw, n1);
+    cx<T> *res = stockham<T>(L.buf[0], L.buf[1], n2, nb, A.radA, A.npassA, L.tw, 1);
     cx<T> *Y = reinterpret_cast<cx<T> *>(A.Y);
     for (int idx = threadIdx.x; idx < nb * n2; idx += blockDim.x) {
         const int bl = idx / n2, k2 = idx - bl * n2;
         const int j1 = j1_0 + bl;
-        Y[(size_t)j1 * n2 + k2] = cmul(res[bl * n2 + k2], tw[j1 * k2]);
+        Y[(size_t)j1 * n2 + k2] = cmul(res[idx], L.otw[idx]);
     }
 }
 
@@ -779,13 +878,14 @@ __device__ void fft_stageB_body(const FftArgs &A, int w, FftLds<T> &L)
     const int k2_0 = blk * B;
     const int nb = min(B, n2 - k2_0);
     const cx<T> *Y = reinterpret_cast<const cx<T> *>(A.Y);
+    const cx<T> *gtw = reinterpret_cast<const cx<T> *>(A.tw);
     for (int idx = threadIdx.x; idx < nb * n1; idx += blockDim.x) {
         const int j1 = idx / nb, bl = idx - j1 * nb;
+        if (idx < n1) L.tw[idx] = gtw[idx * n2];
         L.buf[0][bl * n1 + j1] = Y[(size_t)j1 * n2 + k2_0 + bl];
     }
     __syncthreads();
-    const cx<T> *tw = reinterpret_cast<const cx<T> *>(A.tw);
-    cx<T> *res = stockham<T>(L.buf[0], L.buf[1], n1, nb, A.radB, A.npassB, tw, n2);
+    cx<T> *res = stockham<T>(L.buf[0], L.buf[1], n1, nb, A.radB, A.npassB, L.tw, 1);
     for (int idx = threadIdx.x; idx < nb * n1; idx += blockDim.x) {
         const int bl = idx / n1, k1 = idx - bl * n1;
         fft_store<T>(A, k2_0 + bl + n2 * k1, res[bl * n1 + k1]);
@@ -812,15 +912,13 @@ __device__ __forceinline__ int batch_plan(const BatchTable &T, int g)
 }
 
 template <int TM>
-__global__ __launch_bounds__(64) void k_spread32_batch(BatchTable T)
+__global__ __launch_bounds__(kThreads32, TM <= 16 ? 6 : 4) void k_spread32_batch(BatchTable T)
 {
     __shared__ Spread32Lds<TM> L;
     const int p = batch_plan(T, blockIdx.x);
     const SpreadArgs A = T.desc[p]->sp;
     const int g = blockIdx.x - T.start[p];
     if (g >= A.ngrid) return;
-    stage_taps(L.C, A.C, 2 * A.m);
-    __syncthreads();
     spread32_slot<TM>(A, static_cast<const cx<float> *>(T.in[p]), g, L);
 }
 
@@ -834,16 +932,15 @@ __global__ __launch_bounds__(64) void k_spread64_batch(BatchTable T)
     spread64_slot(A, static_cast<const cx<double> *>(T.in[p]), g, L);
 }
 
-__global__ __launch_bounds__(64) void k_interp32_batch(BatchTable T)
+template <int CD>
+__global__ __launch_bounds__(kThreads32) void k_interp32_batch(BatchTable T)
 {
-    __shared__ float Cs[2 * kMaxM * (kDeg + 1)];
+    __shared__ Interp32Lds L;
     const int p = batch_plan(T, blockIdx.x);
     const InterpArgs A = T.desc[p]->ip;
     const int g = blockIdx.x - T.start[p];
     if (g >= A.ngrid) return;
-    stage_taps(Cs, A.C, 2 * A.m);
-    __syncthreads();
-    interp32_slot(A, static_cast<cx<float> *>(T.out[p]), g, Cs);
+    interp32_slot<CD>(A, static_cast<cx<float> *>(T.out[p]), g, L);
 }
 
 __global__ __launch_bounds__(64) void k_interp64_batch(BatchTable T)
@@ -901,28 +998,33 @@ static void launch_fft(const FftArgs &A, hipStream_t s)
     }
 }
 
-// grid of a slot-looping launch: all slots, or a multiple of 8 below the cap
-static int grid_of(int nslots, int cap)
+// evaluated degree of the 1/phi_hat_1 series: the smallest variant >= deg
+static int corr_variant(int deg)
 {
-    if (cap <= 0 || nslots <= cap) return nslots;
-    return std::max(8, cap / 8 * 8);
+    return deg <= 8 ? 8 : deg <= 10 ? 10 : deg <= 12 ? 12 : 16;
 }
+
 
 hipError_t launch_exec(const PlanDev &P, const void *f, void *y, hipStream_t s, hipEvent_t *ev)
 {
     if (ev) (void)hipEventRecord(ev[0], s);
     if (P.prec == NNFFT_FP32_COMP) {
         const cx<float> *fin = reinterpret_cast<const cx<float> *>(f);
-        const int gs = grid_of(P.sp.ngrid, P.sp_grid_max), gi = grid_of(P.ip.ngrid, P.ip_grid_max);
+        const int gs = P.sp.ngrid, gi = P.ip.ngrid;
         if (2 * P.sp.m <= 16)
-            hipLaunchKernelGGL((k_spread32<16>), dim3(gs), dim3(kItemsPerWg), 0, s, P.sp, fin);
+            hipLaunchKernelGGL((k_spread32<16>), dim3(gs), dim3(kThreads32), 0, s, P.sp, fin);
         else
-            hipLaunchKernelGGL((k_spread32<32>), dim3(gs), dim3(kItemsPerWg), 0, s, P.sp, fin);
+            hipLaunchKernelGGL((k_spread32<32>), dim3(gs), dim3(kThreads32), 0, s, P.sp, fin);
         if (ev) (void)hipEventRecord(ev[1], s);
         launch_fft<float>(P.fft, s);
         if (ev) (void)hipEventRecord(ev[2], s);
-        hipLaunchKernelGGL(k_interp32, dim3(gi), dim3(kItemsPerWg), 0, s, P.ip,
-                           reinterpret_cast<cx<float> *>(y));
+        cx<float> *yo = reinterpret_cast<cx<float> *>(y);
+        switch (corr_variant(P.ip.corr_deg)) {
+        case 8: hipLaunchKernelGGL((k_interp32<8>), dim3(gi), dim3(kThreads32), 0, s, P.ip, yo); break;
+        case 10: hipLaunchKernelGGL((k_interp32<10>), dim3(gi), dim3(kThreads32), 0, s, P.ip, yo); break;
+        case 12: hipLaunchKernelGGL((k_interp32<12>), dim3(gi), dim3(kThreads32), 0, s, P.ip, yo); break;
+        default: hipLaunchKernelGGL((k_interp32<16>), dim3(gi), dim3(kThreads32), 0, s, P.ip, yo); break;
+        }
     } else {
         hipLaunchKernelGGL(k_spread64, dim3(P.sp.ngrid), dim3(kItemsPerWg), 0, s, P.sp,
                            reinterpret_cast<const cx<double> *>(f));
@@ -945,6 +1047,7 @@ hipError_t launch_exec_batch(int n, const PlanDev *const *host, const PlanDev *c
         BatchTable Tsp{}, Tip{}, TA{}, TB{};
         int ssp = 0, sip = 0, sA = 0, sB = 0, thrA = 64, thrB = 64;
         bool long_window = false;
+        int corr_deg = 0;
         for (int i = 0; i < nb; ++i) {
             const PlanDev &P = *host[b0 + i];
             for (BatchTable *T : {&Tsp, &Tip, &TA, &TB}) {
@@ -968,6 +1071,7 @@ hipError_t launch_exec_batch(int n, const PlanDev *const *host, const PlanDev *c
                 thrB = std::max(thrB, P.fft.threadsB);
             }
             long_window = long_window || 2 * P.sp.m > 16;
+            corr_deg = std::max(corr_deg, P.ip.corr_deg);
         }
         Tsp.start[nb] = ssp;
         Tip.start[nb] = sip;
@@ -976,12 +1080,17 @@ hipError_t launch_exec_batch(int n, const PlanDev *const *host, const PlanDev *c
         Tsp.n = Tip.n = TA.n = TB.n = nb;
         if (host[b0]->prec == NNFFT_FP32_COMP) {
             if (long_window)
-                hipLaunchKernelGGL((k_spread32_batch<32>), dim3(ssp), dim3(kItemsPerWg), 0, s, Tsp);
+                hipLaunchKernelGGL((k_spread32_batch<32>), dim3(ssp), dim3(kThreads32), 0, s, Tsp);
             else
-                hipLaunchKernelGGL((k_spread32_batch<16>), dim3(ssp), dim3(kItemsPerWg), 0, s, Tsp);
+                hipLaunchKernelGGL((k_spread32_batch<16>), dim3(ssp), dim3(kThreads32), 0, s, Tsp);
             hipLaunchKernelGGL((k_fftA_batch<float>), dim3(sA), dim3(thrA), 0, s, TA);
             if (sB > 0) hipLaunchKernelGGL((k_fftB_batch<float>), dim3(sB), dim3(thrB), 0, s, TB);
-            hipLaunchKernelGGL(k_interp32_batch, dim3(sip), dim3(kItemsPerWg), 0, s, Tip);
+            switch (corr_variant(corr_deg)) {
+            case 8: hipLaunchKernelGGL((k_interp32_batch<8>), dim3(sip), dim3(kThreads32), 0, s, Tip); break;
+            case 10: hipLaunchKernelGGL((k_interp32_batch<10>), dim3(sip), dim3(kThreads32), 0, s, Tip); break;
+            case 12: hipLaunchKernelGGL((k_interp32_batch<12>), dim3(sip), dim3(kThreads32), 0, s, Tip); break;
+            default: hipLaunchKernelGGL((k_interp32_batch<16>), dim3(sip), dim3(kThreads32), 0, s, Tip); break;
+            }
         } else {
             hipLaunchKernelGGL(k_spread64_batch, dim3(ssp), dim3(kItemsPerWg), 0, s, Tsp);
             hipLaunchKernelGGL((k_fftA_batch<double>), dim3(sA), dim3(thrA), 0, s, TA);

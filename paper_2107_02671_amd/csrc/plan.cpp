@@ -87,15 +87,12 @@ Layout rule_layout(int64_t M, bool fp32)
     L.Q = Q;
     const int64_t bmax = fp32 ? (int64_t)1 << 17 : (int64_t)1 << 16;
     L.block = bmax;
-    L.grid_max = 0;
     return sanitize_layout(L, M, fp32);
 }
 
 Layout sanitize_layout(Layout L, int64_t M, bool fp32)
 {
     L.Q = std::max(1, std::min(L.Q, fp32 ? 64 : 8));   // the FP64 kernels hold 8 points per item
-    if (!fp32) L.grid_max = 0;                           // FP64 launches are one workgroup per slot
-    L.grid_max = std::max(0, L.grid_max);
     const int64_t bmin = (int64_t)1 << 14;
     int64_t block = std::max<int64_t>(1, L.block);
     int64_t nblk = (M + block - 1) / block;
@@ -206,13 +203,52 @@ bool build_side(const std::vector<double> &nodes, double scale, int64_t off, int
             c.nitem = (int32_t)(cj - ci);
             c.bin_lo = blo;
             c.nbin = S.items[cj - 1].bin - blo + 1;
-            c.part_off = (int32_t)part;
-            if (m > 0) part += c.nbin + 2 * m - 1;
             S.chunks.push_back(c);
             S.chunk_block.push_back((int32_t)blk);
             S.chunk_item0.push_back((int32_t)ci);
             ci = cj;
         }
+    }
+    // spreading windows: chunk c covers cells [bin_lo - m + 1, bin_lo + nbin + m).
+    // Windows are coloured greedily in order of their first cell (interval
+    // colouring: at most as many colours as windows overlap at one cell);
+    // colour s writes into plane s of G1 = nbins cells, so a cell's partial
+    // sums sit at fixed offsets s * G1 + cell.  Windows beyond kMaxPlanes
+    // colours go to an overflow area merged through index lists.
+    if (m > 0) {
+        std::vector<int32_t> ord(S.chunks.size());
+        for (size_t c = 0; c < ord.size(); ++c) ord[c] = (int32_t)c;
+        std::stable_sort(ord.begin(), ord.end(),
+                         [&](int32_t a, int32_t b) { return S.chunks[a].bin_lo < S.chunks[b].bin_lo; });
+        std::vector<int64_t> plane_end;   // first free cell of each colour
+        int64_t ovf = 0;
+        std::vector<int64_t> ovf_off(S.chunks.size(), -1);
+        for (int32_t c : ord) {
+            Chunk &ch = S.chunks[c];
+            // cells lo .. hi - 1: nbin + 2 m - 1 of them
+            const int64_t lo = (int64_t)ch.bin_lo - m + 1, hi = lo + ch.nbin + 2 * m - 1;
+            int colour = -1;
+            for (size_t k = 0; k < plane_end.size(); ++k)
+                if (plane_end[k] <= lo) {
+                    colour = (int)k;
+                    break;
+                }
+            if (colour < 0 && (int)plane_end.size() < kMaxPlanes) {
+                colour = (int)plane_end.size();
+                plane_end.push_back(0);
+            }
+            if (colour >= 0) {
+                plane_end[colour] = hi;
+                ch.part_off = (int32_t)(colour * nbins + lo);
+            } else {
+                ovf_off[c] = ovf;
+                ovf += hi - lo;
+            }
+        }
+        S.nplanes = (int32_t)plane_end.size();
+        for (size_t c = 0; c < S.chunks.size(); ++c)
+            if (ovf_off[c] >= 0) S.chunks[c].part_off = (int32_t)(S.nplanes * nbins + ovf_off[c]);
+        part = S.nplanes * nbins + ovf;
     }
     S.part_cells = part;
     // XCD-aware schedule: workgroup w runs on XCD w % 8 (round-robin dispatch),
@@ -232,37 +268,35 @@ bool build_side(const std::vector<double> &nodes, double scale, int64_t off, int
         order.resize(S.chunks.size());
         for (size_t c = 0; c < S.chunks.size(); ++c) order[c] = (int32_t)c;
     }
-    const Chunk empty{0, 0, 0, 0, 0, 0, 0, 0};
+    const Chunk empty{0, 0, 0, 0};
     const Item pad_item{0, 0, 0, 0};
     S.launch.assign(order.size(), empty);
     S.launch_items.assign(order.size() * kItemsPerWg, pad_item);
-    int64_t roff = 0;
+    // FP32 records: one transposed block of Q rows per launch slot, point q of
+    // item t of slot g at (g Q + q) 64 + t; rows past an item's end repeat its
+    // last record (same address, masked in the kernel), empty items point at 0
+    const int64_t rows = L.Q;
+    if (fp32) {
+        if ((int64_t)order.size() * rows * kItemsPerWg >= ((int64_t)1 << 31)) {
+            err = "too many padded records";
+            return false;
+        }
+        S.trec32.assign((size_t)(order.size() * rows * kItemsPerWg), PtRec{0, 0.f});
+    }
     for (size_t g = 0; g < order.size(); ++g) {
         if (order[g] < 0) continue;
-        Chunk c = S.chunks[order[g]];
+        const Chunk c = S.chunks[order[g]];
         const int32_t i0 = S.chunk_item0[order[g]];
-        int qmax = 0;
-        for (int i = 0; i < c.nitem; ++i) {
-            S.launch_items[g * kItemsPerWg + i] = S.items[i0 + i];
-            qmax = std::max(qmax, (int)S.items[i0 + i].n);
-        }
-        c.qmax = qmax;
-        c.rec_off = (int32_t)roff;
+        for (int i = 0; i < c.nitem; ++i) S.launch_items[g * kItemsPerWg + i] = S.items[i0 + i];
         if (fp32) {
-            // transposed block: point q of item t at rec_off + 64 q + t
-            S.trec32.resize((size_t)(roff + (int64_t)qmax * kItemsPerWg), PtRec{0, 0.f});
+            PtRec *blk = S.trec32.data() + (size_t)g * rows * kItemsPerWg;
             for (int i = 0; i < c.nitem; ++i) {
                 const Item &it = S.items[i0 + i];
-                for (int q = 0; q < it.n; ++q)
-                    S.trec32[(size_t)(roff + (int64_t)q * kItemsPerWg + i)] = S.rec32[(size_t)(it.p0 + q)];
+                for (int64_t q = 0; q < rows; ++q)
+                    blk[q * kItemsPerWg + i] = S.rec32[(size_t)(it.p0 + std::min<int64_t>(q, it.n - 1))];
             }
-            roff += (int64_t)qmax * kItemsPerWg;
         }
         S.launch[g] = c;
-    }
-    if (roff >= ((int64_t)1 << 31)) {
-        err = "too many padded records";
-        return false;
     }
     return true;
 }
@@ -327,8 +361,6 @@ void layout_plan(const HostPlan &H, Carver &C, PlanDev &D, size_t *upload_end, P
     const bool fp32 = H.fp32;
     D = PlanDev{};
     D.prec = P.precision;
-    D.sp_grid_max = H.lay1.grid_max;
-    D.ip_grid_max = H.lay2.grid_max;
     SpreadArgs &SA = D.sp;
     InterpArgs &IA = D.ip;
     FftArgs &FA = D.fft;
@@ -374,6 +406,9 @@ void layout_plan(const HostPlan &H, Carver &C, PlanDev &D, size_t *upload_end, P
     IA.hlin = FA.hlin;
     FA.N2 = (int32_t)P.N2;
     FA.G1 = (int32_t)P.G1;
+    FA.nplanes = H.sp.nplanes;
+    SA.rows = H.lay1.Q;
+    IA.rows = H.lay2.Q;
     FA.n1 = H.fd.n1;
     FA.n2 = H.fd.n2;
     FA.batchA = H.fd.batchA;
@@ -407,8 +442,8 @@ nnfft_status plan_host(HostPlan &H, int64_t N, int64_t M1, int64_t M2, double si
     if (fp32 && (m1 < 4 || m2 < 4))
         return fail(NNFFT_ERR_UNSUPPORTED, "the FP32 path needs m >= 4 (its window polynomials "
                                            "cannot reach FP32 accuracy for smaller m)");
-    if (P.N2 > ((int64_t)1 << 24) || P.G1 > ((int64_t)1 << 24))
-        return fail(NNFFT_ERR_UNSUPPORTED, "grid longer than 2^24");
+    if (P.N2 > ((int64_t)1 << 24) || P.G1 > ((int64_t)1 << 24) || (!fp32 && P.N2 > ((int64_t)1 << 22)))
+        return fail(NNFFT_ERR_UNSUPPORTED, "FFT longer than 2^24 (FP32) or 2^22 (FP64)");
     for (int64_t k = 0; k < M1; ++k)
         if (!(std::fabs(v[k]) <= 0.5)) return fail(NNFFT_ERR_DOMAIN, "frequency node outside [-1/2, 1/2]");
     for (int64_t j = 0; j < M2; ++j)
@@ -471,9 +506,12 @@ nnfft_status plan_host(HostPlan &H, int64_t N, int64_t M1, int64_t M2, double si
     std::vector<PtRec>().swap(H.sp.rec32);
     std::vector<PtRec>().swap(H.ip.rec32);
 
-    // merge lists: for each grid cell the partial cells of the chunks covering it
+    // merge lists of the overflow windows (those without a plane): for each
+    // grid cell the partial cells of the overflow chunks covering it
+    const int64_t plane_cells = (int64_t)H.sp.nplanes * P.G1;
     H.moff.assign(P.G1 + 1, 0);
     for (const Chunk &c : H.sp.chunks) {
+        if (c.part_off < plane_cells) continue;
         const int W = c.nbin + 2 * m1 - 1;
         for (int w = 0; w < W; ++w) {
             const int64_t cell = (int64_t)c.bin_lo - m1 + 1 + w;
@@ -486,6 +524,7 @@ nnfft_status plan_host(HostPlan &H, int64_t N, int64_t M1, int64_t M2, double si
     {
         std::vector<int32_t> cur(H.moff.begin(), H.moff.end() - 1);
         for (const Chunk &c : H.sp.chunks) {
+            if (c.part_off < plane_cells) continue;
             const int W = c.nbin + 2 * m1 - 1;
             for (int w = 0; w < W; ++w) {
                 const int64_t cell = (int64_t)c.bin_lo - m1 + 1 + w;
@@ -502,7 +541,7 @@ nnfft_status plan_host(HostPlan &H, int64_t N, int64_t M1, int64_t M2, double si
     // many workgroups (one or two columns each) so that the partial merge in
     // the first stage's load runs with enough workgroups in flight
     const int64_t single_max = 1024;
-    const int kvals = 4096;
+    const int kvals = fp32 ? 4096 : 2048;   // values per FFT workgroup (LDS)
     auto threads_for = [](int64_t vals) {
         int64_t t = (vals + 63) / 64 * 64;
         return (int32_t)std::max<int64_t>(64, std::min<int64_t>(256, t));
@@ -555,6 +594,79 @@ nnfft_status plan_host(HostPlan &H, int64_t N, int64_t M1, int64_t M2, double si
     return NNFFT_OK;
 }
 
+// Checks the invariants the kernels rely on: every point in exactly one
+// item of at most Q points of one bin, chunks within 64 bins, FP32 record
+// blocks matching the items, spreading windows inside the grid with no two
+// windows of one plane sharing a cell, overflow windows disjoint and listed
+// in the merge lists exactly once per cell.
+nnfft_status check_plan(const HostPlan &H, const std::vector<double> &v, const std::vector<double> &x)
+{
+    const nnfft_info_t &P = H.info;
+    auto side = [&](const SideHost &S, const Layout &L, int64_t M, int64_t nbins, int m, const char *name) {
+        std::vector<char> seen(M, 0);
+        const size_t rows = (size_t)L.Q;
+        for (size_t g = 0; g < S.launch.size(); ++g) {
+            const Chunk &c = S.launch[g];
+            if (c.nitem < 0 || c.nitem > kItemsPerWg || c.nbin < 0 || c.nbin > kItemsPerWg)
+                return std::string(name) + ": chunk size";
+            for (int t = 0; t < kItemsPerWg; ++t) {
+                const Item &it = S.launch_items[g * kItemsPerWg + t];
+                if (t >= c.nitem) {
+                    if (it.n != 0) return std::string(name) + ": padding item with points";
+                    continue;
+                }
+                if (it.n < 1 || it.n > L.Q) return std::string(name) + ": item size";
+                if (it.bin < c.bin_lo || it.bin >= c.bin_lo + c.nbin || it.bin >= nbins)
+                    return std::string(name) + ": item bin outside its chunk";
+                for (int q = 0; q < it.n; ++q) {
+                    const int64_t k = H.fp32 ? S.trec32[(g * rows + q) * kItemsPerWg + t].perm
+                                             : S.perm[(size_t)(it.p0 + q)];
+                    if (k < 0 || k >= M || seen[k]) return std::string(name) + ": point listed twice or lost";
+                    seen[k] = 1;
+                }
+                if (H.fp32)
+                    for (size_t q = it.n; q < rows; ++q)
+                        if (S.trec32[(g * rows + q) * kItemsPerWg + t].perm !=
+                            S.trec32[(g * rows + it.n - 1) * kItemsPerWg + t].perm)
+                            return std::string(name) + ": record padding";
+            }
+        }
+        for (int64_t k = 0; k < M; ++k)
+            if (!seen[k]) return std::string(name) + ": point not in any item";
+        (void)m;
+        return std::string();
+    };
+    std::string e = side(H.sp, H.lay1, P.M1, P.G1, P.m1, "spreading");
+    if (e.empty()) e = side(H.ip, H.lay2, P.M2, P.N2 + 1, P.m2, "interpolation");
+    if (!e.empty()) return fail(NNFFT_ERR_ARG, "internal: " + e);
+    (void)v;
+    (void)x;
+    // spreading windows
+    const int64_t G1 = P.G1, W0 = 2 * (int64_t)P.m1 - 1;
+    const int64_t plane_cells = (int64_t)H.sp.nplanes * G1;
+    std::vector<int32_t> owner((size_t)H.sp.part_cells, -1), ovf_count(G1, 0);
+    for (size_t c = 0; c < H.sp.chunks.size(); ++c) {
+        const Chunk &ch = H.sp.chunks[c];
+        const int64_t lo = (int64_t)ch.bin_lo - P.m1 + 1, W = ch.nbin + W0;
+        if (lo < 0 || lo + W > G1) return fail(NNFFT_ERR_ARG, "internal: window outside the grid");
+        const int64_t off = ch.part_off;
+        if (off < plane_cells && (off % G1 != lo)) return fail(NNFFT_ERR_ARG, "internal: window not at its cells");
+        if (off + W > H.sp.part_cells) return fail(NNFFT_ERR_ARG, "internal: window outside the partial buffer");
+        for (int64_t w = 0; w < W; ++w) {
+            if (owner[off + w] >= 0) return fail(NNFFT_ERR_ARG, "internal: two windows share a partial cell");
+            owner[off + w] = (int32_t)c;
+            if (off >= plane_cells) ovf_count[lo + w]++;
+        }
+    }
+    for (int64_t cell = 0; cell < G1; ++cell)
+        if (H.moff[cell + 1] - H.moff[cell] != ovf_count[cell])
+            return fail(NNFFT_ERR_ARG, "internal: merge list does not match the overflow windows");
+    for (int32_t e2 : H.midx)
+        if (e2 < plane_cells || e2 >= H.sp.part_cells || owner[e2] < 0)
+            return fail(NNFFT_ERR_ARG, "internal: merge list entry outside the overflow windows");
+    return NNFFT_OK;
+}
+
 nnfft_status plan_create(const HostPlan &H, const DevMem &mem, hipStream_t s, nnfft_plan_t *out)
 {
     *out = nullptr;
@@ -577,6 +689,8 @@ nnfft_status plan_create(const HostPlan &H, const DevMem &mem, hipStream_t s, nn
         hip_check(hipMemcpyAsync(base, stage.data(), upload_end, hipMemcpyHostToDevice, s), "hipMemcpyAsync");
         hip_check(hipMemcpyAsync(pl->ddesc, &pl->desc, sizeof(PlanDev), hipMemcpyHostToDevice, s),
                   "hipMemcpyAsync");
+        // plane cells that no window covers are read as zeros by every exec
+        hip_check(hipMemsetAsync(pl->desc.sp.partial, 0, (size_t)H.sp.part_cells * 16, s), "hipMemsetAsync");
         hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
     } catch (const HipError &e) {
         delete pl;
@@ -723,6 +837,26 @@ nnfft_status nnfft_plan(nnfft_plan_t *out, int64_t N, int64_t M1, int64_t M2, do
     }
 }
 
+nnfft_status nnfft_plan_dry_run(int64_t N, int64_t M1, int64_t M2, double sigma1, double sigma2, int m1, int m2,
+                                nnfft_precision prec, const double *v, const double *x, nnfft_info_t *out)
+{
+    if (!v || !x || !out) return fail(NNFFT_ERR_ARG, "null argument");
+    if (M1 < 1 || M2 < 1 || M1 > ((int64_t)1 << 30) || M2 > ((int64_t)1 << 30))
+        return fail(NNFFT_ERR_ARG, "node counts must be in [1, 2^30]");
+    try {
+        std::vector<double> hv(v, v + M1), hx(x, x + M2);
+        HostPlan H;
+        nnfft_status st = plan_host(H, N, M1, M2, sigma1, sigma2, m1, m2, prec, hv, hx);
+        if (st != NNFFT_OK) return st;
+        st = check_plan(H, hv, hx);
+        if (st != NNFFT_OK) return st;
+        *out = H.info;
+        return NNFFT_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(NNFFT_ERR_NOMEM, "host allocation failed");
+    }
+}
+
 nnfft_status nnfft_exec(nnfft_plan_t p, const void *f, void *y, void *stream)
 {
     if (!p || !f || !y) return fail(NNFFT_ERR_ARG, "null argument");
@@ -833,12 +967,11 @@ nnfft_status nnfft_destroy(nnfft_plan_t p)
 nnfft_status nnfft_set_tuning(nnfft_precision prec, int64_t M, const nnfft_tuning_t *t)
 {
     if (!t || M < 1 || (prec != NNFFT_FP64_PLAIN && prec != NNFFT_FP32_COMP) || t->items_points < 1 ||
-        t->block_points < 1 || t->grid_max < 0)
+        t->block_points < 1)
         return fail(NNFFT_ERR_ARG, "bad tuning");
     Layout L;
     L.Q = t->items_points;
     L.block = t->block_points;
-    L.grid_max = t->grid_max;
     set_tuned_layout(prec == NNFFT_FP32_COMP, M, L);
     return NNFFT_OK;
 }
@@ -853,7 +986,6 @@ nnfft_status nnfft_get_tuning(nnfft_precision prec, int64_t M, nnfft_tuning_t *o
     L = choose_layout(M, fp32);
     *out = nnfft_tuning_t{};
     out->items_points = L.Q;
-    out->grid_max = L.grid_max;
     out->block_points = L.block;
     out->tuned = tuned ? 1 : 0;
     return NNFFT_OK;

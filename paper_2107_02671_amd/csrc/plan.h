@@ -20,7 +20,6 @@ nnfft_status fail(nnfft_status st, const std::string &msg);
 struct Layout {
     int64_t block = 0;   // points per node block (consecutive caller indices)
     int Q = 0;           // max points per work item
-    int grid_max = 0;    // FP32: workgroups of a slot-looping launch (0: one per slot)
 };
 
 // The tuned layout for M nodes if the table has one, else the rule.
@@ -43,8 +42,9 @@ struct SideHost {
     std::vector<int32_t> chunk_item0;   // first item of each chunk
     std::vector<Chunk> launch;          // chunks in launch order, empty ones pad
     std::vector<Item> launch_items;     // 64 items per launch slot, n = 0 pads
-    std::vector<PtRec> trec32;          // FP32: records in per-chunk transposed blocks
-    int64_t part_cells = 0;
+    std::vector<PtRec> trec32;          // FP32: records in per-slot transposed blocks
+    int64_t part_cells = 0;             // spreading side: plane cells + overflow cells
+    int32_t nplanes = 0;                // spreading side: colours of the windows
     int64_t nblocks = 0;
 };
 
@@ -133,6 +133,9 @@ nnfft_status sinc_host(SincHostPlan &S, int64_t N, int64_t L1, int64_t L2, sinc_
                        double sigma1, double sigma2, int m1, int m2, nnfft_precision prec,
                        const std::vector<double> &a, const std::vector<double> &b);
 nnfft_status sinc_create(const SincHostPlan &S, const DevMem &mem, hipStream_t s, sinc_plan_t *out);
+
+// Verifies the layout invariants the kernels rely on (no device work).
+nnfft_status check_plan(const HostPlan &H, const std::vector<double> &v, const std::vector<double> &x);
 
 // Device-to-host copy of n FP64 nodes (synchronizes s).
 nnfft_status copy_nodes(const double *d, int64_t n, std::vector<double> &h, hipStream_t s);

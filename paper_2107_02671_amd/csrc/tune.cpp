@@ -69,18 +69,15 @@ extern "C" nnfft_status nnfft_autotune(int64_t N, int64_t M, int m, nnfft_precis
         const std::vector<int> Qs = fp32 ? std::vector<int>{4, 8, 16, 32} : std::vector<int>{2, 4, 8};
         const std::vector<int64_t> blocks = {(int64_t)1 << 13, (int64_t)1 << 14, (int64_t)1 << 15,
                                              (int64_t)1 << 16, (int64_t)1 << 17};
-        const std::vector<int> grids = fp32 ? std::vector<int>{0, 1024} : std::vector<int>{0};
         for (int Q : Qs)
             for (int64_t b : blocks)
-                for (int g : grids) {
+                {
                     Layout L;
                     L.Q = Q;
                     L.block = b;
-                    L.grid_max = g;
                     L = sanitize_layout(L, M, fp32);
                     bool dup = false;
-                    for (const Layout &c : cand)
-                        dup = dup || (c.Q == L.Q && c.block == L.block && c.grid_max == L.grid_max);
+                    for (const Layout &c : cand) dup = dup || (c.Q == L.Q && c.block == L.block);
                     if (!dup) cand.push_back(L);
                 }
 
@@ -118,7 +115,6 @@ extern "C" nnfft_status nnfft_autotune(int64_t N, int64_t M, int m, nnfft_precis
         set_tuned_layout(fp32, M, best_L);
         *best = nnfft_tuning_t{};
         best->items_points = best_L.Q;
-        best->grid_max = best_L.grid_max;
         best->block_points = best_L.block;
         best->exec_ms = best_ms;
         best->candidates = timed;

@@ -83,22 +83,69 @@ def test_tuning_table_rule_set_clear():
     FP32, FP64 = binding.NNFFT_FP32_COMP, binding.NNFFT_FP64_PLAIN
     r = binding.nnfft_get_tuning(FP32, 1 << 20)
     # built-in rule: 16 points per item at 2^20 nodes, 2^17-point blocks, no grid cap
-    assert (r["items_points"], r["block_points"], r["grid_max"], r["tuned"]) == (16, 1 << 17, 0, 0)
+    assert (r["items_points"], r["block_points"], r["tuned"]) == (16, 1 << 17, 0)
     r = binding.nnfft_get_tuning(FP64, 1 << 20)
     assert (r["items_points"], r["block_points"], r["tuned"]) == (8, 1 << 16, 0)
     # small sides keep one block; 8 blocks once every XCD can get 2^14 points
     assert binding.nnfft_get_tuning(FP32, 1000)["block_points"] == 1000
     assert binding.nnfft_get_tuning(FP32, 8 << 14)["block_points"] == 1 << 14
-    binding.nnfft_set_tuning(FP32, 1 << 20, 8, 1 << 16, 2048)
+    binding.nnfft_set_tuning(FP32, 1 << 20, 8, 1 << 16)
+    r = binding.nnfft_get_tuning(FP32, 1 << 20)
+    assert (r["items_points"], r["block_points"], r["tuned"]) == (8, 1 << 16, 1)
     r = binding.nnfft_get_tuning(FP32, (1 << 19) + 1)     # same size class ceil(log2 M) = 20
-    assert (r["items_points"], r["grid_max"], r["tuned"]) == (8, 2048, 1)
+    assert (r["items_points"], r["tuned"]) == (8, 1)
     assert binding.nnfft_get_tuning(FP32, 1 << 19)["tuned"] == 0
-    # FP64 kernels hold at most 8 points per item and never loop over slots
-    binding.nnfft_set_tuning(FP64, 1 << 20, 32, 1 << 16, 512)
+    # FP64 kernels hold at most 8 points per item
+    binding.nnfft_set_tuning(FP64, 1 << 20, 32, 1 << 16)
     r = binding.nnfft_get_tuning(FP64, 1 << 20)
-    assert (r["items_points"], r["grid_max"], r["tuned"]) == (8, 0, 1)
+    assert (r["items_points"], r["tuned"]) == (8, 1)
     with pytest.raises(binding.NnfftError):
         binding.nnfft_set_tuning(FP32, 1 << 20, 0, 1 << 16)
     binding.nnfft_clear_tuning()
     assert binding.nnfft_get_tuning(FP32, 1 << 20)["tuned"] == 0
     assert L is binding.lib()
+
+
+# ---------------------------------------------------------------------------
+# host-side plan construction: layout invariants (no device work)
+# ---------------------------------------------------------------------------
+DRY_CASES = [
+    # N, M1, M2, sigma, m, prec, nodes
+    (119, 11545, 18958, 2.0, 6, P.NNFFT_FP32_COMP, "uniform"),     # 2-point items, deep window overlap
+    (179, 107085, 1217, 2.0, 12, P.NNFFT_FP64_PLAIN, "uniform"),
+    (4096, 1 << 20, 1 << 20, 2.0, 6, P.NNFFT_FP32_COMP, "uniform"),
+    (4096, 1 << 18, 1 << 18, 2.0, 6, P.NNFFT_FP64_PLAIN, "uniform"),
+    (2048, 1 << 16, 1 << 16, 2.0, 8, P.NNFFT_FP32_COMP, "clustered"),
+    (1024, 30000, 30000, 2.0, 6, P.NNFFT_FP64_PLAIN, "chebyshev"),
+    (1200, 2400, 1600, 1.25, 6, P.NNFFT_FP32_COMP, "uniform"),
+    (64, 1, 1, 2.0, 4, P.NNFFT_FP32_COMP, "uniform"),
+    (64, 5000, 3, 2.0, 16, P.NNFFT_FP64_PLAIN, "edge"),
+]
+
+
+@pytest.mark.parametrize("case", DRY_CASES, ids=lambda c: f"N{c[0]}-M{c[1]}x{c[2]}-m{c[4]}-p{c[5]}-{c[6]}")
+def test_plan_dry_run_layout_invariants(case):
+    from paper_2107_02671_amd import workloads as W
+    N, M1, M2, sig, m, prec, kind = case
+    g = W.rng(M1 + M2)
+    if kind == "edge":    # every node on the boundary or at 0: all points in three bins
+        v = g.choice([-0.5, 0.0, 0.5], M1)
+        x = g.choice([-0.5, 0.0, 0.5], M2)
+    else:
+        gen = {"uniform": W.uniform_nodes, "chebyshev": W.chebyshev_nodes, "clustered": W.clustered_nodes}[kind]
+        v, x = gen(g, M1), gen(g, M2)
+    info = binding.nnfft_plan_dry_run(N, v, x, sig, sig, m, m, prec)
+    o = oracle.params(N, sig, sig, m, m)
+    assert (info["N1"], info["G1"], info["N2"]) == (o.N1, o.G1, o.N2)
+    assert info["M1"] == M1 and info["M2"] == M2
+    assert info["device_bytes"] > 8 * (M1 + M2)    # at least one 8-byte record per point
+    assert info["spread_workgroups"] >= (M1 + 64 * info["items_points"] - 1) // (64 * info["items_points"])
+
+
+def test_plan_dry_run_errors():
+    with pytest.raises(binding.NnfftError) as e:
+        binding.nnfft_plan_dry_run(64, np.array([0.1, 0.7]), np.array([0.0]), 2.0, 2.0, 6, 6)
+    assert e.value.status == binding.NNFFT_ERR_DOMAIN
+    with pytest.raises(binding.NnfftError) as e:
+        binding.nnfft_plan_dry_run(64, np.array([0.1]), np.array([0.0]), 2.0, 2.0, 3, 3, P.NNFFT_FP32_COMP)
+    assert e.value.status == binding.NNFFT_ERR_UNSUPPORTED
