@@ -92,13 +92,28 @@ double window_sinh(double u, double beta)
 
 // I_1(z)/z for y = z^2 >= 0 from its Taylor series (1/2) sum y^k/(4^k k!(k+1)!)
 // evaluated in nested (Horner) form from the last kept term down.
+// 1 / (k (k + 1)) for the nested series below
+constexpr int kSeriesMax = 1000;   // terms of the I_1 series (enough for beta <= 2 pi 16)
+
+static const double *inv_k_k1()
+{
+    static const std::vector<double> t = [] {
+        std::vector<double> v(kSeriesMax + 2);
+        v[0] = 0.0;
+        for (int k = 1; k < (int)v.size(); ++k) v[k] = 1.0 / ((double)k * (double)(k + 1));
+        return v;
+    }();
+    return t.data();
+}
+
 static double i1_over_z(double y)
 {
     const double q = 0.25 * y;
     // the terms peak near k = sqrt(q); past ~e sqrt(q) + 40 they are < 1e-20
-    const int K = 40 + (int)(2.72 * std::sqrt(q));
+    const int K = std::min(kSeriesMax, 40 + (int)(2.72 * std::sqrt(q)));
+    const double *r = inv_k_k1();
     double acc = 1.0;
-    for (int k = K; k >= 1; --k) acc = 1.0 + acc * q / ((double)k * (double)(k + 1));
+    for (int k = K; k >= 1; --k) acc = 1.0 + acc * q * r[k];
     return 0.5 * acc;
 }
 
@@ -157,8 +172,8 @@ std::vector<double> fit_window_taps(int m, double beta, int deg, double *max_err
         }
         std::vector<double> c = cheb_fit(deg, f);
         for (int k = 0; k <= deg; ++k) out[(size_t)r * (deg + 1) + k] = c[k];
-        for (int i = 0; i <= 2000; ++i) {
-            const double x = i / 2000.0;
+        for (int i = 0; i <= 500; ++i) {   // the error of a degree-8 fit has 9 lobes
+            const double x = i / 500.0;
             const double e = std::fabs(cheb_eval(c.data(), deg, 2.0 * x - 1.0) -
                                        window_sinh((r - m + 1 - x) / m, beta));
             worst = std::max(worst, e);
@@ -176,6 +191,10 @@ std::vector<double> fit_inverse_phi1(const nnfft_info_t &P, double tol, int max_
         const double v = (double)P.m1 * (double)P.N_star * x / (double)P.N1;
         return 1.0 / ((double)P.m1 / (double)P.N1 * window_sinh_hat(v, P.beta1));
     };
+    // reference values on the check grid, shared by every degree tried
+    constexpr int kGrid = 1000;
+    std::vector<double> ref(kGrid + 1);
+    for (int i = 0; i <= kGrid; ++i) ref[i] = inv(0.5 * i / kGrid);
     std::vector<double> best;
     double best_err = 1e300;
     for (int deg = 4; deg <= max_deg; deg += 2) {
@@ -184,10 +203,9 @@ std::vector<double> fit_inverse_phi1(const nnfft_info_t &P, double tol, int max_
         for (int j = 0; j <= deg; ++j) f[j] = inv(std::sqrt((tn[j] + 1.0) / 8.0));
         std::vector<double> c = cheb_fit(deg, f);
         double err = 0.0;
-        for (int i = 0; i <= 4000; ++i) {
-            const double x = 0.5 * i / 4000.0;
-            const double ref = inv(x);
-            err = std::max(err, std::fabs(cheb_eval(c.data(), deg, 8.0 * x * x - 1.0) / ref - 1.0));
+        for (int i = 0; i <= kGrid; ++i) {
+            const double x = 0.5 * i / kGrid;
+            err = std::max(err, std::fabs(cheb_eval(c.data(), deg, 8.0 * x * x - 1.0) / ref[i] - 1.0));
         }
         if (err < best_err) {
             best_err = err;

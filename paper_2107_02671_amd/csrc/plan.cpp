@@ -475,10 +475,12 @@ nnfft_status plan_host(HostPlan &H, int64_t N, int64_t M1, int64_t M2, double si
     if (fp32) H.corr.resize(kCorr32 + 1, 0.0);   // zero-padded to the unrolled length
 
     H.deconv.resize(P.G1);
-    for (int64_t c = 0; c < P.G1; ++c) {
-        const double l = (double)(c - P.G1 / 2);
+    for (int64_t c = 0; c <= P.G1 / 2; ++c) {   // phi_hat_2 is even: label -l shares the value of l
+        const double l = (double)(P.G1 / 2 - c);
         const double phi2 = (double)m2 / (double)P.N2 * window_sinh_hat(m2 * l / (double)P.N2, P.beta2);
-        H.deconv[c] = 1.0 / ((double)P.N1 * (double)P.N2 * phi2);
+        const double d = 1.0 / ((double)P.N1 * (double)P.N2 * phi2);
+        H.deconv[c] = d;                                  // label -l
+        if (c > 0 && P.G1 / 2 + (P.G1 / 2 - c) < P.G1) H.deconv[P.G1 / 2 + (P.G1 / 2 - c)] = d;   // label +l
     }
     H.tw64 = twiddles(P.N2);
     if (fp32) {
