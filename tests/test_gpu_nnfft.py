@@ -186,3 +186,34 @@ def test_plan_errors():
     with pytest.raises(P.NnfftError) as e:
         P.nnfft_plan(64, ok_v, nan_x, 2.0, 2.0, 6, 6, FP64)
     assert e.value.status == P.binding.NNFFT_ERR_DOMAIN
+
+
+_CLUSTERED = {}
+
+
+def _clustered_reference():
+    # inputs, oracle NNFFT and 64 sampled direct sums, computed once for both precisions
+    if not _CLUSTERED:
+        N, v, x, f, w = W.nnfft_inputs("clustered")
+        m = w["m"]
+        idx = W.rng(98).choice(len(x), 64, replace=False)
+        _CLUSTERED.update(N=N, v=v, x=x, f=f, m=m, idx=idx,
+                          yo=oracle.nnfft(N, v, f, x, 2.0, 2.0, m, m), ex=oracle.direct(N, v, f, x[idx]))
+    return _CLUSTERED
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_clustered_workload_full_size(prec):
+    # N=16384, M1=M2=2^24, nodes in 32 Gaussian clusters (std 1e-3), sigma=2,
+    # m=8: ~1e5 contributions per grid cell.  All outputs against the oracle
+    # NNFFT, 64 sampled outputs against the direct sum.
+    R = _clustered_reference()
+    N, m = R["N"], R["m"]
+    y, info = gpu_nnfft(N, R["v"], R["x"], R["f"], 2.0, 2.0, m, m, prec)
+    e = einf(y, R["yo"])
+    t = tol(prec, N, 2.0, 2.0, m, m)
+    _say(f"    clustered E_inf vs oracle NNFFT = {e:.3e} (tol {t:.2e})")
+    assert e <= t
+    e_direct = float(np.abs(y[R["idx"]] - R["ex"]).max() / np.abs(R["ex"]).max())
+    _say(f"    clustered E_inf vs direct sum (64 samples) = {e_direct:.3e}")
+    assert e_direct <= max(t, 1e-6)
