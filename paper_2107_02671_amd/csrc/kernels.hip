@@ -129,6 +129,13 @@ constexpr int kWaves32 = 4;
 constexpr int kThreads32 = kWaves32 * kItemsPerWg;
 constexpr int kRowsPerWave = 8;   // record rows a wave loads in one batch
 
+// Record row for the j-th load of a wave that owns rows [row0, row0 + rpw):
+// loads past its share repeat its last row (same addresses, no extra lines).
+__device__ __forceinline__ int wave_row(int row0, int j, int rpw, int rows)
+{
+    return min(row0 + min(j, rpw - 1), rows - 1);
+}
+
 // LDS arrays are indexed [moment or tap][item or bin] so that the lanes of a
 // wave (consecutive items or bins) touch consecutive 8-byte words: no bank
 // conflicts in any phase.
@@ -193,7 +200,7 @@ __device__ void spread32_slot(const SpreadArgs &A, const cx<float> *__restrict__
     PtRec r[kRowsPerWave];
     cx<float> fv[kRowsPerWave];
 #pragma unroll
-    for (int j = 0; j < kRowsPerWave; ++j) r[j] = rec[min(row0 + j, rows - 1) * kItemsPerWg];
+    for (int j = 0; j < kRowsPerWave; ++j) r[j] = rec[wave_row(row0, j, rpw, rows) * kItemsPerWg];
 #pragma unroll
     for (int j = 0; j < kRowsPerWave; ++j) fv[j] = f[r[j].perm];
     const Item it = A.items[g * kItemsPerWg + t];
@@ -213,7 +220,7 @@ __device__ void spread32_slot(const SpreadArgs &A, const cx<float> *__restrict__
         for (int j0 = 0; j0 < nq; j0 += kRowsPerWave) {
             if (j0 > 0) {
 #pragma unroll
-                for (int j = 0; j < kRowsPerWave; ++j) r[j] = rec[min(row0 + j0 + j, rows - 1) * kItemsPerWg];
+                for (int j = 0; j < kRowsPerWave; ++j) r[j] = rec[wave_row(row0, j0 + j, rpw, rows) * kItemsPerWg];
 #pragma unroll
                 for (int j = 0; j < kRowsPerWave; ++j) fv[j] = f[r[j].perm];
             }
@@ -307,12 +314,29 @@ __global__ __launch_bounds__(kThreads32, TM <= 16 ? 6 : 4) void k_spread32(Sprea
 // ===========================================================================
 constexpr int Q64 = 8;
 
+// LDS of the FP64 kernels, sized at launch for the plan's 2m taps (dynamic
+// shared memory), so that short windows leave room for more workgroups per CU.
 struct Spread64Lds {
-    cx<double> sitem[kItemsPerWg * 2 * kMaxM];
-    int ibin[kItemsPerWg];
-    int runS[kItemsPerWg];
-    int runE[kItemsPerWg];
+    cx<double> *sitem;   // [2m][64]: tap r of item t at r * 64 + t
+    int *ibin, *runS, *runE;
 };
+
+__device__ __forceinline__ Spread64Lds spread64_lds(int tm)
+{
+    extern __shared__ __align__(16) char smem[];
+    Spread64Lds L;
+    L.sitem = reinterpret_cast<cx<double> *>(smem);
+    int *ip = reinterpret_cast<int *>(smem + (size_t)tm * kItemsPerWg * sizeof(cx<double>));
+    L.ibin = ip;
+    L.runS = ip + kItemsPerWg;
+    L.runE = ip + 2 * kItemsPerWg;
+    return L;
+}
+
+static size_t lds64_bytes(int tm)
+{
+    return (size_t)tm * kItemsPerWg * sizeof(cx<double>) + 3 * kItemsPerWg * sizeof(int);
+}
 
 __device__ void spread64_slot(const SpreadArgs &A, const cx<double> *__restrict__ f, int g, Spread64Lds &L)
 {
@@ -377,7 +401,7 @@ __device__ void spread64_slot(const SpreadArgs &A, const cx<double> *__restrict_
 
 __global__ __launch_bounds__(64) void k_spread64(SpreadArgs A, const cx<double> *__restrict__ f)
 {
-    __shared__ Spread64Lds L;
+    Spread64Lds L = spread64_lds(2 * A.m);
     spread64_slot(A, f, blockIdx.x, L);
 }
 
@@ -404,7 +428,7 @@ __device__ __forceinline__ void interp32_slot(const InterpArgs &A, cx<float> *__
     const PtRec *__restrict__ rec = A.rec32 + (size_t)g * rows * kItemsPerWg + t;
     PtRec r[kRowsPerWave];
 #pragma unroll
-    for (int j = 0; j < kRowsPerWave; ++j) r[j] = rec[min(row0 + j, rows - 1) * kItemsPerWg];
+    for (int j = 0; j < kRowsPerWave; ++j) r[j] = rec[wave_row(row0, j, rpw, rows) * kItemsPerWg];
     const Item it = A.items[g * kItemsPerWg + t];
     const int m = A.m, tm = 2 * m;
     const int lab = it.bin - A.ip_off;
@@ -449,7 +473,7 @@ __device__ __forceinline__ void interp32_slot(const InterpArgs &A, cx<float> *__
         for (int j0 = 0; j0 < nq; j0 += kRowsPerWave) {
             if (j0 > 0) {
 #pragma unroll
-                for (int j = 0; j < kRowsPerWave; ++j) r[j] = rec[min(row0 + j0 + j, rows - 1) * kItemsPerWg];
+                for (int j = 0; j < kRowsPerWave; ++j) r[j] = rec[wave_row(row0, j0 + j, rpw, rows) * kItemsPerWg];
             }
 #pragma unroll
             for (int j = 0; j < kRowsPerWave; ++j) {
@@ -485,10 +509,20 @@ __global__ __launch_bounds__(kThreads32) void k_interp32(InterpArgs A, cx<float>
 }
 
 struct Interp64Lds {
-    cx<double> hw[kItemsPerWg * 2 * kMaxM];
-    int ibin[kItemsPerWg];
-    int used[kItemsPerWg];
+    cx<double> *hw;   // [2m][64]: grid value r of bin b at r * 64 + b
+    int *ibin, *used;
 };
+
+__device__ __forceinline__ Interp64Lds interp64_lds(int tm)
+{
+    extern __shared__ __align__(16) char smem[];
+    Interp64Lds L;
+    L.hw = reinterpret_cast<cx<double> *>(smem);
+    int *ip = reinterpret_cast<int *>(smem + (size_t)tm * kItemsPerWg * sizeof(cx<double>));
+    L.ibin = ip;
+    L.used = ip + kItemsPerWg;
+    return L;
+}
 
 __device__ void interp64_slot(const InterpArgs &A, cx<double> *__restrict__ y, int g, Interp64Lds &L)
 {
@@ -534,24 +568,13 @@ __device__ void interp64_slot(const InterpArgs &A, cx<double> *__restrict__ y, i
 
 __global__ __launch_bounds__(64) void k_interp64(InterpArgs A, cx<double> *__restrict__ y)
 {
-    __shared__ Interp64Lds L;
+    Interp64Lds L = interp64_lds(2 * A.m);
     interp64_slot(A, y, blockIdx.x, L);
 }
 
 // ===========================================================================
 // FFT (steps 2-3)
 // ===========================================================================
-// complex values per FFT workgroup (sub-transform length x batch)
-template <typename T>
-struct FftCfg;
-template <>
-struct FftCfg<float> {
-    static constexpr int vals = 4096;
-};
-template <>
-struct FftCfg<double> {
-    static constexpr int vals = 2048;
-};
 
 // FFT input element q (index mod N2) = merged, deconvolved step-1 output:
 // label l = q (q < N2/2) or q - N2; zero outside I_{G1}.
@@ -563,15 +586,15 @@ __device__ __forceinline__ cx<float> fft_input32(const FftArgs &A, int q)
     const float4 *part = reinterpret_cast<const float4 *>(A.partial);
     float hr = 0.f, hi = 0.f, lr = 0.f, li = 0.f;
     const int e0 = A.merge_off[cell], e1 = A.merge_off[cell + 1];
-    // the planes: fixed offsets s G1 + cell, eight loads in flight at a time
+    // the planes: fixed offsets s G1 + cell, all loads in flight together
     const int np = A.nplanes;
-    for (int s0 = 0; s0 < np; s0 += 8) {
-        float4 v[8];
+    {
+        float4 v[kMaxPlanes];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) v[q] = part[(size_t)min(s0 + q, np - 1) * A.G1 + cell];
+        for (int q = 0; q < kMaxPlanes; ++q) v[q] = part[(size_t)min(q, np - 1) * A.G1 + cell];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            if (s0 + q < np) {
+        for (int q = 0; q < kMaxPlanes; ++q) {
+            if (q < np) {
                 comp_add(hr, lr, v[q].x);
                 comp_add(hi, li, v[q].y);
                 lr += v[q].z;
@@ -610,13 +633,13 @@ __device__ __forceinline__ cx<double> fft_input64(const FftArgs &A, int q)
     double ar = 0.0, ai = 0.0;
     const int e1 = A.merge_off[cell + 1];
     const int np = A.nplanes;
-    for (int s0 = 0; s0 < np; s0 += 8) {
-        double2 v[8];
+    {
+        double2 v[kMaxPlanes];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) v[q] = part[(size_t)min(s0 + q, np - 1) * A.G1 + cell];
+        for (int q = 0; q < kMaxPlanes; ++q) v[q] = part[(size_t)min(q, np - 1) * A.G1 + cell];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            if (s0 + q < np) {
+        for (int q = 0; q < kMaxPlanes; ++q) {
+            if (q < np) {
                 ar += v[q].x;
                 ai += v[q].y;
             }
@@ -788,12 +811,42 @@ __device__ __forceinline__ void fft_store(const FftArgs &A, int k, cx<T> v)
     if (k == half && half <= A.S) h[A.N2] = v;   // label +N2/2 equals label -N2/2
 }
 
+// LDS of an FFT workgroup, sized at launch (dynamic shared memory) for the
+// plan's sub-transforms: two ping-pong buffers, the sub-transform twiddles and
+// (stage A) the four-step twiddles, `vals` complex values each.
 template <typename T>
 struct FftLds {
-    cx<T> buf[2][FftCfg<T>::vals];
-    cx<T> tw[FftCfg<T>::vals];    // exp(-2 pi i e / L) of the sub-transform length L
-    cx<T> otw[FftCfg<T>::vals];   // stage A: the four-step twiddles of this workgroup's columns
+    cx<T> *buf[2];
+    cx<T> *tw;
+    cx<T> *otw;
 };
+
+// complex values per array: the whole transform (one workgroup) or the
+// largest batch of sub-transforms of the two four-step stages
+__host__ __device__ __forceinline__ int fft_vals(const FftArgs &A)
+{
+    return A.n1 == 1 ? A.N2 : max(A.batchA * A.n2, A.batchB * A.n1);
+}
+
+template <typename T>
+__device__ __forceinline__ FftLds<T> fft_lds(const FftArgs &A)
+{
+    extern __shared__ __align__(16) char smem[];
+    cx<T> *p = reinterpret_cast<cx<T> *>(smem);
+    const int v = fft_vals(A);
+    FftLds<T> L;
+    L.buf[0] = p;
+    L.buf[1] = p + v;
+    L.tw = p + 2 * v;
+    L.otw = p + 3 * v;
+    return L;
+}
+
+template <typename T>
+static size_t fft_lds_bytes(const FftArgs &A)
+{
+    return 4 * (size_t)fft_vals(A) * sizeof(cx<T>);
+}
 
 // Column block handled by local workgroup w of a launch of 8 ceil(ng / 8)
 // workgroups: XCD x = w mod 8 takes the contiguous blocks [x per, (x + 1) per),
@@ -824,7 +877,7 @@ __device__ void fft_single_body(const FftArgs &A, FftLds<T> &L)
 template <typename T>
 __global__ __launch_bounds__(256) void k_fft_single(FftArgs A)
 {
-    __shared__ FftLds<T> L;
+    FftLds<T> L = fft_lds<T>(A);
     fft_single_body<T>(A, L);
 }
 
@@ -862,7 +915,7 @@ __device__ void fft_stageA_body(const FftArgs &A, int w, FftLds<T> &L)
 template <typename T>
 __global__ __launch_bounds__(256) void k_fft_stageA(FftArgs A)
 {
-    __shared__ FftLds<T> L;
+    FftLds<T> L = fft_lds<T>(A);
     fft_stageA_body<T>(A, blockIdx.x, L);
 }
 
@@ -895,7 +948,7 @@ __device__ void fft_stageB_body(const FftArgs &A, int w, FftLds<T> &L)
 template <typename T>
 __global__ __launch_bounds__(256) void k_fft_stageB(FftArgs A)
 {
-    __shared__ FftLds<T> L;
+    FftLds<T> L = fft_lds<T>(A);
     fft_stageB_body<T>(A, blockIdx.x, L);
 }
 
@@ -924,9 +977,9 @@ __global__ __launch_bounds__(kThreads32, TM <= 16 ? 6 : 4) void k_spread32_batch
 
 __global__ __launch_bounds__(64) void k_spread64_batch(BatchTable T)
 {
-    __shared__ Spread64Lds L;
     const int p = batch_plan(T, blockIdx.x);
     const SpreadArgs A = T.desc[p]->sp;
+    Spread64Lds L = spread64_lds(2 * A.m);
     const int g = blockIdx.x - T.start[p];
     if (g >= A.ngrid) return;
     spread64_slot(A, static_cast<const cx<double> *>(T.in[p]), g, L);
@@ -945,9 +998,9 @@ __global__ __launch_bounds__(kThreads32) void k_interp32_batch(BatchTable T)
 
 __global__ __launch_bounds__(64) void k_interp64_batch(BatchTable T)
 {
-    __shared__ Interp64Lds L;
     const int p = batch_plan(T, blockIdx.x);
     const InterpArgs A = T.desc[p]->ip;
+    Interp64Lds L = interp64_lds(2 * A.m);
     const int g = blockIdx.x - T.start[p];
     if (g >= A.ngrid) return;
     interp64_slot(A, static_cast<cx<double> *>(T.out[p]), g, L);
@@ -957,9 +1010,9 @@ __global__ __launch_bounds__(64) void k_interp64_batch(BatchTable T)
 template <typename T>
 __global__ __launch_bounds__(256) void k_fftA_batch(BatchTable Tb)
 {
-    __shared__ FftLds<T> L;
     const int p = batch_plan(Tb, blockIdx.x);
     const FftArgs &A = Tb.desc[p]->fft;
+    FftLds<T> L = fft_lds<T>(A);
     const int w = blockIdx.x - Tb.start[p];
     if (A.n1 == 1) {
         if (w == 0) fft_single_body<T>(A, L);
@@ -971,9 +1024,9 @@ __global__ __launch_bounds__(256) void k_fftA_batch(BatchTable Tb)
 template <typename T>
 __global__ __launch_bounds__(256) void k_fftB_batch(BatchTable Tb)
 {
-    __shared__ FftLds<T> L;
     const int p = batch_plan(Tb, blockIdx.x);
     const FftArgs &A = Tb.desc[p]->fft;
+    FftLds<T> L = fft_lds<T>(A);
     fft_stageB_body<T>(A, blockIdx.x - Tb.start[p], L);
 }
 
@@ -990,11 +1043,32 @@ template <typename T>
 static void launch_fft(const FftArgs &A, hipStream_t s)
 {
     if (A.n1 == 1) {
-        hipLaunchKernelGGL((k_fft_single<T>), dim3(1), dim3(A.threadsA), 0, s, A);
+        hipLaunchKernelGGL((k_fft_single<T>), dim3(1), dim3(A.threadsA), fft_lds_bytes<T>(A), s, A);
     } else {
         const int gA = fft_groups(A.n1, A.batchA), gB = fft_groups(A.n2, A.batchB);
-        hipLaunchKernelGGL((k_fft_stageA<T>), dim3(gA), dim3(A.threadsA), 0, s, A);
-        hipLaunchKernelGGL((k_fft_stageB<T>), dim3(gB), dim3(A.threadsB), 0, s, A);
+        hipLaunchKernelGGL((k_fft_stageA<T>), dim3(gA), dim3(A.threadsA), fft_lds_bytes<T>(A), s, A);
+        hipLaunchKernelGGL((k_fft_stageB<T>), dim3(gB), dim3(A.threadsB), fft_lds_bytes<T>(A), s, A);
+    }
+}
+
+// k_interp32 variants: correction degree CD in {8, 10, 12, 16}
+static void launch_interp32(int cd, int grid, hipStream_t s, const InterpArgs &A, cx<float> *y)
+{
+    switch (cd) {
+    case 8: hipLaunchKernelGGL((k_interp32<8>), dim3(grid), dim3(kThreads32), 0, s, A, y); break;
+    case 10: hipLaunchKernelGGL((k_interp32<10>), dim3(grid), dim3(kThreads32), 0, s, A, y); break;
+    case 12: hipLaunchKernelGGL((k_interp32<12>), dim3(grid), dim3(kThreads32), 0, s, A, y); break;
+    default: hipLaunchKernelGGL((k_interp32<16>), dim3(grid), dim3(kThreads32), 0, s, A, y); break;
+    }
+}
+
+static void launch_interp32_batch(int cd, int grid, hipStream_t s, const BatchTable &T)
+{
+    switch (cd) {
+    case 8: hipLaunchKernelGGL((k_interp32_batch<8>), dim3(grid), dim3(kThreads32), 0, s, T); break;
+    case 10: hipLaunchKernelGGL((k_interp32_batch<10>), dim3(grid), dim3(kThreads32), 0, s, T); break;
+    case 12: hipLaunchKernelGGL((k_interp32_batch<12>), dim3(grid), dim3(kThreads32), 0, s, T); break;
+    default: hipLaunchKernelGGL((k_interp32_batch<16>), dim3(grid), dim3(kThreads32), 0, s, T); break;
     }
 }
 
@@ -1018,20 +1092,14 @@ hipError_t launch_exec(const PlanDev &P, const void *f, void *y, hipStream_t s, 
         if (ev) (void)hipEventRecord(ev[1], s);
         launch_fft<float>(P.fft, s);
         if (ev) (void)hipEventRecord(ev[2], s);
-        cx<float> *yo = reinterpret_cast<cx<float> *>(y);
-        switch (corr_variant(P.ip.corr_deg)) {
-        case 8: hipLaunchKernelGGL((k_interp32<8>), dim3(gi), dim3(kThreads32), 0, s, P.ip, yo); break;
-        case 10: hipLaunchKernelGGL((k_interp32<10>), dim3(gi), dim3(kThreads32), 0, s, P.ip, yo); break;
-        case 12: hipLaunchKernelGGL((k_interp32<12>), dim3(gi), dim3(kThreads32), 0, s, P.ip, yo); break;
-        default: hipLaunchKernelGGL((k_interp32<16>), dim3(gi), dim3(kThreads32), 0, s, P.ip, yo); break;
-        }
+        launch_interp32(corr_variant(P.ip.corr_deg), gi, s, P.ip, reinterpret_cast<cx<float> *>(y));
     } else {
-        hipLaunchKernelGGL(k_spread64, dim3(P.sp.ngrid), dim3(kItemsPerWg), 0, s, P.sp,
+        hipLaunchKernelGGL(k_spread64, dim3(P.sp.ngrid), dim3(kItemsPerWg), lds64_bytes(2 * P.sp.m), s, P.sp,
                            reinterpret_cast<const cx<double> *>(f));
         if (ev) (void)hipEventRecord(ev[1], s);
         launch_fft<double>(P.fft, s);
         if (ev) (void)hipEventRecord(ev[2], s);
-        hipLaunchKernelGGL(k_interp64, dim3(P.ip.ngrid), dim3(kItemsPerWg), 0, s, P.ip,
+        hipLaunchKernelGGL(k_interp64, dim3(P.ip.ngrid), dim3(kItemsPerWg), lds64_bytes(2 * P.ip.m), s, P.ip,
                            reinterpret_cast<cx<double> *>(y));
     }
     if (ev) (void)hipEventRecord(ev[3], s);
@@ -1047,6 +1115,8 @@ hipError_t launch_exec_batch(int n, const PlanDev *const *host, const PlanDev *c
         BatchTable Tsp{}, Tip{}, TA{}, TB{};
         int ssp = 0, sip = 0, sA = 0, sB = 0, thrA = 64, thrB = 64;
         bool long_window = false;
+        int tm_sp = 2, tm_ip = 2;   // largest 2m of the group (FP64 LDS size)
+        size_t fft_bytes = 0;       // largest FFT LDS of the group
         int corr_deg = 0;
         for (int i = 0; i < nb; ++i) {
             const PlanDev &P = *host[b0 + i];
@@ -1071,6 +1141,10 @@ hipError_t launch_exec_batch(int n, const PlanDev *const *host, const PlanDev *c
                 thrB = std::max(thrB, P.fft.threadsB);
             }
             long_window = long_window || 2 * P.sp.m > 16;
+            tm_sp = std::max(tm_sp, 2 * P.sp.m);
+            fft_bytes = std::max(fft_bytes, P.prec == NNFFT_FP32_COMP ? fft_lds_bytes<float>(P.fft)
+                                                                      : fft_lds_bytes<double>(P.fft));
+            tm_ip = std::max(tm_ip, 2 * P.ip.m);
             corr_deg = std::max(corr_deg, P.ip.corr_deg);
         }
         Tsp.start[nb] = ssp;
@@ -1083,19 +1157,14 @@ hipError_t launch_exec_batch(int n, const PlanDev *const *host, const PlanDev *c
                 hipLaunchKernelGGL((k_spread32_batch<32>), dim3(ssp), dim3(kThreads32), 0, s, Tsp);
             else
                 hipLaunchKernelGGL((k_spread32_batch<16>), dim3(ssp), dim3(kThreads32), 0, s, Tsp);
-            hipLaunchKernelGGL((k_fftA_batch<float>), dim3(sA), dim3(thrA), 0, s, TA);
-            if (sB > 0) hipLaunchKernelGGL((k_fftB_batch<float>), dim3(sB), dim3(thrB), 0, s, TB);
-            switch (corr_variant(corr_deg)) {
-            case 8: hipLaunchKernelGGL((k_interp32_batch<8>), dim3(sip), dim3(kThreads32), 0, s, Tip); break;
-            case 10: hipLaunchKernelGGL((k_interp32_batch<10>), dim3(sip), dim3(kThreads32), 0, s, Tip); break;
-            case 12: hipLaunchKernelGGL((k_interp32_batch<12>), dim3(sip), dim3(kThreads32), 0, s, Tip); break;
-            default: hipLaunchKernelGGL((k_interp32_batch<16>), dim3(sip), dim3(kThreads32), 0, s, Tip); break;
-            }
+            hipLaunchKernelGGL((k_fftA_batch<float>), dim3(sA), dim3(thrA), fft_bytes, s, TA);
+            if (sB > 0) hipLaunchKernelGGL((k_fftB_batch<float>), dim3(sB), dim3(thrB), fft_bytes, s, TB);
+            launch_interp32_batch(corr_variant(corr_deg), sip, s, Tip);
         } else {
-            hipLaunchKernelGGL(k_spread64_batch, dim3(ssp), dim3(kItemsPerWg), 0, s, Tsp);
-            hipLaunchKernelGGL((k_fftA_batch<double>), dim3(sA), dim3(thrA), 0, s, TA);
-            if (sB > 0) hipLaunchKernelGGL((k_fftB_batch<double>), dim3(sB), dim3(thrB), 0, s, TB);
-            hipLaunchKernelGGL(k_interp64_batch, dim3(sip), dim3(kItemsPerWg), 0, s, Tip);
+            hipLaunchKernelGGL(k_spread64_batch, dim3(ssp), dim3(kItemsPerWg), lds64_bytes(tm_sp), s, Tsp);
+            hipLaunchKernelGGL((k_fftA_batch<double>), dim3(sA), dim3(thrA), fft_bytes, s, TA);
+            if (sB > 0) hipLaunchKernelGGL((k_fftB_batch<double>), dim3(sB), dim3(thrB), fft_bytes, s, TB);
+            hipLaunchKernelGGL(k_interp64_batch, dim3(sip), dim3(kItemsPerWg), lds64_bytes(tm_ip), s, Tip);
         }
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
