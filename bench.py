@@ -290,10 +290,15 @@ def main() -> int:
     #   spreading:      M1 * (8 B f_k + 4 B offset + 4 B index)
     #   interpolation:  M2 * (4 B offset + 4 B index + 8 B y_j)
     #   FFT stage:      G1 * 16 B partial read + N2 * 8 B write (order of)
+    # The dominant kernel is the slower of spreading and interpolation (single
+    # kernels; the FFT stage is two kernels over ~0.3 MB).  Its duration comes
+    # from the library's HIP events at the stage boundaries, which include the
+    # recording of the events themselves (~1-2 us more than the kernel-trace
+    # duration of the same kernel).
     names = ["spread", "fft", "interp"]
     kern = {"spread": "k_spread32", "fft": "k_fft_stage", "interp": "k_interp32"}
     algo = {"spread": 16.0 * M1, "interp": 16.0 * M2, "fft": 16.0 * info32["G1"] + 8.0 * info32["N2"]}
-    dom = max(range(3), key=lambda i: stages32[i])
+    dom = max((0, 2), key=lambda i: stages32[i])
     dname = names[dom]
     achieved = algo[dname] / (stages32[dom] * 1e-3) / 1e9
     out["roofline"] = {"bound": "hbm", "kernel": kern[dname], "achieved": achieved, "peak": HBM_PEAK_GBS,
