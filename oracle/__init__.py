@@ -55,6 +55,10 @@ def lib():
                                     ctypes.c_int, ctypes.c_int, ctypes.c_long, ctypes.c_long, dp, dp,
                                     ctypes.c_long, dp, dp]
         L.orc_num_threads.restype = ctypes.c_int
+        L.orc_nfft_params.argtypes = [ctypes.c_long, ctypes.c_double, ctypes.c_int, ctypes.POINTER(ctypes.c_long),
+                                      ctypes.POINTER(ctypes.c_double)]
+        L.orc_nfft.argtypes = [ctypes.c_long, ctypes.c_double, ctypes.c_int, dp, ctypes.c_long, dp, dp]
+        L.orc_nfft_adjoint.argtypes = [ctypes.c_long, ctypes.c_double, ctypes.c_int, ctypes.c_long, dp, dp, dp]
         _lib = L
     return _lib
 
@@ -139,6 +143,41 @@ def nnfft(N, v, f, x, sigma1=2.0, sigma2=2.0, m1=4, m2=4, return_steps=False):
     if rc:
         raise RuntimeError(f"orc_nnfft failed with code {rc}")
     return (y, g, h) if return_steps else y
+
+
+def nfft_params(N, sigma, m):
+    """(n, beta) of the oracle NFFT: n the smallest even 2,3,5-smooth integer >= sigma N."""
+    n = ctypes.c_long()
+    beta = ctypes.c_double()
+    if lib().orc_nfft_params(int(N), float(sigma), int(m), ctypes.byref(n), ctypes.byref(beta)):
+        raise ValueError("invalid NFFT parameters")
+    return n.value, beta.value
+
+
+def nfft(N, f, x, sigma=2.0, m=6) -> np.ndarray:
+    """y_j = sum_{k in I_N} f_k exp(-2 pi i k x_j) by the NFFT steps (f index k + N/2)."""
+    x, f = _real(x), _cplx(f)
+    y = np.zeros(len(x), dtype=np.complex128)
+    rc = lib().orc_nfft(int(N), float(sigma), int(m), _dp(f.view(np.float64)), len(x), _dp(x),
+                        _dp(y.view(np.float64)))
+    if rc == 2:
+        raise ValueError("node outside [-1/2, 1/2]")
+    if rc:
+        raise RuntimeError(f"orc_nfft failed with code {rc}")
+    return y
+
+
+def nfft_adjoint(N, y, x, sigma=2.0, m=6) -> np.ndarray:
+    """h_k = sum_j y_j exp(+2 pi i k x_j), k in I_N (index k + N/2), by the transposed steps."""
+    x, y = _real(x), _cplx(y)
+    h = np.zeros(int(N), dtype=np.complex128)
+    rc = lib().orc_nfft_adjoint(int(N), float(sigma), int(m), len(x), _dp(x), _dp(y.view(np.float64)),
+                                _dp(h.view(np.float64)))
+    if rc == 2:
+        raise ValueError("node outside [-1/2, 1/2]")
+    if rc:
+        raise RuntimeError(f"orc_nfft_adjoint failed with code {rc}")
+    return h
 
 
 def sinc_direct(N, a, c, b) -> np.ndarray:

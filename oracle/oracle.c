@@ -461,3 +461,123 @@ int orc_num_threads(void)
     return 1;
 #endif
 }
+
+/* ------------------------------------------------------------------------ */
+/* NFFT with equispaced frequencies (Sec. 2, the building block of the NNFFT; */
+/* Sec. 6, the equispaced special cases of the fast sinc transform)          */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * The special case v_k = k / N, k in I_N, of (1.2), and its adjoint:
+ *   forward  y_j = sum_{k in I_N} f_k exp(-2 pi i k x_j),       j in I_M
+ *   adjoint  h_k = sum_{j in I_M} y_j exp(+2 pi i k x_j),       k in I_N
+ * with the sinh-type window of Example 2.1 on an oversampled grid of length n:
+ *   phi(t) = omega(n t / m),  phi_hat(k) = (m / n) omega_hat(m k / n).
+ * Reading: the paper names the NFFT without listing its steps; these are the
+ * standard ones (deconvolution, length-n DFT, window interpolation, and their
+ * transposes).  n is the smallest even 2,3,5-smooth integer >= sigma N (as
+ * for N2 of Algorithm 2.2), sigma_eff = n / N, beta = 2 pi m (1 - 1/(2 sigma_eff)).
+ * Returns 0, 1 for invalid parameters (N < 2 odd, m < 2, sigma <= 1, 2m >= n),
+ * 2 for a node outside [-1/2, 1/2], 3 for allocation failure.
+ */
+int orc_nfft_params(long N, double sigma, int m, long *n_out, double *beta_out)
+{
+    if (N < 2 || (N % 2) || m < 2 || !(sigma > 1.0)) return 1;
+    long n = orc_ceil_tol(sigma * (double)N);
+    if (n % 2) n++;
+    while (!orc_is_smooth235(n)) n += 2;
+    if (2 * m >= n) return 1;
+    *n_out = n;
+    *beta_out = 2.0 * ORC_PI * m * (1.0 - (double)N / (2.0 * (double)n));
+    return 0;
+}
+
+/* l mod n in [0, n) */
+static long orc_mod(long l, long n)
+{
+    long r = l % n;
+    return r < 0 ? r + n : r;
+}
+
+int orc_nfft(long N, double sigma, int m, const double *f, long M, const double *x, double *y)
+{
+    long n;
+    double beta;
+    if (orc_nfft_params(N, sigma, m, &n, &beta)) return 1;
+    for (long j = 0; j < M; j++) if (!(fabs(x[j]) <= 0.5)) return 2;
+    double *g = calloc((size_t)(2 * n), sizeof(double));
+    if (!g) return 3;
+    /* deconvolution and the length-n DFT: g_l = sum_k f_k / (n phi_hat(k)) e^{-2 pi i k l / n} */
+    long l;
+#pragma omp parallel for schedule(static)
+    for (l = 0; l < n; l++) {
+        orc_acc_t re = {0, 0}, im = {0, 0};
+        for (long k = -N / 2; k < N / 2; k++) {
+            const double d = 1.0 / ((double)n * ((double)m / (double)n) * orc_omega_hat(m * (double)k / (double)n, beta));
+            const double fr = f[2 * (k + N / 2)] * d, fi = f[2 * (k + N / 2) + 1] * d;
+            double c, s;
+            orc_expm2pi((double)orc_mod(k * l, n) / (double)n, &c, &s);
+            orc_acc_add(&re, fr * c - fi * s);
+            orc_acc_add(&im, fr * s + fi * c);
+        }
+        g[2 * l] = re.s + re.c;
+        g[2 * l + 1] = im.s + im.c;
+    }
+    /* interpolation with the periodized window */
+    long j;
+#pragma omp parallel for schedule(static)
+    for (j = 0; j < M; j++) {
+        const double u = (double)n * x[j];
+        const long c = (long)floor(u);
+        double sr = 0.0, si = 0.0;
+        for (long ll = c - m + 1; ll <= c + m; ll++) {
+            const double w = orc_omega((u - (double)ll) / m, beta);
+            const long q = orc_mod(ll, n);
+            sr += g[2 * q] * w;
+            si += g[2 * q + 1] * w;
+        }
+        y[2 * j] = sr;
+        y[2 * j + 1] = si;
+    }
+    free(g);
+    return 0;
+}
+
+int orc_nfft_adjoint(long N, double sigma, int m, long M, const double *x, const double *y, double *h)
+{
+    long n;
+    double beta;
+    if (orc_nfft_params(N, sigma, m, &n, &beta)) return 1;
+    for (long j = 0; j < M; j++) if (!(fabs(x[j]) <= 0.5)) return 2;
+    double *g = calloc((size_t)(2 * n), sizeof(double));
+    if (!g) return 3;
+    /* spreading with the periodized window (serial: plain and order-fixed) */
+    for (long j = 0; j < M; j++) {
+        const double u = (double)n * x[j];
+        const long c = (long)floor(u);
+        for (long ll = c - m + 1; ll <= c + m; ll++) {
+            const double w = orc_omega((u - (double)ll) / m, beta);
+            const long q = orc_mod(ll, n);
+            g[2 * q] += y[2 * j] * w;
+            g[2 * q + 1] += y[2 * j + 1] * w;
+        }
+    }
+    /* length-n DFT with the + sign and the deconvolution */
+    long k;
+#pragma omp parallel for schedule(static)
+    for (k = -N / 2; k < N / 2; k++) {
+        orc_acc_t re = {0, 0}, im = {0, 0};
+        for (long l = 0; l < n; l++) {
+            double c, s;
+            orc_expm2pi((double)orc_mod(k * l, n) / (double)n, &c, &s);
+            s = -s;   /* exp(+2 pi i k l / n) */
+            orc_acc_add(&re, g[2 * l] * c - g[2 * l + 1] * s);
+            orc_acc_add(&im, g[2 * l] * s + g[2 * l + 1] * c);
+        }
+        const double d = 1.0 / ((double)n * ((double)m / (double)n) * orc_omega_hat(m * (double)k / (double)n, beta));
+        h[2 * (k + N / 2)] = (re.s + re.c) * d;
+        h[2 * (k + N / 2) + 1] = (im.s + im.c) * d;
+    }
+    free(g);
+    return 0;
+}

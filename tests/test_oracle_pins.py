@@ -421,3 +421,81 @@ def test_sinc_fast_within_theorem_6_2(quad, nq_of_N):
     assert err < 1e-6 * np.abs(ref).max()
     # real coefficients give a real transform
     assert np.abs(h.imag).max() < 1e-9 * np.abs(h).max()
+
+
+# --------------------------------------------------------------------------
+# NFFT with equispaced frequencies and its adjoint (the special case v_k = k/N
+# of (1.2), Sec. 2; the equispaced cases of the fast sinc transform, Sec. 6)
+# --------------------------------------------------------------------------
+
+def _nfft_case(N, M, seed):
+    rng = _rng(seed)
+    x = rng.uniform(-0.5, 0.5, M)
+    x[:3] = [-0.5, 0.5, 0.0]
+    f = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    y = rng.standard_normal(M) + 1j * rng.standard_normal(M)
+    return x, f, y
+
+
+def _nfft_gate(N, sigma, m):
+    # the sinh-type window's NFFT error constant decays like
+    # m^(3/2) exp(-2 pi m sqrt(1 - 1/sigma)); gate with the factor 24 (the
+    # largest entry error of the fast map measured for sigma in [5/4, 2],
+    # m in {4, 6, 8} is 6-14 times m^(3/2) exp(...)); rounding floor 1e-14
+    n, _ = oracle.nfft_params(N, sigma, m)
+    return 24.0 * m ** 1.5 * math.exp(-2 * math.pi * m * math.sqrt(1 - N / n)) + 1e-14
+
+
+@pytest.mark.parametrize("N,M,sigma", [(64, 300, 2.0), (100, 257, 1.5), (250, 64, 2.0), (32, 500, 1.25)])
+@pytest.mark.parametrize("m", [4, 6, 8])
+def test_nfft_forward_and_adjoint_against_direct_sums(N, M, sigma, m):
+    x, f, y = _nfft_case(N, M, N + M + m)
+    k = np.arange(-N // 2, N // 2)
+    yf = oracle.nfft(N, f, x, sigma, m)
+    yd = oracle.direct(N, k / N, f, x)                      # (1.2) with v_k = k / N
+    assert np.abs(yf - yd).max() <= _nfft_gate(N, sigma, m) * np.abs(f).sum()
+    h = oracle.nfft_adjoint(N, y, x, sigma, m)
+    hd = oracle.direct(1, -x, y, k.astype(float))           # sum_j y_j exp(+2 pi i k x_j)
+    assert np.abs(h - hd).max() <= _nfft_gate(N, sigma, m) * np.abs(y).sum()
+
+
+def test_nfft_pair_is_adjoint():
+    # the two fast maps are transposes of each other: <A f, y> = <f, A^H y>
+    for N, M, m in [(64, 300, 4), (128, 1000, 7)]:
+        x, f, y = _nfft_case(N, M, 7 * m)
+        lhs = np.vdot(y, oracle.nfft(N, f, x, 2.0, m))
+        rhs = np.vdot(oracle.nfft_adjoint(N, y, x, 2.0, m), f)
+        assert abs(lhs - rhs) <= 1e-13 * abs(lhs)
+
+
+def test_nfft_equispaced_nodes_is_a_dft():
+    N, m = 64, 8
+    x = np.arange(-N // 2, N // 2) / N
+    rng = _rng(3)
+    f = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    # y_j = sum_k f_k exp(-2 pi i k j / N): numpy's FFT after moving index -N/2 to 0
+    ref = np.fft.fftshift(np.fft.fft(np.fft.ifftshift(f)))
+    np.testing.assert_allclose(oracle.nfft(N, f, x, 2.0, m), ref, atol=1e-12 * np.abs(f).sum())
+    refa = np.fft.fftshift(np.fft.ifft(np.fft.ifftshift(f))) * N
+    np.testing.assert_allclose(oracle.nfft_adjoint(N, f, x, 2.0, m), refa, atol=1e-12 * np.abs(f).sum())
+
+
+def test_nfft_single_frequency_and_errors():
+    N, m = 32, 8
+    x = _rng(4).uniform(-0.5, 0.5, 50)
+    f = np.zeros(N, dtype=complex)
+    f[5 + N // 2] = 1.0
+    np.testing.assert_allclose(oracle.nfft(N, f, x, 2.0, m), np.exp(-2j * np.pi * 5 * x), atol=1e-13)
+    with pytest.raises(ValueError):
+        oracle.nfft(N, f, np.array([0.7]), 2.0, m)
+    with pytest.raises(ValueError):
+        oracle.nfft_params(33, 2.0, 4)
+
+
+def test_nfft_error_decays_exponentially_in_m():
+    N, M = 64, 400
+    x, f, _ = _nfft_case(N, M, 11)
+    yd = oracle.direct(N, np.arange(-N // 2, N // 2) / N, f, x)
+    errs = [np.abs(oracle.nfft(N, f, x, 2.0, m) - yd).max() / np.abs(f).sum() for m in (3, 4, 5, 6)]
+    for a, b in zip(errs, errs[1:]):
+        assert b < a / 30      # about exp(-2 pi sqrt(1/2)) = 1/85 per step of m
