@@ -54,6 +54,7 @@ extern "C" {
 
 typedef struct nnfft_plan_s *nnfft_plan_t;
 typedef struct sinc_plan_s *sinc_plan_t;
+typedef struct nnfft_plan_s *nfft_plan_t;   /* NFFT plans (nfft_plan); not valid for nnfft_exec */
 
 typedef enum {
     NNFFT_OK = 0,
@@ -176,6 +177,38 @@ nnfft_status nnfft_info(nnfft_plan_t p, nnfft_info_t *out);
 nnfft_status nnfft_profile_start(nnfft_plan_t p, int max_execs);
 nnfft_status nnfft_profile_stop(nnfft_plan_t p, double *stage_ms, int *nexecs);
 nnfft_status nnfft_destroy(nnfft_plan_t p);
+
+/*
+ * NFFT with equispaced frequencies: the special case v_k = k / N, k in I_N
+ * (M1 = N, f indexed k + N/2) of (1.2), named in Sec. 2 as the building block
+ * of the NNFFT and in Sec. 6 as the form one NNFFT of Algorithm 6.1 takes
+ * when its nodes are equispaced, and its adjoint:
+ *   nfft_exec     y_j = sum_{k in I_N} f_k exp(-2 pi i k x_j),   j in I_M
+ *   nfft_adjoint  h_k = sum_{j in I_M} y_j exp(+2 pi i k x_j),   k in I_N
+ * Steps (sinh-type window of Example 2.1, phi(t) = omega(n t / m)):
+ *   forward: f_k / (n phi_hat(k)) zero-padded to length n, a length-n FFT,
+ *            window interpolation at n x_j on the 1-periodic grid;
+ *   adjoint: window spreading of y_j at n x_j, folded 1-periodically, a
+ *            length-n transform with the + sign, division by n phi_hat(k).
+ * n is the smallest even 2,3,5-smooth integer >= sigma N; beta =
+ * 2 pi m (1 - N / (2 n)).  The two maps are exact transposes of each other.
+ * The same precisions as the NNFFT (FP32: m >= 4).  x[M]: FP64 device nodes in
+ * [-1/2, 1/2]; f, y, h: c64 (FP32) or c128 (FP64) device arrays, caller-owned.
+ * nnfft_info reports N1 = N2 = n.  NFFT plans cannot be batched.
+ * Errors: ARG (odd N, N < 2, sigma <= 1, m < 2, 2 m >= n, null arrays, an
+ * NNFFT plan given to nfft_exec or the reverse), DOMAIN, UNSUPPORTED (m > 16,
+ * FP32 with m < 4, n too long), NOMEM, DEVICE.
+ */
+nnfft_status nfft_plan(nfft_plan_t *out, int64_t N, int64_t M, double sigma, int m, nnfft_precision prec,
+                       const double *x, void *stream);
+nnfft_status nfft_exec(nfft_plan_t p, const void *f, void *y, void *stream);
+nnfft_status nfft_adjoint(nfft_plan_t p, const void *y, void *h, void *stream);
+nnfft_status nfft_destroy(nfft_plan_t p);
+
+/* Host-only dry run of nfft_plan on HOST nodes x[M], with the layout checks
+ * of nnfft_plan_dry_run.  No device work.  Errors: as nfft_plan. */
+nnfft_status nfft_plan_dry_run(int64_t N, int64_t M, double sigma, int m, nnfft_precision prec, const double *x,
+                               nnfft_info_t *out);
 
 /*
  * Layout tuning.  A plan sorts each node side into blocks of consecutive

@@ -126,6 +126,11 @@ def lib():
     L.nnfft_derive_params.argtypes = [i64, dbl, dbl, ci, ci, ctypes.POINTER(NnfftInfo)]
     L.nnfft_plan.argtypes = [ctypes.POINTER(vp), i64, i64, i64, dbl, dbl, ci, ci, ci, vp, vp, vp]
     L.nnfft_exec.argtypes = [vp, vp, vp, vp]
+    L.nfft_plan.argtypes = [ctypes.POINTER(vp), i64, i64, dbl, ci, ci, vp, vp]
+    L.nfft_exec.argtypes = [vp, vp, vp, vp]
+    L.nfft_adjoint.argtypes = [vp, vp, vp, vp]
+    L.nfft_destroy.argtypes = [vp]
+    L.nfft_plan_dry_run.argtypes = [i64, i64, dbl, ci, ci, ctypes.POINTER(dbl), ctypes.POINTER(NnfftInfo)]
     L.nnfft_plan_dry_run.argtypes = [i64, i64, i64, dbl, dbl, ci, ci, ci, ctypes.POINTER(dbl), ctypes.POINTER(dbl),
                                      ctypes.POINTER(NnfftInfo)]
     L.nnfft_exec_batch.argtypes = [ci, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
@@ -154,7 +159,8 @@ def lib():
     L.nnfft_server_destroy.argtypes = [vp]
     L.nnfft_last_error.restype = ctypes.c_char_p
     L.nnfft_version.restype = ctypes.c_char_p
-    for name in ["nnfft_plan_dry_run", "nnfft_profile_start", "nnfft_profile_stop", "nnfft_quadrature", "nnfft_derive_params",
+    for name in ["nfft_plan", "nfft_exec", "nfft_adjoint", "nfft_destroy", "nfft_plan_dry_run",
+                 "nnfft_plan_dry_run", "nnfft_profile_start", "nnfft_profile_stop", "nnfft_quadrature", "nnfft_derive_params",
                  "nnfft_plan", "nnfft_exec", "nnfft_exec_batch", "nnfft_info", "nnfft_destroy", "sinc_plan",
                  "sinc_exec", "sinc_info", "sinc_destroy", "nnfft_autotune", "nnfft_set_tuning",
                  "nnfft_get_tuning", "nnfft_clear_tuning", "nnfft_server_create", "nnfft_server_submit",
@@ -170,7 +176,7 @@ def header_functions():
     names = set()
     for h in HEADERS:
         src = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
-        names.update(re.findall(r"\b(nnfft_\w+|sinc_\w+)\s*\(", src))
+        names.update(re.findall(r"\b(nnfft_\w+|nfft_\w+|sinc_\w+)\s*\(", src))
     return sorted(names)
 
 
@@ -245,6 +251,88 @@ def nnfft_plan_dry_run(N, v, x, sigma1=2.0, sigma2=2.0, m1=6, m2=6, prec=NNFFT_F
     _check(lib().nnfft_plan_dry_run(int(N), v.size, x.size, float(sigma1), float(sigma2), int(m1), int(m2),
                                     int(prec), v.ctypes.data_as(dptr), x.ctypes.data_as(dptr), ctypes.byref(info)))
     return info.as_dict()
+
+
+def nfft_plan(N, x, sigma=2.0, m=6, prec=NNFFT_FP32_COMP, stream=None):
+    """NFFT plan for the nodes x (float64 CUDA tensor) and frequencies k in I_N."""
+    import torch
+    _require(x, torch.float64, x.numel(), "x")
+    h = ctypes.c_void_p()
+    _check(lib().nfft_plan(ctypes.byref(h), int(N), x.numel(), float(sigma), int(m), int(prec), _ptr(x),
+                           _stream(stream)))
+    return h
+
+
+def nfft_exec(plan, f, y, stream=None):
+    """y_j = sum_{k in I_N} f_k exp(-2 pi i k x_j)."""
+    info = nnfft_info(plan)
+    dt = _cdtype(info["precision"])
+    _require(f, dt, info["N"], "f")
+    _require(y, dt, info["M2"], "y")
+    _check(lib().nfft_exec(plan, _ptr(f), _ptr(y), _stream(stream)))
+
+
+def nfft_adjoint(plan, y, h, stream=None):
+    """h_k = sum_j y_j exp(+2 pi i k x_j), k in I_N."""
+    info = nnfft_info(plan)
+    dt = _cdtype(info["precision"])
+    _require(y, dt, info["M2"], "y")
+    _require(h, dt, info["N"], "h")
+    _check(lib().nfft_adjoint(plan, _ptr(y), _ptr(h), _stream(stream)))
+
+
+def nfft_destroy(plan):
+    _check(lib().nfft_destroy(plan))
+
+
+def nfft_plan_dry_run(N, x, sigma=2.0, m=6, prec=NNFFT_FP32_COMP) -> dict:
+    """Host-only NFFT plan construction and layout check on numpy float64 nodes."""
+    import numpy as np
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    info = NnfftInfo()
+    dptr = ctypes.POINTER(ctypes.c_double)
+    _check(lib().nfft_plan_dry_run(int(N), x.size, float(sigma), int(m), int(prec), x.ctypes.data_as(dptr),
+                                   ctypes.byref(info)))
+    return info.as_dict()
+
+
+class NfftPlan:
+    """Owning wrapper: NfftPlan(N, x, ...); forward(f) -> y; adjoint(y) -> h."""
+
+    def __init__(self, N, x, sigma=2.0, m=6, prec=NNFFT_FP32_COMP, stream=None):
+        self.handle = nfft_plan(N, x, sigma, m, prec, stream)
+        self.info = nnfft_info(self.handle)
+
+    def forward(self, f, y=None, stream=None):
+        import torch
+        if y is None:
+            y = torch.empty(self.info["M2"], dtype=_cdtype(self.info["precision"]), device=f.device)
+        nfft_exec(self.handle, f, y, stream)
+        return y
+
+    def adjoint(self, y, h=None, stream=None):
+        import torch
+        if h is None:
+            h = torch.empty(self.info["N"], dtype=_cdtype(self.info["precision"]), device=y.device)
+        nfft_adjoint(self.handle, y, h, stream)
+        return h
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            nfft_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 def nnfft_info(plan) -> dict:

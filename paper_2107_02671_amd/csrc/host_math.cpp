@@ -11,7 +11,6 @@ namespace nnfft {
 
 namespace {
 
-constexpr double kPi = 3.141592653589793238462643383279502884;
 
 int64_t ceil_with_slack(double x) { return (int64_t)std::ceil(x - 1e-9); }
 

@@ -9,6 +9,8 @@
 
 namespace nnfft {
 
+constexpr double kPi = 3.141592653589793238462643383279502884;
+
 // Sizes of Algorithm 2.2 (see nnfft_derive_params in nnfft.h for the readings).
 nnfft_status derive_params(int64_t N, double sigma1, double sigma2, int m1, int m2,
                            nnfft_info_t *out);

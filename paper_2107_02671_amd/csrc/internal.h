@@ -66,15 +66,21 @@ struct FftArgs {
     const void *partial;      // nplanes planes of G1 cells, then overflow windows
     const int32_t *merge_off; // [G1 + 1] CSR over grid cells of overflow partial indices
     const int32_t *merge_idx;
-    const double *deconv;     // [G1] 1 / (N1 N2 phi_hat_2(l)), l = cell - G1/2
+    const double *deconv;     // NNFFT: [G1] 1 / (N1 N2 phi_hat_2(l)), l = cell - G1/2;
+                              // NFFT: [N] 1 / (n phi_hat(k)), k + N/2
     const void *tw;           // [N2] exp(-2 pi i q / N2) (float2 or double2)
     void *Y;                  // [N2] four-step intermediate
-    void *hlin;               // [N2 + 1] h_s at index s + N2/2, consumed part only
+    void *hlin;               // [2 S + 1] h_s at index s + h_off for |s| <= S
+    const void *dense_in;     // mode 1: the NFFT coefficients f_k (set per exec)
+    void *dense_out;          // mode 2: the adjoint NFFT output h_k (set per exec)
     int32_t N2, G1;
     int32_t n1, n2;           // N2 = n1 * n2; n1 == 1: one workgroup does it all
     int32_t batchA, batchB;   // sub-transforms per workgroup in stage A / B
     int32_t threadsA, threadsB;
     int32_t S;                // outputs with |s| <= S are consumed by step 4
+    int32_t h_off;            // hlin index of label 0
+    int32_t mode;             // 0 NNFFT, 1 NFFT, 2 adjoint NFFT (see fft_input32)
+    int32_t Nout;             // NFFT: number of frequencies N
     int32_t npassA, npassB;
     int32_t nplanes;          // planes of spreading windows summed for every cell
     int8_t radA[kMaxPasses];  // radices of the length-n2 transform (or of N2)
@@ -97,6 +103,7 @@ struct InterpArgs {
     int32_t N2, ip_off;       // bin storage index = floor(u_j) + ip_off
     int32_t corr_deg;
     int32_t rows;             // FP32 path: record rows per slot
+    int32_t h_off, pad;       // hlin index of label 0
 };
 
 struct PlanDev {
@@ -123,6 +130,8 @@ struct BatchTable {
 // Kernel launchers (kernels.hip).  ev: null, or 4 events recorded before
 // spreading, after spreading, after the FFT and after interpolation.
 hipError_t launch_exec(const PlanDev &P, const void *f, void *y, hipStream_t s, hipEvent_t *ev);
+// NFFT plans: forward (in = f_k, out = y_j) or adjoint (in = y_j, out = h_k)
+hipError_t launch_nfft(const PlanDev &P, bool adjoint, const void *in, void *out, hipStream_t s);
 // n plans of one precision: host descriptors (sizes) and their device copies
 hipError_t launch_exec_batch(int n, const PlanDev *const *host, const PlanDev *const *dev,
                              const void *const *f, void *const *y, hipStream_t s);

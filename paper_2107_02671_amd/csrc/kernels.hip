@@ -434,7 +434,7 @@ __device__ __forceinline__ void interp32_slot(const InterpArgs &A, cx<float> *__
     const int lab = it.bin - A.ip_off;
     if (it.n > 0) {
         const float *__restrict__ Cs = A.C;   // same address in every lane: scalar loads
-        const cx<float> *h = reinterpret_cast<const cx<float> *>(A.hlin) + (lab - m + 1 + A.N2 / 2);
+        const cx<float> *h = reinterpret_cast<const cx<float> *>(A.hlin) + (lab - m + 1 + A.h_off);
         constexpr int KW = (D + kWaves32) / kWaves32;   // moments per wave (3)
         float ar[KW], ai[KW];
 #pragma unroll
@@ -542,7 +542,7 @@ __device__ void interp64_slot(const InterpArgs &A, cx<double> *__restrict__ y, i
     const cx<double> *h = reinterpret_cast<const cx<double> *>(A.hlin);
     if (t < ch.nbin && L.used[t]) {
         const int lab = ch.bin_lo + t - A.ip_off;
-        const int s0 = lab - m + 1 + A.N2 / 2;
+        const int s0 = lab - m + 1 + A.h_off;
         for (int r = 0; r < tm; ++r) L.hw[r * kItemsPerWg + t] = h[s0 + r];
     }
     __syncthreads();
@@ -578,13 +578,11 @@ __global__ __launch_bounds__(64) void k_interp64(InterpArgs A, cx<double> *__res
 
 // FFT input element q (index mod N2) = merged, deconvolved step-1 output:
 // label l = q (q < N2/2) or q - N2; zero outside I_{G1}.
-__device__ __forceinline__ cx<float> fft_input32(const FftArgs &A, int q)
+// Adds the partial sums of grid cell `cell` (its window planes, then the
+// overflow windows through their index lists) to the two-sum pairs.
+__device__ __forceinline__ void merge_cell32(const FftArgs &A, int cell, float &hr, float &hi, float &lr, float &li)
 {
-    const int lab = (q < A.N2 / 2) ? q : q - A.N2;
-    if (lab < -A.G1 / 2 || lab >= A.G1 / 2) return cxmk(0.f, 0.f);
-    const int cell = lab + A.G1 / 2;
     const float4 *part = reinterpret_cast<const float4 *>(A.partial);
-    float hr = 0.f, hi = 0.f, lr = 0.f, li = 0.f;
     const int e0 = A.merge_off[cell], e1 = A.merge_off[cell + 1];
     // the planes: fixed offsets s G1 + cell, all loads in flight together
     const int np = A.nplanes;
@@ -602,7 +600,7 @@ __device__ __forceinline__ cx<float> fft_input32(const FftArgs &A, int q)
             }
         }
     }
-    // overflow windows through their index lists: eight entries at a time
+    // overflow windows: eight entries at a time
     for (int e = e0; e < e1; e += 8) {
         int idx[8];
 #pragma unroll
@@ -620,17 +618,11 @@ __device__ __forceinline__ cx<float> fft_input32(const FftArgs &A, int q)
             }
         }
     }
-    const double sc = A.deconv[cell];
-    return cxmk((float)((double)(hr + lr) * sc), (float)((double)(hi + li) * sc));
 }
 
-__device__ __forceinline__ cx<double> fft_input64(const FftArgs &A, int q)
+__device__ __forceinline__ void merge_cell64(const FftArgs &A, int cell, double &ar, double &ai)
 {
-    const int lab = (q < A.N2 / 2) ? q : q - A.N2;
-    if (lab < -A.G1 / 2 || lab >= A.G1 / 2) return cxmk(0.0, 0.0);
-    const int cell = lab + A.G1 / 2;
     const double2 *part = reinterpret_cast<const double2 *>(A.partial);
-    double ar = 0.0, ai = 0.0;
     const int e1 = A.merge_off[cell + 1];
     const int np = A.nplanes;
     {
@@ -650,6 +642,59 @@ __device__ __forceinline__ cx<double> fft_input64(const FftArgs &A, int q)
         ar += v.x;
         ai += v.y;
     }
+}
+
+// FFT input element q (index mod N2):
+//  mode 0 (NNFFT steps 1-2): merged step-1 cell of label l = q or q - N2 (zero
+//    outside I_{G1}) times 1 / (N1 N2 phi_hat_2(l));
+//  mode 1 (NFFT): coefficient f_k, k = l in I_N, times 1 / (n phi_hat(k));
+//  mode 2 (adjoint NFFT): conjugate of the sum of the cells of labels l, l + n,
+//    l - n in the linear grid (the 1-periodic fold of the spread values).
+__device__ __forceinline__ cx<float> fft_input32(const FftArgs &A, int q)
+{
+    const int lab = (q < A.N2 / 2) ? q : q - A.N2;
+    if (A.mode == 1) {
+        if (lab < -A.Nout / 2 || lab >= A.Nout / 2) return cxmk(0.f, 0.f);
+        const cx<float> v = reinterpret_cast<const cx<float> *>(A.dense_in)[lab + A.Nout / 2];
+        const double sc = A.deconv[lab + A.Nout / 2];
+        return cxmk((float)((double)v.re * sc), (float)((double)v.im * sc));
+    }
+    float hr = 0.f, hi = 0.f, lr = 0.f, li = 0.f;
+    if (A.mode == 2) {
+#pragma unroll
+        for (int r = -1; r <= 1; ++r) {
+            const int cell = lab + r * A.N2 + A.G1 / 2;
+            if (cell >= 0 && cell < A.G1) merge_cell32(A, cell, hr, hi, lr, li);
+        }
+        return cxmk(hr + lr, -(hi + li));
+    }
+    if (lab < -A.G1 / 2 || lab >= A.G1 / 2) return cxmk(0.f, 0.f);
+    const int cell = lab + A.G1 / 2;
+    merge_cell32(A, cell, hr, hi, lr, li);
+    const double sc = A.deconv[cell];
+    return cxmk((float)((double)(hr + lr) * sc), (float)((double)(hi + li) * sc));
+}
+
+__device__ __forceinline__ cx<double> fft_input64(const FftArgs &A, int q)
+{
+    const int lab = (q < A.N2 / 2) ? q : q - A.N2;
+    if (A.mode == 1) {
+        if (lab < -A.Nout / 2 || lab >= A.Nout / 2) return cxmk(0.0, 0.0);
+        const cx<double> v = reinterpret_cast<const cx<double> *>(A.dense_in)[lab + A.Nout / 2];
+        return scal(v, A.deconv[lab + A.Nout / 2]);
+    }
+    double ar = 0.0, ai = 0.0;
+    if (A.mode == 2) {
+#pragma unroll
+        for (int r = -1; r <= 1; ++r) {
+            const int cell = lab + r * A.N2 + A.G1 / 2;
+            if (cell >= 0 && cell < A.G1) merge_cell64(A, cell, ar, ai);
+        }
+        return cxmk(ar, -ai);
+    }
+    if (lab < -A.G1 / 2 || lab >= A.G1 / 2) return cxmk(0.0, 0.0);
+    const int cell = lab + A.G1 / 2;
+    merge_cell64(A, cell, ar, ai);
     const double sc = A.deconv[cell];
     return cxmk(ar * sc, ai * sc);
 }
@@ -804,11 +849,23 @@ __device__ cx<T> *stockham(cx<T> *buf0, cx<T> *buf1, int Lsub, int B, const int8
 template <typename T>
 __device__ __forceinline__ void fft_store(const FftArgs &A, int k, cx<T> v)
 {
-    cx<T> *h = reinterpret_cast<cx<T> *>(A.hlin);
     const int half = A.N2 / 2;
     const int s = (k < half) ? k : k - A.N2;
-    if (s >= -A.S && s <= A.S) h[s + half] = v;
-    if (k == half && half <= A.S) h[A.N2] = v;   // label +N2/2 equals label -N2/2
+    if (A.mode == 2) {
+        // adjoint NFFT: h_k = conj(X_k) / (n phi_hat(k)) for k in I_N, dense output
+        if (s >= -A.Nout / 2 && s < A.Nout / 2) {
+            const double sc = A.deconv[s + A.Nout / 2];
+            reinterpret_cast<cx<T> *>(A.dense_out)[s + A.Nout / 2] =
+                cxmk((T)((double)v.re * sc), (T)(-(double)v.im * sc));
+        }
+        return;
+    }
+    // labels s, s + N2, s - N2 that the interpolation reads (|label| <= S),
+    // stored at label + h_off: the 1-periodic extension of the transform
+    cx<T> *h = reinterpret_cast<cx<T> *>(A.hlin);
+    if (s >= -A.S && s <= A.S) h[s + A.h_off] = v;
+    if (s + A.N2 <= A.S) h[s + A.N2 + A.h_off] = v;
+    if (s - A.N2 >= -A.S) h[s - A.N2 + A.h_off] = v;
 }
 
 // LDS of an FFT workgroup, sized at launch (dynamic shared memory) for the
@@ -1170,6 +1227,45 @@ hipError_t launch_exec_batch(int n, const PlanDev *const *host, const PlanDev *c
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+// NFFT with equispaced frequencies: forward = FFT (deconvolved coefficients
+// in the load) + interpolation; adjoint = spreading + FFT (periodic fold and
+// conjugation in the load, conjugation and deconvolution in the store).
+hipError_t launch_nfft(const PlanDev &P, bool adjoint, const void *in, void *out, hipStream_t s)
+{
+    FftArgs F = P.fft;
+    if (!adjoint) {
+        F.mode = 1;
+        F.dense_in = in;
+    } else {
+        F.mode = 2;
+        F.dense_out = out;
+    }
+    if (P.prec == NNFFT_FP32_COMP) {
+        if (adjoint) {
+            const cx<float> *yin = reinterpret_cast<const cx<float> *>(in);
+            if (2 * P.sp.m <= 16)
+                hipLaunchKernelGGL((k_spread32<16>), dim3(P.sp.ngrid), dim3(kThreads32), 0, s, P.sp, yin);
+            else
+                hipLaunchKernelGGL((k_spread32<32>), dim3(P.sp.ngrid), dim3(kThreads32), 0, s, P.sp, yin);
+            launch_fft<float>(F, s);
+        } else {
+            launch_fft<float>(F, s);
+            launch_interp32(corr_variant(P.ip.corr_deg), P.ip.ngrid, s, P.ip, reinterpret_cast<cx<float> *>(out));
+        }
+    } else {
+        if (adjoint) {
+            hipLaunchKernelGGL(k_spread64, dim3(P.sp.ngrid), dim3(kItemsPerWg), lds64_bytes(2 * P.sp.m), s, P.sp,
+                               reinterpret_cast<const cx<double> *>(in));
+            launch_fft<double>(F, s);
+        } else {
+            launch_fft<double>(F, s);
+            hipLaunchKernelGGL(k_interp64, dim3(P.ip.ngrid), dim3(kItemsPerWg), lds64_bytes(2 * P.ip.m), s, P.ip,
+                               reinterpret_cast<cx<double> *>(out));
+        }
+    }
+    return hipGetLastError();
 }
 
 // ===========================================================================

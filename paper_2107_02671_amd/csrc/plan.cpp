@@ -402,11 +402,15 @@ void layout_plan(const HostPlan &H, Carver &C, PlanDev &D, size_t *upload_end, P
     SA.partial = C.scratch((size_t)H.sp.part_cells * 16);
     FA.partial = SA.partial;
     FA.Y = C.scratch((size_t)P.N2 * csz);
-    FA.hlin = C.scratch((size_t)(P.N2 + 1) * csz);
+    FA.hlin = C.scratch((size_t)H.hlin_len * csz);
     IA.hlin = FA.hlin;
     FA.N2 = (int32_t)P.N2;
     FA.G1 = (int32_t)P.G1;
     FA.nplanes = H.sp.nplanes;
+    FA.h_off = H.h_off;
+    FA.mode = 0;
+    FA.Nout = H.kind == 1 ? (int32_t)P.N : 0;
+    IA.h_off = H.h_off;
     SA.rows = H.lay1.Q;
     IA.rows = H.lay2.Q;
     FA.n1 = H.fd.n1;
@@ -423,6 +427,103 @@ void layout_plan(const HostPlan &H, Carver &C, PlanDev &D, size_t *upload_end, P
         FA.radB[i] = (int8_t)H.fd.radB[i];
     }
     *ddesc = static_cast<PlanDev *>(C.scratch(sizeof(PlanDev)));   // the descriptor's device copy
+}
+
+// Merge lists of the overflow windows (those without a plane).
+static nnfft_status build_merge_lists(HostPlan &H, const nnfft_info_t &P, int m1)
+{
+    // merge lists of the overflow windows (those without a plane): for each
+    // grid cell the partial cells of the overflow chunks covering it
+    const int64_t plane_cells = (int64_t)H.sp.nplanes * P.G1;
+    H.moff.assign(P.G1 + 1, 0);
+    for (const Chunk &c : H.sp.chunks) {
+        if (c.part_off < plane_cells) continue;
+        const int W = c.nbin + 2 * m1 - 1;
+        for (int w = 0; w < W; ++w) {
+            const int64_t cell = (int64_t)c.bin_lo - m1 + 1 + w;
+            if (cell < 0 || cell >= P.G1) return fail(NNFFT_ERR_ARG, "internal: window outside the grid");
+            H.moff[cell + 1]++;
+        }
+    }
+    for (int64_t c = 0; c < P.G1; ++c) H.moff[c + 1] += H.moff[c];
+    H.midx.resize(H.moff[P.G1]);
+    {
+        std::vector<int32_t> cur(H.moff.begin(), H.moff.end() - 1);
+        for (const Chunk &c : H.sp.chunks) {
+            if (c.part_off < plane_cells) continue;
+            const int W = c.nbin + 2 * m1 - 1;
+            for (int w = 0; w < W; ++w) {
+                const int64_t cell = (int64_t)c.bin_lo - m1 + 1 + w;
+                H.midx[cur[cell]++] = c.part_off + w;
+            }
+        }
+    }
+
+    return NNFFT_OK;
+}
+
+// FFT factorization of the length-N2 transform; outputs |s| <= S are stored.
+static nnfft_status plan_fft(HostPlan &H, const nnfft_info_t &P, bool fp32, int64_t S)
+{
+    // FFT factorization -----------------------------------------------------
+    FftPlan &fd = H.fd;
+    fd = FftPlan{};
+    fd.N2 = (int32_t)P.N2;
+    // one workgroup for short transforms; longer ones as two launches of
+    // many workgroups (one or two columns each) so that the partial merge in
+    // the first stage's load runs with enough workgroups in flight
+    const int64_t single_max = 1024;
+    const int kvals = fp32 ? 4096 : 2048;   // values per FFT workgroup (LDS)
+    auto threads_for = [](int64_t vals) {
+        int64_t t = (vals + 63) / 64 * 64;
+        return (int32_t)std::max<int64_t>(64, std::min<int64_t>(256, t));
+    };
+    if (P.N2 <= single_max) {
+        const std::vector<int> r = radix_passes(P.N2);
+        if (r.empty() || (int)r.size() > kMaxPasses) return fail(NNFFT_ERR_UNSUPPORTED, "FFT length not 2,3,5-smooth");
+        fd.n1 = 1;
+        fd.n2 = (int32_t)P.N2;
+        fd.npassA = (int32_t)r.size();
+        std::copy(r.begin(), r.end(), fd.radA);
+        fd.threadsA = 256;
+    } else {
+        int64_t n1, n2;
+        if (!fft_factor(P.N2, kvals, n1, n2)) return fail(NNFFT_ERR_UNSUPPORTED, "FFT length cannot be split");
+        const std::vector<int> rA = radix_passes(n2), rB = radix_passes(n1);
+        if (rA.empty() || rB.empty() || (int)rA.size() > kMaxPasses || (int)rB.size() > kMaxPasses)
+            return fail(NNFFT_ERR_UNSUPPORTED, "FFT length not 2,3,5-smooth");
+        fd.n1 = (int32_t)n1;
+        fd.n2 = (int32_t)n2;
+        fd.npassA = (int32_t)rA.size();
+        fd.npassB = (int32_t)rB.size();
+        std::copy(rA.begin(), rA.end(), fd.radA);
+        std::copy(rB.begin(), rB.end(), fd.radB);
+        fd.batchA = (int32_t)std::max<int64_t>(1, std::min<int64_t>(n1 / 128, kvals / n2));
+        fd.batchB = (int32_t)std::max<int64_t>(1, std::min<int64_t>(n2 / 128, kvals / n1));
+        fd.threadsA = threads_for((int64_t)fd.batchA * n2);
+        fd.threadsB = threads_for((int64_t)fd.batchB * n1);
+    }
+    fd.S = (int32_t)S;
+
+    return NNFFT_OK;
+}
+
+// Device block size and the layout figures of the info struct.
+static void size_plan(HostPlan &H, const nnfft_info_t &P)
+{
+    PlanDev D, *dd = nullptr;
+    Carver C(0, nullptr);
+    size_t upload_end = 0;
+    H.info = P;
+    layout_plan(H, C, D, &upload_end, &dd);
+    H.total_bytes = C.off;
+    H.info.device_bytes = (int64_t)C.off;
+    H.info.block_points = H.lay1.block;
+    H.info.items_points = H.lay1.Q;
+    H.info.spread_workgroups = D.sp.ngrid;
+    H.info.interp_workgroups = D.ip.ngrid;
+    H.info.fft_n1 = H.fd.n1;
+    H.info.fft_n2 = H.fd.n2;
 }
 
 nnfft_status plan_host(HostPlan &H, int64_t N, int64_t M1, int64_t M2, double sigma1, double sigma2,
@@ -508,91 +609,104 @@ nnfft_status plan_host(HostPlan &H, int64_t N, int64_t M1, int64_t M2, double si
     std::vector<PtRec>().swap(H.sp.rec32);
     std::vector<PtRec>().swap(H.ip.rec32);
 
-    // merge lists of the overflow windows (those without a plane): for each
-    // grid cell the partial cells of the overflow chunks covering it
-    const int64_t plane_cells = (int64_t)H.sp.nplanes * P.G1;
-    H.moff.assign(P.G1 + 1, 0);
-    for (const Chunk &c : H.sp.chunks) {
-        if (c.part_off < plane_cells) continue;
-        const int W = c.nbin + 2 * m1 - 1;
-        for (int w = 0; w < W; ++w) {
-            const int64_t cell = (int64_t)c.bin_lo - m1 + 1 + w;
-            if (cell < 0 || cell >= P.G1) return fail(NNFFT_ERR_ARG, "internal: window outside the grid");
-            H.moff[cell + 1]++;
-        }
-    }
-    for (int64_t c = 0; c < P.G1; ++c) H.moff[c + 1] += H.moff[c];
-    H.midx.resize(H.moff[P.G1]);
-    {
-        std::vector<int32_t> cur(H.moff.begin(), H.moff.end() - 1);
-        for (const Chunk &c : H.sp.chunks) {
-            if (c.part_off < plane_cells) continue;
-            const int W = c.nbin + 2 * m1 - 1;
-            for (int w = 0; w < W; ++w) {
-                const int64_t cell = (int64_t)c.bin_lo - m1 + 1 + w;
-                H.midx[cur[cell]++] = c.part_off + w;
-            }
-        }
-    }
-
-    // FFT factorization -----------------------------------------------------
-    FftPlan &fd = H.fd;
-    fd = FftPlan{};
-    fd.N2 = (int32_t)P.N2;
-    // one workgroup for short transforms; longer ones as two launches of
-    // many workgroups (one or two columns each) so that the partial merge in
-    // the first stage's load runs with enough workgroups in flight
-    const int64_t single_max = 1024;
-    const int kvals = fp32 ? 4096 : 2048;   // values per FFT workgroup (LDS)
-    auto threads_for = [](int64_t vals) {
-        int64_t t = (vals + 63) / 64 * 64;
-        return (int32_t)std::max<int64_t>(64, std::min<int64_t>(256, t));
-    };
-    if (P.N2 <= single_max) {
-        const std::vector<int> r = radix_passes(P.N2);
-        if (r.empty() || (int)r.size() > kMaxPasses) return fail(NNFFT_ERR_UNSUPPORTED, "FFT length not 2,3,5-smooth");
-        fd.n1 = 1;
-        fd.n2 = (int32_t)P.N2;
-        fd.npassA = (int32_t)r.size();
-        std::copy(r.begin(), r.end(), fd.radA);
-        fd.threadsA = 256;
-    } else {
-        int64_t n1, n2;
-        if (!fft_factor(P.N2, kvals, n1, n2)) return fail(NNFFT_ERR_UNSUPPORTED, "FFT length cannot be split");
-        const std::vector<int> rA = radix_passes(n2), rB = radix_passes(n1);
-        if (rA.empty() || rB.empty() || (int)rA.size() > kMaxPasses || (int)rB.size() > kMaxPasses)
-            return fail(NNFFT_ERR_UNSUPPORTED, "FFT length not 2,3,5-smooth");
-        fd.n1 = (int32_t)n1;
-        fd.n2 = (int32_t)n2;
-        fd.npassA = (int32_t)rA.size();
-        fd.npassB = (int32_t)rB.size();
-        std::copy(rA.begin(), rA.end(), fd.radA);
-        std::copy(rB.begin(), rB.end(), fd.radB);
-        fd.batchA = (int32_t)std::max<int64_t>(1, std::min<int64_t>(n1 / 128, kvals / n2));
-        fd.batchB = (int32_t)std::max<int64_t>(1, std::min<int64_t>(n2 / 128, kvals / n1));
-        fd.threadsA = threads_for((int64_t)fd.batchA * n2);
-        fd.threadsB = threads_for((int64_t)fd.batchB * n1);
-    }
+    st = build_merge_lists(H, P, m1);
+    if (st != NNFFT_OK) return st;
     {
         const double U = (double)P.N2 * (double)P.N_star / (2.0 * (double)P.N1);
-        const int64_t S = (int64_t)std::ceil(U) + m2;
-        fd.S = (int32_t)std::min<int64_t>(S, P.N2 / 2);
+        const int64_t S = std::min<int64_t>((int64_t)std::ceil(U) + m2, P.N2 / 2);
+        st = plan_fft(H, P, fp32, S);
+        if (st != NNFFT_OK) return st;
     }
+    H.hlin_len = P.N2 + 1;
+    H.h_off = P.N2 / 2;
+    size_plan(H, P);
+    return NNFFT_OK;
+}
 
-    // device block size -------------------------------------------------------
-    PlanDev D, *dd = nullptr;
-    Carver C(0, nullptr);
-    size_t upload_end = 0;
-    H.info = P;
-    layout_plan(H, C, D, &upload_end, &dd);
-    H.total_bytes = C.off;
-    H.info.device_bytes = (int64_t)C.off;
-    H.info.block_points = H.lay1.block;
-    H.info.items_points = H.lay1.Q;
-    H.info.spread_workgroups = D.sp.ngrid;
-    H.info.interp_workgroups = D.ip.ngrid;
-    H.info.fft_n1 = fd.n1;
-    H.info.fft_n2 = fd.n2;
+nnfft_status nfft_plan_host(HostPlan &H, int64_t N, int64_t M, double sigma, int m, nnfft_precision prec,
+                            const std::vector<double> &x)
+{
+    if (N < 2 || (N % 2)) return fail(NNFFT_ERR_ARG, "the NFFT needs an even N >= 2");
+    if (M < 1 || M > ((int64_t)1 << 30)) return fail(NNFFT_ERR_ARG, "node count must be in [1, 2^30]");
+    if (!(sigma > 1.0) || m < 2) return fail(NNFFT_ERR_ARG, "sigma > 1 and m >= 2 are required");
+    if (prec != NNFFT_FP64_PLAIN && prec != NNFFT_FP32_COMP) return fail(NNFFT_ERR_ARG, "unknown precision");
+    if ((int64_t)x.size() != M) return fail(NNFFT_ERR_ARG, "node array size");
+    if (m > kMaxM) return fail(NNFFT_ERR_UNSUPPORTED, "m > 16 is not implemented");
+    const bool fp32 = (prec == NNFFT_FP32_COMP);
+    if (fp32 && m < 4)
+        return fail(NNFFT_ERR_UNSUPPORTED, "the FP32 path needs m >= 4 (its window polynomials "
+                                           "cannot reach FP32 accuracy for smaller m)");
+    for (int64_t j = 0; j < M; ++j)
+        if (!(std::fabs(x[j]) <= 0.5)) return fail(NNFFT_ERR_DOMAIN, "node outside [-1/2, 1/2]");
+    // oversampled length: the smallest even 2,3,5-smooth integer >= sigma N
+    int64_t n = (int64_t)std::ceil(sigma * (double)N - 1e-9);
+    if (n % 2) ++n;
+    while (radix_passes(n).empty()) n += 2;
+    if (2 * m >= n) return fail(NNFFT_ERR_ARG, "2 m must be smaller than the oversampled length");
+    if (n > ((int64_t)1 << (fp32 ? 24 : 22)))
+        return fail(NNFFT_ERR_UNSUPPORTED, "FFT longer than 2^24 (FP32) or 2^22 (FP64)");
+
+    nnfft_info_t P{};
+    P.N = N;
+    P.N_star = N;
+    P.N1 = n;
+    P.G1 = n + 2 * m + 2;   // linear spreading grid: labels [-G1/2, G1/2) hold every window
+    P.N2 = n;
+    P.M1 = M;
+    P.M2 = M;
+    P.m1 = P.m2 = m;
+    P.precision = prec;
+    P.sigma1 = P.sigma2 = sigma;
+    P.sigma1_eff = P.sigma2_eff = (double)n / (double)N;
+    P.a = (double)P.G1 / (double)n;
+    P.beta1 = P.beta2 = 2.0 * kPi * m * (1.0 - (double)N / (2.0 * (double)n));
+    P.thm41_applies = 0;
+    H.kind = 1;
+    H.fp32 = fp32;
+    if (fp32) {
+        double e = 0.0;
+        const std::vector<double> c = fit_window_taps(m, P.beta1, kDeg, &e);
+        P.window_degree = kDeg;
+        P.window_fit_err = e;
+        if (e > 5e-8) return fail(NNFFT_ERR_UNSUPPORTED, "window polynomial misses FP32 accuracy for these sigma, m");
+        H.C1.assign(c.begin(), c.end());
+        H.C2 = H.C1;
+    }
+    // no correction after the interpolation: the series of the constant 1
+    H.corr.assign(fp32 ? kCorr32 + 1 : 1, 0.0);
+    H.corr[0] = 1.0;
+    P.corr_degree = 0;
+    P.corr_fit_err = 0.0;
+    // 1 / (n phi_hat(k)) = 1 / (m omega_hat(m k / n)), k in I_N
+    H.deconv.resize(N);
+    for (int64_t k = -N / 2; k < N / 2; ++k)
+        H.deconv[k + N / 2] = 1.0 / ((double)m * window_sinh_hat((double)m * (double)k / (double)n, P.beta1));
+    H.tw64 = twiddles(n);
+    if (fp32) {
+        H.tw32.assign(H.tw64.begin(), H.tw64.end());
+        H.tw64.clear();
+    }
+    H.lay1 = choose_layout(M, fp32);
+    H.lay2 = H.lay1;
+    std::string err;
+    // spreading (adjoint): t_j = n x_j in the linear grid; interpolation (forward): u_j = n x_j
+    if (!build_side(x, (double)n, P.G1 / 2, P.G1, H.lay1, fp32, m, H.sp, err)) return fail(NNFFT_ERR_ARG, err);
+    if (!build_side(x, (double)n, n / 2, n + 1, H.lay2, fp32, 0, H.ip, err)) return fail(NNFFT_ERR_ARG, err);
+    if (H.sp.part_cells >= ((int64_t)1 << 31)) return fail(NNFFT_ERR_UNSUPPORTED, "too many partial cells");
+    if (fp32) {
+        std::vector<int32_t>().swap(H.sp.perm);
+        std::vector<int32_t>().swap(H.ip.perm);
+    }
+    std::vector<PtRec>().swap(H.sp.rec32);
+    std::vector<PtRec>().swap(H.ip.rec32);
+    nnfft_status st = build_merge_lists(H, P, m);
+    if (st != NNFFT_OK) return st;
+    // the interpolation reads labels |s| <= n/2 + m: the periodic extension
+    st = plan_fft(H, P, fp32, n / 2 + m);
+    if (st != NNFFT_OK) return st;
+    H.hlin_len = n + 2 * m + 1;
+    H.h_off = (int32_t)(n / 2 + m);
+    size_plan(H, P);
     return NNFFT_OK;
 }
 
@@ -683,6 +797,7 @@ nnfft_status plan_create(const HostPlan &H, const DevMem &mem, hipStream_t s, nn
     pl->base = base;
     pl->mem = mem;
     pl->info = H.info;
+    pl->kind = H.kind;
     try {
         std::vector<char> stage;
         Carver C((uintptr_t)base, &stage);
@@ -859,9 +974,29 @@ nnfft_status nnfft_plan_dry_run(int64_t N, int64_t M1, int64_t M2, double sigma1
     }
 }
 
+nnfft_status nfft_plan_dry_run(int64_t N, int64_t M, double sigma, int m, nnfft_precision prec, const double *x,
+                               nnfft_info_t *out)
+{
+    if (!x || !out) return fail(NNFFT_ERR_ARG, "null argument");
+    if (M < 1 || M > ((int64_t)1 << 30)) return fail(NNFFT_ERR_ARG, "node count must be in [1, 2^30]");
+    try {
+        std::vector<double> hx(x, x + M);
+        HostPlan H;
+        nnfft_status st = nfft_plan_host(H, N, M, sigma, m, prec, hx);
+        if (st != NNFFT_OK) return st;
+        st = check_plan(H, hx, hx);
+        if (st != NNFFT_OK) return st;
+        *out = H.info;
+        return NNFFT_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(NNFFT_ERR_NOMEM, "host allocation failed");
+    }
+}
+
 nnfft_status nnfft_exec(nnfft_plan_t p, const void *f, void *y, void *stream)
 {
     if (!p || !f || !y) return fail(NNFFT_ERR_ARG, "null argument");
+    if (p->kind != 0) return fail(NNFFT_ERR_ARG, "an NFFT plan: use nfft_exec or nfft_adjoint");
     hipEvent_t *ev = nullptr;
     if (p->prof_used < p->prof_max) ev = &p->prof_ev[4 * (size_t)p->prof_used++];
     const hipError_t e = launch_exec(p->desc, f, y, static_cast<hipStream_t>(stream), ev);
@@ -878,6 +1013,7 @@ nnfft_status nnfft_exec_batch(int n, const nnfft_plan_t *plans, const void *cons
         seen.reserve(n);
         for (int i = 0; i < n; ++i) {
             if (!plans[i] || !f[i] || !y[i]) return fail(NNFFT_ERR_ARG, "null plan or array in the batch");
+            if (plans[i]->kind != 0) return fail(NNFFT_ERR_ARG, "NFFT plans cannot be batched");
             seen.push_back(plans[i]);
         }
         std::sort(seen.begin(), seen.end());
@@ -959,6 +1095,57 @@ nnfft_status nnfft_profile_stop(nnfft_plan_t p, double *stage_ms, int *nexecs)
 nnfft_status nnfft_destroy(nnfft_plan_t p)
 {
     if (!p) return fail(NNFFT_ERR_ARG, "null plan");
+    delete p;
+    return NNFFT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// NFFT with equispaced frequencies
+// ---------------------------------------------------------------------------
+nnfft_status nfft_plan(nfft_plan_t *out, int64_t N, int64_t M, double sigma, int m, nnfft_precision prec,
+                       const double *x, void *stream)
+{
+    if (!out) return fail(NNFFT_ERR_ARG, "null plan pointer");
+    *out = nullptr;
+    if (!x) return fail(NNFFT_ERR_ARG, "null node array");
+    if (M < 1 || M > ((int64_t)1 << 30)) return fail(NNFFT_ERR_ARG, "node count must be in [1, 2^30]");
+    try {
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        std::vector<double> hx;
+        nnfft_status st = copy_nodes(x, M, hx, s);
+        if (st != NNFFT_OK) return st;
+        HostPlan H;
+        st = nfft_plan_host(H, N, M, sigma, m, prec, hx);
+        if (st != NNFFT_OK) return st;
+        return plan_create(H, hip_mem(), s, out);
+    } catch (const std::bad_alloc &) {
+        return fail(NNFFT_ERR_NOMEM, "host allocation failed");
+    }
+}
+
+static nnfft_status nfft_run(nfft_plan_t p, bool adjoint, const void *in, void *out, void *stream)
+{
+    if (!p || !in || !out) return fail(NNFFT_ERR_ARG, "null argument");
+    if (p->kind != 1) return fail(NNFFT_ERR_ARG, "not an NFFT plan");
+    const hipError_t e = launch_nfft(p->desc, adjoint, in, out, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return fail(NNFFT_ERR_DEVICE, std::string("launch: ") + hipGetErrorString(e));
+    return NNFFT_OK;
+}
+
+nnfft_status nfft_exec(nfft_plan_t p, const void *f, void *y, void *stream)
+{
+    return nfft_run(p, false, f, y, stream);
+}
+
+nnfft_status nfft_adjoint(nfft_plan_t p, const void *y, void *h, void *stream)
+{
+    return nfft_run(p, true, y, h, stream);
+}
+
+nnfft_status nfft_destroy(nfft_plan_t p)
+{
+    if (!p) return fail(NNFFT_ERR_ARG, "null plan");
+    if (p->kind != 1) return fail(NNFFT_ERR_ARG, "not an NFFT plan");
     delete p;
     return NNFFT_OK;
 }

@@ -69,6 +69,9 @@ struct HostPlan {
     std::vector<float> tw32;
     std::vector<int32_t> moff, midx;   // merge lists of the spreading windows
     FftPlan fd{};
+    int kind = 0;                      // 0 NNFFT, 1 NFFT with equispaced frequencies
+    int64_t hlin_len = 0;              // FFT outputs kept for the interpolation
+    int32_t h_off = 0;                 // their index of label 0
     size_t total_bytes = 0;            // device bytes of the plan (one block)
 };
 
@@ -84,6 +87,7 @@ const DevMem &hip_mem();                       // hipMalloc / hipFree
 
 // Public handles (opaque in nnfft.h).
 struct nnfft_plan_s {
+    int kind = 0;                      // 0 NNFFT (nnfft_plan), 1 NFFT (nfft_plan)
     nnfft_info_t info{};
     nnfft::PlanDev desc{};
     nnfft::PlanDev *ddesc = nullptr;   // device copy of desc (batched launches)
@@ -115,6 +119,11 @@ nnfft_status plan_host(HostPlan &H, int64_t N, int64_t M1, int64_t M2, double si
                        int m1, int m2, nnfft_precision prec, const std::vector<double> &v,
                        const std::vector<double> &x, const Layout *lay1 = nullptr,
                        const Layout *lay2 = nullptr);
+
+// NFFT with equispaced frequencies k in I_N at nodes x[M] (host copies):
+// the same layout machinery with one node set on both sides.
+nnfft_status nfft_plan_host(HostPlan &H, int64_t N, int64_t M, double sigma, int m, nnfft_precision prec,
+                            const std::vector<double> &x);
 
 // Allocates H.total_bytes from mem, uploads (one copy, synchronizes s) and
 // returns the handle, which releases the block to mem when destroyed.

@@ -1,0 +1,103 @@
+"""GPU parity of the NFFT with equispaced frequencies and its adjoint (the
+special case v_k = k/N of (1.2); Sec. 2 and the equispaced cases of Sec. 6)
+against the FP64 oracle's NFFT steps and the direct sums.
+
+Tolerance (E_inf against max |oracle|): 1e-12 (FP64) or 1e-5 (FP32) times
+max(1, kappa / 4.62), kappa = omega_hat(0) / omega_hat(m N / (2 n)): the
+deconvolution amplifies the rounding of the length-n transform by up to kappa
+at the band edge (kappa = 4.62 at sigma = 2, m = 6; 9.5e3 at sigma = 1.25,
+m = 10, where the GPU and oracle FP64 results differ by 6e-12)."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2107_02671_amd as P
+from paper_2107_02671_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FP64, FP32 = P.NNFFT_FP64_PLAIN, P.NNFFT_FP32_COMP
+DEV = "cuda:0"
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def tol(prec, N, sigma, m):
+    n, beta = oracle.nfft_params(N, sigma, m)
+    kappa = oracle.omega_hat(0.0, beta) / oracle.omega_hat(m * N / (2.0 * n), beta)
+    return (1e-12 if prec == FP64 else 1e-5) * max(1.0, float(kappa) / 4.62)
+
+
+def einf(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+CASES = [
+    # N, M, sigma, m
+    (64, 300, 2.0, 6),
+    (128, 5000, 2.0, 8),
+    (1000, 40000, 2.0, 6),     # n = 2000: four-step FFT
+    (4096, 1 << 17, 2.0, 6),
+    (500, 777, 1.5, 5),
+    (2048, 30000, 1.25, 10),
+]
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"N{c[0]}-M{c[1]}-s{c[2]}-m{c[3]}")
+def test_nfft_parity(case, prec):
+    N, M, sigma, m = case
+    g = W.rng(N + M + m)
+    x = W.uniform_nodes(g, M)
+    x[:3] = [-0.5, 0.5, 0.0]
+    f = W.complex_gaussian(g, N)
+    yv = W.complex_gaussian(g, M)
+    cdt = torch.complex64 if prec == FP32 else torch.complex128
+    _say(f"[gpu] nfft N={N} M={M} sigma={sigma} m={m} prec={prec}")
+    with P.NfftPlan(N, torch.tensor(x, device=DEV), sigma, m, prec) as pl:
+        y = pl.forward(torch.tensor(f, dtype=cdt, device=DEV)).cpu().numpy().astype(np.complex128)
+        h = pl.adjoint(torch.tensor(yv, dtype=cdt, device=DEV)).cpu().numpy().astype(np.complex128)
+        info = pl.info
+    yo = oracle.nfft(N, f, x, sigma, m)
+    ho = oracle.nfft_adjoint(N, yv, x, sigma, m)
+    t = tol(prec, N, sigma, m)
+    ef, ea = einf(y, yo), einf(h, ho)
+    _say(f"    n={info['N2']} fft=({info['fft_n1']},{info['fft_n2']}): E_inf forward {ef:.3e}, adjoint {ea:.3e} (tol {t:.2e})")
+    assert ef <= t and ea <= t
+    # the pair is adjoint: <A f, y> = <f, A^H y>
+    lhs, rhs = np.vdot(yv, y), np.vdot(h, f)
+    assert abs(lhs - rhs) <= max(t, 1e-12) * abs(lhs) * 10
+    # sampled outputs against the direct sums
+    idx = W.rng(5).choice(M, min(M, 64), replace=False)
+    k = np.arange(-N // 2, N // 2)
+    yd = oracle.direct(N, k / N, f, x[idx])
+    assert np.abs(y[idx] - yd).max() <= max(t, 1e-6) * np.abs(yd).max()
+
+
+def test_nfft_plan_errors():
+    _say("[gpu] nfft plan errors")
+    x = torch.tensor([0.1, -0.2], dtype=torch.float64, device=DEV)
+    with pytest.raises(P.NnfftError) as e:
+        P.nfft_plan(63, x, 2.0, 6, FP64)
+    assert e.value.status == P.binding.NNFFT_ERR_ARG
+    with pytest.raises(P.NnfftError) as e:
+        P.nfft_plan(64, torch.tensor([0.7], dtype=torch.float64, device=DEV), 2.0, 6, FP64)
+    assert e.value.status == P.binding.NNFFT_ERR_DOMAIN
+    with P.NfftPlan(64, x, 2.0, 6, FP64) as pl:
+        f = torch.zeros(64, dtype=torch.complex128, device=DEV)
+        y = torch.zeros(2, dtype=torch.complex128, device=DEV)
+        with pytest.raises(P.NnfftError) as e:       # an NFFT plan is not an NNFFT plan
+            P.binding._check(P.binding.lib().nnfft_exec(pl.handle, P.binding._ptr(f), P.binding._ptr(y),
+                                                        P.binding._stream(None)))
+        assert e.value.status == P.binding.NNFFT_ERR_ARG
+        import ctypes
+        vp = ctypes.c_void_p
+        st = P.binding.lib().nnfft_exec_batch(1, (vp * 1)(pl.handle.value), (vp * 1)(f.data_ptr()),
+                                              (vp * 1)(y.data_ptr()), P.binding._stream(None))
+        assert st == P.binding.NNFFT_ERR_ARG   # NFFT plans are not batched

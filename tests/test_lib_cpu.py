@@ -149,3 +149,28 @@ def test_plan_dry_run_errors():
     with pytest.raises(binding.NnfftError) as e:
         binding.nnfft_plan_dry_run(64, np.array([0.1]), np.array([0.0]), 2.0, 2.0, 3, 3, P.NNFFT_FP32_COMP)
     assert e.value.status == binding.NNFFT_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("N,M,m,prec", [(64, 300, 6, P.NNFFT_FP32_COMP), (64, 300, 12, P.NNFFT_FP64_PLAIN),
+                                        (1000, 50000, 6, P.NNFFT_FP32_COMP), (2048, 3, 8, P.NNFFT_FP64_PLAIN),
+                                        (4096, 1 << 18, 8, P.NNFFT_FP32_COMP)])
+def test_nfft_dry_run_layout_invariants(N, M, m, prec):
+    from paper_2107_02671_amd import workloads as W
+    g = W.rng(N + M)
+    x = W.uniform_nodes(g, M)
+    x[:min(3, M)] = [-0.5, 0.5, 0.0][:min(3, M)]   # both edges of the period and the centre
+    info = binding.nfft_plan_dry_run(N, x, 2.0, m, prec)
+    n, beta = oracle.nfft_params(N, 2.0, m)
+    assert info["N1"] == n and info["N2"] == n and info["N"] == N
+    assert abs(info["beta1"] - beta) <= 1e-12 * beta
+
+
+def test_nfft_dry_run_errors():
+    x = np.array([0.1, -0.2])
+    for args, status in [((63, x), binding.NNFFT_ERR_ARG), ((64, np.array([0.6])), binding.NNFFT_ERR_DOMAIN)]:
+        with pytest.raises(binding.NnfftError) as e:
+            binding.nfft_plan_dry_run(*args, 2.0, 6, P.NNFFT_FP64_PLAIN)
+        assert e.value.status == status
+    with pytest.raises(binding.NnfftError) as e:
+        binding.nfft_plan_dry_run(64, x, 2.0, 3, P.NNFFT_FP32_COMP)
+    assert e.value.status == binding.NNFFT_ERR_UNSUPPORTED
