@@ -260,6 +260,13 @@ nnfft_status nnfft_clear_tuning(void);
  * n_quad nodes, or Clenshaw-Curtis (5.4) with n_quad + 1 Chebyshev points.
  * The first NNFFT uses v = a_k, x = z_j / 2, the second v = -z_j / 2,
  * x = b_l, both with bandwidth N and the given sigma, m, precision.
+ * Equispaced nodes take the special cases of Sec. 6 (exact FP64 equality,
+ * decided at plan time):
+ *   a_k = k / L1 for k in I_L1 (a[i] = (i - L1/2) / L1, L1 even, N <= L1):
+ *     step 1 is the NFFT of length L1 (nfft_plan) at the nodes N z_j / (2 L1);
+ *   L2 = N and b_l = l / N for l in I_N: step 3 is the adjoint NFFT of
+ *     length N at the nodes z_j / 2.
+ * Those NFFTs use sigma1 and m1.
  *   a[L1], b[L2]: FP64 device arrays in [-1/2, 1/2].
  * Errors: as nnfft_plan, plus ARG for n_quad < 1 or an unknown rule.
  */
@@ -271,8 +278,14 @@ nnfft_status sinc_plan(sinc_plan_t *out, int64_t N, int64_t L1, int64_t L2, sinc
  * the transform's error.  Asynchronous on `stream`. */
 nnfft_status sinc_exec(sinc_plan_t p, const void *c, void *h, void *stream);
 
-/* Info of the two NNFFT plans inside (which = 0: step 1, which = 1: step 3). */
+/* Info of the two plans inside (which = 0: step 1, which = 1: step 3); an
+ * NFFT step reports N = N_star = its length, N1 = N2 = its FFT length and
+ * M1 = M2 = the quadrature size. */
 nnfft_status sinc_info(sinc_plan_t p, int which, nnfft_info_t *out);
+
+/* Input length L1, output length L2, quadrature size, and which steps are
+ * NFFTs (bit 0: step 1, bit 1: step 3).  Errors: ARG for null arguments. */
+nnfft_status sinc_sizes(sinc_plan_t p, int64_t *L1, int64_t *L2, int64_t *n_nodes, int32_t *nfft_steps);
 nnfft_status sinc_destroy(sinc_plan_t p);
 
 /*

@@ -223,6 +223,28 @@ def sinc_fast(N, a, c, b, nq, quad=QUAD_GAUSS_LEGENDRE, sigma1=2.0, sigma2=2.0, 
     return h
 
 
+def sinc_fast_equispaced(N, a, c, b, nq, quad=QUAD_GAUSS_LEGENDRE, sigma=2.0, m=6,
+                         step1_nfft=False, step3_nfft=False, sigma2=2.0, m2=6):
+    """Algorithm 6.1 with the equispaced special cases of Sec. 6.
+
+    step1_nfft: a_k = k / L1 (k in I_L1, N <= L1), so step 1 is the NFFT with L1
+    frequencies at the nodes N z_j / (2 L1); step3_nfft: b_l = l / N (l in I_N),
+    so step 3 is the adjoint NFFT with N frequencies at the nodes z_j / 2.  The
+    NFFTs use (sigma, m); an NNFFT step that remains uses (sigma, sigma2, m, m2).
+    """
+    a, b, c = _real(a), _real(b), _cplx(c)
+    z, w = gauss_legendre(nq) if quad == QUAD_GAUSS_LEGENDRE else clenshaw_curtis(nq)
+    if step1_nfft:
+        L1 = len(a)
+        g = nfft(L1, c, N * z / (2.0 * L1), sigma, m)
+    else:
+        g = nnfft(N, a, c, z / 2.0, sigma, sigma2, m, m2)
+    g = g * w
+    if step3_nfft:
+        return nfft_adjoint(N, g, z / 2.0, sigma, m)
+    return nnfft(N, -z / 2.0, g, b, sigma, sigma2, m, m2)
+
+
 def num_threads() -> int:
     return int(lib().orc_num_threads())
 

@@ -139,6 +139,8 @@ def lib():
     L.sinc_plan.argtypes = [ctypes.POINTER(vp), i64, i64, i64, ci, i64, dbl, dbl, ci, ci, ci, vp, vp, vp]
     L.sinc_exec.argtypes = [vp, vp, vp, vp]
     L.sinc_info.argtypes = [vp, ci, ctypes.POINTER(NnfftInfo)]
+    L.sinc_sizes.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64),
+                             ctypes.POINTER(ci)]
     L.sinc_destroy.argtypes = [vp]
     dptr = ctypes.POINTER(ctypes.c_double)
     L.nnfft_quadrature.argtypes = [ci, i64, dptr, dptr]
@@ -162,7 +164,7 @@ def lib():
     for name in ["nfft_plan", "nfft_exec", "nfft_adjoint", "nfft_destroy", "nfft_plan_dry_run",
                  "nnfft_plan_dry_run", "nnfft_profile_start", "nnfft_profile_stop", "nnfft_quadrature", "nnfft_derive_params",
                  "nnfft_plan", "nnfft_exec", "nnfft_exec_batch", "nnfft_info", "nnfft_destroy", "sinc_plan",
-                 "sinc_exec", "sinc_info", "sinc_destroy", "nnfft_autotune", "nnfft_set_tuning",
+                 "sinc_exec", "sinc_info", "sinc_sizes", "sinc_destroy", "nnfft_autotune", "nnfft_set_tuning",
                  "nnfft_get_tuning", "nnfft_clear_tuning", "nnfft_server_create", "nnfft_server_submit",
                  "nnfft_server_wait", "nnfft_server_poll", "nnfft_server_stats", "nnfft_server_evict",
                  "nnfft_server_destroy"]:
@@ -401,11 +403,18 @@ def sinc_info(plan, which=0) -> dict:
     return info.as_dict()
 
 
+def sinc_sizes(plan) -> dict:
+    """{"L1", "L2", "n_nodes", "nfft_steps"} (nfft_steps bit 0: step 1, bit 1: step 3)."""
+    L1, L2, nn, steps = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int()
+    _check(lib().sinc_sizes(plan, ctypes.byref(L1), ctypes.byref(L2), ctypes.byref(nn), ctypes.byref(steps)))
+    return {"L1": L1.value, "L2": L2.value, "n_nodes": nn.value, "nfft_steps": steps.value}
+
+
 def sinc_exec(plan, c, h, stream=None):
-    i0, i1 = sinc_info(plan, 0), sinc_info(plan, 1)
-    dt = _cdtype(i0["precision"])
-    _require(c, dt, i0["M1"], "c")
-    _require(h, dt, i1["M2"], "h")
+    sz = sinc_sizes(plan)
+    dt = _cdtype(sinc_info(plan, 0)["precision"])
+    _require(c, dt, sz["L1"], "c")
+    _require(h, dt, sz["L2"], "h")
     _check(lib().sinc_exec(plan, _ptr(c), _ptr(h), _stream(stream)))
 
 
@@ -450,11 +459,12 @@ class SincPlan:
                  m2=6, prec=NNFFT_FP32_COMP, stream=None):
         self.handle = sinc_plan(N, a, b, n_quad, quad, sigma1, sigma2, m1, m2, prec, stream)
         self.info = [sinc_info(self.handle, 0), sinc_info(self.handle, 1)]
+        self.sizes = sinc_sizes(self.handle)
 
     def __call__(self, c, h=None, stream=None):
         import torch
         if h is None:
-            h = torch.empty(self.info[1]["M2"], dtype=_cdtype(self.info[0]["precision"]), device=c.device)
+            h = torch.empty(self.sizes["L2"], dtype=_cdtype(self.info[0]["precision"]), device=c.device)
         sinc_exec(self.handle, c, h, stream)
         return h
 

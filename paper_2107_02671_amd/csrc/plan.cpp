@@ -846,10 +846,33 @@ nnfft_status sinc_host(SincHostPlan &S, int64_t N, int64_t L1, int64_t L2, sinc_
         xs[j] = 0.5 * z[j];    // step 1: spatial nodes z_j / 2
         vs[j] = -0.5 * z[j];   // step 3: frequencies -z_j / 2
     }
-    nnfft_status st = plan_host(S.h1, N, L1, nn, sigma1, sigma2, m1, m2, prec, a, xs);
-    if (st == NNFFT_OK) st = plan_host(S.h2, N, nn, L2, sigma1, sigma2, m1, m2, prec, vs, b);
+    // equispaced special cases (Sec. 6, after Algorithm 6.1): a_k = k / L1,
+    // k in I_{L1} (and N <= L1), makes step 1 an NFFT with L1 frequencies at
+    // the nodes N z_j / (2 L1); b_l = l / N, l in I_N, makes step 3 an adjoint
+    // NFFT with N frequencies at the nodes z_j / 2.  Both use sigma1, m1.
+    auto equispaced = [](const std::vector<double> &t, int64_t L) {
+        if (L < 2 || (L % 2) || (int64_t)t.size() != L) return false;
+        for (int64_t k = 0; k < L; ++k)
+            if (t[k] != (double)(k - L / 2) / (double)L) return false;
+        return true;
+    };
+    S.step1_nfft = equispaced(a, L1) && N <= L1;
+    S.step3_nfft = L2 == N && equispaced(b, L2);
+    nnfft_status st;
+    if (S.step1_nfft) {
+        std::vector<double> xn(nn);
+        for (int64_t j = 0; j < nn; ++j) xn[j] = (double)N * z[j] / (2.0 * (double)L1);
+        st = nfft_plan_host(S.h1, L1, nn, sigma1, m1, prec, xn);
+    } else {
+        st = plan_host(S.h1, N, L1, nn, sigma1, sigma2, m1, m2, prec, a, xs);
+    }
+    if (st == NNFFT_OK)
+        st = S.step3_nfft ? nfft_plan_host(S.h2, N, nn, sigma1, m1, prec, xs)
+                          : plan_host(S.h2, N, nn, L2, sigma1, sigma2, m1, m2, prec, vs, b);
     if (st != NNFFT_OK) return st;
     S.n_nodes = nn;
+    S.L1 = L1;
+    S.L2 = L2;
     S.prec = prec;
     const size_t csz = (prec == NNFFT_FP32_COMP) ? 8 : 16;
     S.wg_bytes = ((size_t)nn * sizeof(double) + 255) / 256 * 256 + (size_t)nn * csz;
@@ -864,7 +887,11 @@ nnfft_status sinc_create(const SincHostPlan &S, const DevMem &mem, hipStream_t s
     if (!sp) return fail(NNFFT_ERR_NOMEM, "host allocation failed");
     sp->mem = mem;
     sp->n_nodes = S.n_nodes;
+    sp->L1 = S.L1;
+    sp->L2 = S.L2;
     sp->prec = S.prec;
+    sp->step1_nfft = S.step1_nfft;
+    sp->step3_nfft = S.step3_nfft;
     nnfft_status st = plan_create(S.h1, mem, s, &sp->p1);
     if (st == NNFFT_OK) st = plan_create(S.h2, mem, s, &sp->p2);
     if (st != NNFFT_OK) {
@@ -1221,11 +1248,13 @@ nnfft_status sinc_exec(sinc_plan_t p, const void *c, void *h, void *stream)
 {
     if (!p || !c || !h) return fail(NNFFT_ERR_ARG, "null argument");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    nnfft_status st = nnfft_exec(p->p1, c, p->g, stream);          // step 1
+    nnfft_status st = p->step1_nfft ? nfft_exec(p->p1, c, p->g, stream)        // step 1
+                                    : nnfft_exec(p->p1, c, p->g, stream);
     if (st != NNFFT_OK) return st;
     const hipError_t e = launch_scale_by_weights(p->prec, p->w, p->g, p->g, p->n_nodes, s);   // step 2
     if (e != hipSuccess) return fail(NNFFT_ERR_DEVICE, hipGetErrorString(e));
-    return nnfft_exec(p->p2, p->g, h, stream);                     // step 3
+    return p->step3_nfft ? nfft_adjoint(p->p2, p->g, h, stream)                 // step 3
+                         : nnfft_exec(p->p2, p->g, h, stream);
 }
 
 nnfft_status nnfft_quadrature(sinc_quad quad, int64_t n_quad, double *z, double *w)
@@ -1249,6 +1278,16 @@ nnfft_status sinc_info(sinc_plan_t p, int which, nnfft_info_t *out)
 {
     if (!p || !out || (which != 0 && which != 1)) return fail(NNFFT_ERR_ARG, "bad argument");
     *out = (which == 0 ? p->p1 : p->p2)->info;
+    return NNFFT_OK;
+}
+
+nnfft_status sinc_sizes(sinc_plan_t p, int64_t *L1, int64_t *L2, int64_t *n_nodes, int32_t *nfft_steps)
+{
+    if (!p || !L1 || !L2 || !n_nodes || !nfft_steps) return fail(NNFFT_ERR_ARG, "bad argument");
+    *L1 = p->L1;
+    *L2 = p->L2;
+    *n_nodes = p->n_nodes;
+    *nfft_steps = (p->step1_nfft ? 1 : 0) | (p->step3_nfft ? 2 : 0);
     return NNFFT_OK;
 }
 

@@ -107,7 +107,10 @@ struct sinc_plan_s {
     void *wg_base = nullptr;  // device block of w and g
     nnfft::DevMem mem{};
     int64_t n_nodes = 0;
+    int64_t L1 = 0, L2 = 0;   // input and output lengths
     int32_t prec = 0;
+    bool step1_nfft = false;  // step 1 is an NFFT (a_k equispaced), step 3 an adjoint
+    bool step3_nfft = false;  // NFFT (b_l = l / N): the special cases of Sec. 6
     ~sinc_plan_s();
 };
 
@@ -134,7 +137,9 @@ struct SincHostPlan {
     HostPlan h1, h2;
     std::vector<double> w;
     int64_t n_nodes = 0;
+    int64_t L1 = 0, L2 = 0;
     int32_t prec = 0;
+    bool step1_nfft = false, step3_nfft = false;
     size_t wg_bytes = 0;
     size_t total_bytes = 0;   // both plans plus weights and intermediate
 };

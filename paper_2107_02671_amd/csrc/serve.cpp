@@ -388,10 +388,13 @@ void nnfft_server_s::executor_loop()
         std::vector<nnfft_plan_t> p1, p3;
         std::vector<const void *> f1, f3;
         std::vector<void *> y1, y3;
+        std::vector<Req *> direct;   // sinc requests with NFFT steps: not batched
         for (Req *q : g->reqs) {
             q->out.launch_ms = t_launch;
             q->out.group_size = (int32_t)g->reqs.size();
-            if (q->splan) {
+            if (q->splan && (q->splan->step1_nfft || q->splan->step3_nfft)) {
+                direct.push_back(q);
+            } else if (q->splan) {
                 p1.push_back(q->splan->p1);
                 f1.push_back(q->r.f);
                 y1.push_back(q->splan->g);
@@ -405,8 +408,10 @@ void nnfft_server_s::executor_loop()
             }
         }
         nnfft_status status = nnfft_exec_batch((int)p1.size(), p1.data(), f1.data(), y1.data(), s);
+        for (Req *q : direct)
+            if (status == NNFFT_OK) status = sinc_exec(q->splan, q->r.f, q->r.y, s);
         for (Req *q : g->reqs) {
-            if (status != NNFFT_OK || !q->splan) continue;
+            if (status != NNFFT_OK || !q->splan || q->splan->step1_nfft || q->splan->step3_nfft) continue;
             const sinc_plan_t sp = q->splan;
             if (launch_scale_by_weights(sp->prec, sp->w, sp->g, sp->g, sp->n_nodes, s) != hipSuccess)
                 status = NNFFT_ERR_DEVICE;

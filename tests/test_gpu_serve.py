@@ -31,13 +31,18 @@ def _req(g, i, max_log2_m=15, sinc_every=0):
     M2 = int(np.rint(np.exp(g.uniform(np.log(2 ** 10), np.log(2 ** max_log2_m)))))
     prec, m = (FP32, 6) if i % 2 == 0 else (FP64, 12)
     kind = P.NNFFT_REQ_SINC if sinc_every and i % sinc_every == sinc_every - 1 else P.NNFFT_REQ_NNFFT
+    # every other sinc request has b_l = l / N: its step 3 is an adjoint NFFT
+    eq = kind == P.NNFFT_REQ_SINC and (i // sinc_every) % 2 == 1
     if kind == P.NNFFT_REQ_SINC:
         v, x = W.chebyshev_nodes(g, M1), W.chebyshev_nodes(g, M2)
+        if eq:
+            N += N % 2
+            x = np.arange(-N // 2, N // 2) / N
         f = g.standard_normal(M1) + 0j
     else:
         v, x, f = W.uniform_nodes(g, M1), W.uniform_nodes(g, M2), W.complex_gaussian(g, M1)
     cdt = torch.complex64 if prec == FP32 else torch.complex128
-    return dict(N=N, prec=prec, m=m, kind=kind, n_quad=2 * N,
+    return dict(N=N, prec=prec, m=m, kind=kind, n_quad=2 * N, eq=eq,
                 v=torch.tensor(v, device=DEV), x=torch.tensor(x, device=DEV),
                 f=torch.tensor(f, dtype=cdt, device=DEV), hv=v, hx=x, hf=f)
 
@@ -88,7 +93,9 @@ def test_autotune_installs_layout():
 def test_server_mix_equals_alone():
     g = W.rng(31)
     reqs = [_req(g, i, sinc_every=6) for i in range(26)]
-    _say(f"[gpu] server: {len(reqs)} mixed requests ({sum(r['kind'] for r in reqs)} sinc)")
+    _say(f"[gpu] server: {len(reqs)} mixed requests ({sum(r['kind'] for r in reqs)} sinc, "
+         f"{sum(r['eq'] for r in reqs)} with equispaced outputs)")
+    assert any(r["eq"] for r in reqs)
     torch.cuda.synchronize()
     with P.Server(hbm_budget_bytes=1 << 30, planner_threads=4, streams=2) as srv:
         sub = [_submit(srv, r) for r in reqs]
@@ -104,13 +111,14 @@ def test_server_mix_equals_alone():
     # parity with the oracle for one request of each kind and precision
     seen = set()
     for r, (_, y) in zip(reqs, sub):
-        k = (r["kind"], r["prec"])
+        k = (r["kind"], r["prec"], r["eq"])
         if k in seen:
             continue
         seen.add(k)
         if r["kind"] == P.NNFFT_REQ_SINC:
-            yo = oracle.sinc_fast(r["N"], r["hv"], r["hf"], r["hx"], r["n_quad"], oracle.QUAD_GAUSS_LEGENDRE,
-                                  2.0, 2.0, r["m"], r["m"])
+            yo = oracle.sinc_fast_equispaced(r["N"], r["hv"], r["hf"], r["hx"], r["n_quad"],
+                                             oracle.QUAD_GAUSS_LEGENDRE, 2.0, r["m"], False, r["eq"],
+                                             2.0, r["m"])
             tol = 1e-12 if r["prec"] == FP64 else 2e-5
         else:
             yo = oracle.nnfft(r["N"], r["hv"], r["hf"], r["hx"], 2.0, 2.0, r["m"], r["m"])

@@ -134,3 +134,35 @@ def test_sinc_plan_errors():
     with pytest.raises(P.NnfftError) as e:
         P.sinc_plan(64, a, bad, 128, GL, 2.0, 2.0, 6, 6, FP64)
     assert e.value.status == P.binding.NNFFT_ERR_DOMAIN
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+@pytest.mark.parametrize("s1,s3,L1,L2,quad", [
+    (True, False, 1 << 12, 3000, GL),     # a_k = k / L1: step 1 is an NFFT (L1 >= N)
+    (False, True, 2500, 1024, GL),        # b_l = l / N: step 3 is an adjoint NFFT
+    (True, True, 1 << 11, 1024, CC),      # both
+    (False, False, 1 << 11, 1000, GL),    # a_k = k / L1 with L1 < N stays an NNFFT
+], ids=["step1", "step3", "both", "L1ltN"])
+def test_sinc_equispaced_special_cases(prec, s1, s3, L1, L2, quad):
+    # the special cases of Sec. 6: the library detects equispaced a or b and
+    # runs NFFTs for those steps; compared with the oracle's chain built the
+    # same way and, on samples, with the direct sum (6.2)
+    N = 1024
+    r = W.rng(123)
+    eq1 = s1 or L1 < N
+    a = np.arange(-L1 // 2, L1 // 2) / L1 if eq1 else 0.5 * np.cos(r.uniform(0, np.pi, L1))
+    b = np.arange(-N // 2, N // 2) / N if s3 else 0.5 * np.cos(r.uniform(0, np.pi, L2))
+    c = r.standard_normal(L1) + 1j * r.standard_normal(L1)
+    nq = 2 * N if quad == GL else 4 * N
+    h, info = gpu_sinc(N, a, b, c, nq, quad, 6, prec)
+    for which, expect in ((0, s1), (1, s3)):
+        i = info[which]
+        is_nfft = i["N_star"] == i["N"] and i["N1"] == i["N2"]
+        assert is_nfft == expect, (which, i)
+    ho = oracle.sinc_fast_equispaced(N, a, c, b, nq, quad, 2.0, 6, s1, s3, 2.0, 6)
+    e = einf(h, ho)
+    _say(f"    E_inf vs oracle (NFFT steps {s1}, {s3}) = {e:.3e}")
+    assert e <= tol(prec, 6)
+    idx = W.rng(5).choice(len(b), min(len(b), 256), replace=False)
+    ex = oracle.sinc_direct(N, a, c, b[idx])
+    assert einf(h[idx], ex) <= 1e-4

@@ -499,3 +499,34 @@ def test_nfft_error_decays_exponentially_in_m():
     errs = [np.abs(oracle.nfft(N, f, x, 2.0, m) - yd).max() / np.abs(f).sum() for m in (3, 4, 5, 6)]
     for a, b in zip(errs, errs[1:]):
         assert b < a / 30      # about exp(-2 pi sqrt(1/2)) = 1/85 per step of m
+
+
+@pytest.mark.parametrize("s1,s3", [(True, False), (False, True), (True, True)])
+@pytest.mark.parametrize("quad", [oracle.QUAD_GAUSS_LEGENDRE, oracle.QUAD_CLENSHAW_CURTIS])
+def test_sinc_equispaced_special_cases_against_direct_sum(s1, s3, quad):
+    # Sec. 6 after Algorithm 6.1: equispaced a_k = k / L1 turn step 1 into an
+    # NFFT, b_l = l / N turn step 3 into an adjoint NFFT; the result is the
+    # sinc sum (6.2) within Theorem 6.2 with the NFFT's error in place of E
+    rng = _rng(41)
+    N, m = 64, 8
+    L1 = 96 if s1 else 150
+    a = np.arange(-L1 // 2, L1 // 2) / L1 if s1 else 0.5 * np.cos(rng.uniform(0, np.pi, L1))
+    b = np.arange(-N // 2, N // 2) / N if s3 else 0.5 * np.cos(rng.uniform(0, np.pi, 130))
+    c = rng.standard_normal(L1) + 1j * rng.standard_normal(L1)
+    nq = 2 * N if quad == oracle.QUAD_GAUSS_LEGENDRE else 4 * N
+    h = oracle.sinc_fast_equispaced(N, a, c, b, nq, quad, 2.0, m, s1, s3, 2.0, m)
+    ref = oracle.sinc_direct(N, a, c, b)
+    if quad == oracle.QUAD_CLENSHAW_CURTIS:
+        eps = oracle.bound_thm53(N, 4)
+    else:
+        z, w = oracle.gauss_legendre(nq)
+        xs = np.linspace(-1, 1, 4001)
+        eps = np.abs((w[None, :] * np.exp(-1j * np.pi * N * np.outer(xs, z))).sum(1) - np.sinc(N * xs)).max()
+    E = max(_nfft_gate(L1 if s1 else N, 2.0, m), _nfft_gate(N, 2.0, m),
+            _bound(oracle.params(N, 2.0, 2.0, m, m)))
+    err = np.abs(h - ref).max()
+    assert err <= oracle.bound_thm62(eps, E) * np.abs(c).sum(), err
+    assert err < 1e-6 * np.abs(ref).max()
+    # and it agrees with the general chain of two NNFFTs
+    hg = oracle.sinc_fast(N, a, c, b, nq, quad, 2.0, 2.0, m, m)
+    assert np.abs(h - hg).max() < 2e-6 * np.abs(ref).max()
