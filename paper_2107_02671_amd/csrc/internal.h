@@ -13,7 +13,7 @@ namespace nnfft {
 constexpr int kDeg = 8;
 constexpr int kMaxM = 16;           // largest truncation parameter m
 constexpr int kMaxCorrDeg = 48;     // largest degree of the 1/phi_hat_1 series
-constexpr int kCorr32 = 16;         // FP32 path: the series is zero-padded to this degree
+constexpr int kCorr32 = 32;         // FP32 path: the series is zero-padded to this degree
 constexpr int kMaxPasses = 20;      // radix passes of one sub-transform
 constexpr int kItemsPerWg = 64;     // items (= threads) of a spreading / interpolation workgroup
 constexpr int kMaxPlanes = 16;      // colours of spreading windows with fixed offsets

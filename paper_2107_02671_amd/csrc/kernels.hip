@@ -1108,14 +1108,16 @@ static void launch_fft(const FftArgs &A, hipStream_t s)
     }
 }
 
-// k_interp32 variants: correction degree CD in {8, 10, 12, 16}
+// k_interp32 variants: correction degree CD in {8, 10, 12, 16, 24, 32}
 static void launch_interp32(int cd, int grid, hipStream_t s, const InterpArgs &A, cx<float> *y)
 {
     switch (cd) {
     case 8: hipLaunchKernelGGL((k_interp32<8>), dim3(grid), dim3(kThreads32), 0, s, A, y); break;
     case 10: hipLaunchKernelGGL((k_interp32<10>), dim3(grid), dim3(kThreads32), 0, s, A, y); break;
     case 12: hipLaunchKernelGGL((k_interp32<12>), dim3(grid), dim3(kThreads32), 0, s, A, y); break;
-    default: hipLaunchKernelGGL((k_interp32<16>), dim3(grid), dim3(kThreads32), 0, s, A, y); break;
+    case 16: hipLaunchKernelGGL((k_interp32<16>), dim3(grid), dim3(kThreads32), 0, s, A, y); break;
+    case 24: hipLaunchKernelGGL((k_interp32<24>), dim3(grid), dim3(kThreads32), 0, s, A, y); break;
+    default: hipLaunchKernelGGL((k_interp32<32>), dim3(grid), dim3(kThreads32), 0, s, A, y); break;
     }
 }
 
@@ -1125,14 +1127,16 @@ static void launch_interp32_batch(int cd, int grid, hipStream_t s, const BatchTa
     case 8: hipLaunchKernelGGL((k_interp32_batch<8>), dim3(grid), dim3(kThreads32), 0, s, T); break;
     case 10: hipLaunchKernelGGL((k_interp32_batch<10>), dim3(grid), dim3(kThreads32), 0, s, T); break;
     case 12: hipLaunchKernelGGL((k_interp32_batch<12>), dim3(grid), dim3(kThreads32), 0, s, T); break;
-    default: hipLaunchKernelGGL((k_interp32_batch<16>), dim3(grid), dim3(kThreads32), 0, s, T); break;
+    case 16: hipLaunchKernelGGL((k_interp32_batch<16>), dim3(grid), dim3(kThreads32), 0, s, T); break;
+    case 24: hipLaunchKernelGGL((k_interp32_batch<24>), dim3(grid), dim3(kThreads32), 0, s, T); break;
+    default: hipLaunchKernelGGL((k_interp32_batch<32>), dim3(grid), dim3(kThreads32), 0, s, T); break;
     }
 }
 
 // evaluated degree of the 1/phi_hat_1 series: the smallest variant >= deg
 static int corr_variant(int deg)
 {
-    return deg <= 8 ? 8 : deg <= 10 ? 10 : deg <= 12 ? 12 : 16;
+    return deg <= 8 ? 8 : deg <= 10 ? 10 : deg <= 12 ? 12 : deg <= 16 ? 16 : deg <= 24 ? 24 : 32;
 }
 
 

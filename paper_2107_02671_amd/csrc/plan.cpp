@@ -430,6 +430,17 @@ void layout_plan(const HostPlan &H, Carver &C, PlanDev &D, size_t *upload_end, P
 }
 
 // Merge lists of the overflow windows (those without a plane).
+// Largest accepted error of the FP32 tap polynomials of one window: 5e-8, or
+// 1e-3 of the window's own error term of Theorem 4.1,
+// (24 m^1.5 + 10) exp(-2 pi m sqrt(1 - 1/sigma)), when that is larger (small
+// m or sigma, where the transform's error dwarfs the polynomial's).
+static double tap_fit_tolerance(int m, double sigma)
+{
+    const double term = (24.0 * std::pow((double)m, 1.5) + 10.0) *
+                        std::exp(-2.0 * kPi * m * std::sqrt(1.0 - 1.0 / sigma));
+    return std::max(5e-8, 1e-3 * term);
+}
+
 static nnfft_status build_merge_lists(HostPlan &H, const nnfft_info_t &P, int m1)
 {
     // merge lists of the overflow windows (those without a plane): for each
@@ -562,7 +573,7 @@ nnfft_status plan_host(HostPlan &H, int64_t N, int64_t M1, int64_t M2, double si
         const std::vector<double> c2 = fit_window_taps(m2, P.beta2, kDeg, &e2);
         P.window_degree = kDeg;
         P.window_fit_err = std::max(e1, e2);
-        if (P.window_fit_err > 5e-8)
+        if (e1 > tap_fit_tolerance(m1, P.sigma1_eff) || e2 > tap_fit_tolerance(m2, P.sigma2_eff))
             return fail(NNFFT_ERR_UNSUPPORTED, "window polynomial misses FP32 accuracy for these sigma, m");
         H.C1.assign(c1.begin(), c1.end());
         H.C2.assign(c2.begin(), c2.end());
@@ -668,7 +679,8 @@ nnfft_status nfft_plan_host(HostPlan &H, int64_t N, int64_t M, double sigma, int
         const std::vector<double> c = fit_window_taps(m, P.beta1, kDeg, &e);
         P.window_degree = kDeg;
         P.window_fit_err = e;
-        if (e > 5e-8) return fail(NNFFT_ERR_UNSUPPORTED, "window polynomial misses FP32 accuracy for these sigma, m");
+        if (e > tap_fit_tolerance(m, P.sigma1_eff))
+            return fail(NNFFT_ERR_UNSUPPORTED, "window polynomial misses FP32 accuracy for these sigma, m");
         H.C1.assign(c.begin(), c.end());
         H.C2 = H.C1;
     }

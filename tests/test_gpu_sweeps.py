@@ -1,0 +1,150 @@
+"""Parameter sweeps of the GPU path over the grids of the paper's numerical
+examples, with seeded synthetic inputs in place of its random draws.
+
+Example 4.2 (NNFFT accuracy): N = 1200, M1 = 2400, M2 = 1600, m1 = 2..8,
+sigma1 in {5/4, 3/2, 2} with (a) m2 = 2 m1, (b) m2 = m1 (both sigma2 = sigma1)
+and (c) sigma2 = 2 sigma1, m2 = m1.  Every case is compared with the oracle
+NNFFT (parity) and with the direct sum (1.2):
+  * (a), (b): E_paper = max|y~ - y| / sum|f| within Theorem 4.1's bound
+    (times 1.08 for its constant slip) plus an FP64 rounding floor;
+  * (c): sigma2 > 2 is outside Theorem 4.1; the error stays within the bound
+    of (b) at the same sigma1, m1 (the paper's advice that a larger sigma2
+    does not hurt), checked as an observed property.
+Parity tolerance (E_inf against the oracle): 1e-12 (FP64) or 1e-5 (FP32)
+times max(1, kappa / 4.62), kappa the amplification of the two phi_hat
+divisions (m2 = 16 at sigma = 5/4 gives kappa ~ 3e6).  FP32 runs where
+m1 >= 4 and kappa <= 1e3.
+
+Example 6.3 (fast sinc accuracy): N = 2^k, k = 5..13, L1 = N/2 random
+a_k in [-1/2, 1/2], b_l = l / N (L2 = N, so step 3 is the adjoint NFFT of
+Sec. 6), Clenshaw-Curtis with n in {4N, 6N, 8N} (n = 4N only at k = 13,
+where the oracle's O(n^2) weights dominate): parity with the oracle's
+chain and the error against the direct sum (6.2) within Theorem 6.2 with
+Theorem 5.3's quadrature bound.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2107_02671_amd as P
+from paper_2107_02671_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FP64, FP32 = P.NNFFT_FP64_PLAIN, P.NNFFT_FP32_COMP
+CC = P.SINC_QUAD_CLENSHAW_CURTIS
+DEV = "cuda:0"
+SLIP = 1.08
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _kappa(Pp, m1, m2):
+    k1 = oracle.omega_hat(0.0, Pp.beta1) / oracle.omega_hat(m1 / (2 * Pp.sigma1_eff), Pp.beta1)
+    k2 = oracle.omega_hat(0.0, Pp.beta2) / oracle.omega_hat(m2 / (2 * Pp.sigma2_eff), Pp.beta2)
+    return float(max(k1, k2))
+
+
+def _parity_tol(prec, kappa):
+    return (1e-12 if prec == FP64 else 1e-5) * max(1.0, kappa / 4.62)
+
+
+_EX42 = {}
+
+
+def _ex42_inputs():
+    if not _EX42:
+        g = W.rng(420)
+        v, x = W.uniform_nodes(g, 2400), W.uniform_nodes(g, 1600)
+        f = W.complex_gaussian(g, 2400)
+        _EX42["in"] = (v, x, f)
+        _EX42["exact"] = oracle.direct(1200, v, f, x)
+    return _EX42["in"], _EX42["exact"]
+
+
+def _variant(var, s1, m1):
+    return {"a": (s1, 2 * m1), "b": (s1, m1), "c": (2 * s1, m1)}[var]
+
+
+@pytest.mark.parametrize("var", ["a", "b", "c"])
+@pytest.mark.parametrize("s1", [1.25, 1.5, 2.0])
+def test_example_4_2_grid(var, s1):
+    N = 1200
+    (v, x, f), exact = _ex42_inputs()
+    tv, tx = torch.tensor(v, device=DEV), torch.tensor(x, device=DEV)
+    sumf = float(np.abs(f).sum())
+    for m1 in range(2, 9):
+        s2, m2 = _variant(var, s1, m1)
+        Pp = oracle.params(N, s1, s2, m1, m2)
+        yo = oracle.nnfft(N, v, f, x, s1, s2, m1, m2)
+        kap = _kappa(Pp, m1, m2)
+        for prec in (FP64, FP32):
+            if prec == FP32 and (m1 < 4 or kap > 1e3):
+                continue          # FP32 tap series need m >= 4; kappa > 1e3 leaves no FP32 digits
+            _say(f"[gpu] example 4.2 ({var}) sigma=({s1},{s2}) m=({m1},{m2}) prec={prec}")
+            cdt = torch.complex128 if prec == FP64 else torch.complex64
+            with P.Plan(N, tv, tx, s1, s2, m1, m2, prec) as pl:
+                y = pl(torch.tensor(f, dtype=cdt, device=DEV))
+                torch.cuda.synchronize()
+            y = y.cpu().numpy().astype(np.complex128)
+            e_or = float(np.abs(y - yo).max() / np.abs(yo).max())
+            e_paper = float(np.abs(y - exact).max() / sumf)
+            _say(f"    E_inf vs oracle {e_or:.2e} (tol {_parity_tol(prec, kap):.1e}), E_paper {e_paper:.2e}")
+            assert e_or <= _parity_tol(prec, kap)
+            if prec != FP64:
+                continue
+            floor = 1e-14 + 1e-16 * kap
+            if var in ("a", "b"):
+                bound = SLIP * oracle.bound_thm41(Pp.N1, m1, m2, Pp.sigma1_eff, Pp.sigma2_eff)
+            else:
+                Pb = oracle.params(N, s1, s1, m1, m1)
+                bound = SLIP * oracle.bound_thm41(Pb.N1, m1, m1, Pb.sigma1_eff, Pb.sigma2_eff)
+            assert e_paper <= bound + floor, (m1, e_paper, bound)
+
+
+@pytest.mark.parametrize("k", range(5, 14))
+def test_example_6_3_grid(k):
+    N = 2 ** k
+    L1 = N // 2
+    g = W.rng(630 + k)
+    a = W.uniform_nodes(g, L1)
+    c = g.standard_normal(L1) + 0j
+    b = np.arange(-N // 2, N // 2) / N
+    exact = oracle.sinc_direct(N, a, c, b)
+    ta, tb = torch.tensor(a, device=DEV), torch.tensor(b, device=DEV)
+    m = 8
+    Pp = oracle.params(N, 2.0, 2.0, m, m)
+    n_nfft, _ = oracle.nfft_params(N, 2.0, m)
+    E = max(SLIP * oracle.bound_thm41(Pp.N1, m, m, Pp.sigma1_eff, Pp.sigma2_eff),
+            24.0 * m ** 1.5 * math.exp(-2 * math.pi * m * math.sqrt(1 - N / n_nfft)))
+    for nu in ((4, 6, 8) if k <= 12 else (4,)):
+        nq = nu * N
+        ho = oracle.sinc_fast_equispaced(N, a, c, b, nq, oracle.QUAD_CLENSHAW_CURTIS, 2.0, m,
+                                         False, True, 2.0, m)
+        for prec in (FP64, FP32):
+            if prec == FP32 and nu != 4:
+                continue
+            _say(f"[gpu] example 6.3 N={N} L1={L1} n={nq} prec={prec}")
+            cdt = torch.complex128 if prec == FP64 else torch.complex64
+            sp = P.SincPlan(N, ta, tb, nq, CC, 2.0, 2.0, m, m, prec)
+            try:
+                assert sp.sizes["nfft_steps"] == 2
+                h = sp(torch.tensor(c, dtype=cdt, device=DEV))
+                torch.cuda.synchronize()
+            finally:
+                sp.close()
+            h = h.cpu().numpy().astype(np.complex128)
+            e_or = float(np.abs(h - ho).max() / np.abs(ho).max())
+            err = float(np.abs(h - exact).max())
+            bound = oracle.bound_thm62(oracle.bound_thm53(N, nu), E) * float(np.abs(c).sum())
+            _say(f"    E_inf vs oracle {e_or:.2e}, max error {err:.2e} (Theorem 6.2: {bound:.2e})")
+            assert e_or <= (1e-12 if prec == FP64 else 2e-5)
+            if prec == FP64:
+                assert err <= bound + 1e-13 * float(np.abs(c).sum())
