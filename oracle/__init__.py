@@ -27,7 +27,8 @@ class _Params(ctypes.Structure):
                 ("G1", ctypes.c_long), ("N2", ctypes.c_long), ("m1", ctypes.c_int),
                 ("m2", ctypes.c_int), ("sigma1", ctypes.c_double), ("sigma2", ctypes.c_double),
                 ("sigma1_eff", ctypes.c_double), ("sigma2_eff", ctypes.c_double),
-                ("a", ctypes.c_double), ("beta1", ctypes.c_double), ("beta2", ctypes.c_double)]
+                ("a", ctypes.c_double), ("beta1", ctypes.c_double), ("beta2", ctypes.c_double),
+                ("window", ctypes.c_int)]
 
 
 def lib():
@@ -39,6 +40,14 @@ def lib():
         dp = ctypes.POINTER(ctypes.c_double)
         L.orc_params.argtypes = [ctypes.c_long, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                  ctypes.c_int, ctypes.POINTER(_Params)]
+        L.orc_params_window.argtypes = [ctypes.c_long, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                        ctypes.c_int, ctypes.c_int, ctypes.POINTER(_Params)]
+        L.orc_window.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_double]
+        L.orc_window.restype = ctypes.c_double
+        L.orc_window_hat.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_double]
+        L.orc_window_hat.restype = ctypes.c_double
+        L.orc_bspline_cardinal.argtypes = [ctypes.c_int, ctypes.c_double]
+        L.orc_bspline_cardinal.restype = ctypes.c_double
         L.orc_omega.argtypes = [ctypes.c_double, ctypes.c_double]
         L.orc_omega.restype = ctypes.c_double
         L.orc_omega_hat.argtypes = [ctypes.c_double, ctypes.c_double]
@@ -49,6 +58,7 @@ def lib():
         L.orc_sinc_direct.argtypes = [ctypes.c_long, ctypes.c_long, dp, dp, ctypes.c_long, dp, dp]
         L.orc_nnfft.argtypes = [ctypes.c_long, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                 ctypes.c_int, ctypes.c_long, dp, dp, ctypes.c_long, dp, dp, dp, dp]
+        L.orc_nnfft_window.argtypes = [ctypes.c_int] + L.orc_nnfft.argtypes
         L.orc_gauss_legendre.argtypes = [ctypes.c_long, dp, dp]
         L.orc_clenshaw_curtis.argtypes = [ctypes.c_long, dp, dp]
         L.orc_sinc_fast.argtypes = [ctypes.c_long, ctypes.c_double, ctypes.c_double, ctypes.c_int,
@@ -91,14 +101,41 @@ class Params:
     a: float
     beta1: float
     beta2: float
+    window: int
 
 
-def params(N, sigma1, sigma2, m1, m2) -> Params:
+# window families of Example 2.1
+WIN_SINH, WIN_BSPLINE, WIN_ALGEBRAIC = 0, 1, 2
+
+
+def params(N, sigma1, sigma2, m1, m2, window=WIN_SINH) -> Params:
     p = _Params()
-    rc = lib().orc_params(int(N), float(sigma1), float(sigma2), int(m1), int(m2), ctypes.byref(p))
+    rc = lib().orc_params_window(int(N), float(sigma1), float(sigma2), int(m1), int(m2), int(window),
+                                 ctypes.byref(p))
     if rc:
-        raise ValueError(f"invalid NNFFT parameters N={N} sigma=({sigma1},{sigma2}) m=({m1},{m2})")
+        raise ValueError(f"invalid NNFFT parameters N={N} sigma=({sigma1},{sigma2}) m=({m1},{m2}) "
+                         f"window={window}")
     return Params(**{f: getattr(p, f) for f, _ in _Params._fields_})
+
+
+def window(kind, u, m, beta) -> np.ndarray:
+    """omega(u) of family `kind` (Example 2.1); beta is ignored by the B-spline."""
+    u = np.asarray(u, dtype=np.float64)
+    return np.vectorize(lambda t: lib().orc_window(int(kind), float(t), int(m), float(beta)),
+                        otypes=[float])(u)
+
+
+def window_hat(kind, v, m, beta) -> np.ndarray:
+    """The Fourier transform of window(kind, ., m, beta) in its closed form (Example 2.1)."""
+    v = np.asarray(v, dtype=np.float64)
+    return np.vectorize(lambda t: lib().orc_window_hat(int(kind), float(t), int(m), float(beta)),
+                        otypes=[float])(v)
+
+
+def bspline_cardinal(n, y) -> np.ndarray:
+    """Cardinal B-spline M_n(y) of order n on [0, n]; B_n(x) = M_n(x + n/2)."""
+    y = np.asarray(y, dtype=np.float64)
+    return np.vectorize(lambda t: lib().orc_bspline_cardinal(int(n), float(t)), otypes=[float])(y)
 
 
 def omega(u, beta) -> np.ndarray:
@@ -125,19 +162,20 @@ def direct(N, v, f, x) -> np.ndarray:
     return y
 
 
-def nnfft(N, v, f, x, sigma1=2.0, sigma2=2.0, m1=4, m2=4, return_steps=False):
-    """Algorithm 2.2 in FP64 with a direct DFT for step 3.
+def nnfft(N, v, f, x, sigma1=2.0, sigma2=2.0, m1=4, m2=4, return_steps=False, window=WIN_SINH):
+    """Algorithm 2.2 in FP64 with a direct DFT for step 3 (both windows of
+    family `window`).
 
     return_steps=True also returns g (step 1, length G1, index l + G1/2) and
     h (step 3, length N2, index s + N2/2)."""
     v, x, f = _real(v), _real(x), _cplx(f)
-    P = params(N, sigma1, sigma2, m1, m2)
+    P = params(N, sigma1, sigma2, m1, m2, window)
     y = np.zeros(len(x), dtype=np.complex128)
     g = np.zeros(P.G1, dtype=np.complex128)
     h = np.zeros(P.N2, dtype=np.complex128)
-    rc = lib().orc_nnfft(int(N), float(sigma1), float(sigma2), int(m1), int(m2), len(v), _dp(v),
-                         _dp(f.view(np.float64)), len(x), _dp(x), _dp(y.view(np.float64)),
-                         _dp(g.view(np.float64)), _dp(h.view(np.float64)))
+    rc = lib().orc_nnfft_window(int(window), int(N), float(sigma1), float(sigma2), int(m1), int(m2), len(v),
+                                _dp(v), _dp(f.view(np.float64)), len(x), _dp(x), _dp(y.view(np.float64)),
+                                _dp(g.view(np.float64)), _dp(h.view(np.float64)))
     if rc == 2:
         raise ValueError("node outside [-1/2, 1/2]")
     if rc:
@@ -260,6 +298,42 @@ def bound_thm41(N1, m1, m2, sigma1, sigma2) -> float:
           * math.exp(2 * math.pi * m1 * (1 - math.sqrt(1 - 1 / sigma1) - 1 / (2 * sigma1)))
           * math.exp(-2 * math.pi * m2 * math.sqrt(1 - 1 / sigma2)))
     return t1 + t2
+
+
+def bound_thm34(kind, m, sigma, beta) -> float:
+    """(3.9), Theorem 3.4: upper bound of the general error constant E_sigma(phi)
+    of a window of family `kind`, from decay constants c1, c2, mu of its
+    transform that hold for every v:
+      B-spline   |omega_hat(v)| <= (m / (pi |v|))^(2m) / (m B_2m(0)), mu = 2m;
+      algebraic  |omega_hat(v)| <= C (pi |v|)^(-beta) (|J_beta| <= 1), mu = beta,
+                 C = pi (2 beta)! / (4^beta beta!);
+    c1 is that envelope at |v| = m (1 - 1/(2 sigma)), where the interval of
+    the theorem starts."""
+    lo = m * (1.0 - 1.0 / (2.0 * sigma))
+    if kind == WIN_BSPLINE:
+        b0 = float(bspline_cardinal(2 * m, m))
+        c2 = (m / math.pi) ** (2 * m) / (m * b0)
+        mu = 2.0 * m
+    elif kind == WIN_ALGEBRAIC:
+        lc = math.log(math.pi) + math.lgamma(2 * beta + 1) - beta * math.log(4.0) - math.lgamma(beta + 1)
+        c2 = math.exp(lc - beta * math.log(math.pi))
+        mu = float(beta)
+    else:
+        raise ValueError("Theorem 3.4 constants are given for the B-spline and algebraic windows")
+    c1 = c2 * lo ** (-mu)
+    inner = 2.0 * c1 + 2.0 * c2 / ((mu - 1.0) * m ** mu) * (1.0 - 1.0 / (2.0 * sigma)) ** (1.0 - mu)
+    return float(inner / window_hat(kind, m / (2.0 * sigma), m, beta))
+
+
+def bound_thm35(kind, N, sigma1, sigma2, m1, m2) -> float:
+    """(3.10), Theorem 3.5: [E_sigma1(phi_1) + a E_sigma2(phi_2) / phi_hat_1(N*/2)],
+    the bound on E_paper, with Theorem 3.4 for both constants and the sizes of
+    the N* substitution (phi_hat_1(N*/2) = (m1/N1) omega_hat_1(m1 / (2 sigma1_eff)))."""
+    P = params(N, sigma1, sigma2, m1, m2, kind)
+    e1 = bound_thm34(kind, m1, P.sigma1_eff, P.beta1)
+    e2 = bound_thm34(kind, m2, P.sigma2_eff, P.beta2)
+    phi1 = m1 / P.N1 * float(window_hat(kind, m1 / (2.0 * P.sigma1_eff), m1, P.beta1))
+    return e1 + P.a / phi1 * e2
 
 
 CC_C = math.pi * (math.e ** 2 - 1) / (2 * math.e)   # C of Theorem 5.3

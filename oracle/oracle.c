@@ -35,8 +35,18 @@ typedef struct {
     double sigma1, sigma2;          /* requested oversampling factors         */
     double sigma1_eff, sigma2_eff;  /* N1 / N*,  N2 / G1                      */
     double a;                       /* (2.6): a = 1 + 2 m1 / N1               */
-    double beta1, beta2;            /* shape parameters of the sinh windows   */
+    double beta1, beta2;            /* shape parameters of the windows        */
+    int window;                     /* ORC_WIN_* of both windows              */
 } orc_params_t;
+
+/* Window families of Example 2.1 */
+#define ORC_WIN_SINH 0        /* sinh-type, beta = 2 pi m (1 - 1/(2 sigma))       */
+#define ORC_WIN_BSPLINE 1     /* B_{2m}(m x) / B_{2m}(0)                           */
+#define ORC_WIN_ALGEBRAIC 2   /* (1 - x^2)^(beta - 1/2), beta = 3m, sigma > pi/3   */
+
+double orc_sinc_pi(double d);
+double orc_window(int kind, double x, int m, double beta);
+double orc_window_hat(int kind, double v, int m, double beta);
 
 /* ------------------------------------------------------------------------ */
 /* Parameter derivation                                                      */
@@ -93,6 +103,28 @@ int orc_params(long N, double sigma1, double sigma2, int m1, int m2, orc_params_
     /* Algorithm 2.2 input: 2 m2 <= (1 - 1/sigma1) N2 */
     if (2.0 * m2 > (1.0 - 1.0 / p->sigma1_eff) * (double)p->N2 + 1e-9) return 1;
     if (2 * m1 >= p->N1) return 1;
+    p->window = ORC_WIN_SINH;
+    return 0;
+}
+
+/*
+ * The same sizes for the windows of family `window` (Example 2.1): the
+ * B-spline windows have no shape parameter (beta = 0); the algebraic windows
+ * take beta_j = 3 m_j and need sigma_j > pi/3.
+ */
+int orc_params_window(long N, double sigma1, double sigma2, int m1, int m2, int window, orc_params_t *p)
+{
+    if (orc_params(N, sigma1, sigma2, m1, m2, p)) return 1;
+    if (window == ORC_WIN_BSPLINE) {
+        p->beta1 = p->beta2 = 0.0;
+    } else if (window == ORC_WIN_ALGEBRAIC) {
+        if (!(p->sigma1_eff > ORC_PI / 3.0) || !(p->sigma2_eff > ORC_PI / 3.0)) return 1;
+        p->beta1 = 3.0 * m1;
+        p->beta2 = 3.0 * m2;
+    } else if (window != ORC_WIN_SINH) {
+        return 1;
+    }
+    p->window = window;
     return 0;
 }
 
@@ -136,11 +168,92 @@ double orc_omega_hat(double v, double beta)
  * Theorem 3.4): phi_hat_j(v) = (m_j / N_j) omega_hat_j(m_j v / N_j). */
 static double orc_phi1_hat(const orc_params_t *p, double v)
 {
-    return (double)p->m1 / (double)p->N1 * orc_omega_hat(p->m1 * v / (double)p->N1, p->beta1);
+    return (double)p->m1 / (double)p->N1 * orc_window_hat(p->window, p->m1 * v / (double)p->N1, p->m1, p->beta1);
 }
 static double orc_phi2_hat(const orc_params_t *p, double v)
 {
-    return (double)p->m2 / (double)p->N2 * orc_omega_hat(p->m2 * v / (double)p->N2, p->beta2);
+    return (double)p->m2 / (double)p->N2 * orc_window_hat(p->window, p->m2 * v / (double)p->N2, p->m2, p->beta2);
+}
+
+/* ------------------------------------------------------------------------ */
+/* B-spline and algebraic windows (Example 2.1)                               */
+/* ------------------------------------------------------------------------ */
+
+/* Cardinal B-spline M_n of order n (support [0, n]) by its recursion
+ * M_1 = indicator of [0, 1),
+ * M_k(y) = (y M_{k-1}(y) + (k - y) M_{k-1}(y - 1)) / (k - 1),
+ * with M_k(y - i) tabulated for the shifts i the recursion reaches.  The
+ * centred spline of the paper is B_n(x) = M_n(x + n/2). */
+double orc_bspline_cardinal(int n, double y)
+{
+    double val[130];
+    if (n < 1 || n > 128) return NAN;
+    for (int i = 0; i < n; i++) val[i] = (y - i >= 0.0 && y - i < 1.0) ? 1.0 : 0.0;
+    for (int k = 2; k <= n; k++)
+        for (int i = 0; i <= n - k; i++) {
+            double yi = y - i;
+            val[i] = (yi * val[i] + ((double)k - yi) * val[i + 1]) / (double)(k - 1);
+        }
+    return val[0];
+}
+
+/* omega_B(x) = B_{2m}(m x) / B_{2m}(0) */
+static double orc_omega_bspline(double x, int m)
+{
+    if (fabs(x) >= 1.0) return 0.0;
+    return orc_bspline_cardinal(2 * m, m * x + m) / orc_bspline_cardinal(2 * m, (double)m);
+}
+
+/* omega_B_hat(v) = sinc(pi v / m)^(2m) / (m B_{2m}(0)) */
+static double orc_omega_hat_bspline(double v, int m)
+{
+    double b0 = orc_bspline_cardinal(2 * m, (double)m);
+    double s = orc_sinc_pi(v / m);
+    return pow(s, 2.0 * m) / ((double)m * b0);
+}
+
+/* omega_alg(x) = (1 - x^2)^(beta - 1/2) on [-1, 1] */
+static double orc_omega_algebraic(double x, double beta)
+{
+    if (fabs(x) >= 1.0) return 0.0;
+    return pow((1.0 - x) * (1.0 + x), beta - 0.5);
+}
+
+/* omega_alg_hat(v) = pi (2 beta)! / (4^beta beta!) (pi v)^(-beta) J_beta(2 pi v)
+ * for integer beta, with the Bessel power series
+ * (pi v)^(-beta) J_beta(2 pi v) = sum_k (-1)^k (pi v)^(2k) / (k! (k + beta)!),
+ * summed in long double (the alternating terms cancel a few digits; accurate to
+ * ~1e-14 for |v| <= m/2, which covers the |v| <= m / (2 sigma) the NNFFT uses). */
+static double orc_omega_hat_algebraic(double v, double beta)
+{
+    long double b = (long double)beta;
+    long double lead = logl((long double)ORC_PI) + lgammal(2.0L * b + 1.0L) - b * logl(4.0L) -
+                       2.0L * lgammal(b + 1.0L);
+    long double term = expl(lead), sum = term;     /* k = 0: pi (2b)! / (4^b (b!)^2) */
+    long double y = (long double)ORC_PI * (long double)v;
+    y *= y;
+    for (int k = 0; k < 2000; k++) {
+        term *= -y / ((long double)(k + 1) * ((long double)(k + 1) + b));
+        sum += term;
+        if (fabsl(term) < 1e-22L * fabsl(sum) && (long double)k > sqrtl(y)) break;
+    }
+    return (double)sum;
+}
+
+/* The window omega of family `kind` (sinh uses beta, B-spline m, algebraic beta). */
+double orc_window(int kind, double x, int m, double beta)
+{
+    if (kind == ORC_WIN_BSPLINE) return orc_omega_bspline(x, m);
+    if (kind == ORC_WIN_ALGEBRAIC) return orc_omega_algebraic(x, beta);
+    return orc_omega(x, beta);
+}
+
+/* Its Fourier transform omega_hat(v) = 2 int_0^1 omega(x) cos(2 pi v x) dx. */
+double orc_window_hat(int kind, double v, int m, double beta)
+{
+    if (kind == ORC_WIN_BSPLINE) return orc_omega_hat_bspline(v, m);
+    if (kind == ORC_WIN_ALGEBRAIC) return orc_omega_hat_algebraic(v, beta);
+    return orc_omega_hat(v, beta);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -222,16 +335,17 @@ int orc_sinc_direct(long N, long L1, const double *a, const double *c,
  * Optional outputs (may be NULL):
  *   g_out[G1]  complex g_l of (2.12), l = -G1/2 .. G1/2-1 stored at l + G1/2
  *   h_out[N2]  complex h_s of step 3,  s = -N2/2 .. N2/2-1 stored at s + N2/2
+ * Both windows are of family `window` (ORC_WIN_*, Example 2.1).
  * Returns 0, 1 for invalid parameters, 2 for a node outside [-1/2, 1/2],
  * 3 for an allocation failure.
  */
-int orc_nnfft(long N, double sigma1, double sigma2, int m1, int m2,
-              long M1, const double *v, const double *f,
-              long M2, const double *x, double *y,
-              double *g_out, double *h_out)
+int orc_nnfft_window(int window, long N, double sigma1, double sigma2, int m1, int m2,
+                     long M1, const double *v, const double *f,
+                     long M2, const double *x, double *y,
+                     double *g_out, double *h_out)
 {
     orc_params_t P;
-    if (orc_params(N, sigma1, sigma2, m1, m2, &P)) return 1;
+    if (orc_params_window(N, sigma1, sigma2, m1, m2, window, &P)) return 1;
     for (long k = 0; k < M1; k++) if (!(fabs(v[k]) <= 0.5)) return 2;
     for (long j = 0; j < M2; j++) if (!(fabs(x[j]) <= 0.5)) return 2;
     const long G1 = P.G1, N1 = P.N1, N2 = P.N2, Ns = P.N_star;
@@ -266,7 +380,7 @@ int orc_nnfft(long N, double sigma1, double sigma2, int m1, int m2,
             double t = (double)N1 * vstar;
             long c = (long)floor(t);
             for (long l = c - m1 + 1; l <= c + m1; l++) {
-                double w = orc_omega(((double)l - t) / m1, P.beta1);
+                double w = orc_window(P.window, ((double)l - t) / m1, m1, P.beta1);
                 long idx = l + G1 / 2;
                 gp[2 * idx] += f[2 * k] * w;
                 gp[2 * idx + 1] += f[2 * k + 1] * w;
@@ -324,7 +438,7 @@ int orc_nnfft(long N, double sigma1, double sigma2, int m1, int m2,
         long c = (long)floor(u);
         double re = 0.0, im = 0.0;
         for (long sv = c - m2 + 1; sv <= c + m2; sv++) {
-            double w = orc_omega((u - (double)sv) / m2, P.beta2);
+            double w = orc_window(P.window, (u - (double)sv) / m2, m2, P.beta2);
             long o = ((sv % N2) + N2) % N2;        /* periodic index */
             long oi = (o >= N2 / 2) ? o - N2 : o;  /* label in I_N2  */
             oi += N2 / 2;
@@ -337,6 +451,15 @@ int orc_nnfft(long N, double sigma1, double sigma2, int m1, int m2,
     }
     free(g); free(gh); free(h); free(tw);
     return 0;
+}
+
+/* Algorithm 2.2 with the sinh-type windows */
+int orc_nnfft(long N, double sigma1, double sigma2, int m1, int m2,
+              long M1, const double *v, const double *f,
+              long M2, const double *x, double *y,
+              double *g_out, double *h_out)
+{
+    return orc_nnfft_window(ORC_WIN_SINH, N, sigma1, sigma2, m1, m2, M1, v, f, M2, x, y, g_out, h_out);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -530,3 +530,93 @@ def test_sinc_equispaced_special_cases_against_direct_sum(s1, s3, quad):
     # and it agrees with the general chain of two NNFFTs
     hg = oracle.sinc_fast(N, a, c, b, nq, quad, 2.0, 2.0, m, m)
     assert np.abs(h - hg).max() < 2e-6 * np.abs(ref).max()
+
+
+# --------------------------------------------------------------------------
+# B-spline and algebraic windows (Example 2.1) and the NNFFT with them
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [2, 3, 4, 7, 12, 16, 32])
+def test_bspline_against_scipy_and_partition_of_unity(n):
+    from scipy.interpolate import BSpline
+    ys = np.linspace(0.003, n - 0.003, 97)
+    ref = np.nan_to_num(BSpline.basis_element(np.arange(n + 1), extrapolate=False)(ys))
+    assert np.abs(oracle.bspline_cardinal(n, ys) - ref).max() < 1e-14
+    # sum over integer shifts is 1
+    y = 0.3721
+    assert abs(sum(float(oracle.bspline_cardinal(n, y + j)) for j in range(-n, n + 1)) - 1.0) < 1e-14
+
+
+def test_bspline_central_values():
+    # B_4(0) = 2/3, B_6(0) = 11/20, B_8(0) = 151/315 (centred cardinal splines)
+    for n, val in ((4, 2 / 3), (6, 11 / 20), (8, 151 / 315)):
+        assert abs(float(oracle.bspline_cardinal(n, n / 2)) - val) < 1e-15
+
+
+@pytest.mark.parametrize("kind,m", [(oracle.WIN_BSPLINE, 3), (oracle.WIN_BSPLINE, 8),
+                                    (oracle.WIN_ALGEBRAIC, 2), (oracle.WIN_ALGEBRAIC, 6),
+                                    (oracle.WIN_ALGEBRAIC, 12)])
+def test_window_transforms_against_quadrature(kind, m):
+    beta = 3.0 * m if kind == oracle.WIN_ALGEBRAIC else 0.0
+    w = lambda x: float(oracle.window(kind, x, m, beta))
+    assert w(0.0) == pytest.approx(1.0, abs=1e-15)
+    assert w(1.0) == 0.0 and w(-1.0) == 0.0
+    assert w(0.37) == pytest.approx(w(-0.37), abs=1e-15)
+    for v in (0.0, 0.25, 0.9, m / 2.5, m / 2.0):
+        ref, _ = scipy.integrate.quad(lambda x: 2.0 * w(x) * math.cos(2 * math.pi * v * x), 0, 1,
+                                      epsabs=1e-16, epsrel=1e-13, limit=400)
+        got = float(oracle.window_hat(kind, v, m, beta))
+        assert abs(got - ref) <= 1e-12 * abs(ref) + 1e-16, (v, got, ref)   # quad: epsabs 1e-16
+
+
+@pytest.mark.parametrize("m", [2, 5, 8, 16])
+def test_algebraic_transform_against_scipy_bessel(m):
+    import scipy.special as sp
+    beta = 3 * m
+    C = math.pi * math.exp(math.lgamma(2 * beta + 1) - beta * math.log(4) - math.lgamma(beta + 1))
+    assert float(oracle.window_hat(oracle.WIN_ALGEBRAIC, 0.0, m, beta)) == pytest.approx(
+        C / math.factorial(beta), rel=1e-13)
+    # the NNFFT evaluates the transform for |v| <= m / (2 sigma) < m / 2
+    for v in np.linspace(0.05, m / 2, 9):
+        ref = C * (math.pi * v) ** (-beta) * sp.jv(beta, 2 * math.pi * v)
+        assert float(oracle.window_hat(oracle.WIN_ALGEBRAIC, v, m, beta)) == pytest.approx(ref, rel=1e-11)
+
+
+def test_bspline_transform_is_a_power_of_sinc():
+    for m in (2, 4, 7):
+        b0 = float(oracle.bspline_cardinal(2 * m, m))
+        for v in (0.0, 0.4, 1.7, m - 0.01):
+            ref = np.sinc(v / m) ** (2 * m) / (m * b0)
+            assert float(oracle.window_hat(oracle.WIN_BSPLINE, v, m, 0.0)) == pytest.approx(ref, rel=1e-13)
+
+
+def test_window_family_parameters():
+    P = oracle.params(100, 2.0, 2.0, 5, 7, oracle.WIN_ALGEBRAIC)
+    assert (P.beta1, P.beta2, P.window) == (15.0, 21.0, oracle.WIN_ALGEBRAIC)
+    assert oracle.params(100, 2.0, 2.0, 5, 7, oracle.WIN_BSPLINE).beta1 == 0.0
+    S = oracle.params(100, 2.0, 2.0, 5, 7)
+    assert oracle.params(100, 2.0, 2.0, 5, 7, oracle.WIN_BSPLINE).N2 == S.N2
+    with pytest.raises(ValueError):      # the algebraic window needs sigma > pi/3
+        oracle.params(100, 1.02, 2.0, 5, 5, oracle.WIN_ALGEBRAIC)
+
+
+@pytest.mark.parametrize("kind", [oracle.WIN_BSPLINE, oracle.WIN_ALGEBRAIC])
+@pytest.mark.parametrize("sigma", [1.5, 2.0])
+def test_nnfft_other_windows_against_direct_sum(kind, sigma):
+    # Theorem 3.5 with Theorem 3.4's constants bounds the error; the error
+    # decays geometrically in m and reaches 1e-9 at m = 12
+    g = _rng(71)
+    N, M1, M2 = 128, 700, 500
+    v, x = g.uniform(-0.5, 0.5, M1), g.uniform(-0.5, 0.5, M2)
+    f = g.standard_normal(M1) + 1j * g.standard_normal(M1)
+    ex = oracle.direct(N, v, f, x)
+    sf = np.abs(f).sum()
+    errs = []
+    for m in (4, 6, 8, 10, 12):
+        y = oracle.nnfft(N, v, f, x, sigma, sigma, m, m, window=kind)
+        e = np.abs(y - ex).max() / sf
+        assert e <= oracle.bound_thm35(kind, N, sigma, sigma, m, m)
+        errs.append(e)
+    for a, b in zip(errs, errs[1:]):
+        assert b < a / 3            # each step of 2 in m gains at least a factor 3
+    assert errs[-1] < 1e-8
