@@ -76,6 +76,21 @@ typedef enum {
     SINC_QUAD_CLENSHAW_CURTIS = 1   /* Chebyshev points, n_quad + 1 nodes, (5.4)     */
 } sinc_quad;
 
+/*
+ * Window families of Example 2.1 (both windows of a plan are of one family):
+ *   SINH       sinh(beta sqrt(1 - x^2)) / sinh(beta), beta_j = 2 pi m_j (1 - 1/(2 sigma_j));
+ *   BSPLINE    B_2m(m x) / B_2m(0), B_2m the centred cardinal B-spline of order 2m,
+ *              transform sinc(pi v / m)^(2m) / (m B_2m(0));
+ *   ALGEBRAIC  (1 - x^2)^(beta - 1/2) on [-1, 1], beta_j = 3 m_j, transform
+ *              pi (2 beta)! / (4^beta beta!) (pi v)^(-beta) J_beta(2 pi v); needs
+ *              sigma_j > pi/3.
+ */
+typedef enum {
+    NNFFT_WINDOW_SINH = 0,
+    NNFFT_WINDOW_BSPLINE = 1,
+    NNFFT_WINDOW_ALGEBRAIC = 2
+} nnfft_window;
+
 /* Derived sizes and diagnostics of a plan (host struct, filled by the library). */
 typedef struct {
     int64_t N, N_star, N1, G1, N2;  /* bandwidth, N*, N1, G1 = N1 + 2 m1, FFT length */
@@ -85,9 +100,11 @@ typedef struct {
     double sigma1, sigma2;          /* requested oversampling factors                */
     double sigma1_eff, sigma2_eff;  /* N1 / N*, N2 / G1 (used in beta and the bound) */
     double a;                       /* (2.6): 1 + 2 m1 / N1                          */
-    double beta1, beta2;            /* 2 pi m_j (1 - 1/(2 sigma_j_eff))              */
-    double bound_thm41;             /* E(phi_sinh) of (4.2) at the effective sigmas  */
-    int32_t thm41_applies;          /* 1 if sigma_eff in [5/4, 2] and m2 >= m1       */
+    double beta1, beta2;            /* sinh: 2 pi m_j (1 - 1/(2 sigma_j_eff));
+                                       algebraic: 3 m_j; B-spline: 0               */
+    double bound_thm41;             /* E(phi_sinh) of (4.2) at the effective sigmas
+                                       (sinh windows; 0 for the others)             */
+    int32_t thm41_applies;          /* 1 if sinh, sigma_eff in [5/4, 2], m2 >= m1    */
     int32_t window_degree;          /* FP32: degree of the per-tap window polynomials*/
     double window_fit_err;          /* FP32: max abs error of those polynomials      */
     int32_t corr_degree;            /* degree of the 1/phi_hat_1 Chebyshev series     */
@@ -98,6 +115,8 @@ typedef struct {
     int32_t spread_workgroups;      /* workgroups of the spreading launch            */
     int32_t interp_workgroups;      /* workgroups of the interpolation launch        */
     int32_t fft_n1, fft_n2;         /* FFT factorization N2 = n1 * n2 (n1 = 1: one WG)*/
+    int32_t window;                 /* nnfft_window of both windows                  */
+    int32_t reserved;
 } nnfft_info_t;
 
 /*
@@ -131,6 +150,21 @@ nnfft_status nnfft_plan(nnfft_plan_t *out, int64_t N, int64_t M1, int64_t M2,
                         const double *v, const double *x, void *stream);
 
 /*
+ * nnfft_plan with windows of family `window` (Example 2.1; nnfft_plan uses
+ * NNFFT_WINDOW_SINH).  Plans of every family run through nnfft_exec,
+ * nnfft_exec_batch and the serving layer alike.  The FP32 path evaluates the
+ * taps of every family from its per-tap Chebyshev series; the FP64 path
+ * evaluates sinh and algebraic taps directly and B-spline taps from the exact
+ * series of their polynomial pieces.  The error of Theorem 3.5 with these
+ * windows is larger than with sinh windows of equal m (Sec. 4 compares them).
+ * Errors: as nnfft_plan, plus ARG for an unknown family or an algebraic
+ * window with sigma_eff <= pi/3.
+ */
+nnfft_status nnfft_plan_window(nnfft_plan_t *out, int64_t N, int64_t M1, int64_t M2,
+                               double sigma1, double sigma2, int m1, int m2, nnfft_precision prec,
+                               nnfft_window window, const double *v, const double *x, void *stream);
+
+/*
  * Host-only dry run of nnfft_plan on HOST node arrays v[M1], x[M2]: the same
  * validations, tables and node layout, then a check of the layout invariants
  * the kernels rely on (every point in exactly one work item, record blocks,
@@ -141,6 +175,11 @@ nnfft_status nnfft_plan(nnfft_plan_t *out, int64_t N, int64_t M1, int64_t M2,
  */
 nnfft_status nnfft_plan_dry_run(int64_t N, int64_t M1, int64_t M2, double sigma1, double sigma2, int m1, int m2,
                                 nnfft_precision prec, const double *v, const double *x, nnfft_info_t *out);
+
+/* nnfft_plan_dry_run for windows of family `window` (as nnfft_plan_window). */
+nnfft_status nnfft_plan_window_dry_run(int64_t N, int64_t M1, int64_t M2, double sigma1, double sigma2, int m1,
+                                       int m2, nnfft_precision prec, nnfft_window window, const double *v,
+                                       const double *x, nnfft_info_t *out);
 
 /*
  * Runs Algorithm 2.2 on `stream`: f[M1] -> y[M2] (c64 or c128 per the plan's

@@ -55,7 +55,7 @@ typedef struct {
     double sigma1, sigma2;
     int32_t m1, m2;
     int32_t quad;          /* sinc: sinc_quad                                            */
-    int32_t reserved;
+    int32_t window;        /* NNFFT: nnfft_window (0: sinh); sinc requests use sinh      */
     int64_t n_quad;        /* sinc: quadrature size                                      */
     const double *v;       /* device FP64 [M1]: frequencies v_k (sinc: a_k)              */
     const double *x;       /* device FP64 [M2]: spatial nodes x_j (sinc: b_l)            */

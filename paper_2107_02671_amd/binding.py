@@ -31,6 +31,7 @@ NNFFT_FP64_PLAIN = 0
 NNFFT_FP32_COMP = 1
 SINC_QUAD_GAUSS_LEGENDRE = 0
 SINC_QUAD_CLENSHAW_CURTIS = 1
+NNFFT_WINDOW_SINH, NNFFT_WINDOW_BSPLINE, NNFFT_WINDOW_ALGEBRAIC = 0, 1, 2
 
 
 class NnfftInfo(ctypes.Structure):
@@ -48,11 +49,11 @@ class NnfftInfo(ctypes.Structure):
         ("device_bytes", ctypes.c_int64), ("block_points", ctypes.c_int64),
         ("items_points", ctypes.c_int32), ("spread_workgroups", ctypes.c_int32),
         ("interp_workgroups", ctypes.c_int32), ("fft_n1", ctypes.c_int32),
-        ("fft_n2", ctypes.c_int32),
+        ("fft_n2", ctypes.c_int32), ("window", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
     def as_dict(self):
-        return {name: getattr(self, name) for name, _ in self._fields_}
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
 
 
 class NnfftTuning(ctypes.Structure):
@@ -73,7 +74,7 @@ class NnfftRequest(ctypes.Structure):
                 ("M1", ctypes.c_int64), ("M2", ctypes.c_int64),
                 ("sigma1", ctypes.c_double), ("sigma2", ctypes.c_double),
                 ("m1", ctypes.c_int32), ("m2", ctypes.c_int32), ("quad", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("n_quad", ctypes.c_int64),
+                ("window", ctypes.c_int32), ("n_quad", ctypes.c_int64),
                 ("v", ctypes.c_void_p), ("x", ctypes.c_void_p), ("f", ctypes.c_void_p), ("y", ctypes.c_void_p),
                 ("plan_key", ctypes.c_uint64)]
 
@@ -125,6 +126,7 @@ def lib():
     vp, i64, dbl, ci = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int
     L.nnfft_derive_params.argtypes = [i64, dbl, dbl, ci, ci, ctypes.POINTER(NnfftInfo)]
     L.nnfft_plan.argtypes = [ctypes.POINTER(vp), i64, i64, i64, dbl, dbl, ci, ci, ci, vp, vp, vp]
+    L.nnfft_plan_window.argtypes = [ctypes.POINTER(vp), i64, i64, i64, dbl, dbl, ci, ci, ci, ci, vp, vp, vp]
     L.nnfft_exec.argtypes = [vp, vp, vp, vp]
     L.nfft_plan.argtypes = [ctypes.POINTER(vp), i64, i64, dbl, ci, ci, vp, vp]
     L.nfft_exec.argtypes = [vp, vp, vp, vp]
@@ -133,6 +135,8 @@ def lib():
     L.nfft_plan_dry_run.argtypes = [i64, i64, dbl, ci, ci, ctypes.POINTER(dbl), ctypes.POINTER(NnfftInfo)]
     L.nnfft_plan_dry_run.argtypes = [i64, i64, i64, dbl, dbl, ci, ci, ci, ctypes.POINTER(dbl), ctypes.POINTER(dbl),
                                      ctypes.POINTER(NnfftInfo)]
+    L.nnfft_plan_window_dry_run.argtypes = [i64, i64, i64, dbl, dbl, ci, ci, ci, ci, ctypes.POINTER(dbl),
+                                            ctypes.POINTER(dbl), ctypes.POINTER(NnfftInfo)]
     L.nnfft_exec_batch.argtypes = [ci, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
     L.nnfft_info.argtypes = [vp, ctypes.POINTER(NnfftInfo)]
     L.nnfft_destroy.argtypes = [vp]
@@ -162,7 +166,7 @@ def lib():
     L.nnfft_last_error.restype = ctypes.c_char_p
     L.nnfft_version.restype = ctypes.c_char_p
     for name in ["nfft_plan", "nfft_exec", "nfft_adjoint", "nfft_destroy", "nfft_plan_dry_run",
-                 "nnfft_plan_dry_run", "nnfft_profile_start", "nnfft_profile_stop", "nnfft_quadrature", "nnfft_derive_params",
+                 "nnfft_plan_dry_run", "nnfft_plan_window", "nnfft_plan_window_dry_run", "nnfft_profile_start", "nnfft_profile_stop", "nnfft_quadrature", "nnfft_derive_params",
                  "nnfft_plan", "nnfft_exec", "nnfft_exec_batch", "nnfft_info", "nnfft_destroy", "sinc_plan",
                  "sinc_exec", "sinc_info", "sinc_sizes", "sinc_destroy", "nnfft_autotune", "nnfft_set_tuning",
                  "nnfft_get_tuning", "nnfft_clear_tuning", "nnfft_server_create", "nnfft_server_submit",
@@ -232,26 +236,40 @@ def _require(t, dtype, n, name):
                          f"got {t.dtype} {tuple(t.shape)} on {t.device}")
 
 
-def nnfft_plan(N, v, x, sigma1=2.0, sigma2=2.0, m1=6, m2=6, prec=NNFFT_FP32_COMP, stream=None):
-    """v, x: float64 CUDA tensors.  Returns an opaque plan handle (c_void_p)."""
+def nnfft_plan(N, v, x, sigma1=2.0, sigma2=2.0, m1=6, m2=6, prec=NNFFT_FP32_COMP, stream=None,
+               window=None):
+    """v, x: float64 CUDA tensors.  Returns an opaque plan handle (c_void_p).
+    window: None (nnfft_plan, sinh windows) or an NNFFT_WINDOW_* family
+    (nnfft_plan_window)."""
     import torch
     _require(v, torch.float64, v.numel(), "v")
     _require(x, torch.float64, x.numel(), "x")
     h = ctypes.c_void_p()
-    _check(lib().nnfft_plan(ctypes.byref(h), int(N), v.numel(), x.numel(), float(sigma1), float(sigma2),
-                            int(m1), int(m2), int(prec), _ptr(v), _ptr(x), _stream(stream)))
+    if window is None:
+        _check(lib().nnfft_plan(ctypes.byref(h), int(N), v.numel(), x.numel(), float(sigma1), float(sigma2),
+                                int(m1), int(m2), int(prec), _ptr(v), _ptr(x), _stream(stream)))
+    else:
+        _check(lib().nnfft_plan_window(ctypes.byref(h), int(N), v.numel(), x.numel(), float(sigma1),
+                                       float(sigma2), int(m1), int(m2), int(prec), int(window), _ptr(v), _ptr(x),
+                                       _stream(stream)))
     return h
 
 
-def nnfft_plan_dry_run(N, v, x, sigma1=2.0, sigma2=2.0, m1=6, m2=6, prec=NNFFT_FP32_COMP) -> dict:
+def nnfft_plan_dry_run(N, v, x, sigma1=2.0, sigma2=2.0, m1=6, m2=6, prec=NNFFT_FP32_COMP, window=None) -> dict:
     """Host-only plan construction and layout check on numpy float64 node arrays."""
     import numpy as np
     v = np.ascontiguousarray(v, dtype=np.float64)
     x = np.ascontiguousarray(x, dtype=np.float64)
     info = NnfftInfo()
     dptr = ctypes.POINTER(ctypes.c_double)
-    _check(lib().nnfft_plan_dry_run(int(N), v.size, x.size, float(sigma1), float(sigma2), int(m1), int(m2),
-                                    int(prec), v.ctypes.data_as(dptr), x.ctypes.data_as(dptr), ctypes.byref(info)))
+    if window is None:
+        _check(lib().nnfft_plan_dry_run(int(N), v.size, x.size, float(sigma1), float(sigma2), int(m1), int(m2),
+                                        int(prec), v.ctypes.data_as(dptr), x.ctypes.data_as(dptr),
+                                        ctypes.byref(info)))
+    else:
+        _check(lib().nnfft_plan_window_dry_run(int(N), v.size, x.size, float(sigma1), float(sigma2), int(m1),
+                                               int(m2), int(prec), int(window), v.ctypes.data_as(dptr),
+                                               x.ctypes.data_as(dptr), ctypes.byref(info)))
     return info.as_dict()
 
 
@@ -425,8 +443,9 @@ def sinc_destroy(plan):
 class Plan:
     """Owning wrapper: Plan(N, v, x, ...) ; plan(f) -> y ; closed on exit/GC."""
 
-    def __init__(self, N, v, x, sigma1=2.0, sigma2=2.0, m1=6, m2=6, prec=NNFFT_FP32_COMP, stream=None):
-        self.handle = nnfft_plan(N, v, x, sigma1, sigma2, m1, m2, prec, stream)
+    def __init__(self, N, v, x, sigma1=2.0, sigma2=2.0, m1=6, m2=6, prec=NNFFT_FP32_COMP, stream=None,
+                 window=None):
+        self.handle = nnfft_plan(N, v, x, sigma1, sigma2, m1, m2, prec, stream, window)
         self.info = nnfft_info(self.handle)
 
     def __call__(self, f, y=None, stream=None):
@@ -515,7 +534,8 @@ def nnfft_server_create(hbm_budget_bytes=0, planner_threads=0, streams=0, max_ba
 
 
 def nnfft_server_submit(server, N, v, x, f, y, sigma1=2.0, sigma2=2.0, m1=6, m2=6, prec=NNFFT_FP32_COMP,
-                        kind=NNFFT_REQ_NNFFT, quad=SINC_QUAD_GAUSS_LEGENDRE, n_quad=0, plan_key=0) -> int:
+                        kind=NNFFT_REQ_NNFFT, quad=SINC_QUAD_GAUSS_LEGENDRE, n_quad=0, plan_key=0,
+                        window=0) -> int:
     """v, x: float64 CUDA tensors; f, y: complex CUDA tensors of the plan's
     precision.  The tensors must stay alive until the result is taken."""
     import torch
@@ -525,7 +545,7 @@ def nnfft_server_submit(server, N, v, x, f, y, sigma1=2.0, sigma2=2.0, m1=6, m2=
     _require(f, dt, v.numel(), "f")
     _require(y, dt, x.numel(), "y")
     r = NnfftRequest(int(kind), int(prec), int(N), v.numel(), x.numel(), float(sigma1), float(sigma2),
-                     int(m1), int(m2), int(quad), 0, int(n_quad), v.data_ptr(), x.data_ptr(), f.data_ptr(),
+                     int(m1), int(m2), int(quad), int(window), int(n_quad), v.data_ptr(), x.data_ptr(), f.data_ptr(),
                      y.data_ptr(), int(plan_key))
     t = ctypes.c_uint64()
     _check(lib().nnfft_server_submit(server, ctypes.byref(r), ctypes.byref(t)))

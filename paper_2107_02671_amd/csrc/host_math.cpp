@@ -158,8 +158,93 @@ double cheb_eval(const double *c, int deg, double t)
     return c[0] + t * b1 - b2;
 }
 
-std::vector<double> fit_window_taps(int m, double beta, int deg, double *max_err)
+// ---------------------------------------------------------------------------
+// Window families of Example 2.1
+// ---------------------------------------------------------------------------
+
+// Cardinal B-spline of order n (support [0, n]) at z: with j = floor(z) and
+// d = z - j, the n values M_n(d + i), i = 0..n-1, are built from M_1(d + i) =
+// [i == 0] by M_{k+1}(y) = (y M_k(y) + (k + 1 - y) M_k(y - 1)) / k, and
+// M_n(z) is the one with i = j.
+static double bspline_cardinal(int n, double z)
 {
+    if (!(z > 0.0) || !(z < (double)n)) return 0.0;
+    const int j = (int)std::floor(z);
+    const double d = z - j;
+    double val[2 * kMaxM + 1] = {1.0};
+    for (int k = 1; k < n; ++k) {
+        val[k] = 0.0;
+        for (int i = k; i >= 0; --i) {
+            const double y = d + i;
+            val[i] = (y * val[i] + (i > 0 ? ((double)(k + 1) - y) * val[i - 1] : 0.0)) / (double)k;
+        }
+    }
+    return val[j];
+}
+
+Window make_window(int kind, int m, double beta)
+{
+    Window w;
+    w.kind = kind;
+    w.m = m;
+    w.beta = beta;
+    if (kind == NNFFT_WINDOW_BSPLINE) w.norm = 1.0 / bspline_cardinal(2 * m, (double)m);
+    return w;
+}
+
+double window_value(const Window &w, double u)
+{
+    switch (w.kind) {
+    case NNFFT_WINDOW_BSPLINE:
+        // B_2m(m u) / B_2m(0), B_2m(x) = M_2m(x + m)
+        return std::fabs(u) < 1.0 ? bspline_cardinal(2 * w.m, w.m * (u + 1.0)) * w.norm : 0.0;
+    case NNFFT_WINDOW_ALGEBRAIC: {
+        const double q = (1.0 - u) * (1.0 + u);
+        return q > 0.0 ? std::pow(q, w.beta - 0.5) : 0.0;
+    }
+    default:
+        return window_sinh(u, w.beta);
+    }
+}
+
+// (pi v)^(-b) J_b(2 pi v) for integer b: its power series where the argument
+// is small against the order, else the library Bessel function.
+static double bessel_ratio(double b, double v)
+{
+    const double a = kPi * std::fabs(v);
+    if (a * a <= b + 1.0) {
+        // sum_k (-1)^k a^(2k) / (k! (k + b)!), nested from the last kept term
+        const int K = 40;
+        double acc = 1.0;
+        for (int k = K; k >= 1; --k) acc = 1.0 - acc * a * a / ((double)k * ((double)k + b));
+        return acc * std::exp(-std::lgamma(b + 1.0));
+    }
+    return std::cyl_bessel_j(b, 2.0 * a) * std::exp(-b * std::log(a));
+}
+
+double window_hat(const Window &w, double v)
+{
+    switch (w.kind) {
+    case NNFFT_WINDOW_BSPLINE: {
+        // sinc(pi v / m)^(2m) / (m B_2m(0))
+        const double t = kPi * v / w.m;
+        const double s = t == 0.0 ? 1.0 : std::sin(t) / t;
+        return std::pow(s, 2.0 * w.m) * w.norm / (double)w.m;
+    }
+    case NNFFT_WINDOW_ALGEBRAIC: {
+        // pi (2b)! / (4^b b!) (pi v)^(-b) J_b(2 pi v)
+        const double b = w.beta;
+        const double lc = std::log(kPi) + std::lgamma(2.0 * b + 1.0) - b * std::log(4.0) - std::lgamma(b + 1.0);
+        return std::exp(lc) * bessel_ratio(b, v);
+    }
+    default:
+        return window_sinh_hat(v, w.beta);
+    }
+}
+
+std::vector<double> fit_window_taps(const Window &w, int deg, double *max_err)
+{
+    const int m = w.m;
     std::vector<double> out((size_t)(2 * m) * (deg + 1));
     const std::vector<double> tn = cheb_nodes(deg);
     double worst = 0.0;
@@ -167,14 +252,14 @@ std::vector<double> fit_window_taps(int m, double beta, int deg, double *max_err
         std::vector<double> f(deg + 1);
         for (int j = 0; j <= deg; ++j) {
             const double x = 0.5 * (tn[j] + 1.0);
-            f[j] = window_sinh((r - m + 1 - x) / m, beta);
+            f[j] = window_value(w, (r - m + 1 - x) / m);
         }
         std::vector<double> c = cheb_fit(deg, f);
         for (int k = 0; k <= deg; ++k) out[(size_t)r * (deg + 1) + k] = c[k];
         for (int i = 0; i <= 500; ++i) {   // the error of a degree-8 fit has 9 lobes
             const double x = i / 500.0;
             const double e = std::fabs(cheb_eval(c.data(), deg, 2.0 * x - 1.0) -
-                                       window_sinh((r - m + 1 - x) / m, beta));
+                                       window_value(w, (r - m + 1 - x) / m));
             worst = std::max(worst, e);
         }
     }
@@ -186,9 +271,10 @@ std::vector<double> fit_inverse_phi1(const nnfft_info_t &P, double tol, int max_
                                      double *max_rel_err)
 {
     // phi_hat_1(N* x) = (m1/N1) omega_hat_1(m1 N* x / N1)
+    const Window w1 = make_window(P.window, P.m1, P.beta1);
     auto inv = [&](double x) {
         const double v = (double)P.m1 * (double)P.N_star * x / (double)P.N1;
-        return 1.0 / ((double)P.m1 / (double)P.N1 * window_sinh_hat(v, P.beta1));
+        return 1.0 / ((double)P.m1 / (double)P.N1 * window_hat(w1, v));
     };
     // reference values on the check grid, shared by every degree tried
     constexpr int kGrid = 1000;

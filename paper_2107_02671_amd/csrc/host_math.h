@@ -27,15 +27,30 @@ std::vector<double> cheb_fit(int deg, const std::vector<double> &fvals_at_nodes)
 std::vector<double> cheb_nodes(int deg);
 double cheb_eval(const double *c, int deg, double t);
 
-// FP32 path: tap r (0 <= r < 2m) of a point at fractional offset x in [0, 1)
-// of its cell carries the weight omega((r - m + 1 - x) / m); as a function of
-// t = 2x - 1 it is fitted by a degree-kDeg Chebyshev series.  Returns the
-// [2m][deg+1] coefficients and the max abs error on a fine grid.
-std::vector<double> fit_window_taps(int m, double beta, int deg, double *max_err);
+// A window of Example 2.1 (family nnfft_window) with its parameters.
+struct Window {
+    int kind = NNFFT_WINDOW_SINH;
+    int m = 2;
+    double beta = 0.0;    // sinh: shape parameter; algebraic: exponent parameter (3m)
+    double norm = 1.0;    // B-spline: 1 / M_2m(m), the value at 0 of the unscaled spline
+};
+Window make_window(int kind, int m, double beta);
+// omega(u) of the family, 0 for |u| >= 1.
+double window_value(const Window &w, double u);
+// Its Fourier transform for |v| <= m/2 (the algorithm needs |v| <= m/(2 sigma)).
+double window_hat(const Window &w, double v);
+
+// Tap r (0 <= r < 2m) of a point at fractional offset x in [0, 1) of its cell
+// carries the weight omega((r - m + 1 - x) / m); as a function of t = 2x - 1
+// it is fitted by a degree-`deg` Chebyshev series (FP32 path: degree kDeg;
+// FP64 path with B-spline windows: degree 2m - 1, where each tap is one
+// polynomial piece and the series is exact).  Returns the [2m][deg+1]
+// coefficients and the max abs error on a fine grid.
+std::vector<double> fit_window_taps(const Window &w, int deg, double *max_err);
 
 // Chebyshev series of 1/phi_hat_1(N* x) in t = 8 x^2 - 1, |x| <= 1/2, of the
 // smallest degree <= max_deg whose max relative error is <= tol (else the
-// best found; *max_rel_err tells).
+// best found; *max_rel_err tells).  The window is P.window with m1, beta1.
 std::vector<double> fit_inverse_phi1(const nnfft_info_t &P, double tol, int max_deg,
                                      double *max_rel_err);
 

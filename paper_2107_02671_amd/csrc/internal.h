@@ -55,10 +55,12 @@ struct SpreadArgs {
     const int32_t *perm;      // FP64 path: caller's index
     const double *frac64;     // FP64 path: offset in the cell
     const float *C;           // FP32 path: [2m][kDeg + 1] tap coefficients
+    const double *T64;        // FP64 path, B-spline windows: [2m][2m] exact tap series
     void *partial;            // chunk windows: float4 (hi, lo) or double2
-    double beta, inv_den;     // FP64 path window: beta, 1 / (1 - exp(-2 beta))
+    double beta, inv_den;     // FP64 path window: beta, 1 / (1 - exp(-2 beta)) (sinh)
     int32_t m, ngrid;
-    int32_t rows, pad;        // FP32 path: record rows per slot (max points per item)
+    int32_t rows;             // FP32 path: record rows per slot (max points per item)
+    int32_t window;           // nnfft_window
 };
 
 // Steps 2-3 (merge, 1/phi_hat_2, FFT) arguments of one plan.
@@ -95,6 +97,7 @@ struct InterpArgs {
     const int32_t *perm;
     const double *frac64;
     const float *C;           // FP32 path: [2m][kDeg + 1] tap coefficients
+    const double *T64;        // FP64 path, B-spline windows: [2m][2m] exact tap series
     const double *corr;       // series of 1/phi_hat_1 in t = 8 x^2 - 1 (FP32: kCorr32 + 1 terms)
     const void *hlin;
     double beta, inv_den;
@@ -103,7 +106,8 @@ struct InterpArgs {
     int32_t N2, ip_off;       // bin storage index = floor(u_j) + ip_off
     int32_t corr_deg;
     int32_t rows;             // FP32 path: record rows per slot
-    int32_t h_off, pad;       // hlin index of label 0
+    int32_t h_off;            // hlin index of label 0
+    int32_t window;           // nnfft_window
 };
 
 struct PlanDev {

@@ -99,6 +99,30 @@ __device__ __forceinline__ double cheb64(const double *__restrict__ c, int deg, 
     return fma(t, b1, c[0] - b2);
 }
 
+// Weight of tap r (0 <= r < 2m) of a point at offset x in [0, 1) of its cell
+// in the FP64 kernels: omega(u) with u = (r - m + 1 - x) / m (the caller may
+// pass -u: every window is even), for the window families of Example 2.1:
+//   sinh       exp form above;
+//   B-spline   tap r is one polynomial piece of degree 2m - 1 in x, stored as
+//              its exact Chebyshev series in 2x - 1 (T: [2m][2m]);
+//   algebraic  (1 - u^2)^(beta - 1/2) = q^(beta - 1) sqrt(q), beta = 3m integer.
+__device__ __forceinline__ double tap64(int window, const double *__restrict__ T, int r, int m, double x,
+                                        double u, double beta, double inv_den)
+{
+    if (window == NNFFT_WINDOW_BSPLINE) return cheb64(T + r * 2 * m, 2 * m - 1, fma(2.0, x, -1.0));
+    if (window == NNFFT_WINDOW_ALGEBRAIC) {
+        const double q = (1.0 - u) * (1.0 + u);
+        if (!(q > 0.0)) return 0.0;
+        double p = 1.0, b = q;
+        for (int e = (int)beta - 1; e > 0; e >>= 1) {
+            if (e & 1) p *= b;
+            b *= b;
+        }
+        return p * sqrt(q);
+    }
+    return omega64(u, beta, inv_den);
+}
+
 // 1/phi_hat_1(N* x_j) from its FP64 Chebyshev series in t = 8 x^2 - 1, with
 // x_j reconstructed in FP64 from the bin label and the cell offset.
 template <int CD>
@@ -364,7 +388,8 @@ __device__ void spread64_slot(const SpreadArgs &A, const cx<double> *__restrict_
 #pragma unroll
             for (int q = 0; q < Q64; ++q) {
                 if (q < it.n) {
-                    const double w = omega64(((double)(r - m + 1) - xf[q]) * inv_m, A.beta, A.inv_den);
+                    const double w = tap64(A.window, A.T64, r, m, xf[q], ((double)(r - m + 1) - xf[q]) * inv_m,
+                                           A.beta, A.inv_den);
                     ar = fma(fv[q].re, w, ar);
                     ai = fma(fv[q].im, w, ai);
                 }
@@ -554,7 +579,8 @@ __device__ void interp64_slot(const InterpArgs &A, cx<double> *__restrict__ y, i
             const double fr = A.frac64[p];
             double sr = 0.0, si = 0.0;
             for (int r = 0; r < tm; ++r) {
-                const double w = omega64((fr + (double)(m - 1 - r)) * inv_m, A.beta, A.inv_den);
+                const double w = tap64(A.window, A.T64, r, m, fr, (fr + (double)(m - 1 - r)) * inv_m, A.beta,
+                                       A.inv_den);
                 const cx<double> hv = L.hw[r * kItemsPerWg + b];
                 sr = fma(hv.re, w, sr);
                 si = fma(hv.im, w, si);

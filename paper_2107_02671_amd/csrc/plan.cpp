@@ -368,14 +368,16 @@ void layout_plan(const HostPlan &H, Carver &C, PlanDev &D, size_t *upload_end, P
     SA.chunks = C.put(H.sp.launch);
     SA.ngrid = (int32_t)H.sp.launch.size();
     SA.m = P.m1;
+    SA.window = P.window;
     SA.beta = P.beta1;
-    SA.inv_den = 1.0 / (1.0 - std::exp(-2.0 * P.beta1));
+    SA.inv_den = P.window == NNFFT_WINDOW_SINH ? 1.0 / (1.0 - std::exp(-2.0 * P.beta1)) : 0.0;
     IA.items = C.put(H.ip.launch_items);
     IA.chunks = C.put(H.ip.launch);
     IA.ngrid = (int32_t)H.ip.launch.size();
     IA.m = P.m2;
+    IA.window = P.window;
     IA.beta = P.beta2;
-    IA.inv_den = 1.0 / (1.0 - std::exp(-2.0 * P.beta2));
+    IA.inv_den = P.window == NNFFT_WINDOW_SINH ? 1.0 / (1.0 - std::exp(-2.0 * P.beta2)) : 0.0;
     IA.N2 = (int32_t)P.N2;
     IA.ip_off = (int32_t)(P.N2 / 2);
     IA.u_to_x = (double)P.N1 / ((double)P.N2 * (double)P.N_star);
@@ -391,6 +393,10 @@ void layout_plan(const HostPlan &H, Carver &C, PlanDev &D, size_t *upload_end, P
         SA.frac64 = C.put(H.sp.frac64);
         IA.perm = C.put(H.ip.perm);
         IA.frac64 = C.put(H.ip.frac64);
+        if (!H.T1.empty()) {
+            SA.T64 = C.put(H.T1);
+            IA.T64 = C.put(H.T2);
+        }
     }
     FA.merge_off = C.put(H.moff);
     FA.merge_idx = C.put(H.midx);
@@ -539,12 +545,28 @@ static void size_plan(HostPlan &H, const nnfft_info_t &P)
 
 nnfft_status plan_host(HostPlan &H, int64_t N, int64_t M1, int64_t M2, double sigma1, double sigma2,
                        int m1, int m2, nnfft_precision prec, const std::vector<double> &v,
-                       const std::vector<double> &x, const Layout *lay1, const Layout *lay2)
+                       const std::vector<double> &x, const Layout *lay1, const Layout *lay2, int window)
 {
     nnfft_info_t P;
     nnfft_status st = derive_params(N, sigma1, sigma2, m1, m2, &P);
     if (st != NNFFT_OK) return fail(st, "invalid NNFFT parameters (N >= 1, m >= 2, sigma > 1, "
                                         "2 m1 < N1 and 2 m2 <= (1 - 1/sigma1) N2 are required)");
+    // window family (Example 2.1): shape parameters and the sinh-only bound
+    P.window = window;
+    if (window == NNFFT_WINDOW_BSPLINE) {
+        P.beta1 = P.beta2 = 0.0;
+    } else if (window == NNFFT_WINDOW_ALGEBRAIC) {
+        if (!(P.sigma1_eff > kPi / 3.0) || !(P.sigma2_eff > kPi / 3.0))
+            return fail(NNFFT_ERR_ARG, "the algebraic window needs sigma > pi/3");
+        P.beta1 = 3.0 * m1;
+        P.beta2 = 3.0 * m2;
+    } else if (window != NNFFT_WINDOW_SINH) {
+        return fail(NNFFT_ERR_ARG, "unknown window family");
+    }
+    if (window != NNFFT_WINDOW_SINH) {
+        P.bound_thm41 = 0.0;
+        P.thm41_applies = 0;
+    }
     if (M1 < 1 || M2 < 1 || M1 > ((int64_t)1 << 30) || M2 > ((int64_t)1 << 30))
         return fail(NNFFT_ERR_ARG, "node counts must be in [1, 2^30]");
     if (prec != NNFFT_FP64_PLAIN && prec != NNFFT_FP32_COMP) return fail(NNFFT_ERR_ARG, "unknown precision");
@@ -569,14 +591,21 @@ nnfft_status plan_host(HostPlan &H, int64_t N, int64_t M1, int64_t M2, double si
     // tables in FP64 -----------------------------------------------------
     double e1 = 0.0, e2 = 0.0;
     if (fp32) {
-        const std::vector<double> c1 = fit_window_taps(m1, P.beta1, kDeg, &e1);
-        const std::vector<double> c2 = fit_window_taps(m2, P.beta2, kDeg, &e2);
+        const std::vector<double> c1 = fit_window_taps(make_window(P.window, m1, P.beta1), kDeg, &e1);
+        const std::vector<double> c2 = fit_window_taps(make_window(P.window, m2, P.beta2), kDeg, &e2);
         P.window_degree = kDeg;
         P.window_fit_err = std::max(e1, e2);
         if (e1 > tap_fit_tolerance(m1, P.sigma1_eff) || e2 > tap_fit_tolerance(m2, P.sigma2_eff))
             return fail(NNFFT_ERR_UNSUPPORTED, "window polynomial misses FP32 accuracy for these sigma, m");
         H.C1.assign(c1.begin(), c1.end());
         H.C2.assign(c2.begin(), c2.end());
+    } else if (window == NNFFT_WINDOW_BSPLINE) {
+        // each tap is one polynomial piece of degree 2m - 1: its series is exact
+        double t1 = 0.0, t2 = 0.0;
+        H.T1 = fit_window_taps(make_window(window, m1, 0.0), 2 * m1 - 1, &t1);
+        H.T2 = fit_window_taps(make_window(window, m2, 0.0), 2 * m2 - 1, &t2);
+        if (std::max(t1, t2) > 1e-14)
+            return fail(NNFFT_ERR_UNSUPPORTED, "B-spline tap series inexact");
     }
     double corr_err = 0.0;
     H.corr = fit_inverse_phi1(P, fp32 ? 1e-9 : 1e-14, fp32 ? kCorr32 : kMaxCorrDeg, &corr_err);
@@ -586,10 +615,11 @@ nnfft_status plan_host(HostPlan &H, int64_t N, int64_t M1, int64_t M2, double si
         return fail(NNFFT_ERR_UNSUPPORTED, "1/phi_hat_1 series does not converge for this sigma1");
     if (fp32) H.corr.resize(kCorr32 + 1, 0.0);   // zero-padded to the unrolled length
 
+    const Window w2 = make_window(P.window, m2, P.beta2);
     H.deconv.resize(P.G1);
     for (int64_t c = 0; c <= P.G1 / 2; ++c) {   // phi_hat_2 is even: label -l shares the value of l
         const double l = (double)(P.G1 / 2 - c);
-        const double phi2 = (double)m2 / (double)P.N2 * window_sinh_hat(m2 * l / (double)P.N2, P.beta2);
+        const double phi2 = (double)m2 / (double)P.N2 * window_hat(w2, m2 * l / (double)P.N2);
         const double d = 1.0 / ((double)P.N1 * (double)P.N2 * phi2);
         H.deconv[c] = d;                                  // label -l
         if (c > 0 && P.G1 / 2 + (P.G1 / 2 - c) < P.G1) H.deconv[P.G1 / 2 + (P.G1 / 2 - c)] = d;   // label +l
@@ -676,7 +706,7 @@ nnfft_status nfft_plan_host(HostPlan &H, int64_t N, int64_t M, double sigma, int
     H.fp32 = fp32;
     if (fp32) {
         double e = 0.0;
-        const std::vector<double> c = fit_window_taps(m, P.beta1, kDeg, &e);
+        const std::vector<double> c = fit_window_taps(make_window(NNFFT_WINDOW_SINH, m, P.beta1), kDeg, &e);
         P.window_degree = kDeg;
         P.window_fit_err = e;
         if (e > tap_fit_tolerance(m, P.sigma1_eff))
@@ -971,6 +1001,13 @@ nnfft_status nnfft_plan(nnfft_plan_t *out, int64_t N, int64_t M1, int64_t M2, do
                         double sigma2, int m1, int m2, nnfft_precision prec, const double *v,
                         const double *x, void *stream)
 {
+    return nnfft_plan_window(out, N, M1, M2, sigma1, sigma2, m1, m2, prec, NNFFT_WINDOW_SINH, v, x, stream);
+}
+
+nnfft_status nnfft_plan_window(nnfft_plan_t *out, int64_t N, int64_t M1, int64_t M2, double sigma1,
+                               double sigma2, int m1, int m2, nnfft_precision prec, nnfft_window window,
+                               const double *v, const double *x, void *stream)
+{
     if (!out) return fail(NNFFT_ERR_ARG, "null plan pointer");
     *out = nullptr;
     if (M1 < 1 || M2 < 1 || M1 > ((int64_t)1 << 30) || M2 > ((int64_t)1 << 30))
@@ -985,7 +1022,7 @@ nnfft_status nnfft_plan(nnfft_plan_t *out, int64_t N, int64_t M1, int64_t M2, do
         st = copy_nodes(x, M2, hx, s);
         if (st != NNFFT_OK) return st;
         HostPlan H;
-        st = plan_host(H, N, M1, M2, sigma1, sigma2, m1, m2, prec, hv, hx);
+        st = plan_host(H, N, M1, M2, sigma1, sigma2, m1, m2, prec, hv, hx, nullptr, nullptr, window);
         if (st != NNFFT_OK) return st;
         return plan_create(H, hip_mem(), s, out);
     } catch (const std::bad_alloc &) {
@@ -996,13 +1033,20 @@ nnfft_status nnfft_plan(nnfft_plan_t *out, int64_t N, int64_t M1, int64_t M2, do
 nnfft_status nnfft_plan_dry_run(int64_t N, int64_t M1, int64_t M2, double sigma1, double sigma2, int m1, int m2,
                                 nnfft_precision prec, const double *v, const double *x, nnfft_info_t *out)
 {
+    return nnfft_plan_window_dry_run(N, M1, M2, sigma1, sigma2, m1, m2, prec, NNFFT_WINDOW_SINH, v, x, out);
+}
+
+nnfft_status nnfft_plan_window_dry_run(int64_t N, int64_t M1, int64_t M2, double sigma1, double sigma2, int m1,
+                                       int m2, nnfft_precision prec, nnfft_window window, const double *v,
+                                       const double *x, nnfft_info_t *out)
+{
     if (!v || !x || !out) return fail(NNFFT_ERR_ARG, "null argument");
     if (M1 < 1 || M2 < 1 || M1 > ((int64_t)1 << 30) || M2 > ((int64_t)1 << 30))
         return fail(NNFFT_ERR_ARG, "node counts must be in [1, 2^30]");
     try {
         std::vector<double> hv(v, v + M1), hx(x, x + M2);
         HostPlan H;
-        nnfft_status st = plan_host(H, N, M1, M2, sigma1, sigma2, m1, m2, prec, hv, hx);
+        nnfft_status st = plan_host(H, N, M1, M2, sigma1, sigma2, m1, m2, prec, hv, hx, nullptr, nullptr, window);
         if (st != NNFFT_OK) return st;
         st = check_plan(H, hv, hx);
         if (st != NNFFT_OK) return st;

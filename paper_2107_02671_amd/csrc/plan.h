@@ -63,6 +63,7 @@ struct HostPlan {
     Layout lay1{}, lay2{};
     SideHost sp, ip;
     std::vector<float> C1, C2;         // FP32: window tap series of both sides
+    std::vector<double> T1, T2;        // FP64 B-spline windows: exact tap series of both sides
     std::vector<double> corr;          // series of 1/phi_hat_1
     std::vector<double> deconv;        // 1 / (N1 N2 phi_hat_2(l))
     std::vector<double> tw64;          // FFT twiddles
@@ -121,7 +122,7 @@ namespace nnfft {
 nnfft_status plan_host(HostPlan &H, int64_t N, int64_t M1, int64_t M2, double sigma1, double sigma2,
                        int m1, int m2, nnfft_precision prec, const std::vector<double> &v,
                        const std::vector<double> &x, const Layout *lay1 = nullptr,
-                       const Layout *lay2 = nullptr);
+                       const Layout *lay2 = nullptr, int window = NNFFT_WINDOW_SINH);
 
 // NFFT with equispaced frequencies k in I_N at nodes x[M] (host copies):
 // the same layout machinery with one node set on both sides.

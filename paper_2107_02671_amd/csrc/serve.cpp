@@ -133,7 +133,8 @@ bool same_shape(const nnfft_request_t &a, const nnfft_request_t &b)
 {
     return a.kind == b.kind && a.precision == b.precision && a.N == b.N && a.M1 == b.M1 && a.M2 == b.M2 &&
            a.sigma1 == b.sigma1 && a.sigma2 == b.sigma2 && a.m1 == b.m1 && a.m2 == b.m2 &&
-           (a.kind != NNFFT_REQ_SINC || (a.quad == b.quad && a.n_quad == b.n_quad));
+           (a.kind != NNFFT_REQ_SINC || (a.quad == b.quad && a.n_quad == b.n_quad)) &&
+           (a.kind == NNFFT_REQ_SINC || a.window == b.window);
 }
 
 }  // namespace
@@ -299,7 +300,7 @@ void nnfft_server_s::planner_loop()
                                            r.m1, r.m2, (nnfft_precision)r.precision, hv, hx);
                     else
                         status = plan_host(H, r.N, r.M1, r.M2, r.sigma1, r.sigma2, r.m1, r.m2,
-                                           (nnfft_precision)r.precision, hv, hx);
+                                           (nnfft_precision)r.precision, hv, hx, nullptr, nullptr, r.window);
                 }
                 if (status != NNFFT_OK) err = nnfft_last_error();
                 // arena blocks are 256-byte granular: one per NNFFT plan, three per sinc plan

@@ -1,0 +1,149 @@
+"""GPU parity of the NNFFT with the B-spline and algebraic windows of
+Example 2.1 (nnfft_plan_window) against the FP64 oracle with the same windows.
+
+Tolerance (E_inf against max |oracle|): 1e-12 (FP64) or 1e-5 (FP32) times
+max(1, kappa / 4.62) with kappa = max_j omega_hat_j(0) / omega_hat_j(m_j /
+(2 sigma_j)) of the family, as for the sinh windows: the two phi_hat divisions
+amplify the rounding of the length-N2 FFT by up to kappa.  Against the
+direct sum (1.2) the error stays within Theorem 3.5 with Theorem 3.4's
+constants.  Plans of every family mix in one batched launch bitwise equal
+to their single runs, and the server runs requests of each family.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2107_02671_amd as P
+from paper_2107_02671_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FP64, FP32 = P.NNFFT_FP64_PLAIN, P.NNFFT_FP32_COMP
+BSPL, ALG = P.NNFFT_WINDOW_BSPLINE, P.NNFFT_WINDOW_ALGEBRAIC
+DEV = "cuda:0"
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _kappa(kind, N, s1, s2, m1, m2):
+    Pp = oracle.params(N, s1, s2, m1, m2, kind)
+    k = [oracle.window_hat(kind, 0.0, m, b) / oracle.window_hat(kind, m / (2 * s), m, b)
+         for m, b, s in ((m1, Pp.beta1, Pp.sigma1_eff), (m2, Pp.beta2, Pp.sigma2_eff))]
+    return float(max(k))
+
+
+def _tol(prec, kind, N, s1, s2, m1, m2):
+    return (1e-12 if prec == FP64 else 1e-5) * max(1.0, _kappa(kind, N, s1, s2, m1, m2) / 4.62)
+
+
+CASES = [
+    # N, M1, M2, sigma1, sigma2, m1, m2
+    (64, 256, 256, 2.0, 2.0, 4, 4),
+    (200, 12345, 9999, 2.0, 2.0, 6, 6),
+    (333, 20001, 7777, 1.5, 2.0, 8, 10),
+    (100, 777, 501, 1.5, 1.5, 5, 7),
+    (4096, 1 << 17, 1 << 17, 2.0, 2.0, 6, 6),
+    (150, 5000, 5001, 2.0, 2.0, 12, 12),
+]
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+@pytest.mark.parametrize("kind", [BSPL, ALG], ids=["bspline", "algebraic"])
+@pytest.mark.parametrize("case", CASES, ids=[f"N{c[0]}_m{c[5]}_{c[6]}" for c in CASES])
+def test_window_parity(case, kind, prec):
+    N, M1, M2, s1, s2, m1, m2 = case
+    g = W.rng(900 + N + m1)
+    v, x, f = W.uniform_nodes(g, M1), W.uniform_nodes(g, M2), W.complex_gaussian(g, M1)
+    v[:2], x[:2] = (-0.5, 0.5), (0.5, -0.5)
+    _say(f"[gpu] window {kind} N={N} M=({M1},{M2}) sigma=({s1},{s2}) m=({m1},{m2}) prec={prec}")
+    cdt = torch.complex64 if prec == FP32 else torch.complex128
+    with P.Plan(N, torch.tensor(v, device=DEV), torch.tensor(x, device=DEV), s1, s2, m1, m2, prec,
+                window=kind) as pl:
+        y = pl(torch.tensor(f, dtype=cdt, device=DEV))
+        torch.cuda.synchronize()
+        info = pl.info
+    assert info["window"] == kind and info["thm41_applies"] == 0
+    y = y.cpu().numpy().astype(np.complex128)
+    yo = oracle.nnfft(N, v, f, x, s1, s2, m1, m2, window=kind)
+    e = float(np.abs(y - yo).max() / np.abs(yo).max())
+    tol = _tol(prec, kind, N, s1, s2, m1, m2)
+    _say(f"    E_inf vs oracle {e:.2e} (tol {tol:.1e})")
+    assert e <= tol
+    idx = W.rng(5).choice(M2, min(M2, 256), replace=False)
+    ex = oracle.direct(N, v, f, x[idx])
+    err = float(np.abs(y[idx] - ex).max() / np.abs(f).sum())
+    bound = oracle.bound_thm35(kind, N, s1, s2, m1, m2)
+    _say(f"    E_paper on 256 samples {err:.2e} (Theorem 3.5 {bound:.1e})")
+    assert err <= bound + tol * np.abs(yo).max() / np.abs(f).sum()
+
+
+def test_windows_mix_in_one_batch():
+    g = W.rng(950)
+    specs = [(P.NNFFT_WINDOW_SINH, FP32, 6), (BSPL, FP32, 6), (ALG, FP32, 8), (BSPL, FP64, 7),
+             (ALG, FP64, 5), (P.NNFFT_WINDOW_SINH, FP64, 12)]
+    plans, fs, singles = [], [], []
+    try:
+        for i, (kind, prec, m) in enumerate(specs):
+            N, M1, M2 = 300 + 50 * i, 3000 + 777 * i, 2500 + 555 * i
+            v, x, f = W.uniform_nodes(g, M1), W.uniform_nodes(g, M2), W.complex_gaussian(g, M1)
+            cdt = torch.complex64 if prec == FP32 else torch.complex128
+            plans.append(P.Plan(N, torch.tensor(v, device=DEV), torch.tensor(x, device=DEV), 2.0, 2.0, m, m,
+                                prec, window=kind))
+            fs.append(torch.tensor(f, dtype=cdt, device=DEV))
+        _say(f"[gpu] batch of {len(plans)} plans with mixed window families")
+        singles = [p(f).clone() for p, f in zip(plans, fs)]
+        ys = [torch.full_like(s, float("nan")) for s in singles]
+        P.nnfft_exec_batch([p.handle for p in plans], fs, ys)
+        torch.cuda.synchronize()
+        for i, (a, b) in enumerate(zip(singles, ys)):
+            assert torch.equal(a, b), f"plan {i} differs from its single exec"
+    finally:
+        for p in plans:
+            p.close()
+
+
+def test_server_runs_window_families():
+    g = W.rng(960)
+    reqs = []
+    for i, kind in enumerate((BSPL, ALG, P.NNFFT_WINDOW_SINH, BSPL)):
+        prec, m = (FP32, 6) if i % 2 == 0 else (FP64, 9)
+        N, M1, M2 = 256 + 64 * i, 4000 + 100 * i, 3000 + 100 * i
+        v, x, f = W.uniform_nodes(g, M1), W.uniform_nodes(g, M2), W.complex_gaussian(g, M1)
+        cdt = torch.complex64 if prec == FP32 else torch.complex128
+        reqs.append(dict(N=N, kind=kind, prec=prec, m=m, hv=v, hx=x, hf=f, v=torch.tensor(v, device=DEV),
+                         x=torch.tensor(x, device=DEV), f=torch.tensor(f, dtype=cdt, device=DEV)))
+    _say(f"[gpu] server with {len(reqs)} requests of three window families")
+    torch.cuda.synchronize()
+    with P.Server(hbm_budget_bytes=1 << 28, planner_threads=2, streams=2) as srv:
+        sub = []
+        for r in reqs:
+            y = torch.full((r["x"].numel(),), float("nan"), dtype=r["f"].dtype, device=DEV)
+            t = srv.submit(r["N"], r["v"], r["x"], r["f"], y, m1=r["m"], m2=r["m"], prec=r["prec"],
+                           window=r["kind"])
+            sub.append((t, y))
+        res = [srv.wait(t) for t, _ in sub]
+    assert all(x["status"] == 0 for x in res), [x["message"] for x in res]
+    for r, (_, y) in zip(reqs, sub):
+        with P.Plan(r["N"], r["v"], r["x"], 2.0, 2.0, r["m"], r["m"], r["prec"], window=r["kind"]) as pl:
+            alone = pl(r["f"]).clone()
+            torch.cuda.synchronize()
+        assert torch.equal(y, alone)
+        yo = oracle.nnfft(r["N"], r["hv"], r["hf"], r["hx"], 2.0, 2.0, r["m"], r["m"], window=r["kind"])
+        e = float(np.abs(y.cpu().numpy() - yo).max() / np.abs(yo).max())
+        assert e <= _tol(r["prec"], r["kind"], r["N"], 2.0, 2.0, r["m"], r["m"])
+
+
+def test_window_plan_errors():
+    v = torch.zeros(4, dtype=torch.float64, device=DEV)
+    with pytest.raises(P.NnfftError) as e:
+        P.Plan(64, v, v, 1.02, 2.0, 4, 4, FP64, window=ALG)     # sigma <= pi/3
+    assert e.value.status == P.binding.NNFFT_ERR_ARG
+    with pytest.raises(P.NnfftError) as e:
+        P.Plan(64, v, v, 2.0, 2.0, 4, 4, FP64, window=7)
+    assert e.value.status == P.binding.NNFFT_ERR_ARG

@@ -174,3 +174,29 @@ def test_nfft_dry_run_errors():
     with pytest.raises(binding.NnfftError) as e:
         binding.nfft_plan_dry_run(64, x, 2.0, 3, P.NNFFT_FP32_COMP)
     assert e.value.status == binding.NNFFT_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("window", [P.NNFFT_WINDOW_BSPLINE, P.NNFFT_WINDOW_ALGEBRAIC])
+@pytest.mark.parametrize("prec", [P.NNFFT_FP64_PLAIN, P.NNFFT_FP32_COMP])
+def test_window_plan_dry_run(window, prec):
+    # plans of the B-spline and algebraic families (Example 2.1): sizes as
+    # for the sinh family, shape parameters of the family, layout invariants
+    g = np.random.default_rng(17)
+    v, x = g.uniform(-0.5, 0.5, 5000), g.uniform(-0.5, 0.5, 3000)
+    for sig, m in ((2.0, 6), (1.5, 8), (1.25, 4)):
+        i = binding.nnfft_plan_dry_run(300, v, x, sig, sig, m, m, prec, window=window)
+        s = binding.nnfft_plan_dry_run(300, v, x, sig, sig, m, m, prec)
+        assert i["window"] == window and s["window"] == P.NNFFT_WINDOW_SINH
+        assert (i["N1"], i["G1"], i["N2"]) == (s["N1"], s["G1"], s["N2"])
+        assert i["thm41_applies"] == 0 and i["bound_thm41"] == 0.0
+        Po = oracle.params(300, sig, sig, m, m, window)
+        assert (i["beta1"], i["beta2"]) == (Po.beta1, Po.beta2)
+        assert i["corr_fit_err"] <= (1e-8 if prec == P.NNFFT_FP32_COMP else 1e-12)
+
+
+def test_window_plan_errors():
+    v = np.zeros(8)
+    with pytest.raises(P.NnfftError):
+        binding.nnfft_plan_dry_run(100, v, v, 1.02, 2.0, 4, 4, P.NNFFT_FP64_PLAIN, window=P.NNFFT_WINDOW_ALGEBRAIC)
+    with pytest.raises(P.NnfftError):
+        binding.nnfft_plan_dry_run(100, v, v, 2.0, 2.0, 4, 4, P.NNFFT_FP64_PLAIN, window=3)
