@@ -33,7 +33,8 @@ struct Chunk {
     int32_t nitem;
     int32_t bin_lo;
     int32_t nbin;
-    int32_t part_off;   // spreading side: partial cell of the window's first cell
+    int32_t part_off;   // spreading side: < 0: the window is in plane -part_off - 1 (cells
+                        // in slot order); >= 0: overflow window at this partial index
 };
 
 // FP32 point record: the caller's index and the fractional offset of the
@@ -61,6 +62,7 @@ struct SpreadArgs {
     int32_t m, ngrid;
     int32_t rows;             // FP32 path: record rows per slot (max points per item)
     int32_t window;           // nnfft_window
+    int32_t slotT, slotP;     // plane cell c at slot (c mod T) P + c div T
 };
 
 // Steps 2-3 (merge, 1/phi_hat_2, FFT) arguments of one plan.
@@ -71,6 +73,9 @@ struct FftArgs {
     const double *deconv;     // NNFFT: [G1] 1 / (N1 N2 phi_hat_2(l)), l = cell - G1/2;
                               // NFFT: [N] 1 / (n phi_hat(k)), k + N/2
     const void *tw;           // [N2] exp(-2 pi i q / N2) (float2 or double2)
+    const void *twA;          // four-step: [n2] exp(-2 pi i k / n2)
+    const void *twB;          // four-step: [n1] exp(-2 pi i k / n1)
+    const void *tw4;          // four-step: [n1][n2] exp(-2 pi i j1 k2 / N2)
     void *Y;                  // [N2] four-step intermediate
     void *hlin;               // [2 S + 1] h_s at index s + h_off for |s| <= S
     const void *dense_in;     // mode 1: the NFFT coefficients f_k (set per exec)
@@ -85,6 +90,7 @@ struct FftArgs {
     int32_t Nout;             // NFFT: number of frequencies N
     int32_t npassA, npassB;
     int32_t nplanes;          // planes of spreading windows summed for every cell
+    int32_t slotT, slotP;     // plane cell c at slot (c mod T) P + c div T
     int8_t radA[kMaxPasses];  // radices of the length-n2 transform (or of N2)
     int8_t radB[kMaxPasses];  // radices of the length-n1 transform
 };

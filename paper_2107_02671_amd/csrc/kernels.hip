@@ -76,6 +76,23 @@ __device__ __forceinline__ void comp_add(float &hi, float &lo, float x)
     lo += e;
 }
 
+// Partial windows of the spreading step.  A plane stores its cells in slot
+// order slot(c) = (c mod T) P + c div T (T: the first four-step factor n1 of
+// the plan's FFT, or 1; P = ceil(G1 / T)), so that the cells one four-step
+// column reads (one residue mod n1) are contiguous.  Chunk.part_off < 0:
+// the window lies in plane -part_off - 1; else it is the overflow window at
+// partial index part_off (cells contiguous).
+__device__ __forceinline__ int cell_slot(int c, int T, int P)
+{
+    return T == 1 ? c : (c % T) * P + c / T;
+}
+
+__device__ __forceinline__ int window_index(const Chunk &ch, int wc, int m, int T, int P)
+{
+    if (ch.part_off >= 0) return ch.part_off + wc;
+    return (-ch.part_off - 1) * (T * P) + cell_slot(ch.bin_lo - m + 1 + wc, T, P);
+}
+
 // sinh window of Example 2.1 in FP64:
 //   sinh(beta s)/sinh(beta) = (e^{beta(s-1)} - e^{-beta(s+1)}) / (1 - e^{-2 beta})
 __device__ __forceinline__ double omega64(double u, double beta, double inv_den)
@@ -106,11 +123,12 @@ __device__ __forceinline__ double cheb64(const double *__restrict__ c, int deg, 
 //   B-spline   tap r is one polynomial piece of degree 2m - 1 in x, stored as
 //              its exact Chebyshev series in 2x - 1 (T: [2m][2m]);
 //   algebraic  (1 - u^2)^(beta - 1/2) = q^(beta - 1) sqrt(q), beta = 3m integer.
-__device__ __forceinline__ double tap64(int window, const double *__restrict__ T, int r, int m, double x,
-                                        double u, double beta, double inv_den)
+template <int WIN>
+__device__ __forceinline__ double tap64(const double *__restrict__ T, int r, int m, double x, double u, double beta,
+                                        double inv_den)
 {
-    if (window == NNFFT_WINDOW_BSPLINE) return cheb64(T + r * 2 * m, 2 * m - 1, fma(2.0, x, -1.0));
-    if (window == NNFFT_WINDOW_ALGEBRAIC) {
+    if constexpr (WIN == NNFFT_WINDOW_BSPLINE) return cheb64(T + r * 2 * m, 2 * m - 1, fma(2.0, x, -1.0));
+    if constexpr (WIN == NNFFT_WINDOW_ALGEBRAIC) {
         const double q = (1.0 - u) * (1.0 + u);
         if (!(q > 0.0)) return 0.0;
         double p = 1.0, b = q;
@@ -302,7 +320,7 @@ __device__ void spread32_slot(const SpreadArgs &A, const cx<float> *__restrict__
     }
     __syncthreads();
     const int W = ch.nbin + tm - 1;
-    float4 *part = reinterpret_cast<float4 *>(A.partial) + ch.part_off;
+    float4 *part = reinterpret_cast<float4 *>(A.partial);
     for (int wc = threadIdx.x; wc < W; wc += blockDim.x) {
         cx<float> v[TM];
 #pragma unroll
@@ -319,7 +337,7 @@ __device__ void spread32_slot(const SpreadArgs &A, const cx<float> *__restrict__
                 comp_add(hi, li, v[rr].im);
             }
         }
-        part[wc] = make_float4(hr, hi, lr, li);
+        part[window_index(ch, wc, m, A.slotT, A.slotP)] = make_float4(hr, hi, lr, li);
     }
 }
 
@@ -362,6 +380,7 @@ static size_t lds64_bytes(int tm)
     return (size_t)tm * kItemsPerWg * sizeof(cx<double>) + 3 * kItemsPerWg * sizeof(int);
 }
 
+template <int WIN>
 __device__ void spread64_slot(const SpreadArgs &A, const cx<double> *__restrict__ f, int g, Spread64Lds &L)
 {
     const int t = threadIdx.x;
@@ -388,8 +407,8 @@ __device__ void spread64_slot(const SpreadArgs &A, const cx<double> *__restrict_
 #pragma unroll
             for (int q = 0; q < Q64; ++q) {
                 if (q < it.n) {
-                    const double w = tap64(A.window, A.T64, r, m, xf[q], ((double)(r - m + 1) - xf[q]) * inv_m,
-                                           A.beta, A.inv_den);
+                    const double w = tap64<WIN>(A.T64, r, m, xf[q], ((double)(r - m + 1) - xf[q]) * inv_m,
+                                                A.beta, A.inv_den);
                     ar = fma(fv[q].re, w, ar);
                     ai = fma(fv[q].im, w, ai);
                 }
@@ -406,7 +425,7 @@ __device__ void spread64_slot(const SpreadArgs &A, const cx<double> *__restrict_
     }
     __syncthreads();
     const int W = ch.nbin + tm - 1;
-    double2 *part = reinterpret_cast<double2 *>(A.partial) + ch.part_off;
+    double2 *part = reinterpret_cast<double2 *>(A.partial);
     for (int w = t; w < W; w += blockDim.x) {
         const int blo = max(0, w - tm + 1), bhi = min(ch.nbin - 1, w);
         double ar = 0.0, ai = 0.0;
@@ -420,14 +439,17 @@ __device__ void spread64_slot(const SpreadArgs &A, const cx<double> *__restrict_
                 ai += v.im;
             }
         }
-        part[w] = make_double2(ar, ai);
+        part[window_index(ch, w, m, A.slotT, A.slotP)] = make_double2(ar, ai);
     }
 }
 
+// WIN: the plan's window family (one instantiation per family keeps the
+// sinh kernel's registers at what the sinh taps need)
+template <int WIN>
 __global__ __launch_bounds__(64) void k_spread64(SpreadArgs A, const cx<double> *__restrict__ f)
 {
     Spread64Lds L = spread64_lds(2 * A.m);
-    spread64_slot(A, f, blockIdx.x, L);
+    spread64_slot<WIN>(A, f, blockIdx.x, L);
 }
 
 // ===========================================================================
@@ -549,6 +571,7 @@ __device__ __forceinline__ Interp64Lds interp64_lds(int tm)
     return L;
 }
 
+template <int WIN>
 __device__ void interp64_slot(const InterpArgs &A, cx<double> *__restrict__ y, int g, Interp64Lds &L)
 {
     const int t = threadIdx.x;
@@ -579,8 +602,8 @@ __device__ void interp64_slot(const InterpArgs &A, cx<double> *__restrict__ y, i
             const double fr = A.frac64[p];
             double sr = 0.0, si = 0.0;
             for (int r = 0; r < tm; ++r) {
-                const double w = tap64(A.window, A.T64, r, m, fr, (fr + (double)(m - 1 - r)) * inv_m, A.beta,
-                                       A.inv_den);
+                const double w = tap64<WIN>(A.T64, r, m, fr, (fr + (double)(m - 1 - r)) * inv_m, A.beta,
+                                            A.inv_den);
                 const cx<double> hv = L.hw[r * kItemsPerWg + b];
                 sr = fma(hv.re, w, sr);
                 si = fma(hv.im, w, si);
@@ -592,30 +615,63 @@ __device__ void interp64_slot(const InterpArgs &A, cx<double> *__restrict__ y, i
     }
 }
 
+template <int WIN>
 __global__ __launch_bounds__(64) void k_interp64(InterpArgs A, cx<double> *__restrict__ y)
 {
     Interp64Lds L = interp64_lds(2 * A.m);
-    interp64_slot(A, y, blockIdx.x, L);
+    interp64_slot<WIN>(A, y, blockIdx.x, L);
+}
+
+static void launch_spread64(const SpreadArgs &A, const void *f, hipStream_t s)
+{
+    const cx<double> *in = reinterpret_cast<const cx<double> *>(f);
+    const size_t lds = lds64_bytes(2 * A.m);
+    switch (A.window) {
+    case NNFFT_WINDOW_BSPLINE:
+        hipLaunchKernelGGL(k_spread64<NNFFT_WINDOW_BSPLINE>, dim3(A.ngrid), dim3(kItemsPerWg), lds, s, A, in);
+        break;
+    case NNFFT_WINDOW_ALGEBRAIC:
+        hipLaunchKernelGGL(k_spread64<NNFFT_WINDOW_ALGEBRAIC>, dim3(A.ngrid), dim3(kItemsPerWg), lds, s, A, in);
+        break;
+    default:
+        hipLaunchKernelGGL(k_spread64<NNFFT_WINDOW_SINH>, dim3(A.ngrid), dim3(kItemsPerWg), lds, s, A, in);
+        break;
+    }
+}
+
+static void launch_interp64(const InterpArgs &A, void *y, hipStream_t s)
+{
+    cx<double> *out = reinterpret_cast<cx<double> *>(y);
+    const size_t lds = lds64_bytes(2 * A.m);
+    switch (A.window) {
+    case NNFFT_WINDOW_BSPLINE:
+        hipLaunchKernelGGL(k_interp64<NNFFT_WINDOW_BSPLINE>, dim3(A.ngrid), dim3(kItemsPerWg), lds, s, A, out);
+        break;
+    case NNFFT_WINDOW_ALGEBRAIC:
+        hipLaunchKernelGGL(k_interp64<NNFFT_WINDOW_ALGEBRAIC>, dim3(A.ngrid), dim3(kItemsPerWg), lds, s, A, out);
+        break;
+    default:
+        hipLaunchKernelGGL(k_interp64<NNFFT_WINDOW_SINH>, dim3(A.ngrid), dim3(kItemsPerWg), lds, s, A, out);
+        break;
+    }
 }
 
 // ===========================================================================
 // FFT (steps 2-3)
 // ===========================================================================
 
-// FFT input element q (index mod N2) = merged, deconvolved step-1 output:
-// label l = q (q < N2/2) or q - N2; zero outside I_{G1}.
-// Adds the partial sums of grid cell `cell` (its window planes, then the
-// overflow windows through their index lists) to the two-sum pairs.
-__device__ __forceinline__ void merge_cell32(const FftArgs &A, int cell, float &hr, float &hi, float &lr, float &li)
+// Adds the partial sums of the grid cell at slot `slot` (its window planes,
+// then the overflow windows through their index lists) to the two-sum pairs.
+__device__ __forceinline__ void merge_cell32(const FftArgs &A, int slot, float &hr, float &hi, float &lr, float &li)
 {
     const float4 *part = reinterpret_cast<const float4 *>(A.partial);
-    const int e0 = A.merge_off[cell], e1 = A.merge_off[cell + 1];
-    // the planes: fixed offsets s G1 + cell, all loads in flight together
-    const int np = A.nplanes;
+    const int e0 = A.merge_off[slot], e1 = A.merge_off[slot + 1];
+    // the planes: fixed offsets s T P + slot, all loads in flight together
+    const int np = A.nplanes, ps = A.slotT * A.slotP;
     {
         float4 v[kMaxPlanes];
 #pragma unroll
-        for (int q = 0; q < kMaxPlanes; ++q) v[q] = part[(size_t)min(q, np - 1) * A.G1 + cell];
+        for (int q = 0; q < kMaxPlanes; ++q) v[q] = part[(size_t)min(q, np - 1) * ps + slot];
 #pragma unroll
         for (int q = 0; q < kMaxPlanes; ++q) {
             if (q < np) {
@@ -646,15 +702,15 @@ __device__ __forceinline__ void merge_cell32(const FftArgs &A, int cell, float &
     }
 }
 
-__device__ __forceinline__ void merge_cell64(const FftArgs &A, int cell, double &ar, double &ai)
+__device__ __forceinline__ void merge_cell64(const FftArgs &A, int slot, double &ar, double &ai)
 {
     const double2 *part = reinterpret_cast<const double2 *>(A.partial);
-    const int e1 = A.merge_off[cell + 1];
-    const int np = A.nplanes;
+    const int e1 = A.merge_off[slot + 1];
+    const int np = A.nplanes, ps = A.slotT * A.slotP;
     {
         double2 v[kMaxPlanes];
 #pragma unroll
-        for (int q = 0; q < kMaxPlanes; ++q) v[q] = part[(size_t)min(q, np - 1) * A.G1 + cell];
+        for (int q = 0; q < kMaxPlanes; ++q) v[q] = part[(size_t)min(q, np - 1) * ps + slot];
 #pragma unroll
         for (int q = 0; q < kMaxPlanes; ++q) {
             if (q < np) {
@@ -663,7 +719,7 @@ __device__ __forceinline__ void merge_cell64(const FftArgs &A, int cell, double 
             }
         }
     }
-    for (int e = A.merge_off[cell]; e < e1; ++e) {
+    for (int e = A.merge_off[slot]; e < e1; ++e) {
         const double2 v = part[A.merge_idx[e]];
         ar += v.x;
         ai += v.y;
@@ -672,7 +728,7 @@ __device__ __forceinline__ void merge_cell64(const FftArgs &A, int cell, double 
 
 // FFT input element q (index mod N2):
 //  mode 0 (NNFFT steps 1-2): merged step-1 cell of label l = q or q - N2 (zero
-//    outside I_{G1}) times 1 / (N1 N2 phi_hat_2(l));
+//    outside I_{G1}) times 1 / (N1 N2 phi_hat_2(l)) (table in slot order);
 //  mode 1 (NFFT): coefficient f_k, k = l in I_N, times 1 / (n phi_hat(k));
 //  mode 2 (adjoint NFFT): conjugate of the sum of the cells of labels l, l + n,
 //    l - n in the linear grid (the 1-periodic fold of the spread values).
@@ -690,14 +746,14 @@ __device__ __forceinline__ cx<float> fft_input32(const FftArgs &A, int q)
 #pragma unroll
         for (int r = -1; r <= 1; ++r) {
             const int cell = lab + r * A.N2 + A.G1 / 2;
-            if (cell >= 0 && cell < A.G1) merge_cell32(A, cell, hr, hi, lr, li);
+            if (cell >= 0 && cell < A.G1) merge_cell32(A, cell_slot(cell, A.slotT, A.slotP), hr, hi, lr, li);
         }
         return cxmk(hr + lr, -(hi + li));
     }
     if (lab < -A.G1 / 2 || lab >= A.G1 / 2) return cxmk(0.f, 0.f);
-    const int cell = lab + A.G1 / 2;
-    merge_cell32(A, cell, hr, hi, lr, li);
-    const double sc = A.deconv[cell];
+    const int slot = cell_slot(lab + A.G1 / 2, A.slotT, A.slotP);
+    const double sc = A.deconv[slot];   // issued with the plane loads
+    merge_cell32(A, slot, hr, hi, lr, li);
     return cxmk((float)((double)(hr + lr) * sc), (float)((double)(hi + li) * sc));
 }
 
@@ -714,14 +770,14 @@ __device__ __forceinline__ cx<double> fft_input64(const FftArgs &A, int q)
 #pragma unroll
         for (int r = -1; r <= 1; ++r) {
             const int cell = lab + r * A.N2 + A.G1 / 2;
-            if (cell >= 0 && cell < A.G1) merge_cell64(A, cell, ar, ai);
+            if (cell >= 0 && cell < A.G1) merge_cell64(A, cell_slot(cell, A.slotT, A.slotP), ar, ai);
         }
         return cxmk(ar, -ai);
     }
     if (lab < -A.G1 / 2 || lab >= A.G1 / 2) return cxmk(0.0, 0.0);
-    const int cell = lab + A.G1 / 2;
-    merge_cell64(A, cell, ar, ai);
-    const double sc = A.deconv[cell];
+    const int slot = cell_slot(lab + A.G1 / 2, A.slotT, A.slotP);
+    const double sc = A.deconv[slot];
+    merge_cell64(A, slot, ar, ai);
     return cxmk(ar * sc, ai * sc);
 }
 
@@ -815,6 +871,44 @@ struct Dft<T, 5> {
     }
 };
 
+template <typename T>
+struct Dft<T, 16> {
+    // n = 4 n1 + n2, k = k1 + 4 k2: length-4 transforms over n1, twiddles
+    // exp(-2 pi i n2 k1 / 16), length-4 transforms over n2
+    __device__ static void run(cx<T> *a)
+    {
+        const T c1 = (T)0.92387953251128675612818318939678829, s1 = (T)0.38268343236508977172845998403039887;
+        const T h = (T)0.70710678118654752440084436210484904;
+        cx<T> y[4][4];
+#pragma unroll
+        for (int n2 = 0; n2 < 4; ++n2) {
+            cx<T> c[4] = {a[n2], a[4 + n2], a[8 + n2], a[12 + n2]};
+            Dft<T, 4>::run(c);
+#pragma unroll
+            for (int k1 = 0; k1 < 4; ++k1) y[n2][k1] = c[k1];
+        }
+        // exp(-2 pi i e / 16) for e = n2 k1 in {1, 2, 3, 4, 6, 9}
+        const cx<T> w1 = cxmk(c1, -s1), w2 = cxmk(h, -h), w3 = cxmk(s1, -c1), w6 = cxmk(-h, -h),
+                    w9 = cxmk(-c1, s1);
+        y[1][1] = cmul(y[1][1], w1);
+        y[1][2] = cmul(y[1][2], w2);
+        y[1][3] = cmul(y[1][3], w3);
+        y[2][1] = cmul(y[2][1], w2);
+        y[2][2] = mul_mi(y[2][2]);
+        y[2][3] = cmul(y[2][3], w6);
+        y[3][1] = cmul(y[3][1], w3);
+        y[3][2] = cmul(y[3][2], w6);
+        y[3][3] = cmul(y[3][3], w9);
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) {
+            cx<T> c[4] = {y[0][k1], y[1][k1], y[2][k1], y[3][k1]};
+            Dft<T, 4>::run(c);
+#pragma unroll
+            for (int k2 = 0; k2 < 4; ++k2) a[k1 + 4 * k2] = c[k2];
+        }
+    }
+};
+
 // One Stockham pass of radix R on B transforms of length Lsub held in LDS
 // (src[b * Lsub + j]) into dst.  Twiddle exp(-2 pi i e / Lsub) = tw[e * tstride]
 // (an LDS table of the sub-transform length, tstride = 1).
@@ -845,12 +939,65 @@ __device__ void stockham_pass(const cx<T> *src, cx<T> *dst, int Lsub, int B, int
     }
 }
 
+// The same pass with the length, radix and stride known at compile time (the
+// index arithmetic reduces to shifts and masks).
+template <typename T, int L, int R, int Ns>
+__device__ __forceinline__ void stockham_pass_fixed(const cx<T> *src, cx<T> *dst, int B, const cx<T> *__restrict__ tw)
+{
+    constexpr int nbf = L / R;
+    constexpr int tws = L / (Ns * R);
+    const int total = nbf * B;
+    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+        const int b = idx / nbf;
+        const int j = idx - b * nbf;
+        const cx<T> *in = src + b * L;
+        cx<T> a[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) a[r] = in[j + r * nbf];
+        const int k = j % Ns;
+        if (Ns > 1) {
+#pragma unroll
+            for (int r = 1; r < R; ++r) a[r] = cmul(a[r], tw[k * r * tws]);
+        }
+        Dft<T, R>::run(a);
+        const int o = (j / Ns) * Ns * R + k;
+        cx<T> *out = dst + b * L;
+#pragma unroll
+        for (int r = 0; r < R; ++r) out[o + r * Ns] = a[r];
+    }
+}
+
+// Passes of radices R, Rest... ping-ponging between the two buffers; the
+// result is in the second buffer after an odd number of passes.
+template <typename T, int L, int Ns, int R, int... Rest>
+__device__ __forceinline__ void stockham_fixed(cx<T> *src, cx<T> *dst, int B, const cx<T> *__restrict__ tw)
+{
+    stockham_pass_fixed<T, L, R, Ns>(src, dst, B, tw);
+    __syncthreads();
+    if constexpr (sizeof...(Rest) > 0) stockham_fixed<T, L, Ns * R, Rest...>(dst, src, B, tw);
+}
+
 // Transforms the B length-Lsub sequences in buf[0] in place (result ends up in
-// buf[0] or buf[1]; the returned pointer tells which).
+// buf[0] or buf[1]; the returned pointer tells which).  Power-of-two lengths
+// 64..4096 take fixed radix-8/16 plans; other lengths the plan's radix list.
 template <typename T>
 __device__ cx<T> *stockham(cx<T> *buf0, cx<T> *buf1, int Lsub, int B, const int8_t *rad, int npass,
                            const cx<T> *__restrict__ tw, int tstride)
 {
+    if (tstride == 1) {
+        int odd = -1;   // passes of the fixed plan modulo 2
+        switch (Lsub) {
+        case 64: stockham_fixed<T, 64, 1, 8, 8>(buf0, buf1, B, tw); odd = 0; break;
+        case 128: stockham_fixed<T, 128, 1, 8, 16>(buf0, buf1, B, tw); odd = 0; break;
+        case 256: stockham_fixed<T, 256, 1, 16, 16>(buf0, buf1, B, tw); odd = 0; break;
+        case 512: stockham_fixed<T, 512, 1, 8, 8, 8>(buf0, buf1, B, tw); odd = 1; break;
+        case 1024: stockham_fixed<T, 1024, 1, 16, 8, 8>(buf0, buf1, B, tw); odd = 1; break;
+        case 2048: stockham_fixed<T, 2048, 1, 16, 16, 8>(buf0, buf1, B, tw); odd = 1; break;
+        case 4096: stockham_fixed<T, 4096, 1, 16, 16, 16>(buf0, buf1, B, tw); odd = 1; break;
+        default: break;
+        }
+        if (odd >= 0) return odd ? buf1 : buf0;
+    }
     cx<T> *src = buf0, *dst = buf1;
     int Ns = 1;
     for (int ps = 0; ps < npass; ++ps) {
@@ -949,8 +1096,10 @@ __device__ void fft_single_body(const FftArgs &A, FftLds<T> &L)
     const cx<T> *gtw = reinterpret_cast<const cx<T> *>(A.tw);
     // data and twiddles in one round of loads; all passes then run from LDS
     for (int q = threadIdx.x; q < N2; q += blockDim.x) {
-        L.tw[q] = gtw[q];
-        L.buf[0][q] = fft_input<T>(A, q);
+        const cx<T> t = gtw[q];
+        const cx<T> xv = fft_input<T>(A, q);
+        L.tw[q] = t;
+        L.buf[0][q] = xv;
     }
     __syncthreads();
     cx<T> *res = stockham<T>(L.buf[0], L.buf[1], N2, 1, A.radA, A.npassA, L.tw, 1);
@@ -965,7 +1114,8 @@ __global__ __launch_bounds__(256) void k_fft_single(FftArgs A)
 }
 
 // Four-step stage A: for columns j1, length-n2 transforms over j2 of
-// x[j1 + n1 j2], times exp(-2 pi i j1 k2 / N2), stored to Y[j1 n2 + k2].
+// x[j1 + n1 j2], times exp(-2 pi i j1 k2 / N2), stored to Y[k2 n1 + j1] (so
+// that stage B reads its columns contiguously).
 template <typename T>
 __device__ void fft_stageA_body(const FftArgs &A, int w, FftLds<T> &L)
 {
@@ -975,15 +1125,21 @@ __device__ void fft_stageA_body(const FftArgs &A, int w, FftLds<T> &L)
     if (blk >= ng) return;
     const int j1_0 = blk * B;
     const int nb = min(B, n1 - j1_0);
-    const cx<T> *gtw = reinterpret_cast<const cx<T> *>(A.tw);
+    const cx<T> *twA = reinterpret_cast<const cx<T> *>(A.twA);
+    const cx<T> *tw4 = reinterpret_cast<const cx<T> *>(A.tw4);
     // one round of loads: the merged input, the length-n2 twiddles and the
-    // four-step twiddles exp(-2 pi i j1 k2 / N2) of these columns
+    // four-step twiddles exp(-2 pi i j1 k2 / N2) of these columns (tables
+    // [n2] and [n1][n2], read contiguously)
+    // (every global load of an element is issued before its LDS stores, so
+    // the loads of one element travel together)
     for (int idx = threadIdx.x; idx < nb * n2; idx += blockDim.x) {
         const int j2 = idx / nb, bl = idx - j2 * nb;
-        const int k2 = idx - (idx / n2) * n2, bo = idx / n2;
-        if (idx < n2) L.tw[idx] = gtw[idx * n1];
-        L.otw[idx] = gtw[(j1_0 + bo) * k2];
-        L.buf[0][bl * n2 + j2] = fft_input<T>(A, j1_0 + bl + n1 * j2);
+        const cx<T> ta = twA[min(idx, n2 - 1)];
+        const cx<T> t4 = tw4[(size_t)j1_0 * n2 + idx];
+        const cx<T> xv = fft_input<T>(A, j1_0 + bl + n1 * j2);
+        if (idx < n2) L.tw[idx] = ta;
+        L.otw[idx] = t4;
+        L.buf[0][bl * n2 + j2] = xv;
     }
     __syncthreads();
     cx<T> *res = stockham<T>(L.buf[0], L.buf[1], n2, nb, A.radA, A.npassA, L.tw, 1);
@@ -991,7 +1147,7 @@ __device__ void fft_stageA_body(const FftArgs &A, int w, FftLds<T> &L)
     for (int idx = threadIdx.x; idx < nb * n2; idx += blockDim.x) {
         const int bl = idx / n2, k2 = idx - bl * n2;
         const int j1 = j1_0 + bl;
-        Y[(size_t)j1 * n2 + k2] = cmul(res[idx], L.otw[idx]);
+        Y[(size_t)k2 * n1 + j1] = cmul(res[idx], L.otw[idx]);
     }
 }
 
@@ -1003,7 +1159,7 @@ __global__ __launch_bounds__(256) void k_fft_stageA(FftArgs A)
 }
 
 // Four-step stage B: for columns k2, length-n1 transforms over j1 of
-// Y[j1 n2 + k2]; output k1 is X[k2 + n2 k1].
+// Y[k2 n1 + j1]; output k1 is X[k2 + n2 k1].
 template <typename T>
 __device__ void fft_stageB_body(const FftArgs &A, int w, FftLds<T> &L)
 {
@@ -1014,11 +1170,12 @@ __device__ void fft_stageB_body(const FftArgs &A, int w, FftLds<T> &L)
     const int k2_0 = blk * B;
     const int nb = min(B, n2 - k2_0);
     const cx<T> *Y = reinterpret_cast<const cx<T> *>(A.Y);
-    const cx<T> *gtw = reinterpret_cast<const cx<T> *>(A.tw);
+    const cx<T> *twB = reinterpret_cast<const cx<T> *>(A.twB);
     for (int idx = threadIdx.x; idx < nb * n1; idx += blockDim.x) {
-        const int j1 = idx / nb, bl = idx - j1 * nb;
-        if (idx < n1) L.tw[idx] = gtw[idx * n2];
-        L.buf[0][bl * n1 + j1] = Y[(size_t)j1 * n2 + k2_0 + bl];
+        const cx<T> tb = twB[min(idx, n1 - 1)];
+        const cx<T> yv = Y[(size_t)k2_0 * n1 + idx];   // column bl = idx / n1, j1 = idx mod n1
+        if (idx < n1) L.tw[idx] = tb;
+        L.buf[0][idx] = yv;
     }
     __syncthreads();
     cx<T> *res = stockham<T>(L.buf[0], L.buf[1], n1, nb, A.radB, A.npassB, L.tw, 1);
@@ -1065,7 +1222,13 @@ __global__ __launch_bounds__(64) void k_spread64_batch(BatchTable T)
     Spread64Lds L = spread64_lds(2 * A.m);
     const int g = blockIdx.x - T.start[p];
     if (g >= A.ngrid) return;
-    spread64_slot(A, static_cast<const cx<double> *>(T.in[p]), g, L);
+    const cx<double> *in = static_cast<const cx<double> *>(T.in[p]);
+    if (A.window == NNFFT_WINDOW_BSPLINE)
+        spread64_slot<NNFFT_WINDOW_BSPLINE>(A, in, g, L);
+    else if (A.window == NNFFT_WINDOW_ALGEBRAIC)
+        spread64_slot<NNFFT_WINDOW_ALGEBRAIC>(A, in, g, L);
+    else
+        spread64_slot<NNFFT_WINDOW_SINH>(A, in, g, L);
 }
 
 template <int CD>
@@ -1086,7 +1249,13 @@ __global__ __launch_bounds__(64) void k_interp64_batch(BatchTable T)
     Interp64Lds L = interp64_lds(2 * A.m);
     const int g = blockIdx.x - T.start[p];
     if (g >= A.ngrid) return;
-    interp64_slot(A, static_cast<cx<double> *>(T.out[p]), g, L);
+    cx<double> *out = static_cast<cx<double> *>(T.out[p]);
+    if (A.window == NNFFT_WINDOW_BSPLINE)
+        interp64_slot<NNFFT_WINDOW_BSPLINE>(A, out, g, L);
+    else if (A.window == NNFFT_WINDOW_ALGEBRAIC)
+        interp64_slot<NNFFT_WINDOW_ALGEBRAIC>(A, out, g, L);
+    else
+        interp64_slot<NNFFT_WINDOW_SINH>(A, out, g, L);
 }
 
 // stage A of four-step plans and the whole transform of one-workgroup plans
@@ -1181,13 +1350,11 @@ hipError_t launch_exec(const PlanDev &P, const void *f, void *y, hipStream_t s, 
         if (ev) (void)hipEventRecord(ev[2], s);
         launch_interp32(corr_variant(P.ip.corr_deg), gi, s, P.ip, reinterpret_cast<cx<float> *>(y));
     } else {
-        hipLaunchKernelGGL(k_spread64, dim3(P.sp.ngrid), dim3(kItemsPerWg), lds64_bytes(2 * P.sp.m), s, P.sp,
-                           reinterpret_cast<const cx<double> *>(f));
+        launch_spread64(P.sp, f, s);
         if (ev) (void)hipEventRecord(ev[1], s);
         launch_fft<double>(P.fft, s);
         if (ev) (void)hipEventRecord(ev[2], s);
-        hipLaunchKernelGGL(k_interp64, dim3(P.ip.ngrid), dim3(kItemsPerWg), lds64_bytes(2 * P.ip.m), s, P.ip,
-                           reinterpret_cast<cx<double> *>(y));
+        launch_interp64(P.ip, y, s);
     }
     if (ev) (void)hipEventRecord(ev[3], s);
     return hipGetLastError();
@@ -1286,13 +1453,11 @@ hipError_t launch_nfft(const PlanDev &P, bool adjoint, const void *in, void *out
         }
     } else {
         if (adjoint) {
-            hipLaunchKernelGGL(k_spread64, dim3(P.sp.ngrid), dim3(kItemsPerWg), lds64_bytes(2 * P.sp.m), s, P.sp,
-                               reinterpret_cast<const cx<double> *>(in));
+            launch_spread64(P.sp, in, s);
             launch_fft<double>(F, s);
         } else {
             launch_fft<double>(F, s);
-            hipLaunchKernelGGL(k_interp64, dim3(P.ip.ngrid), dim3(kItemsPerWg), lds64_bytes(2 * P.ip.m), s, P.ip,
-                               reinterpret_cast<cx<double> *>(out));
+            launch_interp64(P.ip, out, s);
         }
     }
     return hipGetLastError();

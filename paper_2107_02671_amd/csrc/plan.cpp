@@ -1,6 +1,7 @@
 // NNFFT plans (Algorithm 2.2 step 0), the tuning table, the fast sinc
 // transform plan (Algorithm 6.1) and the C ABI of include/nnfft.h.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -212,9 +213,10 @@ bool build_side(const std::vector<double> &nodes, double scale, int64_t off, int
     // spreading windows: chunk c covers cells [bin_lo - m + 1, bin_lo + nbin + m).
     // Windows are coloured greedily in order of their first cell (interval
     // colouring: at most as many colours as windows overlap at one cell);
-    // colour s writes into plane s of G1 = nbins cells, so a cell's partial
-    // sums sit at fixed offsets s * G1 + cell.  Windows beyond kMaxPlanes
-    // colours go to an overflow area merged through index lists.
+    // colour s writes into plane s (part_off = -s - 1), so a cell's partial
+    // sums sit at fixed offsets in every plane.  Windows beyond kMaxPlanes
+    // colours go to an overflow area merged through index lists (part_off =
+    // offset in that area here; finalize_planes places the area).
     if (m > 0) {
         std::vector<int32_t> ord(S.chunks.size());
         for (size_t c = 0; c < ord.size(); ++c) ord[c] = (int32_t)c;
@@ -239,7 +241,7 @@ bool build_side(const std::vector<double> &nodes, double scale, int64_t off, int
             }
             if (colour >= 0) {
                 plane_end[colour] = hi;
-                ch.part_off = (int32_t)(colour * nbins + lo);
+                ch.part_off = -(colour + 1);
             } else {
                 ovf_off[c] = ovf;
                 ovf += hi - lo;
@@ -247,8 +249,8 @@ bool build_side(const std::vector<double> &nodes, double scale, int64_t off, int
         }
         S.nplanes = (int32_t)plane_end.size();
         for (size_t c = 0; c < S.chunks.size(); ++c)
-            if (ovf_off[c] >= 0) S.chunks[c].part_off = (int32_t)(S.nplanes * nbins + ovf_off[c]);
-        part = S.nplanes * nbins + ovf;
+            if (ovf_off[c] >= 0) S.chunks[c].part_off = (int32_t)ovf_off[c];
+        S.ovf_cells = ovf;
     }
     S.part_cells = part;
     // XCD-aware schedule: workgroup w runs on XCD w % 8 (round-robin dispatch),
@@ -403,6 +405,19 @@ void layout_plan(const HostPlan &H, Carver &C, PlanDev &D, size_t *upload_end, P
     FA.deconv = C.put(H.deconv);
     if (fp32) FA.tw = C.put(H.tw32);
     else FA.tw = C.put(H.tw64);
+    if (H.fd.n1 > 1) {
+        if (fp32) {
+            FA.twA = C.put(std::vector<float>(H.twA.begin(), H.twA.end()));
+            FA.twB = C.put(std::vector<float>(H.twB.begin(), H.twB.end()));
+            FA.tw4 = C.put(std::vector<float>(H.tw4.begin(), H.tw4.end()));
+        } else {
+            FA.twA = C.put(H.twA);
+            FA.twB = C.put(H.twB);
+            FA.tw4 = C.put(H.tw4);
+        }
+    }
+    SA.slotT = FA.slotT = H.slotT;
+    SA.slotP = FA.slotP = H.slotP;
     *upload_end = C.off;
     const size_t csz = fp32 ? 8 : 16;
     SA.partial = C.scratch((size_t)H.sp.part_cells * 16);
@@ -447,36 +462,74 @@ static double tap_fit_tolerance(int m, double sigma)
     return std::max(5e-8, 1e-3 * term);
 }
 
+// Plane layout: cells in slot order with T = the first four-step factor n1
+// of the FFT (1 for one-workgroup transforms), so a four-step column reads
+// contiguous slots; the overflow area follows the planes.
+static void finalize_planes(HostPlan &H, int64_t G1)
+{
+    H.slotT = H.fd.n1 > 1 ? H.fd.n1 : 1;
+    H.slotP = (int32_t)((G1 + H.slotT - 1) / H.slotT);
+    const int64_t ps = (int64_t)H.slotT * H.slotP;
+    for (Chunk &c : H.sp.chunks)
+        if (c.part_off >= 0) c.part_off = (int32_t)(H.sp.nplanes * ps + c.part_off);
+    for (Chunk &c : H.sp.launch)   // the launch-order copies the kernels read
+        if (c.nitem > 0 && c.part_off >= 0) c.part_off = (int32_t)(H.sp.nplanes * ps + c.part_off);
+    H.sp.part_cells = H.sp.nplanes * ps + H.sp.ovf_cells;
+}
+
+static int64_t slot_of(const HostPlan &H, int64_t cell)
+{
+    return (cell % H.slotT) * H.slotP + cell / H.slotT;
+}
+
 static nnfft_status build_merge_lists(HostPlan &H, const nnfft_info_t &P, int m1)
 {
     // merge lists of the overflow windows (those without a plane): for each
-    // grid cell the partial cells of the overflow chunks covering it
-    const int64_t plane_cells = (int64_t)H.sp.nplanes * P.G1;
-    H.moff.assign(P.G1 + 1, 0);
+    // grid cell (by slot) the partial cells of the overflow chunks covering it
+    const int64_t ns = (int64_t)H.slotT * H.slotP;
+    H.moff.assign(ns + 1, 0);
     for (const Chunk &c : H.sp.chunks) {
-        if (c.part_off < plane_cells) continue;
+        if (c.part_off < 0) continue;
         const int W = c.nbin + 2 * m1 - 1;
         for (int w = 0; w < W; ++w) {
             const int64_t cell = (int64_t)c.bin_lo - m1 + 1 + w;
             if (cell < 0 || cell >= P.G1) return fail(NNFFT_ERR_ARG, "internal: window outside the grid");
-            H.moff[cell + 1]++;
+            H.moff[slot_of(H, cell) + 1]++;
         }
     }
-    for (int64_t c = 0; c < P.G1; ++c) H.moff[c + 1] += H.moff[c];
-    H.midx.resize(H.moff[P.G1]);
+    for (int64_t c = 0; c < ns; ++c) H.moff[c + 1] += H.moff[c];
+    H.midx.resize(H.moff[ns]);
     {
         std::vector<int32_t> cur(H.moff.begin(), H.moff.end() - 1);
         for (const Chunk &c : H.sp.chunks) {
-            if (c.part_off < plane_cells) continue;
+            if (c.part_off < 0) continue;
             const int W = c.nbin + 2 * m1 - 1;
             for (int w = 0; w < W; ++w) {
                 const int64_t cell = (int64_t)c.bin_lo - m1 + 1 + w;
-                H.midx[cur[cell]++] = c.part_off + w;
+                H.midx[cur[slot_of(H, cell)]++] = c.part_off + w;
             }
         }
     }
-
     return NNFFT_OK;
+}
+
+// Four-step twiddle tables from the plan's length-N2 table (same values):
+// [n2] exp(-2 pi i k / n2), [n1] exp(-2 pi i k / n1), [n1][n2] exp(-2 pi i j1 k2 / N2).
+static void fft_tables(HostPlan &H)
+{
+    if (H.fd.n1 <= 1) return;
+    const int64_t n1 = H.fd.n1, n2 = H.fd.n2;
+    auto tw = [&](int64_t q, int c) { return H.fp32 ? (double)H.tw32[2 * q + c] : H.tw64[2 * q + c]; };
+    H.twA.resize(2 * n2);
+    for (int64_t k = 0; k < n2; ++k)
+        for (int c = 0; c < 2; ++c) H.twA[2 * k + c] = tw(k * n1, c);
+    H.twB.resize(2 * n1);
+    for (int64_t k = 0; k < n1; ++k)
+        for (int c = 0; c < 2; ++c) H.twB[2 * k + c] = tw(k * n2, c);
+    H.tw4.resize(2 * n1 * n2);
+    for (int64_t j1 = 0; j1 < n1; ++j1)
+        for (int64_t k2 = 0; k2 < n2; ++k2)
+            for (int c = 0; c < 2; ++c) H.tw4[2 * (j1 * n2 + k2) + c] = tw(j1 * k2, c);
 }
 
 // FFT factorization of the length-N2 transform; outputs |s| <= S are stored.
@@ -641,7 +694,6 @@ nnfft_status plan_host(HostPlan &H, int64_t N, int64_t M1, int64_t M2, double si
     if (!build_side(x, (double)P.N2 * (double)P.N_star / (double)P.N1, P.N2 / 2, P.N2 + 1, H.lay2, fp32, 0,
                     H.ip, err))
         return fail(NNFFT_ERR_ARG, err);
-    if (H.sp.part_cells >= ((int64_t)1 << 31)) return fail(NNFFT_ERR_UNSUPPORTED, "too many partial cells");
     // the sorted copies are only needed by the FP64 kernels
     if (fp32) {
         std::vector<int32_t>().swap(H.sp.perm);
@@ -650,13 +702,22 @@ nnfft_status plan_host(HostPlan &H, int64_t N, int64_t M1, int64_t M2, double si
     std::vector<PtRec>().swap(H.sp.rec32);
     std::vector<PtRec>().swap(H.ip.rec32);
 
-    st = build_merge_lists(H, P, m1);
-    if (st != NNFFT_OK) return st;
     {
         const double U = (double)P.N2 * (double)P.N_star / (2.0 * (double)P.N1);
         const int64_t S = std::min<int64_t>((int64_t)std::ceil(U) + m2, P.N2 / 2);
         st = plan_fft(H, P, fp32, S);
         if (st != NNFFT_OK) return st;
+    }
+    fft_tables(H);
+    finalize_planes(H, P.G1);
+    if (H.sp.part_cells >= ((int64_t)1 << 31)) return fail(NNFFT_ERR_UNSUPPORTED, "too many partial cells");
+    st = build_merge_lists(H, P, m1);
+    if (st != NNFFT_OK) return st;
+    {
+        // the deconvolution table in slot order, as the FFT load reads it
+        std::vector<double> d((size_t)H.slotT * H.slotP, 0.0);
+        for (int64_t c = 0; c < P.G1; ++c) d[slot_of(H, c)] = H.deconv[c];
+        H.deconv.swap(d);
     }
     H.hlin_len = P.N2 + 1;
     H.h_off = P.N2 / 2;
@@ -734,17 +795,19 @@ nnfft_status nfft_plan_host(HostPlan &H, int64_t N, int64_t M, double sigma, int
     // spreading (adjoint): t_j = n x_j in the linear grid; interpolation (forward): u_j = n x_j
     if (!build_side(x, (double)n, P.G1 / 2, P.G1, H.lay1, fp32, m, H.sp, err)) return fail(NNFFT_ERR_ARG, err);
     if (!build_side(x, (double)n, n / 2, n + 1, H.lay2, fp32, 0, H.ip, err)) return fail(NNFFT_ERR_ARG, err);
-    if (H.sp.part_cells >= ((int64_t)1 << 31)) return fail(NNFFT_ERR_UNSUPPORTED, "too many partial cells");
     if (fp32) {
         std::vector<int32_t>().swap(H.sp.perm);
         std::vector<int32_t>().swap(H.ip.perm);
     }
     std::vector<PtRec>().swap(H.sp.rec32);
     std::vector<PtRec>().swap(H.ip.rec32);
-    nnfft_status st = build_merge_lists(H, P, m);
-    if (st != NNFFT_OK) return st;
     // the interpolation reads labels |s| <= n/2 + m: the periodic extension
-    st = plan_fft(H, P, fp32, n / 2 + m);
+    nnfft_status st = plan_fft(H, P, fp32, n / 2 + m);
+    if (st != NNFFT_OK) return st;
+    fft_tables(H);
+    finalize_planes(H, P.G1);
+    if (H.sp.part_cells >= ((int64_t)1 << 31)) return fail(NNFFT_ERR_UNSUPPORTED, "too many partial cells");
+    st = build_merge_lists(H, P, m);
     if (st != NNFFT_OK) return st;
     H.hlin_len = n + 2 * m + 1;
     H.h_off = (int32_t)(n / 2 + m);
@@ -801,24 +864,45 @@ nnfft_status check_plan(const HostPlan &H, const std::vector<double> &v, const s
     (void)x;
     // spreading windows
     const int64_t G1 = P.G1, W0 = 2 * (int64_t)P.m1 - 1;
-    const int64_t plane_cells = (int64_t)H.sp.nplanes * G1;
+    const int64_t T = H.slotT, Ps = H.slotP, ps = T * Ps;
+    const int64_t plane_cells = (int64_t)H.sp.nplanes * ps;
+    if (T < 1 || Ps * T < G1 || (H.fd.n1 > 1 && T != H.fd.n1) || (int64_t)H.moff.size() != ps + 1 ||
+        (H.kind == 0 && (int64_t)H.deconv.size() != ps))
+        return fail(NNFFT_ERR_ARG, "internal: slot layout of the planes");
     std::vector<int32_t> owner((size_t)H.sp.part_cells, -1), ovf_count(G1, 0);
     for (size_t c = 0; c < H.sp.chunks.size(); ++c) {
         const Chunk &ch = H.sp.chunks[c];
         const int64_t lo = (int64_t)ch.bin_lo - P.m1 + 1, W = ch.nbin + W0;
         if (lo < 0 || lo + W > G1) return fail(NNFFT_ERR_ARG, "internal: window outside the grid");
-        const int64_t off = ch.part_off;
-        if (off < plane_cells && (off % G1 != lo)) return fail(NNFFT_ERR_ARG, "internal: window not at its cells");
-        if (off + W > H.sp.part_cells) return fail(NNFFT_ERR_ARG, "internal: window outside the partial buffer");
+        const bool in_plane = ch.part_off < 0;
+        if (in_plane && -(int64_t)ch.part_off > H.sp.nplanes) return fail(NNFFT_ERR_ARG, "internal: no such plane");
+        if (!in_plane && (ch.part_off < plane_cells || ch.part_off + W > H.sp.part_cells))
+            return fail(NNFFT_ERR_ARG, "internal: window outside the partial buffer");
         for (int64_t w = 0; w < W; ++w) {
-            if (owner[off + w] >= 0) return fail(NNFFT_ERR_ARG, "internal: two windows share a partial cell");
-            owner[off + w] = (int32_t)c;
-            if (off >= plane_cells) ovf_count[lo + w]++;
+            const int64_t cell = lo + w;
+            const int64_t idx = in_plane ? (-(int64_t)ch.part_off - 1) * ps + (cell % T) * Ps + cell / T
+                                         : ch.part_off + w;
+            if (idx < 0 || idx >= H.sp.part_cells) return fail(NNFFT_ERR_ARG, "internal: partial index out of range");
+            if (owner[idx] >= 0) return fail(NNFFT_ERR_ARG, "internal: two windows share a partial cell");
+            owner[idx] = (int32_t)c;
+            if (!in_plane) ovf_count[cell]++;
         }
     }
-    for (int64_t cell = 0; cell < G1; ++cell)
-        if (H.moff[cell + 1] - H.moff[cell] != ovf_count[cell])
+    {
+        // the launch-order copies carry the same windows
+        std::vector<std::array<int32_t, 4>> a, b;
+        for (const Chunk &ch : H.sp.chunks) a.push_back({ch.bin_lo, ch.nbin, ch.part_off, ch.nitem});
+        for (const Chunk &ch : H.sp.launch)
+            if (ch.nitem > 0) b.push_back({ch.bin_lo, ch.nbin, ch.part_off, ch.nitem});
+        std::sort(a.begin(), a.end());
+        std::sort(b.begin(), b.end());
+        if (a != b) return fail(NNFFT_ERR_ARG, "internal: launch chunks differ from the chunks");
+    }
+    for (int64_t cell = 0; cell < G1; ++cell) {
+        const int64_t sl = (cell % T) * Ps + cell / T;
+        if (H.moff[sl + 1] - H.moff[sl] != ovf_count[cell])
             return fail(NNFFT_ERR_ARG, "internal: merge list does not match the overflow windows");
+    }
     for (int32_t e2 : H.midx)
         if (e2 < plane_cells || e2 >= H.sp.part_cells || owner[e2] < 0)
             return fail(NNFFT_ERR_ARG, "internal: merge list entry outside the overflow windows");

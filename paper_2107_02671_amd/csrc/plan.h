@@ -44,6 +44,7 @@ struct SideHost {
     std::vector<Item> launch_items;     // 64 items per launch slot, n = 0 pads
     std::vector<PtRec> trec32;          // FP32: records in per-slot transposed blocks
     int64_t part_cells = 0;             // spreading side: plane cells + overflow cells
+    int64_t ovf_cells = 0;              // spreading side: cells of the overflow windows
     int32_t nplanes = 0;                // spreading side: colours of the windows
     int64_t nblocks = 0;
 };
@@ -68,6 +69,8 @@ struct HostPlan {
     std::vector<double> deconv;        // 1 / (N1 N2 phi_hat_2(l))
     std::vector<double> tw64;          // FFT twiddles
     std::vector<float> tw32;
+    std::vector<double> twA, twB, tw4; // four-step tables (values of the plan's precision)
+    int32_t slotT = 1, slotP = 0;      // plane cell c at slot (c mod T) P + c div T
     std::vector<int32_t> moff, midx;   // merge lists of the spreading windows
     FftPlan fd{};
     int kind = 0;                      // 0 NNFFT, 1 NFFT with equispaced frequencies
