@@ -233,7 +233,8 @@ template <int TM>
 __device__ void spread32_slot(const SpreadArgs &A, const cx<float> *__restrict__ f, int g, Spread32Lds<TM> &L)
 {
     constexpr int D = kDeg;
-    const int t = threadIdx.x & (kItemsPerWg - 1), w = threadIdx.x / kItemsPerWg;
+    // the wave index, known to the compiler as wave-uniform (scalar branches)
+    const int t = threadIdx.x & (kItemsPerWg - 1), w = __builtin_amdgcn_readfirstlane(threadIdx.x / kItemsPerWg);
     const int rows = A.rows, rpw = (rows + kWaves32 - 1) / kWaves32, row0 = w * rpw;
     // this wave's record rows and their coefficient gathers are issued first:
     // their addresses depend on no other load (rows past an item's end repeat
@@ -462,6 +463,8 @@ __global__ __launch_bounds__(64) void k_spread64(SpreadArgs A, const cx<double> 
 // for its rows of the item's points.
 struct Interp32Lds {
     cx<float> H[kDeg + 1][kItemsPerWg];
+    cx<float> hw[kItemsPerWg + 2 * kMaxM - 1];   // the chunk's h_s window
+    float C[2 * kMaxM * (kDeg + 1)];             // tap series [2m][kDeg + 1]
 };
 
 template <int CD>
@@ -469,33 +472,49 @@ __device__ __forceinline__ void interp32_slot(const InterpArgs &A, cx<float> *__
                                               Interp32Lds &L)
 {
     constexpr int D = kDeg;
-    const int t = threadIdx.x & (kItemsPerWg - 1), w = threadIdx.x / kItemsPerWg;
+    // the wave index, known to the compiler as wave-uniform (scalar branches)
+    const int t = threadIdx.x & (kItemsPerWg - 1), w = __builtin_amdgcn_readfirstlane(threadIdx.x / kItemsPerWg);
     const int rows = A.rows, rpw = (rows + kWaves32 - 1) / kWaves32, row0 = w * rpw;
-    // this wave's first record rows are in flight together with the item load
+    const Chunk ch = A.chunks[g];   // one scalar load; its window loads go out first
+    if (ch.nitem == 0) return;
+    const int m = A.m, tm = 2 * m;
+    // the h_s the chunk's items read (labels bin_lo - m + 1 .. bin_lo + nbin + m - 1
+    // after the offset) and the tap series, staged in LDS; the record rows and
+    // the item follow in the same round of loads
+    // (nwin < 64 + 2m <= kThreads32; the series has up to 2 kThreads32 entries)
+    cx<float> hw0 = cxmk(0.f, 0.f);
+    float c0 = 0.f, c1 = 0.f;
+    const int nwin = ch.nbin + tm - 1, nc = tm * (D + 1);
+    if (threadIdx.x < nwin)
+        hw0 = reinterpret_cast<const cx<float> *>(A.hlin)[ch.bin_lo - A.ip_off - m + 1 + A.h_off + threadIdx.x];
+    if (threadIdx.x < nc) c0 = A.C[threadIdx.x];
+    if (threadIdx.x + kThreads32 < nc) c1 = A.C[threadIdx.x + kThreads32];
     const PtRec *__restrict__ rec = A.rec32 + (size_t)g * rows * kItemsPerWg + t;
     PtRec r[kRowsPerWave];
 #pragma unroll
     for (int j = 0; j < kRowsPerWave; ++j) r[j] = rec[wave_row(row0, j, rpw, rows) * kItemsPerWg];
     const Item it = A.items[g * kItemsPerWg + t];
-    const int m = A.m, tm = 2 * m;
     const int lab = it.bin - A.ip_off;
+    if (threadIdx.x < nwin) L.hw[threadIdx.x] = hw0;
+    if (threadIdx.x < nc) L.C[threadIdx.x] = c0;
+    if (threadIdx.x + kThreads32 < nc) L.C[threadIdx.x + kThreads32] = c1;
+    __syncthreads();
     if (it.n > 0) {
-        const float *__restrict__ Cs = A.C;   // same address in every lane: scalar loads
-        const cx<float> *h = reinterpret_cast<const cx<float> *>(A.hlin) + (lab - m + 1 + A.h_off);
+        const cx<float> *h = L.hw + (it.bin - ch.bin_lo);
         constexpr int KW = (D + kWaves32) / kWaves32;   // moments per wave (3)
         float ar[KW], ai[KW];
 #pragma unroll
         for (int j = 0; j < KW; ++j) ar[j] = ai[j] = 0.f;
+        // straight-line body: moments past D (only j = KW - 1 on some waves)
+        // read a valid coefficient and are dropped below
+#pragma unroll 4
         for (int rr = 0; rr < tm; ++rr) {
             const cx<float> hv = h[rr];
 #pragma unroll
             for (int j = 0; j < KW; ++j) {
-                const int k = w + kWaves32 * j;
-                if (k <= D) {
-                    const float c = Cs[rr * (D + 1) + k];
-                    ar[j] = fmaf(c, hv.re, ar[j]);
-                    ai[j] = fmaf(c, hv.im, ai[j]);
-                }
+                const float c = L.C[rr * (D + 1) + min(w + kWaves32 * j, D)];
+                ar[j] = fmaf(c, hv.re, ar[j]);
+                ai[j] = fmaf(c, hv.im, ai[j]);
             }
         }
 #pragma unroll
@@ -871,44 +890,6 @@ struct Dft<T, 5> {
     }
 };
 
-template <typename T>
-struct Dft<T, 16> {
-    // n = 4 n1 + n2, k = k1 + 4 k2: length-4 transforms over n1, twiddles
-    // exp(-2 pi i n2 k1 / 16), length-4 transforms over n2
-    __device__ static void run(cx<T> *a)
-    {
-        const T c1 = (T)0.92387953251128675612818318939678829, s1 = (T)0.38268343236508977172845998403039887;
-        const T h = (T)0.70710678118654752440084436210484904;
-        cx<T> y[4][4];
-#pragma unroll
-        for (int n2 = 0; n2 < 4; ++n2) {
-            cx<T> c[4] = {a[n2], a[4 + n2], a[8 + n2], a[12 + n2]};
-            Dft<T, 4>::run(c);
-#pragma unroll
-            for (int k1 = 0; k1 < 4; ++k1) y[n2][k1] = c[k1];
-        }
-        // exp(-2 pi i e / 16) for e = n2 k1 in {1, 2, 3, 4, 6, 9}
-        const cx<T> w1 = cxmk(c1, -s1), w2 = cxmk(h, -h), w3 = cxmk(s1, -c1), w6 = cxmk(-h, -h),
-                    w9 = cxmk(-c1, s1);
-        y[1][1] = cmul(y[1][1], w1);
-        y[1][2] = cmul(y[1][2], w2);
-        y[1][3] = cmul(y[1][3], w3);
-        y[2][1] = cmul(y[2][1], w2);
-        y[2][2] = mul_mi(y[2][2]);
-        y[2][3] = cmul(y[2][3], w6);
-        y[3][1] = cmul(y[3][1], w3);
-        y[3][2] = cmul(y[3][2], w6);
-        y[3][3] = cmul(y[3][3], w9);
-#pragma unroll
-        for (int k1 = 0; k1 < 4; ++k1) {
-            cx<T> c[4] = {y[0][k1], y[1][k1], y[2][k1], y[3][k1]};
-            Dft<T, 4>::run(c);
-#pragma unroll
-            for (int k2 = 0; k2 < 4; ++k2) a[k1 + 4 * k2] = c[k2];
-        }
-    }
-};
-
 // One Stockham pass of radix R on B transforms of length Lsub held in LDS
 // (src[b * Lsub + j]) into dst.  Twiddle exp(-2 pi i e / Lsub) = tw[e * tstride]
 // (an LDS table of the sub-transform length, tstride = 1).
@@ -979,7 +960,9 @@ __device__ __forceinline__ void stockham_fixed(cx<T> *src, cx<T> *dst, int B, co
 
 // Transforms the B length-Lsub sequences in buf[0] in place (result ends up in
 // buf[0] or buf[1]; the returned pointer tells which).  Power-of-two lengths
-// 64..4096 take fixed radix-8/16 plans; other lengths the plan's radix list.
+// 64..4096 take fixed radix-4/8 plans (radix 16 measured slower: its
+// butterfly is a long serial chain per lane); other lengths the plan's
+// radix list.
 template <typename T>
 __device__ cx<T> *stockham(cx<T> *buf0, cx<T> *buf1, int Lsub, int B, const int8_t *rad, int npass,
                            const cx<T> *__restrict__ tw, int tstride)
@@ -988,12 +971,12 @@ __device__ cx<T> *stockham(cx<T> *buf0, cx<T> *buf1, int Lsub, int B, const int8
         int odd = -1;   // passes of the fixed plan modulo 2
         switch (Lsub) {
         case 64: stockham_fixed<T, 64, 1, 8, 8>(buf0, buf1, B, tw); odd = 0; break;
-        case 128: stockham_fixed<T, 128, 1, 8, 16>(buf0, buf1, B, tw); odd = 0; break;
-        case 256: stockham_fixed<T, 256, 1, 16, 16>(buf0, buf1, B, tw); odd = 0; break;
+        case 128: stockham_fixed<T, 128, 1, 4, 4, 8>(buf0, buf1, B, tw); odd = 1; break;
+        case 256: stockham_fixed<T, 256, 1, 4, 8, 8>(buf0, buf1, B, tw); odd = 1; break;
         case 512: stockham_fixed<T, 512, 1, 8, 8, 8>(buf0, buf1, B, tw); odd = 1; break;
-        case 1024: stockham_fixed<T, 1024, 1, 16, 8, 8>(buf0, buf1, B, tw); odd = 1; break;
-        case 2048: stockham_fixed<T, 2048, 1, 16, 16, 8>(buf0, buf1, B, tw); odd = 1; break;
-        case 4096: stockham_fixed<T, 4096, 1, 16, 16, 16>(buf0, buf1, B, tw); odd = 1; break;
+        case 1024: stockham_fixed<T, 1024, 1, 4, 4, 8, 8>(buf0, buf1, B, tw); odd = 0; break;
+        case 2048: stockham_fixed<T, 2048, 1, 4, 8, 8, 8>(buf0, buf1, B, tw); odd = 0; break;
+        case 4096: stockham_fixed<T, 4096, 1, 8, 8, 8, 8>(buf0, buf1, B, tw); odd = 0; break;
         default: break;
         }
         if (odd >= 0) return odd ? buf1 : buf0;
