@@ -236,17 +236,18 @@ __device__ void spread32_slot(const SpreadArgs &A, const cx<float> *__restrict__
     // the wave index, known to the compiler as wave-uniform (scalar branches)
     const int t = threadIdx.x & (kItemsPerWg - 1), w = __builtin_amdgcn_readfirstlane(threadIdx.x / kItemsPerWg);
     const int rows = A.rows, rpw = (rows + kWaves32 - 1) / kWaves32, row0 = w * rpw;
-    // this wave's record rows and their coefficient gathers are issued first:
-    // their addresses depend on no other load (rows past an item's end repeat
-    // its last record, empty items point at coefficient 0)
+    // this wave's record rows and the item are loaded first, then the
+    // coefficient gathers of the rows that hold points of the item (rows past
+    // an item's end repeat its last record and are not gathered)
     const PtRec *__restrict__ rec = A.rec32 + (size_t)g * rows * kItemsPerWg + t;
     PtRec r[kRowsPerWave];
     cx<float> fv[kRowsPerWave];
 #pragma unroll
     for (int j = 0; j < kRowsPerWave; ++j) r[j] = rec[wave_row(row0, j, rpw, rows) * kItemsPerWg];
-#pragma unroll
-    for (int j = 0; j < kRowsPerWave; ++j) fv[j] = f[r[j].perm];
     const Item it = A.items[g * kItemsPerWg + t];
+#pragma unroll
+    for (int j = 0; j < kRowsPerWave; ++j)
+        fv[j] = (j < rpw && row0 + j < it.n) ? f[r[j].perm] : cxmk(0.f, 0.f);
     const Chunk ch = A.chunks[g];
     if (ch.nitem == 0) return;
     const int m = A.m, tm = 2 * m;
@@ -265,7 +266,8 @@ __device__ void spread32_slot(const SpreadArgs &A, const cx<float> *__restrict__
 #pragma unroll
                 for (int j = 0; j < kRowsPerWave; ++j) r[j] = rec[wave_row(row0, j0 + j, rpw, rows) * kItemsPerWg];
 #pragma unroll
-                for (int j = 0; j < kRowsPerWave; ++j) fv[j] = f[r[j].perm];
+                for (int j = 0; j < kRowsPerWave; ++j)
+                    fv[j] = (j0 + j < nq) ? f[r[j].perm] : cxmk(0.f, 0.f);
             }
 #pragma unroll
             for (int j = 0; j < kRowsPerWave; ++j)
