@@ -78,7 +78,7 @@ nnfft_status fail(nnfft_status st, const std::string &msg)
 // workgroups per CU; blocks of 2^17 nodes (FP32; 1 MB of c64 coefficients,
 // well inside one XCD's 4 MB L2) or 2^16 (FP64), split into 8 when that keeps
 // them >= 2^14 nodes so that every XCD has a block.
-Layout rule_layout(int64_t M, bool fp32)
+Layout rule_layout(int64_t M, bool fp32, bool spreading)
 {
     Layout L;
     const int64_t target_wg = 4 * 256;
@@ -86,7 +86,12 @@ Layout rule_layout(int64_t M, bool fp32)
     int Q = 2;
     while (Q < q && Q < (fp32 ? 32 : 8)) Q *= 2;
     L.Q = Q;
-    const int64_t bmax = fp32 ? (int64_t)1 << 17 : (int64_t)1 << 16;
+    // 2^17 FP32 points per block (1 MB of coefficients per XCD's L2); above 2^20
+    // points a spreading side takes 2^18: fewer blocks mean fewer windows per
+    // grid cell to merge (an interpolation side has no merge and keeps its
+    // scattered stores local)
+    const bool big = spreading && M > ((int64_t)1 << 20);
+    const int64_t bmax = fp32 ? (int64_t)1 << (big ? 18 : 17) : (int64_t)1 << 16;
     L.block = bmax;
     return sanitize_layout(L, M, fp32);
 }
@@ -103,11 +108,11 @@ Layout sanitize_layout(Layout L, int64_t M, bool fp32)
     return L;
 }
 
-Layout choose_layout(int64_t M, bool fp32)
+Layout choose_layout(int64_t M, bool fp32, bool spreading)
 {
     Layout L;
     if (get_tuned_layout(fp32, M, L)) return sanitize_layout(L, M, fp32);
-    return rule_layout(M, fp32);
+    return rule_layout(M, fp32, spreading);
 }
 
 void set_tuned_layout(bool fp32, int64_t M, const Layout &L)
@@ -685,7 +690,7 @@ nnfft_status plan_host(HostPlan &H, int64_t N, int64_t M1, int64_t M2, double si
 
     // node layouts ----------------------------------------------------------
     H.lay1 = lay1 ? sanitize_layout(*lay1, M1, fp32) : choose_layout(M1, fp32);
-    H.lay2 = lay2 ? sanitize_layout(*lay2, M2, fp32) : choose_layout(M2, fp32);
+    H.lay2 = lay2 ? sanitize_layout(*lay2, M2, fp32) : choose_layout(M2, fp32, false);
     std::string err;
     // spreading: t_k = N1 v*_k = N1 N v_k / N*, bin = floor(t_k) + G1/2
     if (!build_side(v, (double)P.N1 * (double)N / (double)P.N_star, P.G1 / 2, P.G1, H.lay1, fp32, m1, H.sp, err))
@@ -790,7 +795,7 @@ nnfft_status nfft_plan_host(HostPlan &H, int64_t N, int64_t M, double sigma, int
         H.tw64.clear();
     }
     H.lay1 = choose_layout(M, fp32);
-    H.lay2 = H.lay1;
+    H.lay2 = choose_layout(M, fp32, false);
     std::string err;
     // spreading (adjoint): t_j = n x_j in the linear grid; interpolation (forward): u_j = n x_j
     if (!build_side(x, (double)n, P.G1 / 2, P.G1, H.lay1, fp32, m, H.sp, err)) return fail(NNFFT_ERR_ARG, err);

@@ -23,8 +23,10 @@ struct Layout {
 };
 
 // The tuned layout for M nodes if the table has one, else the rule.
-Layout choose_layout(int64_t M, bool fp32);
-Layout rule_layout(int64_t M, bool fp32);
+// spreading: the layout of a spreading side (the rule takes larger node
+// blocks there above 2^20 points; interpolation sides keep 2^17).
+Layout choose_layout(int64_t M, bool fp32, bool spreading = true);
+Layout rule_layout(int64_t M, bool fp32, bool spreading = true);
 void set_tuned_layout(bool fp32, int64_t M, const Layout &L);
 bool get_tuned_layout(bool fp32, int64_t M, Layout &L);
 void clear_tuned_layouts();

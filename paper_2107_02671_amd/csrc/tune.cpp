@@ -68,7 +68,7 @@ extern "C" nnfft_status nnfft_autotune(int64_t N, int64_t M, int m, nnfft_precis
         cand.push_back(rule_layout(M, fp32));
         const std::vector<int> Qs = fp32 ? std::vector<int>{4, 8, 16, 32} : std::vector<int>{2, 4, 8};
         const std::vector<int64_t> blocks = {(int64_t)1 << 13, (int64_t)1 << 14, (int64_t)1 << 15,
-                                             (int64_t)1 << 16, (int64_t)1 << 17};
+                                             (int64_t)1 << 16, (int64_t)1 << 17, (int64_t)1 << 18};
         for (int Q : Qs)
             for (int64_t b : blocks)
                 {
