@@ -84,7 +84,12 @@ __device__ __forceinline__ void comp_add(float &hi, float &lo, float x)
 // partial index part_off (cells contiguous).
 __device__ __forceinline__ int cell_slot(int c, int T, int P)
 {
-    return T == 1 ? c : (c % T) * P + c / T;
+    if (T == 1) return c;
+    if ((T & (T - 1)) == 0) {   // power of two (the usual four-step factor): shifts
+        const int sh = __builtin_ctz((unsigned)T);
+        return (c & (T - 1)) * P + (c >> sh);
+    }
+    return (c % T) * P + c / T;
 }
 
 __device__ __forceinline__ int window_index(const Chunk &ch, int wc, int m, int T, int P)
@@ -286,20 +291,27 @@ __device__ void spread32_slot(const SpreadArgs &A, const cx<float> *__restrict__
     __syncthreads();
     if (t < ch.nbin) {
         const int s = L.runS[t], e = L.runE[t];   // s = e for a bin without items
-        for (int k = w; k <= D; k += kWaves32) {
-            float hr = 0.f, hi = 0.f, lr = 0.f, li = 0.f;
-            for (int i = s; i < e; ++i) {
+        constexpr int KW = (D + kWaves32) / kWaves32;   // moments per wave (3; the last one
+        float hr[KW], hi[KW], lr[KW], li[KW];          // only on wave 0)
+#pragma unroll
+        for (int j = 0; j < KW; ++j) hr[j] = hi[j] = lr[j] = li[j] = 0.f;
+        for (int i = s; i < e; ++i) {
+#pragma unroll
+            for (int j = 0; j < KW; ++j) {
+                const int k = min(w + kWaves32 * j, D);
                 cx<float> v = L.mom[0][k][i];
 #pragma unroll
                 for (int ww = 1; ww < kWaves32; ++ww) {
                     v.re += L.mom[ww][k][i].re;
                     v.im += L.mom[ww][k][i].im;
                 }
-                comp_add(hr, lr, v.re);
-                comp_add(hi, li, v.im);
+                comp_add(hr[j], lr[j], v.re);
+                comp_add(hi[j], li[j], v.im);
             }
-            L.bmom[k][t] = cxmk(hr + lr, hi + li);
         }
+#pragma unroll
+        for (int j = 0; j < KW; ++j)
+            if (w + kWaves32 * j <= D) L.bmom[w + kWaves32 * j][t] = cxmk(hr[j] + lr[j], hi[j] + li[j]);
     }
     __syncthreads();
     if (t < ch.nbin) {
