@@ -99,13 +99,17 @@ __device__ __forceinline__ int window_index(const Chunk &ch, int wc, int m, int 
 }
 
 // sinh window of Example 2.1 in FP64:
-//   sinh(beta s)/sinh(beta) = (e^{beta(s-1)} - e^{-beta(s+1)}) / (1 - e^{-2 beta})
+//   sinh(beta s)/sinh(beta) = (e^{beta(s-1)} - e^{-beta(s+1)}) / (1 - e^{-2 beta});
+// the second term is e^{-2 beta s} times the first and is below FP64 rounding
+// (e^{-40} < 5e-18) once 2 beta s > 40, where it is skipped
 __device__ __forceinline__ double omega64(double u, double beta, double inv_den)
 {
     const double q = (1.0 - u) * (1.0 + u);
     if (!(q > 0.0)) return 0.0;
     const double s = sqrt(q);
-    return (exp(beta * (s - 1.0)) - exp(-beta * (s + 1.0))) * inv_den;
+    double v = exp(beta * (s - 1.0));
+    if (2.0 * beta * s <= 40.0) v -= exp(-beta * (s + 1.0));
+    return v * inv_den;
 }
 
 // Chebyshev series sum_k c_k T_k(t) by Clenshaw's recurrence, FP64
@@ -370,6 +374,8 @@ __global__ __launch_bounds__(kThreads32, TM <= 16 ? 6 : 4) void k_spread32(Sprea
 // Spreading, FP64 plain path (items of up to Q64 points)
 // ===========================================================================
 constexpr int Q64 = 8;
+constexpr int kWaves64 = 4;                          // waves per FP64 workgroup
+constexpr int kThreads64 = kWaves64 * kItemsPerWg;
 
 // LDS of the FP64 kernels, sized at launch for the plan's 2m taps (dynamic
 // shared memory), so that short windows leave room for more workgroups per CU.
@@ -395,15 +401,17 @@ static size_t lds64_bytes(int tm)
     return (size_t)tm * kItemsPerWg * sizeof(cx<double>) + 3 * kItemsPerWg * sizeof(int);
 }
 
+// Four waves per chunk: lane t of every wave holds item t; wave w forms the
+// taps r = w, w + 4, ... of the item (disjoint outputs, no reduction).
 template <int WIN>
 __device__ void spread64_slot(const SpreadArgs &A, const cx<double> *__restrict__ f, int g, Spread64Lds &L)
 {
-    const int t = threadIdx.x;
+    const int t = threadIdx.x & (kItemsPerWg - 1), wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kItemsPerWg);
     const Item it = A.items[g * kItemsPerWg + t];
     const Chunk ch = A.chunks[g];
     if (ch.nitem == 0) return;
     const int m = A.m, tm = 2 * m;
-    if (t < ch.nbin) {
+    if (wv == 0 && t < ch.nbin) {
         L.runS[t] = -1;
         L.runE[t] = 0;
     }
@@ -417,7 +425,7 @@ __device__ void spread64_slot(const SpreadArgs &A, const cx<double> *__restrict_
             fv[q] = (q < it.n) ? f[A.perm[p]] : cxmk(0.0, 0.0);
         }
         const double inv_m = 1.0 / (double)m;
-        for (int r = 0; r < tm; ++r) {
+        for (int r = wv; r < tm; r += kWaves64) {
             double ar = 0.0, ai = 0.0;
 #pragma unroll
             for (int q = 0; q < Q64; ++q) {
@@ -430,10 +438,10 @@ __device__ void spread64_slot(const SpreadArgs &A, const cx<double> *__restrict_
             }
             L.sitem[r * kItemsPerWg + t] = cxmk(ar, ai);
         }
-        L.ibin[t] = it.bin - ch.bin_lo;
+        if (wv == 0) L.ibin[t] = it.bin - ch.bin_lo;
     }
     __syncthreads();
-    if (t < ch.nitem) {
+    if (wv == 0 && t < ch.nitem) {
         const int b = L.ibin[t];
         if (t == 0 || L.ibin[t - 1] != b) L.runS[b] = t;
         if (t == ch.nitem - 1 || L.ibin[t + 1] != b) L.runE[b] = t + 1;
@@ -441,7 +449,7 @@ __device__ void spread64_slot(const SpreadArgs &A, const cx<double> *__restrict_
     __syncthreads();
     const int W = ch.nbin + tm - 1;
     double2 *part = reinterpret_cast<double2 *>(A.partial);
-    for (int w = t; w < W; w += blockDim.x) {
+    for (int w = threadIdx.x; w < W; w += blockDim.x) {
         const int blo = max(0, w - tm + 1), bhi = min(ch.nbin - 1, w);
         double ar = 0.0, ai = 0.0;
         for (int b = blo; b <= bhi; ++b) {
@@ -461,7 +469,7 @@ __device__ void spread64_slot(const SpreadArgs &A, const cx<double> *__restrict_
 // WIN: the plan's window family (one instantiation per family keeps the
 // sinh kernel's registers at what the sinh taps need)
 template <int WIN>
-__global__ __launch_bounds__(64) void k_spread64(SpreadArgs A, const cx<double> *__restrict__ f)
+__global__ __launch_bounds__(kThreads64) void k_spread64(SpreadArgs A, const cx<double> *__restrict__ f)
 {
     Spread64Lds L = spread64_lds(2 * A.m);
     spread64_slot<WIN>(A, f, blockIdx.x, L);
@@ -589,8 +597,7 @@ __global__ __launch_bounds__(kThreads32) void k_interp32(InterpArgs A, cx<float>
 }
 
 struct Interp64Lds {
-    cx<double> *hw;   // [2m][64]: grid value r of bin b at r * 64 + b
-    int *ibin, *used;
+    cx<double> *hw;   // the chunk's window: h at labels bin_lo - ip_off - m + 1 + i
 };
 
 __device__ __forceinline__ Interp64Lds interp64_lds(int tm)
@@ -598,46 +605,38 @@ __device__ __forceinline__ Interp64Lds interp64_lds(int tm)
     extern __shared__ __align__(16) char smem[];
     Interp64Lds L;
     L.hw = reinterpret_cast<cx<double> *>(smem);
-    int *ip = reinterpret_cast<int *>(smem + (size_t)tm * kItemsPerWg * sizeof(cx<double>));
-    L.ibin = ip;
-    L.used = ip + kItemsPerWg;
+    (void)tm;
     return L;
 }
 
+// Four waves per chunk: lane t of every wave holds item t; wave w computes
+// the points p0 + w, p0 + w + 4, ... of the item.  The chunk's h window
+// (< 64 + 2m values) is staged in LDS with one round of loads.
 template <int WIN>
 __device__ void interp64_slot(const InterpArgs &A, cx<double> *__restrict__ y, int g, Interp64Lds &L)
 {
-    const int t = threadIdx.x;
-    const Item it = A.items[g * kItemsPerWg + t];
+    const int t = threadIdx.x & (kItemsPerWg - 1), wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kItemsPerWg);
     const Chunk ch = A.chunks[g];
     if (ch.nitem == 0) return;
     const int m = A.m, tm = 2 * m;
-    if (t < ch.nbin) L.used[t] = 0;
+    const int nwin = ch.nbin + tm - 1;   // < 64 + 2m <= kThreads64
+    cx<double> hv0 = cxmk(0.0, 0.0);
+    if (threadIdx.x < nwin)
+        hv0 = reinterpret_cast<const cx<double> *>(A.hlin)[ch.bin_lo - A.ip_off - m + 1 + A.h_off + threadIdx.x];
+    const Item it = A.items[g * kItemsPerWg + t];
+    if (threadIdx.x < nwin) L.hw[threadIdx.x] = hv0;
     __syncthreads();
     if (it.n > 0) {
         const int b = it.bin - ch.bin_lo;
-        L.ibin[t] = b;
-        L.used[b] = 1;
-    }
-    __syncthreads();
-    const cx<double> *h = reinterpret_cast<const cx<double> *>(A.hlin);
-    if (t < ch.nbin && L.used[t]) {
-        const int lab = ch.bin_lo + t - A.ip_off;
-        const int s0 = lab - m + 1 + A.h_off;
-        for (int r = 0; r < tm; ++r) L.hw[r * kItemsPerWg + t] = h[s0 + r];
-    }
-    __syncthreads();
-    if (it.n > 0) {
-        const int b = L.ibin[t];
         const int lab = ch.bin_lo + b - A.ip_off;
         const double inv_m = 1.0 / (double)m;
-        for (int p = it.p0; p < it.p0 + it.n; ++p) {
+        for (int p = it.p0 + wv; p < it.p0 + it.n; p += kWaves64) {
             const double fr = A.frac64[p];
             double sr = 0.0, si = 0.0;
             for (int r = 0; r < tm; ++r) {
                 const double w = tap64<WIN>(A.T64, r, m, fr, (fr + (double)(m - 1 - r)) * inv_m, A.beta,
                                             A.inv_den);
-                const cx<double> hv = L.hw[r * kItemsPerWg + b];
+                const cx<double> hv = L.hw[b + r];
                 sr = fma(hv.re, w, sr);
                 si = fma(hv.im, w, si);
             }
@@ -649,7 +648,7 @@ __device__ void interp64_slot(const InterpArgs &A, cx<double> *__restrict__ y, i
 }
 
 template <int WIN>
-__global__ __launch_bounds__(64) void k_interp64(InterpArgs A, cx<double> *__restrict__ y)
+__global__ __launch_bounds__(kThreads64) void k_interp64(InterpArgs A, cx<double> *__restrict__ y)
 {
     Interp64Lds L = interp64_lds(2 * A.m);
     interp64_slot<WIN>(A, y, blockIdx.x, L);
@@ -661,13 +660,13 @@ static void launch_spread64(const SpreadArgs &A, const void *f, hipStream_t s)
     const size_t lds = lds64_bytes(2 * A.m);
     switch (A.window) {
     case NNFFT_WINDOW_BSPLINE:
-        hipLaunchKernelGGL(k_spread64<NNFFT_WINDOW_BSPLINE>, dim3(A.ngrid), dim3(kItemsPerWg), lds, s, A, in);
+        hipLaunchKernelGGL(k_spread64<NNFFT_WINDOW_BSPLINE>, dim3(A.ngrid), dim3(kThreads64), lds, s, A, in);
         break;
     case NNFFT_WINDOW_ALGEBRAIC:
-        hipLaunchKernelGGL(k_spread64<NNFFT_WINDOW_ALGEBRAIC>, dim3(A.ngrid), dim3(kItemsPerWg), lds, s, A, in);
+        hipLaunchKernelGGL(k_spread64<NNFFT_WINDOW_ALGEBRAIC>, dim3(A.ngrid), dim3(kThreads64), lds, s, A, in);
         break;
     default:
-        hipLaunchKernelGGL(k_spread64<NNFFT_WINDOW_SINH>, dim3(A.ngrid), dim3(kItemsPerWg), lds, s, A, in);
+        hipLaunchKernelGGL(k_spread64<NNFFT_WINDOW_SINH>, dim3(A.ngrid), dim3(kThreads64), lds, s, A, in);
         break;
     }
 }
@@ -678,13 +677,13 @@ static void launch_interp64(const InterpArgs &A, void *y, hipStream_t s)
     const size_t lds = lds64_bytes(2 * A.m);
     switch (A.window) {
     case NNFFT_WINDOW_BSPLINE:
-        hipLaunchKernelGGL(k_interp64<NNFFT_WINDOW_BSPLINE>, dim3(A.ngrid), dim3(kItemsPerWg), lds, s, A, out);
+        hipLaunchKernelGGL(k_interp64<NNFFT_WINDOW_BSPLINE>, dim3(A.ngrid), dim3(kThreads64), lds, s, A, out);
         break;
     case NNFFT_WINDOW_ALGEBRAIC:
-        hipLaunchKernelGGL(k_interp64<NNFFT_WINDOW_ALGEBRAIC>, dim3(A.ngrid), dim3(kItemsPerWg), lds, s, A, out);
+        hipLaunchKernelGGL(k_interp64<NNFFT_WINDOW_ALGEBRAIC>, dim3(A.ngrid), dim3(kThreads64), lds, s, A, out);
         break;
     default:
-        hipLaunchKernelGGL(k_interp64<NNFFT_WINDOW_SINH>, dim3(A.ngrid), dim3(kItemsPerWg), lds, s, A, out);
+        hipLaunchKernelGGL(k_interp64<NNFFT_WINDOW_SINH>, dim3(A.ngrid), dim3(kThreads64), lds, s, A, out);
         break;
     }
 }
@@ -1212,7 +1211,7 @@ __global__ __launch_bounds__(kThreads32, TM <= 16 ? 6 : 4) void k_spread32_batch
     spread32_slot<TM>(A, static_cast<const cx<float> *>(T.in[p]), g, L);
 }
 
-__global__ __launch_bounds__(64) void k_spread64_batch(BatchTable T)
+__global__ __launch_bounds__(kThreads64) void k_spread64_batch(BatchTable T)
 {
     const int p = batch_plan(T, blockIdx.x);
     const SpreadArgs A = T.desc[p]->sp;
@@ -1239,7 +1238,7 @@ __global__ __launch_bounds__(kThreads32) void k_interp32_batch(BatchTable T)
     interp32_slot<CD>(A, static_cast<cx<float> *>(T.out[p]), g, L);
 }
 
-__global__ __launch_bounds__(64) void k_interp64_batch(BatchTable T)
+__global__ __launch_bounds__(kThreads64) void k_interp64_batch(BatchTable T)
 {
     const int p = batch_plan(T, blockIdx.x);
     const InterpArgs A = T.desc[p]->ip;
@@ -1412,10 +1411,10 @@ hipError_t launch_exec_batch(int n, const PlanDev *const *host, const PlanDev *c
             if (sB > 0) hipLaunchKernelGGL((k_fftB_batch<float>), dim3(sB), dim3(thrB), fft_bytes, s, TB);
             launch_interp32_batch(corr_variant(corr_deg), sip, s, Tip);
         } else {
-            hipLaunchKernelGGL(k_spread64_batch, dim3(ssp), dim3(kItemsPerWg), lds64_bytes(tm_sp), s, Tsp);
+            hipLaunchKernelGGL(k_spread64_batch, dim3(ssp), dim3(kThreads64), lds64_bytes(tm_sp), s, Tsp);
             hipLaunchKernelGGL((k_fftA_batch<double>), dim3(sA), dim3(thrA), fft_bytes, s, TA);
             if (sB > 0) hipLaunchKernelGGL((k_fftB_batch<double>), dim3(sB), dim3(thrB), fft_bytes, s, TB);
-            hipLaunchKernelGGL(k_interp64_batch, dim3(sip), dim3(kItemsPerWg), lds64_bytes(tm_ip), s, Tip);
+            hipLaunchKernelGGL(k_interp64_batch, dim3(sip), dim3(kThreads64), lds64_bytes(tm_ip), s, Tip);
         }
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;

@@ -200,6 +200,16 @@ struct nnfft_server_s {
     void completion_loop(int si);
     bool admit(size_t bytes, std::unique_lock<std::mutex> &lk, std::string &err);
     void release_resident_if_evicted(Resident *rs);   // mu held
+    // the least recently used resident plan that no request uses or waits for
+    Resident *idle_resident()   // mu held
+    {
+        Resident *lru = nullptr;
+        for (auto &kv : residents) {
+            Resident *r = kv.second;
+            if (!r->busy && !r->building && r->waiting.empty() && (!lru || r->last_use < lru->last_use)) lru = r;
+        }
+        return lru;
+    }
 };
 
 // Reserves `bytes` of the arena for a plan about to be created, evicting
@@ -213,11 +223,7 @@ bool nnfft_server_s::admit(size_t bytes, std::unique_lock<std::mutex> &lk, std::
             active_bytes += (int64_t)bytes;
             return true;
         }
-        Resident *lru = nullptr;
-        for (auto &kv : residents) {
-            Resident *r = kv.second;
-            if (!r->busy && !r->building && r->waiting.empty() && (!lru || r->last_use < lru->last_use)) lru = r;
-        }
+        Resident *lru = idle_resident();
         if (lru) {
             drop_resident(lru);
             st.evictions++;
@@ -315,7 +321,11 @@ void nnfft_server_s::planner_loop()
 
         lk.lock();
         // admission: reserve, create in the arena; an allocation that fails
-        // on fragmentation waits for the next release and tries again
+        // on fragmentation waits for the next release and tries again.  Plans
+        // leave the arena only under mu, together with their reservation, so
+        // active_bytes == 0 here means the arena emptied while this create
+        // ran: retry at once, and give up only if that retry fails as well.
+        bool retried_empty = false;
         while (status == NNFFT_OK) {
             if (!admit(bytes, lk, err)) {
                 status = NNFFT_ERR_NOMEM;
@@ -329,9 +339,17 @@ void nnfft_server_s::planner_loop()
             if (status == NNFFT_OK) break;
             active_bytes -= (int64_t)bytes;
             cv_space.notify_all();
-            if (status != NNFFT_ERR_NOMEM || active_bytes == 0) break;
-            st.admission_waits++;
-            cv_space.wait(lk);
+            if (status != NNFFT_ERR_NOMEM) break;
+            if (Resident *lru = idle_resident()) {   // free space held by an idle resident plan
+                drop_resident(lru);
+                st.evictions++;
+            } else if (active_bytes == 0) {
+                if (retried_empty) break;
+                retried_empty = true;
+            } else {
+                st.admission_waits++;
+                cv_space.wait(lk);
+            }
             status = NNFFT_OK;
         }
         --planning;

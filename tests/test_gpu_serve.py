@@ -163,7 +163,7 @@ def test_server_admission_and_errors():
         rb, re_ = srv.wait(tb), srv.wait(te)
         st = srv.stats()
     _say(f"    stats {st}; refused: {rb['message']}")
-    assert all(r["status"] == 0 for r in res)
+    assert all(r["status"] == 0 for r in res), [(r["status"], r["message"]) for r in res if r["status"]]
     assert st["arena_peak"] <= budget
     assert st["evictions"] >= 1
     assert rb["status"] == P.binding.NNFFT_ERR_NOMEM
