@@ -164,6 +164,15 @@ bool build_side(const std::vector<double> &nodes, double scale, int64_t off, int
     std::vector<int32_t> sbin(M);
     std::vector<int64_t> cnt(nbins + 1);
     S.nblocks = (M + L.block - 1) / L.block;
+    {
+        // upper bounds of the item and chunk counts (no reallocation while filling)
+        const size_t items_max = (size_t)(M / std::max(1, L.Q) + S.nblocks * nbins + 64);
+        S.items.reserve(items_max);
+        const size_t chunks_max = items_max / kItemsPerWg + (size_t)S.nblocks * (nbins / kItemsPerWg + 2) + 64;
+        S.chunks.reserve(chunks_max);
+        S.chunk_block.reserve(chunks_max);
+        S.chunk_item0.reserve(chunks_max);
+    }
     int64_t part = 0;
     for (int64_t blk = 0; blk < S.nblocks; ++blk) {
         const int64_t k0 = blk * L.block, k1 = std::min(M, k0 + L.block);
@@ -296,12 +305,12 @@ bool build_side(const std::vector<double> &nodes, double scale, int64_t off, int
         const int32_t i0 = S.chunk_item0[order[g]];
         for (int i = 0; i < c.nitem; ++i) S.launch_items[g * kItemsPerWg + i] = S.items[i0 + i];
         if (fp32) {
+            // row by row, so the writes are sequential
             PtRec *blk = S.trec32.data() + (size_t)g * rows * kItemsPerWg;
-            for (int i = 0; i < c.nitem; ++i) {
-                const Item &it = S.items[i0 + i];
-                for (int64_t q = 0; q < rows; ++q)
-                    blk[q * kItemsPerWg + i] = S.rec32[(size_t)(it.p0 + std::min<int64_t>(q, it.n - 1))];
-            }
+            const Item *its = S.items.data() + i0;
+            for (int64_t q = 0; q < rows; ++q)
+                for (int i = 0; i < c.nitem; ++i)
+                    blk[q * kItemsPerWg + i] = S.rec32[(size_t)(its[i].p0 + std::min<int64_t>(q, its[i].n - 1))];
         }
         S.launch[g] = c;
     }
