@@ -288,8 +288,8 @@ nnfft_status nnfft_autotune(int64_t N, int64_t M, int m, nnfft_precision prec, i
 nnfft_status nnfft_set_tuning(nnfft_precision prec, int64_t M, const nnfft_tuning_t *t);
 
 /* The layout a spreading side of M nodes would use now (tuned = 1 if from the
- * table).  Without a table entry the rule takes 2^17-point blocks (FP32; 2^16
- * FP64), 2^18 for spreading sides above 2^20 points. */
+ * table).  Without a table entry the rule takes 2^17-point blocks, 2^18 for
+ * spreading sides above 2^20 points. */
 nnfft_status nnfft_get_tuning(nnfft_precision prec, int64_t M, nnfft_tuning_t *out);
 
 /* Empties the table (plans fall back to the built-in rule). */

@@ -84,14 +84,14 @@ Layout rule_layout(int64_t M, bool fp32, bool spreading)
     const int64_t target_wg = 4 * 256;
     const int64_t q = M / (kItemsPerWg * target_wg);
     int Q = 2;
-    while (Q < q && Q < (fp32 ? 32 : 8)) Q *= 2;
+    while (Q < q && Q < (fp32 ? 32 : 4)) Q *= 2;
     L.Q = Q;
-    // 2^17 FP32 points per block (1 MB of coefficients per XCD's L2); above 2^20
-    // points a spreading side takes 2^18: fewer blocks mean fewer windows per
-    // grid cell to merge (an interpolation side has no merge and keeps its
-    // scattered stores local)
+    // 2^17 points per block (1 MB of FP32 coefficients per XCD's L2); above
+    // 2^20 points a spreading side takes 2^18: fewer blocks mean fewer windows
+    // per grid cell to merge (an interpolation side has no merge and keeps
+    // its scattered stores local)
     const bool big = spreading && M > ((int64_t)1 << 20);
-    const int64_t bmax = fp32 ? (int64_t)1 << (big ? 18 : 17) : (int64_t)1 << 16;
+    const int64_t bmax = (int64_t)1 << (big ? 18 : 17);
     L.block = bmax;
     return sanitize_layout(L, M, fp32);
 }

@@ -85,7 +85,9 @@ def test_tuning_table_rule_set_clear():
     # built-in rule: 16 points per item at 2^20 nodes, 2^17-point blocks, no grid cap
     assert (r["items_points"], r["block_points"], r["tuned"]) == (16, 1 << 17, 0)
     r = binding.nnfft_get_tuning(FP64, 1 << 20)
-    assert (r["items_points"], r["block_points"], r["tuned"]) == (8, 1 << 16, 0)
+    assert (r["items_points"], r["block_points"], r["tuned"]) == (4, 1 << 17, 0)
+    # spreading sides above 2^20 points take 2^18-point blocks
+    assert binding.nnfft_get_tuning(FP32, 1 << 22)["block_points"] == 1 << 18
     # small sides keep one block; 8 blocks once every XCD can get 2^14 points
     assert binding.nnfft_get_tuning(FP32, 1000)["block_points"] == 1000
     assert binding.nnfft_get_tuning(FP32, 8 << 14)["block_points"] == 1 << 14
