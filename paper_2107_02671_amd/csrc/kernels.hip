@@ -76,6 +76,15 @@ __device__ __forceinline__ void comp_add(float &hi, float &lo, float x)
     lo += e;
 }
 
+// Workgroup barrier that orders LDS accesses only: global loads issued
+// before it stay in flight (__syncthreads also waits for those).
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Partial windows of the spreading step.  A plane stores its cells in slot
 // order slot(c) = (c mod T) P + c div T (T: the first four-step factor n1 of
 // the plan's FFT, or 1; P = ceil(G1 / T)), so that the cells one four-step
@@ -511,16 +520,16 @@ __device__ __forceinline__ void interp32_slot(const InterpArgs &A, cx<float> *__
         hw0 = reinterpret_cast<const cx<float> *>(A.hlin)[ch.bin_lo - A.ip_off - m + 1 + A.h_off + threadIdx.x];
     if (threadIdx.x < nc) c0 = A.C[threadIdx.x];
     if (threadIdx.x + kThreads32 < nc) c1 = A.C[threadIdx.x + kThreads32];
+    const Item it = A.items[g * kItemsPerWg + t];   // before the records: waited for first
     const PtRec *__restrict__ rec = A.rec32 + (size_t)g * rows * kItemsPerWg + t;
     PtRec r[kRowsPerWave];
 #pragma unroll
     for (int j = 0; j < kRowsPerWave; ++j) r[j] = rec[wave_row(row0, j, rpw, rows) * kItemsPerWg];
-    const Item it = A.items[g * kItemsPerWg + t];
     const int lab = it.bin - A.ip_off;
     if (threadIdx.x < nwin) L.hw[threadIdx.x] = hw0;
     if (threadIdx.x < nc) L.C[threadIdx.x] = c0;
     if (threadIdx.x + kThreads32 < nc) L.C[threadIdx.x + kThreads32] = c1;
-    __syncthreads();
+    lds_barrier();   // the record rows stay in flight
     if (it.n > 0) {
         const cx<float> *h = L.hw + (it.bin - ch.bin_lo);
         constexpr int KW = (D + kWaves32) / kWaves32;   // moments per wave (3)
@@ -545,7 +554,7 @@ __device__ __forceinline__ void interp32_slot(const InterpArgs &A, cx<float> *__
             if (k <= D) L.H[k][t] = cxmk(ar[j], ai[j]);
         }
     }
-    __syncthreads();
+    lds_barrier();
     if (it.n > 0) {
         float Hr[D + 1], Hi[D + 1];
 #pragma unroll
