@@ -166,16 +166,22 @@ def nnfft(N, v, f, x, sigma1=2.0, sigma2=2.0, m1=4, m2=4, return_steps=False, wi
     """Algorithm 2.2 in FP64 with a direct DFT for step 3 (both windows of
     family `window`).
 
-    return_steps=True also returns g (step 1, length G1, index l + G1/2) and
-    h (step 3, length N2, index s + N2/2)."""
+    Step 3 forms only the h_s that step 4 reads for these x, so outputs at a
+    few nodes of a large-bandwidth problem cost a few direct sums of length
+    G1 each.  return_steps=True forms all of them and also returns g (step 1,
+    length G1, index l + G1/2) and h (step 3, length N2, index s + N2/2)."""
     v, x, f = _real(v), _real(x), _cplx(f)
     P = params(N, sigma1, sigma2, m1, m2, window)
     y = np.zeros(len(x), dtype=np.complex128)
-    g = np.zeros(P.G1, dtype=np.complex128)
-    h = np.zeros(P.N2, dtype=np.complex128)
+    g = h = None
+    gp = hp = None
+    if return_steps:
+        g = np.zeros(P.G1, dtype=np.complex128)
+        h = np.zeros(P.N2, dtype=np.complex128)
+        gp, hp = _dp(g.view(np.float64)), _dp(h.view(np.float64))
     rc = lib().orc_nnfft_window(int(window), int(N), float(sigma1), float(sigma2), int(m1), int(m2), len(v),
                                 _dp(v), _dp(f.view(np.float64)), len(x), _dp(x), _dp(y.view(np.float64)),
-                                _dp(g.view(np.float64)), _dp(h.view(np.float64)))
+                                gp, hp)
     if rc == 2:
         raise ValueError("node outside [-1/2, 1/2]")
     if rc:

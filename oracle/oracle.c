@@ -405,14 +405,30 @@ int orc_nnfft_window(int window, long N, double sigma1, double sigma2, int m1, i
 
     /* Step 3: h_s = (1/N2) sum_{l in I_G1} g_hat_l exp(-2 pi i l s / N2),
      * s in I_N2, as a direct DFT.  The exponent only depends on
-     * (l s) mod N2, which is reduced exactly in integers. */
+     * (l s) mod N2, which is reduced exactly in integers.  Step 4 reads h_s
+     * only for the 2 m2 labels s next to each u_j, so only those are
+     * formed (all of them once M2 covers the grid); each one is the same sum.
+     * Without h_out the other entries stay unset and unread. */
+    unsigned char *need = calloc((size_t)N2, 1);
+    if (!need) { free(g); free(gh); free(h); free(tw); return 3; }
+    if (h_out) memset(need, 1, (size_t)N2);
+    for (long j = 0; j < M2; j++) {
+        double u = (double)N2 * (double)Ns * x[j] / (double)N1;
+        long c = (long)floor(u);
+        for (long sv = c - m2 + 1; sv <= c + m2; sv++) {
+            long o = ((sv % N2) + N2) % N2;
+            long oi = (o >= N2 / 2) ? o - N2 : o;
+            need[oi + N2 / 2] = 1;
+        }
+    }
     for (long q = 0; q < N2; q++) {
         tw[2 * q] = cos(2.0 * ORC_PI * (double)q / (double)N2);
         tw[2 * q + 1] = -sin(2.0 * ORC_PI * (double)q / (double)N2);
     }
     long s;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(dynamic, 64)
     for (s = -N2 / 2; s < N2 / 2; s++) {
+        if (!need[s + N2 / 2]) continue;
         double re = 0.0, im = 0.0;
         for (long l = -G1 / 2; l < G1 / 2; l++) {
             long q = ((l * s) % N2 + N2) % N2;
@@ -424,6 +440,7 @@ int orc_nnfft_window(int window, long N, double sigma1, double sigma2, int m1, i
         h[2 * o] = re / (double)N2;
         h[2 * o + 1] = im / (double)N2;
     }
+    free(need);
     if (h_out) memcpy(h_out, h, sizeof(double) * (size_t)(2 * N2));
 
     /* Step 4 and output: s1(N x_j) = sum_{|s/N2 - x_j/sigma1| < m2/N2} h_s

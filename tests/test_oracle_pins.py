@@ -265,6 +265,30 @@ def test_nnfft_linearity():
     np.testing.assert_allclose(lhs, rhs, rtol=0, atol=1e-12 * np.abs(lhs).max())
 
 
+def test_nnfft_outputs_at_node_subsets():
+    # Each output of Algorithm 2.2 depends on its own node only, and step 3 of
+    # the oracle forms just the h_s that step 4 reads: outputs at a subset of
+    # the nodes (grid edges included) equal the full run's bit for bit, and a
+    # few nodes at a large bandwidth still meet Theorem 4.1.  (With the step
+    # outputs requested, every h_s is formed.)
+    rng = _rng(27)
+    N, m = 300, 6
+    v = rng.uniform(-0.5, 0.5, 400)
+    x = np.concatenate([[-0.5, 0.5, 0.0], rng.uniform(-0.5, 0.5, 300)])
+    f = _cgauss(rng, 400)
+    full = oracle.nnfft(N, v, f, x, 2.0, 2.0, m, m, return_steps=True)[0]     # every h_s formed
+    idx = np.array([0, 1, 2, 17, 150, 302])
+    np.testing.assert_array_equal(oracle.nnfft(N, v, f, x[idx], 2.0, 2.0, m, m), full[idx])
+    N = 1 << 17
+    P = oracle.params(N, 2.0, 2.0, m, m)
+    v = rng.uniform(-0.5, 0.5, 2000)
+    f = _cgauss(rng, 2000)
+    xs = np.concatenate([[0.5, -0.5], rng.uniform(-0.5, 0.5, 6)])
+    y = oracle.nnfft(N, v, f, xs, 2.0, 2.0, m, m)
+    err = np.abs(y - oracle.direct(N, v, f, xs)).max() / np.abs(f).sum()
+    assert err <= _bound(P)
+
+
 # --------------------------------------------------------------------------
 # quadrature rules
 # --------------------------------------------------------------------------
