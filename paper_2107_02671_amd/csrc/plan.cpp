@@ -6,10 +6,12 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <exception>
 #include <map>
 #include <mutex>
 #include <new>
 #include <string>
+#include <thread>
 #include <utility>
 #include <vector>
 
@@ -145,19 +147,21 @@ bool build_side(const std::vector<double> &nodes, double scale, int64_t off, int
                 const Layout &L, bool fp32, int m, SideHost &S, std::string &err)
 {
     const int64_t M = (int64_t)nodes.size();
-    std::vector<int32_t> bin(M);
-    std::vector<double> fr(M);
-    for (int64_t k = 0; k < M; ++k) {
-        const double t = scale * nodes[k];
-        const double c = std::floor(t);
-        const int64_t b = (int64_t)c + off;
-        if (b < 0 || b >= nbins) {
-            err = "internal: node record outside the grid";
-            return false;
-        }
-        bin[k] = (int32_t)b;
-        fr[k] = t - c;
+    if (!(std::fabs(scale) <= (double)((int64_t)1 << 26))) {
+        err = "internal: grid scale out of range";
+        return false;
     }
+    // cell and offset of node k, formed again by each pass that needs them
+    // (the same expression, so the same values) instead of held in arrays
+    // (|t| <= 2^25 for nodes in [-1/2, 1/2], so truncation stepped down for
+    // negative non-integers is the exact floor, without a library call)
+    auto cell_of = [&](int64_t k, double *frac) {
+        const double t = scale * nodes[k];
+        const double tr = (double)(int64_t)t;
+        const double c = tr > t ? tr - 1.0 : tr;
+        *frac = t - c;
+        return (int64_t)c + off;
+    };
     S.perm.assign(M, 0);
     if (fp32) S.rec32.assign(M, PtRec{0, 0.f});
     else S.frac64.assign(M, 0.0);
@@ -177,19 +181,29 @@ bool build_side(const std::vector<double> &nodes, double scale, int64_t off, int
     for (int64_t blk = 0; blk < S.nblocks; ++blk) {
         const int64_t k0 = blk * L.block, k1 = std::min(M, k0 + L.block);
         std::fill(cnt.begin(), cnt.end(), 0);
-        for (int64_t k = k0; k < k1; ++k) cnt[bin[k] + 1]++;
+        for (int64_t k = k0; k < k1; ++k) {
+            double fr;
+            const int64_t b = cell_of(k, &fr);
+            if (b < 0 || b >= nbins) {
+                err = "internal: node record outside the grid";
+                return false;
+            }
+            cnt[b + 1]++;
+        }
         for (int64_t b = 0; b < nbins; ++b) cnt[b + 1] += cnt[b];
         // stable counting sort of the block by bin
         for (int64_t k = k0; k < k1; ++k) {
-            const int64_t pos = k0 + cnt[bin[k]]++;
+            double fr;
+            const int64_t b = cell_of(k, &fr);
+            const int64_t pos = k0 + cnt[b]++;
             S.perm[pos] = (int32_t)k;
-            sbin[pos] = bin[k];
+            sbin[pos] = (int32_t)b;
             if (fp32) {
-                float f = (float)fr[k];
+                float f = (float)fr;
                 if (!(f < 1.0f)) f = 0.99999994f;   // keep the offset inside [0, 1)
                 S.rec32[pos] = PtRec{(int32_t)k, f};
             } else {
-                S.frac64[pos] = fr[k];
+                S.frac64[pos] = fr;
             }
         }
         // items: balanced split of each bin run into ceil(n / Q) pieces
@@ -316,6 +330,51 @@ bool build_side(const std::vector<double> &nodes, double scale, int64_t off, int
     }
     return true;
 }
+
+// Runs the two side builds, the second one on a thread of its own when
+// `parallel` is set (they share no state); the first failure's message goes
+// to err and an exception of either build is rethrown here.
+template <typename BuildA, typename BuildB>
+bool build_both_sides(BuildA &&a, BuildB &&b, bool parallel, std::string &err)
+{
+    std::string ea, eb;
+    bool okb = false;
+    std::exception_ptr xb;
+    std::thread tb;
+    if (parallel) {
+        try {
+            tb = std::thread([&] {
+                try {
+                    okb = b(eb);
+                } catch (...) {
+                    xb = std::current_exception();
+                }
+            });
+        } catch (const std::system_error &) {   // no thread available: build in turn
+        }
+    }
+    bool oka = false;
+    try {
+        oka = a(ea);
+    } catch (...) {
+        if (tb.joinable()) tb.join();
+        throw;
+    }
+    if (tb.joinable()) {
+        tb.join();
+        if (xb) std::rethrow_exception(xb);
+    } else {
+        okb = b(eb);
+    }
+    if (!oka || !okb) {
+        err = oka ? eb : ea;
+        return false;
+    }
+    return true;
+}
+
+// Both sides on two threads once each holds this many points
+constexpr int64_t kParallelSidePoints = (int64_t)1 << 15;
 
 // largest-square-ish factorization N2 = n1 * n2 with both parts <= limit
 bool fft_factor(int64_t N2, int64_t limit, int64_t &n1, int64_t &n2)
@@ -702,11 +761,17 @@ nnfft_status plan_host(HostPlan &H, int64_t N, int64_t M1, int64_t M2, double si
     H.lay2 = lay2 ? sanitize_layout(*lay2, M2, fp32) : choose_layout(M2, fp32, false);
     std::string err;
     // spreading: t_k = N1 v*_k = N1 N v_k / N*, bin = floor(t_k) + G1/2
-    if (!build_side(v, (double)P.N1 * (double)N / (double)P.N_star, P.G1 / 2, P.G1, H.lay1, fp32, m1, H.sp, err))
-        return fail(NNFFT_ERR_ARG, err);
     // interpolation: u_j = N2 N* x_j / N1, bin = floor(u_j) + N2/2
-    if (!build_side(x, (double)P.N2 * (double)P.N_star / (double)P.N1, P.N2 / 2, P.N2 + 1, H.lay2, fp32, 0,
-                    H.ip, err))
+    if (!build_both_sides(
+            [&](std::string &e) {
+                return build_side(v, (double)P.N1 * (double)N / (double)P.N_star, P.G1 / 2, P.G1, H.lay1, fp32,
+                                  m1, H.sp, e);
+            },
+            [&](std::string &e) {
+                return build_side(x, (double)P.N2 * (double)P.N_star / (double)P.N1, P.N2 / 2, P.N2 + 1, H.lay2,
+                                  fp32, 0, H.ip, e);
+            },
+            std::min(M1, M2) >= kParallelSidePoints, err))
         return fail(NNFFT_ERR_ARG, err);
     // the sorted copies are only needed by the FP64 kernels
     if (fp32) {
@@ -807,8 +872,11 @@ nnfft_status nfft_plan_host(HostPlan &H, int64_t N, int64_t M, double sigma, int
     H.lay2 = choose_layout(M, fp32, false);
     std::string err;
     // spreading (adjoint): t_j = n x_j in the linear grid; interpolation (forward): u_j = n x_j
-    if (!build_side(x, (double)n, P.G1 / 2, P.G1, H.lay1, fp32, m, H.sp, err)) return fail(NNFFT_ERR_ARG, err);
-    if (!build_side(x, (double)n, n / 2, n + 1, H.lay2, fp32, 0, H.ip, err)) return fail(NNFFT_ERR_ARG, err);
+    if (!build_both_sides(
+            [&](std::string &e) { return build_side(x, (double)n, P.G1 / 2, P.G1, H.lay1, fp32, m, H.sp, e); },
+            [&](std::string &e) { return build_side(x, (double)n, n / 2, n + 1, H.lay2, fp32, 0, H.ip, e); },
+            M >= kParallelSidePoints, err))
+        return fail(NNFFT_ERR_ARG, err);
     if (fp32) {
         std::vector<int32_t>().swap(H.sp.perm);
         std::vector<int32_t>().swap(H.ip.perm);
@@ -871,9 +939,18 @@ nnfft_status check_plan(const HostPlan &H, const std::vector<double> &v, const s
         (void)m;
         return std::string();
     };
-    std::string e = side(H.sp, H.lay1, P.M1, P.G1, P.m1, "spreading");
-    if (e.empty()) e = side(H.ip, H.lay2, P.M2, P.N2 + 1, P.m2, "interpolation");
-    if (!e.empty()) return fail(NNFFT_ERR_ARG, "internal: " + e);
+    std::string e;
+    if (!build_both_sides(
+            [&](std::string &r) {
+                r = side(H.sp, H.lay1, P.M1, P.G1, P.m1, "spreading");
+                return r.empty();
+            },
+            [&](std::string &r) {
+                r = side(H.ip, H.lay2, P.M2, P.N2 + 1, P.m2, "interpolation");
+                return r.empty();
+            },
+            std::min(P.M1, P.M2) >= kParallelSidePoints, e))
+        return fail(NNFFT_ERR_ARG, "internal: " + e);
     (void)v;
     (void)x;
     // spreading windows
