@@ -208,8 +208,16 @@ double window_value(const Window &w, double u)
     }
 }
 
-// (pi v)^(-b) J_b(2 pi v) for integer b: its power series where the argument
-// is small against the order, else the library Bessel function.
+// log Gamma(x) through the reentrant form: the plain lgamma stores the sign
+// in a process-wide variable, which races when planner threads run it at once.
+static double log_gamma(double x)
+{
+    int sign = 0;
+    return ::lgamma_r(x, &sign);
+}
+
+// (pi v)^(-b) J_b(2 pi v) for integer b (the algebraic window's b = 3 m): its
+// power series where the argument is small against the order, else libm's jn.
 static double bessel_ratio(double b, double v)
 {
     const double a = kPi * std::fabs(v);
@@ -218,9 +226,11 @@ static double bessel_ratio(double b, double v)
         const int K = 40;
         double acc = 1.0;
         for (int k = K; k >= 1; --k) acc = 1.0 - acc * a * a / ((double)k * ((double)k + b));
-        return acc * std::exp(-std::lgamma(b + 1.0));
+        return acc * std::exp(-log_gamma(b + 1.0));
     }
-    return std::cyl_bessel_j(b, 2.0 * a) * std::exp(-b * std::log(a));
+    // libm's integer-order jn keeps no state (the C++ library's general-order
+    // Bessel function calls the plain lgamma, which does), so threads may share it
+    return ::jn((int)b, 2.0 * a) * std::exp(-b * std::log(a));
 }
 
 double window_hat(const Window &w, double v)
@@ -235,7 +245,7 @@ double window_hat(const Window &w, double v)
     case NNFFT_WINDOW_ALGEBRAIC: {
         // pi (2b)! / (4^b b!) (pi v)^(-b) J_b(2 pi v)
         const double b = w.beta;
-        const double lc = std::log(kPi) + std::lgamma(2.0 * b + 1.0) - b * std::log(4.0) - std::lgamma(b + 1.0);
+        const double lc = std::log(kPi) + log_gamma(2.0 * b + 1.0) - b * std::log(4.0) - log_gamma(b + 1.0);
         return std::exp(lc) * bessel_ratio(b, v);
     }
     default:

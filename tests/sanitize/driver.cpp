@@ -1,0 +1,71 @@
+// Plans every window family and precision for a spread of bandwidths, kernel
+// sizes and node sets (uniform, clustered, edge nodes, single nodes) on the
+// host only, through the dry-run entry point and the NFFT planner.  Built
+// with sanitizers, it checks the planner's memory accesses and, with planner
+// threads of its own on top of the two-sided builds, its threading.
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <random>
+#include <thread>
+#include <vector>
+#include "../../include/nnfft.h"
+#include "../../paper_2107_02671_amd/csrc/plan.h"
+
+static int run(unsigned seed, bool small)
+{
+    std::mt19937_64 g(seed);
+    std::uniform_real_distribution<double> U(-0.5, 0.5);
+    std::normal_distribution<double> Nrm(0.0, 1e-3);
+    int refused = 0;
+    const std::vector<int64_t> Ms = small ? std::vector<int64_t>{1, 65, 1000, 40000}
+                                          : std::vector<int64_t>{1, 2, 63, 64, 65, 1000, 40000};
+    for (int64_t M : Ms)
+        for (int prec : {0, 1})
+            for (int win : {0, 1, 2})
+                for (int N : {2, 64, 333, 4096})
+                    for (int m : {4, 6, 16})
+                        for (int clustered : {0, 1}) {
+                            if (M >= 40000 && m != 6) continue;
+                            std::vector<double> v(M), x(M);
+                            for (int64_t k = 0; k < M; ++k) {
+                                if (clustered) {
+                                    const double c = (double)(k % 7) * 0.1 - 0.3;
+                                    v[k] = std::clamp(c + Nrm(g), -0.5, 0.5);
+                                    x[k] = std::clamp(-c + Nrm(g), -0.5, 0.5);
+                                } else {
+                                    v[k] = U(g);
+                                    x[k] = U(g);
+                                }
+                            }
+                            if (M > 2) {
+                                v[0] = -0.5;
+                                v[1] = 0.5;
+                                x[0] = 0.5;
+                                x[1] = -0.5;
+                            }
+                            nnfft_info_t info;
+                            if (nnfft_plan_window_dry_run(N, M, M, 2.0, 1.5, m, m, (nnfft_precision)prec,
+                                                          (nnfft_window)win, v.data(), x.data(), &info) != NNFFT_OK)
+                                ++refused;
+                            nnfft::HostPlan H;
+                            if (nnfft::nfft_plan_host(H, 2 * N, M, 2.0, m, (nnfft_precision)prec, x) != NNFFT_OK)
+                                ++refused;
+                        }
+    return refused;
+}
+
+int main(int argc, char **argv)
+{
+    // "threads": four planner threads at once (smaller node sets each)
+    if (argc > 1 && std::strcmp(argv[1], "threads") == 0) {
+        std::vector<std::thread> th;
+        int refused[4] = {0, 0, 0, 0};
+        for (int t = 0; t < 4; ++t) th.emplace_back([t, &refused] { refused[t] = run(100 + t, true); });
+        for (auto &x : th) x.join();
+        std::printf("refused %d\n", refused[0] + refused[1] + refused[2] + refused[3]);
+        return 0;
+    }
+    std::printf("refused %d\n", run(11, false));
+    return 0;
+}
