@@ -261,7 +261,10 @@ __device__ void spread32_slot(const SpreadArgs &A, const cx<float> *__restrict__
     PtRec r[kRowsPerWave];
     cx<float> fv[kRowsPerWave];
 #pragma unroll
-    for (int j = 0; j < kRowsPerWave; ++j) r[j] = rec[wave_row(row0, j, rpw, rows) * kItemsPerWg];
+    for (int j = 0; j < kRowsPerWave; ++j) {   // rpw is uniform: rows past it are not loaded
+        r[j] = PtRec{0, 0.f};
+        if (j < rpw) r[j] = rec[wave_row(row0, j, rpw, rows) * kItemsPerWg];
+    }
     const Item it = A.items[g * kItemsPerWg + t];
 #pragma unroll
     for (int j = 0; j < kRowsPerWave; ++j)
@@ -524,7 +527,10 @@ __device__ __forceinline__ void interp32_slot(const InterpArgs &A, cx<float> *__
     const PtRec *__restrict__ rec = A.rec32 + (size_t)g * rows * kItemsPerWg + t;
     PtRec r[kRowsPerWave];
 #pragma unroll
-    for (int j = 0; j < kRowsPerWave; ++j) r[j] = rec[wave_row(row0, j, rpw, rows) * kItemsPerWg];
+    for (int j = 0; j < kRowsPerWave; ++j) {   // rpw is uniform: rows past it are not loaded
+        r[j] = PtRec{0, 0.f};
+        if (j < rpw) r[j] = rec[wave_row(row0, j, rpw, rows) * kItemsPerWg];
+    }
     const int lab = it.bin - A.ip_off;
     if (threadIdx.x < nwin) L.hw[threadIdx.x] = hw0;
     if (threadIdx.x < nc) L.C[threadIdx.x] = c0;
@@ -1333,6 +1339,17 @@ static void launch_interp32_batch(int cd, int grid, hipStream_t s, const BatchTa
     }
 }
 
+// k_spread32 variants: tap rows TM in {12, 16, 32}, the smallest >= 2m
+static void launch_spread32(const SpreadArgs &A, int grid, const cx<float> *f, hipStream_t s)
+{
+    if (2 * A.m <= 12)
+        hipLaunchKernelGGL((k_spread32<12>), dim3(grid), dim3(kThreads32), 0, s, A, f);
+    else if (2 * A.m <= 16)
+        hipLaunchKernelGGL((k_spread32<16>), dim3(grid), dim3(kThreads32), 0, s, A, f);
+    else
+        hipLaunchKernelGGL((k_spread32<32>), dim3(grid), dim3(kThreads32), 0, s, A, f);
+}
+
 // evaluated degree of the 1/phi_hat_1 series: the smallest variant >= deg
 static int corr_variant(int deg)
 {
@@ -1346,10 +1363,7 @@ hipError_t launch_exec(const PlanDev &P, const void *f, void *y, hipStream_t s, 
     if (P.prec == NNFFT_FP32_COMP) {
         const cx<float> *fin = reinterpret_cast<const cx<float> *>(f);
         const int gs = P.sp.ngrid, gi = P.ip.ngrid;
-        if (2 * P.sp.m <= 16)
-            hipLaunchKernelGGL((k_spread32<16>), dim3(gs), dim3(kThreads32), 0, s, P.sp, fin);
-        else
-            hipLaunchKernelGGL((k_spread32<32>), dim3(gs), dim3(kThreads32), 0, s, P.sp, fin);
+        launch_spread32(P.sp, gs, fin, s);
         if (ev) (void)hipEventRecord(ev[1], s);
         launch_fft<float>(P.fft, s);
         if (ev) (void)hipEventRecord(ev[2], s);
@@ -1373,8 +1387,7 @@ hipError_t launch_exec_batch(int n, const PlanDev *const *host, const PlanDev *c
         const int nb = std::min(kMaxBatch, n - b0);
         BatchTable Tsp{}, Tip{}, TA{}, TB{};
         int ssp = 0, sip = 0, sA = 0, sB = 0, thrA = 64, thrB = 64;
-        bool long_window = false;
-        int tm_sp = 2, tm_ip = 2;   // largest 2m of the group (FP64 LDS size)
+        int tm_sp = 2, tm_ip = 2;   // largest 2m of the group (FP32 variant, FP64 LDS size)
         size_t fft_bytes = 0;       // largest FFT LDS of the group
         int corr_deg = 0;
         for (int i = 0; i < nb; ++i) {
@@ -1399,7 +1412,6 @@ hipError_t launch_exec_batch(int n, const PlanDev *const *host, const PlanDev *c
                 thrA = std::max(thrA, P.fft.threadsA);
                 thrB = std::max(thrB, P.fft.threadsB);
             }
-            long_window = long_window || 2 * P.sp.m > 16;
             tm_sp = std::max(tm_sp, 2 * P.sp.m);
             fft_bytes = std::max(fft_bytes, P.prec == NNFFT_FP32_COMP ? fft_lds_bytes<float>(P.fft)
                                                                       : fft_lds_bytes<double>(P.fft));
@@ -1412,10 +1424,12 @@ hipError_t launch_exec_batch(int n, const PlanDev *const *host, const PlanDev *c
         TB.start[nb] = sB;
         Tsp.n = Tip.n = TA.n = TB.n = nb;
         if (host[b0]->prec == NNFFT_FP32_COMP) {
-            if (long_window)
+            if (tm_sp > 16)
                 hipLaunchKernelGGL((k_spread32_batch<32>), dim3(ssp), dim3(kThreads32), 0, s, Tsp);
-            else
+            else if (tm_sp > 12)
                 hipLaunchKernelGGL((k_spread32_batch<16>), dim3(ssp), dim3(kThreads32), 0, s, Tsp);
+            else
+                hipLaunchKernelGGL((k_spread32_batch<12>), dim3(ssp), dim3(kThreads32), 0, s, Tsp);
             hipLaunchKernelGGL((k_fftA_batch<float>), dim3(sA), dim3(thrA), fft_bytes, s, TA);
             if (sB > 0) hipLaunchKernelGGL((k_fftB_batch<float>), dim3(sB), dim3(thrB), fft_bytes, s, TB);
             launch_interp32_batch(corr_variant(corr_deg), sip, s, Tip);
@@ -1447,10 +1461,7 @@ hipError_t launch_nfft(const PlanDev &P, bool adjoint, const void *in, void *out
     if (P.prec == NNFFT_FP32_COMP) {
         if (adjoint) {
             const cx<float> *yin = reinterpret_cast<const cx<float> *>(in);
-            if (2 * P.sp.m <= 16)
-                hipLaunchKernelGGL((k_spread32<16>), dim3(P.sp.ngrid), dim3(kThreads32), 0, s, P.sp, yin);
-            else
-                hipLaunchKernelGGL((k_spread32<32>), dim3(P.sp.ngrid), dim3(kThreads32), 0, s, P.sp, yin);
+            launch_spread32(P.sp, P.sp.ngrid, yin, s);
             launch_fft<float>(F, s);
         } else {
             launch_fft<float>(F, s);
