@@ -389,52 +389,83 @@ constexpr int Q64 = 8;
 constexpr int kWaves64 = 4;                          // waves per FP64 workgroup
 constexpr int kThreads64 = kWaves64 * kItemsPerWg;
 
-// LDS of the FP64 kernels, sized at launch for the plan's 2m taps (dynamic
-// shared memory), so that short windows leave room for more workgroups per CU.
+// LDS of the FP64 spreading kernel, sized at launch for the plan's 2m taps and
+// item size (dynamic shared memory), so that short windows and small items
+// leave room for more workgroups per CU.
 struct Spread64Lds {
     cx<double> *sitem;   // [2m][64]: tap r of item t at r * 64 + t
+    cx<double> *pv;      // [rows][64]: coefficient of point q of item t at q * 64 + t
+    double *pf;          // [rows][64]: its cell offset
     int *ibin, *runS, *runE;
 };
 
-__device__ __forceinline__ Spread64Lds spread64_lds(int tm)
+__device__ __forceinline__ Spread64Lds spread64_lds(int tm, int rows)
 {
     extern __shared__ __align__(16) char smem[];
     Spread64Lds L;
     L.sitem = reinterpret_cast<cx<double> *>(smem);
-    int *ip = reinterpret_cast<int *>(smem + (size_t)tm * kItemsPerWg * sizeof(cx<double>));
+    L.pv = L.sitem + (size_t)tm * kItemsPerWg;
+    L.pf = reinterpret_cast<double *>(L.pv + (size_t)rows * kItemsPerWg);
+    int *ip = reinterpret_cast<int *>(L.pf + (size_t)rows * kItemsPerWg);
     L.ibin = ip;
     L.runS = ip + kItemsPerWg;
     L.runE = ip + 2 * kItemsPerWg;
     return L;
 }
 
-static size_t lds64_bytes(int tm)
+static size_t lds64_bytes(int tm, int rows)
 {
-    return (size_t)tm * kItemsPerWg * sizeof(cx<double>) + 3 * kItemsPerWg * sizeof(int);
+    return ((size_t)tm + rows) * kItemsPerWg * sizeof(cx<double>) + (size_t)rows * kItemsPerWg * sizeof(double) +
+           3 * kItemsPerWg * sizeof(int);
 }
 
-// Four waves per chunk: lane t of every wave holds item t; wave w forms the
-// taps r = w, w + 4, ... of the item (disjoint outputs, no reduction).
+// Four waves per chunk: lane t of every wave holds item t.  Wave w loads the
+// points q = w, w + 4 of the item (each point once) into LDS; then wave w
+// forms the taps r = w, w + 4, ... of the item over all its points
+// (disjoint outputs, no reduction).
 template <int WIN>
 __device__ void spread64_slot(const SpreadArgs &A, const cx<double> *__restrict__ f, int g, Spread64Lds &L)
 {
+    constexpr int QW = Q64 / kWaves64;   // points of an item one wave loads
     const int t = threadIdx.x & (kItemsPerWg - 1), wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kItemsPerWg);
     const Item it = A.items[g * kItemsPerWg + t];
     const Chunk ch = A.chunks[g];
     if (ch.nitem == 0) return;
-    const int m = A.m, tm = 2 * m;
+    const int m = A.m, tm = 2 * m, rows = A.rows;   // rows <= Q64
     if (wv == 0 && t < ch.nbin) {
         L.runS[t] = -1;
         L.runE[t] = 0;
     }
+    {
+        int pm[QW];
+        double xl[QW];
+        cx<double> fl[QW];
+#pragma unroll
+        for (int j = 0; j < QW; ++j) {
+            const int q = wv + kWaves64 * j;
+            const int p = it.p0 + (q < it.n ? q : 0);
+            pm[j] = (q < it.n) ? A.perm[p] : -1;
+            xl[j] = (q < it.n) ? A.frac64[p] : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < QW; ++j) fl[j] = pm[j] >= 0 ? f[pm[j]] : cxmk(0.0, 0.0);
+#pragma unroll
+        for (int j = 0; j < QW; ++j) {
+            const int q = wv + kWaves64 * j;
+            if (q < rows) {
+                L.pv[q * kItemsPerWg + t] = fl[j];
+                L.pf[q * kItemsPerWg + t] = xl[j];
+            }
+        }
+    }
+    __syncthreads();
     if (it.n > 0) {
         double xf[Q64];
         cx<double> fv[Q64];
 #pragma unroll
         for (int q = 0; q < Q64; ++q) {
-            const int p = it.p0 + (q < it.n ? q : 0);
-            xf[q] = A.frac64[p];
-            fv[q] = (q < it.n) ? f[A.perm[p]] : cxmk(0.0, 0.0);
+            xf[q] = q < rows ? L.pf[q * kItemsPerWg + t] : 0.0;
+            fv[q] = q < rows ? L.pv[q * kItemsPerWg + t] : cxmk(0.0, 0.0);
         }
         const double inv_m = 1.0 / (double)m;
         for (int r = wv; r < tm; r += kWaves64) {
@@ -483,7 +514,7 @@ __device__ void spread64_slot(const SpreadArgs &A, const cx<double> *__restrict_
 template <int WIN>
 __global__ __launch_bounds__(kThreads64) void k_spread64(SpreadArgs A, const cx<double> *__restrict__ f)
 {
-    Spread64Lds L = spread64_lds(2 * A.m);
+    Spread64Lds L = spread64_lds(2 * A.m, A.rows);
     spread64_slot<WIN>(A, f, blockIdx.x, L);
 }
 
@@ -615,13 +646,18 @@ struct Interp64Lds {
     cx<double> *hw;   // the chunk's window: h at labels bin_lo - ip_off - m + 1 + i
 };
 
-__device__ __forceinline__ Interp64Lds interp64_lds(int tm)
+__device__ __forceinline__ Interp64Lds interp64_lds()
 {
     extern __shared__ __align__(16) char smem[];
     Interp64Lds L;
     L.hw = reinterpret_cast<cx<double> *>(smem);
-    (void)tm;
     return L;
+}
+
+// the window holds nbin + 2m - 1 < 64 + 2m values
+static size_t interp64_lds_bytes(int tm)
+{
+    return ((size_t)kItemsPerWg + tm) * sizeof(cx<double>);
 }
 
 // Four waves per chunk: lane t of every wave holds item t; wave w computes
@@ -665,14 +701,14 @@ __device__ void interp64_slot(const InterpArgs &A, cx<double> *__restrict__ y, i
 template <int WIN>
 __global__ __launch_bounds__(kThreads64) void k_interp64(InterpArgs A, cx<double> *__restrict__ y)
 {
-    Interp64Lds L = interp64_lds(2 * A.m);
+    Interp64Lds L = interp64_lds();
     interp64_slot<WIN>(A, y, blockIdx.x, L);
 }
 
 static void launch_spread64(const SpreadArgs &A, const void *f, hipStream_t s)
 {
     const cx<double> *in = reinterpret_cast<const cx<double> *>(f);
-    const size_t lds = lds64_bytes(2 * A.m);
+    const size_t lds = lds64_bytes(2 * A.m, A.rows);
     switch (A.window) {
     case NNFFT_WINDOW_BSPLINE:
         hipLaunchKernelGGL(k_spread64<NNFFT_WINDOW_BSPLINE>, dim3(A.ngrid), dim3(kThreads64), lds, s, A, in);
@@ -689,7 +725,7 @@ static void launch_spread64(const SpreadArgs &A, const void *f, hipStream_t s)
 static void launch_interp64(const InterpArgs &A, void *y, hipStream_t s)
 {
     cx<double> *out = reinterpret_cast<cx<double> *>(y);
-    const size_t lds = lds64_bytes(2 * A.m);
+    const size_t lds = interp64_lds_bytes(2 * A.m);
     switch (A.window) {
     case NNFFT_WINDOW_BSPLINE:
         hipLaunchKernelGGL(k_interp64<NNFFT_WINDOW_BSPLINE>, dim3(A.ngrid), dim3(kThreads64), lds, s, A, out);
@@ -1230,7 +1266,7 @@ __global__ __launch_bounds__(kThreads64) void k_spread64_batch(BatchTable T)
 {
     const int p = batch_plan(T, blockIdx.x);
     const SpreadArgs A = T.desc[p]->sp;
-    Spread64Lds L = spread64_lds(2 * A.m);
+    Spread64Lds L = spread64_lds(2 * A.m, A.rows);
     const int g = blockIdx.x - T.start[p];
     if (g >= A.ngrid) return;
     const cx<double> *in = static_cast<const cx<double> *>(T.in[p]);
@@ -1257,7 +1293,7 @@ __global__ __launch_bounds__(kThreads64) void k_interp64_batch(BatchTable T)
 {
     const int p = batch_plan(T, blockIdx.x);
     const InterpArgs A = T.desc[p]->ip;
-    Interp64Lds L = interp64_lds(2 * A.m);
+    Interp64Lds L = interp64_lds();
     const int g = blockIdx.x - T.start[p];
     if (g >= A.ngrid) return;
     cx<double> *out = static_cast<cx<double> *>(T.out[p]);
@@ -1388,6 +1424,7 @@ hipError_t launch_exec_batch(int n, const PlanDev *const *host, const PlanDev *c
         BatchTable Tsp{}, Tip{}, TA{}, TB{};
         int ssp = 0, sip = 0, sA = 0, sB = 0, thrA = 64, thrB = 64;
         int tm_sp = 2, tm_ip = 2;   // largest 2m of the group (FP32 variant, FP64 LDS size)
+        int rows_sp = 1;            // largest item size of the group (FP64 LDS size)
         size_t fft_bytes = 0;       // largest FFT LDS of the group
         int corr_deg = 0;
         for (int i = 0; i < nb; ++i) {
@@ -1413,6 +1450,7 @@ hipError_t launch_exec_batch(int n, const PlanDev *const *host, const PlanDev *c
                 thrB = std::max(thrB, P.fft.threadsB);
             }
             tm_sp = std::max(tm_sp, 2 * P.sp.m);
+            rows_sp = std::max(rows_sp, P.sp.rows);
             fft_bytes = std::max(fft_bytes, P.prec == NNFFT_FP32_COMP ? fft_lds_bytes<float>(P.fft)
                                                                       : fft_lds_bytes<double>(P.fft));
             tm_ip = std::max(tm_ip, 2 * P.ip.m);
@@ -1434,10 +1472,12 @@ hipError_t launch_exec_batch(int n, const PlanDev *const *host, const PlanDev *c
             if (sB > 0) hipLaunchKernelGGL((k_fftB_batch<float>), dim3(sB), dim3(thrB), fft_bytes, s, TB);
             launch_interp32_batch(corr_variant(corr_deg), sip, s, Tip);
         } else {
-            hipLaunchKernelGGL(k_spread64_batch, dim3(ssp), dim3(kThreads64), lds64_bytes(tm_sp), s, Tsp);
+            hipLaunchKernelGGL(k_spread64_batch, dim3(ssp), dim3(kThreads64), lds64_bytes(tm_sp, rows_sp), s,
+                               Tsp);
             hipLaunchKernelGGL((k_fftA_batch<double>), dim3(sA), dim3(thrA), fft_bytes, s, TA);
             if (sB > 0) hipLaunchKernelGGL((k_fftB_batch<double>), dim3(sB), dim3(thrB), fft_bytes, s, TB);
-            hipLaunchKernelGGL(k_interp64_batch, dim3(sip), dim3(kThreads64), lds64_bytes(tm_ip), s, Tip);
+            hipLaunchKernelGGL(k_interp64_batch, dim3(sip), dim3(kThreads64), interp64_lds_bytes(tm_ip), s,
+                               Tip);
         }
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
