@@ -460,24 +460,18 @@ __device__ void spread64_slot(const SpreadArgs &A, const cx<double> *__restrict_
     }
     __syncthreads();
     if (it.n > 0) {
-        double xf[Q64];
-        cx<double> fv[Q64];
-#pragma unroll
-        for (int q = 0; q < Q64; ++q) {
-            xf[q] = q < rows ? L.pf[q * kItemsPerWg + t] : 0.0;
-            fv[q] = q < rows ? L.pv[q * kItemsPerWg + t] : cxmk(0.0, 0.0);
-        }
+        // the points are read from LDS per tap (it.n <= rows), not held in
+        // registers: the kernel then fits twice the waves per SIMD
         const double inv_m = 1.0 / (double)m;
         for (int r = wv; r < tm; r += kWaves64) {
             double ar = 0.0, ai = 0.0;
-#pragma unroll
-            for (int q = 0; q < Q64; ++q) {
-                if (q < it.n) {
-                    const double w = tap64<WIN>(A.T64, r, m, xf[q], ((double)(r - m + 1) - xf[q]) * inv_m,
-                                                A.beta, A.inv_den);
-                    ar = fma(fv[q].re, w, ar);
-                    ai = fma(fv[q].im, w, ai);
-                }
+            for (int q = 0; q < it.n; ++q) {
+                const double xq = L.pf[q * kItemsPerWg + t];
+                const cx<double> fq = L.pv[q * kItemsPerWg + t];
+                const double w = tap64<WIN>(A.T64, r, m, xq, ((double)(r - m + 1) - xq) * inv_m, A.beta,
+                                            A.inv_den);
+                ar = fma(fq.re, w, ar);
+                ai = fma(fq.im, w, ai);
             }
             L.sitem[r * kItemsPerWg + t] = cxmk(ar, ai);
         }
