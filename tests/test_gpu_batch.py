@@ -100,3 +100,29 @@ def test_batch_errors_and_empty():
     finally:
         for p in plans:
             p.close()
+
+
+def test_batch_with_maximum_bandwidths():
+    # the longest FFTs the plans take (FP32 N2 = 2^24 and 3 * 2^21, FP64 2^22)
+    # batched with short ones: the batched FFT stages run every plan with the
+    # group's largest LDS size and thread count; results stay bitwise equal
+    g = W.rng(13)
+    specs = [(1 << 22, FP32, 6), (200, FP32, 6), (3 << 19, FP32, 8), (1 << 20, FP64, 6), (300, FP64, 12)]
+    plans, fs = [], []
+    try:
+        for N, prec, m in specs:
+            M = 1 << 13
+            v, x, f = W.uniform_nodes(g, M), W.uniform_nodes(g, M), W.complex_gaussian(g, M)
+            cdt = torch.complex64 if prec == FP32 else torch.complex128
+            plans.append(P.Plan(N, torch.tensor(v, device=DEV), torch.tensor(x, device=DEV), 2.0, 2.0, m, m, prec))
+            fs.append(torch.tensor(f, dtype=cdt, device=DEV))
+        _say(f"[gpu] batch with maximum bandwidths: {[(s[0], s[1]) for s in specs]}")
+        singles = [p(f).clone() for p, f in zip(plans, fs)]
+        ys = [torch.full_like(s, float("nan")) for s in singles]
+        P.nnfft_exec_batch([p.handle for p in plans], fs, ys)
+        torch.cuda.synchronize()
+        for i, (a, b) in enumerate(zip(singles, ys)):
+            assert torch.equal(a, b), f"plan {i} (N={specs[i][0]}) differs from its single exec"
+    finally:
+        for p in plans:
+            p.close()
