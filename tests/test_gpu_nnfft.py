@@ -254,3 +254,43 @@ def test_maximum_bandwidth(case):
     ex = oracle.direct(N, v, f, x[idx])
     e_paper = np.abs(y[idx] - ex).max() / np.abs(f).sum()
     assert e_paper <= 1.08 * info["bound_thm41"] + t * np.abs(ex).max() / np.abs(f).sum()
+
+
+def _degenerate_nodes(kind, N, m):
+    g = W.rng(77)
+    Pp = oracle.params(N, 2.0, 2.0, m, m)
+    if kind == "identical_v":      # every frequency node in one cell: ~2^17 points in one bin
+        return np.full(1 << 17, 0.123), W.uniform_nodes(g, 1 << 13)
+    if kind == "identical_x":      # every spatial node equal: all outputs equal
+        return W.uniform_nodes(g, 1 << 15), np.full(1 << 13, -0.37)
+    if kind == "on_grid":          # t_k = N1 N v_k / N* and u_j = N2 N* x_j / N1 at (or next to) integers
+        a = int(0.5 * Pp.N1 * N / Pp.N_star) - 1
+        b = int(0.5 * Pp.N2 * Pp.N_star / Pp.N1) - 1
+        v = g.integers(-a, a + 1, 20000) * Pp.N_star / (Pp.N1 * N)
+        x = g.integers(-b, b + 1, 20000) * Pp.N1 / (Pp.N2 * Pp.N_star)
+        return np.clip(v, -0.5, 0.5), np.clip(x, -0.5, 0.5)
+    # edges only: the two ends of [-1/2, 1/2], repeated
+    return np.tile([-0.5, 0.5], 3000), np.tile([0.5, -0.5, 0.0], 1000)
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+@pytest.mark.parametrize("kind", ["identical_v", "identical_x", "on_grid", "edges_only"])
+def test_degenerate_node_sets(kind, prec):
+    # node sets at the corners of the method: one bin holding every point
+    # (items split it, the chunk windows overflow the planes into merge
+    # lists), one output node, nodes on grid points, only the interval ends
+    N, m = 1000, 6
+    v, x = _degenerate_nodes(kind, N, m)
+    f = W.complex_gaussian(W.rng(78), len(v))
+    y, info = gpu_nnfft(N, v, x, f, 2.0, 2.0, m, m, prec)
+    yo = oracle.nnfft(N, v, f, x, 2.0, 2.0, m, m)
+    e = einf(y, yo)
+    t = tol(prec, N, 2.0, 2.0, m, m)
+    _say(f"    {kind}: E_inf vs oracle = {e:.3e} (tol {t:.2e})")
+    assert e <= t
+    if kind == "identical_x":
+        assert np.all(y == y[0])
+    if kind == "identical_v":
+        # closed form: y_j = (sum_k f_k) exp(-2 pi i N v x_j), within Theorem 4.1
+        ex = f.sum() * np.exp(-2j * np.pi * N * 0.123 * x)
+        assert np.abs(y - ex).max() / np.abs(f).sum() <= 1.08 * info["bound_thm41"] + t * np.abs(yo).max() / np.abs(f).sum()
