@@ -140,6 +140,47 @@ void clear_tuned_layouts()
 
 namespace {
 
+// Runs body(i, thread) for i in [0, n) on up to nthr threads: thread r takes
+// the i with i mod nthr == r, the calling thread r = 0 and the residues of
+// threads that could not be started.  An exception of any body is rethrown
+// here once every thread has finished.
+template <typename Body>
+void parallel_strided(int64_t n, int nthr, Body &&body)
+{
+    nthr = (int)std::max<int64_t>(1, std::min<int64_t>(nthr, n));
+    std::vector<std::thread> th;
+    std::vector<std::exception_ptr> xs((size_t)nthr);
+    try {
+        for (int r = 1; r < nthr; ++r)
+            th.emplace_back([&, r] {
+                try {
+                    for (int64_t i = r; i < n; i += nthr) body(i, r);
+                } catch (...) {
+                    xs[(size_t)r] = std::current_exception();
+                }
+            });
+    } catch (...) {   // fewer threads (none left or no memory for one): the rest runs here
+    }
+    const int started = (int)th.size() + 1;
+    try {
+        for (int64_t i = 0; i < n; ++i)
+            if (i % nthr == 0 || i % nthr >= started) body(i, 0);
+    } catch (...) {
+        xs[0] = std::current_exception();
+    }
+    for (auto &t : th) t.join();
+    for (auto &x : xs)
+        if (x) std::rethrow_exception(x);
+}
+
+// Both sides on two threads once each holds this many points
+constexpr int64_t kParallelSidePoints = (int64_t)1 << 15;
+// Node blocks of one side on up to kBlockThreads threads once the side holds
+// kParallelBlockPoints points (and the per-thread bin counts stay small)
+constexpr int64_t kParallelBlockPoints = (int64_t)1 << 18;
+constexpr int64_t kParallelBlockBins = (int64_t)1 << 21;
+constexpr int kBlockThreads = 4;
+
 // Builds the sorted records, items, chunks and schedule of one side.
 // t_k = scale * node_k (grid units); bin = floor(t_k) + off in [0, nbins).
 // Spreading side: `m` > 0 gives the chunk windows of 2m - 1 + nbin cells.
@@ -166,27 +207,28 @@ bool build_side(const std::vector<double> &nodes, double scale, int64_t off, int
     if (fp32) S.rec32.assign(M, PtRec{0, 0.f});
     else S.frac64.assign(M, 0.0);
     std::vector<int32_t> sbin(M);
-    std::vector<int64_t> cnt(nbins + 1);
     S.nblocks = (M + L.block - 1) / L.block;
-    {
-        // upper bounds of the item and chunk counts (no reallocation while filling)
-        const size_t items_max = (size_t)(M / std::max(1, L.Q) + S.nblocks * nbins + 64);
-        S.items.reserve(items_max);
-        const size_t chunks_max = items_max / kItemsPerWg + (size_t)S.nblocks * (nbins / kItemsPerWg + 2) + 64;
-        S.chunks.reserve(chunks_max);
-        S.chunk_block.reserve(chunks_max);
-        S.chunk_item0.reserve(chunks_max);
-    }
-    int64_t part = 0;
-    for (int64_t blk = 0; blk < S.nblocks; ++blk) {
+    // Each node block is sorted and cut into items and chunks on its own
+    // (writes to its own range of perm / records / sbin and its own lists),
+    // on up to kBlockThreads threads for large sides; the lists are then
+    // appended in block order, so the result does not depend on the threads.
+    struct BlockOut {
+        std::vector<Item> items;
+        std::vector<Chunk> chunks;
+        std::vector<int32_t> item0;   // first item of each chunk, within the block
+        bool ok = true;
+    };
+    std::vector<BlockOut> outs((size_t)S.nblocks);
+    auto run_block = [&](int64_t blk, std::vector<int64_t> &cnt) {
+        BlockOut &o = outs[(size_t)blk];
         const int64_t k0 = blk * L.block, k1 = std::min(M, k0 + L.block);
         std::fill(cnt.begin(), cnt.end(), 0);
         for (int64_t k = k0; k < k1; ++k) {
             double fr;
             const int64_t b = cell_of(k, &fr);
             if (b < 0 || b >= nbins) {
-                err = "internal: node record outside the grid";
-                return false;
+                o.ok = false;
+                return;
             }
             cnt[b + 1]++;
         }
@@ -207,7 +249,6 @@ bool build_side(const std::vector<double> &nodes, double scale, int64_t off, int
             }
         }
         // items: balanced split of each bin run into ceil(n / Q) pieces
-        const size_t it0 = S.items.size();
         for (int64_t i = k0; i < k1;) {
             int64_t j = i;
             while (j < k1 && sbin[j] == sbin[i]) ++j;
@@ -217,27 +258,59 @@ bool build_side(const std::vector<double> &nodes, double scale, int64_t off, int
             int64_t p = i;
             for (int64_t q = 0; q < nit; ++q) {
                 const int64_t len = base + (q < rem ? 1 : 0);
-                S.items.push_back(Item{sbin[i], (int32_t)p, (int32_t)len, 0});
+                o.items.push_back(Item{sbin[i], (int32_t)p, (int32_t)len, 0});
                 p += len;
             }
             i = j;
         }
         // chunks: consecutive items, at most IW items and IW bins
-        const size_t it1 = S.items.size();
-        for (size_t ci = it0; ci < it1;) {
-            const int32_t blo = S.items[ci].bin;
+        const size_t it1 = o.items.size();
+        for (size_t ci = 0; ci < it1;) {
+            const int32_t blo = o.items[ci].bin;
             size_t cj = ci;
-            while (cj < it1 && (int)(cj - ci) < kItemsPerWg && S.items[cj].bin - blo < kItemsPerWg) ++cj;
+            while (cj < it1 && (int)(cj - ci) < kItemsPerWg && o.items[cj].bin - blo < kItemsPerWg) ++cj;
             Chunk c{};
             c.nitem = (int32_t)(cj - ci);
             c.bin_lo = blo;
-            c.nbin = S.items[cj - 1].bin - blo + 1;
-            S.chunks.push_back(c);
-            S.chunk_block.push_back((int32_t)blk);
-            S.chunk_item0.push_back((int32_t)ci);
+            c.nbin = o.items[cj - 1].bin - blo + 1;
+            o.chunks.push_back(c);
+            o.item0.push_back((int32_t)ci);
             ci = cj;
         }
+    };
+    const int nthr = (M >= kParallelBlockPoints && nbins <= kParallelBlockBins) ? kBlockThreads : 1;
+    std::vector<std::vector<int64_t>> cnts((size_t)nthr);   // bin counts of each thread
+    parallel_strided(S.nblocks, nthr, [&](int64_t blk, int r) {
+        if (cnts[(size_t)r].empty()) cnts[(size_t)r].resize((size_t)nbins + 1);
+        run_block(blk, cnts[(size_t)r]);
+    });
+    {
+        size_t ni = 0, nc = 0;
+        for (const BlockOut &o : outs) {
+            if (!o.ok) {
+                err = "internal: node record outside the grid";
+                return false;
+            }
+            ni += o.items.size();
+            nc += o.chunks.size();
+        }
+        S.items.reserve(ni);
+        S.chunks.reserve(nc);
+        S.chunk_block.reserve(nc);
+        S.chunk_item0.reserve(nc);
+        for (int64_t blk = 0; blk < S.nblocks; ++blk) {
+            BlockOut &o = outs[(size_t)blk];
+            const int32_t base = (int32_t)S.items.size();
+            S.items.insert(S.items.end(), o.items.begin(), o.items.end());
+            for (size_t c = 0; c < o.chunks.size(); ++c) {
+                S.chunks.push_back(o.chunks[c]);
+                S.chunk_block.push_back((int32_t)blk);
+                S.chunk_item0.push_back(base + o.item0[c]);
+            }
+            std::vector<Item>().swap(o.items);
+        }
     }
+    int64_t part = 0;
     // spreading windows: chunk c covers cells [bin_lo - m + 1, bin_lo + nbin + m).
     // Windows are coloured greedily in order of their first cell (interval
     // colouring: at most as many colours as windows overlap at one cell);
@@ -373,8 +446,6 @@ bool build_both_sides(BuildA &&a, BuildB &&b, bool parallel, std::string &err)
     return true;
 }
 
-// Both sides on two threads once each holds this many points
-constexpr int64_t kParallelSidePoints = (int64_t)1 << 15;
 
 // largest-square-ish factorization N2 = n1 * n2 with both parts <= limit
 bool fft_factor(int64_t N2, int64_t limit, int64_t &n1, int64_t &n2)

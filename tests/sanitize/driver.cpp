@@ -1,6 +1,7 @@
 // Plans every window family and precision for a spread of bandwidths, kernel
 // sizes and node sets (uniform, clustered, edge nodes, single nodes) on the
-// host only, through the dry-run entry point and the NFFT planner.  Built
+// host only, through the dry-run entry point and the NFFT planner (2^18-point
+// sides too, whose node blocks are sorted on several threads).  Built
 // with sanitizers, it checks the planner's memory accesses and, with planner
 // threads of its own on top of the two-sided builds, its threading.
 #include <algorithm>
@@ -52,6 +53,19 @@ static int run(unsigned seed, bool small)
                             if (nnfft::nfft_plan_host(H, 2 * N, M, 2.0, m, (nnfft_precision)prec, x) != NNFFT_OK)
                                 ++refused;
                         }
+    // one side large enough for its node blocks to be sorted on several threads
+    for (int prec : {0, 1}) {
+        const int64_t M = (int64_t)1 << 18;
+        std::vector<double> v(M), x(M);
+        for (int64_t k = 0; k < M; ++k) {
+            v[k] = U(g);
+            x[k] = U(g);
+        }
+        nnfft_info_t info;
+        if (nnfft_plan_window_dry_run(4096, M, M, 2.0, 2.0, 6, 6, (nnfft_precision)prec, NNFFT_WINDOW_SINH, v.data(),
+                                      x.data(), &info) != NNFFT_OK)
+            ++refused;
+    }
     return refused;
 }
 
