@@ -2,6 +2,7 @@
 // transform plan (Algorithm 6.1) and the C ABI of include/nnfft.h.
 #include <algorithm>
 #include <array>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -140,14 +141,43 @@ void clear_tuned_layouts()
 
 namespace {
 
-// Runs body(i, thread) for i in [0, n) on up to nthr threads: thread r takes
-// the i with i mod nthr == r, the calling thread r = 0 and the residues of
-// threads that could not be started.  An exception of any body is rethrown
-// here once every thread has finished.
+// Helper threads that plans may start, shared by every planning thread of the
+// process: a plan takes what is free and runs the rest itself, so concurrent
+// planners (the request server's) do not multiply the host's thread count.
+constexpr int kHelperBudget = 8;
+std::atomic<int> g_helpers_free{kHelperBudget};
+
+struct HelperGrant {
+    int n = 0;
+    explicit HelperGrant(int want)
+    {
+        int cur = g_helpers_free.load(std::memory_order_relaxed);
+        while (want > 0 && cur > 0) {
+            const int got = std::min(want, cur);
+            if (g_helpers_free.compare_exchange_weak(cur, cur - got)) {
+                n = got;
+                break;
+            }
+        }
+    }
+    ~HelperGrant()
+    {
+        if (n > 0) g_helpers_free.fetch_add(n);
+    }
+    HelperGrant(const HelperGrant &) = delete;
+    HelperGrant &operator=(const HelperGrant &) = delete;
+};
+
+// Runs body(i, thread) for i in [0, n) on up to nthr threads (as many helpers
+// as the budget grants): thread r takes the i with i mod nthr == r, the
+// calling thread r = 0 and the residues of threads that could not be started.
+// An exception of any body is rethrown here once every thread has finished.
 template <typename Body>
 void parallel_strided(int64_t n, int nthr, Body &&body)
 {
     nthr = (int)std::max<int64_t>(1, std::min<int64_t>(nthr, n));
+    const HelperGrant grant(nthr - 1);
+    nthr = grant.n + 1;
     std::vector<std::thread> th;
     std::vector<std::exception_ptr> xs((size_t)nthr);
     try {
@@ -405,16 +435,18 @@ bool build_side(const std::vector<double> &nodes, double scale, int64_t off, int
 }
 
 // Runs the two side builds, the second one on a thread of its own when
-// `parallel` is set (they share no state); the first failure's message goes
-// to err and an exception of either build is rethrown here.
+// `parallel` is set and the helper budget grants one (they share no state);
+// the first failure's message goes to err and an exception of either build
+// is rethrown here.
 template <typename BuildA, typename BuildB>
 bool build_both_sides(BuildA &&a, BuildB &&b, bool parallel, std::string &err)
 {
     std::string ea, eb;
     bool okb = false;
     std::exception_ptr xb;
+    const HelperGrant grant(parallel ? 1 : 0);
     std::thread tb;
-    if (parallel) {
+    if (grant.n > 0) {
         try {
             tb = std::thread([&] {
                 try {
