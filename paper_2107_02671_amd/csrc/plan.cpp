@@ -118,6 +118,55 @@ Layout choose_layout(int64_t M, bool fp32, bool spreading)
     return rule_layout(M, fp32, spreading);
 }
 
+// choose_layout for a given node set (grid coordinate t = scale * node): where
+// a typical node's bin holds more than eight of the rule's items within its
+// block, the item size is raised to the smallest power of two >= load / 1.5
+// (up to 32 on the FP32 path, 8 on the FP64 path), load = block x sum_b p_b^2
+// estimated from strided samples of up to four blocks ((sum_b c_b^2 - S) /
+// (S (S - 1)) over S sampled cells).  One thread sums the items of a bin, so
+// dense cells cut into many short items serialize their chunk.  A tuned entry
+// is used as it is.
+Layout choose_layout_nodes(const std::vector<double> &nodes, double scale, bool fp32, bool spreading)
+{
+    const int64_t M = (int64_t)nodes.size();
+    Layout L;
+    if (get_tuned_layout(fp32, M, L)) return sanitize_layout(L, M, fp32);
+    L = rule_layout(M, fp32, spreading);
+    const int qmax = fp32 ? 32 : 8;
+    const int64_t nblk = (M + L.block - 1) / L.block;
+    const int64_t nsb = std::min<int64_t>(nblk, 4);
+    double load = 0.0;
+    int64_t used = 0;
+    std::vector<int64_t> cell;
+    for (int64_t sb = 0; sb < nsb && L.Q < qmax; ++sb) {
+        const int64_t blk = sb * nblk / nsb;
+        const int64_t k0 = blk * L.block, len = std::min(M, k0 + L.block) - k0;
+        const int64_t S = std::min<int64_t>(len, 4096);
+        if (S < 2) continue;
+        cell.resize((size_t)S);
+        for (int64_t i = 0; i < S; ++i) cell[(size_t)i] = (int64_t)std::floor(scale * nodes[(size_t)(k0 + i * len / S)]);
+        std::sort(cell.begin(), cell.end());
+        double sumsq = 0.0;
+        for (int64_t i = 0; i < S;) {
+            int64_t j = i;
+            while (j < S && cell[(size_t)j] == cell[(size_t)i]) ++j;
+            sumsq += (double)(j - i) * (double)(j - i);
+            i = j;
+        }
+        load += (double)len * (sumsq - (double)S) / ((double)S * (double)(S - 1));
+        ++used;
+    }
+    if (used > 0) {
+        load /= (double)used;
+        // only where the rule's items would cut a typical bin into more than
+        // eight pieces (the rule's item size already balances the launch
+        // width against that loop for uniform nodes, at up to four pieces)
+        if (load > 8.0 * L.Q)
+            while (L.Q < qmax && L.Q < load / 1.5) L.Q *= 2;
+    }
+    return L;
+}
+
 void set_tuned_layout(bool fp32, int64_t M, const Layout &L)
 {
     std::lock_guard<std::mutex> g(g_tune_mu);
@@ -860,20 +909,16 @@ nnfft_status plan_host(HostPlan &H, int64_t N, int64_t M1, int64_t M2, double si
     }
 
     // node layouts ----------------------------------------------------------
-    H.lay1 = lay1 ? sanitize_layout(*lay1, M1, fp32) : choose_layout(M1, fp32);
-    H.lay2 = lay2 ? sanitize_layout(*lay2, M2, fp32) : choose_layout(M2, fp32, false);
+    const double scale1 = (double)P.N1 * (double)N / (double)P.N_star;   // t_k = scale1 v_k
+    const double scale2 = (double)P.N2 * (double)P.N_star / (double)P.N1; // u_j = scale2 x_j
+    H.lay1 = lay1 ? sanitize_layout(*lay1, M1, fp32) : choose_layout_nodes(v, scale1, fp32, true);
+    H.lay2 = lay2 ? sanitize_layout(*lay2, M2, fp32) : choose_layout_nodes(x, scale2, fp32, false);
     std::string err;
     // spreading: t_k = N1 v*_k = N1 N v_k / N*, bin = floor(t_k) + G1/2
     // interpolation: u_j = N2 N* x_j / N1, bin = floor(u_j) + N2/2
     if (!build_both_sides(
-            [&](std::string &e) {
-                return build_side(v, (double)P.N1 * (double)N / (double)P.N_star, P.G1 / 2, P.G1, H.lay1, fp32,
-                                  m1, H.sp, e);
-            },
-            [&](std::string &e) {
-                return build_side(x, (double)P.N2 * (double)P.N_star / (double)P.N1, P.N2 / 2, P.N2 + 1, H.lay2,
-                                  fp32, 0, H.ip, e);
-            },
+            [&](std::string &e) { return build_side(v, scale1, P.G1 / 2, P.G1, H.lay1, fp32, m1, H.sp, e); },
+            [&](std::string &e) { return build_side(x, scale2, P.N2 / 2, P.N2 + 1, H.lay2, fp32, 0, H.ip, e); },
             std::min(M1, M2) >= kParallelSidePoints, err))
         return fail(NNFFT_ERR_ARG, err);
     // the sorted copies are only needed by the FP64 kernels
@@ -971,8 +1016,8 @@ nnfft_status nfft_plan_host(HostPlan &H, int64_t N, int64_t M, double sigma, int
         H.tw32.assign(H.tw64.begin(), H.tw64.end());
         H.tw64.clear();
     }
-    H.lay1 = choose_layout(M, fp32);
-    H.lay2 = choose_layout(M, fp32, false);
+    H.lay1 = choose_layout_nodes(x, (double)n, fp32, true);
+    H.lay2 = choose_layout_nodes(x, (double)n, fp32, false);
     std::string err;
     // spreading (adjoint): t_j = n x_j in the linear grid; interpolation (forward): u_j = n x_j
     if (!build_both_sides(

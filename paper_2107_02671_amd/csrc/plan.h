@@ -27,6 +27,7 @@ struct Layout {
 // blocks there above 2^20 points; interpolation sides keep 2^17).
 Layout choose_layout(int64_t M, bool fp32, bool spreading = true);
 Layout rule_layout(int64_t M, bool fp32, bool spreading = true);
+Layout choose_layout_nodes(const std::vector<double> &nodes, double scale, bool fp32, bool spreading);
 void set_tuned_layout(bool fp32, int64_t M, const Layout &L);
 bool get_tuned_layout(bool fp32, int64_t M, Layout &L);
 void clear_tuned_layouts();
