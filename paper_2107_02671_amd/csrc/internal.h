@@ -55,6 +55,8 @@ struct SpreadArgs {
     const PtRec *rec32;       // FP32 path records
     const int32_t *perm;      // FP64 path: caller's index
     const double *frac64;     // FP64 path: offset in the cell
+    const double *wts;        // null, or [M] weights the coefficients are multiplied
+                              // by as they are loaded (set per exec)
     const float *C;           // FP32 path: [2m][kDeg + 1] tap coefficients
     const double *T64;        // FP64 path, B-spline windows: [2m][2m] exact tap series
     void *partial;            // chunk windows: float4 (hi, lo) or double2

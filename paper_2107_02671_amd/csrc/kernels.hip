@@ -178,6 +178,24 @@ __device__ __forceinline__ double inv_phi1_fixed(const double *__restrict__ c, d
     return fma(t, b1, c[0] - b2);
 }
 
+// Coefficient k of the spreading input, times w[k] when weights are given
+// (the fast sinc transform's quadrature weights, step 2 of its Algorithm 6.1,
+// folded into the load: the same products in the same precision as a
+// separate scaling pass, in FP64 and rounded once).
+__device__ __forceinline__ cx<float> coef32(const cx<float> *__restrict__ f, const double *__restrict__ w, int k)
+{
+    const cx<float> v = f[k];
+    if (w == nullptr) return v;
+    const double s = w[k];
+    return cxmk((float)((double)v.re * s), (float)((double)v.im * s));
+}
+
+__device__ __forceinline__ cx<double> coef64(const cx<double> *__restrict__ f, const double *__restrict__ w, int k)
+{
+    const cx<double> v = f[k];
+    return w == nullptr ? v : scal(v, w[k]);
+}
+
 // ===========================================================================
 // Spreading, FP32 path
 // ===========================================================================
@@ -268,7 +286,7 @@ __device__ void spread32_slot(const SpreadArgs &A, const cx<float> *__restrict__
     const Item it = A.items[g * kItemsPerWg + t];
 #pragma unroll
     for (int j = 0; j < kRowsPerWave; ++j)
-        fv[j] = (j < rpw && row0 + j < it.n) ? f[r[j].perm] : cxmk(0.f, 0.f);
+        fv[j] = (j < rpw && row0 + j < it.n) ? coef32(f, A.wts, r[j].perm) : cxmk(0.f, 0.f);
     const Chunk ch = A.chunks[g];
     if (ch.nitem == 0) return;
     const int m = A.m, tm = 2 * m;
@@ -288,7 +306,7 @@ __device__ void spread32_slot(const SpreadArgs &A, const cx<float> *__restrict__
                 for (int j = 0; j < kRowsPerWave; ++j) r[j] = rec[wave_row(row0, j0 + j, rpw, rows) * kItemsPerWg];
 #pragma unroll
                 for (int j = 0; j < kRowsPerWave; ++j)
-                    fv[j] = (j0 + j < nq) ? f[r[j].perm] : cxmk(0.f, 0.f);
+                    fv[j] = (j0 + j < nq) ? coef32(f, A.wts, r[j].perm) : cxmk(0.f, 0.f);
             }
 #pragma unroll
             for (int j = 0; j < kRowsPerWave; ++j)
@@ -448,7 +466,7 @@ __device__ void spread64_slot(const SpreadArgs &A, const cx<double> *__restrict_
             xl[j] = (q < it.n) ? A.frac64[p] : 0.0;
         }
 #pragma unroll
-        for (int j = 0; j < QW; ++j) fl[j] = pm[j] >= 0 ? f[pm[j]] : cxmk(0.0, 0.0);
+        for (int j = 0; j < QW; ++j) fl[j] = pm[j] >= 0 ? coef64(f, A.wts, pm[j]) : cxmk(0.0, 0.0);
 #pragma unroll
         for (int j = 0; j < QW; ++j) {
             const int q = wv + kWaves64 * j;

@@ -1630,10 +1630,14 @@ nnfft_status sinc_exec(sinc_plan_t p, const void *c, void *h, void *stream)
     nnfft_status st = p->step1_nfft ? nfft_exec(p->p1, c, p->g, stream)        // step 1
                                     : nnfft_exec(p->p1, c, p->g, stream);
     if (st != NNFFT_OK) return st;
-    const hipError_t e = launch_scale_by_weights(p->prec, p->w, p->g, p->g, p->n_nodes, s);   // step 2
-    if (e != hipSuccess) return fail(NNFFT_ERR_DEVICE, hipGetErrorString(e));
-    return p->step3_nfft ? nfft_adjoint(p->p2, p->g, h, stream)                 // step 3
-                         : nnfft_exec(p->p2, p->g, h, stream);
+    // step 2 (alpha_j = w_j g_j) is folded into the coefficient loads of
+    // step 3's spreading
+    PlanDev D = p->p2->desc;
+    D.sp.wts = p->w;
+    const hipError_t e = p->step3_nfft ? launch_nfft(D, true, p->g, h, s)       // step 3
+                                       : launch_exec(D, p->g, h, s, nullptr);
+    if (e != hipSuccess) return fail(NNFFT_ERR_DEVICE, std::string("launch: ") + hipGetErrorString(e));
+    return NNFFT_OK;
 }
 
 nnfft_status nnfft_quadrature(sinc_quad quad, int64_t n_quad, double *z, double *w)
