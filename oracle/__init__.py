@@ -297,24 +297,50 @@ def num_threads() -> int:
 # Closed-form error bounds (formulas transcribed from the theorems)
 # --------------------------------------------------------------------------
 
+# Theorem 4.1 slip: the proof bounds I_1(x) from below by (2/5) x^(-1/2) e^x
+# for x >= 4 pi / sqrt(5); the true constant there is sqrt(x0) e^(-x0) I_1(x0)
+# = 0.3705 (x0 = 4 pi / sqrt(5)), so the factor of the second term of (4.2)
+# holds only after multiplying it by 0.4 / 0.3705 = 1.08.  The first term is
+# untouched (its bound (4.3) does not use that inequality).
+THM41_SLIP = 1.08
+
+
+def thm41_terms(N1, m1, m2, sigma1, sigma2):
+    """The three factors of (4.2), Theorem 4.1, as Theorem 3.5 composes them:
+      E1 = (24 m1^(3/2) + 10) e^(-2 pi m1 sqrt(1 - 1/sigma1))   bound (4.3) on E_sigma1(phi_1)
+      F  = (2 N1 + 4 m1) / sqrt(2 pi m1) e^(2 pi m1 (1 - sqrt(1 - 1/sigma1) - 1/(2 sigma1)))
+                                                              bound on a / phi_hat_1(N/2)
+      E2 = (24 m2^(3/2) + 10) e^(-2 pi m2 sqrt(1 - 1/sigma2))   bound (4.3) on E_sigma2(phi_2)
+    with (4.2) = E1 + F E2 (2 N1 a = 2 N1 + 4 m1 by (2.6))."""
+    E1 = (24 * m1 ** 1.5 + 10) * math.exp(-2 * math.pi * m1 * math.sqrt(1 - 1 / sigma1))
+    F = ((2 * N1 + 4 * m1) / math.sqrt(2 * m1 * math.pi)
+         * math.exp(2 * math.pi * m1 * (1 - math.sqrt(1 - 1 / sigma1) - 1 / (2 * sigma1))))
+    E2 = (24 * m2 ** 1.5 + 10) * math.exp(-2 * math.pi * m2 * math.sqrt(1 - 1 / sigma2))
+    return E1, F, E2
+
+
 def bound_thm41(N1, m1, m2, sigma1, sigma2) -> float:
-    """E(phi_sinh) of (4.2), Theorem 4.1: bound on E_paper for sinh windows."""
-    t1 = (24 * m1 ** 1.5 + 10) * math.exp(-2 * math.pi * m1 * math.sqrt(1 - 1 / sigma1))
-    t2 = ((24 * m2 ** 1.5 + 10) * (2 * N1 + 4 * m1) / math.sqrt(2 * m1 * math.pi)
-          * math.exp(2 * math.pi * m1 * (1 - math.sqrt(1 - 1 / sigma1) - 1 / (2 * sigma1)))
-          * math.exp(-2 * math.pi * m2 * math.sqrt(1 - 1 / sigma2)))
-    return t1 + t2
+    """E(phi_sinh) of (4.2), Theorem 4.1, as printed: bound on E_paper for sinh windows."""
+    E1, F, E2 = thm41_terms(N1, m1, m2, sigma1, sigma2)
+    return E1 + F * E2
 
 
-def bound_thm34(kind, m, sigma, beta) -> float:
-    """(3.9), Theorem 3.4: upper bound of the general error constant E_sigma(phi)
-    of a window of family `kind`, from decay constants c1, c2, mu of its
-    transform that hold for every v:
-      B-spline   |omega_hat(v)| <= (m / (pi |v|))^(2m) / (m B_2m(0)), mu = 2m;
-      algebraic  |omega_hat(v)| <= C (pi |v|)^(-beta) (|J_beta| <= 1), mu = beta,
-                 C = pi (2 beta)! / (4^beta beta!);
-    c1 is that envelope at |v| = m (1 - 1/(2 sigma)), where the interval of
-    the theorem starts."""
+def bound_thm41_gate(N1, m1, m2, sigma1, sigma2) -> float:
+    """(4.2) with the slip of its proof corrected: E1 + 1.08 F E2 (THM41_SLIP)."""
+    E1, F, E2 = thm41_terms(N1, m1, m2, sigma1, sigma2)
+    return E1 + THM41_SLIP * F * E2
+
+
+def thm34_constants(kind, m, sigma, beta):
+    """Decay constants (c1, c2, mu) of Theorem 3.4's condition for the windows
+    of Example 2.1, holding for every v:
+      B-spline   |omega_hat(v)| <= (m / (pi |v|))^(2m) / (m B_2m(0)), mu = 2m
+                 (|sin| <= 1 in the power of sinc);
+      algebraic  |omega_hat(v)| <= C (pi |v|)^(-beta), mu = beta,
+                 C = pi (2 beta)! / (4^beta beta!) (|J_beta| <= 1);
+    c2 is the coefficient of |v|^(-mu) and c1 the envelope at |v| =
+    m (1 - 1/(2 sigma)), where the interval of the theorem starts (the envelope
+    decreases, so it bounds |omega_hat| on the whole interval)."""
     lo = m * (1.0 - 1.0 / (2.0 * sigma))
     if kind == WIN_BSPLINE:
         b0 = float(bspline_cardinal(2 * m, m))
@@ -327,6 +353,13 @@ def bound_thm34(kind, m, sigma, beta) -> float:
     else:
         raise ValueError("Theorem 3.4 constants are given for the B-spline and algebraic windows")
     c1 = c2 * lo ** (-mu)
+    return c1, c2, mu
+
+
+def bound_thm34(kind, m, sigma, beta) -> float:
+    """(3.9), Theorem 3.4: upper bound of the general error constant E_sigma(phi)
+    of a window of family `kind` from the constants of thm34_constants."""
+    c1, c2, mu = thm34_constants(kind, m, sigma, beta)
     inner = 2.0 * c1 + 2.0 * c2 / ((mu - 1.0) * m ** mu) * (1.0 - 1.0 / (2.0 * sigma)) ** (1.0 - mu)
     return float(inner / window_hat(kind, m / (2.0 * sigma), m, beta))
 

@@ -125,13 +125,11 @@ Layout choose_layout(int64_t M, bool fp32, bool spreading)
 // estimated from strided samples of up to four blocks ((sum_b c_b^2 - S) /
 // (S (S - 1)) over S sampled cells).  One thread sums the items of a bin, so
 // dense cells cut into many short items serialize their chunk.  A tuned entry
-// is used as it is.
+// (timed on uniform nodes) takes the place of the rule and gets the same raise.
 Layout choose_layout_nodes(const std::vector<double> &nodes, double scale, bool fp32, bool spreading)
 {
     const int64_t M = (int64_t)nodes.size();
-    Layout L;
-    if (get_tuned_layout(fp32, M, L)) return sanitize_layout(L, M, fp32);
-    L = rule_layout(M, fp32, spreading);
+    Layout L = choose_layout(M, fp32, spreading);
     const int qmax = fp32 ? 32 : 8;
     const int64_t nblk = (M + L.block - 1) / L.block;
     const int64_t nsb = std::min<int64_t>(nblk, 4);

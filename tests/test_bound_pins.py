@@ -1,0 +1,285 @@
+"""Pins of the oracle's error-bound helpers (Theorems 3.4, 3.5, 4.1 and 6.2).
+
+The helpers gate other pins (the oracle NNFFT within Theorem 4.1, the fast
+sinc transform within Theorem 6.2, the other window families within
+Theorem 3.5), so each factor is checked here against quantities computed
+another way:
+
+* the error constant E_sigma(phi) of (3.7) written out as the sum
+  max_{|u| <= 1/(2 sigma)} sum_{r != 0} |omega_hat(m (u + r))| / omega_hat(m u)
+  (which bounds the C(T) norm of (3.7) from above, and is what the proof of
+  Theorem 3.4 bounds), truncated at |r| <= R, with the window transforms taken
+  from scipy's Bessel functions (not from the oracle's C code);
+* a / phi_hat_1(N/2) from the same transforms;
+* hand-worked values of Theorem 3.4's constants for m = 2;
+* Theorem 6.2's composition on a constructed worst case.
+A slip that inflates a bound (a dropped sign in an exponent, a wrong factor,
+swapped sigma or m) breaks the two-sided checks.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.interpolate
+import scipy.special as sp
+
+import oracle
+
+SIGMAS = (1.25, 1.5, 2.0)
+
+
+# --------------------------------------------------------------------------
+# window transforms from scipy (Example 2.1)
+# --------------------------------------------------------------------------
+
+def what_sinh(v, beta):
+    """(2.1) with I_1 through scipy's exponentially scaled ive and J_1."""
+    v = np.atleast_1d(np.asarray(v, dtype=np.float64))
+    y = beta * beta - 4.0 * np.pi ** 2 * v * v
+    z = np.sqrt(np.abs(y))
+    zs = np.where(z > 0, z, 1.0)
+    # log(pi beta / sinh beta)
+    lpre = math.log(math.pi * beta) - (beta + math.log1p(-math.exp(-2.0 * beta)) - math.log(2.0))
+    hi = np.exp(lpre + np.where(y > 0, z, 0.0)) * sp.ive(1, zs) / zs
+    lo = math.exp(lpre) * sp.j1(zs) / zs
+    mid = math.exp(lpre) * 0.5
+    return np.where(y > 0, hi, np.where(y < 0, lo, mid))
+
+
+def what_bspline(v, m):
+    """sinc(pi v / m)^(2m) / (m B_2m(0)); B_2m(0) = M_2m(m) from scipy's B-spline basis."""
+    knots = np.arange(2 * m + 1, dtype=np.float64)
+    b0 = float(scipy.interpolate.BSpline.basis_element(knots)(float(m)))
+    v = np.atleast_1d(np.asarray(v, dtype=np.float64))
+    return np.sinc(v / m) ** (2 * m) / (m * b0)
+
+
+def what_alg(v, beta):
+    """pi (2 beta)! / (4^beta beta!) (pi v)^(-beta) J_beta(2 pi v), scipy's jv."""
+    v = np.atleast_1d(np.asarray(v, dtype=np.float64))
+    lc = math.log(math.pi) + math.lgamma(2 * beta + 1) - beta * math.log(4.0) - math.lgamma(beta + 1)
+    a = np.pi * np.abs(v)
+    asafe = np.where(a > 0, a, 1.0)
+    return np.where(a > 0, np.exp(lc) * sp.jv(beta, 2.0 * asafe) / asafe ** beta,
+                    math.exp(lc - math.lgamma(beta + 1)))
+
+
+def error_constant(what, m, sigma, R=3000, nu=61):
+    """Truncated sum form of E_sigma(phi) (3.7): a lower estimate of the sum,
+    an upper bound of the C(T) norm the theorem bounds."""
+    u = np.linspace(-1.0 / (2.0 * sigma), 1.0 / (2.0 * sigma), nu)
+    r = np.concatenate([np.arange(-R, 0), np.arange(1, R + 1)]).astype(np.float64)
+    best = 0.0
+    for uu in u:
+        best = max(best, float(np.abs(what(m * (uu + r))).sum() / what(m * uu)[0]))
+    return best
+
+
+# --------------------------------------------------------------------------
+# Theorem 4.1
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("sigma", SIGMAS)
+@pytest.mark.parametrize("m", [2, 4, 6, 8, 12])
+def test_thm41_window_term_bounds_the_error_constant(sigma, m):
+    # (4.3): E1 >= E_sigma(phi_sinh), and not by more than the bound's known
+    # looseness (2.3x .. 45x over sigma in [5/4, 2], m <= 12)
+    beta = 2 * math.pi * m * (1 - 1 / (2 * sigma))
+    exact = error_constant(lambda v: what_sinh(v, beta), m, sigma)
+    E1, _, E2 = oracle.thm41_terms(1000, m, m, sigma, sigma)
+    assert E1 == E2
+    assert exact <= E1 <= 60.0 * exact, (exact, E1)
+
+
+@pytest.mark.parametrize("N", [8, 64, 4096])
+@pytest.mark.parametrize("sigma", SIGMAS)
+@pytest.mark.parametrize("m", [2, 4, 6, 8, 12])
+def test_thm41_factor_bounds_a_over_phi_hat(N, sigma, m):
+    # F bounds a / phi_hat_1(N/2) = G1 / (m1 omega_hat_1(m1 / (2 sigma1))) once
+    # the slip of its proof is corrected (x 1.08), and exceeds it by at most
+    # 1.6 (the (5/3) 2^(1/4) step at sigma = 5/4); without the correction it
+    # falls below at sigma = 2 (F / exact = 0.962 at m = 2)
+    try:
+        P = oracle.params(N, sigma, sigma, m, m)
+    except ValueError:
+        pytest.skip("2 m >= N1")
+    exact = P.G1 / (m * what_sinh(m / (2 * P.sigma1_eff), P.beta1)[0])
+    _, F, _ = oracle.thm41_terms(P.N1, m, m, P.sigma1_eff, P.sigma2_eff)
+    assert exact <= oracle.THM41_SLIP * F, (exact, F)
+    assert F <= 1.6 * exact, (exact, F)
+
+
+@pytest.mark.parametrize("N,sigma,m", [(8, 1.5, 2), (64, 1.25, 6), (1200, 2.0, 4), (4096, 1.5, 12), (40, 1.25, 3)])
+def test_thm41_factor_through_the_proof_chain(N, sigma, m):
+    # The proof of Theorem 4.1 reaches F from the exact a / phi_hat_1(N/2) by
+    # three inequalities; as equalities they read
+    #   F / exact = [2 / R(sigma1)] [c(x) / (2/5)] [e^beta1 / (2 sinh beta1)],
+    # R(s) = (5/2) (1 - 1/(2s))^-1 (1 - 1/s)^(3/4) (the step "<= (5/3) sqrt 2 < 2"),
+    # c(x) = sqrt(x) e^-x I_1(x) at x = 2 pi m1 sqrt(1 - 1/sigma1) (the I_1 bound)
+    # and sinh beta1 < e^beta1 / 2.  This fixes F exactly (its N1, m1 and sigma1
+    # dependence), not only within the window of the test above.
+    P = oracle.params(N, sigma, 2.0, m, m + 3)   # F depends on the first window only
+    s1 = P.sigma1_eff
+    exact = P.G1 / (m * what_sinh(m / (2 * s1), P.beta1)[0])
+    _, F, _ = oracle.thm41_terms(P.N1, m, m + 3, s1, P.sigma2_eff)
+    x = 2 * math.pi * m * math.sqrt(1 - 1 / s1)
+    cx = math.sqrt(x) * sp.ive(1, x)
+    R = 2.5 / (1 - 1 / (2 * s1)) * (1 - 1 / s1) ** 0.75
+    sh = 1.0 / (1.0 - math.exp(-2.0 * P.beta1))      # e^beta / (2 sinh beta)
+    assert F / exact == pytest.approx((2.0 / R) * (cx / 0.4) * sh, rel=1e-10)
+
+
+def test_thm41_slip_is_needed():
+    # the proof's constant 2/5 for I_1(x) >= c x^(-1/2) e^x (x >= 4 pi / sqrt 5)
+    # is 0.3705 in fact, and F alone undercuts the exact ratio at sigma = 2
+    x0 = 4 * math.pi / math.sqrt(5)
+    c = math.sqrt(x0) * math.exp(-x0) * sp.iv(1, x0)
+    assert c == pytest.approx(0.3705, abs=5e-5)
+    assert oracle.THM41_SLIP >= 0.4 / c
+    P = oracle.params(64, 2.0, 2.0, 2, 2)
+    exact = P.G1 / (2 * what_sinh(2 / (2 * P.sigma1_eff), P.beta1)[0])
+    _, F, _ = oracle.thm41_terms(P.N1, 2, 2, P.sigma1_eff, P.sigma2_eff)
+    assert F < exact < oracle.THM41_SLIP * F
+
+
+@pytest.mark.parametrize("N,s1,s2,m1,m2", [(64, 2.0, 1.5, 4, 8), (1200, 1.25, 2.0, 6, 3), (8, 1.5, 1.25, 2, 5)])
+def test_thm41_composition_and_argument_roles(N, s1, s2, m1, m2):
+    # (4.2) = E1 + F E2, each factor against its exact counterpart with the
+    # arguments in their roles (sigma1 / m1 for the first window and the
+    # factor, sigma2 / m2 for the second window)
+    P = oracle.params(N, s1, s2, m1, m2)
+    E1, F, E2 = oracle.thm41_terms(P.N1, m1, m2, P.sigma1_eff, P.sigma2_eff)
+    b = oracle.bound_thm41(P.N1, m1, m2, P.sigma1_eff, P.sigma2_eff)
+    g = oracle.bound_thm41_gate(P.N1, m1, m2, P.sigma1_eff, P.sigma2_eff)
+    assert b == pytest.approx(E1 + F * E2, rel=1e-14)
+    assert g == pytest.approx(E1 + oracle.THM41_SLIP * F * E2, rel=1e-14)
+    e1 = error_constant(lambda v: what_sinh(v, P.beta1), m1, P.sigma1_eff, nu=31)
+    e2 = error_constant(lambda v: what_sinh(v, P.beta2), m2, P.sigma2_eff, nu=31)
+    ratio = P.G1 / (m1 * what_sinh(m1 / (2 * P.sigma1_eff), P.beta1)[0])
+    assert e1 <= E1 <= 60 * e1
+    assert e2 <= E2 <= 60 * e2
+    assert ratio <= oracle.THM41_SLIP * F <= 1.8 * ratio
+    # Theorem 3.5 with the exact constants lies below the gate
+    assert e1 + ratio * e2 <= g
+
+
+# --------------------------------------------------------------------------
+# Theorem 3.4 / 3.5 (B-spline and algebraic windows)
+# --------------------------------------------------------------------------
+
+def test_thm34_constants_hand_worked():
+    # B-spline, m = 2: B_4(0) = 2/3, so c2 = (2/pi)^4 / (2 * 2/3) = 12 / pi^4,
+    # mu = 4; at sigma = 2 the interval starts at 2 (1 - 1/4) = 3/2 and
+    # c1 = c2 (3/2)^-4 = 64 / (27 pi^4)
+    c1, c2, mu = oracle.thm34_constants(oracle.WIN_BSPLINE, 2, 2.0, 0.0)
+    assert mu == 4.0
+    assert c2 == pytest.approx(12.0 / math.pi ** 4, rel=1e-13)
+    assert c1 == pytest.approx(64.0 / (27.0 * math.pi ** 4), rel=1e-13)
+    # algebraic, m = 2, beta = 6: C = pi 12! / (4^6 6!) = pi 479001600 / 2949120
+    # = 162.421875 pi, c2 = C pi^-6 = 162.421875 / pi^5, mu = 6; at sigma = 3/2
+    # the interval starts at 2 (1 - 1/3) = 4/3 and c1 = c2 (4/3)^-6
+    c1, c2, mu = oracle.thm34_constants(oracle.WIN_ALGEBRAIC, 2, 1.5, 6.0)
+    assert mu == 6.0
+    assert c2 == pytest.approx(162.421875 / math.pi ** 5, rel=1e-13)
+    assert c1 == pytest.approx(162.421875 / math.pi ** 5 * (3.0 / 4.0) ** 6, rel=1e-13)
+    # B-spline, m = 3: B_6(0) = 11/20, c2 = (3/pi)^6 / (3 * 11/20) = 4860 / (11 pi^6)
+    _, c2, mu = oracle.thm34_constants(oracle.WIN_BSPLINE, 3, 1.5, 0.0)
+    assert mu == 6.0 and c2 == pytest.approx(4860.0 / (11.0 * math.pi ** 6), rel=1e-13)
+
+
+def _family(kind, m):
+    if kind == oracle.WIN_BSPLINE:
+        return (lambda v: what_bspline(v, m)), 0.0
+    return (lambda v: what_alg(v, 3 * m)), 3.0 * m
+
+
+@pytest.mark.parametrize("kind", [oracle.WIN_BSPLINE, oracle.WIN_ALGEBRAIC], ids=["bspline", "algebraic"])
+@pytest.mark.parametrize("sigma", SIGMAS)
+@pytest.mark.parametrize("m", [2, 3, 5, 8, 12])
+def test_thm34_decay_condition_holds_and_is_attained(kind, sigma, m):
+    if kind == oracle.WIN_ALGEBRAIC and sigma <= math.pi / 3:
+        pytest.skip("the algebraic window needs sigma > pi/3")
+    what, beta = _family(kind, m)
+    c1, c2, mu = oracle.thm34_constants(kind, m, sigma, beta)
+    lo, hi = m * (1 - 1 / (2 * sigma)), m * (1 + 1 / (2 * sigma))
+    v1 = np.linspace(lo, hi, 2001)
+    assert np.abs(what(v1)).max() <= c1 * (1 + 1e-12)
+    v2 = np.linspace(hi, 60.0 * m, 200001)
+    ratio = np.abs(what(v2)) * v2 ** mu / c2
+    assert ratio.max() <= 1 + 1e-9
+    # the envelope is reached (B-spline: |sin| = 1 at the peaks) or close
+    # (algebraic: |J_beta| <= 1 is loose by the Bessel amplitude there)
+    assert ratio.max() >= (0.95 if kind == oracle.WIN_BSPLINE else 0.02), ratio.max()
+
+
+@pytest.mark.parametrize("kind", [oracle.WIN_BSPLINE, oracle.WIN_ALGEBRAIC], ids=["bspline", "algebraic"])
+@pytest.mark.parametrize("sigma", SIGMAS)
+@pytest.mark.parametrize("m", [2, 4, 6])
+def test_thm34_bound_against_error_constant(kind, sigma, m):
+    if kind == oracle.WIN_ALGEBRAIC and sigma <= math.pi / 3:
+        pytest.skip("the algebraic window needs sigma > pi/3")
+    what, beta = _family(kind, m)
+    exact = error_constant(what, m, sigma, R=2000, nu=41)
+    b = oracle.bound_thm34(kind, m, sigma, beta)
+    # measured looseness: 2.8x .. 140x for these m and sigma
+    assert exact <= b <= 300 * exact, (exact, b)
+    # (3.9) from its constants, the denominator omega_hat(m / (2 sigma)) from scipy
+    c1, c2, mu = oracle.thm34_constants(kind, m, sigma, beta)
+    inner = 2 * c1 + 2 * c2 / ((mu - 1) * m ** mu) * (1 - 1 / (2 * sigma)) ** (1 - mu)
+    assert b == pytest.approx(inner / what(m / (2 * sigma))[0], rel=1e-10)
+
+
+@pytest.mark.parametrize("kind", [oracle.WIN_BSPLINE, oracle.WIN_ALGEBRAIC], ids=["bspline", "algebraic"])
+@pytest.mark.parametrize("N,s1,s2,m1,m2", [(64, 2.0, 2.0, 4, 4), (1200, 1.5, 2.0, 3, 6), (40, 2.0, 1.5, 5, 2)])
+def test_thm35_composition(kind, N, s1, s2, m1, m2):
+    # (3.10) = E_sigma1(phi_1) + a / phi_hat_1(N*/2) E_sigma2(phi_2), with
+    # phi_hat_1(N*/2) = (m1 / N1) omega_hat_1(m1 / (2 sigma1_eff)) from scipy
+    P = oracle.params(N, s1, s2, m1, m2, kind)
+    b1 = 0.0 if kind == oracle.WIN_BSPLINE else P.beta1
+    b2 = 0.0 if kind == oracle.WIN_BSPLINE else P.beta2
+    w1, _ = _family(kind, m1)
+    e1 = oracle.bound_thm34(kind, m1, P.sigma1_eff, b1)
+    e2 = oracle.bound_thm34(kind, m2, P.sigma2_eff, b2)
+    ratio = P.a / (m1 / P.N1 * w1(m1 / (2 * P.sigma1_eff))[0])
+    assert oracle.bound_thm35(kind, N, s1, s2, m1, m2) == pytest.approx(e1 + ratio * e2, rel=1e-10)
+    # and it lies above Theorem 3.5 with the exact constants
+    w2, _ = _family(kind, m2)
+    x1 = error_constant(w1, m1, P.sigma1_eff, R=1000, nu=21)
+    x2 = error_constant(w2, m2, P.sigma2_eff, R=1000, nu=21)
+    assert x1 + ratio * x2 <= oracle.bound_thm35(kind, N, s1, s2, m1, m2)
+
+
+# --------------------------------------------------------------------------
+# Theorem 6.2
+# --------------------------------------------------------------------------
+
+def test_thm62_hand_values_and_simplified_form():
+    assert oracle.bound_thm62(0.0, 0.0) == 0.0
+    assert oracle.bound_thm62(1e-9, 0.0) == 1e-9
+    assert oracle.bound_thm62(0.0, 1.0) == 3.0
+    assert oracle.bound_thm62(1e-3, 1e-2) == pytest.approx(1e-3 + 2e-2 + 1e-4, rel=1e-15)
+    # (6.8): for E <= 1 the bound is at most eps + 3 E, with equality at E = 1
+    for E in np.linspace(0.0, 1.0, 11):
+        assert oracle.bound_thm62(1e-6, E) <= 1e-6 + 3 * E + 1e-15
+    assert oracle.bound_thm62(1e-6, 1.0) == pytest.approx(1e-6 + 3.0, rel=1e-15)
+
+
+@pytest.mark.parametrize("E", [1e-6, 1e-2, 0.5])
+def test_thm62_attained_by_a_worst_case(E):
+    # Algorithm 6.1 with both transforms replaced by maps of relative error E in
+    # the worst direction (each returns (1 + E) times its exact value) and an
+    # exact quadrature: h~ = (1 + E)^2 h, so |h~ - h| = (2 E + E^2) |h|, and
+    # with one coefficient at b = a, |h| = sum |c|: the bound (6.7) is attained
+    N, n = 16, 64
+    z, w = np.polynomial.legendre.leggauss(n)
+    w = w / 2.0
+    a, b, c = 0.1, 0.1, 2.5
+    g = (1 + E) * c * np.exp(-1j * np.pi * N * a * z)           # step 1 with error
+    h = (1 + E) * np.sum(w * g * np.exp(1j * np.pi * N * b * z))  # steps 2-3 with error
+    exact = c * np.sinc(N * (b - a))
+    err = abs(h - exact)
+    eps = abs(np.sum(w * np.exp(1j * np.pi * N * (b - a) * z)) - np.sinc(N * (b - a)))
+    assert eps < 1e-14
+    assert err == pytest.approx((2 * E + E * E) * abs(c), rel=1e-9, abs=1e-13)
+    assert err <= oracle.bound_thm62(eps, E) * abs(c) + 1e-14
+    assert oracle.bound_thm62(0.0, E) * abs(c) == pytest.approx(err, rel=1e-9, abs=1e-13)

@@ -14,6 +14,9 @@ from paper_2107_02671_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 FP64, FP32 = P.NNFFT_FP64_PLAIN, P.NNFFT_FP32_COMP
+# the kappa-scaled FP32 gate never exceeds 1e-3 (the measured errors at the
+# largest kappa tested, sigma = 5/4 with m = 10, are ~3e-4)
+FP32_CAP = 1e-3
 DEV = "cuda:0"
 
 
@@ -24,7 +27,7 @@ def _tol(prec, N, m):
     Pp = oracle.params(N, 2.0, 2.0, m, m)
     k = max(oracle.omega_hat(0.0, b) / oracle.omega_hat(m / (2 * s), b)
             for b, s in ((Pp.beta1, Pp.sigma1_eff), (Pp.beta2, Pp.sigma2_eff)))
-    return 1e-5 * max(1.0, float(k) / 4.62)
+    return min(FP32_CAP, 1e-5 * max(1.0, float(k) / 4.62))
 
 
 def _say(*a):

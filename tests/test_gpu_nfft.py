@@ -6,7 +6,8 @@ Tolerance (E_inf against max |oracle|): 1e-12 (FP64) or 1e-5 (FP32) times
 max(1, kappa / 4.62), kappa = omega_hat(0) / omega_hat(m N / (2 n)): the
 deconvolution amplifies the rounding of the length-n transform by up to kappa
 at the band edge (kappa = 4.62 at sigma = 2, m = 6; 9.5e3 at sigma = 1.25,
-m = 10, where the GPU and oracle FP64 results differ by 6e-12)."""
+m = 10, where the GPU and oracle FP64 results differ by 6e-12).  The FP32
+gate is capped at 1e-3."""
 import sys
 
 import numpy as np
@@ -20,6 +21,9 @@ from paper_2107_02671_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 FP64, FP32 = P.NNFFT_FP64_PLAIN, P.NNFFT_FP32_COMP
+# the kappa-scaled FP32 gate never exceeds 1e-3 (the measured errors at the
+# largest kappa tested, sigma = 5/4 with m = 10, are ~3e-4)
+FP32_CAP = 1e-3
 DEV = "cuda:0"
 
 
@@ -31,7 +35,9 @@ def _say(*a):
 def tol(prec, N, sigma, m):
     n, beta = oracle.nfft_params(N, sigma, m)
     kappa = oracle.omega_hat(0.0, beta) / oracle.omega_hat(m * N / (2.0 * n), beta)
-    return (1e-12 if prec == FP64 else 1e-5) * max(1.0, float(kappa) / 4.62)
+    if prec == FP64:
+        return 1e-12 * max(1.0, float(kappa) / 4.62)
+    return min(FP32_CAP, 1e-5 * max(1.0, float(kappa) / 4.62))
 
 
 def einf(a, b):

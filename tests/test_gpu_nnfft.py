@@ -14,7 +14,8 @@ Tolerances (relative l-infinity error E_inf = max|y_gpu - y_oracle| / max|y_orac
                    phi_hat (steps 2 and output): the FFT's absolute FP32
                    rounding is divided by phi_hat_1(N x_j), which is kappa
                    times smaller at |x_j| = 1/2 than at 0.  1e-5 is the stated
-                   FP32 requirement at m = 6, sigma = 2, where kappa = 4.62.
+                   FP32 requirement at m = 6, sigma = 2, where kappa = 4.62;
+                   capped at 1e-3.
 Cases span several workgroups and node blocks with ragged tails, the FFT in
 one workgroup and in four-step form, radix 3/5 transform lengths, unequal
 sigma and m, edge and clustered nodes, and single-node inputs.  At the
@@ -34,6 +35,9 @@ from paper_2107_02671_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 FP64, FP32 = P.NNFFT_FP64_PLAIN, P.NNFFT_FP32_COMP
+# the kappa-scaled FP32 gate never exceeds 1e-3 (the measured errors at the
+# largest kappa tested, sigma = 5/4 with m = 10, are ~3e-4)
+FP32_CAP = 1e-3
 TOL = {FP64: 1e-12, FP32: 1e-5}
 DEV = "cuda:0"
 KAPPA_REF = 4.62   # kappa at m = 6, sigma = 2
@@ -49,7 +53,7 @@ def kappa(N, s1, s2, m1, m2):
 def tol(prec, N, s1, s2, m1, m2):
     if prec == FP64:
         return max(TOL[FP64], 4.0 * N * 2.0 ** -53)
-    return TOL[FP32] * max(1.0, kappa(N, s1, s2, m1, m2) / KAPPA_REF)
+    return min(FP32_CAP, TOL[FP32] * max(1.0, kappa(N, s1, s2, m1, m2) / KAPPA_REF))
 
 
 def _say(*a):
@@ -121,7 +125,7 @@ def test_small_workload_against_direct_sum(prec):
     ex = oracle.direct(N, v, f, x)
     assert einf(y, yo) <= TOL[prec]
     e_paper = np.abs(y - ex).max() / np.abs(f).sum()
-    assert e_paper <= 1.08 * info["bound_thm41"]
+    assert e_paper <= gate41(info)
 
 
 @pytest.mark.parametrize("prec", [FP64, FP32])
@@ -253,7 +257,12 @@ def test_maximum_bandwidth(case):
     assert e <= t
     ex = oracle.direct(N, v, f, x[idx])
     e_paper = np.abs(y[idx] - ex).max() / np.abs(f).sum()
-    assert e_paper <= 1.08 * info["bound_thm41"] + t * np.abs(ex).max() / np.abs(f).sum()
+    assert e_paper <= gate41(info) + t * np.abs(ex).max() / np.abs(f).sum()
+
+
+def gate41(info):
+    """(4.2) at the plan's sizes with the slip of its proof corrected (second term x 1.08)."""
+    return oracle.bound_thm41_gate(info["N1"], info["m1"], info["m2"], info["sigma1_eff"], info["sigma2_eff"])
 
 
 def _degenerate_nodes(kind, N, m):
@@ -293,4 +302,4 @@ def test_degenerate_node_sets(kind, prec):
     if kind == "identical_v":
         # closed form: y_j = (sum_k f_k) exp(-2 pi i N v x_j), within Theorem 4.1
         ex = f.sum() * np.exp(-2j * np.pi * N * 0.123 * x)
-        assert np.abs(y - ex).max() / np.abs(f).sum() <= 1.08 * info["bound_thm41"] + t * np.abs(yo).max() / np.abs(f).sum()
+        assert np.abs(y - ex).max() / np.abs(f).sum() <= gate41(info) + t * np.abs(yo).max() / np.abs(f).sum()

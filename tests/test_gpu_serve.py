@@ -119,7 +119,7 @@ def test_server_mix_equals_alone():
             yo = oracle.sinc_fast_equispaced(r["N"], r["hv"], r["hf"], r["hx"], r["n_quad"],
                                              oracle.QUAD_GAUSS_LEGENDRE, 2.0, r["m"], False, r["eq"],
                                              2.0, r["m"])
-            tol = 1e-12 if r["prec"] == FP64 else 2e-5
+            tol = 1e-12 if r["prec"] == FP64 else 1e-5
         else:
             yo = oracle.nnfft(r["N"], r["hv"], r["hf"], r["hx"], 2.0, 2.0, r["m"], r["m"])
             tol = 1e-12 if r["prec"] == FP64 else 1e-5

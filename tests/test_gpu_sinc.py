@@ -7,12 +7,11 @@ sampled outputs with the direct sum (6.2).
 
 Tolerances (relative l-infinity error against max |h_oracle|):
   FP64 plain  1e-12
-  FP32        2e-5 * max(1, kappa / 4.62): two chained NNFFTs.  The first
-              transform's error delta_j (<= 1e-5 max|g| by the NNFFT gate) enters
-              the second only through sum_j w_j delta_j e^(...), and the weights
-              are positive with sum 1, so it adds at most 1e-5 max|g|; max|g| is
-              reached at z = 0 where g(0) = sum c_k = h at coincident nodes up to
-              the sinc decay, so both halves are of the size of max|h|.
+  FP32        1e-5, the stated FP32 requirement, for every result (every
+              case here has sigma = 2 and m >= 6).  Two NNFFTs are chained, but
+              the first one's error enters the second only through
+              sum_j w_j delta_j e^(...) with positive weights of sum 1, and the
+              measured E_inf of the chain is ~4e-7.
 """
 import sys
 
@@ -39,7 +38,8 @@ def _say(*a):
 def tol(prec, m):
     if prec == FP64:
         return 1e-12
-    return 2e-5 * (1.0 if m >= 6 else 3.0)
+    assert m >= 6, "the FP32 sinc cases run at m >= 6"
+    return 1e-5
 
 
 def gpu_sinc(N, a, b, c, n_quad, quad, m, prec):
@@ -98,7 +98,7 @@ def test_sinc_full_size_against_direct_sum(prec):
     xs = np.linspace(-1, 1, 8001)
     eps = np.abs((wq[None, :] * np.exp(-1j * np.pi * N * np.outer(xs, z))).sum(1) - np.sinc(N * xs)).max()
     Pp = oracle.params(N, 2.0, 2.0, 6, 6)
-    E = 1.08 * oracle.bound_thm41(Pp.N1, 6, 6, Pp.sigma1_eff, Pp.sigma2_eff)
+    E = oracle.bound_thm41_gate(Pp.N1, 6, 6, Pp.sigma1_eff, Pp.sigma2_eff)
     bound = oracle.bound_thm62(eps, E) * np.abs(c).sum()
     assert err <= bound + tol(prec, 6) * np.abs(ho).max()
     assert e_direct <= 1e-4

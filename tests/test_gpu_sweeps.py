@@ -12,8 +12,8 @@ NNFFT (parity) and with the direct sum (1.2):
     does not hurt), checked as an observed property.
 Parity tolerance (E_inf against the oracle): 1e-12 (FP64) or 1e-5 (FP32)
 times max(1, kappa / 4.62), kappa the amplification of the two phi_hat
-divisions (m2 = 16 at sigma = 5/4 gives kappa ~ 3e6).  FP32 runs where
-m1 >= 4 and kappa <= 1e3.
+divisions (m2 = 16 at sigma = 5/4 gives kappa ~ 3e6), the FP32 gate capped
+at 1e-3.  FP32 runs where m1 >= 4 and kappa <= 1e3.
 
 Example 6.3 (fast sinc accuracy): N = 2^k, k = 5..13, L1 = N/2 random
 a_k in [-1/2, 1/2], b_l = l / N (L2 = N, so step 3 is the adjoint NFFT of
@@ -36,6 +36,9 @@ from paper_2107_02671_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 FP64, FP32 = P.NNFFT_FP64_PLAIN, P.NNFFT_FP32_COMP
+# the kappa-scaled FP32 gate never exceeds 1e-3 (the measured errors at the
+# largest kappa tested, sigma = 5/4 with m = 10, are ~3e-4)
+FP32_CAP = 1e-3
 CC = P.SINC_QUAD_CLENSHAW_CURTIS
 DEV = "cuda:0"
 SLIP = 1.08
@@ -53,7 +56,9 @@ def _kappa(Pp, m1, m2):
 
 
 def _parity_tol(prec, kappa):
-    return (1e-12 if prec == FP64 else 1e-5) * max(1.0, kappa / 4.62)
+    if prec == FP64:
+        return 1e-12 * max(1.0, kappa / 4.62)
+    return min(FP32_CAP, 1e-5 * max(1.0, kappa / 4.62))
 
 
 _EX42 = {}
@@ -102,10 +107,10 @@ def test_example_4_2_grid(var, s1):
                 continue
             floor = 1e-14 + 1e-16 * kap
             if var in ("a", "b"):
-                bound = SLIP * oracle.bound_thm41(Pp.N1, m1, m2, Pp.sigma1_eff, Pp.sigma2_eff)
+                bound = oracle.bound_thm41_gate(Pp.N1, m1, m2, Pp.sigma1_eff, Pp.sigma2_eff)
             else:
                 Pb = oracle.params(N, s1, s1, m1, m1)
-                bound = SLIP * oracle.bound_thm41(Pb.N1, m1, m1, Pb.sigma1_eff, Pb.sigma2_eff)
+                bound = oracle.bound_thm41_gate(Pb.N1, m1, m1, Pb.sigma1_eff, Pb.sigma2_eff)
             assert e_paper <= bound + floor, (m1, e_paper, bound)
 
 
@@ -122,7 +127,7 @@ def test_example_6_3_grid(k):
     m = 8
     Pp = oracle.params(N, 2.0, 2.0, m, m)
     n_nfft, _ = oracle.nfft_params(N, 2.0, m)
-    E = max(SLIP * oracle.bound_thm41(Pp.N1, m, m, Pp.sigma1_eff, Pp.sigma2_eff),
+    E = max(oracle.bound_thm41_gate(Pp.N1, m, m, Pp.sigma1_eff, Pp.sigma2_eff),
             24.0 * m ** 1.5 * math.exp(-2 * math.pi * m * math.sqrt(1 - N / n_nfft)))
     for nu in ((4, 6, 8) if k <= 12 else (4,)):
         nq = nu * N
@@ -145,6 +150,6 @@ def test_example_6_3_grid(k):
             err = float(np.abs(h - exact).max())
             bound = oracle.bound_thm62(oracle.bound_thm53(N, nu), E) * float(np.abs(c).sum())
             _say(f"    E_inf vs oracle {e_or:.2e}, max error {err:.2e} (Theorem 6.2: {bound:.2e})")
-            assert e_or <= (1e-12 if prec == FP64 else 2e-5)
+            assert e_or <= (1e-12 if prec == FP64 else 1e-5)
             if prec == FP64:
                 assert err <= bound + 1e-13 * float(np.abs(c).sum())

@@ -22,6 +22,9 @@ from paper_2107_02671_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 FP64, FP32 = P.NNFFT_FP64_PLAIN, P.NNFFT_FP32_COMP
+# the kappa-scaled FP32 gate never exceeds 1e-3 (the measured errors at the
+# largest kappa tested, sigma = 5/4 with m = 10, are ~3e-4)
+FP32_CAP = 1e-3
 BSPL, ALG = P.NNFFT_WINDOW_BSPLINE, P.NNFFT_WINDOW_ALGEBRAIC
 DEV = "cuda:0"
 
@@ -39,7 +42,9 @@ def _kappa(kind, N, s1, s2, m1, m2):
 
 
 def _tol(prec, kind, N, s1, s2, m1, m2):
-    return (1e-12 if prec == FP64 else 1e-5) * max(1.0, _kappa(kind, N, s1, s2, m1, m2) / 4.62)
+    if prec == FP64:
+        return 1e-12 * max(1.0, _kappa(kind, N, s1, s2, m1, m2) / 4.62)
+    return min(FP32_CAP, 1e-5 * max(1.0, _kappa(kind, N, s1, s2, m1, m2) / 4.62))
 
 
 CASES = [

@@ -202,3 +202,28 @@ def test_window_plan_errors():
         binding.nnfft_plan_dry_run(100, v, v, 1.02, 2.0, 4, 4, P.NNFFT_FP64_PLAIN, window=P.NNFFT_WINDOW_ALGEBRAIC)
     with pytest.raises(P.NnfftError):
         binding.nnfft_plan_dry_run(100, v, v, 2.0, 2.0, 4, 4, P.NNFFT_FP64_PLAIN, window=3)
+
+
+@pytest.mark.parametrize("prec,qmax", [(P.NNFFT_FP32_COMP, 32), (P.NNFFT_FP64_PLAIN, 8)])
+@pytest.mark.parametrize("kind", ["chebyshev", "clustered"])
+def test_dense_node_sets_raise_the_item_size(prec, qmax, kind):
+    # 2^18 dense nodes at N = 1024 (the sinc workload's first spreading side,
+    # ~127 nodes per grid cell and far more at the crowded ends): the layout
+    # raises the item size to the family's maximum, with or without a tuned
+    # entry for that size class (tuned entries are timed on uniform nodes)
+    from paper_2107_02671_amd import workloads as W
+    g = W.rng(18)
+    gen = W.chebyshev_nodes if kind == "chebyshev" else W.clustered_nodes
+    v = gen(g, 1 << 18)
+    x = W.uniform_nodes(g, 2048)
+    try:
+        binding.nnfft_clear_tuning()
+        assert binding.nnfft_plan_dry_run(1024, v, x, 2.0, 2.0, 6, 6, prec)["items_points"] == qmax
+        binding.nnfft_set_tuning(prec, 1 << 18, 4, 1 << 15)
+        assert binding.nnfft_get_tuning(prec, 1 << 18)["tuned"] == 1
+        assert binding.nnfft_plan_dry_run(1024, v, x, 2.0, 2.0, 6, 6, prec)["items_points"] == qmax
+        # uniform nodes of the same size class keep the tuned item size
+        u = W.uniform_nodes(g, 1 << 18)
+        assert binding.nnfft_plan_dry_run(1024, u, x, 2.0, 2.0, 6, 6, prec)["items_points"] == 4
+    finally:
+        binding.nnfft_clear_tuning()

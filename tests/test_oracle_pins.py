@@ -21,10 +21,6 @@ import oracle
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
-# Theorem 4.1 slip: the proof's lower bound for I_1 holds with the constant
-# sqrt(x0) e^{-x0} I_1(x0) = 0.3705 at x0 = 4 pi / sqrt 5, not 2/5, so the
-# second term of (4.2) is scaled by 0.4 / 0.3705 = 1.08 when used as a gate.
-THM41_SLIP = 1.08
 
 
 def _rng(seed):
@@ -36,7 +32,8 @@ def _cgauss(rng, n):
 
 
 def _bound(P):
-    return THM41_SLIP * oracle.bound_thm41(P.N1, P.m1, P.m2, P.sigma1_eff, P.sigma2_eff)
+    # (4.2) with the slip of its proof corrected on the second term (1.08)
+    return oracle.bound_thm41_gate(P.N1, P.m1, P.m2, P.sigma1_eff, P.sigma2_eff)
 
 
 # --------------------------------------------------------------------------
