@@ -1,26 +1,37 @@
 #!/usr/bin/env python3
-"""Benchmark of the NNFFT (Algorithm 2.2) on one MI355X.
+"""Benchmark of the NNFFT (Algorithm 2.2) and the fast sinc transform
+(Algorithm 6.1) on one MI355X.
 
-Workload: N = 4096, M1 = M2 = 2^20, v_k, x_j iid uniform in [-1/2, 1/2),
-f_k complex Gaussian, sigma1 = sigma2 = 2, m1 = m2 = 6 (seeded synthetic
-inputs).  One step = one nnfft_exec (spreading, merge + deconvolution + FFT,
-interpolation + correction) with the plan and all inputs resident in HBM.
+Headline workload: N = 4096, M1 = M2 = 2^20, v_k, x_j iid uniform in
+[-1/2, 1/2), f_k complex Gaussian, sigma1 = sigma2 = 2, m1 = m2 = 6 (seeded
+synthetic inputs).  One step = one nnfft_exec (spreading, merge +
+deconvolution + FFT, interpolation + correction) with the plan and all inputs
+resident in HBM.
 
 Reported (one JSON line):
   value          (M1 + M2) points/s of the FP32 compensated path over the timed steps
+  step_ms        mean (wall clock), median and p99 (device span of each exec)
   fp64_plain     the same for the FP64 plain path (the comparator)
-  rel_err_inf    E_inf of both results against the FP64 CPU oracle
+  rel_err_inf    E_inf of both results against the FP64 CPU oracle (all outputs)
   latency_ms     p50 / p99 of exec latency (submit to completion, one at a time)
-  roofline       the slowest kernel's algorithmic bytes per launch / its average
-                 duration, from HIP events recorded on the library's stream
+  roofline       the dominant kernel's algorithmic bytes per launch / its
+                 average duration; durations come from HIP events attached to
+                 each kernel's dispatch during the timed steps (on the stream
+                 the kernels run on); kernels: every FP32 kernel's fraction
   cpu_baseline   the FP64 CPU oracle NNFFT on the same workload
+  sinc           the fast sinc transform: N = 1024, L1 = L2 = 2^18
+                 Chebyshev-distributed nodes, 2048 Gauss-Legendre nodes,
+                 (L1 + L2) points/s and E_inf against the direct sum (6.2)
+  clustered      N = 16384, M1 = M2 = 2^24 nodes in 32 Gaussian clusters, m = 8:
+                 pts/s (FP32, FP64), spreading GB/s, E_inf against the direct sum
   batched        the served request mix (N log-uniform in [64, 8192], M1, M2
                  log-uniform in [2^10, 2^20]) as resident plans run by
                  nnfft_exec_batch: FP32 (m=6) against FP64 plain (m=12) pts/s
   served         the same mix through the serving layer (plans built per
-                 request, admitted by HBM footprint, continuous batching):
-                 closed-loop capacity, then Poisson arrivals at 0.5, 0.8 and
-                 1.0 times that rate with p50 / p99 latency (submit to done)
+                 request, admitted by HBM footprint, continuous batching), all
+                 10,000 requests: closed-loop capacity, then Poisson arrivals at
+                 0.5, 0.8 and 1.0 times that rate with p50 / p99 latency
+                 measured from each request's scheduled arrival
 """
 from __future__ import annotations
 
@@ -28,6 +39,7 @@ import argparse
 import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -48,31 +60,106 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per launch from the rocprofv3 counter runs, if they were taken
-    on the current kernel sources (else None)."""
+def measured_traffic():
+    """HBM bytes per launch of each kernel from the rocprofv3 counter runs, if
+    they were taken on the current kernel sources (else {})."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
-        return None
+        return {}
     if t.get("source_sha256") != kernel_source_hash():
-        return None
-    k = t.get("kernels", {}).get(kernel)
-    return None if k is None else float(k["bytes_per_launch"])
+        return {}
+    return {k: float(v["bytes_per_launch"]) for k, v in t.get("kernels", {}).items()}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
 
 
 def time_steps(fn, steps, warmup, torch, before=None):
     for _ in range(warmup):
         fn()
+    torch.cuda.synchronize()
     if before is not None:
         before()
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         fn()
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) / steps
+
+
+def pct(a, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(a), q)) if len(a) else None
+
+
+def kernel_bytes(name, M1, M2, info, b):
+    """Algorithmic bytes per launch of one kernel (b: bytes per complex value).
+    Spreading reads f and an 8-byte node record per point and writes the grid
+    (G1 values); stage A reads the grid and writes the N2-point intermediate;
+    stage B (or the one-workgroup FFT) writes the 2S + 1 consumed outputs;
+    interpolation reads them and a record per point and writes y."""
+    import math
+    G1, N2 = info["G1"], info["N2"]
+    # outputs |s| <= S of the FFT are consumed by the interpolation
+    S = min(N2 // 2, math.ceil(N2 * info["N_star"] / (2 * info["N1"])) + info["m2"])
+    rec = 8 if b == 8 else 12
+    if name.startswith("k_spread"):
+        return M1 * (b + rec) + G1 * b
+    if name == "k_fft_stageA":
+        return G1 * b + N2 * b
+    if name == "k_fft_stageB":
+        return N2 * b + (2 * S + 1) * b
+    if name == "k_fft_single":
+        return G1 * b + (2 * S + 1) * b
+    if name.startswith("k_interp"):
+        return M2 * (rec + b) + (2 * S + 1) * b
+    return None
+
+
+def profiled_steps(P, torch, plan, step, steps, warmup):
+    """Three passes of `steps` execs: (1) the timed region, host clock around
+    the whole pass, nothing else recorded; (2) a HIP event pair recorded on
+    the stream around each exec, for the spread of the step time; (3) kernel
+    events attached to every kernel dispatch (nnfft_profile_start), for each
+    kernel's own duration.  The events of (2) and (3) add marker packets and
+    host work between kernels, so (1) alone gives the throughput."""
+    s = time_steps(step, steps, warmup, torch)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    for a, b in ev:
+        a.record()
+        step()
+        b.record()
+    torch.cuda.synchronize()
+    spans = [a.elapsed_time(b) for a, b in ev]
+    P.nnfft_profile_start(plan.handle, steps)
+    for _ in range(steps):
+        step()
+    kern, _ = P.nnfft_profile_kernels(plan.handle, steps)
+    return s, spans, kern
+
+
+def roofline_table(kern, M1, M2, info, b, traffic):
+    out = {}
+    for k in kern:
+        ab = kernel_bytes(k["name"], M1, M2, info, b)
+        if ab is None:
+            continue
+        gbs = ab / (k["avg_ms"] * 1e-3) / 1e9
+        out[k["name"]] = {"avg_ms": k["avg_ms"], "min_ms": k["min_ms"], "max_ms": k["max_ms"],
+                          "algorithmic_bytes": ab, "achieved_GBs": gbs, "frac": gbs / HBM_PEAK_GBS,
+                          "traffic": traffic.get(k["name"])}
+    return out
 
 
 def request_inputs(torch, req, fp32, dev):
@@ -87,9 +174,87 @@ def request_inputs(torch, req, fp32, dev):
     return v, x, f, y
 
 
+def sinc_benchmark(P, W, torch, steps, warmup, accuracy):
+    """Fast sinc transform, N = 1024, L1 = L2 = 2^18 Chebyshev nodes, 2N
+    Gauss-Legendre nodes, sigma = 2, m = 6."""
+    import numpy as np
+    dev = torch.device("cuda:0")
+    N, a, b, c, w = W.nnfft_inputs("sinc")
+    nq, sig, m = w["n_quad"], w["sigma"], w["m"]
+    ta, tb = torch.tensor(a, device=dev), torch.tensor(b, device=dev)
+    out = {"workload": "sinc_chebyshev_N1024_L2^18_GL2048_m6_sigma2", "N": N, "L1": len(a), "L2": len(b),
+           "n_quad": nq, "quadrature": "Gauss-Legendre"}
+    res = {}
+    for name, prec, cdt in [("fp32", P.NNFFT_FP32_COMP, torch.complex64),
+                            ("fp64", P.NNFFT_FP64_PLAIN, torch.complex128)]:
+        sp = P.SincPlan(N, ta, tb, nq, P.SINC_QUAD_GAUSS_LEGENDRE, sig, sig, m, m, prec)
+        tc = torch.tensor(c, dtype=cdt, device=dev)
+        h = torch.empty(len(b), dtype=cdt, device=dev)
+        st = torch.cuda.current_stream()
+        fn = lambda: P.binding.lib().sinc_exec(sp.handle, P.binding._ptr(tc), P.binding._ptr(h),  # noqa: E731
+                                               P.binding._stream(st))
+        t = time_steps(fn, steps, warmup, torch)
+        fn()
+        torch.cuda.synchronize()
+        res[name] = {"ms_per_step": t * 1e3, "value": (len(a) + len(b)) / t, "unit": "pts/s",
+                     "h": h.cpu().numpy()}
+        sp.close()
+    for name in res:
+        out[name] = {k: v for k, v in res[name].items() if k != "h"}
+    if accuracy:
+        import oracle
+        idx = np.linspace(0, len(b) - 1, 1024).astype(np.int64)
+        ho = oracle.sinc_direct(N, a, c + 0j, b[idx])
+        den = np.abs(ho).max()
+        out["rel_err_inf"] = {name: float(np.abs(res[name]["h"][idx] - ho).max() / den) for name in res}
+        out["rel_err_inf"]["reference"] = "direct sum (6.2) in FP64 on 1024 evenly spaced outputs"
+    return out
+
+
+def clustered_benchmark(P, W, torch, steps, warmup, accuracy, traffic):
+    """N = 16384, M1 = M2 = 2^24 nodes in 32 Gaussian clusters, m = 8."""
+    import numpy as np
+    dev = torch.device("cuda:0")
+    N, v, x, f, w = W.nnfft_inputs("clustered")
+    M1, M2, m, sig = len(v), len(x), w["m"], w["sigma"]
+    tv, tx = torch.tensor(v, device=dev), torch.tensor(x, device=dev)
+    out = {"workload": "nnfft_clustered32_N16384_M2^24_m8_sigma2", "N": N, "M1": M1, "M2": M2, "m": m,
+           "nodes": "32 Gaussian clusters, std 1e-3, centres uniform in [-0.45, 0.45]"}
+    ys = {}
+    for name, prec, cdt, b in [("fp32", P.NNFFT_FP32_COMP, torch.complex64, 8),
+                               ("fp64", P.NNFFT_FP64_PLAIN, torch.complex128, 16)]:
+        t0 = time.perf_counter()
+        p = P.Plan(N, tv, tx, sig, sig, m, m, prec)
+        plan_s = time.perf_counter() - t0
+        tf = torch.tensor(f, dtype=cdt, device=dev)
+        y = torch.empty(M2, dtype=cdt, device=dev)
+        st = torch.cuda.current_stream()
+        fn = lambda: P.binding.lib().nnfft_exec(p.handle, P.binding._ptr(tf), P.binding._ptr(y),  # noqa: E731
+                                                P.binding._stream(st))
+        t, spans, kern = profiled_steps(P, torch, p, fn, steps, warmup)
+        info = P.nnfft_info(p.handle)
+        out[name] = {"ms_per_step": t * 1e3, "value": (M1 + M2) / t, "unit": "pts/s",
+                     "step_ms_median": pct(spans, 50), "plan_s": plan_s,
+                     "kernels": roofline_table(kern, M1, M2, info, b, traffic if name == "fp32" else {})}
+        fn()
+        torch.cuda.synchronize()
+        ys[name] = y.cpu().numpy()
+        p.close()
+        del tf, y
+    out["speedup_fp32_over_fp64"] = out["fp32"]["value"] / out["fp64"]["value"]
+    if accuracy:
+        import oracle
+        g = W.rng(55)
+        idx = np.sort(g.choice(M2, 64, replace=False))
+        yo = oracle.direct(N, v, f, x[idx])
+        den = np.abs(yo).max()
+        out["rel_err_inf"] = {name: float(np.abs(ys[name][idx] - yo).max() / den) for name in ys}
+        out["rel_err_inf"]["reference"] = "direct sum (1.2) in FP64 on 64 random outputs"
+    return out
+
+
 def batched_benchmark(P, W, torch, nplans, reps=20):
     """Resident plans of the served mix, one nnfft_exec_batch per step."""
-    import numpy as np
     dev = torch.device("cuda:0")
     reqs = W.served_requests(nplans * 4, seed=4)
     out = {}
@@ -113,7 +278,10 @@ def batched_benchmark(P, W, torch, nplans, reps=20):
 
 
 def served_benchmark(P, W, torch, n_req, planners=12, budget=16 << 30):
-    """The served request stream: closed loop for capacity, then Poisson arrivals."""
+    """The served request stream: closed loop for capacity, then Poisson
+    arrivals.  Under Poisson arrivals a request's latency runs from its
+    scheduled arrival (not from its submit call) to its completion, so time
+    the generator spends behind schedule counts against the server."""
     import threading
 
     import numpy as np
@@ -124,6 +292,8 @@ def served_benchmark(P, W, torch, n_req, planners=12, budget=16 << 30):
         srv = P.Server(hbm_budget_bytes=budget, planner_threads=planners, streams=2)
         results = [None] * len(reqs)
         tickets = [None] * len(reqs)
+        t_sub = np.zeros(len(reqs))      # perf_counter just before each submit call
+        t_sched = np.zeros(len(reqs))    # scheduled arrival (perf_counter clock)
         ready = threading.Semaphore(0)
         window = threading.Semaphore(256)      # at most 256 outstanding (input memory)
 
@@ -140,24 +310,39 @@ def served_benchmark(P, W, torch, n_req, planners=12, budget=16 << 30):
         for i, r in enumerate(reqs):
             if rate is not None:
                 arrival += r["gap"] / rate
-                while time.perf_counter() - t0 < arrival:
-                    time.sleep(min(1e-3, max(0.0, arrival - (time.perf_counter() - t0))))
+                t_sched[i] = t0 + arrival
+                while time.perf_counter() < t_sched[i]:
+                    time.sleep(min(1e-3, max(0.0, t_sched[i] - time.perf_counter())))
             window.acquire()
             v, x, f, y = request_inputs(torch, r, r["fp32"], dev)
             torch.cuda.current_stream().synchronize()
             prec = P.NNFFT_FP32_COMP if r["fp32"] else P.NNFFT_FP64_PLAIN
+            t_sub[i] = time.perf_counter()
             tickets[i] = srv.submit(r["N"], v, x, f, y, sigma1=2.0, sigma2=2.0, m1=r["m"], m2=r["m"], prec=prec)
+            if rate is None:
+                t_sched[i] = t_sub[i]
             ready.release()
         th.join()
         wall = time.perf_counter() - t0
         st = srv.stats()
         srv.close()
-        lat = np.array([res["done_ms"] - res["submit_ms"] for res in results])
+        sub_ms = np.array([res["submit_ms"] for res in results])
+        done_ms = np.array([res["done_ms"] for res in results])
+        # server clock (ms since its creation, steady clock) -> perf_counter
+        # seconds (both CLOCK_MONOTONIC): the submit stamp is taken inside the
+        # submit call, after t_sub, so every t_sub - submit stamp is at most
+        # the offset and the largest one is the closest
+        off = float(np.max(t_sub - sub_ms * 1e-3))
+        done = done_ms * 1e-3 + off
+        lat = (done - t_sched) * 1e3
+        lag = (t_sub - t_sched) * 1e3
         ok = sum(res["status"] == 0 for res in results)
         pts = sum(r["M1"] + r["M2"] for r in reqs)
         return {"requests": len(reqs), "ok": ok, "wall_s": wall, "req_per_s": len(reqs) / wall,
-                "value": pts / wall, "unit": "pts/s", "p50_ms": float(np.percentile(lat, 50)),
-                "p99_ms": float(np.percentile(lat, 99)),
+                "value": pts / wall, "unit": "pts/s", "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
+                "latency_from": "submit" if rate is None else "scheduled arrival",
+                "server_p50_ms": pct(done_ms - sub_ms, 50), "server_p99_ms": pct(done_ms - sub_ms, 99),
+                "generator_lag_ms": {"p50": pct(lag, 50), "p99": pct(lag, 99), "max": float(lag.max())},
                 "mean_group": float(np.mean([res["group_size"] for res in results])),
                 "admission_waits": st["admission_waits"], "arena_peak_bytes": st["arena_peak"]}
 
@@ -181,10 +366,12 @@ def main() -> int:
     ap.add_argument("--fp32-only", action="store_true", help="skip the FP64 plain comparator")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 256 MiB device copy (counter calibration runs)")
-    ap.add_argument("--serve-requests", type=int, default=2000,
-                    help="requests per served run (the full request stream has 10000; 0 skips)")
+    ap.add_argument("--serve-requests", type=int, default=10000,
+                    help="requests per served run (the request stream has 10000; 0 skips)")
     ap.add_argument("--batch-plans", type=int, default=48,
                     help="resident plans per precision in the batched measurement (0 skips)")
+    ap.add_argument("--no-sinc", action="store_true", help="skip the fast sinc transform leg")
+    ap.add_argument("--no-clustered", action="store_true", help="skip the clustered 2^24-node leg")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -199,6 +386,7 @@ def main() -> int:
     from paper_2107_02671_amd import workloads as W
 
     dev = torch.device("cuda:0")
+    traffic = measured_traffic()
     N, v, x, f, w = W.nnfft_inputs("large")
     M1, M2, m, sig = len(v), len(x), w["m"], w["sigma"]
     tv = torch.tensor(v, device=dev)
@@ -224,26 +412,15 @@ def main() -> int:
         P.binding.lib().nnfft_exec(p64.handle, P.binding._ptr(f64), P.binding._ptr(y64),
                                    P.binding._stream(stream))
 
-    # timed region: exactly `steps` FP32 execs, synchronized on both sides
+    # timed region: exactly `steps` FP32 execs, synchronized on both sides;
+    # then the same steps again with events (step spread, kernel durations)
     print(f"[bench] timing FP32 ({args.steps} steps)", file=sys.stderr, flush=True)
-    s32 = time_steps(step32, args.steps, args.warmup, torch)
+    s32, spans32, kern32 = profiled_steps(P, torch, p32, step32, args.steps, args.warmup)
     if not args.fp32_only:
         print(f"[bench] timing FP64 plain ({args.steps} steps)", file=sys.stderr, flush=True)
-        s64 = time_steps(step64, args.steps, args.warmup, torch)
-    # kernel durations: the same steps again with HIP events recorded by the
-    # library at the stage boundaries on its stream (each event costs a few
-    # microseconds of stream time, so these steps are not the timed region)
-    print("[bench] stage events", file=sys.stderr, flush=True)
-    s32_ev = time_steps(step32, args.steps, 0, torch,
-                        before=lambda: P.nnfft_profile_start(p32.handle, args.steps))
-    stages32, n32 = P.nnfft_profile_stop(p32.handle)
-    if args.fp32_only:
-        s64 = s64_ev = float("nan")
-        stages64 = (float("nan"),) * 3
+        s64, spans64, kern64 = profiled_steps(P, torch, p64, step64, args.steps, args.warmup)
     else:
-        s64_ev = time_steps(step64, args.steps, 0, torch,
-                            before=lambda: P.nnfft_profile_start(p64.handle, args.steps))
-        stages64, n64 = P.nnfft_profile_stop(p64.handle)
+        s64, spans64, kern64 = float("nan"), [], []
 
     # exec latency, one call at a time
     lat = []
@@ -252,8 +429,9 @@ def main() -> int:
         step32()
         torch.cuda.synchronize()
         lat.append((time.perf_counter() - t0) * 1e3)
-    lat = np.array(lat)
 
+    info32 = P.nnfft_info(p32.handle)
+    info64 = P.nnfft_info(p64.handle)
     out = {
         "metric": METRIC,
         "value": (M1 + M2) / s32,
@@ -271,43 +449,36 @@ def main() -> int:
                    "sigma1": sig, "sigma2": sig, "m1": m, "m2": m,
                    "nodes": "iid uniform [-1/2,1/2)", "coefficients": "complex Gaussian",
                    "precision": "FP32 data path, two-sum compensated grid cells, FP64 phi_hat"},
-        "ms_per_step_with_stage_events": {"fp32": s32_ev * 1e3, "fp64": s64_ev * 1e3},
+        "step_ms": {"mean": s32 * 1e3, "median": pct(spans32, 50), "p99": pct(spans32, 99),
+                    "min": float(min(spans32)),
+                    "kind": "mean: host clock over the timed steps; median/p99/min: HIP event pair "
+                            "recorded on the stream around each of the same number of execs"},
         "fp64_plain": {"value": (M1 + M2) / s64, "unit": "pts/s", "ms_per_step": s64 * 1e3,
-                       "speedup_fp32_over_fp64": s64 / s32},
-        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                       "step_ms_median": pct(spans64, 50), "step_ms_p99": pct(spans64, 99),
+                       "speedup_fp32_over_fp64": s64 / s32,
+                       "kernels": roofline_table(kern64, M1, M2, info64, 16, {})},
+        "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99),
                        "kind": "single exec, submit to completion"},
         "plan_s": {"fp32": t_plan32, "fp64": t_plan64},
     }
-    info32 = P.nnfft_info(p32.handle)
-    out["stages_ms"] = {"fp32": dict(zip(["spread", "fft", "interp"], stages32)),
-                        "fp64": dict(zip(["spread", "fft", "interp"], stages64))}
     out["plan_info"] = {k: info32[k] for k in ["N_star", "N1", "G1", "N2", "fft_n1", "fft_n2",
                                                "spread_workgroups", "interp_workgroups",
                                                "items_points", "block_points", "window_degree",
                                                "window_fit_err", "corr_degree"]}
 
-    # roofline of the slowest FP32 kernel: algorithmic bytes per launch
-    #   spreading:      M1 * (8 B f_k + 4 B offset + 4 B index)
-    #   interpolation:  M2 * (4 B offset + 4 B index + 8 B y_j)
-    #   FFT stage:      G1 * 16 B partial read + N2 * 8 B write (order of)
-    # The dominant kernel is the slower of spreading and interpolation (single
-    # kernels; the FFT stage is two kernels over ~0.3 MB).  Its duration comes
-    # from the library's HIP events at the stage boundaries, which include the
-    # recording of the events themselves (~1-2 us more than the kernel-trace
-    # duration of the same kernel).
-    names = ["spread", "fft", "interp"]
-    kern = {"spread": "k_spread32", "fft": "k_fft_stage", "interp": "k_interp32"}
-    algo = {"spread": 16.0 * M1, "interp": 16.0 * M2, "fft": 16.0 * info32["G1"] + 8.0 * info32["N2"]}
-    dom = max((0, 2), key=lambda i: stages32[i])
-    dname = names[dom]
-    achieved = algo[dname] / (stages32[dom] * 1e-3) / 1e9
-    out["roofline"] = {"bound": "hbm", "kernel": kern[dname], "achieved": achieved, "peak": HBM_PEAK_GBS,
-                       "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                       "traffic": measured_traffic(kern[dname]),
-                       "algorithmic_bytes_per_launch": algo[dname],
-                       "avg_launch_ms": stages32[dom], "launches_timed": n32}
-    out["roofline_all_kernels"] = {names[i]: {"achieved_GBs": algo[names[i]] / (stages32[i] * 1e-3) / 1e9,
-                                              "avg_ms": stages32[i]} for i in range(3)}
+    # roofline: every FP32 kernel's algorithmic bytes per launch over its
+    # average dispatch duration in the timed steps; the dominant kernel (the
+    # longest) is the headline figure
+    kt = roofline_table(kern32, M1, M2, info32, 8, traffic)
+    dom = max(kt, key=lambda k: kt[k]["avg_ms"])
+    d = kt[dom]
+    out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": d["achieved_GBs"], "peak": HBM_PEAK_GBS,
+                       "unit": "GB/s", "frac": d["frac"], "traffic": d["traffic"],
+                       "algorithmic_bytes_per_launch": d["algorithmic_bytes"], "avg_launch_ms": d["avg_ms"],
+                       "launches_timed": args.steps,
+                       "timing": "HIP events attached to each kernel dispatch (hipExtLaunchKernel) over "
+                                 "as many execs as the timed steps, on the exec stream",
+                       "kernels": kt}
 
     if not args.no_accuracy or not args.no_cpu_baseline:
         import oracle
@@ -333,8 +504,19 @@ def main() -> int:
             reps += 1
         out["cpu_baseline"] = {"value": (M1 + M2) * reps / tot, "unit": "pts/s",
                                "cores": oracle.num_threads(), "kind": "oracle",
+                               "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+                               "affinity_cpus": len(os.sched_getaffinity(0)),
                                "sample": f"full workload (M1=M2=2^20, N=4096, m=6), {reps} runs of "
                                          f"the FP64 oracle NNFFT (plan + all steps), {tot:.1f} s"}
+    p32.close()
+    p64.close()
+    del f32, f64, y32, y64, tv, tx
+    if not args.no_sinc:
+        print("[bench] fast sinc transform", file=sys.stderr, flush=True)
+        out["sinc"] = sinc_benchmark(P, W, torch, max(20, args.steps // 4), 5, not args.no_accuracy)
+    if not args.no_clustered:
+        print("[bench] clustered 2^24-node transform", file=sys.stderr, flush=True)
+        out["clustered"] = clustered_benchmark(P, W, torch, 20, 3, not args.no_accuracy, traffic)
     if args.batch_plans > 0:
         print("[bench] batched resident plans", file=sys.stderr, flush=True)
         out["batched"] = batched_benchmark(P, W, torch, args.batch_plans)
@@ -347,8 +529,6 @@ def main() -> int:
         b.copy_(a)
         torch.cuda.synchronize()
         out["calibration_copy_bytes"] = {"read": a.numel() * 4, "write": b.numel() * 4}
-    p32.close()
-    p64.close()
     print(json.dumps(out), flush=True)
     return 0
 

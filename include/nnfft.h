@@ -205,16 +205,34 @@ nnfft_status nnfft_exec_batch(int n, const nnfft_plan_t *plans, const void *cons
 nnfft_status nnfft_info(nnfft_plan_t p, nnfft_info_t *out);
 
 /*
- * Stage timing.  nnfft_profile_start makes the next `max_execs` execs of the
- * plan record HIP events on their stream at the stage boundaries (before
- * spreading, after spreading, after the FFT, after interpolation);
- * nnfft_profile_stop waits for the last of them and returns the average
- * duration in milliseconds of each stage over the recorded execs in
- * stage_ms[0..2] = {spreading, FFT (with merge and deconvolution),
- * interpolation} and their count in *nexecs.  Errors: ARG, NOMEM, DEVICE.
+ * Kernel timing (not part of the transform).  nnfft_profile_start makes the
+ * next `max_execs` nnfft_exec calls on the plan launch each of their kernels
+ * with a pair of HIP events attached to the kernel's dispatch
+ * (hipExtLaunchKernel), so an event pair measures that kernel's execution
+ * on the device, on the stream it runs on, without the gaps between
+ * kernels.  The results are read once, by one of:
+ *   nnfft_profile_stop     average duration (ms) of each stage over the
+ *                          recorded execs in stage_ms[0..2] = {spreading,
+ *                          FFT (with merge and deconvolution: the sum of its
+ *                          kernels), interpolation}; count in *nexecs;
+ *   nnfft_profile_kernels  per kernel in launch order (up to kcap entries,
+ *                          count in *nkernels): name, stage, average,
+ *                          minimum and maximum duration; per exec (up to
+ *                          ecap values in exec_ms) the span from the start
+ *                          of its first kernel to the end of its last; the
+ *                          number of recorded execs in *nexecs.
+ * Both wait for the last recorded exec and release the events; host arrays
+ * are owned by the caller.  Errors: ARG, NOMEM, DEVICE.
  */
+typedef struct {
+    char name[32];     /* kernel name, e.g. "k_spread32" */
+    int stage;         /* 0 spreading, 1 FFT, 2 interpolation */
+    double avg_ms, min_ms, max_ms;
+} nnfft_kernel_time_t;
 nnfft_status nnfft_profile_start(nnfft_plan_t p, int max_execs);
 nnfft_status nnfft_profile_stop(nnfft_plan_t p, double *stage_ms, int *nexecs);
+nnfft_status nnfft_profile_kernels(nnfft_plan_t p, nnfft_kernel_time_t *kernels, int kcap, int *nkernels,
+                                   double *exec_ms, int ecap, int *nexecs);
 nnfft_status nnfft_destroy(nnfft_plan_t p);
 
 /*

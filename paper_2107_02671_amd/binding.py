@@ -105,6 +105,11 @@ class NnfftServerStats(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class NnfftKernelTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("stage", ctypes.c_int), ("avg_ms", ctypes.c_double),
+                ("min_ms", ctypes.c_double), ("max_ms", ctypes.c_double)]
+
+
 class NnfftError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
@@ -150,6 +155,8 @@ def lib():
     L.nnfft_quadrature.argtypes = [ci, i64, dptr, dptr]
     L.nnfft_profile_start.argtypes = [vp, ci]
     L.nnfft_profile_stop.argtypes = [vp, dptr, ctypes.POINTER(ci)]
+    L.nnfft_profile_kernels.argtypes = [vp, ctypes.POINTER(NnfftKernelTime), ci, ctypes.POINTER(ci), dptr, ci,
+                                        ctypes.POINTER(ci)]
     tp = ctypes.POINTER(NnfftTuning)
     L.nnfft_autotune.argtypes = [i64, i64, ci, ci, ci, vp, tp]
     L.nnfft_set_tuning.argtypes = [ci, i64, tp]
@@ -166,7 +173,7 @@ def lib():
     L.nnfft_last_error.restype = ctypes.c_char_p
     L.nnfft_version.restype = ctypes.c_char_p
     for name in ["nfft_plan", "nfft_exec", "nfft_adjoint", "nfft_destroy", "nfft_plan_dry_run",
-                 "nnfft_plan_dry_run", "nnfft_plan_window", "nnfft_plan_window_dry_run", "nnfft_profile_start", "nnfft_profile_stop", "nnfft_quadrature", "nnfft_derive_params",
+                 "nnfft_plan_dry_run", "nnfft_plan_window", "nnfft_plan_window_dry_run", "nnfft_profile_start", "nnfft_profile_stop", "nnfft_profile_kernels", "nnfft_quadrature", "nnfft_derive_params",
                  "nnfft_plan", "nnfft_exec", "nnfft_exec_batch", "nnfft_info", "nnfft_destroy", "sinc_plan",
                  "sinc_exec", "sinc_info", "sinc_sizes", "sinc_destroy", "nnfft_autotune", "nnfft_set_tuning",
                  "nnfft_get_tuning", "nnfft_clear_tuning", "nnfft_server_create", "nnfft_server_submit",
@@ -397,6 +404,18 @@ def nnfft_profile_stop(plan):
     n = ctypes.c_int()
     _check(lib().nnfft_profile_stop(plan, ms, ctypes.byref(n)))
     return (ms[0], ms[1], ms[2]), n.value
+
+
+def nnfft_profile_kernels(plan, max_execs):
+    """Kernel times of the profiled execs: ([{name, stage, avg_ms, min_ms, max_ms}] in launch
+    order, [span of each exec in ms])."""
+    K = (NnfftKernelTime * 8)()
+    E = (ctypes.c_double * max(1, int(max_execs)))()
+    nk, ne = ctypes.c_int(), ctypes.c_int()
+    _check(lib().nnfft_profile_kernels(plan, K, 8, ctypes.byref(nk), E, int(max_execs), ctypes.byref(ne)))
+    kern = [{"name": K[i].name.decode(), "stage": K[i].stage, "avg_ms": K[i].avg_ms, "min_ms": K[i].min_ms,
+             "max_ms": K[i].max_ms} for i in range(nk.value)]
+    return kern, [E[i] for i in range(min(ne.value, int(max_execs)))]
 
 
 def nnfft_destroy(plan):

@@ -139,9 +139,24 @@ struct BatchTable {
     int32_t n;
 };
 
-// Kernel launchers (kernels.hip).  ev: null, or 4 events recorded before
-// spreading, after spreading, after the FFT and after interpolation.
-hipError_t launch_exec(const PlanDev &P, const void *f, void *y, hipStream_t s, hipEvent_t *ev);
+// Kernel timing of one exec: every kernel of the exec is launched with a
+// pair of events attached to its dispatch (hipExtLaunchKernel), so their
+// elapsed time is the kernel's own execution on the device, without the
+// gaps between kernels.  Filled in launch order.
+constexpr int kMaxTimedKernels = 6;
+enum KernelId : int32_t {
+    KID_SPREAD32 = 0, KID_SPREAD64, KID_FFT_SINGLE, KID_FFT_A, KID_FFT_B, KID_INTERP32, KID_INTERP64, KID_COUNT
+};
+struct KernelTimes {
+    hipEvent_t start[kMaxTimedKernels] = {}, stop[kMaxTimedKernels] = {};
+    int32_t kid[kMaxTimedKernels] = {};
+    int32_t n = 0;
+};
+const char *kernel_name(int kid);
+int kernel_stage(int kid);   // 0 spreading, 1 FFT, 2 interpolation
+
+// Kernel launchers (kernels.hip).  kt: null, or the event pairs of this exec.
+hipError_t launch_exec(const PlanDev &P, const void *f, void *y, hipStream_t s, KernelTimes *kt);
 // NFFT plans: forward (in = f_k, out = y_j) or adjoint (in = y_j, out = h_k)
 hipError_t launch_nfft(const PlanDev &P, bool adjoint, const void *in, void *out, hipStream_t s);
 // n plans of one precision: host descriptors (sizes) and their device copies

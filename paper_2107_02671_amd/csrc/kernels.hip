@@ -27,10 +27,44 @@
 //
 // FP64 path (the plain comparator): the same decomposition, windows evaluated
 // exactly per tap with exp/sqrt in FP64, plain FP64 sums.
+#include <hip/hip_ext.h>
+
 #include "internal.h"
 #include "../../include/nnfft.h"
 
 namespace nnfft {
+
+// Launches `kernel`; with a timing record, through hipExtLaunchKernelGGL
+// with the record's next event pair attached to the dispatch.
+template <typename K, typename... Args>
+static void launch_k(KernelTimes *kt, int kid, K kernel, dim3 grid, dim3 block, uint32_t lds, hipStream_t s,
+                     Args... args)
+{
+    if (kt != nullptr && kt->n < kMaxTimedKernels) {
+        hipExtLaunchKernelGGL(kernel, grid, block, lds, s, kt->start[kt->n], kt->stop[kt->n], 0, args...);
+        kt->kid[kt->n++] = kid;
+    } else {
+        hipLaunchKernelGGL(kernel, grid, block, lds, s, args...);
+    }
+}
+
+const char *kernel_name(int kid)
+{
+    static const char *const names[KID_COUNT] = {"k_spread32", "k_spread64", "k_fft_single", "k_fft_stageA",
+                                                 "k_fft_stageB", "k_interp32", "k_interp64"};
+    return kid >= 0 && kid < KID_COUNT ? names[kid] : "?";
+}
+
+int kernel_stage(int kid)
+{
+    switch (kid) {
+    case KID_SPREAD32:
+    case KID_SPREAD64: return 0;
+    case KID_INTERP32:
+    case KID_INTERP64: return 2;
+    default: return 1;
+    }
+}
 
 template <typename T>
 struct alignas(2 * sizeof(T)) cx {
@@ -717,36 +751,39 @@ __global__ __launch_bounds__(kThreads64) void k_interp64(InterpArgs A, cx<double
     interp64_slot<WIN>(A, y, blockIdx.x, L);
 }
 
-static void launch_spread64(const SpreadArgs &A, const void *f, hipStream_t s)
+static void launch_spread64(const SpreadArgs &A, const void *f, hipStream_t s, KernelTimes *kt = nullptr)
 {
     const cx<double> *in = reinterpret_cast<const cx<double> *>(f);
     const size_t lds = lds64_bytes(2 * A.m, A.rows);
     switch (A.window) {
     case NNFFT_WINDOW_BSPLINE:
-        hipLaunchKernelGGL(k_spread64<NNFFT_WINDOW_BSPLINE>, dim3(A.ngrid), dim3(kThreads64), lds, s, A, in);
+        launch_k(kt, KID_SPREAD64, k_spread64<NNFFT_WINDOW_BSPLINE>, dim3(A.ngrid), dim3(kThreads64), lds, s, A, in);
         break;
     case NNFFT_WINDOW_ALGEBRAIC:
-        hipLaunchKernelGGL(k_spread64<NNFFT_WINDOW_ALGEBRAIC>, dim3(A.ngrid), dim3(kThreads64), lds, s, A, in);
+        launch_k(kt, KID_SPREAD64, k_spread64<NNFFT_WINDOW_ALGEBRAIC>, dim3(A.ngrid), dim3(kThreads64), lds, s, A, in);
         break;
     default:
-        hipLaunchKernelGGL(k_spread64<NNFFT_WINDOW_SINH>, dim3(A.ngrid), dim3(kThreads64), lds, s, A, in);
+        launch_k(kt, KID_SPREAD64, k_spread64<NNFFT_WINDOW_SINH>, dim3(A.ngrid), dim3(kThreads64), lds, s, A, in);
         break;
     }
 }
 
-static void launch_interp64(const InterpArgs &A, void *y, hipStream_t s)
+static void launch_interp64(const InterpArgs &A, void *y, hipStream_t s, KernelTimes *kt = nullptr)
 {
     cx<double> *out = reinterpret_cast<cx<double> *>(y);
     const size_t lds = interp64_lds_bytes(2 * A.m);
     switch (A.window) {
     case NNFFT_WINDOW_BSPLINE:
-        hipLaunchKernelGGL(k_interp64<NNFFT_WINDOW_BSPLINE>, dim3(A.ngrid), dim3(kThreads64), lds, s, A, out);
+        launch_k(kt, KID_INTERP64, k_interp64<NNFFT_WINDOW_BSPLINE>, dim3(A.ngrid), dim3(kThreads64), lds, s, A,
+                 out);
         break;
     case NNFFT_WINDOW_ALGEBRAIC:
-        hipLaunchKernelGGL(k_interp64<NNFFT_WINDOW_ALGEBRAIC>, dim3(A.ngrid), dim3(kThreads64), lds, s, A, out);
+        launch_k(kt, KID_INTERP64, k_interp64<NNFFT_WINDOW_ALGEBRAIC>, dim3(A.ngrid), dim3(kThreads64), lds, s, A,
+                 out);
         break;
     default:
-        hipLaunchKernelGGL(k_interp64<NNFFT_WINDOW_SINH>, dim3(A.ngrid), dim3(kThreads64), lds, s, A, out);
+        launch_k(kt, KID_INTERP64, k_interp64<NNFFT_WINDOW_SINH>, dim3(A.ngrid), dim3(kThreads64), lds, s, A,
+                 out);
         break;
     }
 }
@@ -1351,27 +1388,30 @@ static int fft_groups(int ncol, int batch)
 }
 
 template <typename T>
-static void launch_fft(const FftArgs &A, hipStream_t s)
+static void launch_fft(const FftArgs &A, hipStream_t s, KernelTimes *kt = nullptr)
 {
+    const uint32_t lds = (uint32_t)fft_lds_bytes<T>(A);
     if (A.n1 == 1) {
-        hipLaunchKernelGGL((k_fft_single<T>), dim3(1), dim3(A.threadsA), fft_lds_bytes<T>(A), s, A);
+        launch_k(kt, KID_FFT_SINGLE, k_fft_single<T>, dim3(1), dim3(A.threadsA), lds, s, A);
     } else {
         const int gA = fft_groups(A.n1, A.batchA), gB = fft_groups(A.n2, A.batchB);
-        hipLaunchKernelGGL((k_fft_stageA<T>), dim3(gA), dim3(A.threadsA), fft_lds_bytes<T>(A), s, A);
-        hipLaunchKernelGGL((k_fft_stageB<T>), dim3(gB), dim3(A.threadsB), fft_lds_bytes<T>(A), s, A);
+        launch_k(kt, KID_FFT_A, k_fft_stageA<T>, dim3(gA), dim3(A.threadsA), lds, s, A);
+        launch_k(kt, KID_FFT_B, k_fft_stageB<T>, dim3(gB), dim3(A.threadsB), lds, s, A);
     }
 }
 
 // k_interp32 variants: correction degree CD in {8, 10, 12, 16, 24, 32}
-static void launch_interp32(int cd, int grid, hipStream_t s, const InterpArgs &A, cx<float> *y)
+static void launch_interp32(int cd, int grid, hipStream_t s, const InterpArgs &A, cx<float> *y,
+                            KernelTimes *kt = nullptr)
 {
+    const dim3 g(grid), b(kThreads32);
     switch (cd) {
-    case 8: hipLaunchKernelGGL((k_interp32<8>), dim3(grid), dim3(kThreads32), 0, s, A, y); break;
-    case 10: hipLaunchKernelGGL((k_interp32<10>), dim3(grid), dim3(kThreads32), 0, s, A, y); break;
-    case 12: hipLaunchKernelGGL((k_interp32<12>), dim3(grid), dim3(kThreads32), 0, s, A, y); break;
-    case 16: hipLaunchKernelGGL((k_interp32<16>), dim3(grid), dim3(kThreads32), 0, s, A, y); break;
-    case 24: hipLaunchKernelGGL((k_interp32<24>), dim3(grid), dim3(kThreads32), 0, s, A, y); break;
-    default: hipLaunchKernelGGL((k_interp32<32>), dim3(grid), dim3(kThreads32), 0, s, A, y); break;
+    case 8: launch_k(kt, KID_INTERP32, k_interp32<8>, g, b, 0, s, A, y); break;
+    case 10: launch_k(kt, KID_INTERP32, k_interp32<10>, g, b, 0, s, A, y); break;
+    case 12: launch_k(kt, KID_INTERP32, k_interp32<12>, g, b, 0, s, A, y); break;
+    case 16: launch_k(kt, KID_INTERP32, k_interp32<16>, g, b, 0, s, A, y); break;
+    case 24: launch_k(kt, KID_INTERP32, k_interp32<24>, g, b, 0, s, A, y); break;
+    default: launch_k(kt, KID_INTERP32, k_interp32<32>, g, b, 0, s, A, y); break;
     }
 }
 
@@ -1388,14 +1428,16 @@ static void launch_interp32_batch(int cd, int grid, hipStream_t s, const BatchTa
 }
 
 // k_spread32 variants: tap rows TM in {12, 16, 32}, the smallest >= 2m
-static void launch_spread32(const SpreadArgs &A, int grid, const cx<float> *f, hipStream_t s)
+static void launch_spread32(const SpreadArgs &A, int grid, const cx<float> *f, hipStream_t s,
+                            KernelTimes *kt = nullptr)
 {
+    const dim3 g(grid), b(kThreads32);
     if (2 * A.m <= 12)
-        hipLaunchKernelGGL((k_spread32<12>), dim3(grid), dim3(kThreads32), 0, s, A, f);
+        launch_k(kt, KID_SPREAD32, k_spread32<12>, g, b, 0, s, A, f);
     else if (2 * A.m <= 16)
-        hipLaunchKernelGGL((k_spread32<16>), dim3(grid), dim3(kThreads32), 0, s, A, f);
+        launch_k(kt, KID_SPREAD32, k_spread32<16>, g, b, 0, s, A, f);
     else
-        hipLaunchKernelGGL((k_spread32<32>), dim3(grid), dim3(kThreads32), 0, s, A, f);
+        launch_k(kt, KID_SPREAD32, k_spread32<32>, g, b, 0, s, A, f);
 }
 
 // evaluated degree of the 1/phi_hat_1 series: the smallest variant >= deg
@@ -1405,25 +1447,20 @@ static int corr_variant(int deg)
 }
 
 
-hipError_t launch_exec(const PlanDev &P, const void *f, void *y, hipStream_t s, hipEvent_t *ev)
+hipError_t launch_exec(const PlanDev &P, const void *f, void *y, hipStream_t s, KernelTimes *kt)
 {
-    if (ev) (void)hipEventRecord(ev[0], s);
+    if (kt) kt->n = 0;
     if (P.prec == NNFFT_FP32_COMP) {
         const cx<float> *fin = reinterpret_cast<const cx<float> *>(f);
         const int gs = P.sp.ngrid, gi = P.ip.ngrid;
-        launch_spread32(P.sp, gs, fin, s);
-        if (ev) (void)hipEventRecord(ev[1], s);
-        launch_fft<float>(P.fft, s);
-        if (ev) (void)hipEventRecord(ev[2], s);
-        launch_interp32(corr_variant(P.ip.corr_deg), gi, s, P.ip, reinterpret_cast<cx<float> *>(y));
+        launch_spread32(P.sp, gs, fin, s, kt);
+        launch_fft<float>(P.fft, s, kt);
+        launch_interp32(corr_variant(P.ip.corr_deg), gi, s, P.ip, reinterpret_cast<cx<float> *>(y), kt);
     } else {
-        launch_spread64(P.sp, f, s);
-        if (ev) (void)hipEventRecord(ev[1], s);
-        launch_fft<double>(P.fft, s);
-        if (ev) (void)hipEventRecord(ev[2], s);
-        launch_interp64(P.ip, y, s);
+        launch_spread64(P.sp, f, s, kt);
+        launch_fft<double>(P.fft, s, kt);
+        launch_interp64(P.ip, y, s, kt);
     }
-    if (ev) (void)hipEventRecord(ev[3], s);
     return hipGetLastError();
 }
 

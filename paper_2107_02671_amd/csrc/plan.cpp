@@ -1282,9 +1282,12 @@ nnfft_status sinc_create(const SincHostPlan &S, const DevMem &mem, hipStream_t s
 
 void nnfft_plan_s::drop_events()
 {
-    for (hipEvent_t e : prof_ev)
-        if (e) (void)hipEventDestroy(e);
-    prof_ev.clear();
+    for (nnfft::KernelTimes &k : prof)
+        for (int i = 0; i < nnfft::kMaxTimedKernels; ++i) {
+            if (k.start[i]) (void)hipEventDestroy(k.start[i]);
+            if (k.stop[i]) (void)hipEventDestroy(k.stop[i]);
+        }
+    prof.clear();
     prof_max = prof_used = 0;
 }
 
@@ -1401,9 +1404,9 @@ nnfft_status nnfft_exec(nnfft_plan_t p, const void *f, void *y, void *stream)
 {
     if (!p || !f || !y) return fail(NNFFT_ERR_ARG, "null argument");
     if (p->kind != 0) return fail(NNFFT_ERR_ARG, "an NFFT plan: use nfft_exec or nfft_adjoint");
-    hipEvent_t *ev = nullptr;
-    if (p->prof_used < p->prof_max) ev = &p->prof_ev[4 * (size_t)p->prof_used++];
-    const hipError_t e = launch_exec(p->desc, f, y, static_cast<hipStream_t>(stream), ev);
+    KernelTimes *kt = nullptr;
+    if (p->prof_used < p->prof_max) kt = &p->prof[(size_t)p->prof_used++];
+    const hipError_t e = launch_exec(p->desc, f, y, static_cast<hipStream_t>(stream), kt);
     if (e != hipSuccess) return fail(NNFFT_ERR_DEVICE, std::string("launch: ") + hipGetErrorString(e));
     return NNFFT_OK;
 }
@@ -1458,42 +1461,85 @@ nnfft_status nnfft_profile_start(nnfft_plan_t p, int max_execs)
 {
     if (!p || max_execs < 1) return fail(NNFFT_ERR_ARG, "bad argument");
     p->drop_events();
-    p->prof_ev.assign(4 * (size_t)max_execs, nullptr);
-    for (auto &e : p->prof_ev) {
-        if (hipEventCreate(&e) != hipSuccess) {
-            e = nullptr;
-            p->drop_events();
-            return fail(NNFFT_ERR_DEVICE, "hipEventCreate failed");
-        }
+    try {
+        p->prof.assign((size_t)max_execs, KernelTimes{});
+    } catch (const std::bad_alloc &) {
+        return fail(NNFFT_ERR_NOMEM, "host allocation failed");
     }
+    for (KernelTimes &k : p->prof)
+        for (int i = 0; i < kMaxTimedKernels; ++i)
+            if (hipEventCreate(&k.start[i]) != hipSuccess || hipEventCreate(&k.stop[i]) != hipSuccess) {
+                p->drop_events();
+                return fail(NNFFT_ERR_DEVICE, "hipEventCreate failed");
+            }
     p->prof_max = max_execs;
     p->prof_used = 0;
+    return NNFFT_OK;
+}
+
+// Reads the kernel times of the profiled execs (waits for the last one) and
+// releases the events.  Every exec of a plan launches the same kernels.
+static nnfft_status read_profile(nnfft_plan_t p, nnfft_kernel_time_t *kern, int kcap, int *nk, double *exec_ms,
+                                 int ecap, int *nexecs)
+{
+    const int n = p->prof_used;
+    const int nkern = n > 0 ? p->prof[0].n : 0;
+    if (n > 0 && nkern > 0 && hipEventSynchronize(p->prof[(size_t)n - 1].stop[nkern - 1]) != hipSuccess) {
+        p->drop_events();
+        return fail(NNFFT_ERR_DEVICE, "hipEventSynchronize failed");
+    }
+    auto elapsed = [](hipEvent_t a, hipEvent_t b, double *ms) {
+        float f = 0.f;
+        if (hipEventElapsedTime(&f, a, b) != hipSuccess) return false;
+        *ms = f;
+        return true;
+    };
+    for (int k = 0; k < std::min(kcap, nkern); ++k) {
+        nnfft_kernel_time_t &o = kern[k];
+        o = nnfft_kernel_time_t{};
+        std::snprintf(o.name, sizeof o.name, "%s", kernel_name(p->prof[0].kid[k]));
+        o.stage = kernel_stage(p->prof[0].kid[k]);
+        o.min_ms = 1e300;
+        for (int i = 0; i < n; ++i) {
+            double ms = 0.0;
+            if (!elapsed(p->prof[(size_t)i].start[k], p->prof[(size_t)i].stop[k], &ms)) {
+                p->drop_events();
+                return fail(NNFFT_ERR_DEVICE, "hipEventElapsedTime failed");
+            }
+            o.avg_ms += ms / n;
+            o.min_ms = std::min(o.min_ms, ms);
+            o.max_ms = std::max(o.max_ms, ms);
+        }
+    }
+    for (int i = 0; i < std::min(ecap, n); ++i)
+        if (nkern == 0 || !elapsed(p->prof[(size_t)i].start[0], p->prof[(size_t)i].stop[nkern - 1], &exec_ms[i])) {
+            p->drop_events();
+            return fail(NNFFT_ERR_DEVICE, "hipEventElapsedTime failed");
+        }
+    if (nk) *nk = nkern;
+    if (nexecs) *nexecs = n;
+    p->drop_events();
     return NNFFT_OK;
 }
 
 nnfft_status nnfft_profile_stop(nnfft_plan_t p, double *stage_ms, int *nexecs)
 {
     if (!p || !stage_ms) return fail(NNFFT_ERR_ARG, "bad argument");
-    const int n = p->prof_used;
-    double acc[3] = {0.0, 0.0, 0.0};
-    if (n > 0 && hipEventSynchronize(p->prof_ev[4 * (size_t)(n - 1) + 3]) != hipSuccess) {
-        p->drop_events();
-        return fail(NNFFT_ERR_DEVICE, "hipEventSynchronize failed");
-    }
-    for (int i = 0; i < n; ++i)
-        for (int s = 0; s < 3; ++s) {
-            float ms = 0.f;
-            if (hipEventElapsedTime(&ms, p->prof_ev[4 * (size_t)i + s], p->prof_ev[4 * (size_t)i + s + 1]) !=
-                hipSuccess) {
-                p->drop_events();
-                return fail(NNFFT_ERR_DEVICE, "hipEventElapsedTime failed");
-            }
-            acc[s] += ms;
-        }
-    for (int s = 0; s < 3; ++s) stage_ms[s] = n > 0 ? acc[s] / n : 0.0;
-    if (nexecs) *nexecs = n;
-    p->drop_events();
+    nnfft_kernel_time_t k[kMaxTimedKernels];
+    int nk = 0;
+    const nnfft_status st = read_profile(p, k, kMaxTimedKernels, &nk, nullptr, 0, nexecs);
+    if (st != NNFFT_OK) return st;
+    for (int s = 0; s < 3; ++s) stage_ms[s] = 0.0;
+    for (int i = 0; i < nk; ++i) stage_ms[k[i].stage] += k[i].avg_ms;
     return NNFFT_OK;
+}
+
+nnfft_status nnfft_profile_kernels(nnfft_plan_t p, nnfft_kernel_time_t *kernels, int kcap, int *nkernels,
+                                   double *exec_ms, int ecap, int *nexecs)
+{
+    if (!p || kcap < 0 || ecap < 0 || (kcap > 0 && !kernels) || (ecap > 0 && !exec_ms))
+        return fail(NNFFT_ERR_ARG, "bad argument");
+    return read_profile(p, kernels, kcap, nkernels, exec_ms, ecap, nexecs);
 }
 
 nnfft_status nnfft_destroy(nnfft_plan_t p)
