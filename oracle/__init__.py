@@ -53,6 +53,8 @@ def lib():
         L.orc_omega_hat.argtypes = [ctypes.c_double, ctypes.c_double]
         L.orc_omega_hat.restype = ctypes.c_double
         L.orc_sinc_pi.argtypes = [ctypes.c_double]
+        L.orc_i0_minus_1.argtypes = [ctypes.c_double]
+        L.orc_i0_minus_1.restype = ctypes.c_double
         L.orc_sinc_pi.restype = ctypes.c_double
         L.orc_direct.argtypes = [ctypes.c_long, ctypes.c_long, dp, dp, ctypes.c_long, dp, dp]
         L.orc_sinc_direct.argtypes = [ctypes.c_long, ctypes.c_long, dp, dp, ctypes.c_long, dp, dp]
@@ -104,8 +106,11 @@ class Params:
     window: int
 
 
-# window families of Example 2.1
-WIN_SINH, WIN_BSPLINE, WIN_ALGEBRAIC = 0, 1, 2
+# window families of Example 2.1, and the continuous Kaiser-Bessel window
+# (the Kaiser-Bessel family of Example 4.2's comparison runs, in the form that
+# belongs to the set Omega of Sec. 2: (I_0(beta sqrt(1 - x^2)) - 1) / (I_0(beta) - 1),
+# beta = 2 pi m (1 - 1/(2 sigma)))
+WIN_SINH, WIN_BSPLINE, WIN_ALGEBRAIC, WIN_KAISER_BESSEL = 0, 1, 2, 3
 
 
 def params(N, sigma1, sigma2, m1, m2, window=WIN_SINH) -> Params:
@@ -340,8 +345,28 @@ def thm34_constants(kind, m, sigma, beta):
                  C = pi (2 beta)! / (4^beta beta!) (|J_beta| <= 1);
     c2 is the coefficient of |v|^(-mu) and c1 the envelope at |v| =
     m (1 - 1/(2 sigma)), where the interval of the theorem starts (the envelope
-    decreases, so it bounds |omega_hat| on the whole interval)."""
+    decreases, so it bounds |omega_hat| on the whole interval).
+
+    Continuous Kaiser-Bessel (beta = 2 pi m (1 - 1/(2 sigma)), so the interval
+    starts at the branch point |v| = beta / (2 pi)): with K = 2 / (I_0(beta) - 1),
+    b = 2 pi |v| and a = sqrt(b^2 - beta^2),
+      omega_hat(v) = K (sin(a)/a - sin(b)/b),
+    so |omega_hat| <= K (1 + 1/beta) on the interval (|sin t / t| <= 1 and
+    b >= beta) and, beyond it (b >= b0 = beta (2 sigma + 1) / (2 sigma - 1),
+    a >= rho b with rho = sqrt(8 sigma) / (2 sigma + 1)), by the mean value
+    theorem with |d/dt (sin t / t)| <= (1 + 1/t) / t and b - a = beta^2 / (a + b),
+      |omega_hat| <= K beta^2 (1 + 1/(rho b0)) / (rho (1 + rho) b^2):
+    mu = 2, c1 = K (1 + 1/beta), c2 = K beta^2 (1 + 1/(rho b0)) / (4 pi^2 rho (1 + rho))."""
     lo = m * (1.0 - 1.0 / (2.0 * sigma))
+    if kind == WIN_KAISER_BESSEL:
+        if not abs(beta - 2.0 * math.pi * lo) <= 1e-12 * beta:
+            raise ValueError("the Kaiser-Bessel constants need beta = 2 pi m (1 - 1/(2 sigma))")
+        K = 2.0 / float(lib().orc_i0_minus_1(float(beta)))
+        rho = math.sqrt(8.0 * sigma) / (2.0 * sigma + 1.0)
+        b0 = beta * (2.0 * sigma + 1.0) / (2.0 * sigma - 1.0)
+        c1 = K * (1.0 + 1.0 / beta)
+        c2 = K * beta * beta * (1.0 + 1.0 / (rho * b0)) / (4.0 * math.pi ** 2 * rho * (1.0 + rho))
+        return c1, c2, 2.0
     if kind == WIN_BSPLINE:
         b0 = float(bspline_cardinal(2 * m, m))
         c2 = (m / math.pi) ** (2 * m) / (m * b0)
@@ -351,7 +376,8 @@ def thm34_constants(kind, m, sigma, beta):
         c2 = math.exp(lc - beta * math.log(math.pi))
         mu = float(beta)
     else:
-        raise ValueError("Theorem 3.4 constants are given for the B-spline and algebraic windows")
+        raise ValueError("Theorem 3.4 constants are given for the B-spline, algebraic and "
+                         "Kaiser-Bessel windows")
     c1 = c2 * lo ** (-mu)
     return c1, c2, mu
 

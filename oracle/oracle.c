@@ -43,6 +43,8 @@ typedef struct {
 #define ORC_WIN_SINH 0        /* sinh-type, beta = 2 pi m (1 - 1/(2 sigma))       */
 #define ORC_WIN_BSPLINE 1     /* B_{2m}(m x) / B_{2m}(0)                           */
 #define ORC_WIN_ALGEBRAIC 2   /* (1 - x^2)^(beta - 1/2), beta = 3m, sigma > pi/3   */
+#define ORC_WIN_KAISER_BESSEL 3 /* (I_0(beta sqrt(1 - x^2)) - 1) / (I_0(beta) - 1),
+                                   beta = 2 pi m (1 - 1/(2 sigma))                   */
 
 double orc_sinc_pi(double d);
 double orc_window(int kind, double x, int m, double beta);
@@ -110,7 +112,8 @@ int orc_params(long N, double sigma1, double sigma2, int m1, int m2, orc_params_
 /*
  * The same sizes for the windows of family `window` (Example 2.1): the
  * B-spline windows have no shape parameter (beta = 0); the algebraic windows
- * take beta_j = 3 m_j and need sigma_j > pi/3.
+ * take beta_j = 3 m_j and need sigma_j > pi/3; the continuous Kaiser-Bessel
+ * windows take the sinh windows' beta_j.
  */
 int orc_params_window(long N, double sigma1, double sigma2, int m1, int m2, int window, orc_params_t *p)
 {
@@ -121,7 +124,7 @@ int orc_params_window(long N, double sigma1, double sigma2, int m1, int m2, int 
         if (!(p->sigma1_eff > ORC_PI / 3.0) || !(p->sigma2_eff > ORC_PI / 3.0)) return 1;
         p->beta1 = 3.0 * m1;
         p->beta2 = 3.0 * m2;
-    } else if (window != ORC_WIN_SINH) {
+    } else if (window != ORC_WIN_SINH && window != ORC_WIN_KAISER_BESSEL) {
         return 1;
     }
     p->window = window;
@@ -240,11 +243,52 @@ static double orc_omega_hat_algebraic(double v, double beta)
     return (double)sum;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Continuous Kaiser-Bessel window (the Kaiser-Bessel family of the paper's   */
+/* comparison runs, Example 4.2, in the form that belongs to Omega)          */
+/* ------------------------------------------------------------------------ */
+
+/* I_0(z) - 1 = sum_{k >= 1} (z^2/4)^k / (k!)^2: the power series of the
+ * modified Bessel function without its constant term (all terms positive). */
+double orc_i0_minus_1(double z)
+{
+    double q = 0.25 * z * z, term = 1.0, sum = 0.0;
+    for (int k = 1; k < 2000; k++) {
+        term *= q / ((double)k * (double)k);
+        sum += term;
+        if (term <= 1e-18 * sum && (double)k > sqrt(q)) break;
+    }
+    return sum;
+}
+
+/* omega_KB(x) = (I_0(beta sqrt(1 - x^2)) - 1) / (I_0(beta) - 1) on [-1, 1]:
+ * even, 1 at 0, decreasing on [0, 1], 0 at +-1 (continuous). */
+static double orc_omega_kb(double x, double beta)
+{
+    if (fabs(x) >= 1.0) return 0.0;
+    return orc_i0_minus_1(beta * sqrt((1.0 - x) * (1.0 + x))) / orc_i0_minus_1(beta);
+}
+
+/* Its Fourier transform.  int_{-1}^{1} I_0(beta sqrt(1 - x^2)) e^{-2 pi i v x} dx
+ * = 2 sinh(sqrt(y)) / sqrt(y), y = beta^2 - 4 pi^2 v^2 (2 sin(sqrt(-y)) / sqrt(-y)
+ * for y < 0, 2 at y = 0), and the constant 1 on [-1, 1] transforms to
+ * 2 sin(2 pi v) / (2 pi v), so
+ *   omega_KB_hat(v) = 2 / (I_0(beta) - 1) [sinh(sqrt(y))/sqrt(y) - sinc(2 pi v)]. */
+static double orc_omega_hat_kb(double v, double beta)
+{
+    double y = beta * beta - 4.0 * ORC_PI * ORC_PI * v * v, s;
+    if (y > 1e-8) s = sinh(sqrt(y)) / sqrt(y);
+    else if (y < -1e-8) s = sin(sqrt(-y)) / sqrt(-y);
+    else s = 1.0 + y / 6.0;
+    return 2.0 / orc_i0_minus_1(beta) * (s - orc_sinc_pi(2.0 * v));
+}
+
 /* The window omega of family `kind` (sinh uses beta, B-spline m, algebraic beta). */
 double orc_window(int kind, double x, int m, double beta)
 {
     if (kind == ORC_WIN_BSPLINE) return orc_omega_bspline(x, m);
     if (kind == ORC_WIN_ALGEBRAIC) return orc_omega_algebraic(x, beta);
+    if (kind == ORC_WIN_KAISER_BESSEL) return orc_omega_kb(x, beta);
     return orc_omega(x, beta);
 }
 
@@ -253,6 +297,7 @@ double orc_window_hat(int kind, double v, int m, double beta)
 {
     if (kind == ORC_WIN_BSPLINE) return orc_omega_hat_bspline(v, m);
     if (kind == ORC_WIN_ALGEBRAIC) return orc_omega_hat_algebraic(v, beta);
+    if (kind == ORC_WIN_KAISER_BESSEL) return orc_omega_hat_kb(v, beta);
     return orc_omega_hat(v, beta);
 }
 

@@ -576,14 +576,18 @@ def test_bspline_central_values():
 
 @pytest.mark.parametrize("kind,m", [(oracle.WIN_BSPLINE, 3), (oracle.WIN_BSPLINE, 8),
                                     (oracle.WIN_ALGEBRAIC, 2), (oracle.WIN_ALGEBRAIC, 6),
-                                    (oracle.WIN_ALGEBRAIC, 12)])
+                                    (oracle.WIN_ALGEBRAIC, 12), (oracle.WIN_KAISER_BESSEL, 2),
+                                    (oracle.WIN_KAISER_BESSEL, 6), (oracle.WIN_KAISER_BESSEL, 12)])
 def test_window_transforms_against_quadrature(kind, m):
-    beta = 3.0 * m if kind == oracle.WIN_ALGEBRAIC else 0.0
+    beta = {oracle.WIN_ALGEBRAIC: 3.0 * m, oracle.WIN_KAISER_BESSEL: 1.5 * math.pi * m}.get(kind, 0.0)
     w = lambda x: float(oracle.window(kind, x, m, beta))
     assert w(0.0) == pytest.approx(1.0, abs=1e-15)
     assert w(1.0) == 0.0 and w(-1.0) == 0.0
     assert w(0.37) == pytest.approx(w(-0.37), abs=1e-15)
-    for v in (0.0, 0.25, 0.9, m / 2.5, m / 2.0):
+    # (Kaiser-Bessel at v = m/2, where the transform is 1e-6 of the integrand's
+    # scale, is beyond quad's absolute accuracy: the mpmath pin below covers it)
+    vs = (0.0, 0.25, 0.9, m / 2.5) + (() if kind == oracle.WIN_KAISER_BESSEL else (m / 2.0,))
+    for v in vs:
         ref, _ = scipy.integrate.quad(lambda x: 2.0 * w(x) * math.cos(2 * math.pi * v * x), 0, 1,
                                       epsabs=1e-16, epsrel=1e-13, limit=400)
         got = float(oracle.window_hat(kind, v, m, beta))
@@ -603,6 +607,40 @@ def test_algebraic_transform_against_scipy_bessel(m):
         assert float(oracle.window_hat(oracle.WIN_ALGEBRAIC, v, m, beta)) == pytest.approx(ref, rel=1e-11)
 
 
+@pytest.mark.parametrize("m,sigma", [(2, 1.25), (4, 2.0), (6, 1.5), (12, 2.0), (16, 2.0)])
+def test_kaiser_bessel_window_closed_form(m, sigma):
+    # (I_0(beta sqrt(1 - x^2)) - 1) / (I_0(beta) - 1) with scipy's i0; in the
+    # set Omega: even, 1 at 0, 0 at +-1, decreasing on [0, 1]
+    import scipy.special as sp
+    beta = 2 * math.pi * m * (1 - 1 / (2 * sigma))
+    xs = np.linspace(0.0, 0.999, 300)
+    got = oracle.window(oracle.WIN_KAISER_BESSEL, xs, m, beta)
+    ref = (sp.i0(beta * np.sqrt(1 - xs * xs)) - 1) / (sp.i0(beta) - 1)
+    assert np.abs(got - ref).max() <= 1e-13
+    assert np.all(np.diff(got) < 0)
+    assert float(oracle.window(oracle.WIN_KAISER_BESSEL, 1.0, m, beta)) == 0.0
+    assert float(oracle.window(oracle.WIN_KAISER_BESSEL, -0.3, m, beta)) == float(
+        oracle.window(oracle.WIN_KAISER_BESSEL, 0.3, m, beta))
+    # near the support ends the window vanishes like (beta^2/4)(1 - x^2) / (I_0(beta) - 1)
+    x = 1 - 1e-9
+    lead = beta * beta / 4 * (1 - x * x) / (sp.i0(beta) - 1)
+    assert float(oracle.window(oracle.WIN_KAISER_BESSEL, x, m, beta)) == pytest.approx(lead, rel=1e-6)
+
+
+@pytest.mark.parametrize("m,v", [(2, 1.6), (2, 5.3), (6, 4.6), (6, 9.25), (6, 40.1), (12, 6.0)])
+def test_kaiser_bessel_transform_past_the_branch_point(m, v):
+    # beyond |v| = beta / (2 pi) the transform is the sin branch, small and
+    # oscillating: checked against 30-digit quadrature of the window (mpmath)
+    import mpmath as mp
+    mp.mp.dps = 30
+    beta = 1.5 * math.pi * m            # sigma = 2
+    i0b = mp.besseli(0, beta) - 1
+    w = lambda x: (mp.besseli(0, beta * mp.sqrt(1 - x * x)) - 1) / i0b
+    ref = 2 * mp.quad(lambda x: w(x) * mp.cos(2 * mp.pi * v * x), mp.linspace(0, 1, 40))
+    got = float(oracle.window_hat(oracle.WIN_KAISER_BESSEL, v, m, beta))
+    assert abs(got - float(ref)) <= 1e-12 * abs(float(ref)) + 1e-300, (got, float(ref))
+
+
 def test_bspline_transform_is_a_power_of_sinc():
     for m in (2, 4, 7):
         b0 = float(oracle.bspline_cardinal(2 * m, m))
@@ -619,13 +657,17 @@ def test_window_family_parameters():
     assert oracle.params(100, 2.0, 2.0, 5, 7, oracle.WIN_BSPLINE).N2 == S.N2
     with pytest.raises(ValueError):      # the algebraic window needs sigma > pi/3
         oracle.params(100, 1.02, 2.0, 5, 5, oracle.WIN_ALGEBRAIC)
+    K = oracle.params(100, 2.0, 1.5, 5, 7, oracle.WIN_KAISER_BESSEL)   # the sinh windows' beta
+    S = oracle.params(100, 2.0, 1.5, 5, 7)
+    assert (K.beta1, K.beta2, K.N2, K.window) == (S.beta1, S.beta2, S.N2, oracle.WIN_KAISER_BESSEL)
 
 
-@pytest.mark.parametrize("kind", [oracle.WIN_BSPLINE, oracle.WIN_ALGEBRAIC])
+@pytest.mark.parametrize("kind", [oracle.WIN_BSPLINE, oracle.WIN_ALGEBRAIC, oracle.WIN_KAISER_BESSEL])
 @pytest.mark.parametrize("sigma", [1.5, 2.0])
 def test_nnfft_other_windows_against_direct_sum(kind, sigma):
     # Theorem 3.5 with Theorem 3.4's constants bounds the error; the error
-    # decays geometrically in m and reaches 1e-9 at m = 12
+    # decays geometrically in m and reaches 1e-9 at m = 12 (the Kaiser-Bessel
+    # window at m = 6, and FP64 rounding, ~1e-14 of sum |f|, from m = 8 on)
     g = _rng(71)
     N, M1, M2 = 128, 700, 500
     v, x = g.uniform(-0.5, 0.5, M1), g.uniform(-0.5, 0.5, M2)
@@ -633,7 +675,8 @@ def test_nnfft_other_windows_against_direct_sum(kind, sigma):
     ex = oracle.direct(N, v, f, x)
     sf = np.abs(f).sum()
     errs = []
-    for m in (4, 6, 8, 10, 12):
+    ms = (2, 4, 6) if kind == oracle.WIN_KAISER_BESSEL else (4, 6, 8, 10, 12)
+    for m in ms:
         y = oracle.nnfft(N, v, f, x, sigma, sigma, m, m, window=kind)
         e = np.abs(y - ex).max() / sf
         assert e <= oracle.bound_thm35(kind, N, sigma, sigma, m, m)
@@ -641,3 +684,22 @@ def test_nnfft_other_windows_against_direct_sum(kind, sigma):
     for a, b in zip(errs, errs[1:]):
         assert b < a / 3            # each step of 2 in m gains at least a factor 3
     assert errs[-1] < 1e-8
+    if kind == oracle.WIN_KAISER_BESSEL:
+        for m in (10, 12):
+            y = oracle.nnfft(N, v, f, x, sigma, sigma, m, m, window=kind)
+            assert np.abs(y - ex).max() / sf <= max(oracle.bound_thm35(kind, N, sigma, sigma, m, m), 2e-13)
+
+
+@pytest.mark.parametrize("sigma,m", [(1.25, 4), (1.5, 6), (2.0, 4), (2.0, 8)])
+def test_nnfft_kaiser_bessel_tracks_the_sinh_window(sigma, m):
+    # the two windows are close relatives (both ~ exp(beta (sqrt(1 - x^2) - 1))
+    # in the bulk, same beta): their NNFFT errors at the sizes of Example 4.2
+    # agree within a factor 10
+    g = _rng(73)
+    N, M1, M2 = 1200, 2400, 1600
+    v, x = g.uniform(-0.5, 0.5, M1), g.uniform(-0.5, 0.5, M2)
+    f = g.standard_normal(M1) + 1j * g.standard_normal(M1)
+    ex = oracle.direct(N, v, f, x)
+    ek = np.abs(oracle.nnfft(N, v, f, x, sigma, sigma, m, m, window=oracle.WIN_KAISER_BESSEL) - ex).max()
+    es = np.abs(oracle.nnfft(N, v, f, x, sigma, sigma, m, m) - ex).max()
+    assert es / 10 <= ek <= es * 10, (ek, es)
