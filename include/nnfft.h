@@ -83,12 +83,18 @@ typedef enum {
  *              transform sinc(pi v / m)^(2m) / (m B_2m(0));
  *   ALGEBRAIC  (1 - x^2)^(beta - 1/2) on [-1, 1], beta_j = 3 m_j, transform
  *              pi (2 beta)! / (4^beta beta!) (pi v)^(-beta) J_beta(2 pi v); needs
- *              sigma_j > pi/3.
+ *              sigma_j > pi/3;
+ * and the Kaiser-Bessel family of the comparison runs of Example 4.2, in its
+ * continuous form, which belongs to the set Omega of Sec. 2:
+ *   KAISER_BESSEL  (I_0(beta sqrt(1 - x^2)) - 1) / (I_0(beta) - 1) on [-1, 1],
+ *              beta_j as for SINH, transform 2 / (I_0(beta) - 1) [sinh(z)/z -
+ *              sin(2 pi v)/(2 pi v)], z = sqrt(beta^2 - 4 pi^2 v^2).
  */
 typedef enum {
     NNFFT_WINDOW_SINH = 0,
     NNFFT_WINDOW_BSPLINE = 1,
-    NNFFT_WINDOW_ALGEBRAIC = 2
+    NNFFT_WINDOW_ALGEBRAIC = 2,
+    NNFFT_WINDOW_KAISER_BESSEL = 3
 } nnfft_window;
 
 /* Derived sizes and diagnostics of a plan (host struct, filled by the library). */

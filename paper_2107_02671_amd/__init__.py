@@ -13,7 +13,8 @@ from .binding import (NNFFT_FP32_COMP, NNFFT_FP64_PLAIN, SINC_QUAD_CLENSHAW_CURT
                       sinc_destroy, sinc_exec, sinc_info, sinc_plan, sinc_sizes, nnfft_autotune, nnfft_set_tuning,
                       nnfft_get_tuning, nnfft_clear_tuning, Server, NNFFT_REQ_NNFFT, NNFFT_REQ_SINC,
                       NfftPlan, nfft_plan, nfft_exec, nfft_adjoint, nfft_destroy, nfft_plan_dry_run,
-                      NNFFT_WINDOW_SINH, NNFFT_WINDOW_BSPLINE, NNFFT_WINDOW_ALGEBRAIC)
+                      NNFFT_WINDOW_SINH, NNFFT_WINDOW_BSPLINE, NNFFT_WINDOW_ALGEBRAIC,
+                      NNFFT_WINDOW_KAISER_BESSEL)
 
 __all__ = ["binding", "Plan", "SincPlan", "NnfftError", "nnfft_plan", "nnfft_exec", "nnfft_exec_batch",
            "nnfft_info", "nnfft_destroy", "nnfft_profile_start", "nnfft_profile_stop", "nnfft_profile_kernels", "nnfft_derive_params", "nnfft_last_error", "nnfft_quadrature", "nnfft_version",
@@ -21,4 +22,5 @@ __all__ = ["binding", "Plan", "SincPlan", "NnfftError", "nnfft_plan", "nnfft_exe
            "SINC_QUAD_GAUSS_LEGENDRE", "SINC_QUAD_CLENSHAW_CURTIS", "nnfft_autotune", "nnfft_set_tuning",
            "nnfft_get_tuning", "nnfft_clear_tuning", "Server", "NNFFT_REQ_NNFFT", "NNFFT_REQ_SINC",
            "NfftPlan", "nfft_plan", "nfft_exec", "nfft_adjoint", "nfft_destroy", "nfft_plan_dry_run",
-           "NNFFT_WINDOW_SINH", "NNFFT_WINDOW_BSPLINE", "NNFFT_WINDOW_ALGEBRAIC"]
+           "NNFFT_WINDOW_SINH", "NNFFT_WINDOW_BSPLINE", "NNFFT_WINDOW_ALGEBRAIC",
+           "NNFFT_WINDOW_KAISER_BESSEL"]

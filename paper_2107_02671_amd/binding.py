@@ -31,7 +31,7 @@ NNFFT_FP64_PLAIN = 0
 NNFFT_FP32_COMP = 1
 SINC_QUAD_GAUSS_LEGENDRE = 0
 SINC_QUAD_CLENSHAW_CURTIS = 1
-NNFFT_WINDOW_SINH, NNFFT_WINDOW_BSPLINE, NNFFT_WINDOW_ALGEBRAIC = 0, 1, 2
+NNFFT_WINDOW_SINH, NNFFT_WINDOW_BSPLINE, NNFFT_WINDOW_ALGEBRAIC, NNFFT_WINDOW_KAISER_BESSEL = 0, 1, 2, 3
 
 
 class NnfftInfo(ctypes.Structure):

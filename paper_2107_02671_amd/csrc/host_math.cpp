@@ -126,6 +126,18 @@ double window_sinh_hat(double v, double beta)
     return pre * ::j1(z) / z;
 }
 
+// I_0(z) - 1 = sum_{k >= 1} q^k / (k!)^2, q = z^2 / 4, nested from the last
+// kept term down: q (1 + q/2^2 (1 + q/3^2 (1 + ...))).  The terms peak near
+// k = sqrt(q); past k = 30 + 3 sqrt(q) the tail is below 1e-18 of the sum.
+static double bessel_i0_minus_1(double z)
+{
+    const double q = 0.25 * z * z;
+    const int K = 30 + (int)(3.0 * std::sqrt(q));
+    double acc = 1.0;
+    for (int k = K; k >= 2; --k) acc = 1.0 + acc * q / ((double)k * (double)k);
+    return q * acc;
+}
+
 // ---------------------------------------------------------------------------
 // Chebyshev fits
 // ---------------------------------------------------------------------------
@@ -203,6 +215,10 @@ double window_value(const Window &w, double u)
         const double q = (1.0 - u) * (1.0 + u);
         return q > 0.0 ? std::pow(q, w.beta - 0.5) : 0.0;
     }
+    case NNFFT_WINDOW_KAISER_BESSEL: {
+        const double q = (1.0 - u) * (1.0 + u);
+        return q > 0.0 ? bessel_i0_minus_1(w.beta * std::sqrt(q)) / bessel_i0_minus_1(w.beta) : 0.0;
+    }
     default:
         return window_sinh(u, w.beta);
     }
@@ -233,9 +249,34 @@ static double bessel_ratio(double b, double v)
     return ::jn((int)b, 2.0 * a) * std::exp(-b * std::log(a));
 }
 
+std::vector<double> kaiser_bessel_series(double beta)
+{
+    const double q = 0.25 * beta * beta, den = bessel_i0_minus_1(beta);
+    std::vector<double> t;
+    double term = 1.0 / den, sum = 0.0;
+    for (int k = 1; k <= 1000; ++k) {
+        term *= q / ((double)k * (double)k);
+        t.push_back(term);
+        sum += term;
+        if ((double)k > std::sqrt(q) && term < 1e-18 * sum) break;
+    }
+    return t;
+}
+
 double window_hat(const Window &w, double v)
 {
     switch (w.kind) {
+    case NNFFT_WINDOW_KAISER_BESSEL: {
+        // 2 / (I_0(beta) - 1) [sinh(z)/z - sin(2 pi v)/(2 pi v)], z^2 = beta^2 - 4 pi^2 v^2
+        const double y = w.beta * w.beta - 4.0 * kPi * kPi * v * v;
+        double s;
+        if (y > 1e-8) s = std::sinh(std::sqrt(y)) / std::sqrt(y);
+        else if (y < -1e-8) s = std::sin(std::sqrt(-y)) / std::sqrt(-y);
+        else s = 1.0 + y / 6.0;
+        const double a = 2.0 * kPi * v;
+        const double c = std::fabs(a) < 1e-8 ? 1.0 - a * a / 6.0 : std::sin(a) / a;
+        return 2.0 / bessel_i0_minus_1(w.beta) * (s - c);
+    }
     case NNFFT_WINDOW_BSPLINE: {
         // sinc(pi v / m)^(2m) / (m B_2m(0))
         const double t = kPi * v / w.m;

@@ -40,6 +40,12 @@ double window_value(const Window &w, double u);
 // Its Fourier transform for |v| <= m/2 (the algorithm needs |v| <= m/(2 sigma)).
 double window_hat(const Window &w, double v);
 
+// Continuous Kaiser-Bessel window as a power series in s = 1 - u^2:
+// omega(u) = sum_{k >= 1} t_k s^k, t_k = (beta^2/4)^k / ((k!)^2 (I_0(beta) - 1));
+// returns t_1 .. t_K with the tail past K below 1e-18 of the sum (the FP64
+// kernels evaluate it by Horner's rule).
+std::vector<double> kaiser_bessel_series(double beta);
+
 // Tap r (0 <= r < 2m) of a point at fractional offset x in [0, 1) of its cell
 // carries the weight omega((r - m + 1 - x) / m); as a function of t = 2x - 1
 // it is fitted by a degree-`deg` Chebyshev series (FP32 path: degree kDeg;

@@ -58,13 +58,15 @@ struct SpreadArgs {
     const double *wts;        // null, or [M] weights the coefficients are multiplied
                               // by as they are loaded (set per exec)
     const float *C;           // FP32 path: [2m][kDeg + 1] tap coefficients
-    const double *T64;        // FP64 path, B-spline windows: [2m][2m] exact tap series
+    const double *T64;        // FP64 path, B-spline windows: [2m][2m] exact tap series;
+                              // Kaiser-Bessel windows: [nser] power series in 1 - u^2
     void *partial;            // chunk windows: float4 (hi, lo) or double2
     double beta, inv_den;     // FP64 path window: beta, 1 / (1 - exp(-2 beta)) (sinh)
     int32_t m, ngrid;
     int32_t rows;             // FP32 path: record rows per slot (max points per item)
     int32_t window;           // nnfft_window
     int32_t slotT, slotP;     // plane cell c at slot (c mod T) P + c div T
+    int32_t nser;             // FP64 path, Kaiser-Bessel windows: terms of T64
 };
 
 // Steps 2-3 (merge, 1/phi_hat_2, FFT) arguments of one plan.
@@ -105,7 +107,8 @@ struct InterpArgs {
     const int32_t *perm;
     const double *frac64;
     const float *C;           // FP32 path: [2m][kDeg + 1] tap coefficients
-    const double *T64;        // FP64 path, B-spline windows: [2m][2m] exact tap series
+    const double *T64;        // FP64 path, B-spline windows: [2m][2m] exact tap series;
+                              // Kaiser-Bessel windows: [nser] power series in 1 - u^2
     const double *corr;       // series of 1/phi_hat_1 in t = 8 x^2 - 1 (FP32: kCorr32 + 1 terms)
     const void *hlin;
     double beta, inv_den;
@@ -116,6 +119,7 @@ struct InterpArgs {
     int32_t rows;             // FP32 path: record rows per slot
     int32_t h_off;            // hlin index of label 0
     int32_t window;           // nnfft_window
+    int32_t nser;             // FP64 path, Kaiser-Bessel windows: terms of T64
 };
 
 struct PlanDev {

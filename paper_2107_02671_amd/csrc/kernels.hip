@@ -174,12 +174,21 @@ __device__ __forceinline__ double cheb64(const double *__restrict__ c, int deg, 
 //   sinh       exp form above;
 //   B-spline   tap r is one polynomial piece of degree 2m - 1 in x, stored as
 //              its exact Chebyshev series in 2x - 1 (T: [2m][2m]);
-//   algebraic  (1 - u^2)^(beta - 1/2) = q^(beta - 1) sqrt(q), beta = 3m integer.
+//   algebraic  (1 - u^2)^(beta - 1/2) = q^(beta - 1) sqrt(q), beta = 3m integer;
+//   Kaiser-Bessel  (I_0(beta sqrt(q)) - 1) / (I_0(beta) - 1) = sum_k T[k] q^(k+1),
+//              q = 1 - u^2, by Horner's rule (nser positive terms).
 template <int WIN>
 __device__ __forceinline__ double tap64(const double *__restrict__ T, int r, int m, double x, double u, double beta,
-                                        double inv_den)
+                                        double inv_den, int nser)
 {
     if constexpr (WIN == NNFFT_WINDOW_BSPLINE) return cheb64(T + r * 2 * m, 2 * m - 1, fma(2.0, x, -1.0));
+    if constexpr (WIN == NNFFT_WINDOW_KAISER_BESSEL) {
+        const double q = (1.0 - u) * (1.0 + u);
+        if (!(q > 0.0)) return 0.0;
+        double acc = T[nser - 1];
+        for (int k = nser - 2; k >= 0; --k) acc = fma(acc, q, T[k]);
+        return acc * q;
+    }
     if constexpr (WIN == NNFFT_WINDOW_ALGEBRAIC) {
         const double q = (1.0 - u) * (1.0 + u);
         if (!(q > 0.0)) return 0.0;
@@ -521,7 +530,7 @@ __device__ void spread64_slot(const SpreadArgs &A, const cx<double> *__restrict_
                 const double xq = L.pf[q * kItemsPerWg + t];
                 const cx<double> fq = L.pv[q * kItemsPerWg + t];
                 const double w = tap64<WIN>(A.T64, r, m, xq, ((double)(r - m + 1) - xq) * inv_m, A.beta,
-                                            A.inv_den);
+                                            A.inv_den, A.nser);
                 ar = fma(fq.re, w, ar);
                 ai = fma(fq.im, w, ai);
             }
@@ -732,7 +741,7 @@ __device__ void interp64_slot(const InterpArgs &A, cx<double> *__restrict__ y, i
             double sr = 0.0, si = 0.0;
             for (int r = 0; r < tm; ++r) {
                 const double w = tap64<WIN>(A.T64, r, m, fr, (fr + (double)(m - 1 - r)) * inv_m, A.beta,
-                                            A.inv_den);
+                                            A.inv_den, A.nser);
                 const cx<double> hv = L.hw[b + r];
                 sr = fma(hv.re, w, sr);
                 si = fma(hv.im, w, si);
@@ -762,6 +771,10 @@ static void launch_spread64(const SpreadArgs &A, const void *f, hipStream_t s, K
     case NNFFT_WINDOW_ALGEBRAIC:
         launch_k(kt, KID_SPREAD64, k_spread64<NNFFT_WINDOW_ALGEBRAIC>, dim3(A.ngrid), dim3(kThreads64), lds, s, A, in);
         break;
+    case NNFFT_WINDOW_KAISER_BESSEL:
+        launch_k(kt, KID_SPREAD64, k_spread64<NNFFT_WINDOW_KAISER_BESSEL>, dim3(A.ngrid), dim3(kThreads64), lds, s,
+                 A, in);
+        break;
     default:
         launch_k(kt, KID_SPREAD64, k_spread64<NNFFT_WINDOW_SINH>, dim3(A.ngrid), dim3(kThreads64), lds, s, A, in);
         break;
@@ -780,6 +793,10 @@ static void launch_interp64(const InterpArgs &A, void *y, hipStream_t s, KernelT
     case NNFFT_WINDOW_ALGEBRAIC:
         launch_k(kt, KID_INTERP64, k_interp64<NNFFT_WINDOW_ALGEBRAIC>, dim3(A.ngrid), dim3(kThreads64), lds, s, A,
                  out);
+        break;
+    case NNFFT_WINDOW_KAISER_BESSEL:
+        launch_k(kt, KID_INTERP64, k_interp64<NNFFT_WINDOW_KAISER_BESSEL>, dim3(A.ngrid), dim3(kThreads64), lds, s,
+                 A, out);
         break;
     default:
         launch_k(kt, KID_INTERP64, k_interp64<NNFFT_WINDOW_SINH>, dim3(A.ngrid), dim3(kThreads64), lds, s, A,
@@ -1323,6 +1340,8 @@ __global__ __launch_bounds__(kThreads64) void k_spread64_batch(BatchTable T)
         spread64_slot<NNFFT_WINDOW_BSPLINE>(A, in, g, L);
     else if (A.window == NNFFT_WINDOW_ALGEBRAIC)
         spread64_slot<NNFFT_WINDOW_ALGEBRAIC>(A, in, g, L);
+    else if (A.window == NNFFT_WINDOW_KAISER_BESSEL)
+        spread64_slot<NNFFT_WINDOW_KAISER_BESSEL>(A, in, g, L);
     else
         spread64_slot<NNFFT_WINDOW_SINH>(A, in, g, L);
 }
@@ -1350,6 +1369,8 @@ __global__ __launch_bounds__(kThreads64) void k_interp64_batch(BatchTable T)
         interp64_slot<NNFFT_WINDOW_BSPLINE>(A, out, g, L);
     else if (A.window == NNFFT_WINDOW_ALGEBRAIC)
         interp64_slot<NNFFT_WINDOW_ALGEBRAIC>(A, out, g, L);
+    else if (A.window == NNFFT_WINDOW_KAISER_BESSEL)
+        interp64_slot<NNFFT_WINDOW_KAISER_BESSEL>(A, out, g, L);
     else
         interp64_slot<NNFFT_WINDOW_SINH>(A, out, g, L);
 }

@@ -621,6 +621,8 @@ void layout_plan(const HostPlan &H, Carver &C, PlanDev &D, size_t *upload_end, P
         if (!H.T1.empty()) {
             SA.T64 = C.put(H.T1);
             IA.T64 = C.put(H.T2);
+            SA.nser = (int32_t)H.T1.size();
+            IA.nser = (int32_t)H.T2.size();
         }
     }
     FA.merge_off = C.put(H.moff);
@@ -836,7 +838,7 @@ nnfft_status plan_host(HostPlan &H, int64_t N, int64_t M1, int64_t M2, double si
             return fail(NNFFT_ERR_ARG, "the algebraic window needs sigma > pi/3");
         P.beta1 = 3.0 * m1;
         P.beta2 = 3.0 * m2;
-    } else if (window != NNFFT_WINDOW_SINH) {
+    } else if (window != NNFFT_WINDOW_SINH && window != NNFFT_WINDOW_KAISER_BESSEL) {
         return fail(NNFFT_ERR_ARG, "unknown window family");
     }
     if (window != NNFFT_WINDOW_SINH) {
@@ -882,6 +884,10 @@ nnfft_status plan_host(HostPlan &H, int64_t N, int64_t M1, int64_t M2, double si
         H.T2 = fit_window_taps(make_window(window, m2, 0.0), 2 * m2 - 1, &t2);
         if (std::max(t1, t2) > 1e-14)
             return fail(NNFFT_ERR_UNSUPPORTED, "B-spline tap series inexact");
+    } else if (window == NNFFT_WINDOW_KAISER_BESSEL) {
+        // the window's power series in 1 - u^2, evaluated per tap
+        H.T1 = kaiser_bessel_series(P.beta1);
+        H.T2 = kaiser_bessel_series(P.beta2);
     }
     double corr_err = 0.0;
     H.corr = fit_inverse_phi1(P, fp32 ? 1e-9 : 1e-14, fp32 ? kCorr32 : kMaxCorrDeg, &corr_err);

@@ -178,11 +178,12 @@ def test_nfft_dry_run_errors():
     assert e.value.status == binding.NNFFT_ERR_UNSUPPORTED
 
 
-@pytest.mark.parametrize("window", [P.NNFFT_WINDOW_BSPLINE, P.NNFFT_WINDOW_ALGEBRAIC])
+@pytest.mark.parametrize("window", [P.NNFFT_WINDOW_BSPLINE, P.NNFFT_WINDOW_ALGEBRAIC, P.NNFFT_WINDOW_KAISER_BESSEL])
 @pytest.mark.parametrize("prec", [P.NNFFT_FP64_PLAIN, P.NNFFT_FP32_COMP])
 def test_window_plan_dry_run(window, prec):
-    # plans of the B-spline and algebraic families (Example 2.1): sizes as
-    # for the sinh family, shape parameters of the family, layout invariants
+    # plans of the B-spline and algebraic families (Example 2.1) and the
+    # Kaiser-Bessel family: sizes as for the sinh family, shape parameters of
+    # the family, layout invariants
     g = np.random.default_rng(17)
     v, x = g.uniform(-0.5, 0.5, 5000), g.uniform(-0.5, 0.5, 3000)
     for sig, m in ((2.0, 6), (1.5, 8), (1.25, 4)):
@@ -201,7 +202,7 @@ def test_window_plan_errors():
     with pytest.raises(P.NnfftError):
         binding.nnfft_plan_dry_run(100, v, v, 1.02, 2.0, 4, 4, P.NNFFT_FP64_PLAIN, window=P.NNFFT_WINDOW_ALGEBRAIC)
     with pytest.raises(P.NnfftError):
-        binding.nnfft_plan_dry_run(100, v, v, 2.0, 2.0, 4, 4, P.NNFFT_FP64_PLAIN, window=3)
+        binding.nnfft_plan_dry_run(100, v, v, 2.0, 2.0, 4, 4, P.NNFFT_FP64_PLAIN, window=4)
 
 
 @pytest.mark.parametrize("prec,qmax", [(P.NNFFT_FP32_COMP, 32), (P.NNFFT_FP64_PLAIN, 8)])
