@@ -194,6 +194,23 @@ nnfft_status nnfft_plan_window_dry_run(int64_t N, int64_t M1, int64_t M2, double
 nnfft_status nnfft_exec(nnfft_plan_t p, const void *f, void *y, void *stream);
 
 /*
+ * For callers that cannot allocate device memory while they run (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid it): the
+ * same transform as nnfft_exec on the same kernels, with the per-exec
+ * working memory (window planes, FFT intermediate and consumed outputs) in a
+ * static device array of the library, 64 MiB, one per GPU, held until the
+ * process ends; this call allocates nothing and records no memset.  The
+ * caller passes the plan, f and y as for nnfft_exec; the results are bitwise
+ * those of nnfft_exec.  Every call on one GPU shares that GPU's array: calls
+ * that overlap on one GPU (other streams, other threads) race and must be
+ * ordered by the caller.  The array keeps the last call's contents; the call
+ * clears what must start at zero itself.  Errors: ARG (null argument, an
+ * NFFT plan, or a plan whose working memory exceeds 64 MiB: the message
+ * states both sizes), DEVICE.
+ */
+nnfft_status nnfft_exec_noalloc(nnfft_plan_t p, const void *f, void *y, void *stream);
+
+/*
  * Batched form (Algorithm 2.2 on many plans at once): runs n independent
  * plans of any sizes N, M1, M2, sigma, m with one launch per stage for all
  * plans of one precision -- spreading, FFT stage A (whole transforms of

@@ -133,6 +133,7 @@ def lib():
     L.nnfft_plan.argtypes = [ctypes.POINTER(vp), i64, i64, i64, dbl, dbl, ci, ci, ci, vp, vp, vp]
     L.nnfft_plan_window.argtypes = [ctypes.POINTER(vp), i64, i64, i64, dbl, dbl, ci, ci, ci, ci, vp, vp, vp]
     L.nnfft_exec.argtypes = [vp, vp, vp, vp]
+    L.nnfft_exec_noalloc.argtypes = [vp, vp, vp, vp]
     L.nfft_plan.argtypes = [ctypes.POINTER(vp), i64, i64, dbl, ci, ci, vp, vp]
     L.nfft_exec.argtypes = [vp, vp, vp, vp]
     L.nfft_adjoint.argtypes = [vp, vp, vp, vp]
@@ -174,7 +175,7 @@ def lib():
     L.nnfft_version.restype = ctypes.c_char_p
     for name in ["nfft_plan", "nfft_exec", "nfft_adjoint", "nfft_destroy", "nfft_plan_dry_run",
                  "nnfft_plan_dry_run", "nnfft_plan_window", "nnfft_plan_window_dry_run", "nnfft_profile_start", "nnfft_profile_stop", "nnfft_profile_kernels", "nnfft_quadrature", "nnfft_derive_params",
-                 "nnfft_plan", "nnfft_exec", "nnfft_exec_batch", "nnfft_info", "nnfft_destroy", "sinc_plan",
+                 "nnfft_plan", "nnfft_exec", "nnfft_exec_noalloc", "nnfft_exec_batch", "nnfft_info", "nnfft_destroy", "sinc_plan",
                  "sinc_exec", "sinc_info", "sinc_sizes", "sinc_destroy", "nnfft_autotune", "nnfft_set_tuning",
                  "nnfft_get_tuning", "nnfft_clear_tuning", "nnfft_server_create", "nnfft_server_submit",
                  "nnfft_server_wait", "nnfft_server_poll", "nnfft_server_stats", "nnfft_server_evict",
@@ -379,6 +380,15 @@ def nnfft_exec(plan, f, y, stream=None):
     _require(f, dt, info["M1"], "f")
     _require(y, dt, info["M2"], "y")
     _check(lib().nnfft_exec(plan, _ptr(f), _ptr(y), _stream(stream)))
+
+
+def nnfft_exec_noalloc(plan, f, y, stream=None):
+    """nnfft_exec with the working memory in the library's static device array."""
+    info = nnfft_info(plan)
+    dt = _cdtype(info["precision"])
+    _require(f, dt, info["M1"], "f")
+    _require(y, dt, info["M2"], "y")
+    _check(lib().nnfft_exec_noalloc(plan, _ptr(f), _ptr(y), _stream(stream)))
 
 
 def nnfft_exec_batch(plans, fs, ys, stream=None):

@@ -169,4 +169,21 @@ hipError_t launch_exec_batch(int n, const PlanDev *const *host, const PlanDev *c
 hipError_t launch_scale_by_weights(int prec, const double *w, const void *src, void *dst, int64_t n,
                                    hipStream_t s);
 
+// Per-exec working memory of a plan (window planes and overflow windows, the
+// four-step intermediate, the consumed FFT outputs), in bytes; the planes
+// (the first plane_bytes of the window area) hold cells no window writes,
+// which must read as zero.
+struct ExecScratch {
+    size_t part_bytes, plane_bytes, y_bytes, hlin_bytes;
+};
+// Largest working memory that nnfft_exec_noalloc takes from the library's
+// static device array.
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+// Bytes of the static array a plan needs (each part 256-byte aligned).
+size_t static_scratch_need(const ExecScratch &sz);
+// nnfft_exec with the working memory in the static device array of the
+// current device (the plan's own scratch is not touched).  Returns
+// hipErrorInvalidValue if the plan needs more than kStaticScratchBytes.
+hipError_t launch_exec_static(const PlanDev &P, const ExecScratch &sz, const void *f, void *y, hipStream_t s);
+
 }  // namespace nnfft

@@ -29,6 +29,9 @@
 // exactly per tap with exp/sqrt in FP64, plain FP64 sums.
 #include <hip/hip_ext.h>
 
+#include <algorithm>
+#include <mutex>
+
 #include "internal.h"
 #include "../../include/nnfft.h"
 
@@ -1604,6 +1607,73 @@ __global__ void k_scale64(const double *__restrict__ w, const cx<double> *src, c
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) dst[i] = scal(src[i], w[i]);
+}
+
+// ===========================================================================
+// Exec without allocation: working memory in a static device array
+// ===========================================================================
+// One array per device (the runtime places a copy on every GPU the library
+// runs on; it lives until the process ends).  Host code never passes the
+// array's name to a kernel: in host code it is a stand-in, and its device
+// address comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+}   // namespace
+
+// Device address of the current device's array (null on failure).
+static void *static_scratch_ptr()
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[dev] == nullptr) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+        g_scratch_ptr[dev] = p;
+    }
+    return g_scratch_ptr[dev];
+}
+
+__global__ void k_zero16(float4 *p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+static size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
+
+size_t static_scratch_need(const ExecScratch &sz)
+{
+    return align256(sz.part_bytes) + align256(sz.y_bytes) + align256(sz.hlin_bytes);
+}
+
+hipError_t launch_exec_static(const PlanDev &P, const ExecScratch &sz, const void *f, void *y, hipStream_t s)
+{
+    if (static_scratch_need(sz) > kStaticScratchBytes) return hipErrorInvalidValue;
+    unsigned char *base = static_cast<unsigned char *>(static_scratch_ptr());
+    if (base == nullptr) return hipErrorInvalidSymbol;
+    PlanDev D = P;
+    void *part = base;
+    void *Y = base + align256(sz.part_bytes);
+    void *hlin = base + align256(sz.part_bytes) + align256(sz.y_bytes);
+    D.sp.partial = part;
+    D.fft.partial = part;
+    D.fft.Y = Y;
+    D.fft.hlin = hlin;
+    D.ip.hlin = hlin;
+    // the array keeps the previous call's contents: plane cells that no
+    // window of this plan writes must read as zero (a fill kernel, so the
+    // call stays capturable in a graph)
+    const int64_t n16 = (int64_t)(sz.plane_bytes / 16);
+    if (n16 > 0) {
+        const int64_t blocks = std::min<int64_t>((n16 + 255) / 256, 2048);
+        hipLaunchKernelGGL(k_zero16, dim3((unsigned)blocks), dim3(256), 0, s, static_cast<float4 *>(part), n16);
+    }
+    return launch_exec(D, f, y, s, nullptr);
 }
 
 hipError_t launch_scale_by_weights(int prec, const double *w, const void *src, void *dst, int64_t n,

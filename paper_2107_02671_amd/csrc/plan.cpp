@@ -1167,6 +1167,13 @@ nnfft_status plan_create(const HostPlan &H, const DevMem &mem, hipStream_t s, nn
     pl->mem = mem;
     pl->info = H.info;
     pl->kind = H.kind;
+    {
+        const size_t csz = H.fp32 ? 8 : 16;
+        pl->scratch.part_bytes = (size_t)H.sp.part_cells * 16;
+        pl->scratch.plane_bytes = (size_t)H.sp.nplanes * (size_t)H.slotT * (size_t)H.slotP * 16;
+        pl->scratch.y_bytes = (size_t)H.info.N2 * csz;
+        pl->scratch.hlin_bytes = (size_t)H.hlin_len * csz;
+    }
     try {
         std::vector<char> stage;
         Carver C((uintptr_t)base, &stage);
@@ -1413,6 +1420,20 @@ nnfft_status nnfft_exec(nnfft_plan_t p, const void *f, void *y, void *stream)
     KernelTimes *kt = nullptr;
     if (p->prof_used < p->prof_max) kt = &p->prof[(size_t)p->prof_used++];
     const hipError_t e = launch_exec(p->desc, f, y, static_cast<hipStream_t>(stream), kt);
+    if (e != hipSuccess) return fail(NNFFT_ERR_DEVICE, std::string("launch: ") + hipGetErrorString(e));
+    return NNFFT_OK;
+}
+
+nnfft_status nnfft_exec_noalloc(nnfft_plan_t p, const void *f, void *y, void *stream)
+{
+    if (!p || !f || !y) return fail(NNFFT_ERR_ARG, "null argument");
+    if (p->kind != 0) return fail(NNFFT_ERR_ARG, "an NFFT plan: use nfft_exec or nfft_adjoint");
+    const size_t need = static_scratch_need(p->scratch);
+    if (need > kStaticScratchBytes)
+        return fail(NNFFT_ERR_ARG, "nnfft_exec_noalloc: the plan needs " + std::to_string(need) +
+                                       " bytes of working memory; the static scratch holds " +
+                                       std::to_string(kStaticScratchBytes));
+    const hipError_t e = launch_exec_static(p->desc, p->scratch, f, y, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return fail(NNFFT_ERR_DEVICE, std::string("launch: ") + hipGetErrorString(e));
     return NNFFT_OK;
 }

@@ -100,6 +100,7 @@ struct nnfft_plan_s {
     nnfft::PlanDev *ddesc = nullptr;   // device copy of desc (batched launches)
     void *base = nullptr;              // the plan's device block
     nnfft::DevMem mem{};
+    nnfft::ExecScratch scratch{};      // sizes of the per-exec working memory
     std::vector<nnfft::KernelTimes> prof;   // kernel event pairs of each profiled exec
     int prof_max = 0, prof_used = 0;
 
