@@ -188,6 +188,25 @@ nnfft_status nnfft_plan_window_dry_run(int64_t N, int64_t M1, int64_t M2, double
                                        const double *x, nnfft_info_t *out);
 
 /*
+ * Layout digests (Algorithm 2.2 step 0).  nnfft_plan orders the nodes on the
+ * device (cell/offset split in FP64, domain check, per-block bin counts and a
+ * stable sort by (node block, cell)) and builds the work schedule on the host
+ * from the bin counts; the dry run builds the same layout from host nodes on
+ * the host alone.  Both digests hash, with 64-bit FNV-1a, the byte image of
+ * the plan's tables, schedule and point records as the kernels read them, so
+ * equal digests mean bit-for-bit equal layouts.
+ *   nnfft_plan_digest           of a plan on the device (copies the image to
+ *                               the host; synchronizes the device);
+ *   nnfft_plan_window_dry_run_digest  of the layout the dry run builds from
+ *                               host nodes v[M1], x[M2].
+ * Errors: as nnfft_plan_dry_run; ARG (null argument), DEVICE.
+ */
+nnfft_status nnfft_plan_digest(nnfft_plan_t p, uint64_t *digest);
+nnfft_status nnfft_plan_window_dry_run_digest(int64_t N, int64_t M1, int64_t M2, double sigma1, double sigma2,
+                                              int m1, int m2, nnfft_precision prec, nnfft_window window,
+                                              const double *v, const double *x, uint64_t *digest);
+
+/*
  * Runs Algorithm 2.2 on `stream`: f[M1] -> y[M2] (c64 or c128 per the plan's
  * precision; y in the caller's node order).  f and y must not overlap.
  */

@@ -144,6 +144,9 @@ def lib():
     L.nnfft_plan_window_dry_run.argtypes = [i64, i64, i64, dbl, dbl, ci, ci, ci, ci, ctypes.POINTER(dbl),
                                             ctypes.POINTER(dbl), ctypes.POINTER(NnfftInfo)]
     L.nnfft_exec_batch.argtypes = [ci, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
+    L.nnfft_plan_digest.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64)]
+    L.nnfft_plan_window_dry_run_digest.argtypes = [i64, i64, i64, dbl, dbl, ci, ci, ci, ci, ctypes.POINTER(dbl),
+                                                   ctypes.POINTER(dbl), ctypes.POINTER(ctypes.c_uint64)]
     L.nnfft_info.argtypes = [vp, ctypes.POINTER(NnfftInfo)]
     L.nnfft_destroy.argtypes = [vp]
     L.sinc_plan.argtypes = [ctypes.POINTER(vp), i64, i64, i64, ci, i64, dbl, dbl, ci, ci, ci, vp, vp, vp]
@@ -174,7 +177,7 @@ def lib():
     L.nnfft_last_error.restype = ctypes.c_char_p
     L.nnfft_version.restype = ctypes.c_char_p
     for name in ["nfft_plan", "nfft_exec", "nfft_adjoint", "nfft_destroy", "nfft_plan_dry_run",
-                 "nnfft_plan_dry_run", "nnfft_plan_window", "nnfft_plan_window_dry_run", "nnfft_profile_start", "nnfft_profile_stop", "nnfft_profile_kernels", "nnfft_quadrature", "nnfft_derive_params",
+                 "nnfft_plan_dry_run", "nnfft_plan_window", "nnfft_plan_digest", "nnfft_plan_window_dry_run_digest", "nnfft_plan_window_dry_run", "nnfft_profile_start", "nnfft_profile_stop", "nnfft_profile_kernels", "nnfft_quadrature", "nnfft_derive_params",
                  "nnfft_plan", "nnfft_exec", "nnfft_exec_noalloc", "nnfft_exec_batch", "nnfft_info", "nnfft_destroy", "sinc_plan",
                  "sinc_exec", "sinc_info", "sinc_sizes", "sinc_destroy", "nnfft_autotune", "nnfft_set_tuning",
                  "nnfft_get_tuning", "nnfft_clear_tuning", "nnfft_server_create", "nnfft_server_submit",
@@ -279,6 +282,27 @@ def nnfft_plan_dry_run(N, v, x, sigma1=2.0, sigma2=2.0, m1=6, m2=6, prec=NNFFT_F
                                                int(m2), int(prec), int(window), v.ctypes.data_as(dptr),
                                                x.ctypes.data_as(dptr), ctypes.byref(info)))
     return info.as_dict()
+
+
+def nnfft_plan_digest(plan) -> int:
+    """64-bit digest of a plan's layout image on the device."""
+    d = ctypes.c_uint64()
+    _check(lib().nnfft_plan_digest(plan, ctypes.byref(d)))
+    return d.value
+
+
+def nnfft_plan_dry_run_digest(N, v, x, sigma1=2.0, sigma2=2.0, m1=6, m2=6, prec=NNFFT_FP32_COMP,
+                              window=NNFFT_WINDOW_SINH) -> int:
+    """Digest of the layout the dry run builds on the host from host nodes."""
+    import numpy as np
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    dptr = ctypes.POINTER(ctypes.c_double)
+    d = ctypes.c_uint64()
+    _check(lib().nnfft_plan_window_dry_run_digest(int(N), v.size, x.size, float(sigma1), float(sigma2), int(m1),
+                                                  int(m2), int(prec), int(window), v.ctypes.data_as(dptr),
+                                                  x.ctypes.data_as(dptr), ctypes.byref(d)))
+    return d.value
 
 
 def nfft_plan(N, x, sigma=2.0, m=6, prec=NNFFT_FP32_COMP, stream=None):

@@ -22,7 +22,7 @@ COMMON = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unknown-pragmas",
 ]
-SOURCES = ["kernels.hip", "host_math.cpp", "plan.cpp", "tune.cpp", "serve.cpp"]
+SOURCES = ["kernels.hip", "plan_device.hip", "host_math.cpp", "plan.cpp", "tune.cpp", "serve.cpp"]
 
 
 def _compile(src: str) -> str:

@@ -169,6 +169,25 @@ hipError_t launch_exec_batch(int n, const PlanDev *const *host, const PlanDev *c
 hipError_t launch_scale_by_weights(int prec, const double *w, const void *src, void *dst, int64_t n,
                                    hipStream_t s);
 
+// Node preparation on the device (plan_device.hip): the key of node k of a
+// side is (block << bbits) | bin; device_sort_nodes checks the domain (flag
+// bit 0: a node outside [-1/2, 1/2] or NaN; bit 1: a bin outside [0, nbins)),
+// adds the bin counts of every block to counts[block * nbins + bin] (zeroed
+// by the caller) and sorts the caller indices stably by key into
+// *sorted_idx (inside tmp, device_sort_tmp_bytes(M) bytes).
+bool device_sort_fits(int64_t M, int64_t nbins, int64_t block);
+size_t device_sort_tmp_bytes(int64_t M);
+hipError_t device_sort_nodes(const double *x, int64_t M, double scale, int64_t off, int64_t nbins, int64_t block,
+                             int32_t *counts, int32_t *flag, void *tmp, int32_t **sorted_idx, hipStream_t s);
+// The records of the sorted points: FP64 caller index and cell offset, or
+// FP32 (index, offset) records in sorted order.
+hipError_t device_sorted_records(const double *x, const int32_t *sorted_idx, int64_t M, double scale, bool fp32,
+                                 int32_t *perm, double *frac64, PtRec *rec32, hipStream_t s);
+// FP32 records in per-slot transposed blocks from the sorted records.
+hipError_t device_transpose_records(const PtRec *rec32, const Item *launch_items, int64_t nslot, int rows,
+                                    PtRec *trec32, hipStream_t s);
+hipError_t device_gather(const double *x, const int64_t *idx, int64_t n, double *out, hipStream_t s);
+
 // Per-exec working memory of a plan (window planes and overflow windows, the
 // four-step intermediate, the consumed FFT outputs), in bytes; the planes
 // (the first plane_bytes of the window area) hold cells no window writes,

@@ -118,31 +118,51 @@ Layout choose_layout(int64_t M, bool fp32, bool spreading)
     return rule_layout(M, fp32, spreading);
 }
 
-// choose_layout for a given node set (grid coordinate t = scale * node): where
-// a typical node's bin holds more than eight of the rule's items within its
-// block, the item size is raised to the smallest power of two >= load / 1.5
-// (up to 32 on the FP32 path, 8 on the FP64 path), load = block x sum_b p_b^2
-// estimated from strided samples of up to four blocks ((sum_b c_b^2 - S) /
-// (S (S - 1)) over S sampled cells).  One thread sums the items of a bin, so
-// dense cells cut into many short items serialize their chunk.  A tuned entry
-// (timed on uniform nodes) takes the place of the rule and gets the same raise.
-Layout choose_layout_nodes(const std::vector<double> &nodes, double scale, bool fp32, bool spreading)
+// Indices of the density samples of a node set of M points laid out by L:
+// strided samples (up to 4096) of up to four node blocks, in the order the
+// item size rule reads them; none when the rule's items are already the
+// largest.
+std::vector<int64_t> density_sample_indices(int64_t M, const Layout &L, bool fp32)
 {
-    const int64_t M = (int64_t)nodes.size();
-    Layout L = choose_layout(M, fp32, spreading);
+    std::vector<int64_t> idx;
     const int qmax = fp32 ? 32 : 8;
+    if (L.Q >= qmax) return idx;
+    const int64_t nblk = (M + L.block - 1) / L.block;
+    const int64_t nsb = std::min<int64_t>(nblk, 4);
+    for (int64_t sb = 0; sb < nsb; ++sb) {
+        const int64_t blk = sb * nblk / nsb;
+        const int64_t k0 = blk * L.block, len = std::min(M, k0 + L.block) - k0;
+        const int64_t S = std::min<int64_t>(len, 4096);
+        if (S < 2) continue;
+        for (int64_t i = 0; i < S; ++i) idx.push_back(k0 + i * len / S);
+    }
+    return idx;
+}
+
+// The item size rule for dense node sets, from the sampled node values (in
+// density_sample_indices order): where a typical node's bin holds more than
+// eight of the rule's items within its block, the item size is raised to the
+// smallest power of two >= load / 1.5 (up to 32 on the FP32 path, 8 on the
+// FP64 path), load = block x sum_b p_b^2 estimated from the samples of each
+// block ((sum_b c_b^2 - S) / (S (S - 1)) over S sampled cells).  One thread
+// sums the items of a bin, so dense cells cut into many short items
+// serialize their chunk.
+Layout raise_item_size(Layout L, int64_t M, double scale, bool fp32, const double *vals)
+{
+    const int qmax = fp32 ? 32 : 8;
+    if (L.Q >= qmax) return L;
     const int64_t nblk = (M + L.block - 1) / L.block;
     const int64_t nsb = std::min<int64_t>(nblk, 4);
     double load = 0.0;
-    int64_t used = 0;
+    int64_t used = 0, at = 0;
     std::vector<int64_t> cell;
-    for (int64_t sb = 0; sb < nsb && L.Q < qmax; ++sb) {
+    for (int64_t sb = 0; sb < nsb; ++sb) {
         const int64_t blk = sb * nblk / nsb;
         const int64_t k0 = blk * L.block, len = std::min(M, k0 + L.block) - k0;
         const int64_t S = std::min<int64_t>(len, 4096);
         if (S < 2) continue;
         cell.resize((size_t)S);
-        for (int64_t i = 0; i < S; ++i) cell[(size_t)i] = (int64_t)std::floor(scale * nodes[(size_t)(k0 + i * len / S)]);
+        for (int64_t i = 0; i < S; ++i) cell[(size_t)i] = (int64_t)std::floor(scale * vals[at++]);
         std::sort(cell.begin(), cell.end());
         double sumsq = 0.0;
         for (int64_t i = 0; i < S;) {
@@ -163,6 +183,19 @@ Layout choose_layout_nodes(const std::vector<double> &nodes, double scale, bool 
             while (L.Q < qmax && L.Q < load / 1.5) L.Q *= 2;
     }
     return L;
+}
+
+// choose_layout for a given node set (grid coordinate t = scale * node); a
+// tuned entry (timed on uniform nodes) takes the place of the rule and gets
+// the same raise for dense node sets.
+Layout choose_layout_nodes(const std::vector<double> &nodes, double scale, bool fp32, bool spreading)
+{
+    const int64_t M = (int64_t)nodes.size();
+    const Layout L = choose_layout(M, fp32, spreading);
+    const std::vector<int64_t> idx = density_sample_indices(M, L, fp32);
+    std::vector<double> vals(idx.size());
+    for (size_t i = 0; i < idx.size(); ++i) vals[i] = nodes[(size_t)idx[i]];
+    return raise_item_size(L, M, scale, fp32, vals.data());
 }
 
 void set_tuned_layout(bool fp32, int64_t M, const Layout &L)
@@ -258,109 +291,48 @@ constexpr int64_t kParallelBlockPoints = (int64_t)1 << 18;
 constexpr int64_t kParallelBlockBins = (int64_t)1 << 21;
 constexpr int kBlockThreads = 4;
 
-// Builds the sorted records, items, chunks and schedule of one side.
-// t_k = scale * node_k (grid units); bin = floor(t_k) + off in [0, nbins).
-// Spreading side: `m` > 0 gives the chunk windows of 2m - 1 + nbin cells.
-bool build_side(const std::vector<double> &nodes, double scale, int64_t off, int64_t nbins,
-                const Layout &L, bool fp32, int m, SideHost &S, std::string &err)
+}  // namespace
+
+// Items and chunks of one node block (consecutive caller indices) from the
+// block's bin counts cnt[0 .. nbins): the block's points sorted by bin start
+// at sorted position k0; each bin run is split into ceil(n / Q) balanced
+// items; a chunk takes consecutive items, at most kItemsPerWg of them, within
+// kItemsPerWg bins.  Both the host and the device node layouts build their
+// schedule here, so they agree item for item.
+void block_schedule(const int32_t *cnt, int64_t nbins, int64_t k0, int Q, BlockOut &o)
 {
-    const int64_t M = (int64_t)nodes.size();
-    if (!(std::fabs(scale) <= (double)((int64_t)1 << 26))) {
-        err = "internal: grid scale out of range";
-        return false;
+    int64_t p = k0;
+    for (int64_t b = 0; b < nbins; ++b) {
+        const int64_t n = cnt[b];
+        if (n == 0) continue;
+        const int64_t nit = (n + Q - 1) / Q;
+        const int64_t base = n / nit, rem = n % nit;
+        for (int64_t q = 0; q < nit; ++q) {
+            const int64_t len = base + (q < rem ? 1 : 0);
+            o.items.push_back(Item{(int32_t)b, (int32_t)p, (int32_t)len, 0});
+            p += len;
+        }
     }
-    // cell and offset of node k, formed again by each pass that needs them
-    // (the same expression, so the same values) instead of held in arrays
-    // (|t| <= 2^25 for nodes in [-1/2, 1/2], so truncation stepped down for
-    // negative non-integers is the exact floor, without a library call)
-    auto cell_of = [&](int64_t k, double *frac) {
-        const double t = scale * nodes[k];
-        const double tr = (double)(int64_t)t;
-        const double c = tr > t ? tr - 1.0 : tr;
-        *frac = t - c;
-        return (int64_t)c + off;
-    };
-    S.perm.assign(M, 0);
-    if (fp32) S.rec32.assign(M, PtRec{0, 0.f});
-    else S.frac64.assign(M, 0.0);
-    std::vector<int32_t> sbin(M);
-    S.nblocks = (M + L.block - 1) / L.block;
-    // Each node block is sorted and cut into items and chunks on its own
-    // (writes to its own range of perm / records / sbin and its own lists),
-    // on up to kBlockThreads threads for large sides; the lists are then
-    // appended in block order, so the result does not depend on the threads.
-    struct BlockOut {
-        std::vector<Item> items;
-        std::vector<Chunk> chunks;
-        std::vector<int32_t> item0;   // first item of each chunk, within the block
-        bool ok = true;
-    };
-    std::vector<BlockOut> outs((size_t)S.nblocks);
-    auto run_block = [&](int64_t blk, std::vector<int64_t> &cnt) {
-        BlockOut &o = outs[(size_t)blk];
-        const int64_t k0 = blk * L.block, k1 = std::min(M, k0 + L.block);
-        std::fill(cnt.begin(), cnt.end(), 0);
-        for (int64_t k = k0; k < k1; ++k) {
-            double fr;
-            const int64_t b = cell_of(k, &fr);
-            if (b < 0 || b >= nbins) {
-                o.ok = false;
-                return;
-            }
-            cnt[b + 1]++;
-        }
-        for (int64_t b = 0; b < nbins; ++b) cnt[b + 1] += cnt[b];
-        // stable counting sort of the block by bin
-        for (int64_t k = k0; k < k1; ++k) {
-            double fr;
-            const int64_t b = cell_of(k, &fr);
-            const int64_t pos = k0 + cnt[b]++;
-            S.perm[pos] = (int32_t)k;
-            sbin[pos] = (int32_t)b;
-            if (fp32) {
-                float f = (float)fr;
-                if (!(f < 1.0f)) f = 0.99999994f;   // keep the offset inside [0, 1)
-                S.rec32[pos] = PtRec{(int32_t)k, f};
-            } else {
-                S.frac64[pos] = fr;
-            }
-        }
-        // items: balanced split of each bin run into ceil(n / Q) pieces
-        for (int64_t i = k0; i < k1;) {
-            int64_t j = i;
-            while (j < k1 && sbin[j] == sbin[i]) ++j;
-            const int64_t n = j - i;
-            const int64_t nit = (n + L.Q - 1) / L.Q;
-            const int64_t base = n / nit, rem = n % nit;
-            int64_t p = i;
-            for (int64_t q = 0; q < nit; ++q) {
-                const int64_t len = base + (q < rem ? 1 : 0);
-                o.items.push_back(Item{sbin[i], (int32_t)p, (int32_t)len, 0});
-                p += len;
-            }
-            i = j;
-        }
-        // chunks: consecutive items, at most IW items and IW bins
-        const size_t it1 = o.items.size();
-        for (size_t ci = 0; ci < it1;) {
-            const int32_t blo = o.items[ci].bin;
-            size_t cj = ci;
-            while (cj < it1 && (int)(cj - ci) < kItemsPerWg && o.items[cj].bin - blo < kItemsPerWg) ++cj;
-            Chunk c{};
-            c.nitem = (int32_t)(cj - ci);
-            c.bin_lo = blo;
-            c.nbin = o.items[cj - 1].bin - blo + 1;
-            o.chunks.push_back(c);
-            o.item0.push_back((int32_t)ci);
-            ci = cj;
-        }
-    };
-    const int nthr = (M >= kParallelBlockPoints && nbins <= kParallelBlockBins) ? kBlockThreads : 1;
-    std::vector<std::vector<int64_t>> cnts((size_t)nthr);   // bin counts of each thread
-    parallel_strided(S.nblocks, nthr, [&](int64_t blk, int r) {
-        if (cnts[(size_t)r].empty()) cnts[(size_t)r].resize((size_t)nbins + 1);
-        run_block(blk, cnts[(size_t)r]);
-    });
+    const size_t it1 = o.items.size();
+    for (size_t ci = 0; ci < it1;) {
+        const int32_t blo = o.items[ci].bin;
+        size_t cj = ci;
+        while (cj < it1 && (int)(cj - ci) < kItemsPerWg && o.items[cj].bin - blo < kItemsPerWg) ++cj;
+        Chunk c{};
+        c.nitem = (int32_t)(cj - ci);
+        c.bin_lo = blo;
+        c.nbin = o.items[cj - 1].bin - blo + 1;
+        o.chunks.push_back(c);
+        o.item0.push_back((int32_t)ci);
+        ci = cj;
+    }
+}
+
+// Appends the blocks' items and chunks in block order, colours the spreading
+// windows (m > 0) and lays out the launch slots (XCD-aware order, 64 items
+// per slot).  The FP32 records of the slots are transposed separately.
+bool finish_side(std::vector<BlockOut> &outs, int m, SideHost &S, std::string &err)
+{
     {
         size_t ni = 0, nc = 0;
         for (const BlockOut &o : outs) {
@@ -375,7 +347,7 @@ bool build_side(const std::vector<double> &nodes, double scale, int64_t off, int
         S.chunks.reserve(nc);
         S.chunk_block.reserve(nc);
         S.chunk_item0.reserve(nc);
-        for (int64_t blk = 0; blk < S.nblocks; ++blk) {
+        for (int64_t blk = 0; blk < (int64_t)outs.size(); ++blk) {
             BlockOut &o = outs[(size_t)blk];
             const int32_t base = (int32_t)S.items.size();
             S.items.insert(S.items.end(), o.items.begin(), o.items.end());
@@ -452,32 +424,120 @@ bool build_side(const std::vector<double> &nodes, double scale, int64_t off, int
     const Item pad_item{0, 0, 0, 0};
     S.launch.assign(order.size(), empty);
     S.launch_items.assign(order.size() * kItemsPerWg, pad_item);
-    // FP32 records: one transposed block of Q rows per launch slot, point q of
-    // item t of slot g at (g Q + q) 64 + t; rows past an item's end repeat its
-    // last record (same address, masked in the kernel), empty items point at 0
-    const int64_t rows = L.Q;
-    if (fp32) {
-        if ((int64_t)order.size() * rows * kItemsPerWg >= ((int64_t)1 << 31)) {
-            err = "too many padded records";
-            return false;
-        }
-        S.trec32.assign((size_t)(order.size() * rows * kItemsPerWg), PtRec{0, 0.f});
-    }
     for (size_t g = 0; g < order.size(); ++g) {
         if (order[g] < 0) continue;
         const Chunk c = S.chunks[order[g]];
         const int32_t i0 = S.chunk_item0[order[g]];
         for (int i = 0; i < c.nitem; ++i) S.launch_items[g * kItemsPerWg + i] = S.items[i0 + i];
-        if (fp32) {
-            // row by row, so the writes are sequential
-            PtRec *blk = S.trec32.data() + (size_t)g * rows * kItemsPerWg;
-            const Item *its = S.items.data() + i0;
-            for (int64_t q = 0; q < rows; ++q)
-                for (int i = 0; i < c.nitem; ++i)
-                    blk[q * kItemsPerWg + i] = S.rec32[(size_t)(its[i].p0 + std::min<int64_t>(q, its[i].n - 1))];
-        }
         S.launch[g] = c;
     }
+    return true;
+}
+
+namespace {
+
+// FP32 records: one transposed block of Q rows per launch slot, point q of
+// item t of slot g at (g Q + q) 64 + t; rows past an item's end repeat its
+// last record (same address, masked in the kernel), empty items hold zeros.
+static bool transpose_records(SideHost &S, int64_t rows, std::string &err)
+{
+    const size_t nslot = S.launch.size();
+    if ((int64_t)nslot * rows * kItemsPerWg >= ((int64_t)1 << 31)) {
+        err = "too many padded records";
+        return false;
+    }
+    S.trec32.assign((size_t)(nslot * rows * kItemsPerWg), PtRec{0, 0.f});
+    for (size_t g = 0; g < nslot; ++g) {
+        const Chunk &c = S.launch[g];
+        // row by row, so the writes are sequential
+        PtRec *blk = S.trec32.data() + (size_t)g * rows * kItemsPerWg;
+        const Item *its = S.launch_items.data() + g * kItemsPerWg;
+        for (int64_t q = 0; q < rows; ++q)
+            for (int i = 0; i < c.nitem; ++i)
+                blk[q * kItemsPerWg + i] = S.rec32[(size_t)(its[i].p0 + std::min<int64_t>(q, its[i].n - 1))];
+    }
+    return true;
+}
+
+// Builds the sorted records, items, chunks and schedule of one side on the
+// host.  t_k = scale * node_k (grid units); bin = floor(t_k) + off in [0, nbins).
+// Spreading side: `m` > 0 gives the chunk windows of 2m - 1 + nbin cells.
+bool build_side(const std::vector<double> &nodes, double scale, int64_t off, int64_t nbins,
+                const Layout &L, bool fp32, int m, SideHost &S, std::string &err)
+{
+    const int64_t M = (int64_t)nodes.size();
+    if (!(std::fabs(scale) <= (double)((int64_t)1 << 26))) {
+        err = "internal: grid scale out of range";
+        return false;
+    }
+    // cell and offset of node k, formed again by each pass that needs them
+    // (the same expression, so the same values) instead of held in arrays
+    // (|t| <= 2^25 for nodes in [-1/2, 1/2], so truncation stepped down for
+    // negative non-integers is the exact floor, without a library call)
+    auto cell_of = [&](int64_t k, double *frac) {
+        const double t = scale * nodes[k];
+        const double tr = (double)(int64_t)t;
+        const double c = tr > t ? tr - 1.0 : tr;
+        *frac = t - c;
+        return (int64_t)c + off;
+    };
+    S.perm.assign(M, 0);
+    if (fp32) S.rec32.assign(M, PtRec{0, 0.f});
+    else S.frac64.assign(M, 0.0);
+    S.nblocks = (M + L.block - 1) / L.block;
+    S.rows = L.Q;
+    S.npts = M;
+    // Each node block is sorted (stable counting sort by bin) and cut into
+    // items and chunks on its own (writes to its own range of perm / records
+    // and its own lists), on up to kBlockThreads threads for large sides; the
+    // lists are then appended in block order, so the result does not depend
+    // on the threads.
+    std::vector<BlockOut> outs((size_t)S.nblocks);
+    auto run_block = [&](int64_t blk, std::vector<int32_t> &cnt, std::vector<int64_t> &pos) {
+        BlockOut &o = outs[(size_t)blk];
+        const int64_t k0 = blk * L.block, k1 = std::min(M, k0 + L.block);
+        std::fill(cnt.begin(), cnt.end(), 0);
+        for (int64_t k = k0; k < k1; ++k) {
+            double fr;
+            const int64_t b = cell_of(k, &fr);
+            if (b < 0 || b >= nbins) {
+                o.ok = false;
+                return;
+            }
+            cnt[b]++;
+        }
+        block_schedule(cnt.data(), nbins, k0, L.Q, o);
+        int64_t acc = k0;
+        for (int64_t b = 0; b < nbins; ++b) {
+            pos[b] = acc;
+            acc += cnt[b];
+        }
+        for (int64_t k = k0; k < k1; ++k) {
+            double fr;
+            const int64_t b = cell_of(k, &fr);
+            const int64_t p = pos[b]++;
+            S.perm[p] = (int32_t)k;
+            if (fp32) {
+                float f = (float)fr;
+                if (!(f < 1.0f)) f = 0.99999994f;   // keep the offset inside [0, 1)
+                S.rec32[p] = PtRec{(int32_t)k, f};
+            } else {
+                S.frac64[p] = fr;
+            }
+        }
+    };
+    const int nthr = (M >= kParallelBlockPoints && nbins <= kParallelBlockBins) ? kBlockThreads : 1;
+    std::vector<std::vector<int32_t>> cnts((size_t)nthr);   // bin counts of each thread
+    std::vector<std::vector<int64_t>> poss((size_t)nthr);
+    parallel_strided(S.nblocks, nthr, [&](int64_t blk, int r) {
+        if (cnts[(size_t)r].empty()) {
+            cnts[(size_t)r].resize((size_t)nbins);
+            poss[(size_t)r].resize((size_t)nbins);
+        }
+        run_block(blk, cnts[(size_t)r], poss[(size_t)r]);
+    });
+    if (!finish_side(outs, m, S, err)) return false;
+    if (fp32 && !transpose_records(S, L.Q, err)) return false;
     return true;
 }
 
@@ -569,6 +629,15 @@ struct Carver {
         off += nb;
         return p;
     }
+    // an array written on the device after the upload (no host image)
+    template <typename T>
+    T *reserve(size_t n)
+    {
+        off = (off + 255) & ~(size_t)255;
+        T *p = reinterpret_cast<T *>(base + off);
+        off += std::max<size_t>(1, n) * sizeof(T);
+        return p;
+    }
     void *scratch(size_t nb)
     {
         off = (off + 255) & ~(size_t)255;
@@ -580,7 +649,8 @@ struct Carver {
 
 // Lays the plan out in its device block (base 0: sizing pass) and fills the
 // kernel descriptors.  Returns the end of the uploaded part in *upload_end.
-void layout_plan(const HostPlan &H, Carver &C, PlanDev &D, size_t *upload_end, PlanDev **ddesc)
+void layout_plan(const HostPlan &H, Carver &C, PlanDev &D, size_t *upload_end, PlanDev **ddesc,
+                 size_t *dev_start = nullptr)
 {
     const nnfft_info_t &P = H.info;
     const bool fp32 = H.fp32;
@@ -609,15 +679,9 @@ void layout_plan(const HostPlan &H, Carver &C, PlanDev &D, size_t *upload_end, P
     IA.corr = C.put(H.corr);
     IA.corr_deg = P.corr_degree;
     if (fp32) {
-        SA.rec32 = C.put(H.sp.trec32);
-        IA.rec32 = C.put(H.ip.trec32);
         SA.C = C.put(H.C1);
         IA.C = C.put(H.C2);
     } else {
-        SA.perm = C.put(H.sp.perm);
-        SA.frac64 = C.put(H.sp.frac64);
-        IA.perm = C.put(H.ip.perm);
-        IA.frac64 = C.put(H.ip.frac64);
         if (!H.T1.empty()) {
             SA.T64 = C.put(H.T1);
             IA.T64 = C.put(H.T2);
@@ -643,6 +707,23 @@ void layout_plan(const HostPlan &H, Carver &C, PlanDev &D, size_t *upload_end, P
     }
     SA.slotT = FA.slotT = H.slotT;
     SA.slotP = FA.slotP = H.slotP;
+    // the per-point records last: a plan whose nodes were sorted on the
+    // device writes them there after the upload of everything before
+    C.off = (C.off + 255) & ~(size_t)255;
+    if (dev_start) *dev_start = C.off;
+    auto side_records = [&](const SideHost &S, const PtRec **rec, const int32_t **perm, const double **frac) {
+        if (fp32)
+            *rec = S.dev ? C.reserve<PtRec>(S.launch.size() * (size_t)S.rows * kItemsPerWg) : C.put(S.trec32);
+        else if (S.dev) {
+            *perm = C.reserve<int32_t>((size_t)S.npts);
+            *frac = C.reserve<double>((size_t)S.npts);
+        } else {
+            *perm = C.put(S.perm);
+            *frac = C.put(S.frac64);
+        }
+    };
+    side_records(H.sp, &SA.rec32, &SA.perm, &SA.frac64);
+    side_records(H.ip, &IA.rec32, &IA.perm, &IA.frac64);
     *upload_end = C.off;
     const size_t csz = fp32 ? 8 : 16;
     SA.partial = C.scratch((size_t)H.sp.part_cells * 16);
@@ -821,11 +902,14 @@ static void size_plan(HostPlan &H, const nnfft_info_t &P)
     H.info.fft_n2 = H.fd.n2;
 }
 
-nnfft_status plan_host(HostPlan &H, int64_t N, int64_t M1, int64_t M2, double sigma1, double sigma2,
-                       int m1, int m2, nnfft_precision prec, const std::vector<double> &v,
-                       const std::vector<double> &x, const Layout *lay1, const Layout *lay2, int window)
+// Algorithm 2.2 step 0 without the nodes: parameters, validations and the
+// FP64 tables (tap series, 1/phi_hat_1 series, phi_hat_2 deconvolution,
+// twiddles); H.info holds the parameters.
+static nnfft_status plan_params_tables(HostPlan &H, int64_t N, int64_t M1, int64_t M2, double sigma1,
+                                       double sigma2, int m1, int m2, nnfft_precision prec, int window)
 {
-    nnfft_info_t P;
+    nnfft_info_t &P = H.info;
+    P = nnfft_info_t{};
     nnfft_status st = derive_params(N, sigma1, sigma2, m1, m2, &P);
     if (st != NNFFT_OK) return fail(st, "invalid NNFFT parameters (N >= 1, m >= 2, sigma > 1, "
                                         "2 m1 < N1 and 2 m2 <= (1 - 1/sigma1) N2 are required)");
@@ -848,7 +932,6 @@ nnfft_status plan_host(HostPlan &H, int64_t N, int64_t M1, int64_t M2, double si
     if (M1 < 1 || M2 < 1 || M1 > ((int64_t)1 << 30) || M2 > ((int64_t)1 << 30))
         return fail(NNFFT_ERR_ARG, "node counts must be in [1, 2^30]");
     if (prec != NNFFT_FP64_PLAIN && prec != NNFFT_FP32_COMP) return fail(NNFFT_ERR_ARG, "unknown precision");
-    if ((int64_t)v.size() != M1 || (int64_t)x.size() != M2) return fail(NNFFT_ERR_ARG, "node array sizes");
     if (m1 > kMaxM || m2 > kMaxM) return fail(NNFFT_ERR_UNSUPPORTED, "m > 16 is not implemented");
     const bool fp32 = (prec == NNFFT_FP32_COMP);
     if (fp32 && (m1 < 4 || m2 < 4))
@@ -856,10 +939,6 @@ nnfft_status plan_host(HostPlan &H, int64_t N, int64_t M1, int64_t M2, double si
                                            "cannot reach FP32 accuracy for smaller m)");
     if (P.N2 > ((int64_t)1 << 24) || P.G1 > ((int64_t)1 << 24) || (!fp32 && P.N2 > ((int64_t)1 << 22)))
         return fail(NNFFT_ERR_UNSUPPORTED, "FFT longer than 2^24 (FP32) or 2^22 (FP64)");
-    for (int64_t k = 0; k < M1; ++k)
-        if (!(std::fabs(v[k]) <= 0.5)) return fail(NNFFT_ERR_DOMAIN, "frequency node outside [-1/2, 1/2]");
-    for (int64_t j = 0; j < M2; ++j)
-        if (!(std::fabs(x[j]) <= 0.5)) return fail(NNFFT_ERR_DOMAIN, "spatial node outside [-1/2, 1/2]");
 
     P.M1 = M1;
     P.M2 = M2;
@@ -911,28 +990,17 @@ nnfft_status plan_host(HostPlan &H, int64_t N, int64_t M1, int64_t M2, double si
         H.tw32.assign(H.tw64.begin(), H.tw64.end());
         H.tw64.clear();
     }
+    return NNFFT_OK;
+}
 
-    // node layouts ----------------------------------------------------------
-    const double scale1 = (double)P.N1 * (double)N / (double)P.N_star;   // t_k = scale1 v_k
-    const double scale2 = (double)P.N2 * (double)P.N_star / (double)P.N1; // u_j = scale2 x_j
-    H.lay1 = lay1 ? sanitize_layout(*lay1, M1, fp32) : choose_layout_nodes(v, scale1, fp32, true);
-    H.lay2 = lay2 ? sanitize_layout(*lay2, M2, fp32) : choose_layout_nodes(x, scale2, fp32, false);
-    std::string err;
-    // spreading: t_k = N1 v*_k = N1 N v_k / N*, bin = floor(t_k) + G1/2
-    // interpolation: u_j = N2 N* x_j / N1, bin = floor(u_j) + N2/2
-    if (!build_both_sides(
-            [&](std::string &e) { return build_side(v, scale1, P.G1 / 2, P.G1, H.lay1, fp32, m1, H.sp, e); },
-            [&](std::string &e) { return build_side(x, scale2, P.N2 / 2, P.N2 + 1, H.lay2, fp32, 0, H.ip, e); },
-            std::min(M1, M2) >= kParallelSidePoints, err))
-        return fail(NNFFT_ERR_ARG, err);
-    // the sorted copies are only needed by the FP64 kernels
-    if (fp32) {
-        std::vector<int32_t>().swap(H.sp.perm);
-        std::vector<int32_t>().swap(H.ip.perm);
-    }
-    std::vector<PtRec>().swap(H.sp.rec32);
-    std::vector<PtRec>().swap(H.ip.rec32);
-
+// The rest of step 0 once both node sides are laid out: FFT factorization
+// and tables, window planes, merge lists, sizes.
+static nnfft_status plan_finish(HostPlan &H)
+{
+    const nnfft_info_t &P = H.info;
+    const int m1 = P.m1, m2 = P.m2;
+    const bool fp32 = H.fp32;
+    nnfft_status st = NNFFT_OK;
     {
         const double U = (double)P.N2 * (double)P.N_star / (2.0 * (double)P.N1);
         const int64_t S = std::min<int64_t>((int64_t)std::ceil(U) + m2, P.N2 / 2);
@@ -955,6 +1023,43 @@ nnfft_status plan_host(HostPlan &H, int64_t N, int64_t M1, int64_t M2, double si
     size_plan(H, P);
     return NNFFT_OK;
 }
+
+nnfft_status plan_host(HostPlan &H, int64_t N, int64_t M1, int64_t M2, double sigma1, double sigma2,
+                       int m1, int m2, nnfft_precision prec, const std::vector<double> &v,
+                       const std::vector<double> &x, const Layout *lay1, const Layout *lay2, int window)
+{
+    nnfft_status st = plan_params_tables(H, N, M1, M2, sigma1, sigma2, m1, m2, prec, window);
+    if (st != NNFFT_OK) return st;
+    const nnfft_info_t &P = H.info;
+    const bool fp32 = H.fp32;
+    if ((int64_t)v.size() != M1 || (int64_t)x.size() != M2) return fail(NNFFT_ERR_ARG, "node array sizes");
+    for (int64_t k = 0; k < M1; ++k)
+        if (!(std::fabs(v[k]) <= 0.5)) return fail(NNFFT_ERR_DOMAIN, "frequency node outside [-1/2, 1/2]");
+    for (int64_t j = 0; j < M2; ++j)
+        if (!(std::fabs(x[j]) <= 0.5)) return fail(NNFFT_ERR_DOMAIN, "spatial node outside [-1/2, 1/2]");
+    // node layouts ----------------------------------------------------------
+    const double scale1 = (double)P.N1 * (double)N / (double)P.N_star;   // t_k = scale1 v_k
+    const double scale2 = (double)P.N2 * (double)P.N_star / (double)P.N1; // u_j = scale2 x_j
+    H.lay1 = lay1 ? sanitize_layout(*lay1, M1, fp32) : choose_layout_nodes(v, scale1, fp32, true);
+    H.lay2 = lay2 ? sanitize_layout(*lay2, M2, fp32) : choose_layout_nodes(x, scale2, fp32, false);
+    std::string err;
+    // spreading: t_k = N1 v*_k = N1 N v_k / N*, bin = floor(t_k) + G1/2
+    // interpolation: u_j = N2 N* x_j / N1, bin = floor(u_j) + N2/2
+    if (!build_both_sides(
+            [&](std::string &e) { return build_side(v, scale1, P.G1 / 2, P.G1, H.lay1, fp32, m1, H.sp, e); },
+            [&](std::string &e) { return build_side(x, scale2, P.N2 / 2, P.N2 + 1, H.lay2, fp32, 0, H.ip, e); },
+            std::min(M1, M2) >= kParallelSidePoints, err))
+        return fail(NNFFT_ERR_ARG, err);
+    // the sorted copies are only needed by the FP64 kernels
+    if (fp32) {
+        std::vector<int32_t>().swap(H.sp.perm);
+        std::vector<int32_t>().swap(H.ip.perm);
+    }
+    std::vector<PtRec>().swap(H.sp.rec32);
+    std::vector<PtRec>().swap(H.ip.rec32);
+    return plan_finish(H);
+}
+
 
 nnfft_status nfft_plan_host(HostPlan &H, int64_t N, int64_t M, double sigma, int m, nnfft_precision prec,
                             const std::vector<double> &x)
@@ -1152,7 +1257,19 @@ nnfft_status check_plan(const HostPlan &H, const std::vector<double> &v, const s
     return NNFFT_OK;
 }
 
-nnfft_status plan_create(const HostPlan &H, const DevMem &mem, hipStream_t s, nnfft_plan_t *out)
+uint64_t fnv1a64(const void *p, size_t n)
+{
+    const unsigned char *b = static_cast<const unsigned char *>(p);
+    uint64_t h = 1469598103934665603ull;
+    for (size_t i = 0; i < n; ++i) {
+        h ^= b[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+nnfft_status plan_create(const HostPlan &H, const DevMem &mem, hipStream_t s, nnfft_plan_t *out,
+                         const DevRecords *dev)
 {
     *out = nullptr;
     void *base = mem.alloc(mem.ctx, H.total_bytes);
@@ -1177,9 +1294,36 @@ nnfft_status plan_create(const HostPlan &H, const DevMem &mem, hipStream_t s, nn
     try {
         std::vector<char> stage;
         Carver C((uintptr_t)base, &stage);
-        size_t upload_end = 0;
-        layout_plan(H, C, pl->desc, &upload_end, &pl->ddesc);
-        hip_check(hipMemcpyAsync(base, stage.data(), upload_end, hipMemcpyHostToDevice, s), "hipMemcpyAsync");
+        size_t upload_end = 0, dev_start = 0;
+        layout_plan(H, C, pl->desc, &upload_end, &pl->ddesc, &dev_start);
+        pl->upload_bytes = upload_end;
+        const size_t up = dev ? dev_start : upload_end;   // device-written records follow dev_start
+        if (stage.size() < up) stage.resize(up);
+        hip_check(hipMemcpyAsync(base, stage.data(), up, hipMemcpyHostToDevice, s), "hipMemcpyAsync");
+        if (dev) {
+            // the gaps between the device-written arrays (alignment) read as zeros, as in the host image
+            hip_check(hipMemsetAsync(static_cast<char *>(base) + dev_start, 0, upload_end - dev_start, s),
+                      "hipMemsetAsync");
+            const PlanDev &D = pl->desc;
+            auto side = [&](const SideHost &S, const DevSideRecords &R, const Item *items, const PtRec *rec32,
+                            const int32_t *perm, const double *frac) {
+                if (!S.dev) return;
+                if (H.fp32) {
+                    PtRec *tmp = static_cast<PtRec *>(R.rec_tmp);
+                    hip_check(device_sorted_records(R.x, R.sorted, S.npts, R.scale, true, nullptr, nullptr, tmp, s),
+                              "sorted records");
+                    hip_check(device_transpose_records(tmp, items, (int64_t)S.launch.size(), S.rows,
+                                                       const_cast<PtRec *>(rec32), s),
+                              "transposed records");
+                } else {
+                    hip_check(device_sorted_records(R.x, R.sorted, S.npts, R.scale, false, const_cast<int32_t *>(perm),
+                                                    const_cast<double *>(frac), nullptr, s),
+                              "sorted records");
+                }
+            };
+            side(H.sp, dev->sp, D.sp.items, D.sp.rec32, D.sp.perm, D.sp.frac64);
+            side(H.ip, dev->ip, D.ip.items, D.ip.rec32, D.ip.perm, D.ip.frac64);
+        }
         hip_check(hipMemcpyAsync(pl->ddesc, &pl->desc, sizeof(PlanDev), hipMemcpyHostToDevice, s),
                   "hipMemcpyAsync");
         // plane cells that no window covers are read as zeros by every exec
@@ -1194,6 +1338,123 @@ nnfft_status plan_create(const HostPlan &H, const DevMem &mem, hipStream_t s, nn
     }
     *out = pl;
     return NNFFT_OK;
+}
+
+// Device memory of the node preparation of one side, released on scope exit.
+struct DevSideTmp {
+    void *mem = nullptr;
+    void *sort_tmp = nullptr;   // radix sort buffers (then the FP32 sorted records)
+    int32_t *counts = nullptr;  // [nblocks * nbins] bin counts of every node block
+    int32_t *flag = nullptr;    // domain flags
+    int64_t *sidx = nullptr;    // density sample indices
+    double *svals = nullptr;    // and values
+    int32_t *sorted = nullptr;  // caller indices in the stable (block, bin) order
+    DevSideTmp() = default;
+    DevSideTmp(const DevSideTmp &) = delete;
+    DevSideTmp &operator=(const DevSideTmp &) = delete;
+    ~DevSideTmp()
+    {
+        if (mem) (void)hipFree(mem);
+    }
+};
+
+// One side's node layout with the nodes x[M] on the device: the keys, the
+// domain check, the bin counts of the node blocks and the stable sort run on
+// the GPU; the host builds the items, chunks, window colours and launch
+// slots from the counts alone (block_schedule, finish_side, the same code as
+// the host layout, so both agree exactly); plan_create writes the records
+// from the sorted indices.  L: the side's layout (the rule, raised for dense
+// node sets from density samples gathered on the device).
+static nnfft_status build_side_device(const double *x, int64_t M, double scale, int64_t off, int64_t nbins,
+                                      bool fp32, bool spreading, int m, const char *what, Layout &L,
+                                      SideHost &S, DevSideTmp &T, hipStream_t s)
+{
+    L = choose_layout(M, fp32, spreading);
+    const int64_t nblocks = (M + L.block - 1) / L.block;
+    const std::vector<int64_t> sidx = density_sample_indices(M, L, fp32);
+    auto al = [](size_t n) { return (n + 255) & ~(size_t)255; };
+    const size_t sort_b = al(device_sort_tmp_bytes(M)), cnt_b = al((size_t)nblocks * (size_t)nbins * 4);
+    const size_t smp_b = al(std::max<size_t>(1, sidx.size()) * 8);
+    if (hipMalloc(&T.mem, sort_b + cnt_b + 256 + 2 * smp_b) != hipSuccess) {
+        (void)hipGetLastError();
+        T.mem = nullptr;
+        return fail(NNFFT_ERR_NOMEM, "device memory for the node sort is not available");
+    }
+    unsigned char *p = static_cast<unsigned char *>(T.mem);
+    T.sort_tmp = p;
+    T.counts = reinterpret_cast<int32_t *>(p + sort_b);
+    T.flag = reinterpret_cast<int32_t *>(p + sort_b + cnt_b);
+    T.sidx = reinterpret_cast<int64_t *>(p + sort_b + cnt_b + 256);
+    T.svals = reinterpret_cast<double *>(p + sort_b + cnt_b + 256 + smp_b);
+    std::vector<int32_t> counts((size_t)nblocks * (size_t)nbins);
+    std::vector<double> svals(sidx.size());
+    int32_t flag = 0;
+    hip_check(hipMemsetAsync(T.counts, 0, cnt_b + 256, s), "hipMemsetAsync");
+    hip_check(device_sort_nodes(x, M, scale, off, nbins, L.block, T.counts, T.flag, T.sort_tmp, &T.sorted, s),
+              "node sort");
+    hip_check(hipMemcpyAsync(counts.data(), T.counts, counts.size() * 4, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+    hip_check(hipMemcpyAsync(&flag, T.flag, 4, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+    hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+    if (flag & 1) return fail(NNFFT_ERR_DOMAIN, std::string(what) + " node outside [-1/2, 1/2]");
+    if (flag & 2) return fail(NNFFT_ERR_ARG, "internal: node record outside the grid");
+    if (!sidx.empty()) {
+        hip_check(hipMemcpyAsync(T.sidx, sidx.data(), sidx.size() * 8, hipMemcpyHostToDevice, s), "hipMemcpyAsync");
+        hip_check(device_gather(x, T.sidx, (int64_t)sidx.size(), T.svals, s), "density samples");
+        hip_check(hipMemcpyAsync(svals.data(), T.svals, svals.size() * 8, hipMemcpyDeviceToHost, s),
+                  "hipMemcpyAsync");
+        hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+    }
+    L = raise_item_size(L, M, scale, fp32, svals.data());
+    S = SideHost{};
+    S.nblocks = nblocks;
+    S.rows = L.Q;
+    S.npts = M;
+    S.dev = true;
+    std::vector<BlockOut> outs((size_t)nblocks);
+    const int nthr = (M >= kParallelBlockPoints && nbins <= kParallelBlockBins) ? kBlockThreads : 1;
+    parallel_strided(nblocks, nthr, [&](int64_t blk, int) {
+        block_schedule(counts.data() + (size_t)blk * (size_t)nbins, nbins, blk * L.block, L.Q, outs[(size_t)blk]);
+    });
+    std::string err;
+    if (!finish_side(outs, m, S, err)) return fail(NNFFT_ERR_ARG, err);
+    if (fp32 && (int64_t)S.launch.size() * L.Q * kItemsPerWg >= ((int64_t)1 << 31))
+        return fail(NNFFT_ERR_ARG, "too many padded records");
+    return NNFFT_OK;
+}
+
+// nnfft_plan_window with the nodes on the device: both node sides prepared
+// on the device (build_side_device).  Sets *host and returns NNFFT_OK without
+// a plan where the sort keys do not fit 32 bits: the caller then plans on the
+// host.
+static nnfft_status plan_from_device_nodes(int64_t N, int64_t M1, int64_t M2, double sigma1, double sigma2, int m1,
+                                           int m2, nnfft_precision prec, int window, const double *v,
+                                           const double *x, hipStream_t s, nnfft_plan_t *out, bool *host)
+{
+    *host = false;
+    HostPlan H;
+    nnfft_status st = plan_params_tables(H, N, M1, M2, sigma1, sigma2, m1, m2, prec, window);
+    if (st != NNFFT_OK) return st;
+    const nnfft_info_t &P = H.info;
+    const bool fp32 = H.fp32;
+    const double scale1 = (double)P.N1 * (double)N / (double)P.N_star;
+    const double scale2 = (double)P.N2 * (double)P.N_star / (double)P.N1;
+    if (!device_sort_fits(M1, P.G1, choose_layout(M1, fp32, true).block) ||
+        !device_sort_fits(M2, P.N2 + 1, choose_layout(M2, fp32, false).block) ||
+        !(std::fabs(scale1) <= (double)((int64_t)1 << 26)) || !(std::fabs(scale2) <= (double)((int64_t)1 << 26))) {
+        *host = true;
+        return NNFFT_OK;
+    }
+    DevSideTmp T1, T2;
+    st = build_side_device(v, M1, scale1, P.G1 / 2, P.G1, fp32, true, m1, "frequency", H.lay1, H.sp, T1, s);
+    if (st != NNFFT_OK) return st;
+    st = build_side_device(x, M2, scale2, P.N2 / 2, P.N2 + 1, fp32, false, 0, "spatial", H.lay2, H.ip, T2, s);
+    if (st != NNFFT_OK) return st;
+    st = plan_finish(H);
+    if (st != NNFFT_OK) return st;
+    DevRecords R;
+    R.sp = DevSideRecords{v, T1.sorted, scale1, T1.sort_tmp};
+    R.ip = DevSideRecords{x, T2.sorted, scale2, T2.sort_tmp};
+    return plan_create(H, hip_mem(), s, out, &R);
 }
 
 nnfft_status copy_nodes(const double *d, int64_t n, std::vector<double> &h, hipStream_t s)
@@ -1353,8 +1614,12 @@ nnfft_status nnfft_plan_window(nnfft_plan_t *out, int64_t N, int64_t M1, int64_t
     if (!v || !x) return fail(NNFFT_ERR_ARG, "null node array");
     try {
         hipStream_t s = static_cast<hipStream_t>(stream);
+        bool host = false;
+        nnfft_status st = plan_from_device_nodes(N, M1, M2, sigma1, sigma2, m1, m2, prec, window, v, x, s, out, &host);
+        if (!host) return st;
+        // sort keys wider than 32 bits: the node layout is built on the host
         std::vector<double> hv, hx;
-        nnfft_status st = copy_nodes(v, M1, hv, s);
+        st = copy_nodes(v, M1, hv, s);
         if (st != NNFFT_OK) return st;
         st = copy_nodes(x, M2, hx, s);
         if (st != NNFFT_OK) return st;
@@ -1362,6 +1627,8 @@ nnfft_status nnfft_plan_window(nnfft_plan_t *out, int64_t N, int64_t M1, int64_t
         st = plan_host(H, N, M1, M2, sigma1, sigma2, m1, m2, prec, hv, hx, nullptr, nullptr, window);
         if (st != NNFFT_OK) return st;
         return plan_create(H, hip_mem(), s, out);
+    } catch (const HipError &e) {
+        return fail(NNFFT_ERR_DEVICE, std::string(e.what) + ": " + hipGetErrorString(e.err));
     } catch (const std::bad_alloc &) {
         return fail(NNFFT_ERR_NOMEM, "host allocation failed");
     }
@@ -1388,6 +1655,46 @@ nnfft_status nnfft_plan_window_dry_run(int64_t N, int64_t M1, int64_t M2, double
         st = check_plan(H, hv, hx);
         if (st != NNFFT_OK) return st;
         *out = H.info;
+        return NNFFT_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(NNFFT_ERR_NOMEM, "host allocation failed");
+    }
+}
+
+nnfft_status nnfft_plan_window_dry_run_digest(int64_t N, int64_t M1, int64_t M2, double sigma1, double sigma2,
+                                              int m1, int m2, nnfft_precision prec, nnfft_window window,
+                                              const double *v, const double *x, uint64_t *digest)
+{
+    if (!v || !x || !digest) return fail(NNFFT_ERR_ARG, "null argument");
+    if (M1 < 1 || M2 < 1 || M1 > ((int64_t)1 << 30) || M2 > ((int64_t)1 << 30))
+        return fail(NNFFT_ERR_ARG, "node counts must be in [1, 2^30]");
+    try {
+        std::vector<double> hv(v, v + M1), hx(x, x + M2);
+        HostPlan H;
+        nnfft_status st = plan_host(H, N, M1, M2, sigma1, sigma2, m1, m2, prec, hv, hx, nullptr, nullptr, window);
+        if (st != NNFFT_OK) return st;
+        std::vector<char> stage;
+        Carver C(0, &stage);
+        PlanDev D;
+        PlanDev *dd = nullptr;
+        size_t upload_end = 0;
+        layout_plan(H, C, D, &upload_end, &dd);
+        stage.resize(upload_end);
+        *digest = fnv1a64(stage.data(), stage.size());
+        return NNFFT_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(NNFFT_ERR_NOMEM, "host allocation failed");
+    }
+}
+
+nnfft_status nnfft_plan_digest(nnfft_plan_t p, uint64_t *digest)
+{
+    if (!p || !digest) return fail(NNFFT_ERR_ARG, "null argument");
+    try {
+        std::vector<char> img(p->upload_bytes);
+        const hipError_t e = hipMemcpy(img.data(), p->base, img.size(), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return fail(NNFFT_ERR_DEVICE, std::string("copying the plan: ") + hipGetErrorString(e));
+        *digest = fnv1a64(img.data(), img.size());
         return NNFFT_OK;
     } catch (const std::bad_alloc &) {
         return fail(NNFFT_ERR_NOMEM, "host allocation failed");

@@ -50,7 +50,20 @@ struct SideHost {
     int64_t ovf_cells = 0;              // spreading side: cells of the overflow windows
     int32_t nplanes = 0;                // spreading side: colours of the windows
     int64_t nblocks = 0;
+    int32_t rows = 0;                   // FP32: record rows per slot (the item size)
+    bool dev = false;                   // records sorted and written on the device
+    int64_t npts = 0;                   // points of the side
 };
+
+// Items and chunks of one node block (host schedule of a side).
+struct BlockOut {
+    std::vector<Item> items;
+    std::vector<Chunk> chunks;
+    std::vector<int32_t> item0;   // first item of each chunk, within the block
+    bool ok = true;
+};
+void block_schedule(const int32_t *cnt, int64_t nbins, int64_t k0, int Q, BlockOut &o);
+bool finish_side(std::vector<BlockOut> &outs, int m, SideHost &S, std::string &err);
 
 // FFT factorization chosen at plan time (copied into FftArgs).
 struct FftPlan {
@@ -101,6 +114,7 @@ struct nnfft_plan_s {
     void *base = nullptr;              // the plan's device block
     nnfft::DevMem mem{};
     nnfft::ExecScratch scratch{};      // sizes of the per-exec working memory
+    size_t upload_bytes = 0;           // tables, schedule and records at the block's start
     std::vector<nnfft::KernelTimes> prof;   // kernel event pairs of each profiled exec
     int prof_max = 0, prof_used = 0;
 
@@ -136,9 +150,27 @@ nnfft_status plan_host(HostPlan &H, int64_t N, int64_t M1, int64_t M2, double si
 nnfft_status nfft_plan_host(HostPlan &H, int64_t N, int64_t M, double sigma, int m, nnfft_precision prec,
                             const std::vector<double> &x);
 
+// The records of a side whose nodes were sorted on the device: the nodes,
+// the sorted caller indices, the grid scale, and device memory of at least
+// 8 M bytes for the FP32 sorted records.
+struct DevSideRecords {
+    const double *x = nullptr;
+    const int32_t *sorted = nullptr;
+    double scale = 0.0;
+    void *rec_tmp = nullptr;
+};
+struct DevRecords {
+    DevSideRecords sp, ip;
+};
+
 // Allocates H.total_bytes from mem, uploads (one copy, synchronizes s) and
-// returns the handle, which releases the block to mem when destroyed.
-nnfft_status plan_create(const HostPlan &H, const DevMem &mem, hipStream_t s, nnfft_plan_t *out);
+// returns the handle, which releases the block to mem when destroyed.  With
+// dev, the sides marked dev get their records written on the device.
+nnfft_status plan_create(const HostPlan &H, const DevMem &mem, hipStream_t s, nnfft_plan_t *out,
+                         const DevRecords *dev = nullptr);
+
+// FNV-1a hash of a byte range (layout digests).
+uint64_t fnv1a64(const void *p, size_t n);
 
 // Fast sinc transform (Algorithm 6.1) on the host: quadrature and both plans.
 struct SincHostPlan {

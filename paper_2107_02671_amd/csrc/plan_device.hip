@@ -1,0 +1,315 @@
+// Node preparation of Algorithm 2.2 step 0 on the device: the (cell, offset)
+// split of every node in FP64, the domain check, the bin counts of every node
+// block and the stable sort of the nodes by (block, bin), and the sorted and
+// per-slot transposed point records the exec kernels read.
+//
+// A side's nodes x[M] (FP64, device) have grid coordinates t_k = scale x_k,
+// cell c_k = floor(t_k) and offset t_k - c_k in [0, 1); bin = c_k + off in
+// [0, nbins).  Node block b holds the caller indices [b B, (b + 1) B).  The
+// sort key of node k is (block << bbits) | bin, so a stable sort of the
+// indices by key is the per-block stable counting sort by bin: the host
+// builds the items and chunks from the counts alone, and the positions of
+// the points agree with the host layout exactly.
+//
+// Stable sort: least-significant-digit radix sort, 8-bit digits, over the
+// key bits in use.  Each pass: per-tile digit histograms (tile = 4096
+// elements), one exclusive scan over (digit, tile) in digit-major order,
+// and a scatter that ranks the elements of a tile in index order (ballot
+// match within a wavefront, per-wave counts in LDS across wavefronts).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+
+#include "internal.h"
+
+namespace nnfft {
+
+namespace {
+
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;                           // elements per thread and tile
+constexpr int kTile = kSortThreads * kSortItems;          // 4096
+constexpr int kRadix = 256;
+constexpr int kSortWaves = kSortThreads / 64;
+
+// cell of t by truncation stepped down for negative non-integers: the exact
+// floor for |t| <= 2^52 (the host layout uses the same expression)
+__device__ __forceinline__ double cell_floor(double t)
+{
+    const double tr = (double)(long long)t;
+    return tr > t ? tr - 1.0 : tr;
+}
+
+// keys[k] = (block << bbits) | bin, vals[k] = k; counts[block * nbins + bin]
+// += 1; flag bit 0: a node outside [-1/2, 1/2] (or NaN), bit 1: a bin outside
+// [0, nbins) (then the key uses a clamped bin and the plan is refused)
+__global__ void k_node_keys(const double *__restrict__ x, int64_t M, double scale, int64_t off, int64_t nbins,
+                            int64_t block, int bbits, uint32_t *__restrict__ keys, int32_t *__restrict__ vals,
+                            int32_t *__restrict__ counts, int32_t *__restrict__ flag)
+{
+#pragma clang fp contract(off)
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < M; k += (int64_t)gridDim.x * blockDim.x) {
+        const double v = x[k];
+        int fl = 0;
+        if (!(fabs(v) <= 0.5)) fl |= 1;
+        const double t = scale * v;
+        int64_t bin = 0;
+        if (fl == 0) {
+            bin = (int64_t)cell_floor(t) + off;
+            if (bin < 0 || bin >= nbins) fl |= 2;
+        }
+        if (fl != 0) {
+            atomicOr(flag, fl);
+            bin = 0;
+        }
+        const int64_t blk = k / block;
+        keys[k] = ((uint32_t)blk << bbits) | (uint32_t)bin;
+        vals[k] = (int32_t)k;
+        atomicAdd(&counts[blk * nbins + bin], 1);
+    }
+}
+
+// digit histogram of each tile: hist[d * ntiles + tile]
+__global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t *__restrict__ keys, int64_t n, int shift,
+                                                             int64_t ntiles, uint32_t *__restrict__ hist)
+{
+    __shared__ uint32_t cnt[kRadix];
+    const int tid = threadIdx.x;
+    cnt[tid] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    for (int r = 0; r < kSortItems; ++r) {
+        const int64_t e = base + (int64_t)r * kSortThreads + tid;
+        if (e < n) atomicAdd(&cnt[(keys[e] >> shift) & (kRadix - 1)], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)tid * ntiles + blockIdx.x] = cnt[tid];
+}
+
+// exclusive scan of hist[0 .. len) in place, one workgroup of 1024 threads:
+// each thread scans a contiguous segment, the segment totals are scanned in
+// LDS
+__global__ __launch_bounds__(1024) void k_radix_scan(uint32_t *__restrict__ hist, int64_t len)
+{
+    __shared__ uint32_t tot[1024];
+    const int tid = threadIdx.x;
+    const int64_t seg = (len + 1023) / 1024;
+    const int64_t a = std::min<int64_t>(len, (int64_t)tid * seg), b = std::min<int64_t>(len, a + seg);
+    uint32_t s = 0;
+    for (int64_t i = a; i < b; ++i) s += hist[i];
+    tot[tid] = s;
+    __syncthreads();
+    // Hillis-Steele inclusive scan of the 1024 totals
+    for (int d = 1; d < 1024; d <<= 1) {
+        const uint32_t add = tid >= d ? tot[tid - d] : 0u;
+        __syncthreads();
+        tot[tid] += add;
+        __syncthreads();
+    }
+    uint32_t run = tid > 0 ? tot[tid - 1] : 0u;
+    for (int64_t i = a; i < b; ++i) {
+        const uint32_t h = hist[i];
+        hist[i] = run;
+        run += h;
+    }
+}
+
+// stable scatter of one tile: elements are ranked in index order (round r,
+// then thread order) among the tile's elements of the same digit
+__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t *__restrict__ kin,
+                                                                const int32_t *__restrict__ vin, int64_t n,
+                                                                int shift, int64_t ntiles,
+                                                                const uint32_t *__restrict__ offs,
+                                                                uint32_t *__restrict__ kout,
+                                                                int32_t *__restrict__ vout)
+{
+    __shared__ uint32_t base_d[kRadix];           // tile's first output position of each digit
+    __shared__ uint32_t wcnt[kSortWaves][kRadix];  // elements of each digit in each wave, this round
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    base_d[tid] = offs[(int64_t)tid * ntiles + blockIdx.x];
+    for (int w = 0; w < kSortWaves; ++w) wcnt[w][tid] = 0;
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));   // lanes below this one
+    const int64_t tbase = (int64_t)blockIdx.x * kTile;
+    for (int r = 0; r < kSortItems; ++r) {
+        __syncthreads();   // base_d and wcnt settled (previous round's updates)
+        const int64_t e = tbase + (int64_t)r * kSortThreads + tid;
+        const bool valid = e < n;
+        uint32_t key = 0;
+        int32_t val = 0;
+        if (valid) {
+            key = kin[e];
+            val = vin[e];
+        }
+        const uint32_t d = (key >> shift) & (kRadix - 1);
+        // lanes of this wave holding the same digit
+        uint64_t mask = __ballot(valid);
+        for (int bit = 0; bit < 8; ++bit) {
+            const bool on = (d >> bit) & 1u;
+            const uint64_t bb = __ballot(on);
+            mask &= on ? bb : ~bb;
+        }
+        const int rank_w = __popcll(mask & lt);
+        if (valid && rank_w == 0) wcnt[wave][d] = (uint32_t)__popcll(mask);
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = base_d[d] + (uint32_t)rank_w;
+            for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
+            kout[pos] = key;
+            vout[pos] = val;
+        }
+        __syncthreads();
+        // thread tid advances digit tid past this round and clears its counts
+        uint32_t add = 0;
+        for (int w = 0; w < kSortWaves; ++w) {
+            add += wcnt[w][tid];
+            wcnt[w][tid] = 0;
+        }
+        base_d[tid] += add;
+    }
+}
+
+// sorted records: p-th point of the sorted order is node k = idx[p]
+__global__ void k_sorted_records(const double *__restrict__ x, const int32_t *__restrict__ idx, int64_t M,
+                                 double scale, int fp32, int32_t *__restrict__ perm, double *__restrict__ frac64,
+                                 PtRec *__restrict__ rec32)
+{
+    // the product and the difference rounded separately, as on the host (a
+    // fused multiply-subtract would give another offset in FP64)
+#pragma clang fp contract(off)
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < M; p += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t k = idx[p];
+        const double t = scale * x[k];
+        const double fr = t - cell_floor(t);
+        if (fp32) {
+            float f = (float)fr;
+            if (!(f < 1.0f)) f = 0.99999994f;   // keep the offset inside [0, 1)
+            PtRec r;
+            r.perm = k;
+            r.frac = f;
+            rec32[p] = r;
+        } else {
+            perm[p] = k;
+            frac64[p] = fr;
+        }
+    }
+}
+
+// FP32 records in per-slot transposed blocks: point q of item t of slot g at
+// (g rows + q) 64 + t; rows past an item's end repeat its last record; empty
+// items hold zeros
+__global__ void k_transpose_records(const PtRec *__restrict__ rec, const Item *__restrict__ items, int64_t nslot,
+                                    int rows, PtRec *__restrict__ out)
+{
+    const int64_t total = nslot * rows * kItemsPerWg;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int t = (int)(i % kItemsPerWg);
+        const int64_t gq = i / kItemsPerWg;
+        const int64_t g = gq / rows, q = gq % rows;
+        const Item it = items[g * kItemsPerWg + t];
+        PtRec r;
+        r.perm = 0;
+        r.frac = 0.f;
+        if (it.n > 0) r = rec[it.p0 + std::min<int64_t>(q, it.n - 1)];
+        out[i] = r;
+    }
+}
+
+__global__ void k_gather(const double *__restrict__ x, const int64_t *__restrict__ idx, int64_t n,
+                         double *__restrict__ out)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = x[idx[i]];
+}
+
+unsigned grid_for(int64_t n, int threads)
+{
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + threads - 1) / threads, 8192));
+}
+
+int bit_width(uint64_t v)
+{
+    int b = 0;
+    while (v > 0) {
+        ++b;
+        v >>= 1;
+    }
+    return b;
+}
+
+size_t al256(size_t n) { return (n + 255) & ~(size_t)255; }
+
+}  // namespace
+
+bool device_sort_fits(int64_t M, int64_t nbins, int64_t block)
+{
+    const int64_t nblocks = (M + block - 1) / block;
+    const int bbits = std::max(1, bit_width((uint64_t)(nbins - 1)));
+    return bbits + bit_width((uint64_t)(nblocks - 1)) <= 32 && M < ((int64_t)1 << 31);
+}
+
+size_t device_sort_tmp_bytes(int64_t M)
+{
+    const int64_t ntiles = (M + kTile - 1) / kTile;
+    return 2 * al256((size_t)M * 4) + 2 * al256((size_t)M * 4) + al256((size_t)kRadix * ntiles * 4) + 256;
+}
+
+hipError_t device_sort_nodes(const double *x, int64_t M, double scale, int64_t off, int64_t nbins, int64_t block,
+                             int32_t *counts, int32_t *flag, void *tmp, int32_t **sorted_idx, hipStream_t s)
+{
+    const int64_t nblocks = (M + block - 1) / block;
+    const int bbits = std::max(1, bit_width((uint64_t)(nbins - 1)));
+    const int kbits = bbits + bit_width((uint64_t)(nblocks - 1));
+    const int64_t ntiles = (M + kTile - 1) / kTile;
+    unsigned char *p = static_cast<unsigned char *>(tmp);
+    uint32_t *keys[2];
+    int32_t *vals[2];
+    keys[0] = reinterpret_cast<uint32_t *>(p);
+    p += al256((size_t)M * 4);
+    keys[1] = reinterpret_cast<uint32_t *>(p);
+    p += al256((size_t)M * 4);
+    vals[0] = reinterpret_cast<int32_t *>(p);
+    p += al256((size_t)M * 4);
+    vals[1] = reinterpret_cast<int32_t *>(p);
+    p += al256((size_t)M * 4);
+    uint32_t *hist = reinterpret_cast<uint32_t *>(p);
+    hipLaunchKernelGGL(k_node_keys, dim3(grid_for(M, 256)), dim3(256), 0, s, x, M, scale, off, nbins, block, bbits,
+                       keys[0], vals[0], counts, flag);
+    int cur = 0;
+    for (int shift = 0; shift < kbits; shift += 8) {
+        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)ntiles), dim3(kSortThreads), 0, s, keys[cur], M, shift,
+                           ntiles, hist);
+        hipLaunchKernelGGL(k_radix_scan, dim3(1), dim3(1024), 0, s, hist, (int64_t)kRadix * ntiles);
+        hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)ntiles), dim3(kSortThreads), 0, s, keys[cur], vals[cur],
+                           M, shift, ntiles, hist, keys[1 - cur], vals[1 - cur]);
+        cur = 1 - cur;
+    }
+    *sorted_idx = vals[cur];
+    return hipGetLastError();
+}
+
+hipError_t device_sorted_records(const double *x, const int32_t *sorted_idx, int64_t M, double scale, bool fp32,
+                                 int32_t *perm, double *frac64, PtRec *rec32, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sorted_records, dim3(grid_for(M, 256)), dim3(256), 0, s, x, sorted_idx, M, scale,
+                       fp32 ? 1 : 0, perm, frac64, rec32);
+    return hipGetLastError();
+}
+
+hipError_t device_transpose_records(const PtRec *rec32, const Item *launch_items, int64_t nslot, int rows,
+                                    PtRec *trec32, hipStream_t s)
+{
+    const int64_t total = nslot * rows * kItemsPerWg;
+    hipLaunchKernelGGL(k_transpose_records, dim3(grid_for(total, 256)), dim3(256), 0, s, rec32, launch_items, nslot,
+                       rows, trec32);
+    return hipGetLastError();
+}
+
+hipError_t device_gather(const double *x, const int64_t *idx, int64_t n, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gather, dim3(grid_for(n, 256)), dim3(256), 0, s, x, idx, n, out);
+    return hipGetLastError();
+}
+
+}  // namespace nnfft
