@@ -8,7 +8,9 @@
 #include <cstdlib>
 #include <cstring>
 #include <exception>
+#include <list>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <string>
@@ -26,11 +28,6 @@ using namespace nnfft;
 namespace {
 
 thread_local std::string g_last_error;
-
-struct HipError {
-    hipError_t err;
-    const char *what;
-};
 
 void hip_check(hipError_t e, const char *what)
 {
@@ -902,11 +899,10 @@ static void size_plan(HostPlan &H, const nnfft_info_t &P)
     H.info.fft_n2 = H.fd.n2;
 }
 
-// Algorithm 2.2 step 0 without the nodes: parameters, validations and the
-// FP64 tables (tap series, 1/phi_hat_1 series, phi_hat_2 deconvolution,
-// twiddles); H.info holds the parameters.
-static nnfft_status plan_params_tables(HostPlan &H, int64_t N, int64_t M1, int64_t M2, double sigma1,
-                                       double sigma2, int m1, int m2, nnfft_precision prec, int window)
+// Algorithm 2.2 step 0 without the nodes: parameters and their validation;
+// H.info holds the parameters.
+static nnfft_status plan_params(HostPlan &H, int64_t N, int64_t M1, int64_t M2, double sigma1, double sigma2,
+                                int m1, int m2, nnfft_precision prec, int window)
 {
     nnfft_info_t &P = H.info;
     P = nnfft_info_t{};
@@ -944,7 +940,19 @@ static nnfft_status plan_params_tables(HostPlan &H, int64_t N, int64_t M1, int64
     P.M2 = M2;
     P.precision = prec;
     H.fp32 = fp32;
+    return NNFFT_OK;
+}
 
+// The FP64 tables of a plan whose parameters plan_params set: window tap
+// series, the 1/phi_hat_1 series, the phi_hat_2 deconvolution and the
+// twiddles.  They depend on (N, sigma, m, precision, window) only and are
+// kept in a small cache, so plans of repeated parameters skip them.
+static nnfft_status plan_tables_compute(HostPlan &H)
+{
+    nnfft_info_t &P = H.info;
+    const bool fp32 = H.fp32;
+    const int m1 = P.m1, m2 = P.m2;
+    const int window = P.window;
     // tables in FP64 -----------------------------------------------------
     double e1 = 0.0, e2 = 0.0;
     if (fp32) {
@@ -993,6 +1001,90 @@ static nnfft_status plan_params_tables(HostPlan &H, int64_t N, int64_t M1, int64
     return NNFFT_OK;
 }
 
+// Cache of the tables of recent parameter sets (least recently used out).
+struct TableKey {
+    int64_t N;
+    double sigma1, sigma2;
+    int m1, m2, prec, window;
+    bool operator==(const TableKey &o) const
+    {
+        return N == o.N && sigma1 == o.sigma1 && sigma2 == o.sigma2 && m1 == o.m1 && m2 == o.m2 &&
+               prec == o.prec && window == o.window;
+    }
+};
+struct TableSet {
+    TableKey key;
+    int32_t window_degree, corr_degree;
+    double window_fit_err, corr_fit_err;
+    std::vector<float> C1, C2, tw32;
+    std::vector<double> T1, T2, corr, deconv, tw64;
+    size_t bytes = 0;
+};
+constexpr size_t kTableCacheEntries = 64;
+constexpr size_t kTableCacheBytes = (size_t)256 << 20;
+std::mutex g_tables_mu;
+std::list<std::shared_ptr<const TableSet>> g_tables;   // most recent first
+size_t g_tables_bytes = 0;
+
+static nnfft_status plan_tables(HostPlan &H)
+{
+    const nnfft_info_t &P = H.info;
+    const TableKey key{P.N, P.sigma1, P.sigma2, P.m1, P.m2, P.precision, P.window};
+    std::shared_ptr<const TableSet> hit;
+    {
+        std::lock_guard<std::mutex> g(g_tables_mu);
+        for (auto it = g_tables.begin(); it != g_tables.end(); ++it)
+            if ((*it)->key == key) {
+                hit = *it;
+                g_tables.splice(g_tables.begin(), g_tables, it);
+                break;
+            }
+    }
+    if (hit) {
+        H.info.window_degree = hit->window_degree;
+        H.info.window_fit_err = hit->window_fit_err;
+        H.info.corr_degree = hit->corr_degree;
+        H.info.corr_fit_err = hit->corr_fit_err;
+        H.C1 = hit->C1;
+        H.C2 = hit->C2;
+        H.T1 = hit->T1;
+        H.T2 = hit->T2;
+        H.corr = hit->corr;
+        H.deconv = hit->deconv;
+        H.tw64 = hit->tw64;
+        H.tw32 = hit->tw32;
+        return NNFFT_OK;
+    }
+    const nnfft_status st = plan_tables_compute(H);
+    if (st != NNFFT_OK) return st;
+    auto t = std::make_shared<TableSet>();
+    t->key = key;
+    t->window_degree = H.info.window_degree;
+    t->window_fit_err = H.info.window_fit_err;
+    t->corr_degree = H.info.corr_degree;
+    t->corr_fit_err = H.info.corr_fit_err;
+    t->C1 = H.C1;
+    t->C2 = H.C2;
+    t->T1 = H.T1;
+    t->T2 = H.T2;
+    t->corr = H.corr;
+    t->deconv = H.deconv;
+    t->tw64 = H.tw64;
+    t->tw32 = H.tw32;
+    t->bytes = 4 * (t->C1.size() + t->C2.size() + t->tw32.size()) +
+               8 * (t->T1.size() + t->T2.size() + t->corr.size() + t->deconv.size() + t->tw64.size());
+    if (t->bytes <= kTableCacheBytes / 4) {
+        std::lock_guard<std::mutex> g(g_tables_mu);
+        g_tables.push_front(t);
+        g_tables_bytes += t->bytes;
+        while (g_tables.size() > kTableCacheEntries || g_tables_bytes > kTableCacheBytes) {
+            g_tables_bytes -= g_tables.back()->bytes;
+            g_tables.pop_back();
+        }
+    }
+    return NNFFT_OK;
+}
+
 // The rest of step 0 once both node sides are laid out: FFT factorization
 // and tables, window planes, merge lists, sizes.
 static nnfft_status plan_finish(HostPlan &H)
@@ -1028,7 +1120,8 @@ nnfft_status plan_host(HostPlan &H, int64_t N, int64_t M1, int64_t M2, double si
                        int m1, int m2, nnfft_precision prec, const std::vector<double> &v,
                        const std::vector<double> &x, const Layout *lay1, const Layout *lay2, int window)
 {
-    nnfft_status st = plan_params_tables(H, N, M1, M2, sigma1, sigma2, m1, m2, prec, window);
+    nnfft_status st = plan_params(H, N, M1, M2, sigma1, sigma2, m1, m2, prec, window);
+    if (st == NNFFT_OK) st = plan_tables(H);
     if (st != NNFFT_OK) return st;
     const nnfft_info_t &P = H.info;
     const bool fp32 = H.fp32;
@@ -1340,121 +1433,188 @@ nnfft_status plan_create(const HostPlan &H, const DevMem &mem, hipStream_t s, nn
     return NNFFT_OK;
 }
 
-// Device memory of the node preparation of one side, released on scope exit.
-struct DevSideTmp {
-    void *mem = nullptr;
-    void *sort_tmp = nullptr;   // radix sort buffers (then the FP32 sorted records)
-    int32_t *counts = nullptr;  // [nblocks * nbins] bin counts of every node block
-    int32_t *flag = nullptr;    // domain flags
-    int64_t *sidx = nullptr;    // density sample indices
-    double *svals = nullptr;    // and values
-    int32_t *sorted = nullptr;  // caller indices in the stable (block, bin) order
-    DevSideTmp() = default;
-    DevSideTmp(const DevSideTmp &) = delete;
-    DevSideTmp &operator=(const DevSideTmp &) = delete;
-    ~DevSideTmp()
-    {
-        if (mem) (void)hipFree(mem);
-    }
-};
-
-// One side's node layout with the nodes x[M] on the device: the keys, the
-// domain check, the bin counts of the node blocks and the stable sort run on
-// the GPU; the host builds the items, chunks, window colours and launch
-// slots from the counts alone (block_schedule, finish_side, the same code as
-// the host layout, so both agree exactly); plan_create writes the records
-// from the sorted indices.  L: the side's layout (the rule, raised for dense
-// node sets from density samples gathered on the device).
-static nnfft_status build_side_device(const double *x, int64_t M, double scale, int64_t off, int64_t nbins,
-                                      bool fp32, bool spreading, int m, const char *what, Layout &L,
-                                      SideHost &S, DevSideTmp &T, hipStream_t s)
+NodePrepScratch::~NodePrepScratch()
 {
-    L = choose_layout(M, fp32, spreading);
-    const int64_t nblocks = (M + L.block - 1) / L.block;
-    const std::vector<int64_t> sidx = density_sample_indices(M, L, fp32);
-    auto al = [](size_t n) { return (n + 255) & ~(size_t)255; };
-    const size_t sort_b = al(device_sort_tmp_bytes(M)), cnt_b = al((size_t)nblocks * (size_t)nbins * 4);
-    const size_t smp_b = al(std::max<size_t>(1, sidx.size()) * 8);
-    if (hipMalloc(&T.mem, sort_b + cnt_b + 256 + 2 * smp_b) != hipSuccess) {
-        (void)hipGetLastError();
-        T.mem = nullptr;
-        return fail(NNFFT_ERR_NOMEM, "device memory for the node sort is not available");
-    }
-    unsigned char *p = static_cast<unsigned char *>(T.mem);
-    T.sort_tmp = p;
-    T.counts = reinterpret_cast<int32_t *>(p + sort_b);
-    T.flag = reinterpret_cast<int32_t *>(p + sort_b + cnt_b);
-    T.sidx = reinterpret_cast<int64_t *>(p + sort_b + cnt_b + 256);
-    T.svals = reinterpret_cast<double *>(p + sort_b + cnt_b + 256 + smp_b);
-    std::vector<int32_t> counts((size_t)nblocks * (size_t)nbins);
-    std::vector<double> svals(sidx.size());
-    int32_t flag = 0;
-    hip_check(hipMemsetAsync(T.counts, 0, cnt_b + 256, s), "hipMemsetAsync");
-    hip_check(device_sort_nodes(x, M, scale, off, nbins, L.block, T.counts, T.flag, T.sort_tmp, &T.sorted, s),
-              "node sort");
-    hip_check(hipMemcpyAsync(counts.data(), T.counts, counts.size() * 4, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
-    hip_check(hipMemcpyAsync(&flag, T.flag, 4, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
-    hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
-    if (flag & 1) return fail(NNFFT_ERR_DOMAIN, std::string(what) + " node outside [-1/2, 1/2]");
-    if (flag & 2) return fail(NNFFT_ERR_ARG, "internal: node record outside the grid");
-    if (!sidx.empty()) {
-        hip_check(hipMemcpyAsync(T.sidx, sidx.data(), sidx.size() * 8, hipMemcpyHostToDevice, s), "hipMemcpyAsync");
-        hip_check(device_gather(x, T.sidx, (int64_t)sidx.size(), T.svals, s), "density samples");
-        hip_check(hipMemcpyAsync(svals.data(), T.svals, svals.size() * 8, hipMemcpyDeviceToHost, s),
-                  "hipMemcpyAsync");
-        hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
-    }
-    L = raise_item_size(L, M, scale, fp32, svals.data());
-    S = SideHost{};
-    S.nblocks = nblocks;
-    S.rows = L.Q;
-    S.npts = M;
-    S.dev = true;
-    std::vector<BlockOut> outs((size_t)nblocks);
-    const int nthr = (M >= kParallelBlockPoints && nbins <= kParallelBlockBins) ? kBlockThreads : 1;
-    parallel_strided(nblocks, nthr, [&](int64_t blk, int) {
-        block_schedule(counts.data() + (size_t)blk * (size_t)nbins, nbins, blk * L.block, L.Q, outs[(size_t)blk]);
-    });
-    std::string err;
-    if (!finish_side(outs, m, S, err)) return fail(NNFFT_ERR_ARG, err);
-    if (fp32 && (int64_t)S.launch.size() * L.Q * kItemsPerWg >= ((int64_t)1 << 31))
-        return fail(NNFFT_ERR_ARG, "too many padded records");
-    return NNFFT_OK;
+    if (dev) (void)hipFree(dev);
+    if (pin) (void)hipHostFree(pin);
 }
 
-// nnfft_plan_window with the nodes on the device: both node sides prepared
-// on the device (build_side_device).  Sets *host and returns NNFFT_OK without
-// a plan where the sort keys do not fit 32 bits: the caller then plans on the
-// host.
-static nnfft_status plan_from_device_nodes(int64_t N, int64_t M1, int64_t M2, double sigma1, double sigma2, int m1,
-                                           int m2, nnfft_precision prec, int window, const double *v,
-                                           const double *x, hipStream_t s, nnfft_plan_t *out, bool *host)
+bool NodePrepScratch::reserve(size_t dev_need, size_t pin_need)
+{
+    if (dev_need > dev_bytes) {
+        if (dev) (void)hipFree(dev);
+        dev = nullptr;
+        dev_bytes = 0;
+        if (hipMalloc(&dev, dev_need) != hipSuccess) {
+            (void)hipGetLastError();
+            dev = nullptr;
+            return false;
+        }
+        dev_bytes = dev_need;
+    }
+    if (pin_need > pin_bytes) {
+        if (pin) (void)hipHostFree(pin);
+        pin = nullptr;
+        pin_bytes = 0;
+        if (hipHostMalloc(&pin, pin_need, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            pin = nullptr;
+            return false;
+        }
+        pin_bytes = pin_need;
+    }
+    return true;
+}
+
+namespace {
+
+// One node side being prepared on the device: inputs, layout and its parts
+// of the scratch memory.
+struct DevSide {
+    const double *x = nullptr;
+    int64_t M = 0, off = 0, nbins = 0, nblocks = 0;
+    double scale = 0.0;
+    bool spreading = false;
+    int m = 0;
+    const char *what = "";
+    Layout L;
+    std::vector<int64_t> sidx;          // density sample indices
+    size_t sort_b = 0, cnt_b = 0, smp_b = 0;
+    // device
+    void *sort_tmp = nullptr;
+    int32_t *counts = nullptr, *flag = nullptr, *sorted = nullptr;
+    int64_t *sidx_dev = nullptr;
+    double *svals_dev = nullptr;
+    // pinned host
+    int32_t *counts_h = nullptr, *flag_h = nullptr;
+    int64_t *sidx_h = nullptr;
+    double *svals_h = nullptr;
+};
+
+size_t al256(size_t n) { return (n + 255) & ~(size_t)255; }
+
+}  // namespace
+
+// Host plan of an NNFFT whose nodes are on the device.  Both node sides are
+// ordered on the GPU (keys with the domain check, bin counts of the node
+// blocks, the stable sort, density samples) while the host computes the
+// tables; after one synchronization the host builds both sides' schedules
+// from the counts alone (block_schedule, finish_side: the code of the host
+// layout, so both agree exactly), on two threads.  plan_create then writes
+// the point records on the device from R.  Sets *host and does nothing where
+// the sort keys do not fit 32 bits.
+nnfft_status plan_device_nodes(HostPlan &H, DevRecords &R, NodePrepScratch &T, int64_t N, int64_t M1, int64_t M2,
+                               double sigma1, double sigma2, int m1, int m2, nnfft_precision prec, int window,
+                               const double *v, const double *x, hipStream_t s, bool *host)
 {
     *host = false;
-    HostPlan H;
-    nnfft_status st = plan_params_tables(H, N, M1, M2, sigma1, sigma2, m1, m2, prec, window);
+    nnfft_status st = plan_params(H, N, M1, M2, sigma1, sigma2, m1, m2, prec, window);
     if (st != NNFFT_OK) return st;
     const nnfft_info_t &P = H.info;
     const bool fp32 = H.fp32;
-    const double scale1 = (double)P.N1 * (double)N / (double)P.N_star;
-    const double scale2 = (double)P.N2 * (double)P.N_star / (double)P.N1;
-    if (!device_sort_fits(M1, P.G1, choose_layout(M1, fp32, true).block) ||
-        !device_sort_fits(M2, P.N2 + 1, choose_layout(M2, fp32, false).block) ||
-        !(std::fabs(scale1) <= (double)((int64_t)1 << 26)) || !(std::fabs(scale2) <= (double)((int64_t)1 << 26))) {
-        *host = true;
-        return NNFFT_OK;
+    DevSide sd[2];
+    sd[0].x = v;
+    sd[0].M = M1;
+    sd[0].scale = (double)P.N1 * (double)N / (double)P.N_star;   // t_k = N1 v*_k
+    sd[0].off = P.G1 / 2;
+    sd[0].nbins = P.G1;
+    sd[0].spreading = true;
+    sd[0].m = m1;
+    sd[0].what = "frequency";
+    sd[1].x = x;
+    sd[1].M = M2;
+    sd[1].scale = (double)P.N2 * (double)P.N_star / (double)P.N1;   // u_j = N2 N* x_j / N1
+    sd[1].off = P.N2 / 2;
+    sd[1].nbins = P.N2 + 1;
+    sd[1].spreading = false;
+    sd[1].m = 0;
+    sd[1].what = "spatial";
+    size_t dev_need = 0, pin_need = 0;
+    for (DevSide &d : sd) {
+        d.L = choose_layout(d.M, fp32, d.spreading);
+        if (!device_sort_fits(d.M, d.nbins, d.L.block) || !(std::fabs(d.scale) <= (double)((int64_t)1 << 26))) {
+            *host = true;
+            return NNFFT_OK;
+        }
+        d.nblocks = (d.M + d.L.block - 1) / d.L.block;
+        d.sidx = density_sample_indices(d.M, d.L, fp32);
+        d.sort_b = al256(device_sort_tmp_bytes(d.M));
+        d.cnt_b = al256((size_t)d.nblocks * (size_t)d.nbins * 4);
+        d.smp_b = al256(std::max<size_t>(1, d.sidx.size()) * 8);
+        dev_need += d.sort_b + d.cnt_b + 256 + 2 * d.smp_b;
+        pin_need += d.cnt_b + 256 + 2 * d.smp_b;
     }
-    DevSideTmp T1, T2;
-    st = build_side_device(v, M1, scale1, P.G1 / 2, P.G1, fp32, true, m1, "frequency", H.lay1, H.sp, T1, s);
+    if (!T.reserve(dev_need, pin_need))
+        return fail(NNFFT_ERR_NOMEM, "memory for the node preparation is not available");
+    unsigned char *pd = static_cast<unsigned char *>(T.dev), *ph = static_cast<unsigned char *>(T.pin);
+    for (DevSide &d : sd) {
+        d.sort_tmp = pd;
+        d.counts = reinterpret_cast<int32_t *>(pd + d.sort_b);
+        d.flag = reinterpret_cast<int32_t *>(pd + d.sort_b + d.cnt_b);
+        d.sidx_dev = reinterpret_cast<int64_t *>(pd + d.sort_b + d.cnt_b + 256);
+        d.svals_dev = reinterpret_cast<double *>(pd + d.sort_b + d.cnt_b + 256 + d.smp_b);
+        pd += d.sort_b + d.cnt_b + 256 + 2 * d.smp_b;
+        d.counts_h = reinterpret_cast<int32_t *>(ph);
+        d.flag_h = reinterpret_cast<int32_t *>(ph + d.cnt_b);
+        d.sidx_h = reinterpret_cast<int64_t *>(ph + d.cnt_b + 256);
+        d.svals_h = reinterpret_cast<double *>(ph + d.cnt_b + 256 + d.smp_b);
+        ph += d.cnt_b + 256 + 2 * d.smp_b;
+        std::copy(d.sidx.begin(), d.sidx.end(), d.sidx_h);
+    }
+    // device work of both sides, then the tables on the host meanwhile
+    for (DevSide &d : sd) {
+        hip_check(hipMemsetAsync(d.counts, 0, d.cnt_b + 256, s), "hipMemsetAsync");
+        hip_check(device_sort_nodes(d.x, d.M, d.scale, d.off, d.nbins, d.L.block, d.counts, d.flag, d.sort_tmp,
+                                    &d.sorted, s),
+                  "node sort");
+        if (!d.sidx.empty()) {
+            hip_check(hipMemcpyAsync(d.sidx_dev, d.sidx_h, d.sidx.size() * 8, hipMemcpyHostToDevice, s),
+                      "hipMemcpyAsync");
+            hip_check(device_gather(d.x, d.sidx_dev, (int64_t)d.sidx.size(), d.svals_dev, s), "density samples");
+            hip_check(hipMemcpyAsync(d.svals_h, d.svals_dev, d.sidx.size() * 8, hipMemcpyDeviceToHost, s),
+                      "hipMemcpyAsync");
+        }
+        hip_check(hipMemcpyAsync(d.counts_h, d.counts, d.cnt_b + 256, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+    }
+    st = plan_tables(H);
+    hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
     if (st != NNFFT_OK) return st;
-    st = build_side_device(x, M2, scale2, P.N2 / 2, P.N2 + 1, fp32, false, 0, "spatial", H.lay2, H.ip, T2, s);
-    if (st != NNFFT_OK) return st;
+    for (DevSide &d : sd) {
+        if (*d.flag_h & 1) return fail(NNFFT_ERR_DOMAIN, std::string(d.what) + " node outside [-1/2, 1/2]");
+        if (*d.flag_h & 2) return fail(NNFFT_ERR_ARG, "internal: node record outside the grid");
+    }
+    SideHost *S[2] = {&H.sp, &H.ip};
+    Layout *Ls[2] = {&H.lay1, &H.lay2};
+    auto schedule = [&](int i, std::string &err) {
+        DevSide &d = sd[i];
+        d.L = raise_item_size(d.L, d.M, d.scale, fp32, d.svals_h);
+        *Ls[i] = d.L;
+        SideHost &Sd = *S[i];
+        Sd = SideHost{};
+        Sd.nblocks = d.nblocks;
+        Sd.rows = d.L.Q;
+        Sd.npts = d.M;
+        Sd.dev = true;
+        std::vector<BlockOut> outs((size_t)d.nblocks);
+        for (int64_t blk = 0; blk < d.nblocks; ++blk)
+            block_schedule(d.counts_h + (size_t)blk * (size_t)d.nbins, d.nbins, blk * d.L.block, d.L.Q,
+                           outs[(size_t)blk]);
+        if (!finish_side(outs, d.m, Sd, err)) return false;
+        if (fp32 && (int64_t)Sd.launch.size() * d.L.Q * kItemsPerWg >= ((int64_t)1 << 31)) {
+            err = "too many padded records";
+            return false;
+        }
+        return true;
+    };
+    std::string err;
+    if (!build_both_sides([&](std::string &e) { return schedule(0, e); }, [&](std::string &e) { return schedule(1, e); },
+                          std::min(M1, M2) >= kParallelSidePoints, err))
+        return fail(NNFFT_ERR_ARG, err);
     st = plan_finish(H);
     if (st != NNFFT_OK) return st;
-    DevRecords R;
-    R.sp = DevSideRecords{v, T1.sorted, scale1, T1.sort_tmp};
-    R.ip = DevSideRecords{x, T2.sorted, scale2, T2.sort_tmp};
-    return plan_create(H, hip_mem(), s, out, &R);
+    R.sp = DevSideRecords{v, sd[0].sorted, sd[0].scale, sd[0].sort_tmp};
+    R.ip = DevSideRecords{x, sd[1].sorted, sd[1].scale, sd[1].sort_tmp};
+    return NNFFT_OK;
 }
 
 nnfft_status copy_nodes(const double *d, int64_t n, std::vector<double> &h, hipStream_t s)
@@ -1615,11 +1775,17 @@ nnfft_status nnfft_plan_window(nnfft_plan_t *out, int64_t N, int64_t M1, int64_t
     try {
         hipStream_t s = static_cast<hipStream_t>(stream);
         bool host = false;
-        nnfft_status st = plan_from_device_nodes(N, M1, M2, sigma1, sigma2, m1, m2, prec, window, v, x, s, out, &host);
-        if (!host) return st;
+        {
+            NodePrepScratch T;
+            HostPlan H;
+            DevRecords R;
+            nnfft_status st = plan_device_nodes(H, R, T, N, M1, M2, sigma1, sigma2, m1, m2, prec, window, v, x, s,
+                                                &host);
+            if (!host) return st == NNFFT_OK ? plan_create(H, hip_mem(), s, out, &R) : st;
+        }
         // sort keys wider than 32 bits: the node layout is built on the host
         std::vector<double> hv, hx;
-        st = copy_nodes(v, M1, hv, s);
+        nnfft_status st = copy_nodes(v, M1, hv, s);
         if (st != NNFFT_OK) return st;
         st = copy_nodes(x, M2, hx, s);
         if (st != NNFFT_OK) return st;

@@ -13,6 +13,13 @@
 
 namespace nnfft {
 
+// A failed HIP call inside plan construction (thrown by the plan code,
+// turned into NNFFT_ERR_DEVICE at the C ABI).
+struct HipError {
+    hipError_t err;
+    const char *what;
+};
+
 // Records the message for nnfft_last_error (thread-local) and returns st.
 nnfft_status fail(nnfft_status st, const std::string &msg);
 
@@ -168,6 +175,28 @@ struct DevRecords {
 // dev, the sides marked dev get their records written on the device.
 nnfft_status plan_create(const HostPlan &H, const DevMem &mem, hipStream_t s, nnfft_plan_t *out,
                          const DevRecords *dev = nullptr);
+
+// Device and pinned host memory of the node preparation, reused across plans
+// (grown on demand, freed with the object).
+struct NodePrepScratch {
+    void *dev = nullptr;
+    size_t dev_bytes = 0;
+    void *pin = nullptr;
+    size_t pin_bytes = 0;
+    NodePrepScratch() = default;
+    NodePrepScratch(const NodePrepScratch &) = delete;
+    NodePrepScratch &operator=(const NodePrepScratch &) = delete;
+    ~NodePrepScratch();
+    bool reserve(size_t dev_need, size_t pin_need);
+};
+
+// Host plan of an NNFFT with device nodes v[M1], x[M2]: node order on the
+// device, schedule and tables on the host; R (pointing into T) feeds
+// plan_create, which must run before T is reused.  *host: the sort keys do
+// not fit 32 bits, nothing was done, plan on the host instead.
+nnfft_status plan_device_nodes(HostPlan &H, DevRecords &R, NodePrepScratch &T, int64_t N, int64_t M1, int64_t M2,
+                               double sigma1, double sigma2, int m1, int m2, nnfft_precision prec, int window,
+                               const double *v, const double *x, hipStream_t s, bool *host);
 
 // FNV-1a hash of a byte range (layout digests).
 uint64_t fnv1a64(const void *p, size_t n);

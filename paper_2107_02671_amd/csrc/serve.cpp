@@ -243,6 +243,7 @@ void nnfft_server_s::planner_loop()
 {
     hipStream_t s = nullptr;
     const bool have_stream = hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess;
+    NodePrepScratch prep;   // this planner's node-sort memory, reused request after request
     std::unique_lock<std::mutex> lk(mu);
     for (;;) {
         cv_pending.wait(lk, [&] { return stopping || !pending.empty(); });
@@ -289,30 +290,46 @@ void nnfft_server_s::planner_loop()
         ++planning;
         lk.unlock();
 
-        // host work: node copies and Algorithm 2.2 step 0
+        // Algorithm 2.2 step 0: NNFFT requests order their nodes on the device
+        // (planner stream) and schedule on the host; sinc requests (and keys
+        // wider than 32 bits) plan on the host from node copies
         nnfft_status status = have_stream ? NNFFT_OK : NNFFT_ERR_DEVICE;
         std::string err = have_stream ? "" : "planner stream";
         HostPlan H;
         SincHostPlan S;
+        DevRecords R;
+        bool dev_nodes = false;
         size_t bytes = 0;
         if (status == NNFFT_OK) {
             try {
-                std::vector<double> hv, hx;
-                status = copy_nodes(r.v, r.M1, hv, s);
-                if (status == NNFFT_OK) status = copy_nodes(r.x, r.M2, hx, s);
-                if (status == NNFFT_OK) {
-                    if (r.kind == NNFFT_REQ_SINC)
-                        status = sinc_host(S, r.N, r.M1, r.M2, (sinc_quad)r.quad, r.n_quad, r.sigma1, r.sigma2,
-                                           r.m1, r.m2, (nnfft_precision)r.precision, hv, hx);
-                    else
-                        status = plan_host(H, r.N, r.M1, r.M2, r.sigma1, r.sigma2, r.m1, r.m2,
-                                           (nnfft_precision)r.precision, hv, hx, nullptr, nullptr, r.window);
+                bool host = true;
+                if (r.kind != NNFFT_REQ_SINC) {
+                    status = plan_device_nodes(H, R, prep, r.N, r.M1, r.M2, r.sigma1, r.sigma2, r.m1, r.m2,
+                                               (nnfft_precision)r.precision, r.window, r.v, r.x, s, &host);
+                    dev_nodes = !host;
+                }
+                if (status == NNFFT_OK && host) {
+                    std::vector<double> hv, hx;
+                    H = HostPlan{};
+                    status = copy_nodes(r.v, r.M1, hv, s);
+                    if (status == NNFFT_OK) status = copy_nodes(r.x, r.M2, hx, s);
+                    if (status == NNFFT_OK) {
+                        if (r.kind == NNFFT_REQ_SINC)
+                            status = sinc_host(S, r.N, r.M1, r.M2, (sinc_quad)r.quad, r.n_quad, r.sigma1, r.sigma2,
+                                               r.m1, r.m2, (nnfft_precision)r.precision, hv, hx);
+                        else
+                            status = plan_host(H, r.N, r.M1, r.M2, r.sigma1, r.sigma2, r.m1, r.m2,
+                                               (nnfft_precision)r.precision, hv, hx, nullptr, nullptr, r.window);
+                    }
                 }
                 if (status != NNFFT_OK) err = nnfft_last_error();
                 // arena blocks are 256-byte granular: one per NNFFT plan, three per sinc plan
                 auto r256 = [](size_t b) { return (b + 255) & ~(size_t)255; };
                 bytes = r.kind == NNFFT_REQ_SINC ? r256(S.h1.total_bytes) + r256(S.h2.total_bytes) + r256(S.wg_bytes)
                                                  : r256(H.total_bytes);
+            } catch (const HipError &e) {
+                status = NNFFT_ERR_DEVICE;
+                err = std::string(e.what) + ": " + hipGetErrorString(e.err);
             } catch (const std::bad_alloc &) {
                 status = NNFFT_ERR_NOMEM;
                 err = "host allocation failed";
@@ -333,7 +350,7 @@ void nnfft_server_s::planner_loop()
             }
             lk.unlock();
             if (r.kind == NNFFT_REQ_SINC) status = sinc_create(S, mem, s, &q->splan);
-            else status = plan_create(H, mem, s, &q->plan);
+            else status = plan_create(H, mem, s, &q->plan, dev_nodes ? &R : nullptr);
             if (status != NNFFT_OK) err = nnfft_last_error();
             lk.lock();
             if (status == NNFFT_OK) break;

@@ -6,6 +6,7 @@
 // threads of its own on top of the two-sided builds, its threading.
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <random>
 #include <thread>
@@ -23,7 +24,7 @@ static int run(unsigned seed, bool small)
                                           : std::vector<int64_t>{1, 2, 63, 64, 65, 1000, 40000};
     for (int64_t M : Ms)
         for (int prec : {0, 1})
-            for (int win : {0, 1, 2})
+            for (int win : {0, 1, 2, 3})
                 for (int N : {2, 64, 333, 4096})
                     for (int m : {4, 6, 16})
                         for (int clustered : {0, 1}) {
@@ -65,6 +66,13 @@ static int run(unsigned seed, bool small)
         if (nnfft_plan_window_dry_run(4096, M, M, 2.0, 2.0, 6, 6, (nnfft_precision)prec, NNFFT_WINDOW_SINH, v.data(),
                                       x.data(), &info) != NNFFT_OK)
             ++refused;
+        // the layout image and its digest (tables cached by the first plan)
+        uint64_t d1 = 0, d2 = 0;
+        if (nnfft_plan_window_dry_run_digest(4096, M, M, 2.0, 2.0, 6, 6, (nnfft_precision)prec, NNFFT_WINDOW_SINH,
+                                             v.data(), x.data(), &d1) != NNFFT_OK ||
+            nnfft_plan_window_dry_run_digest(4096, M, M, 2.0, 2.0, 6, 6, (nnfft_precision)prec, NNFFT_WINDOW_SINH,
+                                             v.data(), x.data(), &d2) != NNFFT_OK || d1 != d2)
+            std::abort();
     }
     return refused;
 }
