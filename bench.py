@@ -281,12 +281,27 @@ def served_benchmark(P, W, torch, n_req, planners=12, budget=16 << 30):
     """The served request stream: closed loop for capacity, then Poisson
     arrivals.  Under Poisson arrivals a request's latency runs from its
     scheduled arrival (not from its submit call) to its completion, so time
-    the generator spends behind schedule counts against the server."""
+    the generator spends behind schedule counts against the server.
+
+    Request inputs are windows of seeded device pools (2^21 uniform nodes per
+    side, complex Gaussian coefficients in both precisions) at seeded random
+    offsets, so that submitting a request costs no generation work (the
+    server handle keeps each request's arrays referenced until it is
+    waited for)."""
     import threading
 
     import numpy as np
     dev = torch.device("cuda:0")
     reqs = W.served_requests(10000, seed=4)[:n_req]
+    pool = 1 << 21
+    g = torch.Generator(device=dev)
+    g.manual_seed(4_000_000)
+    v_pool = torch.rand(pool, dtype=torch.float64, device=dev, generator=g) - 0.5
+    x_pool = torch.rand(pool, dtype=torch.float64, device=dev, generator=g) - 0.5
+    f_pool = {True: torch.randn(pool, dtype=torch.complex64, device=dev, generator=g),
+              False: torch.randn(pool, dtype=torch.complex128, device=dev, generator=g)}
+    offs = W.rng(44).integers(0, pool - (1 << 20), (len(reqs), 2))
+    torch.cuda.synchronize()
 
     def run(rate):
         srv = P.Server(hbm_budget_bytes=budget, planner_threads=planners, streams=2)
@@ -314,8 +329,10 @@ def served_benchmark(P, W, torch, n_req, planners=12, budget=16 << 30):
                 while time.perf_counter() < t_sched[i]:
                     time.sleep(min(1e-3, max(0.0, t_sched[i] - time.perf_counter())))
             window.acquire()
-            v, x, f, y = request_inputs(torch, r, r["fp32"], dev)
-            torch.cuda.current_stream().synchronize()
+            o1, o2 = int(offs[i, 0]), int(offs[i, 1])
+            v, x = v_pool[o1:o1 + r["M1"]], x_pool[o2:o2 + r["M2"]]
+            f = f_pool[r["fp32"]][o1:o1 + r["M1"]]
+            y = torch.empty(r["M2"], dtype=f.dtype, device=dev)
             prec = P.NNFFT_FP32_COMP if r["fp32"] else P.NNFFT_FP64_PLAIN
             t_sub[i] = time.perf_counter()
             tickets[i] = srv.submit(r["N"], v, x, f, y, sigma1=2.0, sigma2=2.0, m1=r["m"], m2=r["m"], prec=prec)

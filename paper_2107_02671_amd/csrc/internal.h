@@ -93,6 +93,7 @@ struct FftArgs {
     int32_t mode;             // 0 NNFFT, 1 NFFT, 2 adjoint NFFT (see fft_input32)
     int32_t Nout;             // NFFT: number of frequencies N
     int32_t npassA, npassB;
+    int32_t fusedB;           // 1: no stage B launch, interpolation folds it in
     int32_t nplanes;          // planes of spreading windows summed for every cell
     int32_t slotT, slotP;     // plane cell c at slot (c mod T) P + c div T
     int8_t radA[kMaxPasses];  // radices of the length-n2 transform (or of N2)
@@ -111,6 +112,12 @@ struct InterpArgs {
                               // Kaiser-Bessel windows: [nser] power series in 1 - u^2
     const double *corr;       // series of 1/phi_hat_1 in t = 8 x^2 - 1 (FP32: kCorr32 + 1 terms)
     const void *hlin;
+    // second four-step stage folded into the window load (fusedB > 0): h_s =
+    // sum_{j1 < n1} Y[k2 n1 + j1] exp(-2 pi i j1 k1 / n1), k = s mod N2 =
+    // k2 + n2 k1, with Y the first stage's output and twB its [n1] twiddles
+    const void *Y;
+    const void *twB;
+    int32_t fusedB, fn2;      // n1 (0: read hlin) and n2 of the fold
     double beta, inv_den;
     double u_to_x;            // x_j = u_j * u_to_x, u_j = N2 N* x_j / N1
     int32_t m, ngrid;

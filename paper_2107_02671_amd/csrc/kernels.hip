@@ -228,6 +228,48 @@ __device__ __forceinline__ double inv_phi1_fixed(const double *__restrict__ c, d
 // (the fast sinc transform's quadrature weights, step 2 of its Algorithm 6.1,
 // folded into the load: the same products in the same precision as a
 // separate scaling pass, in FP64 and rounded once).
+// Output s (a label, |s| <= N2/2) of the length-N2 transform whose second
+// four-step stage is folded into the interpolation: with k = s mod N2 =
+// k2 + n2 k1, h_s = sum_{j1 < n1} Y[k2 n1 + j1] exp(-2 pi i j1 k1 / n1), Y the
+// first stage's output (its row k2 is contiguous).
+// The sum is evaluated by Horner's rule in w = exp(-2 pi i k1 / n1) (one
+// twiddle; the row is read with 16-byte loads).
+template <typename T, int N1>
+__device__ __forceinline__ cx<T> folded_row(const cx<T> *__restrict__ row, cx<T> w)
+{
+    cx<T> y[N1];
+    if constexpr (sizeof(T) == 4) {
+        const float4 *r4 = reinterpret_cast<const float4 *>(row);
+#pragma unroll
+        for (int j = 0; j < N1 / 2; ++j) {
+            const float4 v = r4[j];
+            y[2 * j] = cxmk(v.x, v.y);
+            y[2 * j + 1] = cxmk(v.z, v.w);
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < N1; ++j) y[j] = row[j];
+    }
+    cx<T> acc = y[N1 - 1];
+#pragma unroll
+    for (int j = N1 - 2; j >= 0; --j) acc = cmul(acc, w) + y[j];
+    return acc;
+}
+
+template <typename T>
+__device__ __forceinline__ cx<T> folded_output(const InterpArgs &A, int s)
+{
+    const int n1 = A.fusedB, n2 = A.fn2, N2 = A.N2;
+    const int k = s < 0 ? s + N2 : s;
+    const int k1 = k / n2, k2 = k - k1 * n2;
+    const cx<T> *__restrict__ row = reinterpret_cast<const cx<T> *>(A.Y) + (size_t)k2 * n1;
+    const cx<T> w = reinterpret_cast<const cx<T> *>(A.twB)[k1];
+    if (n1 == 16) return folded_row<T, 16>(row, w);
+    cx<T> acc = row[n1 - 1];
+    for (int j = n1 - 2; j >= 0; --j) acc = cmul(acc, w) + row[j];
+    return acc;
+}
+
 __device__ __forceinline__ cx<float> coef32(const cx<float> *__restrict__ f, const double *__restrict__ w, int k)
 {
     const cx<float> v = f[k];
@@ -608,8 +650,10 @@ __device__ __forceinline__ void interp32_slot(const InterpArgs &A, cx<float> *__
     cx<float> hw0 = cxmk(0.f, 0.f);
     float c0 = 0.f, c1 = 0.f;
     const int nwin = ch.nbin + tm - 1, nc = tm * (D + 1);
-    if (threadIdx.x < nwin)
-        hw0 = reinterpret_cast<const cx<float> *>(A.hlin)[ch.bin_lo - A.ip_off - m + 1 + A.h_off + threadIdx.x];
+    if (threadIdx.x < nwin) {
+        const int s = ch.bin_lo - A.ip_off - m + 1 + threadIdx.x;   // label of window value
+        hw0 = A.fusedB ? folded_output<float>(A, s) : reinterpret_cast<const cx<float> *>(A.hlin)[s + A.h_off];
+    }
     if (threadIdx.x < nc) c0 = A.C[threadIdx.x];
     if (threadIdx.x + kThreads32 < nc) c1 = A.C[threadIdx.x + kThreads32];
     const Item it = A.items[g * kItemsPerWg + t];   // before the records: waited for first
@@ -730,8 +774,10 @@ __device__ void interp64_slot(const InterpArgs &A, cx<double> *__restrict__ y, i
     const int m = A.m, tm = 2 * m;
     const int nwin = ch.nbin + tm - 1;   // < 64 + 2m <= kThreads64
     cx<double> hv0 = cxmk(0.0, 0.0);
-    if (threadIdx.x < nwin)
-        hv0 = reinterpret_cast<const cx<double> *>(A.hlin)[ch.bin_lo - A.ip_off - m + 1 + A.h_off + threadIdx.x];
+    if (threadIdx.x < nwin) {
+        const int s = ch.bin_lo - A.ip_off - m + 1 + threadIdx.x;   // label of window value
+        hv0 = A.fusedB ? folded_output<double>(A, s) : reinterpret_cast<const cx<double> *>(A.hlin)[s + A.h_off];
+    }
     const Item it = A.items[g * kItemsPerWg + t];
     if (threadIdx.x < nwin) L.hw[threadIdx.x] = hv0;
     __syncthreads();
@@ -1420,7 +1466,7 @@ static void launch_fft(const FftArgs &A, hipStream_t s, KernelTimes *kt = nullpt
     } else {
         const int gA = fft_groups(A.n1, A.batchA), gB = fft_groups(A.n2, A.batchB);
         launch_k(kt, KID_FFT_A, k_fft_stageA<T>, dim3(gA), dim3(A.threadsA), lds, s, A);
-        launch_k(kt, KID_FFT_B, k_fft_stageB<T>, dim3(gB), dim3(A.threadsB), lds, s, A);
+        if (!A.fusedB) launch_k(kt, KID_FFT_B, k_fft_stageB<T>, dim3(gB), dim3(A.threadsB), lds, s, A);
     }
 }
 
@@ -1518,7 +1564,7 @@ hipError_t launch_exec_batch(int n, const PlanDev *const *host, const PlanDev *c
                 thrA = std::max(thrA, P.fft.threadsA);
             } else {
                 sA += fft_groups(P.fft.n1, P.fft.batchA);
-                sB += fft_groups(P.fft.n2, P.fft.batchB);
+                if (!P.fft.fusedB) sB += fft_groups(P.fft.n2, P.fft.batchB);
                 thrA = std::max(thrA, P.fft.threadsA);
                 thrB = std::max(thrB, P.fft.threadsB);
             }
@@ -1665,6 +1711,7 @@ hipError_t launch_exec_static(const PlanDev &P, const ExecScratch &sz, const voi
     D.fft.Y = Y;
     D.fft.hlin = hlin;
     D.ip.hlin = hlin;
+    if (D.ip.fusedB) D.ip.Y = Y;
     // the array keeps the previous call's contents: plane cells that no
     // window of this plan writes must read as zero (a fill kernel, so the
     // call stays capturable in a graph)

@@ -746,6 +746,13 @@ void layout_plan(const HostPlan &H, Carver &C, PlanDev &D, size_t *upload_end, P
     FA.S = H.fd.S;
     FA.npassA = H.fd.npassA;
     FA.npassB = H.fd.npassB;
+    FA.fusedB = H.fd.fusedB ? 1 : 0;
+    if (H.fd.fusedB) {
+        IA.Y = FA.Y;
+        IA.twB = FA.twB;
+        IA.fusedB = H.fd.n1;
+        IA.fn2 = H.fd.n2;
+    }
     for (int i = 0; i < kMaxPasses; ++i) {
         FA.radA[i] = (int8_t)H.fd.radA[i];
         FA.radB[i] = (int8_t)H.fd.radB[i];
@@ -836,6 +843,15 @@ static void fft_tables(HostPlan &H)
 }
 
 // FFT factorization of the length-N2 transform; outputs |s| <= S are stored.
+// NNFFT plans with 1024 < N2 <= 4096 split N2 = 16 n2: stage A runs 16
+// length-n2 transforms (n2 <= 256, one cell per thread) and the
+// interpolation evaluates the 16-point second stage for the <= 64 + 2m
+// outputs each of its workgroups reads, so the transform takes one launch.
+// Longer transforms keep the two-launch split: 16 stage-A workgroups then
+// merge too many window planes each (measured slower at N2 = 16384).
+constexpr int kFusedN1 = 16;
+constexpr int64_t kFusedMaxN2 = 4096;
+
 static nnfft_status plan_fft(HostPlan &H, const nnfft_info_t &P, bool fp32, int64_t S)
 {
     // FFT factorization -----------------------------------------------------
@@ -861,7 +877,14 @@ static nnfft_status plan_fft(HostPlan &H, const nnfft_info_t &P, bool fp32, int6
         fd.threadsA = 256;
     } else {
         int64_t n1, n2;
-        if (!fft_factor(P.N2, kvals, n1, n2)) return fail(NNFFT_ERR_UNSUPPORTED, "FFT length cannot be split");
+        const bool fuse = H.kind == 0 && P.N2 <= kFusedMaxN2 && P.N2 % kFusedN1 == 0;
+        if (fuse) {
+            n1 = kFusedN1;
+            n2 = P.N2 / kFusedN1;
+        } else if (!fft_factor(P.N2, kvals, n1, n2)) {
+            return fail(NNFFT_ERR_UNSUPPORTED, "FFT length cannot be split");
+        }
+        fd.fusedB = fuse;
         const std::vector<int> rA = radix_passes(n2), rB = radix_passes(n1);
         if (rA.empty() || rB.empty() || (int)rA.size() > kMaxPasses || (int)rB.size() > kMaxPasses)
             return fail(NNFFT_ERR_UNSUPPORTED, "FFT length not 2,3,5-smooth");
@@ -871,7 +894,7 @@ static nnfft_status plan_fft(HostPlan &H, const nnfft_info_t &P, bool fp32, int6
         fd.npassB = (int32_t)rB.size();
         std::copy(rA.begin(), rA.end(), fd.radA);
         std::copy(rB.begin(), rB.end(), fd.radB);
-        fd.batchA = (int32_t)std::max<int64_t>(1, std::min<int64_t>(n1 / 128, kvals / n2));
+        fd.batchA = fuse ? 1 : (int32_t)std::max<int64_t>(1, std::min<int64_t>(n1 / 128, kvals / n2));
         fd.batchB = (int32_t)std::max<int64_t>(1, std::min<int64_t>(n2 / 128, kvals / n1));
         fd.threadsA = threads_for((int64_t)fd.batchA * n2);
         fd.threadsB = threads_for((int64_t)fd.batchB * n1);

@@ -77,6 +77,7 @@ struct FftPlan {
     int32_t N2 = 0, n1 = 0, n2 = 0, npassA = 0, npassB = 0;
     int radA[kMaxPasses] = {}, radB[kMaxPasses] = {};
     int32_t batchA = 0, batchB = 0, threadsA = 0, threadsB = 0, S = 0;
+    bool fusedB = false;   // stage B folded into the interpolation's window load
 };
 
 // Everything of one plan that is computed on the host, and the size of the
