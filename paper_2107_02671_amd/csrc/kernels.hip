@@ -353,64 +353,95 @@ __device__ __forceinline__ void add_moments(float *mr, float *mi, cx<float> fv, 
 //  B2: thread (w, bin) forms taps r = w, w + 4, ...: sum_k C[r][k] M_k;
 //  C: window cell c (grid cell bin_lo - m + 1 + c) = two-sum over r of tap r
 //     of bin c - r, stored as (hi.re, hi.im, lo.re, lo.im).
-template <int TM>
-__device__ void spread32_slot(const SpreadArgs &A, const cx<float> *__restrict__ f, int g, Spread32Lds<TM> &L)
-{
-    constexpr int D = kDeg;
-    // the wave index, known to the compiler as wave-uniform (scalar branches)
-    const int t = threadIdx.x & (kItemsPerWg - 1), w = __builtin_amdgcn_readfirstlane(threadIdx.x / kItemsPerWg);
-    const int rows = A.rows, rpw = (rows + kWaves32 - 1) / kWaves32, row0 = w * rpw;
-    // this wave's record rows and the item are loaded first, then the
-    // coefficient gathers of the rows that hold points of the item (rows past
-    // an item's end repeat its last record and are not gathered)
-    const PtRec *__restrict__ rec = A.rec32 + (size_t)g * rows * kItemsPerWg + t;
+// (All of a workgroup's loads are issued before any arithmetic; the kernel
+// is VALU- and latency-bound, one chunk per workgroup with all chunks
+// resident at once: a persistent variant that prefetched the next chunk
+// during the LDS phases measured 2.4x slower.)
+
+// per-thread registers of a chunk's loads: this wave's record rows of item
+// t, the item, and the gathered coefficients of the rows that hold points
+struct Spread32Regs {
     PtRec r[kRowsPerWave];
     cx<float> fv[kRowsPerWave];
+    Item it;
+};
+
+__device__ __forceinline__ void spread32_load_records(const SpreadArgs &A, int g, Spread32Regs &R)
+{
+    const int t = threadIdx.x & (kItemsPerWg - 1), w = __builtin_amdgcn_readfirstlane(threadIdx.x / kItemsPerWg);
+    const int rows = A.rows, rpw = (rows + kWaves32 - 1) / kWaves32, row0 = w * rpw;
+    const PtRec *__restrict__ rec = A.rec32 + (size_t)g * rows * kItemsPerWg + t;
 #pragma unroll
     for (int j = 0; j < kRowsPerWave; ++j) {   // rpw is uniform: rows past it are not loaded
-        r[j] = PtRec{0, 0.f};
-        if (j < rpw) r[j] = rec[wave_row(row0, j, rpw, rows) * kItemsPerWg];
+        R.r[j] = PtRec{0, 0.f};
+        if (j < rpw) R.r[j] = rec[wave_row(row0, j, rpw, rows) * kItemsPerWg];
     }
-    const Item it = A.items[g * kItemsPerWg + t];
+    R.it = A.items[g * kItemsPerWg + t];
+}
+
+// rows past an item's end repeat its last record and are not gathered
+__device__ __forceinline__ void spread32_gather(const SpreadArgs &A, const cx<float> *__restrict__ f,
+                                                Spread32Regs &R)
+{
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kItemsPerWg);
+    const int rows = A.rows, rpw = (rows + kWaves32 - 1) / kWaves32, row0 = w * rpw;
 #pragma unroll
     for (int j = 0; j < kRowsPerWave; ++j)
-        fv[j] = (j < rpw && row0 + j < it.n) ? coef32(f, A.wts, r[j].perm) : cxmk(0.f, 0.f);
-    const Chunk ch = A.chunks[g];
-    if (ch.nitem == 0) return;
-    const int m = A.m, tm = 2 * m;
-    stage_taps(L.C, A.C, tm);   // read after the barriers below
+        R.fv[j] = (j < rpw && row0 + j < R.it.n) ? coef32(f, A.wts, R.r[j].perm) : cxmk(0.f, 0.f);
+}
+
+// Phase A arithmetic: this wave's item moments into LDS (and the item's bin);
+// the run bounds of the bins are cleared.  Rows past the first batch of
+// kRowsPerWave (items longer than 4 kRowsPerWave points) are loaded here.
+template <int TM>
+__device__ __forceinline__ void spread32_moments(const SpreadArgs &A, const cx<float> *__restrict__ f, int g,
+                                                 const Chunk &ch, Spread32Regs &R, Spread32Lds<TM> &L)
+{
+    constexpr int D = kDeg;
+    const int t = threadIdx.x & (kItemsPerWg - 1), w = __builtin_amdgcn_readfirstlane(threadIdx.x / kItemsPerWg);
+    const int rows = A.rows, rpw = (rows + kWaves32 - 1) / kWaves32, row0 = w * rpw;
+    const PtRec *__restrict__ rec = A.rec32 + (size_t)g * rows * kItemsPerWg + t;
     if (w == 0 && t < ch.nbin) {   // empty run unless an item of the bin sets it
         L.runS[t] = 0;
         L.runE[t] = 0;
     }
-    {
-        float mr[D + 1], mi[D + 1];
+    float mr[D + 1], mi[D + 1];
 #pragma unroll
-        for (int k = 0; k <= D; ++k) mr[k] = mi[k] = 0.f;
-        const int nq = min(rpw, it.n - row0);   // this wave's points of the item
-        for (int j0 = 0; j0 < nq; j0 += kRowsPerWave) {
-            if (j0 > 0) {
+    for (int k = 0; k <= D; ++k) mr[k] = mi[k] = 0.f;
+    const int nq = min(rpw, R.it.n - row0);   // this wave's points of the item
+    for (int j0 = 0; j0 < nq; j0 += kRowsPerWave) {
+        if (j0 > 0) {
 #pragma unroll
-                for (int j = 0; j < kRowsPerWave; ++j) r[j] = rec[wave_row(row0, j0 + j, rpw, rows) * kItemsPerWg];
-#pragma unroll
-                for (int j = 0; j < kRowsPerWave; ++j)
-                    fv[j] = (j0 + j < nq) ? coef32(f, A.wts, r[j].perm) : cxmk(0.f, 0.f);
-            }
+            for (int j = 0; j < kRowsPerWave; ++j) R.r[j] = rec[wave_row(row0, j0 + j, rpw, rows) * kItemsPerWg];
 #pragma unroll
             for (int j = 0; j < kRowsPerWave; ++j)
-                if (j0 + j < nq) add_moments(mr, mi, fv[j], fmaf(2.f, r[j].frac, -1.f));
+                R.fv[j] = (j0 + j < nq) ? coef32(f, A.wts, R.r[j].perm) : cxmk(0.f, 0.f);
         }
 #pragma unroll
-        for (int k = 0; k <= D; ++k) L.mom[w][k][t] = cxmk(mr[k], mi[k]);
-        if (w == 0 && it.n > 0) L.ibin[t] = it.bin - ch.bin_lo;
+        for (int j = 0; j < kRowsPerWave; ++j)
+            if (j0 + j < nq) add_moments(mr, mi, R.fv[j], fmaf(2.f, R.r[j].frac, -1.f));
     }
-    __syncthreads();
+#pragma unroll
+    for (int k = 0; k <= D; ++k) L.mom[w][k][t] = cxmk(mr[k], mi[k]);
+    if (w == 0 && R.it.n > 0) L.ibin[t] = R.it.bin - ch.bin_lo;
+}
+
+// Phases B1, B2, C: bin moments, taps, window cells (the tap coefficients
+// are in L.C).  Barriers order LDS only, so loads issued before stay in
+// flight.
+template <int TM>
+__device__ __forceinline__ void spread32_cells(const SpreadArgs &A, const Chunk &ch, Spread32Lds<TM> &L)
+{
+    constexpr int D = kDeg;
+    const int t = threadIdx.x & (kItemsPerWg - 1), w = __builtin_amdgcn_readfirstlane(threadIdx.x / kItemsPerWg);
+    const int m = A.m, tm = 2 * m;
+    lds_barrier();
     if (w == 0 && t < ch.nitem) {
         const int b = L.ibin[t];
         if (t == 0 || L.ibin[t - 1] != b) L.runS[b] = t;
         if (t == ch.nitem - 1 || L.ibin[t + 1] != b) L.runE[b] = t + 1;
     }
-    __syncthreads();
+    lds_barrier();
     if (t < ch.nbin) {
         const int s = L.runS[t], e = L.runE[t];   // s = e for a bin without items
         constexpr int KW = (D + kWaves32) / kWaves32;   // moments per wave (3; the last one
@@ -435,7 +466,7 @@ __device__ void spread32_slot(const SpreadArgs &A, const cx<float> *__restrict__
         for (int j = 0; j < KW; ++j)
             if (w + kWaves32 * j <= D) L.bmom[w + kWaves32 * j][t] = cxmk(hr[j] + lr[j], hi[j] + li[j]);
     }
-    __syncthreads();
+    lds_barrier();
     if (t < ch.nbin) {
         float Mr[D + 1], Mi[D + 1];
 #pragma unroll
@@ -455,7 +486,7 @@ __device__ void spread32_slot(const SpreadArgs &A, const cx<float> *__restrict__
             L.sbin[r0][t] = cxmk(ar, ai);
         }
     }
-    __syncthreads();
+    lds_barrier();
     const int W = ch.nbin + tm - 1;
     float4 *part = reinterpret_cast<float4 *>(A.partial);
     for (int wc = threadIdx.x; wc < W; wc += blockDim.x) {
@@ -476,6 +507,20 @@ __device__ void spread32_slot(const SpreadArgs &A, const cx<float> *__restrict__
         }
         part[window_index(ch, wc, m, A.slotT, A.slotP)] = make_float4(hr, hi, lr, li);
     }
+}
+
+// One chunk, one workgroup (the batched kernel's body)
+template <int TM>
+__device__ void spread32_slot(const SpreadArgs &A, const cx<float> *__restrict__ f, int g, Spread32Lds<TM> &L)
+{
+    Spread32Regs R;
+    spread32_load_records(A, g, R);
+    spread32_gather(A, f, R);
+    const Chunk ch = A.chunks[g];
+    if (ch.nitem == 0) return;
+    stage_taps(L.C, A.C, 2 * A.m);   // read after the barriers below
+    spread32_moments<TM>(A, f, g, ch, R, L);
+    spread32_cells<TM>(A, ch, L);
 }
 
 // One workgroup per launch slot (slot g runs on XCD g mod 8).  At least 6
