@@ -51,9 +51,13 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
+# the sources of the exec kernels whose traffic the counter runs measured
+KERNEL_SOURCES = ["kernels.hip", "internal.h"]
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for name in sorted(os.listdir(os.path.join(ROOT, "paper_2107_02671_amd", "csrc"))):
+    for name in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_2107_02671_amd", "csrc", name), "rb") as fh:
             h.update(name.encode())
             h.update(fh.read())
@@ -71,6 +75,33 @@ def measured_traffic():
     if t.get("source_sha256") != kernel_source_hash():
         return {}
     return {k: float(v["bytes_per_launch"]) for k, v in t.get("kernels", {}).items()}
+
+
+PROFILE_STATS = os.path.join(ROOT, "profiles", "nnfft_large_kernel_stats.txt")
+
+
+def profiled_kernel_avg_ms():
+    """Average kernel durations (ms) of the FP32 headline kernels in the
+    committed rocprofv3 kernel-trace summary, if it was taken on the current
+    kernel sources (else {})."""
+    import csv
+    import re
+    try:
+        with open(PROFILE_STATS) as fh:
+            text = fh.read()
+    except OSError:
+        return {}
+    if kernel_source_hash()[:16] not in text:
+        return {}
+    out = {}
+    rows = [ln for ln in text.splitlines() if ln and not ln.startswith("#")]
+    for r in csv.DictReader(rows):
+        name = r["Name"]
+        mt = re.search(r"nnfft::(k_\w+)", name)
+        if not mt or "double" in name or "64" in mt.group(1):
+            continue
+        out.setdefault(mt.group(1), float(r["AverageNs"]) * 1e-6)
+    return out
 
 
 def cpu_model() -> str:
@@ -489,10 +520,16 @@ def main() -> int:
     kt = roofline_table(kern32, M1, M2, info32, 8, traffic)
     dom = max(kt, key=lambda k: kt[k]["avg_ms"])
     d = kt[dom]
+    prof = profiled_kernel_avg_ms()
+    for k, v in kt.items():
+        if k in prof:
+            v["profile_avg_ms"] = prof[k]
+            v["frac_from_profile"] = v["algorithmic_bytes"] / (prof[k] * 1e-3) / 1e9 / HBM_PEAK_GBS
     out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": d["achieved_GBs"], "peak": HBM_PEAK_GBS,
                        "unit": "GB/s", "frac": d["frac"], "traffic": d["traffic"],
                        "algorithmic_bytes_per_launch": d["algorithmic_bytes"], "avg_launch_ms": d["avg_ms"],
                        "launches_timed": args.steps,
+                       "profile_avg_ms": d.get("profile_avg_ms"), "frac_from_profile": d.get("frac_from_profile"),
                        "timing": "HIP events attached to each kernel dispatch (hipExtLaunchKernel) over "
                                  "as many execs as the timed steps, on the exec stream",
                        "kernels": kt}
