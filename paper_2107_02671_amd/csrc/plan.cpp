@@ -1491,6 +1491,35 @@ bool NodePrepScratch::reserve(size_t dev_need, size_t pin_need)
 
 namespace {
 
+// Node-sort scratch of nnfft_plan calls, kept between calls (a plan of up to
+// 2^22 points per side fits the kept ones; larger ones are released after
+// their plan): each call leases one, concurrent calls get their own.
+// (The pool is never destroyed: its memory goes with the process, not with a
+// static destructor that could run after the HIP runtime's own teardown.)
+constexpr size_t kKeptScratchBytes = (size_t)256 << 20;
+std::mutex g_scratch_mu;
+std::vector<std::unique_ptr<NodePrepScratch>> &g_scratch_pool = *new std::vector<std::unique_ptr<NodePrepScratch>>();
+
+struct ScratchLease {
+    std::unique_ptr<NodePrepScratch> s;
+    ScratchLease()
+    {
+        std::lock_guard<std::mutex> g(g_scratch_mu);
+        if (!g_scratch_pool.empty()) {
+            s = std::move(g_scratch_pool.back());
+            g_scratch_pool.pop_back();
+        }
+        if (!s) s.reset(new NodePrepScratch());
+    }
+    ~ScratchLease()
+    {
+        if (s->dev_bytes > kKeptScratchBytes) return;   // freed with s
+        std::lock_guard<std::mutex> g(g_scratch_mu);
+        if (g_scratch_pool.size() < 4) g_scratch_pool.push_back(std::move(s));
+    }
+    NodePrepScratch &operator*() { return *s; }
+};
+
 // One node side being prepared on the device: inputs, layout and its parts
 // of the scratch memory.
 struct DevSide {
@@ -1799,10 +1828,10 @@ nnfft_status nnfft_plan_window(nnfft_plan_t *out, int64_t N, int64_t M1, int64_t
         hipStream_t s = static_cast<hipStream_t>(stream);
         bool host = false;
         {
-            NodePrepScratch T;
+            ScratchLease T;
             HostPlan H;
             DevRecords R;
-            nnfft_status st = plan_device_nodes(H, R, T, N, M1, M2, sigma1, sigma2, m1, m2, prec, window, v, x, s,
+            nnfft_status st = plan_device_nodes(H, R, *T, N, M1, M2, sigma1, sigma2, m1, m2, prec, window, v, x, s,
                                                 &host);
             if (!host) return st == NNFFT_OK ? plan_create(H, hip_mem(), s, out, &R) : st;
         }

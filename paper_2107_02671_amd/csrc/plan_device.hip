@@ -12,10 +12,13 @@
 // the points agree with the host layout exactly.
 //
 // Stable sort: least-significant-digit radix sort, 8-bit digits, over the
-// key bits in use.  Each pass: per-tile digit histograms (tile = 4096
-// elements), one exclusive scan over (digit, tile) in digit-major order,
-// and a scatter that ranks the elements of a tile in index order (ballot
-// match within a wavefront, per-wave counts in LDS across wavefronts).
+// key bits in use.  Each pass: per-tile digit histograms (tile = 1024
+// elements), an exclusive scan of each digit's row over the tiles (one
+// workgroup per digit) with the row totals, and a scatter that starts each
+// digit at the prefix of the totals plus its row scan and ranks the
+// elements of a tile in index order (ballot match within a wavefront,
+// per-wave counts in LDS across wavefronts).  The bin counts are then read
+// off the sorted keys: the length of each key's run.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -28,8 +31,8 @@ namespace nnfft {
 namespace {
 
 constexpr int kSortThreads = 256;
-constexpr int kSortItems = 16;                           // elements per thread and tile
-constexpr int kTile = kSortThreads * kSortItems;          // 4096
+constexpr int kSortItems = 4;                            // elements per thread and tile
+constexpr int kTile = kSortThreads * kSortItems;          // 1024
 constexpr int kRadix = 256;
 constexpr int kSortWaves = kSortThreads / 64;
 
@@ -41,12 +44,12 @@ __device__ __forceinline__ double cell_floor(double t)
     return tr > t ? tr - 1.0 : tr;
 }
 
-// keys[k] = (block << bbits) | bin, vals[k] = k; counts[block * nbins + bin]
-// += 1; flag bit 0: a node outside [-1/2, 1/2] (or NaN), bit 1: a bin outside
-// [0, nbins) (then the key uses a clamped bin and the plan is refused)
+// keys[k] = (block << bbits) | bin, vals[k] = k; flag bit 0: a node
+// outside [-1/2, 1/2] (or NaN), bit 1: a bin outside [0, nbins) (then the key
+// uses bin 0 and the plan is refused)
 __global__ void k_node_keys(const double *__restrict__ x, int64_t M, double scale, int64_t off, int64_t nbins,
                             int64_t block, int bbits, uint32_t *__restrict__ keys, int32_t *__restrict__ vals,
-                            int32_t *__restrict__ counts, int32_t *__restrict__ flag)
+                            int32_t *__restrict__ flag)
 {
 #pragma clang fp contract(off)
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < M; k += (int64_t)gridDim.x * blockDim.x) {
@@ -66,7 +69,31 @@ __global__ void k_node_keys(const double *__restrict__ x, int64_t M, double scal
         const int64_t blk = k / block;
         keys[k] = ((uint32_t)blk << bbits) | (uint32_t)bin;
         vals[k] = (int32_t)k;
-        atomicAdd(&counts[blk * nbins + bin], 1);
+    }
+}
+
+// Bin counts from the sorted keys: counts[block * nbins + bin] = length of
+// the key's run.  Run starts store their position, run ends (a later
+// launch) replace it by the length.
+__global__ void k_run_starts(const uint32_t *__restrict__ keys, int64_t M, int bbits, int64_t nbins,
+                             int32_t *__restrict__ counts)
+{
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < M; p += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t k = keys[p];
+        if (p == 0 || keys[p - 1] != k)
+            counts[(int64_t)(k >> bbits) * nbins + (k & ((1u << bbits) - 1u))] = (int32_t)p;
+    }
+}
+
+__global__ void k_run_ends(const uint32_t *__restrict__ keys, int64_t M, int bbits, int64_t nbins,
+                           int32_t *__restrict__ counts)
+{
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < M; p += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t k = keys[p];
+        if (p == M - 1 || keys[p + 1] != k) {
+            int32_t *c = &counts[(int64_t)(k >> bbits) * nbins + (k & ((1u << bbits) - 1u))];
+            *c = (int32_t)(p + 1) - *c;
+        }
     }
 }
 
@@ -87,32 +114,44 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t *__r
     hist[(int64_t)tid * ntiles + blockIdx.x] = cnt[tid];
 }
 
-// exclusive scan of hist[0 .. len) in place, one workgroup of 1024 threads:
-// each thread scans a contiguous segment, the segment totals are scanned in
-// LDS
-__global__ __launch_bounds__(1024) void k_radix_scan(uint32_t *__restrict__ hist, int64_t len)
+// exclusive scan of each digit's row hist[d * ntiles .. (d + 1) * ntiles) in
+// place (workgroup d), the row total to tot[d]: segments of 256 x 16
+// entries, each thread summing 16 consecutive ones, the thread sums scanned in
+// LDS, a carry between segments
+__global__ __launch_bounds__(kSortThreads) void k_radix_scan_rows(uint32_t *__restrict__ hist, int64_t ntiles,
+                                                                  uint32_t *__restrict__ tot)
 {
-    __shared__ uint32_t tot[1024];
+    __shared__ uint32_t sums[kSortThreads];
     const int tid = threadIdx.x;
-    const int64_t seg = (len + 1023) / 1024;
-    const int64_t a = std::min<int64_t>(len, (int64_t)tid * seg), b = std::min<int64_t>(len, a + seg);
-    uint32_t s = 0;
-    for (int64_t i = a; i < b; ++i) s += hist[i];
-    tot[tid] = s;
-    __syncthreads();
-    // Hillis-Steele inclusive scan of the 1024 totals
-    for (int d = 1; d < 1024; d <<= 1) {
-        const uint32_t add = tid >= d ? tot[tid - d] : 0u;
+    uint32_t *row = hist + (int64_t)blockIdx.x * ntiles;
+    uint32_t carry = 0;
+    for (int64_t seg = 0; seg < ntiles; seg += kSortThreads * 16) {
+        const int64_t a = seg + (int64_t)tid * 16;
+        uint32_t v[16];
+        uint32_t s = 0;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            v[i] = (a + i < ntiles) ? row[a + i] : 0u;
+            s += v[i];
+        }
+        sums[tid] = s;
         __syncthreads();
-        tot[tid] += add;
+        for (int d = 1; d < kSortThreads; d <<= 1) {   // inclusive scan of the thread sums
+            const uint32_t add = tid >= d ? sums[tid - d] : 0u;
+            __syncthreads();
+            sums[tid] += add;
+            __syncthreads();
+        }
+        uint32_t run = carry + (tid > 0 ? sums[tid - 1] : 0u);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            if (a + i < ntiles) row[a + i] = run;
+            run += v[i];
+        }
+        carry += sums[kSortThreads - 1];
         __syncthreads();
     }
-    uint32_t run = tid > 0 ? tot[tid - 1] : 0u;
-    for (int64_t i = a; i < b; ++i) {
-        const uint32_t h = hist[i];
-        hist[i] = run;
-        run += h;
-    }
+    if (tid == 0) tot[blockIdx.x] = carry;
 }
 
 // stable scatter of one tile: elements are ranked in index order (round r,
@@ -121,13 +160,24 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t *
                                                                 const int32_t *__restrict__ vin, int64_t n,
                                                                 int shift, int64_t ntiles,
                                                                 const uint32_t *__restrict__ offs,
+                                                                const uint32_t *__restrict__ tot,
                                                                 uint32_t *__restrict__ kout,
                                                                 int32_t *__restrict__ vout)
 {
     __shared__ uint32_t base_d[kRadix];           // tile's first output position of each digit
     __shared__ uint32_t wcnt[kSortWaves][kRadix];  // elements of each digit in each wave, this round
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    base_d[tid] = offs[(int64_t)tid * ntiles + blockIdx.x];
+    // digit starts: exclusive scan of the digit totals (in wcnt[0] as scratch)
+    wcnt[0][tid] = tot[tid];
+    __syncthreads();
+    for (int d = 1; d < kRadix; d <<= 1) {
+        const uint32_t add = tid >= d ? wcnt[0][tid - d] : 0u;
+        __syncthreads();
+        wcnt[0][tid] += add;
+        __syncthreads();
+    }
+    base_d[tid] = (tid > 0 ? wcnt[0][tid - 1] : 0u) + offs[(int64_t)tid * ntiles + blockIdx.x];
+    __syncthreads();
     for (int w = 0; w < kSortWaves; ++w) wcnt[w][tid] = 0;
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));   // lanes below this one
     const int64_t tbase = (int64_t)blockIdx.x * kTile;
@@ -252,7 +302,8 @@ bool device_sort_fits(int64_t M, int64_t nbins, int64_t block)
 size_t device_sort_tmp_bytes(int64_t M)
 {
     const int64_t ntiles = (M + kTile - 1) / kTile;
-    return 2 * al256((size_t)M * 4) + 2 * al256((size_t)M * 4) + al256((size_t)kRadix * ntiles * 4) + 256;
+    return 2 * al256((size_t)M * 4) + 2 * al256((size_t)M * 4) + al256((size_t)kRadix * ntiles * 4) +
+           al256((size_t)kRadix * 4);
 }
 
 hipError_t device_sort_nodes(const double *x, int64_t M, double scale, int64_t off, int64_t nbins, int64_t block,
@@ -274,17 +325,21 @@ hipError_t device_sort_nodes(const double *x, int64_t M, double scale, int64_t o
     vals[1] = reinterpret_cast<int32_t *>(p);
     p += al256((size_t)M * 4);
     uint32_t *hist = reinterpret_cast<uint32_t *>(p);
+    p += al256((size_t)kRadix * ntiles * 4);
+    uint32_t *tot = reinterpret_cast<uint32_t *>(p);
     hipLaunchKernelGGL(k_node_keys, dim3(grid_for(M, 256)), dim3(256), 0, s, x, M, scale, off, nbins, block, bbits,
-                       keys[0], vals[0], counts, flag);
+                       keys[0], vals[0], flag);
     int cur = 0;
     for (int shift = 0; shift < kbits; shift += 8) {
         hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)ntiles), dim3(kSortThreads), 0, s, keys[cur], M, shift,
                            ntiles, hist);
-        hipLaunchKernelGGL(k_radix_scan, dim3(1), dim3(1024), 0, s, hist, (int64_t)kRadix * ntiles);
+        hipLaunchKernelGGL(k_radix_scan_rows, dim3(kRadix), dim3(kSortThreads), 0, s, hist, ntiles, tot);
         hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)ntiles), dim3(kSortThreads), 0, s, keys[cur], vals[cur],
-                           M, shift, ntiles, hist, keys[1 - cur], vals[1 - cur]);
+                           M, shift, ntiles, hist, tot, keys[1 - cur], vals[1 - cur]);
         cur = 1 - cur;
     }
+    hipLaunchKernelGGL(k_run_starts, dim3(grid_for(M, 256)), dim3(256), 0, s, keys[cur], M, bbits, nbins, counts);
+    hipLaunchKernelGGL(k_run_ends, dim3(grid_for(M, 256)), dim3(256), 0, s, keys[cur], M, bbits, nbins, counts);
     *sorted_idx = vals[cur];
     return hipGetLastError();
 }
