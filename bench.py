@@ -521,10 +521,10 @@ def main() -> int:
     dom = max(kt, key=lambda k: kt[k]["avg_ms"])
     d = kt[dom]
     prof = profiled_kernel_avg_ms()
-    for k, v in kt.items():
-        if k in prof:
-            v["profile_avg_ms"] = prof[k]
-            v["frac_from_profile"] = v["algorithmic_bytes"] / (prof[k] * 1e-3) / 1e9 / HBM_PEAK_GBS
+    for kname, rec in kt.items():
+        if kname in prof:
+            rec["profile_avg_ms"] = prof[kname]
+            rec["frac_from_profile"] = rec["algorithmic_bytes"] / (prof[kname] * 1e-3) / 1e9 / HBM_PEAK_GBS
     out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": d["achieved_GBs"], "peak": HBM_PEAK_GBS,
                        "unit": "GB/s", "frac": d["frac"], "traffic": d["traffic"],
                        "algorithmic_bytes_per_launch": d["algorithmic_bytes"], "avg_launch_ms": d["avg_ms"],
