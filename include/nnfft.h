@@ -390,6 +390,31 @@ nnfft_status sinc_sizes(sinc_plan_t p, int64_t *L1, int64_t *L2, int64_t *n_node
 nnfft_status sinc_destroy(sinc_plan_t p);
 
 /*
+ * The middle of Algorithm 6.1 as one operator.  Between the two FFTs the
+ * transform is linear in the first FFT's outputs h_s and depends on the
+ * quadrature and the plan parameters only: the first plan's interpolation
+ * (2.13) at x_j = z_j / 2 with its factors 1/phi_hat_1(N* x_j), the weights w_j
+ * of step 2, and the second plan's spreading (2.12) from v_j = -z_j / 2 with
+ * its deconvolution 1/phi_hat_2(l) (step 2 of Algorithm 2.2) compose to
+ *   u_l = sum_s K[l][s] h_s,  l in I_G1,
+ *   K[l][s] = sum_j phi_1(l/N1 - v*_j) w_j phi_2(x_j/sigma1 - s/N2)
+ *             / (N1 N2 phi_hat_1(N* x_j) phi_hat_2(l)),
+ * a band of about 2 (m1 + m2) labels s per row l.  sinc_plan builds K on
+ * the host in FP64 with the exact windows when both steps are NNFFTs and the
+ * rule has at most 2^16 nodes; sinc_exec then runs spreading + FFT of the
+ * first plan, one launch of the band, FFT + interpolation of the second plan
+ * (instead of the first plan's interpolation at the quadrature nodes and the
+ * second plan's spreading from them).  The results agree with the two-kernel
+ * form up to rounding.
+ *   on = 1: sinc_exec uses the operator (the default where it was built);
+ *   on = 0: the two-kernel form; any other value: no change.
+ *   built, active (may be null): 1 if the plan has the operator / if
+ *   sinc_exec uses it.
+ * Errors: ARG for a null plan, UNSUPPORTED for on = 1 without the operator.
+ */
+nnfft_status sinc_middle(sinc_plan_t p, int on, int32_t *built, int32_t *active);
+
+/*
  * The quadrature rule sinc_plan uses, on the host (no device work):
  * z[n_nodes], w[n_nodes] HOST arrays with n_nodes = n_quad (Gauss-Legendre)
  * or n_quad + 1 (Clenshaw-Curtis); weights sum to 1 (sinc(N pi x) is half the

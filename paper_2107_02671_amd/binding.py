@@ -155,6 +155,7 @@ def lib():
     L.sinc_sizes.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64),
                              ctypes.POINTER(ci)]
     L.sinc_destroy.argtypes = [vp]
+    L.sinc_middle.argtypes = [vp, ci, ctypes.POINTER(ci), ctypes.POINTER(ci)]
     dptr = ctypes.POINTER(ctypes.c_double)
     L.nnfft_quadrature.argtypes = [ci, i64, dptr, dptr]
     L.nnfft_profile_start.argtypes = [vp, ci]
@@ -179,7 +180,7 @@ def lib():
     for name in ["nfft_plan", "nfft_exec", "nfft_adjoint", "nfft_destroy", "nfft_plan_dry_run",
                  "nnfft_plan_dry_run", "nnfft_plan_window", "nnfft_plan_digest", "nnfft_plan_window_dry_run_digest", "nnfft_plan_window_dry_run", "nnfft_profile_start", "nnfft_profile_stop", "nnfft_profile_kernels", "nnfft_quadrature", "nnfft_derive_params",
                  "nnfft_plan", "nnfft_exec", "nnfft_exec_noalloc", "nnfft_exec_batch", "nnfft_info", "nnfft_destroy", "sinc_plan",
-                 "sinc_exec", "sinc_info", "sinc_sizes", "sinc_destroy", "nnfft_autotune", "nnfft_set_tuning",
+                 "sinc_exec", "sinc_info", "sinc_sizes", "sinc_destroy", "sinc_middle", "nnfft_autotune", "nnfft_set_tuning",
                  "nnfft_get_tuning", "nnfft_clear_tuning", "nnfft_server_create", "nnfft_server_submit",
                  "nnfft_server_wait", "nnfft_server_poll", "nnfft_server_stats", "nnfft_server_evict",
                  "nnfft_server_destroy"]:
@@ -491,6 +492,14 @@ def sinc_exec(plan, c, h, stream=None):
 
 def sinc_destroy(plan):
     _check(lib().sinc_destroy(plan))
+
+
+def sinc_middle(plan, on=-1) -> dict:
+    """on = 1 / 0: sinc_exec runs the middle operator / the two-kernel form;
+    other values leave it.  Returns {"built", "active"}."""
+    built, active = ctypes.c_int(), ctypes.c_int()
+    _check(lib().sinc_middle(plan, int(on), ctypes.byref(built), ctypes.byref(active)))
+    return {"built": built.value, "active": active.value}
 
 
 class Plan:

@@ -82,7 +82,8 @@ struct FftArgs {
     const void *tw4;          // four-step: [n1][n2] exp(-2 pi i j1 k2 / N2)
     void *Y;                  // [N2] four-step intermediate
     void *hlin;               // [2 S + 1] h_s at index s + h_off for |s| <= S
-    const void *dense_in;     // mode 1: the NFFT coefficients f_k (set per exec)
+    const void *dense_in;     // mode 1: the NFFT coefficients f_k; mode 3: the inputs at
+                              // labels l in I_G1, index l + G1/2 (set per exec)
     void *dense_out;          // mode 2: the adjoint NFFT output h_k (set per exec)
     int32_t N2, G1;
     int32_t n1, n2;           // N2 = n1 * n2; n1 == 1: one workgroup does it all
@@ -90,7 +91,7 @@ struct FftArgs {
     int32_t threadsA, threadsB;
     int32_t S;                // outputs with |s| <= S are consumed by step 4
     int32_t h_off;            // hlin index of label 0
-    int32_t mode;             // 0 NNFFT, 1 NFFT, 2 adjoint NFFT (see fft_input32)
+    int32_t mode;             // 0 NNFFT, 1 NFFT, 2 adjoint NFFT, 3 dense NNFFT input (see fft_input32)
     int32_t Nout;             // NFFT: number of frequencies N
     int32_t npassA, npassB;
     int32_t fusedB;           // 1: no stage B launch, interpolation folds it in
@@ -137,6 +138,22 @@ struct PlanDev {
     InterpArgs ip;
 };
 
+// The middle operator of a fast sinc transform (the first plan's
+// interpolation, the quadrature weights and the second plan's spreading as
+// one banded map from the first FFT's outputs to the second FFT's inputs):
+// row r (label r - G1/2) is out[r] = sum_{b < Wb} K[b][r] h_{lo[r] + b};
+// workgroup g (rows 256 g .. 256 g + 255) stages h at labels
+// [base[g], base[g] + span[g]) in LDS (labels with |s| > S read as zero).
+struct SincMidArgs {
+    InterpArgs h;             // the first plan's access to its FFT outputs
+    const double *K;          // [Wb][G1]
+    const int32_t *lo;        // [G1]
+    const int32_t *base;      // [nwg]
+    const int32_t *span;      // [nwg]
+    void *out;                // [G1] complex of the plan's precision
+    int32_t G1, Wb, S, span_max, nwg;
+};
+
 // Batched launches: up to kMaxBatch plans of one precision per launch.  The
 // table travels as the kernel argument; workgroups [start[p], start[p + 1])
 // belong to plan p (start[p] is a multiple of 8, so a plan's local workgroup
@@ -156,7 +173,8 @@ struct BatchTable {
 // gaps between kernels.  Filled in launch order.
 constexpr int kMaxTimedKernels = 6;
 enum KernelId : int32_t {
-    KID_SPREAD32 = 0, KID_SPREAD64, KID_FFT_SINGLE, KID_FFT_A, KID_FFT_B, KID_INTERP32, KID_INTERP64, KID_COUNT
+    KID_SPREAD32 = 0, KID_SPREAD64, KID_FFT_SINGLE, KID_FFT_A, KID_FFT_B, KID_INTERP32, KID_INTERP64, KID_SINC_MID,
+    KID_COUNT
 };
 struct KernelTimes {
     hipEvent_t start[kMaxTimedKernels] = {}, stop[kMaxTimedKernels] = {};
@@ -175,6 +193,10 @@ hipError_t launch_exec_batch(int n, const PlanDev *const *host, const PlanDev *c
                              const void *const *f, void *const *y, hipStream_t s);
 hipError_t launch_scale_by_weights(int prec, const double *w, const void *src, void *dst, int64_t n,
                                    hipStream_t s);
+// Fast sinc transform with its middle operator: spreading and FFT of P1 from
+// c, the middle operator M, FFT of P2 from M.out and its interpolation to h.
+hipError_t launch_sinc_middle(const PlanDev &P1, const SincMidArgs &M, const PlanDev &P2, const void *c, void *h,
+                              hipStream_t s);
 
 // Node preparation on the device (plan_device.hip): the key of node k of a
 // side is (block << bbits) | bin; device_sort_nodes checks the domain (flag

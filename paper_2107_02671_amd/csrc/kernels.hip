@@ -54,7 +54,7 @@ static void launch_k(KernelTimes *kt, int kid, K kernel, dim3 grid, dim3 block, 
 const char *kernel_name(int kid)
 {
     static const char *const names[KID_COUNT] = {"k_spread32", "k_spread64", "k_fft_single", "k_fft_stageA",
-                                                 "k_fft_stageB", "k_interp32", "k_interp64"};
+                                                 "k_fft_stageB", "k_interp32", "k_interp64", "k_sinc_mid"};
     return kid >= 0 && kid < KID_COUNT ? names[kid] : "?";
 }
 
@@ -974,10 +974,16 @@ __device__ __forceinline__ void merge_cell64(const FftArgs &A, int slot, double 
 //    outside I_{G1}) times 1 / (N1 N2 phi_hat_2(l)) (table in slot order);
 //  mode 1 (NFFT): coefficient f_k, k = l in I_N, times 1 / (n phi_hat(k));
 //  mode 2 (adjoint NFFT): conjugate of the sum of the cells of labels l, l + n,
-//    l - n in the linear grid (the 1-periodic fold of the spread values).
+//    l - n in the linear grid (the 1-periodic fold of the spread values);
+//  mode 3 (fast sinc transform, second plan): the value the middle operator
+//    wrote for label l (zero outside I_{G1}; already deconvolved).
 __device__ __forceinline__ cx<float> fft_input32(const FftArgs &A, int q)
 {
     const int lab = (q < A.N2 / 2) ? q : q - A.N2;
+    if (A.mode == 3) {
+        if (lab < -A.G1 / 2 || lab >= A.G1 / 2) return cxmk(0.f, 0.f);
+        return reinterpret_cast<const cx<float> *>(A.dense_in)[lab + A.G1 / 2];
+    }
     if (A.mode == 1) {
         if (lab < -A.Nout / 2 || lab >= A.Nout / 2) return cxmk(0.f, 0.f);
         const cx<float> v = reinterpret_cast<const cx<float> *>(A.dense_in)[lab + A.Nout / 2];
@@ -1003,6 +1009,10 @@ __device__ __forceinline__ cx<float> fft_input32(const FftArgs &A, int q)
 __device__ __forceinline__ cx<double> fft_input64(const FftArgs &A, int q)
 {
     const int lab = (q < A.N2 / 2) ? q : q - A.N2;
+    if (A.mode == 3) {
+        if (lab < -A.G1 / 2 || lab >= A.G1 / 2) return cxmk(0.0, 0.0);
+        return reinterpret_cast<const cx<double> *>(A.dense_in)[lab + A.G1 / 2];
+    }
     if (A.mode == 1) {
         if (lab < -A.Nout / 2 || lab >= A.Nout / 2) return cxmk(0.0, 0.0);
         const cx<double> v = reinterpret_cast<const cx<double> *>(A.dense_in)[lab + A.Nout / 2];
@@ -1400,6 +1410,46 @@ __global__ __launch_bounds__(256) void k_fft_stageB(FftArgs A)
 }
 
 // ===========================================================================
+// Fast sinc transform: the middle operator (Algorithm 6.1 steps 1-3 between
+// the two FFTs, composed on the host into the band K)
+// ===========================================================================
+constexpr int kMidThreads = 256;
+
+// h_s of the first plan, as its interpolation reads it
+template <typename T>
+__device__ __forceinline__ cx<T> plan_output(const InterpArgs &A, int s)
+{
+    return A.fusedB ? folded_output<T>(A, s) : reinterpret_cast<const cx<T> *>(A.hlin)[s + A.h_off];
+}
+
+// One workgroup per 256 rows: the labels its rows read are staged in LDS
+// (FP64 accumulation of the band; K is read coalesced, [b][row]).
+template <typename T>
+__global__ __launch_bounds__(kMidThreads) void k_sinc_mid(SincMidArgs A)
+{
+    extern __shared__ __align__(16) char smem[];
+    cx<T> *hw = reinterpret_cast<cx<T> *>(smem);
+    const int g = blockIdx.x;
+    const int base = A.base[g], span = A.span[g];
+    for (int i = threadIdx.x; i < span; i += kMidThreads) {
+        const int sl = base + i;
+        hw[i] = (sl >= -A.S && sl <= A.S) ? plan_output<T>(A.h, sl) : cxmk((T)0, (T)0);
+    }
+    __syncthreads();
+    const int row = g * kMidThreads + threadIdx.x;
+    if (row >= A.G1) return;
+    const cx<T> *hr = hw + (A.lo[row] - base);
+    double re = 0.0, im = 0.0;
+    for (int b = 0; b < A.Wb; ++b) {
+        const double k = A.K[(size_t)b * A.G1 + row];
+        const cx<T> v = hr[b];
+        re = fma(k, (double)v.re, re);
+        im = fma(k, (double)v.im, im);
+    }
+    reinterpret_cast<cx<T> *>(A.out)[row] = cxmk((T)re, (T)im);
+}
+
+// ===========================================================================
 // Batched kernels: one launch per stage for up to kMaxBatch plans of one
 // precision.  Each workgroup finds its plan in the table and runs the same
 // slot / column code as the plan's own launch, so results are bitwise equal.
@@ -1575,6 +1625,30 @@ hipError_t launch_exec(const PlanDev &P, const void *f, void *y, hipStream_t s, 
         launch_spread64(P.sp, f, s, kt);
         launch_fft<double>(P.fft, s, kt);
         launch_interp64(P.ip, y, s, kt);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_sinc_middle(const PlanDev &P1, const SincMidArgs &M, const PlanDev &P2, const void *c, void *h,
+                              hipStream_t s)
+{
+    FftArgs F = P2.fft;
+    F.mode = 3;
+    F.dense_in = M.out;
+    if (P1.prec == NNFFT_FP32_COMP) {
+        launch_spread32(P1.sp, P1.sp.ngrid, reinterpret_cast<const cx<float> *>(c), s);
+        launch_fft<float>(P1.fft, s);
+        hipLaunchKernelGGL(k_sinc_mid<float>, dim3(M.nwg), dim3(kMidThreads), (size_t)M.span_max * sizeof(cx<float>),
+                           s, M);
+        launch_fft<float>(F, s);
+        launch_interp32(corr_variant(P2.ip.corr_deg), P2.ip.ngrid, s, P2.ip, reinterpret_cast<cx<float> *>(h));
+    } else {
+        launch_spread64(P1.sp, c, s, nullptr);
+        launch_fft<double>(P1.fft, s);
+        hipLaunchKernelGGL(k_sinc_mid<double>, dim3(M.nwg), dim3(kMidThreads),
+                           (size_t)M.span_max * sizeof(cx<double>), s, M);
+        launch_fft<double>(F, s);
+        launch_interp64(P2.ip, h, s, nullptr);
     }
     return hipGetLastError();
 }

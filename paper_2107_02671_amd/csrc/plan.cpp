@@ -1679,9 +1679,130 @@ nnfft_status copy_nodes(const double *d, int64_t n, std::vector<double> &h, hipS
     return NNFFT_OK;
 }
 
+// The middle operator of SincMiddle from the two host plans and the
+// quadrature (z, w), in FP64 with the exact windows.  False (and nothing
+// built) where it does not pay or does not fit: more than kMidMaxNodes
+// quadrature nodes (host time grows with their number), a band wider than
+// kMidMaxBand labels, or a workgroup window longer than kMidMaxSpan labels.
+constexpr int64_t kMidMaxNodes = (int64_t)1 << 16;
+constexpr int kMidMaxBand = 256;
+constexpr int kMidMaxSpan = 4096;
+constexpr int kMidRows = 256;   // rows per workgroup of the middle kernel
+
+// Device layout of the middle operator (after the weights and the
+// intermediate): K, lo, base, span, out, each 256-byte aligned.
+struct SincMidLayout {
+    size_t K, lo, base, span, out, bytes;
+};
+static SincMidLayout sinc_middle_layout(const SincHostPlan &S)
+{
+    auto a256 = [](size_t x) { return (x + 255) / 256 * 256; };
+    const SincMiddle &M = S.mid;
+    const size_t csz = (S.prec == NNFFT_FP32_COMP) ? 8 : 16;
+    SincMidLayout L;
+    L.K = 0;
+    L.lo = a256(M.K.size() * sizeof(double));
+    L.base = L.lo + a256(M.lo.size() * sizeof(int32_t));
+    L.span = L.base + a256(M.base.size() * sizeof(int32_t));
+    L.out = L.span + a256(M.span.size() * sizeof(int32_t));
+    L.bytes = L.out + a256(M.lo.size() * csz);
+    return L;
+}
+static size_t sinc_middle_bytes(const SincHostPlan &S) { return sinc_middle_layout(S).bytes; }
+
+static bool build_sinc_middle(SincHostPlan &S, const std::vector<double> &z)
+{
+    const nnfft_info_t &A = S.h1.info, &B = S.h2.info;
+    const int64_t nn = (int64_t)z.size();
+    if (nn > kMidMaxNodes || nn < 1) return false;
+    const Window w_ip = make_window(A.window, A.m2, A.beta2);   // first plan: interpolation
+    const Window w_c1 = make_window(A.window, A.m1, A.beta1);   // first plan: 1/phi_hat_1
+    const Window w_sp = make_window(B.window, B.m1, B.beta1);   // second plan: spreading
+    const Window w_d2 = make_window(B.window, B.m2, B.beta2);   // second plan: 1/phi_hat_2
+    const int64_t G1 = B.G1, S_lab = S.h1.fd.S;
+    const int ma = A.m2, mb = B.m1;
+    // nodes: interpolation cell cu and spreading cell ct of each quadrature node
+    std::vector<double> u(nn), t(nn);
+    std::vector<int64_t> cu(nn), ct(nn);
+    std::vector<int64_t> lo(G1, INT64_MAX), hi(G1, INT64_MIN);
+    for (int64_t j = 0; j < nn; ++j) {
+        const double x = 0.5 * z[j], v = -0.5 * z[j];
+        u[j] = (double)A.N2 * (double)A.N_star * x / (double)A.N1;
+        t[j] = (double)B.N1 * ((double)B.N * v / (double)B.N_star);
+        cu[j] = (int64_t)std::floor(u[j]);
+        ct[j] = (int64_t)std::floor(t[j]);
+        if (cu[j] - ma + 1 < -S_lab || cu[j] + ma > S_lab) return false;
+        for (int q = 0; q < 2 * mb; ++q) {
+            const int64_t row = ct[j] - mb + 1 + q + G1 / 2;
+            if (row < 0 || row >= G1) return false;
+            lo[row] = std::min(lo[row], cu[j] - ma + 1);
+            hi[row] = std::max(hi[row], cu[j] + ma);
+        }
+    }
+    int64_t Wb = 1;
+    for (int64_t r = 0; r < G1; ++r)
+        if (hi[r] >= lo[r]) Wb = std::max(Wb, hi[r] - lo[r] + 1);
+    if (Wb > kMidMaxBand) return false;
+    // workgroup windows; rows without entries read the start of theirs
+    const int64_t nwg = (G1 + kMidRows - 1) / kMidRows;
+    SincMiddle &Mi = S.mid;
+    Mi.base.assign(nwg, 0);
+    Mi.span.assign(nwg, 0);
+    Mi.lo.assign(G1, 0);
+    int64_t span_max = 1;
+    for (int64_t g = 0; g < nwg; ++g) {
+        const int64_t r0 = g * kMidRows, r1 = std::min(G1, r0 + kMidRows);
+        int64_t b0 = INT64_MAX;
+        for (int64_t r = r0; r < r1; ++r)
+            if (hi[r] >= lo[r]) b0 = std::min(b0, lo[r]);
+        if (b0 == INT64_MAX) b0 = 0;
+        int64_t end = b0 + 1;
+        for (int64_t r = r0; r < r1; ++r) {
+            const int64_t l0 = hi[r] >= lo[r] ? lo[r] : b0;
+            Mi.lo[r] = (int32_t)l0;
+            end = std::max(end, l0 + Wb);
+        }
+        Mi.base[g] = (int32_t)b0;
+        Mi.span[g] = (int32_t)(end - b0);
+        span_max = std::max(span_max, end - b0);
+    }
+    if (span_max > kMidMaxSpan) return false;
+    // the band: sum over the nodes of spreading tap x weight / phi_hat_1 x
+    // interpolation tap, then the deconvolution of each row
+    std::vector<double> Kr((size_t)(G1 * Wb), 0.0);
+    std::vector<double> tap_ip(2 * ma), tap_sp(2 * mb);
+    for (int64_t j = 0; j < nn; ++j) {
+        const double x = 0.5 * z[j];
+        const double phi1 = (double)A.m1 / (double)A.N1 *
+                            window_hat(w_c1, (double)A.m1 * (double)A.N_star * x / (double)A.N1);
+        const double a = S.w[j] / phi1;
+        for (int r = 0; r < 2 * ma; ++r)
+            tap_ip[r] = window_value(w_ip, (u[j] - (double)(cu[j] - ma + 1 + r)) / ma);
+        for (int q = 0; q < 2 * mb; ++q)
+            tap_sp[q] = window_value(w_sp, ((double)(ct[j] - mb + 1 + q) - t[j]) / mb);
+        for (int q = 0; q < 2 * mb; ++q) {
+            const int64_t row = ct[j] - mb + 1 + q + G1 / 2;
+            double *k = Kr.data() + row * Wb + (cu[j] - ma + 1 - Mi.lo[row]);
+            const double aq = a * tap_sp[q];
+            for (int r = 0; r < 2 * ma; ++r) k[r] += aq * tap_ip[r];
+        }
+    }
+    Mi.K.assign((size_t)(G1 * Wb), 0.0);
+    for (int64_t r = 0; r < G1; ++r) {
+        const double l = (double)(r - G1 / 2);
+        const double phi2 = (double)B.m2 / (double)B.N2 * window_hat(w_d2, (double)B.m2 * l / (double)B.N2);
+        const double d = 1.0 / ((double)B.N1 * (double)B.N2 * phi2);
+        for (int64_t b = 0; b < Wb; ++b) Mi.K[(size_t)(b * G1 + r)] = d * Kr[(size_t)(r * Wb + b)];
+    }
+    Mi.Wb = (int32_t)Wb;
+    Mi.span_max = (int32_t)span_max;
+    Mi.S = (int32_t)S_lab;
+    return true;
+}
+
 nnfft_status sinc_host(SincHostPlan &S, int64_t N, int64_t L1, int64_t L2, sinc_quad quad, int64_t n_quad,
                        double sigma1, double sigma2, int m1, int m2, nnfft_precision prec,
-                       const std::vector<double> &a, const std::vector<double> &b)
+                       const std::vector<double> &a, const std::vector<double> &b, bool middle)
 {
     if (n_quad < 1 || n_quad > ((int64_t)1 << 24)) return fail(NNFFT_ERR_ARG, "n_quad out of range");
     if (quad != SINC_QUAD_GAUSS_LEGENDRE && quad != SINC_QUAD_CLENSHAW_CURTIS)
@@ -1725,6 +1846,8 @@ nnfft_status sinc_host(SincHostPlan &S, int64_t N, int64_t L1, int64_t L2, sinc_
     S.prec = prec;
     const size_t csz = (prec == NNFFT_FP32_COMP) ? 8 : 16;
     S.wg_bytes = ((size_t)nn * sizeof(double) + 255) / 256 * 256 + (size_t)nn * csz;
+    S.mid_ok = middle && !S.step1_nfft && !S.step3_nfft && build_sinc_middle(S, z);
+    if (S.mid_ok) S.wg_bytes = (S.wg_bytes + 255) / 256 * 256 + sinc_middle_bytes(S);
     S.total_bytes = S.h1.total_bytes + S.h2.total_bytes + S.wg_bytes;
     return NNFFT_OK;
 }
@@ -1755,6 +1878,33 @@ nnfft_status sinc_create(const SincHostPlan &S, const DevMem &mem, hipStream_t s
     sp->w = static_cast<double *>(sp->wg_base);
     sp->g = static_cast<char *>(sp->wg_base) + ((size_t)S.n_nodes * sizeof(double) + 255) / 256 * 256;
     hipError_t e = hipMemcpyAsync(sp->w, S.w.data(), (size_t)S.n_nodes * sizeof(double), hipMemcpyHostToDevice, s);
+    if (S.mid_ok) {
+        const size_t csz = (S.prec == NNFFT_FP32_COMP) ? 8 : 16;
+        const size_t off = ((size_t)S.n_nodes * sizeof(double) + 255) / 256 * 256 + (size_t)S.n_nodes * csz;
+        char *mb = static_cast<char *>(sp->wg_base) + (off + 255) / 256 * 256;
+        const SincMidLayout L = sinc_middle_layout(S);
+        const SincMiddle &M = S.mid;
+        SincMidArgs &A = sp->mid;
+        A.h = sp->p1->desc.ip;
+        A.K = reinterpret_cast<const double *>(mb + L.K);
+        A.lo = reinterpret_cast<const int32_t *>(mb + L.lo);
+        A.base = reinterpret_cast<const int32_t *>(mb + L.base);
+        A.span = reinterpret_cast<const int32_t *>(mb + L.span);
+        A.out = mb + L.out;
+        A.G1 = (int32_t)M.lo.size();
+        A.Wb = M.Wb;
+        A.S = M.S;
+        A.span_max = M.span_max;
+        A.nwg = (int32_t)M.base.size();
+        auto put = [&](size_t at, const void *src, size_t n) {
+            if (e == hipSuccess && n > 0) e = hipMemcpyAsync(mb + at, src, n, hipMemcpyHostToDevice, s);
+        };
+        put(L.K, M.K.data(), M.K.size() * sizeof(double));
+        put(L.lo, M.lo.data(), M.lo.size() * sizeof(int32_t));
+        put(L.base, M.base.data(), M.base.size() * sizeof(int32_t));
+        put(L.span, M.span.data(), M.span.size() * sizeof(int32_t));
+        sp->has_mid = sp->use_mid = true;
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         delete sp;
@@ -2211,7 +2361,7 @@ nnfft_status sinc_plan(sinc_plan_t *out, int64_t N, int64_t L1, int64_t L2, sinc
         st = copy_nodes(b, L2, hb, s);
         if (st != NNFFT_OK) return st;
         SincHostPlan S;
-        st = sinc_host(S, N, L1, L2, quad, n_quad, sigma1, sigma2, m1, m2, prec, ha, hb);
+        st = sinc_host(S, N, L1, L2, quad, n_quad, sigma1, sigma2, m1, m2, prec, ha, hb, true);
         if (st != NNFFT_OK) return st;
         return sinc_create(S, hip_mem(), s, out);
     } catch (const std::bad_alloc &) {
@@ -2223,6 +2373,11 @@ nnfft_status sinc_exec(sinc_plan_t p, const void *c, void *h, void *stream)
 {
     if (!p || !c || !h) return fail(NNFFT_ERR_ARG, "null argument");
     hipStream_t s = static_cast<hipStream_t>(stream);
+    if (p->use_mid) {
+        const hipError_t e = launch_sinc_middle(p->p1->desc, p->mid, p->p2->desc, c, h, s);
+        if (e != hipSuccess) return fail(NNFFT_ERR_DEVICE, std::string("launch: ") + hipGetErrorString(e));
+        return NNFFT_OK;
+    }
     nnfft_status st = p->step1_nfft ? nfft_exec(p->p1, c, p->g, stream)        // step 1
                                     : nnfft_exec(p->p1, c, p->g, stream);
     if (st != NNFFT_OK) return st;
@@ -2267,6 +2422,16 @@ nnfft_status sinc_sizes(sinc_plan_t p, int64_t *L1, int64_t *L2, int64_t *n_node
     *L2 = p->L2;
     *n_nodes = p->n_nodes;
     *nfft_steps = (p->step1_nfft ? 1 : 0) | (p->step3_nfft ? 2 : 0);
+    return NNFFT_OK;
+}
+
+nnfft_status sinc_middle(sinc_plan_t p, int on, int32_t *built, int32_t *active)
+{
+    if (!p) return fail(NNFFT_ERR_ARG, "null plan");
+    if (on == 1 && !p->has_mid) return fail(NNFFT_ERR_UNSUPPORTED, "the plan has no middle operator");
+    if (on == 0 || on == 1) p->use_mid = (on == 1);
+    if (built) *built = p->has_mid ? 1 : 0;
+    if (active) *active = p->use_mid ? 1 : 0;
     return NNFFT_OK;
 }
 

@@ -134,7 +134,10 @@ struct sinc_plan_s {
     nnfft_plan_t p1 = nullptr, p2 = nullptr;
     double *w = nullptr;      // [n_nodes] quadrature weights (FP64, device)
     void *g = nullptr;        // [n_nodes] complex intermediate
-    void *wg_base = nullptr;  // device block of w and g
+    void *wg_base = nullptr;  // device block of w and g (and of the middle operator)
+    nnfft::SincMidArgs mid{}; // the middle operator (has_mid)
+    bool has_mid = false;     // built at plan time
+    bool use_mid = false;     // sinc_exec runs it (sinc_set_middle)
     nnfft::DevMem mem{};
     int64_t n_nodes = 0;
     int64_t L1 = 0, L2 = 0;   // input and output lengths
@@ -203,9 +206,29 @@ nnfft_status plan_device_nodes(HostPlan &H, DevRecords &R, NodePrepScratch &T, i
 uint64_t fnv1a64(const void *p, size_t n);
 
 // Fast sinc transform (Algorithm 6.1) on the host: quadrature and both plans.
+// The middle of Algorithm 6.1 as one operator: the first plan's
+// interpolation at x_j = z_j / 2 with its 1/phi_hat_1 factors, the weights and
+// the second plan's spreading from v_j = -z_j / 2 with its 1/phi_hat_2
+// deconvolution are linear in the first FFT's outputs h_s and depend on the
+// quadrature and the plan parameters only:
+//   u_l = sum_s K[l][s] h_s,  l in I_G1 (the second FFT's input at label l),
+//   K[l][s] = d(l) sum_j omega_1((l - t_j) / m1) w_j / phi_hat_1(N* x_j)
+//                       omega_2((u_j - s) / m2),
+// t_j = N1 N v_j / N*, u_j = N2 N* x_j / N1, d(l) = 1 / (N1 N2 phi_hat_2(l)).
+// Row l (index l + G1/2) has its nonzero entries at labels s in
+// [lo[l], lo[l] + Wb); workgroup g (rows 256 g ..) reads the labels
+// [base[g], base[g] + span[g]).
+struct SincMiddle {
+    int32_t Wb = 0, span_max = 0, S = 0;
+    std::vector<double> K;                   // [Wb][G1]
+    std::vector<int32_t> lo, base, span;     // [G1], [nwg], [nwg]
+};
+
 struct SincHostPlan {
     HostPlan h1, h2;
     std::vector<double> w;
+    SincMiddle mid;           // built when mid_ok
+    bool mid_ok = false;
     int64_t n_nodes = 0;
     int64_t L1 = 0, L2 = 0;
     int32_t prec = 0;
@@ -215,7 +238,7 @@ struct SincHostPlan {
 };
 nnfft_status sinc_host(SincHostPlan &S, int64_t N, int64_t L1, int64_t L2, sinc_quad quad, int64_t n_quad,
                        double sigma1, double sigma2, int m1, int m2, nnfft_precision prec,
-                       const std::vector<double> &a, const std::vector<double> &b);
+                       const std::vector<double> &a, const std::vector<double> &b, bool middle = false);
 nnfft_status sinc_create(const SincHostPlan &S, const DevMem &mem, hipStream_t s, sinc_plan_t *out);
 
 // Verifies the layout invariants the kernels rely on (no device work).

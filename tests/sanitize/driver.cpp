@@ -5,6 +5,7 @@
 // with sanitizers, it checks the planner's memory accesses and, with planner
 // threads of its own on top of the two-sided builds, its threading.
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -74,6 +75,27 @@ static int run(unsigned seed, bool small)
                                              v.data(), x.data(), &d2) != NNFFT_OK || d1 != d2)
             std::abort();
     }
+    // fast sinc transform plans with the middle operator (both rules, both
+    // precisions, Chebyshev-crowded nodes, small and large bands)
+    for (int prec : {0, 1})
+        for (int quad : {0, 1})
+            for (int N : {64, 1024})
+                for (int m : {4, 6}) {
+                    const int64_t L = small ? 3000 : 20000;
+                    std::vector<double> a(L), b(L);
+                    for (int64_t k = 0; k < L; ++k) {
+                        a[k] = 0.5 * std::cos(3.141592653589793 * (k + 0.5) / (double)L);
+                        b[k] = U(g);
+                    }
+                    nnfft::SincHostPlan S;
+                    if (nnfft::sinc_host(S, N, L, L, (sinc_quad)quad, 2 * N, 2.0, 2.0, m, m, (nnfft_precision)prec, a,
+                                         b, true) != NNFFT_OK) {
+                        ++refused;
+                        continue;
+                    }
+                    if (!S.mid_ok || S.mid.Wb < 2 * m || S.mid.K.size() != (size_t)S.mid.Wb * S.mid.lo.size())
+                        std::abort();
+                }
     return refused;
 }
 

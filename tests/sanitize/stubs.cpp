@@ -8,6 +8,10 @@ namespace nnfft {
 hipError_t launch_nfft(const PlanDev &, bool, const void *, void *, hipStream_t) { std::abort(); }
 hipError_t launch_exec(const PlanDev &, const void *, void *, hipStream_t, KernelTimes *) { std::abort(); }
 hipError_t launch_scale_by_weights(int, const double *, const void *, void *, int64_t, hipStream_t) { std::abort(); }
+hipError_t launch_sinc_middle(const PlanDev &, const SincMidArgs &, const PlanDev &, const void *, void *, hipStream_t)
+{
+    std::abort();
+}
 hipError_t launch_exec_batch(int, const PlanDev *const *, const PlanDev *const *, const void *const *,
                              void *const *, hipStream_t)
 {

@@ -166,3 +166,74 @@ def test_sinc_equispaced_special_cases(prec, s1, s3, L1, L2, quad):
     idx = W.rng(5).choice(len(b), min(len(b), 256), replace=False)
     ex = oracle.sinc_direct(N, a, c, b[idx])
     assert einf(h[idx], ex) <= 1e-4
+
+
+def _sinc_both_forms(N, a, b, c, n_quad, quad, s1, s2, m, prec):
+    """Runs one plan with its middle operator and in the two-kernel form."""
+    cdt = torch.complex64 if prec == FP32 else torch.complex128
+    sp = P.SincPlan(N, torch.tensor(a, device=DEV), torch.tensor(b, device=DEV), n_quad, quad, s1, s2, m, m, prec)
+    try:
+        tc = torch.tensor(c, dtype=cdt, device=DEV)
+        st = P.sinc_middle(sp.handle)
+        assert st == {"built": 1, "active": 1}, st
+        h_mid = sp(tc).clone()
+        assert P.sinc_middle(sp.handle, 0) == {"built": 1, "active": 0}
+        h_two = sp(tc).clone()
+        assert P.sinc_middle(sp.handle, 1) == {"built": 1, "active": 1}
+        h_again = sp(tc).clone()
+        torch.cuda.synchronize()
+    finally:
+        sp.close()
+    assert torch.equal(h_mid, h_again)   # deterministic
+    return (h_mid.cpu().numpy().astype(np.complex128), h_two.cpu().numpy().astype(np.complex128))
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+@pytest.mark.parametrize("N,L1,L2,quad,nqf,s1,s2,m", [
+    (1024, 1 << 14, 1 << 14, GL, 2, 2.0, 2.0, 6),
+    (1024, 5000, 7001, CC, 4, 2.0, 2.0, 6),
+    (333, 4000, 3000, GL, 3, 1.5, 2.0, 8),     # sigma1 != sigma2: rows read a wider band of h
+    (200, 3000, 2500, CC, 2, 2.0, 1.5, 7),
+    (64, 800, 900, GL, 8, 2.0, 2.0, 12),
+], ids=["gl_N1024", "cc_N1024", "gl_s15_m8", "cc_s2_15_m7", "gl_N64_m12"])
+def test_sinc_middle_operator(prec, N, L1, L2, quad, nqf, s1, s2, m):
+    # the middle operator (first interpolation, weights and second spreading
+    # as one band) against the oracle's Algorithm 6.1 and against the
+    # two-kernel form of the same plan
+    if prec == FP32 and m < 6:
+        pytest.skip("FP32 sinc cases run at m >= 6")
+    r = W.rng(700 + N + m)
+    a = 0.5 * np.cos(np.pi * (np.arange(L1) + 0.5) / L1)
+    b = r.uniform(-0.5, 0.5, L2)
+    b[:2] = (-0.5, 0.5)
+    c = r.standard_normal(L1) + 1j * r.standard_normal(L1)
+    n_quad = nqf * N
+    _say(f"[gpu] sinc middle N={N} L=({L1},{L2}) quad={quad} n={n_quad} sigma=({s1},{s2}) m={m} prec={prec}")
+    h_mid, h_two = _sinc_both_forms(N, a, b, c, n_quad, quad, s1, s2, m, prec)
+    ho = oracle.sinc_fast(N, a, c, b, n_quad, quad, s1, s2, m, m)
+    e_mid, e_two, e_mt = einf(h_mid, ho), einf(h_two, ho), einf(h_mid, h_two)
+    _say(f"    E_inf vs oracle: middle {e_mid:.3e}, two kernels {e_two:.3e}; between them {e_mt:.3e}")
+    # kappa-scaled gate of the NNFFT parity tests (the two phi_hat divisions
+    # amplify the FFT's rounding by up to kappa = omega_hat(0) / omega_hat(m / (2 sigma)))
+    Pp = oracle.params(N, s1, s2, m, m)
+    kap = max(oracle.window_hat(0, 0.0, m, bt) / oracle.window_hat(0, m / (2 * se), m, bt)
+              for bt, se in ((Pp.beta1, Pp.sigma1_eff), (Pp.beta2, Pp.sigma2_eff)))
+    t = (1e-12 if prec == FP64 else 1e-5) * max(1.0, kap / 4.62)
+    _say(f"    gate {t:.1e} (kappa {kap:.1f})")
+    assert e_mid <= t and e_two <= t and e_mt <= 2 * t
+
+
+def test_sinc_middle_availability():
+    # equispaced steps (NFFTs) have no middle operator; asking for it fails
+    N = 1024
+    a = torch.tensor(np.arange(-N, N) / (2 * N), device=DEV)
+    b = torch.tensor(W.rng(3).uniform(-0.5, 0.5, 100), device=DEV)
+    sp = P.SincPlan(N, a, b, 2 * N, GL, 2.0, 2.0, 6, 6, FP64)
+    try:
+        assert P.sinc_middle(sp.handle) == {"built": 0, "active": 0}
+        with pytest.raises(P.NnfftError) as e:
+            P.sinc_middle(sp.handle, 1)
+        assert e.value.status == P.binding.NNFFT_ERR_UNSUPPORTED
+        assert P.sinc_middle(sp.handle, 0) == {"built": 0, "active": 0}
+    finally:
+        sp.close()
