@@ -20,8 +20,9 @@
  * resident plans that are idle are evicted, least recently used first, when
  * a new plan needs their space.
  *
- * Results are those of nnfft_exec / sinc_exec on the same plan: every
- * request's output is bitwise the same alone or in any mix.
+ * Results are those of nnfft_exec / sinc_exec on the same plan (sinc
+ * requests: in the two-kernel form, sinc_middle(p, 0)): every request's
+ * output is bitwise the same alone or in any mix.
  *
  * Conventions: as in nnfft.h.  The request's device arrays (v, x, f, y) are
  * the caller's; they must hold their data before nnfft_server_submit (the

@@ -421,12 +421,14 @@ void gauss_legendre_rule(int64_t n, std::vector<double> &z, std::vector<double> 
         const double th = kPi * (4.0 * i - 1.0) / (4.0 * nn + 2.0);
         double t = (1.0 - (nn - 1.0) / (8.0 * nn * nn * nn)) * std::cos(th);
         double p, pm;
+        // quadratic convergence: once a step is below 1e-14 of the node (or
+        // of 1e-3 for nodes near 0), the node is at the rounding floor
         for (int it = 0; it < 60; ++it) {
             legendre(t, p, pm);
             const double dp = nn * (pm - t * p) / ((1.0 - t) * (1.0 + t));
             const double step = p / dp;
             t -= step;
-            if (std::fabs(step) <= 1e-17) break;
+            if (std::fabs(step) <= 1e-14 * std::max(std::fabs(t), 1e-3)) break;
         }
         legendre(t, p, pm);
         const double omt2 = (1.0 - t) * (1.0 + t);

@@ -294,6 +294,7 @@ __device__ __forceinline__ cx<double> coef64(const cx<double> *__restrict__ f, c
 constexpr int kWaves32 = 4;
 constexpr int kThreads32 = kWaves32 * kItemsPerWg;
 constexpr int kRowsPerWave = 8;   // record rows a wave loads in one batch
+constexpr int kSerialRun = 8;     // bins of up to this many items in a chunk are summed in order
 
 // Record row for the j-th load of a wave that owns rows [row0, row0 + rpw):
 // loads past its share repeat its last row (same addresses, no extra lines).
@@ -442,29 +443,95 @@ __device__ __forceinline__ void spread32_cells(const SpreadArgs &A, const Chunk 
         if (t == ch.nitem - 1 || L.ibin[t + 1] != b) L.runE[b] = t + 1;
     }
     lds_barrier();
-    if (t < ch.nbin) {
-        const int s = L.runS[t], e = L.runE[t];   // s = e for a bin without items
-        constexpr int KW = (D + kWaves32) / kWaves32;   // moments per wave (3; the last one
-        float hr[KW], hi[KW], lr[KW], li[KW];          // only on wave 0)
+    constexpr int KW = (D + kWaves32) / kWaves32;   // moments per wave (3; the last one only on wave 0)
+    // the longest run of items of one bin in the chunk (each wave finds it)
+    int run = (t < ch.nbin) ? L.runE[t] - L.runS[t] : 0;
 #pragma unroll
-        for (int j = 0; j < KW; ++j) hr[j] = hi[j] = lr[j] = li[j] = 0.f;
-        for (int i = s; i < e; ++i) {
+    for (int o = kItemsPerWg / 2; o > 0; o >>= 1) run = max(run, __shfl_xor(run, o));
+    run = __builtin_amdgcn_readfirstlane(run);
+    if (run <= kSerialRun) {
+        // short runs: thread (w, bin) adds the bin's items in order
+        if (t < ch.nbin) {
+            const int s = L.runS[t], e = L.runE[t];   // s = e for a bin without items
+            float hr[KW], hi[KW], lr[KW], li[KW];
+#pragma unroll
+            for (int j = 0; j < KW; ++j) hr[j] = hi[j] = lr[j] = li[j] = 0.f;
+            for (int i = s; i < e; ++i) {
+#pragma unroll
+                for (int j = 0; j < KW; ++j) {
+                    const int k = min(w + kWaves32 * j, D);
+                    cx<float> v = L.mom[0][k][i];
+#pragma unroll
+                    for (int ww = 1; ww < kWaves32; ++ww) {
+                        v.re += L.mom[ww][k][i].re;
+                        v.im += L.mom[ww][k][i].im;
+                    }
+                    comp_add(hr[j], lr[j], v.re);
+                    comp_add(hi[j], li[j], v.im);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < KW; ++j)
+                if (w + kWaves32 * j <= D) L.bmom[w + kWaves32 * j][t] = cxmk(hr[j] + lr[j], hi[j] + li[j]);
+        }
+    } else {
+        // long runs (crowded cells): a tree over each run.  Thread (w, item)
+        // owns moments k = w + 4 j of its item: the item total (plain sum of
+        // the wave shares, as above) becomes the pair (mom[0], mom[1]) =
+        // (hi, lo); in round d the item at run offset r = 0 mod 2d adds the
+        // pair at r + d with two-sum; the run's first item ends with the sum.
+        if (t < ch.nitem) {
 #pragma unroll
             for (int j = 0; j < KW; ++j) {
-                const int k = min(w + kWaves32 * j, D);
-                cx<float> v = L.mom[0][k][i];
+                const int k = w + kWaves32 * j;
+                if (k <= D) {
+                    cx<float> v = L.mom[0][k][t];
 #pragma unroll
-                for (int ww = 1; ww < kWaves32; ++ww) {
-                    v.re += L.mom[ww][k][i].re;
-                    v.im += L.mom[ww][k][i].im;
+                    for (int ww = 1; ww < kWaves32; ++ww) {
+                        v.re += L.mom[ww][k][t].re;
+                        v.im += L.mom[ww][k][t].im;
+                    }
+                    L.mom[0][k][t] = v;
+                    L.mom[1][k][t] = cxmk(0.f, 0.f);
                 }
-                comp_add(hr[j], lr[j], v.re);
-                comp_add(hi[j], li[j], v.im);
             }
         }
+        lds_barrier();
+        const int bt = (t < ch.nitem) ? L.ibin[t] : 0;
+        const int r = t - L.runS[bt], len = L.runE[bt] - L.runS[bt];
+        for (int d = 1; d < run; d <<= 1) {
+            if (t < ch.nitem && (r & (2 * d - 1)) == 0 && r + d < len) {
 #pragma unroll
-        for (int j = 0; j < KW; ++j)
-            if (w + kWaves32 * j <= D) L.bmom[w + kWaves32 * j][t] = cxmk(hr[j] + lr[j], hi[j] + li[j]);
+                for (int j = 0; j < KW; ++j) {
+                    const int k = w + kWaves32 * j;
+                    if (k <= D) {
+                        cx<float> h = L.mom[0][k][t], l = L.mom[1][k][t];
+                        const cx<float> h2 = L.mom[0][k][t + d], l2 = L.mom[1][k][t + d];
+                        float sr, er, si, ei;
+                        two_sum(h.re, h2.re, sr, er);
+                        two_sum(h.im, h2.im, si, ei);
+                        L.mom[0][k][t] = cxmk(sr, si);
+                        L.mom[1][k][t] = cxmk(l.re + l2.re + er, l.im + l2.im + ei);
+                    }
+                }
+            }
+            lds_barrier();
+        }
+        if (t < ch.nbin) {
+            const int s0 = L.runS[t], e0 = L.runE[t];
+#pragma unroll
+            for (int j = 0; j < KW; ++j) {
+                const int k = w + kWaves32 * j;
+                if (k <= D) {
+                    cx<float> v = cxmk(0.f, 0.f);
+                    if (s0 < e0) {
+                        const cx<float> h = L.mom[0][k][s0], l = L.mom[1][k][s0];
+                        v = cxmk(h.re + l.re, h.im + l.im);
+                    }
+                    L.bmom[k][t] = v;
+                }
+            }
+        }
     }
     lds_barrier();
     if (t < ch.nbin) {

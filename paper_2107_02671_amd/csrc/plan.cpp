@@ -1689,6 +1689,36 @@ constexpr int kMidMaxBand = 256;
 constexpr int kMidMaxSpan = 4096;
 constexpr int kMidRows = 256;   // rows per workgroup of the middle kernel
 
+// The quadrature rules of recent plans (the Gauss-Legendre rule costs
+// O(n_quad^2) on the host), least recently used out.
+static void quadrature_rule(sinc_quad quad, int64_t n, std::vector<double> &z, std::vector<double> &w)
+{
+    struct Rule {
+        int quad;
+        int64_t n;
+        std::vector<double> z, w;
+    };
+    constexpr size_t kRules = 8;
+    static std::mutex mu;
+    static std::list<Rule> *cache = new std::list<Rule>();   // leaked: outlives static destructors
+    {
+        std::lock_guard<std::mutex> g(mu);
+        for (auto it = cache->begin(); it != cache->end(); ++it)
+            if (it->quad == (int)quad && it->n == n) {
+                cache->splice(cache->begin(), *cache, it);
+                z = it->z;
+                w = it->w;
+                return;
+            }
+    }
+    if (quad == SINC_QUAD_GAUSS_LEGENDRE) gauss_legendre_rule(n, z, w);
+    else clenshaw_curtis_rule(n, z, w);
+    if (n > ((int64_t)1 << 16)) return;   // kept: rules of up to 2^16 nodes (1 MB)
+    std::lock_guard<std::mutex> g(mu);
+    cache->push_front(Rule{(int)quad, n, z, w});
+    if (cache->size() > kRules) cache->pop_back();
+}
+
 // Device layout of the middle operator (after the weights and the
 // intermediate): K, lo, base, span, out, each 256-byte aligned.
 struct SincMidLayout {
@@ -1808,8 +1838,7 @@ nnfft_status sinc_host(SincHostPlan &S, int64_t N, int64_t L1, int64_t L2, sinc_
     if (quad != SINC_QUAD_GAUSS_LEGENDRE && quad != SINC_QUAD_CLENSHAW_CURTIS)
         return fail(NNFFT_ERR_ARG, "unknown quadrature rule");
     std::vector<double> z;
-    if (quad == SINC_QUAD_GAUSS_LEGENDRE) gauss_legendre_rule(n_quad, z, S.w);
-    else clenshaw_curtis_rule(n_quad, z, S.w);
+    quadrature_rule(quad, n_quad, z, S.w);
     const int64_t nn = (int64_t)z.size();
     std::vector<double> xs(nn), vs(nn);
     for (int64_t j = 0; j < nn; ++j) {
@@ -2398,8 +2427,7 @@ nnfft_status nnfft_quadrature(sinc_quad quad, int64_t n_quad, double *z, double 
         return fail(NNFFT_ERR_ARG, "unknown quadrature rule");
     try {
         std::vector<double> zz, ww;
-        if (quad == SINC_QUAD_GAUSS_LEGENDRE) gauss_legendre_rule(n_quad, zz, ww);
-        else clenshaw_curtis_rule(n_quad, zz, ww);
+        quadrature_rule(quad, n_quad, zz, ww);
         std::copy(zz.begin(), zz.end(), z);
         std::copy(ww.begin(), ww.end(), w);
     } catch (const std::bad_alloc &) {

@@ -1,7 +1,7 @@
 """Layout autotuning and the serving layer (include/nnfft_serve.h) on the GPU.
 
 Served results are compared bitwise with the same plan run alone
-(nnfft_exec / sinc_exec): continuous batching may group a request with any
+(nnfft_exec / sinc_exec, the latter in its two-kernel form): continuous batching may group a request with any
 others, on any stream, in arena memory, and must not change a bit of it."""
 import sys
 
@@ -51,6 +51,7 @@ def _alone(r):
     if r["kind"] == P.NNFFT_REQ_SINC:
         sp = P.SincPlan(r["N"], r["v"], r["x"], r["n_quad"], GL, 2.0, 2.0, r["m"], r["m"], r["prec"])
         try:
+            P.sinc_middle(sp.handle, 0)   # served sinc requests run the two-kernel form
             return sp(r["f"]).clone()
         finally:
             torch.cuda.synchronize()
