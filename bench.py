@@ -218,7 +218,11 @@ def sinc_benchmark(P, W, torch, steps, warmup, accuracy):
     res = {}
     for name, prec, cdt in [("fp32", P.NNFFT_FP32_COMP, torch.complex64),
                             ("fp64", P.NNFFT_FP64_PLAIN, torch.complex128)]:
+        t0 = time.perf_counter()
         sp = P.SincPlan(N, ta, tb, nq, P.SINC_QUAD_GAUSS_LEGENDRE, sig, sig, m, m, prec)
+        torch.cuda.synchronize()
+        plan_s = time.perf_counter() - t0
+        mid = P.sinc_middle(sp.handle)
         tc = torch.tensor(c, dtype=cdt, device=dev)
         h = torch.empty(len(b), dtype=cdt, device=dev)
         st = torch.cuda.current_stream()
@@ -228,7 +232,12 @@ def sinc_benchmark(P, W, torch, steps, warmup, accuracy):
         fn()
         torch.cuda.synchronize()
         res[name] = {"ms_per_step": t * 1e3, "value": (len(a) + len(b)) / t, "unit": "pts/s",
-                     "h": h.cpu().numpy()}
+                     "plan_s": plan_s, "middle_operator": bool(mid["active"]), "h": h.cpu().numpy()}
+        if mid["active"]:
+            # the two-kernel form of the same plan, for reference
+            P.sinc_middle(sp.handle, 0)
+            res[name]["two_kernel_ms_per_step"] = time_steps(fn, steps, warmup, torch) * 1e3
+            P.sinc_middle(sp.handle, 1)
         sp.close()
     for name in res:
         out[name] = {k: v for k, v in res[name].items() if k != "h"}

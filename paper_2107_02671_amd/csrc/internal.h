@@ -20,10 +20,12 @@ constexpr int kMaxPlanes = 16;      // colours of spreading windows with fixed o
 
 // One work item: up to Q consecutive sorted points of one cell bin.
 struct Item {
-    int32_t bin;   // bin (cell) storage index
-    int32_t p0;    // first sorted point
-    int32_t n;     // number of points (0: padding item)
-    int32_t pad;
+    int32_t bin;      // bin (cell) storage index
+    int32_t p0;       // first sorted point
+    int32_t n;        // number of points (0: padding item)
+    int32_t maxrun;   // first item of a chunk: the most items of one bin in the
+                      // chunk (the spreading kernels choose how to sum a bin
+                      // by it); 0 elsewhere
 };
 
 // One workgroup's share: up to 64 consecutive items of one node block with

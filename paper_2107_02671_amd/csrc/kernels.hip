@@ -256,6 +256,19 @@ __device__ __forceinline__ cx<T> folded_row(const cx<T> *__restrict__ row, cx<T>
     return acc;
 }
 
+// The same sum from a row already loaded as 8 float4 (FP32, n1 = 16)
+__device__ __forceinline__ cx<float> horner16(const float4 (&r4)[8], cx<float> w)
+{
+    cx<float> acc = cxmk(r4[7].z, r4[7].w);
+    acc = cmul(acc, w) + cxmk(r4[7].x, r4[7].y);
+#pragma unroll
+    for (int j = 6; j >= 0; --j) {
+        acc = cmul(acc, w) + cxmk(r4[j].z, r4[j].w);
+        acc = cmul(acc, w) + cxmk(r4[j].x, r4[j].y);
+    }
+    return acc;
+}
+
 template <typename T>
 __device__ __forceinline__ cx<T> folded_output(const InterpArgs &A, int s)
 {
@@ -372,11 +385,11 @@ __device__ __forceinline__ void spread32_load_records(const SpreadArgs &A, int g
     const int t = threadIdx.x & (kItemsPerWg - 1), w = __builtin_amdgcn_readfirstlane(threadIdx.x / kItemsPerWg);
     const int rows = A.rows, rpw = (rows + kWaves32 - 1) / kWaves32, row0 = w * rpw;
     const PtRec *__restrict__ rec = A.rec32 + (size_t)g * rows * kItemsPerWg + t;
+    // every row load is issued unconditionally (rows past the wave's share
+    // repeat its last row: same lines): under a branch per row the compiler
+    // completes each load before issuing the next
 #pragma unroll
-    for (int j = 0; j < kRowsPerWave; ++j) {   // rpw is uniform: rows past it are not loaded
-        R.r[j] = PtRec{0, 0.f};
-        if (j < rpw) R.r[j] = rec[wave_row(row0, j, rpw, rows) * kItemsPerWg];
-    }
+    for (int j = 0; j < kRowsPerWave; ++j) R.r[j] = rec[wave_row(row0, j, rpw, rows) * kItemsPerWg];
     R.it = A.items[g * kItemsPerWg + t];
 }
 
@@ -431,7 +444,7 @@ __device__ __forceinline__ void spread32_moments(const SpreadArgs &A, const cx<f
 // are in L.C).  Barriers order LDS only, so loads issued before stay in
 // flight.
 template <int TM>
-__device__ __forceinline__ void spread32_cells(const SpreadArgs &A, const Chunk &ch, Spread32Lds<TM> &L)
+__device__ __forceinline__ void spread32_cells(const SpreadArgs &A, const Chunk &ch, int run, Spread32Lds<TM> &L)
 {
     constexpr int D = kDeg;
     const int t = threadIdx.x & (kItemsPerWg - 1), w = __builtin_amdgcn_readfirstlane(threadIdx.x / kItemsPerWg);
@@ -444,11 +457,6 @@ __device__ __forceinline__ void spread32_cells(const SpreadArgs &A, const Chunk 
     }
     lds_barrier();
     constexpr int KW = (D + kWaves32) / kWaves32;   // moments per wave (3; the last one only on wave 0)
-    // the longest run of items of one bin in the chunk (each wave finds it)
-    int run = (t < ch.nbin) ? L.runE[t] - L.runS[t] : 0;
-#pragma unroll
-    for (int o = kItemsPerWg / 2; o > 0; o >>= 1) run = max(run, __shfl_xor(run, o));
-    run = __builtin_amdgcn_readfirstlane(run);
     if (run <= kSerialRun) {
         // short runs: thread (w, bin) adds the bin's items in order
         if (t < ch.nbin) {
@@ -587,7 +595,9 @@ __device__ void spread32_slot(const SpreadArgs &A, const cx<float> *__restrict__
     if (ch.nitem == 0) return;
     stage_taps(L.C, A.C, 2 * A.m);   // read after the barriers below
     spread32_moments<TM>(A, f, g, ch, R, L);
-    spread32_cells<TM>(A, ch, L);
+    // the chunk's longest bin run, from its first item (lane 0 of every wave)
+    const int run = __builtin_amdgcn_readfirstlane(R.it.maxrun);
+    spread32_cells<TM>(A, ch, run, L);
 }
 
 // One workgroup per launch slot (slot g runs on XCD g mod 8).  At least 6
@@ -759,23 +769,37 @@ __device__ __forceinline__ void interp32_slot(const InterpArgs &A, cx<float> *__
     // after the offset) and the tap series, staged in LDS; the record rows and
     // the item follow in the same round of loads
     // (nwin < 64 + 2m <= kThreads32; the series has up to 2 kThreads32 entries)
-    cx<float> hw0 = cxmk(0.f, 0.f);
-    float c0 = 0.f, c1 = 0.f;
+    // Loads in the order they are needed (the memory counter completes them
+    // in issue order): the window values' data, the tap series and the item,
+    // then the record rows (unconditional, as in spreading), which stay in
+    // flight across the LDS barrier below.  A folded window value is formed
+    // from its row only after the record rows are issued.
     const int nwin = ch.nbin + tm - 1, nc = tm * (D + 1);
-    if (threadIdx.x < nwin) {
-        const int s = ch.bin_lo - A.ip_off - m + 1 + threadIdx.x;   // label of window value
-        hw0 = A.fusedB ? folded_output<float>(A, s) : reinterpret_cast<const cx<float> *>(A.hlin)[s + A.h_off];
+    // (the FP32 fold has n1 = 16; the loads of both forms go to registers
+    // of their own, so that neither waits for the other's)
+    const int sw = ch.bin_lo - A.ip_off - m + 1 + min((int)threadIdx.x, nwin - 1);   // label of window value
+    float4 wrow[8];
+    cx<float> wtw, hv;
+    if (A.fusedB) {
+        const int k = sw < 0 ? sw + A.N2 : sw;
+        const int k1 = k / A.fn2, k2 = k - k1 * A.fn2;
+        const float4 *row = reinterpret_cast<const float4 *>(reinterpret_cast<const cx<float> *>(A.Y) + (size_t)k2 * 16);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) wrow[j] = row[j];
+        wtw = reinterpret_cast<const cx<float> *>(A.twB)[k1];
+    } else {
+        hv = reinterpret_cast<const cx<float> *>(A.hlin)[sw + A.h_off];
     }
-    if (threadIdx.x < nc) c0 = A.C[threadIdx.x];
-    if (threadIdx.x + kThreads32 < nc) c1 = A.C[threadIdx.x + kThreads32];
-    const Item it = A.items[g * kItemsPerWg + t];   // before the records: waited for first
+    const float c0 = A.C[min((int)threadIdx.x, nc - 1)];
+    const float c1 = A.C[min((int)threadIdx.x + kThreads32, nc - 1)];
+    const Item it = A.items[g * kItemsPerWg + t];
     const PtRec *__restrict__ rec = A.rec32 + (size_t)g * rows * kItemsPerWg + t;
     PtRec r[kRowsPerWave];
 #pragma unroll
-    for (int j = 0; j < kRowsPerWave; ++j) {   // rpw is uniform: rows past it are not loaded
-        r[j] = PtRec{0, 0.f};
-        if (j < rpw) r[j] = rec[wave_row(row0, j, rpw, rows) * kItemsPerWg];
-    }
+    for (int j = 0; j < kRowsPerWave; ++j) r[j] = rec[wave_row(row0, j, rpw, rows) * kItemsPerWg];
+    cx<float> hw0;
+    if (A.fusedB) hw0 = horner16(wrow, wtw);
+    else hw0 = hv;
     const int lab = it.bin - A.ip_off;
     if (threadIdx.x < nwin) L.hw[threadIdx.x] = hw0;
     if (threadIdx.x < nc) L.C[threadIdx.x] = c0;

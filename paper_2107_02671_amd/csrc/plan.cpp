@@ -319,6 +319,12 @@ void block_schedule(const int32_t *cnt, int64_t nbins, int64_t k0, int Q, BlockO
         c.nitem = (int32_t)(cj - ci);
         c.bin_lo = blo;
         c.nbin = o.items[cj - 1].bin - blo + 1;
+        int32_t run = 1, maxrun = 1;
+        for (size_t i = ci + 1; i < cj; ++i) {
+            run = (o.items[i].bin == o.items[i - 1].bin) ? run + 1 : 1;
+            maxrun = std::max(maxrun, run);
+        }
+        o.items[ci].maxrun = maxrun;
         o.chunks.push_back(c);
         o.item0.push_back((int32_t)ci);
         ci = cj;
@@ -849,7 +855,7 @@ static void fft_tables(HostPlan &H)
 // outputs each of its workgroups reads, so the transform takes one launch.
 // Longer transforms keep the two-launch split: 16 stage-A workgroups then
 // merge too many window planes each (measured slower at N2 = 16384).
-constexpr int kFusedN1 = 16;
+constexpr int kFusedN1 = 16;   // the FP32 interpolation folds rows of exactly 16 values
 constexpr int64_t kFusedMaxN2 = 4096;
 
 static nnfft_status plan_fft(HostPlan &H, const nnfft_info_t &P, bool fp32, int64_t S)
@@ -1292,6 +1298,17 @@ nnfft_status check_plan(const HostPlan &H, const std::vector<double> &v, const s
                     continue;
                 }
                 if (it.n < 1 || it.n > L.Q) return std::string(name) + ": item size";
+                if (t == 0) {
+                    int run = 1, maxrun = 1;
+                    for (int u = 1; u < c.nitem; ++u) {
+                        const int b0 = S.launch_items[g * kItemsPerWg + u - 1].bin;
+                        run = (S.launch_items[g * kItemsPerWg + u].bin == b0) ? run + 1 : 1;
+                        maxrun = std::max(maxrun, run);
+                    }
+                    if (it.maxrun != maxrun) return std::string(name) + ": chunk's longest bin run";
+                } else if (it.maxrun != 0) {
+                    return std::string(name) + ": run length outside a chunk's first item";
+                }
                 if (it.bin < c.bin_lo || it.bin >= c.bin_lo + c.nbin || it.bin >= nbins)
                     return std::string(name) + ": item bin outside its chunk";
                 for (int q = 0; q < it.n; ++q) {
