@@ -365,8 +365,8 @@ __device__ __forceinline__ void add_moments(float *mr, float *mi, cx<float> fv, 
 //     item moment is the plain sum of the four wave shares, items of a bin are
 //     added with two-sum;
 //  B2: thread (w, bin) forms taps r = w, w + 4, ...: sum_k C[r][k] M_k;
-//  C: window cell c (grid cell bin_lo - m + 1 + c) = two-sum over r of tap r
-//     of bin c - r, stored as (hi.re, hi.im, lo.re, lo.im).
+//  C: window cell c (grid cell bin_lo - m + 1 + c) = sum over r of tap r of
+//     bin c - r in FP64, stored as the FP32 pair (hi.re, hi.im, lo.re, lo.im).
 // (All of a workgroup's loads are issued before any arithmetic; the kernel
 // is VALU- and latency-bound, one chunk per workgroup with all chunks
 // resident at once: a persistent variant that prefetched the next chunk
@@ -571,16 +571,21 @@ __device__ __forceinline__ void spread32_cells(const SpreadArgs &A, const Chunk 
             const int b = min(max(wc - rr, 0), ch.nbin - 1);
             v[rr] = L.sbin[rr][b];
         }
-        float hr = 0.f, hi = 0.f, lr = 0.f, li = 0.f;
+        // the at most 2m taps of the cell added in FP64 (exact for FP32
+        // terms of similar size, far below FP32 rounding otherwise), then
+        // split into the (hi, lo) FP32 pair the merge adds with two-sum
+        double sr = 0.0, si = 0.0;
 #pragma unroll
         for (int rr = 0; rr < TM; ++rr) {
             const int b = wc - rr;
             if (rr < tm && b >= 0 && b < ch.nbin) {
-                comp_add(hr, lr, v[rr].re);
-                comp_add(hi, li, v[rr].im);
+                sr += (double)v[rr].re;
+                si += (double)v[rr].im;
             }
         }
-        part[window_index(ch, wc, m, A.slotT, A.slotP)] = make_float4(hr, hi, lr, li);
+        const float hr = (float)sr, hi = (float)si;
+        part[window_index(ch, wc, m, A.slotT, A.slotP)] =
+            make_float4(hr, hi, (float)(sr - (double)hr), (float)(si - (double)hi));
     }
 }
 
