@@ -326,10 +326,17 @@ struct Spread32Lds {
         cx<float> sbin[TM][kItemsPerWg];                  // 2m taps of each bin (B2, C)
     };
     cx<float> bmom[kDeg + 1][kItemsPerWg];                // moments of each bin
+    float C[TM * (kDeg + 1)];                         // tap coefficients
     int ibin[kItemsPerWg];
     int runS[kItemsPerWg];
     int runE[kItemsPerWg];
 };
+
+// Copies the [2m][kDeg + 1] tap coefficients into LDS.
+__device__ __forceinline__ void stage_taps(float *dst, const float *__restrict__ src, int tm)
+{
+    for (int i = threadIdx.x; i < tm * (kDeg + 1); i += blockDim.x) dst[i] = src[i];
+}
 
 // Chebyshev moments mu_k += f * T_k(y), k = 0..kDeg
 __device__ __forceinline__ void add_moments(float *mr, float *mi, cx<float> fv, float y)
@@ -433,9 +440,9 @@ __device__ __forceinline__ void spread32_moments(const SpreadArgs &A, const cx<f
     if (w == 0 && R.it.n > 0) L.ibin[t] = R.it.bin - ch.bin_lo;
 }
 
-// Phases B1, B2, C: bin moments, taps, window cells (the tap coefficients,
-// the same for every lane of a wave, are read with scalar loads).  Barriers
-// order LDS only, so loads issued before stay in flight.
+// Phases B1, B2, C: bin moments, taps, window cells (the tap coefficients
+// are in L.C).  Barriers order LDS only, so loads issued before stay in
+// flight.
 template <int TM>
 __device__ __forceinline__ void spread32_cells(const SpreadArgs &A, const Chunk &ch, int run, Spread32Lds<TM> &L)
 {
@@ -544,7 +551,7 @@ __device__ __forceinline__ void spread32_cells(const SpreadArgs &A, const Chunk 
             Mi[k] = v.im;
         }
         for (int r0 = w; r0 < tm; r0 += kWaves32) {
-            const float *__restrict__ c = A.C + r0 * (D + 1);   // wave-uniform: scalar loads
+            const float *c = L.C + r0 * (D + 1);
             float ar = 0.f, ai = 0.f;
 #pragma unroll
             for (int k = 0; k <= D; ++k) {
@@ -591,6 +598,7 @@ __device__ void spread32_slot(const SpreadArgs &A, const cx<float> *__restrict__
     spread32_gather(A, f, R);
     const Chunk ch = A.chunks[g];
     if (ch.nitem == 0) return;
+    stage_taps(L.C, A.C, 2 * A.m);   // read after the barriers below
     spread32_moments<TM>(A, f, g, ch, R, L);
     // the chunk's longest bin run, from its first item (lane 0 of every wave)
     const int run = __builtin_amdgcn_readfirstlane(R.it.maxrun);

@@ -298,18 +298,38 @@ constexpr int kBlockThreads = 4;
 // schedule here, so they agree item for item.
 void block_schedule(const int32_t *cnt, int64_t nbins, int64_t k0, int Q, BlockOut &o)
 {
-    int64_t p = k0;
+    // items: one per bin of at most Q points, else the bin's points split
+    // evenly.  The common case is written without a branch (an empty bin's
+    // item is overwritten by the next one): bin counts are random, so
+    // branches on them are mispredicted.
+    int64_t npts = 0, nz = 0;
     for (int64_t b = 0; b < nbins; ++b) {
-        const int64_t n = cnt[b];
-        if (n == 0) continue;
-        const int64_t nit = (n + Q - 1) / Q;
-        const int64_t base = n / nit, rem = n % nit;
-        for (int64_t q = 0; q < nit; ++q) {
-            const int64_t len = base + (q < rem ? 1 : 0);
-            o.items.push_back(Item{(int32_t)b, (int32_t)p, (int32_t)len, 0});
+        npts += cnt[b];
+        nz += cnt[b] != 0;
+    }
+    o.items.resize((size_t)(nz + npts / Q + 1));
+    Item *it = o.items.data();
+    int64_t k = 0;
+    int32_t p = (int32_t)k0;
+    for (int64_t b = 0; b < nbins; ++b) {
+        const int32_t n = cnt[b];
+        if (n <= Q) {
+            it[k] = Item{(int32_t)b, p, n, 0};
+            k += n != 0;
+            p += n;
+            continue;
+        }
+        const int32_t nit = (n + Q - 1) / Q;
+        const int32_t base = n / nit, rem = n - base * nit;
+        for (int32_t q = 0; q < nit; ++q) {
+            const int32_t len = base + (q < rem ? 1 : 0);
+            it[k++] = Item{(int32_t)b, p, len, 0};
             p += len;
         }
     }
+    o.items.resize((size_t)k);
+    o.chunks.reserve(o.items.size() / 16 + 1);
+    o.item0.reserve(o.items.size() / 16 + 1);
     const size_t it1 = o.items.size();
     for (size_t ci = 0; ci < it1;) {
         const int32_t blo = o.items[ci].bin;
@@ -337,29 +357,24 @@ void block_schedule(const int32_t *cnt, int64_t nbins, int64_t k0, int Q, BlockO
 bool finish_side(std::vector<BlockOut> &outs, int m, SideHost &S, std::string &err)
 {
     {
-        size_t ni = 0, nc = 0;
+        size_t nc = 0;
         for (const BlockOut &o : outs) {
             if (!o.ok) {
                 err = "internal: node record outside the grid";
                 return false;
             }
-            ni += o.items.size();
             nc += o.chunks.size();
         }
-        S.items.reserve(ni);
+        // the items stay in their blocks' outputs until the launch slots are
+        // filled (no concatenated copy)
         S.chunks.reserve(nc);
         S.chunk_block.reserve(nc);
         S.chunk_item0.reserve(nc);
         for (int64_t blk = 0; blk < (int64_t)outs.size(); ++blk) {
             BlockOut &o = outs[(size_t)blk];
-            const int32_t base = (int32_t)S.items.size();
-            S.items.insert(S.items.end(), o.items.begin(), o.items.end());
-            for (size_t c = 0; c < o.chunks.size(); ++c) {
-                S.chunks.push_back(o.chunks[c]);
-                S.chunk_block.push_back((int32_t)blk);
-                S.chunk_item0.push_back(base + o.item0[c]);
-            }
-            std::vector<Item>().swap(o.items);
+            S.chunks.insert(S.chunks.end(), o.chunks.begin(), o.chunks.end());
+            S.chunk_block.insert(S.chunk_block.end(), o.chunks.size(), (int32_t)blk);
+            S.chunk_item0.insert(S.chunk_item0.end(), o.item0.begin(), o.item0.end());
         }
     }
     int64_t part = 0;
@@ -430,10 +445,11 @@ bool finish_side(std::vector<BlockOut> &outs, int m, SideHost &S, std::string &e
     for (size_t g = 0; g < order.size(); ++g) {
         if (order[g] < 0) continue;
         const Chunk c = S.chunks[order[g]];
-        const int32_t i0 = S.chunk_item0[order[g]];
-        for (int i = 0; i < c.nitem; ++i) S.launch_items[g * kItemsPerWg + i] = S.items[i0 + i];
+        const Item *src = outs[(size_t)S.chunk_block[order[g]]].items.data() + S.chunk_item0[order[g]];
+        std::copy(src, src + c.nitem, S.launch_items.begin() + (ptrdiff_t)(g * kItemsPerWg));
         S.launch[g] = c;
     }
+    for (BlockOut &o : outs) std::vector<Item>().swap(o.items);
     return true;
 }
 

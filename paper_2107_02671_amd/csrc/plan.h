@@ -46,10 +46,9 @@ struct SideHost {
     std::vector<int32_t> perm;          // FP64: caller's index of each sorted point
     std::vector<PtRec> rec32;           // FP32: (index, offset) of each sorted point
     std::vector<double> frac64;         // FP64: offset of each sorted point
-    std::vector<Item> items;
     std::vector<Chunk> chunks;
     std::vector<int32_t> chunk_block;
-    std::vector<int32_t> chunk_item0;   // first item of each chunk
+    std::vector<int32_t> chunk_item0;   // first item of each chunk in its block's items
     std::vector<Chunk> launch;          // chunks in launch order, empty ones pad
     std::vector<Item> launch_items;     // 64 items per launch slot, n = 0 pads
     std::vector<PtRec> trec32;          // FP32: records in per-slot transposed blocks
@@ -70,6 +69,7 @@ struct BlockOut {
     bool ok = true;
 };
 void block_schedule(const int32_t *cnt, int64_t nbins, int64_t k0, int Q, BlockOut &o);
+// (the blocks' items are consumed: copied into the launch slots and freed)
 bool finish_side(std::vector<BlockOut> &outs, int m, SideHost &S, std::string &err);
 
 // FFT factorization chosen at plan time (copied into FftArgs).
