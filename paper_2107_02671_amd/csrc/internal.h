@@ -132,12 +132,24 @@ struct InterpArgs {
     int32_t nser;             // FP64 path, Kaiser-Bessel windows: terms of T64
 };
 
+// Pre-merge of long merge lists (crowded cells covered by many overflow
+// windows): segment s sums the partial cells idx[seg[2 s] ..][0 .. seg[2 s + 1])
+// of one grid cell into partial cell base + s, which the cell's merge list
+// names instead, so no FFT thread walks a long list.
+struct PreMergeArgs {
+    void *partial;            // the plan's partial cells (the spreading output)
+    const int32_t *seg;       // [2 nseg]: first index in idx, count
+    const int32_t *idx;
+    int32_t nseg, base;
+};
+
 struct PlanDev {
     int32_t prec;             // nnfft_precision
     int32_t pad0, pad1;
     SpreadArgs sp;
     FftArgs fft;
     InterpArgs ip;
+    PreMergeArgs pm;          // nseg = 0: none
 };
 
 // The middle operator of a fast sinc transform (the first plan's
@@ -176,7 +188,7 @@ struct BatchTable {
 constexpr int kMaxTimedKernels = 6;
 enum KernelId : int32_t {
     KID_SPREAD32 = 0, KID_SPREAD64, KID_FFT_SINGLE, KID_FFT_A, KID_FFT_B, KID_INTERP32, KID_INTERP64, KID_SINC_MID,
-    KID_COUNT
+    KID_PREMERGE, KID_COUNT
 };
 struct KernelTimes {
     hipEvent_t start[kMaxTimedKernels] = {}, stop[kMaxTimedKernels] = {};

@@ -54,7 +54,7 @@ static void launch_k(KernelTimes *kt, int kid, K kernel, dim3 grid, dim3 block, 
 const char *kernel_name(int kid)
 {
     static const char *const names[KID_COUNT] = {"k_spread32", "k_spread64", "k_fft_single", "k_fft_stageA",
-                                                 "k_fft_stageB", "k_interp32", "k_interp64", "k_sinc_mid"};
+                                                 "k_fft_stageB", "k_interp32", "k_interp64", "k_sinc_mid", "k_premerge"};
     return kid >= 0 && kid < KID_COUNT ? names[kid] : "?";
 }
 
@@ -1065,6 +1065,58 @@ __device__ __forceinline__ void merge_cell64(const FftArgs &A, int slot, double 
     }
 }
 
+// Pre-merge of long merge lists: one thread per segment, its entries added in
+// list order with the merge's own arithmetic (two-sum pairs in FP32, plain
+// sums in FP64), eight loads in flight at a time.
+template <typename T>
+__global__ __launch_bounds__(256) void k_premerge(PreMergeArgs A)
+{
+    const int sg = blockIdx.x * 256 + threadIdx.x;
+    if (sg >= A.nseg) return;
+    const int e0 = A.seg[2 * sg], e1 = e0 + A.seg[2 * sg + 1];
+    if constexpr (sizeof(T) == 4) {
+        float4 *part = reinterpret_cast<float4 *>(A.partial);
+        float hr = 0.f, hi = 0.f, lr = 0.f, li = 0.f;
+        for (int e = e0; e < e1; e += 8) {
+            int idx[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) idx[q] = A.idx[(e + q < e1) ? e + q : e0];
+            float4 v[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v[q] = part[idx[q]];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                if (e + q < e1) {
+                    comp_add(hr, lr, v[q].x);
+                    comp_add(hi, li, v[q].y);
+                    lr += v[q].z;
+                    li += v[q].w;
+                }
+            }
+        }
+        part[A.base + sg] = make_float4(hr, hi, lr, li);
+    } else {
+        double2 *part = reinterpret_cast<double2 *>(A.partial);
+        double ar = 0.0, ai = 0.0;
+        for (int e = e0; e < e1; e += 8) {
+            int idx[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) idx[q] = A.idx[(e + q < e1) ? e + q : e0];
+            double2 v[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v[q] = part[idx[q]];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                if (e + q < e1) {
+                    ar += v[q].x;
+                    ai += v[q].y;
+                }
+            }
+        }
+        part[A.base + sg] = make_double2(ar, ai);
+    }
+}
+
 // FFT input element q (index mod N2):
 //  mode 0 (NNFFT steps 1-2): merged step-1 cell of label l = q or q - N2 (zero
 //    outside I_{G1}) times 1 / (N1 N2 phi_hat_2(l)) (table in slot order);
@@ -1708,6 +1760,13 @@ static int corr_variant(int deg)
 }
 
 
+// the pre-merge of long merge lists, between the spreading and the FFT
+template <typename T>
+static void launch_premerge(const PreMergeArgs &M, hipStream_t s, KernelTimes *kt = nullptr)
+{
+    if (M.nseg > 0) launch_k(kt, KID_PREMERGE, k_premerge<T>, dim3((M.nseg + 255) / 256), dim3(256), 0, s, M);
+}
+
 hipError_t launch_exec(const PlanDev &P, const void *f, void *y, hipStream_t s, KernelTimes *kt)
 {
     if (kt) kt->n = 0;
@@ -1715,10 +1774,12 @@ hipError_t launch_exec(const PlanDev &P, const void *f, void *y, hipStream_t s, 
         const cx<float> *fin = reinterpret_cast<const cx<float> *>(f);
         const int gs = P.sp.ngrid, gi = P.ip.ngrid;
         launch_spread32(P.sp, gs, fin, s, kt);
+        launch_premerge<float>(P.pm, s, kt);
         launch_fft<float>(P.fft, s, kt);
         launch_interp32(corr_variant(P.ip.corr_deg), gi, s, P.ip, reinterpret_cast<cx<float> *>(y), kt);
     } else {
         launch_spread64(P.sp, f, s, kt);
+        launch_premerge<double>(P.pm, s, kt);
         launch_fft<double>(P.fft, s, kt);
         launch_interp64(P.ip, y, s, kt);
     }
@@ -1733,6 +1794,7 @@ hipError_t launch_sinc_middle(const PlanDev &P1, const SincMidArgs &M, const Pla
     F.dense_in = M.out;
     if (P1.prec == NNFFT_FP32_COMP) {
         launch_spread32(P1.sp, P1.sp.ngrid, reinterpret_cast<const cx<float> *>(c), s);
+        launch_premerge<float>(P1.pm, s);
         launch_fft<float>(P1.fft, s);
         hipLaunchKernelGGL(k_sinc_mid<float>, dim3(M.nwg), dim3(kMidThreads), (size_t)M.span_max * sizeof(cx<float>),
                            s, M);
@@ -1740,6 +1802,7 @@ hipError_t launch_sinc_middle(const PlanDev &P1, const SincMidArgs &M, const Pla
         launch_interp32(corr_variant(P2.ip.corr_deg), P2.ip.ngrid, s, P2.ip, reinterpret_cast<cx<float> *>(h));
     } else {
         launch_spread64(P1.sp, c, s, nullptr);
+        launch_premerge<double>(P1.pm, s);
         launch_fft<double>(P1.fft, s);
         hipLaunchKernelGGL(k_sinc_mid<double>, dim3(M.nwg), dim3(kMidThreads),
                            (size_t)M.span_max * sizeof(cx<double>), s, M);
@@ -1802,12 +1865,14 @@ hipError_t launch_exec_batch(int n, const PlanDev *const *host, const PlanDev *c
                 hipLaunchKernelGGL((k_spread32_batch<16>), dim3(ssp), dim3(kThreads32), 0, s, Tsp);
             else
                 hipLaunchKernelGGL((k_spread32_batch<12>), dim3(ssp), dim3(kThreads32), 0, s, Tsp);
+            for (int i = 0; i < nb; ++i) launch_premerge<float>(host[b0 + i]->pm, s);   // plans that need it
             hipLaunchKernelGGL((k_fftA_batch<float>), dim3(sA), dim3(thrA), fft_bytes, s, TA);
             if (sB > 0) hipLaunchKernelGGL((k_fftB_batch<float>), dim3(sB), dim3(thrB), fft_bytes, s, TB);
             launch_interp32_batch(corr_variant(corr_deg), sip, s, Tip);
         } else {
             hipLaunchKernelGGL(k_spread64_batch, dim3(ssp), dim3(kThreads64), lds64_bytes(tm_sp, rows_sp), s,
                                Tsp);
+            for (int i = 0; i < nb; ++i) launch_premerge<double>(host[b0 + i]->pm, s);
             hipLaunchKernelGGL((k_fftA_batch<double>), dim3(sA), dim3(thrA), fft_bytes, s, TA);
             if (sB > 0) hipLaunchKernelGGL((k_fftB_batch<double>), dim3(sB), dim3(thrB), fft_bytes, s, TB);
             hipLaunchKernelGGL(k_interp64_batch, dim3(sip), dim3(kThreads64), interp64_lds_bytes(tm_ip), s,
@@ -1836,6 +1901,7 @@ hipError_t launch_nfft(const PlanDev &P, bool adjoint, const void *in, void *out
         if (adjoint) {
             const cx<float> *yin = reinterpret_cast<const cx<float> *>(in);
             launch_spread32(P.sp, P.sp.ngrid, yin, s);
+            launch_premerge<float>(P.pm, s);
             launch_fft<float>(F, s);
         } else {
             launch_fft<float>(F, s);
@@ -1844,6 +1910,7 @@ hipError_t launch_nfft(const PlanDev &P, bool adjoint, const void *in, void *out
     } else {
         if (adjoint) {
             launch_spread64(P.sp, in, s);
+            launch_premerge<double>(P.pm, s);
             launch_fft<double>(F, s);
         } else {
             launch_fft<double>(F, s);
@@ -1923,6 +1990,7 @@ hipError_t launch_exec_static(const PlanDev &P, const ExecScratch &sz, const voi
     void *hlin = base + align256(sz.part_bytes) + align256(sz.y_bytes);
     D.sp.partial = part;
     D.fft.partial = part;
+    D.pm.partial = part;
     D.fft.Y = Y;
     D.fft.hlin = hlin;
     D.ip.hlin = hlin;

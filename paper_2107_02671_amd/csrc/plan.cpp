@@ -710,6 +710,12 @@ void layout_plan(const HostPlan &H, Carver &C, PlanDev &D, size_t *upload_end, P
     }
     FA.merge_off = C.put(H.moff);
     FA.merge_idx = C.put(H.midx);
+    if (H.pm_cells > 0) {
+        D.pm.seg = C.put(H.pm_seg);
+        D.pm.idx = C.put(H.pm_idx);
+        D.pm.nseg = (int32_t)H.pm_cells;
+        D.pm.base = (int32_t)H.pm_base;
+    }
     FA.deconv = C.put(H.deconv);
     if (fp32) FA.tw = C.put(H.tw32);
     else FA.tw = C.put(H.tw64);
@@ -747,6 +753,7 @@ void layout_plan(const HostPlan &H, Carver &C, PlanDev &D, size_t *upload_end, P
     const size_t csz = fp32 ? 8 : 16;
     SA.partial = C.scratch((size_t)H.sp.part_cells * 16);
     FA.partial = SA.partial;
+    D.pm.partial = SA.partial;
     FA.Y = C.scratch((size_t)P.N2 * csz);
     FA.hlin = C.scratch((size_t)H.hlin_len * csz);
     IA.hlin = FA.hlin;
@@ -814,6 +821,8 @@ static int64_t slot_of(const HostPlan &H, int64_t cell)
     return (cell % H.slotT) * H.slotP + cell / H.slotT;
 }
 
+constexpr int32_t kMergeDirect = 8;   // longest merge list the FFT load walks itself
+
 static nnfft_status build_merge_lists(HostPlan &H, const nnfft_info_t &P, int m1)
 {
     // merge lists of the overflow windows (those without a plane): for each
@@ -841,6 +850,41 @@ static nnfft_status build_merge_lists(HostPlan &H, const nnfft_info_t &P, int m1
                 H.midx[cur[slot_of(H, cell)]++] = c.part_off + w;
             }
         }
+    }
+    // lists longer than kMergeDirect entries: cut into segments of
+    // L = ceil(n / kMergeDirect) entries, each pre-merged into a partial cell
+    // of its own (after the existing ones), so every list the FFT load walks
+    // has at most kMergeDirect entries (one round of loads)
+    H.pm_seg.clear();
+    H.pm_idx.clear();
+    H.pm_base = H.sp.part_cells;
+    H.pm_cells = 0;
+    bool longer = false;
+    for (int64_t sl = 0; sl < ns && !longer; ++sl) longer = H.moff[sl + 1] - H.moff[sl] > kMergeDirect;
+    if (longer) {
+        std::vector<int32_t> off2(ns + 1, 0), idx2;
+        idx2.reserve(H.midx.size());
+        for (int64_t sl = 0; sl < ns; ++sl) {
+            const int32_t e0 = H.moff[sl], n = H.moff[sl + 1] - e0;
+            if (n <= kMergeDirect) {
+                idx2.insert(idx2.end(), H.midx.begin() + e0, H.midx.begin() + e0 + n);
+            } else {
+                const int32_t L = (n + kMergeDirect - 1) / kMergeDirect;
+                for (int32_t s0 = 0; s0 < n; s0 += L) {
+                    const int32_t cnt = std::min(L, n - s0);
+                    H.pm_seg.push_back((int32_t)H.pm_idx.size());
+                    H.pm_seg.push_back(cnt);
+                    H.pm_idx.insert(H.pm_idx.end(), H.midx.begin() + e0 + s0, H.midx.begin() + e0 + s0 + cnt);
+                    idx2.push_back((int32_t)(H.pm_base + H.pm_cells));
+                    ++H.pm_cells;
+                }
+            }
+            off2[sl + 1] = (int32_t)idx2.size();
+        }
+        H.moff.swap(off2);
+        H.midx.swap(idx2);
+        H.sp.part_cells += H.pm_cells;
+        if (H.sp.part_cells >= ((int64_t)1 << 31)) return fail(NNFFT_ERR_UNSUPPORTED, "too many partial cells");
     }
     return NNFFT_OK;
 }
@@ -1367,6 +1411,7 @@ nnfft_status check_plan(const HostPlan &H, const std::vector<double> &v, const s
         (H.kind == 0 && (int64_t)H.deconv.size() != ps))
         return fail(NNFFT_ERR_ARG, "internal: slot layout of the planes");
     std::vector<int32_t> owner((size_t)H.sp.part_cells, -1), ovf_count(G1, 0);
+    std::vector<int64_t> cell_of((size_t)H.sp.part_cells, -1);   // overflow partial cell -> grid cell
     for (size_t c = 0; c < H.sp.chunks.size(); ++c) {
         const Chunk &ch = H.sp.chunks[c];
         const int64_t lo = (int64_t)ch.bin_lo - P.m1 + 1, W = ch.nbin + W0;
@@ -1382,7 +1427,10 @@ nnfft_status check_plan(const HostPlan &H, const std::vector<double> &v, const s
             if (idx < 0 || idx >= H.sp.part_cells) return fail(NNFFT_ERR_ARG, "internal: partial index out of range");
             if (owner[idx] >= 0) return fail(NNFFT_ERR_ARG, "internal: two windows share a partial cell");
             owner[idx] = (int32_t)c;
-            if (!in_plane) ovf_count[cell]++;
+            if (!in_plane) {
+                ovf_count[cell]++;
+                cell_of[idx] = cell;
+            }
         }
     }
     {
@@ -1395,14 +1443,41 @@ nnfft_status check_plan(const HostPlan &H, const std::vector<double> &v, const s
         std::sort(b.begin(), b.end());
         if (a != b) return fail(NNFFT_ERR_ARG, "internal: launch chunks differ from the chunks");
     }
+    // every overflow partial cell is merged exactly once, into its own grid
+    // cell: directly from the cell's list, or through one pre-merge segment
+    // named there (each segment named once)
+    if ((int64_t)H.pm_seg.size() != 2 * H.pm_cells || H.pm_base + H.pm_cells != H.sp.part_cells)
+        return fail(NNFFT_ERR_ARG, "internal: pre-merge segments");
+    std::vector<char> merged((size_t)H.sp.part_cells, 0), seg_used((size_t)H.pm_cells, 0);
+    auto take = [&](int64_t e2, int64_t cell) {
+        if (e2 < plane_cells || e2 >= H.pm_base || owner[e2] < 0 || cell_of[e2] != cell || merged[e2]) return false;
+        merged[e2] = 1;
+        return true;
+    };
     for (int64_t cell = 0; cell < G1; ++cell) {
         const int64_t sl = (cell % T) * Ps + cell / T;
-        if (H.moff[sl + 1] - H.moff[sl] != ovf_count[cell])
-            return fail(NNFFT_ERR_ARG, "internal: merge list does not match the overflow windows");
+        int64_t n = 0;
+        for (int32_t e = H.moff[sl]; e < H.moff[sl + 1]; ++e) {
+            const int64_t e2 = H.midx[e];
+            if (e2 >= H.pm_base) {
+                const int64_t sg = e2 - H.pm_base;
+                if (sg >= H.pm_cells || seg_used[sg]) return fail(NNFFT_ERR_ARG, "internal: pre-merge segment reuse");
+                seg_used[sg] = 1;
+                const int32_t i0 = H.pm_seg[2 * sg], cnt = H.pm_seg[2 * sg + 1];
+                if (i0 < 0 || cnt < 1 || (size_t)i0 + cnt > H.pm_idx.size())
+                    return fail(NNFFT_ERR_ARG, "internal: pre-merge segment range");
+                for (int32_t q = 0; q < cnt; ++q)
+                    if (!take(H.pm_idx[i0 + q], cell))
+                        return fail(NNFFT_ERR_ARG, "internal: pre-merge entry outside the cell's overflow windows");
+                n += cnt;
+            } else {
+                if (!take(e2, cell)) return fail(NNFFT_ERR_ARG, "internal: merge list entry outside the overflow windows");
+                ++n;
+            }
+        }
+        if (n != ovf_count[cell]) return fail(NNFFT_ERR_ARG, "internal: merge list does not match the overflow windows");
+        if (H.moff[sl + 1] - H.moff[sl] > kMergeDirect) return fail(NNFFT_ERR_ARG, "internal: merge list too long");
     }
-    for (int32_t e2 : H.midx)
-        if (e2 < plane_cells || e2 >= H.sp.part_cells || owner[e2] < 0)
-            return fail(NNFFT_ERR_ARG, "internal: merge list entry outside the overflow windows");
     return NNFFT_OK;
 }
 

@@ -96,6 +96,8 @@ struct HostPlan {
     std::vector<double> twA, twB, tw4; // four-step tables (values of the plan's precision)
     int32_t slotT = 1, slotP = 0;      // plane cell c at slot (c mod T) P + c div T
     std::vector<int32_t> moff, midx;   // merge lists of the spreading windows
+    std::vector<int32_t> pm_seg, pm_idx;   // pre-merge segments of long lists (PreMergeArgs)
+    int64_t pm_base = 0, pm_cells = 0;     // their output cells: partial cells pm_base ..
     FftPlan fd{};
     int kind = 0;                      // 0 NNFFT, 1 NFFT with equispaced frequencies
     int64_t hlin_len = 0;              // FFT outputs kept for the interpolation

@@ -1,0 +1,119 @@
+"""Crowded cells: node sets whose grid cells lie under more overflow windows
+than the FFT load merges itself (more than 8 beyond the 16 window planes) get
+their long merge lists pre-merged in segments (k_premerge) before the FFT.
+
+Checked on node sets concentrated in a few tight clusters, where every
+cluster cell is covered by windows of every node block: the plan launches
+the pre-merge (kernel profile), the result agrees with the FP64 oracle at the
+NNFFT gates (and with the direct sum (1.2) on samples), a batched launch of
+such plans with uncrowded ones is bitwise equal to their single execs, and
+the allocation-free entry point equals nnfft_exec.  The layout invariants of
+the segments (each overflow partial cell merged exactly once, into its own
+grid cell, no list longer than 8) are checked by every plan's dry run.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2107_02671_amd as P
+from paper_2107_02671_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FP64, FP32 = P.NNFFT_FP64_PLAIN, P.NNFFT_FP32_COMP
+DEV = "cuda:0"
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _crowded(g, M, nclusters=3, std=2e-4):
+    return W.clustered_nodes(g, M, nclusters=nclusters, std=std)
+
+
+def _kernels(pl, f):
+    P.nnfft_profile_start(pl.handle, 2)
+    pl(f)
+    pl(f)
+    torch.cuda.synchronize()
+    kern, _ = P.nnfft_profile_kernels(pl.handle, 2)
+    return [k["name"] for k in kern]
+
+
+@pytest.mark.parametrize("prec", [FP32, FP64])
+def test_crowded_cells_parity(prec):
+    N, M = 2048, 1 << 18
+    g = W.rng(1701)
+    v, x, f = _crowded(g, M), _crowded(g, M), W.complex_gaussian(g, M)
+    cdt = torch.complex64 if prec == FP32 else torch.complex128
+    _say(f"[gpu] crowded cells N={N} M={M} prec={prec}")
+    with P.Plan(N, torch.tensor(v, device=DEV), torch.tensor(x, device=DEV), 2.0, 2.0, 6, 6, prec) as pl:
+        tf = torch.tensor(f, dtype=cdt, device=DEV)
+        names = _kernels(pl, tf)
+        y = pl(tf)
+        torch.cuda.synchronize()
+    _say(f"    kernels {names}")
+    assert "k_premerge" in names
+    y = y.cpu().numpy().astype(np.complex128)
+    yo = oracle.nnfft(N, v, f, x, 2.0, 2.0, 6, 6)
+    e = float(np.abs(y - yo).max() / np.abs(yo).max())
+    tol = 1e-12 if prec == FP64 else 1e-5
+    _say(f"    E_inf vs oracle {e:.2e} (tol {tol:.0e})")
+    assert e <= tol
+    # against the direct sum (1.2) on samples: within Theorem 4.1
+    idx = W.rng(3).choice(M, 64, replace=False)
+    ex = oracle.direct(N, v, f, x[idx])
+    Pp = oracle.params(N, 2.0, 2.0, 6, 6)
+    E = oracle.bound_thm41_gate(Pp.N1, 6, 6, Pp.sigma1_eff, Pp.sigma2_eff)
+    err = float(np.abs(y[idx] - ex).max() / np.abs(f).sum())
+    _say(f"    E_paper on 64 samples {err:.2e} (Theorem 4.1 {E:.1e})")
+    assert err <= E + tol * np.abs(yo).max() / np.abs(f).sum()
+
+
+def test_crowded_plans_in_a_batch_equal_single_execs():
+    g = W.rng(1702)
+    specs = [(FP32, 1 << 18, True), (FP32, 20000, False), (FP64, 1 << 18, True), (FP64, 30000, False),
+             (FP32, 1 << 16, True)]
+    plans, fs, singles = [], [], []
+    try:
+        for prec, M, crowd in specs:
+            v = _crowded(g, M) if crowd else W.uniform_nodes(g, M)
+            x = _crowded(g, M) if crowd else W.uniform_nodes(g, M)
+            cdt = torch.complex64 if prec == FP32 else torch.complex128
+            plans.append(P.Plan(2048, torch.tensor(v, device=DEV), torch.tensor(x, device=DEV), 2.0, 2.0, 6, 6,
+                                prec))
+            fs.append(torch.tensor(W.complex_gaussian(g, M), dtype=cdt, device=DEV))
+        _say(f"[gpu] batch of {len(plans)} plans, three with crowded cells")
+        singles = [p(f).clone() for p, f in zip(plans, fs)]
+        ys = [torch.full_like(s, float("nan")) for s in singles]
+        for prec in (FP32, FP64):
+            sel = [i for i, sp in enumerate(specs) if sp[0] == prec]
+            P.nnfft_exec_batch([plans[i].handle for i in sel], [fs[i] for i in sel], [ys[i] for i in sel])
+        torch.cuda.synchronize()
+        for i, (a, b) in enumerate(zip(singles, ys)):
+            assert torch.equal(a, b), f"plan {i} differs from its single exec"
+    finally:
+        for p in plans:
+            p.close()
+
+
+@pytest.mark.parametrize("prec", [FP32, FP64])
+def test_crowded_noalloc_equals_exec(prec):
+    g = W.rng(1703)
+    M = 1 << 18
+    v, x = _crowded(g, M), _crowded(g, M)
+    cdt = torch.complex64 if prec == FP32 else torch.complex128
+    _say(f"[gpu] crowded cells, allocation-free exec prec={prec}")
+    with P.Plan(2048, torch.tensor(v, device=DEV), torch.tensor(x, device=DEV), 2.0, 2.0, 6, 6, prec) as pl:
+        f = torch.tensor(W.complex_gaussian(g, M), dtype=cdt, device=DEV)
+        assert "k_premerge" in _kernels(pl, f)
+        a = pl(f).clone()
+        b = torch.full_like(a, float("nan"))
+        P.binding.nnfft_exec_noalloc(pl.handle, f, b)
+        torch.cuda.synchronize()
+    assert torch.equal(a, b)
