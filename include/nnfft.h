@@ -415,6 +415,21 @@ nnfft_status sinc_destroy(sinc_plan_t p);
 nnfft_status sinc_middle(sinc_plan_t p, int on, int32_t *built, int32_t *active);
 
 /*
+ * Host-only: the middle operator sinc_plan would build for bandwidth N, the
+ * quadrature (quad, n_quad) and sigma, m, precision (it does not depend on
+ * the nodes a_k, b_l).  On return *G1 is the number of rows (labels
+ * l = r - G1/2, r = 0..G1-1) and *Wb the band width; if K and lo are non-null
+ * and cap >= G1 * Wb, K[b * G1 + r] receives entry b of row r (label
+ * lo[r] + b of the first FFT's outputs) and lo[r] the row's first label.
+ * Errors: ARG (as sinc_plan, or cap too small with K given), UNSUPPORTED if
+ * the operator is not built for these parameters (more than 2^16 nodes or a
+ * band wider than 256 labels).
+ */
+nnfft_status sinc_middle_dry_run(int64_t N, sinc_quad quad, int64_t n_quad, double sigma1, double sigma2, int m1,
+                                 int m2, nnfft_precision prec, double *K, int32_t *lo, int64_t cap, int64_t *G1,
+                                 int32_t *Wb);
+
+/*
  * The quadrature rule sinc_plan uses, on the host (no device work):
  * z[n_nodes], w[n_nodes] HOST arrays with n_nodes = n_quad (Gauss-Legendre)
  * or n_quad + 1 (Clenshaw-Curtis); weights sum to 1 (sinc(N pi x) is half the

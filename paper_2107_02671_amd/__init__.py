@@ -10,7 +10,7 @@ from .binding import (NNFFT_FP32_COMP, NNFFT_FP64_PLAIN, SINC_QUAD_CLENSHAW_CURT
                       SINC_QUAD_GAUSS_LEGENDRE, NnfftError, Plan, SincPlan, nnfft_derive_params,
                       nnfft_destroy, nnfft_exec, nnfft_exec_batch, nnfft_info, nnfft_last_error,
                       nnfft_plan, nnfft_profile_kernels, nnfft_profile_start, nnfft_profile_stop, nnfft_quadrature, nnfft_version,
-                      sinc_destroy, sinc_exec, sinc_info, sinc_middle, sinc_plan, sinc_sizes, nnfft_autotune, nnfft_set_tuning,
+                      sinc_destroy, sinc_exec, sinc_info, sinc_middle, sinc_middle_dry_run, sinc_plan, sinc_sizes, nnfft_autotune, nnfft_set_tuning,
                       nnfft_get_tuning, nnfft_clear_tuning, Server, NNFFT_REQ_NNFFT, NNFFT_REQ_SINC,
                       NfftPlan, nfft_plan, nfft_exec, nfft_adjoint, nfft_destroy, nfft_plan_dry_run,
                       NNFFT_WINDOW_SINH, NNFFT_WINDOW_BSPLINE, NNFFT_WINDOW_ALGEBRAIC,
@@ -18,7 +18,7 @@ from .binding import (NNFFT_FP32_COMP, NNFFT_FP64_PLAIN, SINC_QUAD_CLENSHAW_CURT
 
 __all__ = ["binding", "Plan", "SincPlan", "NnfftError", "nnfft_plan", "nnfft_exec", "nnfft_exec_batch",
            "nnfft_info", "nnfft_destroy", "nnfft_profile_start", "nnfft_profile_stop", "nnfft_profile_kernels", "nnfft_derive_params", "nnfft_last_error", "nnfft_quadrature", "nnfft_version",
-           "sinc_plan", "sinc_exec", "sinc_info", "sinc_sizes", "sinc_destroy", "sinc_middle", "NNFFT_FP32_COMP", "NNFFT_FP64_PLAIN",
+           "sinc_plan", "sinc_exec", "sinc_info", "sinc_sizes", "sinc_destroy", "sinc_middle", "sinc_middle_dry_run", "NNFFT_FP32_COMP", "NNFFT_FP64_PLAIN",
            "SINC_QUAD_GAUSS_LEGENDRE", "SINC_QUAD_CLENSHAW_CURTIS", "nnfft_autotune", "nnfft_set_tuning",
            "nnfft_get_tuning", "nnfft_clear_tuning", "Server", "NNFFT_REQ_NNFFT", "NNFFT_REQ_SINC",
            "NfftPlan", "nfft_plan", "nfft_exec", "nfft_adjoint", "nfft_destroy", "nfft_plan_dry_run",

@@ -156,6 +156,8 @@ def lib():
                              ctypes.POINTER(ci)]
     L.sinc_destroy.argtypes = [vp]
     L.sinc_middle.argtypes = [vp, ci, ctypes.POINTER(ci), ctypes.POINTER(ci)]
+    L.sinc_middle_dry_run.argtypes = [i64, ci, i64, dbl, dbl, ci, ci, ci, ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_int32), i64, ctypes.POINTER(i64), ctypes.POINTER(ci)]
     dptr = ctypes.POINTER(ctypes.c_double)
     L.nnfft_quadrature.argtypes = [ci, i64, dptr, dptr]
     L.nnfft_profile_start.argtypes = [vp, ci]
@@ -180,7 +182,7 @@ def lib():
     for name in ["nfft_plan", "nfft_exec", "nfft_adjoint", "nfft_destroy", "nfft_plan_dry_run",
                  "nnfft_plan_dry_run", "nnfft_plan_window", "nnfft_plan_digest", "nnfft_plan_window_dry_run_digest", "nnfft_plan_window_dry_run", "nnfft_profile_start", "nnfft_profile_stop", "nnfft_profile_kernels", "nnfft_quadrature", "nnfft_derive_params",
                  "nnfft_plan", "nnfft_exec", "nnfft_exec_noalloc", "nnfft_exec_batch", "nnfft_info", "nnfft_destroy", "sinc_plan",
-                 "sinc_exec", "sinc_info", "sinc_sizes", "sinc_destroy", "sinc_middle", "nnfft_autotune", "nnfft_set_tuning",
+                 "sinc_exec", "sinc_info", "sinc_sizes", "sinc_destroy", "sinc_middle", "sinc_middle_dry_run", "nnfft_autotune", "nnfft_set_tuning",
                  "nnfft_get_tuning", "nnfft_clear_tuning", "nnfft_server_create", "nnfft_server_submit",
                  "nnfft_server_wait", "nnfft_server_poll", "nnfft_server_stats", "nnfft_server_evict",
                  "nnfft_server_destroy"]:
@@ -492,6 +494,21 @@ def sinc_exec(plan, c, h, stream=None):
 
 def sinc_destroy(plan):
     _check(lib().sinc_destroy(plan))
+
+
+def sinc_middle_dry_run(N, quad, n_quad, sigma1=2.0, sigma2=2.0, m1=6, m2=6, prec=NNFFT_FP64_PLAIN):
+    """Host-only middle operator of a sinc plan: (K [Wb, G1], lo [G1]) numpy arrays."""
+    import numpy as np
+    G1, Wb = ctypes.c_int64(), ctypes.c_int()
+    _check(lib().sinc_middle_dry_run(int(N), int(quad), int(n_quad), float(sigma1), float(sigma2), int(m1), int(m2),
+                                     int(prec), None, None, 0, ctypes.byref(G1), ctypes.byref(Wb)))
+    K = np.zeros((Wb.value, G1.value))
+    lo = np.zeros(G1.value, dtype=np.int32)
+    _check(lib().sinc_middle_dry_run(int(N), int(quad), int(n_quad), float(sigma1), float(sigma2), int(m1), int(m2),
+                                     int(prec), K.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                     lo.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), K.size,
+                                     ctypes.byref(G1), ctypes.byref(Wb)))
+    return K, lo
 
 
 def sinc_middle(plan, on=-1) -> dict:

@@ -2571,6 +2571,35 @@ nnfft_status sinc_middle(sinc_plan_t p, int on, int32_t *built, int32_t *active)
     return NNFFT_OK;
 }
 
+nnfft_status sinc_middle_dry_run(int64_t N, sinc_quad quad, int64_t n_quad, double sigma1, double sigma2, int m1,
+                                 int m2, nnfft_precision prec, double *K, int32_t *lo, int64_t cap, int64_t *G1,
+                                 int32_t *Wb)
+{
+    if (!G1 || !Wb) return fail(NNFFT_ERR_ARG, "null argument");
+    if (n_quad + (quad == SINC_QUAD_CLENSHAW_CURTIS ? 1 : 0) > kMidMaxNodes && n_quad <= ((int64_t)1 << 24) &&
+        (quad == SINC_QUAD_GAUSS_LEGENDRE || quad == SINC_QUAD_CLENSHAW_CURTIS))
+        return fail(NNFFT_ERR_UNSUPPORTED, "no middle operator for more than 2^16 quadrature nodes");
+    try {
+        // the operator does not depend on the nodes: one node on each side
+        const std::vector<double> a(1, 0.0), b(1, 0.0);
+        SincHostPlan S;
+        nnfft_status st = sinc_host(S, N, 1, 1, quad, n_quad, sigma1, sigma2, m1, m2, prec, a, b, true);
+        if (st != NNFFT_OK) return st;
+        if (!S.mid_ok) return fail(NNFFT_ERR_UNSUPPORTED, "no middle operator for these parameters");
+        const int64_t rows = (int64_t)S.mid.lo.size();
+        *G1 = rows;
+        *Wb = S.mid.Wb;
+        if (K || lo) {
+            if (!K || !lo || cap < rows * S.mid.Wb) return fail(NNFFT_ERR_ARG, "K / lo missing or too small");
+            std::copy(S.mid.K.begin(), S.mid.K.end(), K);
+            std::copy(S.mid.lo.begin(), S.mid.lo.end(), lo);
+        }
+        return NNFFT_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(NNFFT_ERR_NOMEM, "host allocation failed");
+    }
+}
+
 nnfft_status sinc_destroy(sinc_plan_t p)
 {
     if (!p) return fail(NNFFT_ERR_ARG, "null plan");
