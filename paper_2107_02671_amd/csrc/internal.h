@@ -156,8 +156,9 @@ struct PlanDev {
 // interpolation, the quadrature weights and the second plan's spreading as
 // one banded map from the first FFT's outputs to the second FFT's inputs):
 // row r (label r - G1/2) is out[r] = sum_{b < Wb} K[b][r] h_{lo[r] + b};
-// workgroup g (rows 256 g .. 256 g + 255) stages h at labels
+// workgroup g (rows kSincMidRows g ..) stages h at labels
 // [base[g], base[g] + span[g]) in LDS (labels with |s| > S read as zero).
+constexpr int kSincMidRows = 128;   // rows (= threads) per workgroup of the middle kernel
 struct SincMidArgs {
     InterpArgs h;             // the first plan's access to its FFT outputs
     const double *K;          // [Wb][G1]

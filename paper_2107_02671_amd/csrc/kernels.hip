@@ -1058,10 +1058,22 @@ __device__ __forceinline__ void merge_cell64(const FftArgs &A, int slot, double 
             }
         }
     }
-    for (int e = A.merge_off[slot]; e < e1; ++e) {
-        const double2 v = part[A.merge_idx[e]];
-        ar += v.x;
-        ai += v.y;
+    // overflow windows: eight entries at a time
+    const int e0 = A.merge_off[slot];
+    for (int e = e0; e < e1; e += 8) {
+        int idx[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) idx[q] = A.merge_idx[(e + q < e1) ? e + q : e0];
+        double2 v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = part[idx[q]];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            if (e + q < e1) {
+                ar += v[q].x;
+                ai += v[q].y;
+            }
+        }
     }
 }
 
@@ -1561,8 +1573,6 @@ __global__ __launch_bounds__(256) void k_fft_stageB(FftArgs A)
 // Fast sinc transform: the middle operator (Algorithm 6.1 steps 1-3 between
 // the two FFTs, composed on the host into the band K)
 // ===========================================================================
-constexpr int kMidThreads = 256;
-
 // h_s of the first plan, as its interpolation reads it
 template <typename T>
 __device__ __forceinline__ cx<T> plan_output(const InterpArgs &A, int s)
@@ -1570,25 +1580,41 @@ __device__ __forceinline__ cx<T> plan_output(const InterpArgs &A, int s)
     return A.fusedB ? folded_output<T>(A, s) : reinterpret_cast<const cx<T> *>(A.hlin)[s + A.h_off];
 }
 
-// One workgroup per 256 rows: the labels its rows read are staged in LDS
-// (FP64 accumulation of the band; K is read coalesced, [b][row]).
+// One workgroup per kSincMidRows rows: each thread's first kMidK band
+// coefficients are loaded first (coalesced over the rows, kept in
+// registers), then the labels the workgroup's rows read are staged in LDS;
+// the band is accumulated in FP64.
+constexpr int kMidK = 32;
 template <typename T>
-__global__ __launch_bounds__(kMidThreads) void k_sinc_mid(SincMidArgs A)
+__global__ __launch_bounds__(kSincMidRows) void k_sinc_mid(SincMidArgs A)
 {
     extern __shared__ __align__(16) char smem[];
     cx<T> *hw = reinterpret_cast<cx<T> *>(smem);
     const int g = blockIdx.x;
+    const int row = g * kSincMidRows + threadIdx.x;
+    const int rr = min(row, A.G1 - 1);   // rows past the end read a valid row and store nothing
+    double kr[kMidK];
+#pragma unroll
+    for (int b = 0; b < kMidK; ++b) kr[b] = A.K[(size_t)min(b, A.Wb - 1) * A.G1 + rr];
+    const int lo = A.lo[rr];
     const int base = A.base[g], span = A.span[g];
-    for (int i = threadIdx.x; i < span; i += kMidThreads) {
+    for (int i = threadIdx.x; i < span; i += kSincMidRows) {
         const int sl = base + i;
         hw[i] = (sl >= -A.S && sl <= A.S) ? plan_output<T>(A.h, sl) : cxmk((T)0, (T)0);
     }
     __syncthreads();
-    const int row = g * kMidThreads + threadIdx.x;
     if (row >= A.G1) return;
-    const cx<T> *hr = hw + (A.lo[row] - base);
+    const cx<T> *hr = hw + (lo - base);
     double re = 0.0, im = 0.0;
-    for (int b = 0; b < A.Wb; ++b) {
+#pragma unroll
+    for (int b = 0; b < kMidK; ++b) {
+        if (b < A.Wb) {
+            const cx<T> v = hr[b];
+            re = fma(kr[b], (double)v.re, re);
+            im = fma(kr[b], (double)v.im, im);
+        }
+    }
+    for (int b = kMidK; b < A.Wb; ++b) {   // bands wider than kMidK
         const double k = A.K[(size_t)b * A.G1 + row];
         const cx<T> v = hr[b];
         re = fma(k, (double)v.re, re);
@@ -1796,7 +1822,7 @@ hipError_t launch_sinc_middle(const PlanDev &P1, const SincMidArgs &M, const Pla
         launch_spread32(P1.sp, P1.sp.ngrid, reinterpret_cast<const cx<float> *>(c), s);
         launch_premerge<float>(P1.pm, s);
         launch_fft<float>(P1.fft, s);
-        hipLaunchKernelGGL(k_sinc_mid<float>, dim3(M.nwg), dim3(kMidThreads), (size_t)M.span_max * sizeof(cx<float>),
+        hipLaunchKernelGGL(k_sinc_mid<float>, dim3(M.nwg), dim3(kSincMidRows), (size_t)M.span_max * sizeof(cx<float>),
                            s, M);
         launch_fft<float>(F, s);
         launch_interp32(corr_variant(P2.ip.corr_deg), P2.ip.ngrid, s, P2.ip, reinterpret_cast<cx<float> *>(h));
@@ -1804,7 +1830,7 @@ hipError_t launch_sinc_middle(const PlanDev &P1, const SincMidArgs &M, const Pla
         launch_spread64(P1.sp, c, s, nullptr);
         launch_premerge<double>(P1.pm, s);
         launch_fft<double>(P1.fft, s);
-        hipLaunchKernelGGL(k_sinc_mid<double>, dim3(M.nwg), dim3(kMidThreads),
+        hipLaunchKernelGGL(k_sinc_mid<double>, dim3(M.nwg), dim3(kSincMidRows),
                            (size_t)M.span_max * sizeof(cx<double>), s, M);
         launch_fft<double>(F, s);
         launch_interp64(P2.ip, h, s, nullptr);

@@ -821,7 +821,8 @@ static int64_t slot_of(const HostPlan &H, int64_t cell)
     return (cell % H.slotT) * H.slotP + cell / H.slotT;
 }
 
-constexpr int32_t kMergeDirect = 8;   // longest merge list the FFT load walks itself
+constexpr int32_t kMergeDirect = 32;  // longest merge list the FFT load walks itself (rounds of 8 loads)
+constexpr int32_t kMergeSplit = 8;    // segments a longer list is cut into (one round of loads)
 
 static nnfft_status build_merge_lists(HostPlan &H, const nnfft_info_t &P, int m1)
 {
@@ -852,9 +853,11 @@ static nnfft_status build_merge_lists(HostPlan &H, const nnfft_info_t &P, int m1
         }
     }
     // lists longer than kMergeDirect entries: cut into segments of
-    // L = ceil(n / kMergeDirect) entries, each pre-merged into a partial cell
-    // of its own (after the existing ones), so every list the FFT load walks
-    // has at most kMergeDirect entries (one round of loads)
+    // L = ceil(n / kMergeSplit) entries, each pre-merged into a partial cell
+    // of its own (after the existing ones), so such a list becomes at most
+    // kMergeSplit entries (one round of loads in the FFT load).  Shorter
+    // lists are walked by the FFT load itself: up to four rounds cost less
+    // than the extra launch.
     H.pm_seg.clear();
     H.pm_idx.clear();
     H.pm_base = H.sp.part_cells;
@@ -869,7 +872,7 @@ static nnfft_status build_merge_lists(HostPlan &H, const nnfft_info_t &P, int m1
             if (n <= kMergeDirect) {
                 idx2.insert(idx2.end(), H.midx.begin() + e0, H.midx.begin() + e0 + n);
             } else {
-                const int32_t L = (n + kMergeDirect - 1) / kMergeDirect;
+                const int32_t L = (n + kMergeSplit - 1) / kMergeSplit;
                 for (int32_t s0 = 0; s0 < n; s0 += L) {
                     const int32_t cnt = std::min(L, n - s0);
                     H.pm_seg.push_back((int32_t)H.pm_idx.size());
@@ -1795,7 +1798,6 @@ nnfft_status copy_nodes(const double *d, int64_t n, std::vector<double> &h, hipS
 constexpr int64_t kMidMaxNodes = (int64_t)1 << 16;
 constexpr int kMidMaxBand = 256;
 constexpr int kMidMaxSpan = 4096;
-constexpr int kMidRows = 256;   // rows per workgroup of the middle kernel
 
 // The quadrature rules of recent plans (the Gauss-Legendre rule costs
 // O(n_quad^2) on the host), least recently used out.
@@ -1882,14 +1884,14 @@ static bool build_sinc_middle(SincHostPlan &S, const std::vector<double> &z)
         if (hi[r] >= lo[r]) Wb = std::max(Wb, hi[r] - lo[r] + 1);
     if (Wb > kMidMaxBand) return false;
     // workgroup windows; rows without entries read the start of theirs
-    const int64_t nwg = (G1 + kMidRows - 1) / kMidRows;
+    const int64_t nwg = (G1 + kSincMidRows - 1) / kSincMidRows;
     SincMiddle &Mi = S.mid;
     Mi.base.assign(nwg, 0);
     Mi.span.assign(nwg, 0);
     Mi.lo.assign(G1, 0);
     int64_t span_max = 1;
     for (int64_t g = 0; g < nwg; ++g) {
-        const int64_t r0 = g * kMidRows, r1 = std::min(G1, r0 + kMidRows);
+        const int64_t r0 = g * kSincMidRows, r1 = std::min(G1, r0 + kSincMidRows);
         int64_t b0 = INT64_MAX;
         for (int64_t r = r0; r < r1; ++r)
             if (hi[r] >= lo[r]) b0 = std::min(b0, lo[r]);

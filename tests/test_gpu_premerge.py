@@ -1,6 +1,6 @@
 """Crowded cells: node sets whose grid cells lie under more overflow windows
-than the FFT load merges itself (more than 8 beyond the 16 window planes) get
-their long merge lists pre-merged in segments (k_premerge) before the FFT.
+than the FFT load merges itself (more than 32 beyond the 16 window planes)
+get their long merge lists pre-merged in segments (k_premerge) before the FFT.
 
 Checked on node sets concentrated in a few tight clusters, where every
 cluster cell is covered by windows of every node block: the plan launches
@@ -9,7 +9,7 @@ NNFFT gates (and with the direct sum (1.2) on samples), a batched launch of
 such plans with uncrowded ones is bitwise equal to their single execs, and
 the allocation-free entry point equals nnfft_exec.  The layout invariants of
 the segments (each overflow partial cell merged exactly once, into its own
-grid cell, no list longer than 8) are checked by every plan's dry run.
+grid cell, no list longer than 32) are checked by every plan's dry run.
 """
 import sys
 
@@ -32,7 +32,7 @@ def _say(*a):
     sys.stdout.flush()
 
 
-def _crowded(g, M, nclusters=3, std=2e-4):
+def _crowded(g, M, nclusters=2, std=2e-4):
     return W.clustered_nodes(g, M, nclusters=nclusters, std=std)
 
 
