@@ -223,6 +223,31 @@ def test_sinc_middle_operator(prec, N, L1, L2, quad, nqf, s1, s2, m):
     assert e_mid <= t and e_two <= t and e_mt <= 2 * t
 
 
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_sinc_middle_wide_band_window(prec):
+    # N = 4096: the operator's workgroups of 128 rows each stage their own
+    # window of the first FFT's outputs (~8200 labels in all); against the
+    # oracle's Algorithm 6.1
+    N, L1, L2 = 4096, 12000, 9000
+    r = W.rng(733)
+    a = 0.5 * np.cos(np.pi * (np.arange(L1) + 0.5) / L1)
+    b = r.uniform(-0.5, 0.5, L2)
+    c = r.standard_normal(L1) + 1j * r.standard_normal(L1)
+    cdt = torch.complex64 if prec == FP32 else torch.complex128
+    _say(f"[gpu] sinc middle N={N} L=({L1},{L2}) prec={prec}")
+    sp = P.SincPlan(N, torch.tensor(a, device=DEV), torch.tensor(b, device=DEV), 2 * N, GL, 2.0, 2.0, 6, 6, prec)
+    try:
+        assert P.sinc_middle(sp.handle) == {"built": 1, "active": 1}
+        h = sp(torch.tensor(c, dtype=cdt, device=DEV))
+        torch.cuda.synchronize()
+        h = h.cpu().numpy().astype(np.complex128)
+    finally:
+        sp.close()
+    e = einf(h, oracle.sinc_fast(N, a, c, b, 2 * N, GL, 2.0, 2.0, 6, 6))
+    _say(f"    E_inf vs oracle {e:.3e}")
+    assert e <= tol(prec, 6)
+
+
 def test_sinc_middle_availability():
     # equispaced steps (NFFTs) have no middle operator; asking for it fails
     N = 1024
