@@ -126,6 +126,44 @@ double window_sinh_hat(double v, double beta)
     return pre * ::j1(z) / z;
 }
 
+// window_sinh_hat at n arguments, kLanes at a time: the nested I_1 series of
+// the lanes run side by side (each lane from its own last term, so every
+// value is bitwise the scalar one), which hides the latency of the series'
+// dependent chain.
+static void window_sinh_hat_many(const double *v, double *out, int64_t n, double beta)
+{
+    constexpr int kLanes = 8;
+    const double pre = kPi * beta / std::sinh(beta);
+    const double *r = inv_k_k1();
+    for (int64_t i0 = 0; i0 < n; i0 += kLanes) {
+        const int nl = (int)std::min<int64_t>(kLanes, n - i0);
+        double q[kLanes], acc[kLanes];
+        int K[kLanes], Kmax = 0;
+        bool series = true;
+        for (int l = 0; l < kLanes; ++l) {
+            const double vl = v[i0 + std::min(l, nl - 1)];
+            const double y = beta * beta - 4.0 * kPi * kPi * vl * vl;
+            series = series && y >= 0.0;
+            q[l] = 0.25 * y;
+            K[l] = std::min(kSeriesMax, 20 + (int)(2.0 * std::sqrt(std::max(q[l], 0.0))));
+            Kmax = std::max(Kmax, K[l]);
+            acc[l] = 1.0;
+        }
+        if (!series) {   // an argument past the series' range: one at a time
+            for (int l = 0; l < nl; ++l) out[i0 + l] = window_sinh_hat(v[i0 + l], beta);
+            continue;
+        }
+        for (int k = Kmax; k >= 1; --k) {
+            const double rk = r[k];
+            for (int l = 0; l < kLanes; ++l) {
+                const double nx = 1.0 + acc[l] * q[l] * rk;
+                acc[l] = k <= K[l] ? nx : acc[l];
+            }
+        }
+        for (int l = 0; l < nl; ++l) out[i0 + l] = pre * (0.5 * acc[l]);
+    }
+}
+
 // I_0(z) - 1 = sum_{k >= 1} q^k / (k!)^2, q = z^2 / 4, nested from the last
 // kept term down: q (1 + q/2^2 (1 + q/3^2 (1 + ...))).  The terms peak near
 // k = sqrt(q); past k = 30 + 3 sqrt(q) the tail is below 1e-18 of the sum.
@@ -150,10 +188,15 @@ std::vector<double> cheb_nodes(int deg)
 
 std::vector<double> cheb_fit(int deg, const std::vector<double> &f)
 {
+    // cos(pi k (j + 1/2) / (deg + 1)) depends on k (2j + 1) mod 4 (deg + 1)
+    // only: one table of 4 (deg + 1) cosines
+    const int P = 4 * (deg + 1);
+    std::vector<double> ct((size_t)P);
+    for (int e = 0; e < P; ++e) ct[(size_t)e] = std::cos(kPi * (0.5 * e) / (deg + 1));
     std::vector<double> c(deg + 1, 0.0);
     for (int k = 0; k <= deg; ++k) {
         double s = 0.0;
-        for (int j = 0; j <= deg; ++j) s += f[j] * std::cos(kPi * k * (j + 0.5) / (deg + 1));
+        for (int j = 0; j <= deg; ++j) s += f[j] * ct[(size_t)(((int64_t)k * (2 * j + 1)) % P)];
         c[k] = 2.0 * s / (deg + 1);
     }
     c[0] *= 0.5;
@@ -294,6 +337,15 @@ double window_hat(const Window &w, double v)
     }
 }
 
+void window_hat_many(const Window &w, const double *v, double *out, int64_t n)
+{
+    if (w.kind == NNFFT_WINDOW_SINH) {
+        window_sinh_hat_many(v, out, n, w.beta);
+        return;
+    }
+    for (int64_t i = 0; i < n; ++i) out[i] = window_hat(w, v[i]);
+}
+
 std::vector<double> fit_window_taps(const Window &w, int deg, double *max_err)
 {
     const int m = w.m;
@@ -308,10 +360,12 @@ std::vector<double> fit_window_taps(const Window &w, int deg, double *max_err)
         }
         std::vector<double> c = cheb_fit(deg, f);
         for (int k = 0; k <= deg; ++k) out[(size_t)r * (deg + 1) + k] = c[k];
-        for (int i = 0; i <= 500; ++i) {   // the error of a degree-8 fit has 9 lobes
-            const double x = i / 500.0;
-            const double e = std::fabs(cheb_eval(c.data(), deg, 2.0 * x - 1.0) -
-                                       window_value(w, (r - m + 1 - x) / m));
+        // the error of the interpolant has deg + 1 lobes, denser toward the
+        // ends: eight check points per lobe, uniform in the angle of t = 2x - 1
+        const int G = 8 * (deg + 1);
+        for (int i = 0; i <= G; ++i) {
+            const double t = std::cos(kPi * i / G), x = 0.5 * (t + 1.0);
+            const double e = std::fabs(cheb_eval(c.data(), deg, t) - window_value(w, (r - m + 1 - x) / m));
             worst = std::max(worst, e);
         }
     }
@@ -324,26 +378,34 @@ std::vector<double> fit_inverse_phi1(const nnfft_info_t &P, double tol, int max_
 {
     // phi_hat_1(N* x) = (m1/N1) omega_hat_1(m1 N* x / N1)
     const Window w1 = make_window(P.window, P.m1, P.beta1);
-    auto inv = [&](double x) {
-        const double v = (double)P.m1 * (double)P.N_star * x / (double)P.N1;
-        return 1.0 / ((double)P.m1 / (double)P.N1 * window_hat(w1, v));
+    // 1 / phi_hat_1(N* x) at the points x[0..n)
+    auto inv_many = [&](const std::vector<double> &x, std::vector<double> &out) {
+        std::vector<double> v(x.size());
+        for (size_t i = 0; i < x.size(); ++i) v[i] = (double)P.m1 * (double)P.N_star * x[i] / (double)P.N1;
+        out.resize(x.size());
+        window_hat_many(w1, v.data(), out.data(), (int64_t)v.size());
+        for (double &o : out) o = 1.0 / ((double)P.m1 / (double)P.N1 * o);
     };
-    // reference values on the check grid, shared by every degree tried
-    constexpr int kGrid = 1000;
-    std::vector<double> ref(kGrid + 1);
-    for (int i = 0; i <= kGrid; ++i) ref[i] = inv(0.5 * i / kGrid);
+    // reference values on the check grid, shared by every degree tried:
+    // uniform in the angle of t = 8 x^2 - 1 (dense toward both ends, where
+    // the error of a Chebyshev interpolant peaks)
+    constexpr int kGrid = 400;
+    std::vector<double> tg(kGrid + 1), xg(kGrid + 1), ref;
+    for (int i = 0; i <= kGrid; ++i) {
+        tg[i] = std::cos(kPi * i / kGrid);
+        xg[i] = std::sqrt(std::max(0.0, (tg[i] + 1.0) / 8.0));
+    }
+    inv_many(xg, ref);
     std::vector<double> best;
     double best_err = 1e300;
     for (int deg = 4; deg <= max_deg; deg += 2) {
         const std::vector<double> tn = cheb_nodes(deg);
-        std::vector<double> f(deg + 1);
-        for (int j = 0; j <= deg; ++j) f[j] = inv(std::sqrt((tn[j] + 1.0) / 8.0));
+        std::vector<double> xn(deg + 1), f;
+        for (int j = 0; j <= deg; ++j) xn[j] = std::sqrt((tn[j] + 1.0) / 8.0);
+        inv_many(xn, f);
         std::vector<double> c = cheb_fit(deg, f);
         double err = 0.0;
-        for (int i = 0; i <= kGrid; ++i) {
-            const double x = 0.5 * i / kGrid;
-            err = std::max(err, std::fabs(cheb_eval(c.data(), deg, 8.0 * x * x - 1.0) / ref[i] - 1.0));
-        }
+        for (int i = 0; i <= kGrid; ++i) err = std::max(err, std::fabs(cheb_eval(c.data(), deg, tg[i]) / ref[i] - 1.0));
         if (err < best_err) {
             best_err = err;
             best = c;

@@ -39,6 +39,9 @@ Window make_window(int kind, int m, double beta);
 double window_value(const Window &w, double u);
 // Its Fourier transform for |v| <= m/2 (the algorithm needs |v| <= m/(2 sigma)).
 double window_hat(const Window &w, double v);
+// window_hat at v[0..n) into out[0..n), each value bitwise the scalar one
+// (sinh windows: several series evaluated side by side).
+void window_hat_many(const Window &w, const double *v, double *out, int64_t n);
 
 // Continuous Kaiser-Bessel window as a power series in s = 1 - u^2:
 // omega(u) = sum_{k >= 1} t_k s^k, t_k = (beta^2/4)^k / ((k!)^2 (I_0(beta) - 1));

@@ -1035,6 +1035,79 @@ static nnfft_status plan_params(HostPlan &H, int64_t N, int64_t M1, int64_t M2, 
     return NNFFT_OK;
 }
 
+// Tap series of a window: they depend on its family, m, beta and the degree
+// only, so plans of every bandwidth share them (a short list, most recently
+// used first).
+struct TapSeries {
+    int kind, m, deg;
+    double beta;
+    std::vector<double> c;
+    double err;
+};
+constexpr size_t kTapCacheEntries = 32;
+std::mutex g_taps_mu;
+std::list<std::shared_ptr<const TapSeries>> g_taps;
+
+static std::vector<double> window_taps_cached(const Window &w, int deg, double *max_err)
+{
+    {
+        std::lock_guard<std::mutex> g(g_taps_mu);
+        for (auto it = g_taps.begin(); it != g_taps.end(); ++it) {
+            const TapSeries &t = **it;
+            if (t.kind == w.kind && t.m == w.m && t.deg == deg && t.beta == w.beta) {
+                *max_err = t.err;
+                std::vector<double> c = t.c;
+                g_taps.splice(g_taps.begin(), g_taps, it);
+                return c;
+            }
+        }
+    }
+    auto t = std::make_shared<TapSeries>();
+    t->kind = w.kind;
+    t->m = w.m;
+    t->deg = deg;
+    t->beta = w.beta;
+    t->c = fit_window_taps(w, deg, &t->err);
+    *max_err = t->err;
+    std::lock_guard<std::mutex> g(g_taps_mu);
+    g_taps.push_front(t);
+    if (g_taps.size() > kTapCacheEntries) g_taps.pop_back();
+    return t->c;
+}
+
+// Twiddles exp(-2 pi i q / n) of an FFT length (shared by every plan of that
+// length; a short list, most recently used first, bounded in entries and bytes).
+constexpr size_t kTwCacheEntries = 128;
+constexpr size_t kTwCacheBytes = (size_t)64 << 20;
+std::mutex g_tw_mu;
+std::list<std::pair<int64_t, std::shared_ptr<const std::vector<double>>>> g_tw;
+size_t g_tw_bytes = 0;
+
+static std::vector<double> twiddles_cached(int64_t n)
+{
+    {
+        std::lock_guard<std::mutex> g(g_tw_mu);
+        for (auto it = g_tw.begin(); it != g_tw.end(); ++it)
+            if (it->first == n) {
+                std::vector<double> t = *it->second;
+                g_tw.splice(g_tw.begin(), g_tw, it);
+                return t;
+            }
+    }
+    auto t = std::make_shared<const std::vector<double>>(twiddles(n));
+    const size_t bytes = t->size() * sizeof(double);
+    if (bytes <= kTwCacheBytes / 8) {
+        std::lock_guard<std::mutex> g(g_tw_mu);
+        g_tw.emplace_front(n, t);
+        g_tw_bytes += bytes;
+        while (g_tw.size() > kTwCacheEntries || g_tw_bytes > kTwCacheBytes) {
+            g_tw_bytes -= g_tw.back().second->size() * sizeof(double);
+            g_tw.pop_back();
+        }
+    }
+    return *t;
+}
+
 // The FP64 tables of a plan whose parameters plan_params set: window tap
 // series, the 1/phi_hat_1 series, the phi_hat_2 deconvolution and the
 // twiddles.  They depend on (N, sigma, m, precision, window) only and are
@@ -1048,8 +1121,8 @@ static nnfft_status plan_tables_compute(HostPlan &H)
     // tables in FP64 -----------------------------------------------------
     double e1 = 0.0, e2 = 0.0;
     if (fp32) {
-        const std::vector<double> c1 = fit_window_taps(make_window(P.window, m1, P.beta1), kDeg, &e1);
-        const std::vector<double> c2 = fit_window_taps(make_window(P.window, m2, P.beta2), kDeg, &e2);
+        const std::vector<double> c1 = window_taps_cached(make_window(P.window, m1, P.beta1), kDeg, &e1);
+        const std::vector<double> c2 = window_taps_cached(make_window(P.window, m2, P.beta2), kDeg, &e2);
         P.window_degree = kDeg;
         P.window_fit_err = std::max(e1, e2);
         if (e1 > tap_fit_tolerance(m1, P.sigma1_eff) || e2 > tap_fit_tolerance(m2, P.sigma2_eff))
@@ -1059,8 +1132,8 @@ static nnfft_status plan_tables_compute(HostPlan &H)
     } else if (window == NNFFT_WINDOW_BSPLINE) {
         // each tap is one polynomial piece of degree 2m - 1: its series is exact
         double t1 = 0.0, t2 = 0.0;
-        H.T1 = fit_window_taps(make_window(window, m1, 0.0), 2 * m1 - 1, &t1);
-        H.T2 = fit_window_taps(make_window(window, m2, 0.0), 2 * m2 - 1, &t2);
+        H.T1 = window_taps_cached(make_window(window, m1, 0.0), 2 * m1 - 1, &t1);
+        H.T2 = window_taps_cached(make_window(window, m2, 0.0), 2 * m2 - 1, &t2);
         if (std::max(t1, t2) > 1e-14)
             return fail(NNFFT_ERR_UNSUPPORTED, "B-spline tap series inexact");
     } else if (window == NNFFT_WINDOW_KAISER_BESSEL) {
@@ -1078,14 +1151,16 @@ static nnfft_status plan_tables_compute(HostPlan &H)
 
     const Window w2 = make_window(P.window, m2, P.beta2);
     H.deconv.resize(P.G1);
+    std::vector<double> hv((size_t)(P.G1 / 2 + 1)), ha(hv.size());
+    for (int64_t c = 0; c <= P.G1 / 2; ++c) hv[(size_t)c] = m2 * (double)(P.G1 / 2 - c) / (double)P.N2;
+    window_hat_many(w2, hv.data(), ha.data(), (int64_t)hv.size());
     for (int64_t c = 0; c <= P.G1 / 2; ++c) {   // phi_hat_2 is even: label -l shares the value of l
-        const double l = (double)(P.G1 / 2 - c);
-        const double phi2 = (double)m2 / (double)P.N2 * window_hat(w2, m2 * l / (double)P.N2);
+        const double phi2 = (double)m2 / (double)P.N2 * ha[(size_t)c];
         const double d = 1.0 / ((double)P.N1 * (double)P.N2 * phi2);
         H.deconv[c] = d;                                  // label -l
         if (c > 0 && P.G1 / 2 + (P.G1 / 2 - c) < P.G1) H.deconv[P.G1 / 2 + (P.G1 / 2 - c)] = d;   // label +l
     }
-    H.tw64 = twiddles(P.N2);
+    H.tw64 = twiddles_cached(P.N2);
     if (fp32) {
         H.tw32.assign(H.tw64.begin(), H.tw64.end());
         H.tw64.clear();
@@ -1288,7 +1363,7 @@ nnfft_status nfft_plan_host(HostPlan &H, int64_t N, int64_t M, double sigma, int
     H.fp32 = fp32;
     if (fp32) {
         double e = 0.0;
-        const std::vector<double> c = fit_window_taps(make_window(NNFFT_WINDOW_SINH, m, P.beta1), kDeg, &e);
+        const std::vector<double> c = window_taps_cached(make_window(NNFFT_WINDOW_SINH, m, P.beta1), kDeg, &e);
         P.window_degree = kDeg;
         P.window_fit_err = e;
         if (e > tap_fit_tolerance(m, P.sigma1_eff))
