@@ -385,6 +385,9 @@ def served_benchmark(P, W, torch, n_req, planners=12, budget=16 << 30):
         srv.close()
         sub_ms = np.array([res["submit_ms"] for res in results])
         done_ms = np.array([res["done_ms"] for res in results])
+        built = [res for res in results if res["status"] == 0 and not res["plan_reused"]]
+        plan_ms = np.array([res["admit_ms"] - res["plan_ms"] for res in built]) if built else np.zeros(1)
+        queue_ms = np.array([res["plan_ms"] - res["submit_ms"] for res in results])
         # server clock (ms since its creation, steady clock) -> perf_counter
         # seconds (both CLOCK_MONOTONIC): the submit stamp is taken inside the
         # submit call, after t_sub, so every t_sub - submit stamp is at most
@@ -400,6 +403,10 @@ def served_benchmark(P, W, torch, n_req, planners=12, budget=16 << 30):
                 "latency_from": "submit" if rate is None else "scheduled arrival",
                 "server_p50_ms": pct(done_ms - sub_ms, 50), "server_p99_ms": pct(done_ms - sub_ms, 99),
                 "generator_lag_ms": {"p50": pct(lag, 50), "p99": pct(lag, 99), "max": float(lag.max())},
+                "planning_ms": {"mean": float(plan_ms.mean()), "p50": pct(plan_ms, 50), "p99": pct(plan_ms, 99),
+                                "kind": "planner took the request up -> plan admitted into the arena"},
+                "queue_ms": {"p50": pct(queue_ms, 50), "p99": pct(queue_ms, 99),
+                             "kind": "submitted -> a planner took it up"},
                 "mean_group": float(np.mean([res["group_size"] for res in results])),
                 "admission_waits": st["admission_waits"], "arena_peak_bytes": st["arena_peak"]}
 

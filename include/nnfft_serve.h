@@ -72,6 +72,7 @@ typedef struct {
     int32_t plan_reused;      /* 1 if a resident plan served it                          */
     int32_t reserved;
     double submit_ms;         /* server clock (ms since creation): submitted             */
+    double plan_ms;           /* a planner thread took it up                             */
     double admit_ms;          /* plan built and admitted into the arena                  */
     double launch_ms;         /* launch group issued                                     */
     double done_ms;           /* completion observed                                     */

@@ -82,7 +82,8 @@ class NnfftRequest(ctypes.Structure):
 class NnfftResult(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("group_size", ctypes.c_int32),
                 ("footprint_bytes", ctypes.c_int64), ("plan_reused", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("submit_ms", ctypes.c_double), ("admit_ms", ctypes.c_double),
+                ("reserved", ctypes.c_int32), ("submit_ms", ctypes.c_double), ("plan_ms", ctypes.c_double),
+                ("admit_ms", ctypes.c_double),
                 ("launch_ms", ctypes.c_double), ("done_ms", ctypes.c_double), ("message", ctypes.c_char * 160)]
 
     def as_dict(self):

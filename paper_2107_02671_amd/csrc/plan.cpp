@@ -159,14 +159,29 @@ Layout raise_item_size(Layout L, int64_t M, double scale, bool fp32, const doubl
         const int64_t S = std::min<int64_t>(len, 4096);
         if (S < 2) continue;
         cell.resize((size_t)S);
-        for (int64_t i = 0; i < S; ++i) cell[(size_t)i] = (int64_t)std::floor(scale * vals[at++]);
-        std::sort(cell.begin(), cell.end());
+        int64_t cmin = INT64_MAX, cmax = INT64_MIN;
+        for (int64_t i = 0; i < S; ++i) {
+            const int64_t c = (int64_t)std::floor(scale * vals[at++]);
+            cell[(size_t)i] = c;
+            cmin = std::min(cmin, c);
+            cmax = std::max(cmax, c);
+        }
+        // sum over the sampled cells of (samples in the cell)^2: counted in
+        // an array over the cells' range (a sort where that range is wide);
+        // the terms are integers, so the order of the sum does not matter
         double sumsq = 0.0;
-        for (int64_t i = 0; i < S;) {
-            int64_t j = i;
-            while (j < S && cell[(size_t)j] == cell[(size_t)i]) ++j;
-            sumsq += (double)(j - i) * (double)(j - i);
-            i = j;
+        if (cmax - cmin < ((int64_t)1 << 20)) {
+            std::vector<int32_t> cnt((size_t)(cmax - cmin + 1), 0);
+            for (int64_t i = 0; i < S; ++i) ++cnt[(size_t)(cell[(size_t)i] - cmin)];
+            for (const int32_t c : cnt) sumsq += (double)c * (double)c;
+        } else {
+            std::sort(cell.begin(), cell.end());
+            for (int64_t i = 0; i < S;) {
+                int64_t j = i;
+                while (j < S && cell[(size_t)j] == cell[(size_t)i]) ++j;
+                sumsq += (double)(j - i) * (double)(j - i);
+                i = j;
+            }
         }
         load += (double)len * (sumsq - (double)S) / ((double)S * (double)(S - 1));
         ++used;

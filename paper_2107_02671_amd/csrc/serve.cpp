@@ -254,6 +254,7 @@ void nnfft_server_s::planner_loop()
         Req *q = pending.front();
         pending.pop_front();
         const nnfft_request_t r = q->r;
+        q->out.plan_ms = now_ms();
 
         // keyed request whose plan is resident (or being built): reuse it
         if (r.plan_key != 0) {

@@ -108,7 +108,7 @@ def test_server_mix_equals_alone():
     assert max(r["group_size"] for r in res) >= 1
     for i, (r, (_, y)) in enumerate(zip(reqs, sub)):
         assert torch.equal(y, _alone(r)), f"request {i} differs from its plan run alone"
-        assert res[i]["submit_ms"] <= res[i]["admit_ms"] <= res[i]["launch_ms"] <= res[i]["done_ms"]
+        assert res[i]["submit_ms"] <= res[i]["plan_ms"] <= res[i]["admit_ms"] <= res[i]["launch_ms"] <= res[i]["done_ms"]
     # parity with the oracle for one request of each kind and precision
     seen = set()
     for r, (_, y) in zip(reqs, sub):
