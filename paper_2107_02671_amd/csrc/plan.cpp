@@ -456,15 +456,20 @@ bool finish_side(std::vector<BlockOut> &outs, int m, SideHost &S, std::string &e
     const Chunk empty{0, 0, 0, 0};
     const Item pad_item{0, 0, 0, 0};
     S.launch.assign(order.size(), empty);
-    S.launch_items.assign(order.size() * kItemsPerWg, pad_item);
+    S.launch_items.resize(order.size() * kItemsPerWg);   // every entry written below
     for (size_t g = 0; g < order.size(); ++g) {
-        if (order[g] < 0) continue;
-        const Chunk c = S.chunks[order[g]];
-        const Item *src = outs[(size_t)S.chunk_block[order[g]]].items.data() + S.chunk_item0[order[g]];
-        std::copy(src, src + c.nitem, S.launch_items.begin() + (ptrdiff_t)(g * kItemsPerWg));
-        S.launch[g] = c;
+        Item *dst = S.launch_items.data() + g * kItemsPerWg;
+        int nitem = 0;
+        if (order[g] >= 0) {
+            const Chunk c = S.chunks[order[g]];
+            const Item *src = outs[(size_t)S.chunk_block[order[g]]].items.data() + S.chunk_item0[order[g]];
+            std::copy(src, src + c.nitem, dst);
+            S.launch[g] = c;
+            nitem = c.nitem;
+        }
+        std::fill(dst + nitem, dst + kItemsPerWg, pad_item);
     }
-    for (BlockOut &o : outs) std::vector<Item>().swap(o.items);
+    for (BlockOut &o : outs) ItemBuf().swap(o.items);
     return true;
 }
 
@@ -650,8 +655,8 @@ struct Carver {
     size_t off = 0;
     std::vector<char> *stage;   // host image of the uploaded part (null: sizing pass)
     explicit Carver(uintptr_t b, std::vector<char> *st) : base(b), stage(st) {}
-    template <typename T>
-    T *put(const std::vector<T> &v)
+    template <typename T, typename A>
+    T *put(const std::vector<T, A> &v)
     {
         off = (off + 255) & ~(size_t)255;
         const size_t nb = std::max<size_t>(1, v.size()) * sizeof(T);
@@ -997,6 +1002,7 @@ static void size_plan(HostPlan &H, const nnfft_info_t &P)
     H.info = P;
     layout_plan(H, C, D, &upload_end, &dd);
     H.total_bytes = C.off;
+    H.upload_bytes = upload_end;
     H.info.device_bytes = (int64_t)C.off;
     H.info.block_points = H.lay1.block;
     H.info.items_points = H.lay1.Q;
@@ -1610,6 +1616,7 @@ nnfft_status plan_create(const HostPlan &H, const DevMem &mem, hipStream_t s, nn
     }
     try {
         std::vector<char> stage;
+        stage.reserve(H.upload_bytes);   // the image grows to this size (no reallocation)
         Carver C((uintptr_t)base, &stage);
         size_t upload_end = 0, dev_start = 0;
         layout_plan(H, C, pl->desc, &upload_end, &pl->ddesc, &dev_start);

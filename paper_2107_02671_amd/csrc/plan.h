@@ -5,7 +5,10 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <memory>
 #include <string>
+#include <type_traits>
+#include <utility>
 #include <vector>
 
 #include "../../include/nnfft.h"
@@ -41,6 +44,30 @@ void clear_tuned_layouts();
 // Clamps a requested layout to what the kernels implement.
 Layout sanitize_layout(Layout L, int64_t M, bool fp32);
 
+// An allocator whose resize leaves new elements default-initialized (no
+// zeroing), for buffers of trivial types the planner writes in full.
+template <typename T>
+struct UninitAlloc : std::allocator<T> {
+    template <typename U>
+    struct rebind {
+        using other = UninitAlloc<U>;
+    };
+    UninitAlloc() = default;
+    template <typename U>
+    UninitAlloc(const UninitAlloc<U> &) noexcept {}
+    template <typename U>
+    void construct(U *p) noexcept(std::is_nothrow_default_constructible<U>::value)
+    {
+        ::new (static_cast<void *>(p)) U;
+    }
+    template <typename U, typename... Args>
+    void construct(U *p, Args &&...args)
+    {
+        ::new (static_cast<void *>(p)) U(std::forward<Args>(args)...);
+    }
+};
+using ItemBuf = std::vector<Item, UninitAlloc<Item>>;
+
 // Node layout of one side, built on the host.
 struct SideHost {
     std::vector<int32_t> perm;          // FP64: caller's index of each sorted point
@@ -50,7 +77,7 @@ struct SideHost {
     std::vector<int32_t> chunk_block;
     std::vector<int32_t> chunk_item0;   // first item of each chunk in its block's items
     std::vector<Chunk> launch;          // chunks in launch order, empty ones pad
-    std::vector<Item> launch_items;     // 64 items per launch slot, n = 0 pads
+    ItemBuf launch_items;               // 64 items per launch slot, n = 0 pads
     std::vector<PtRec> trec32;          // FP32: records in per-slot transposed blocks
     int64_t part_cells = 0;             // spreading side: plane cells + overflow cells
     int64_t ovf_cells = 0;              // spreading side: cells of the overflow windows
@@ -63,7 +90,7 @@ struct SideHost {
 
 // Items and chunks of one node block (host schedule of a side).
 struct BlockOut {
-    std::vector<Item> items;
+    ItemBuf items;
     std::vector<Chunk> chunks;
     std::vector<int32_t> item0;   // first item of each chunk, within the block
     bool ok = true;
@@ -103,6 +130,7 @@ struct HostPlan {
     int64_t hlin_len = 0;              // FFT outputs kept for the interpolation
     int32_t h_off = 0;                 // their index of label 0
     size_t total_bytes = 0;            // device bytes of the plan (one block)
+    size_t upload_bytes = 0;           // of which uploaded from the host image
 };
 
 // Provider of the plan's device block.
