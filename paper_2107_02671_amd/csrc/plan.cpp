@@ -1654,9 +1654,11 @@ nnfft_status plan_create(const HostPlan &H, const DevMem &mem, hipStream_t s, nn
         hip_check(hipMemsetAsync(pl->desc.sp.partial, 0, (size_t)H.sp.part_cells * 16, s), "hipMemsetAsync");
         hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
     } catch (const HipError &e) {
+        (void)hipStreamSynchronize(s);   // nothing queued may still write into the released block
         delete pl;
         return fail(NNFFT_ERR_DEVICE, std::string(e.what) + ": " + hipGetErrorString(e.err));
     } catch (const std::bad_alloc &) {
+        (void)hipStreamSynchronize(s);
         delete pl;
         return fail(NNFFT_ERR_NOMEM, "host allocation failed");
     }
