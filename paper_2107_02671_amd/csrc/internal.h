@@ -223,6 +223,21 @@ bool device_sort_fits(int64_t M, int64_t nbins, int64_t block);
 size_t device_sort_tmp_bytes(int64_t M);
 hipError_t device_sort_nodes(const double *x, int64_t M, double scale, int64_t off, int64_t nbins, int64_t block,
                              int32_t *counts, int32_t *flag, void *tmp, int32_t **sorted_idx, hipStream_t s);
+// Both sides of a plan in one sort: side i's keys get i as the bit above the
+// wider side's key bits, so the sorted order is side 0's (by its keys), then
+// side 1's; the indices of each side count from 0 (*sorted_b = *sorted_a +
+// a.M).  tmp: device_sort_tmp_bytes(a.M + b.M) bytes; counts and flag per
+// side as for device_sort_nodes.
+struct SortSide {
+    const double *x;
+    int64_t M;
+    double scale;
+    int64_t off, nbins, block;
+    int32_t *counts, *flag;
+};
+bool device_sort_pair_fits(const SortSide &a, const SortSide &b);
+hipError_t device_sort_node_pair(const SortSide &a, const SortSide &b, void *tmp, int32_t **sorted_a,
+                                 int32_t **sorted_b, hipStream_t s);
 // The records of the sorted points: FP64 caller index and cell offset, or
 // FP32 (index, offset) records in sorted order.
 hipError_t device_sorted_records(const double *x, const int32_t *sorted_idx, int64_t M, double scale, bool fp32,

@@ -1791,7 +1791,6 @@ nnfft_status plan_device_nodes(HostPlan &H, DevRecords &R, NodePrepScratch &T, i
     sd[1].spreading = false;
     sd[1].m = 0;
     sd[1].what = "spatial";
-    size_t dev_need = 0, pin_need = 0;
     for (DevSide &d : sd) {
         d.L = choose_layout(d.M, fp32, d.spreading);
         if (!device_sort_fits(d.M, d.nbins, d.L.block) || !(std::fabs(d.scale) <= (double)((int64_t)1 << 26))) {
@@ -1803,40 +1802,103 @@ nnfft_status plan_device_nodes(HostPlan &H, DevRecords &R, NodePrepScratch &T, i
         d.sort_b = al256(device_sort_tmp_bytes(d.M));
         d.cnt_b = al256((size_t)d.nblocks * (size_t)d.nbins * 4);
         d.smp_b = al256(std::max<size_t>(1, d.sidx.size()) * 8);
-        dev_need += d.sort_b + d.cnt_b + 256 + 2 * d.smp_b;
-        pin_need += d.cnt_b + 256 + 2 * d.smp_b;
     }
-    if (!T.reserve(dev_need, pin_need))
-        return fail(NNFFT_ERR_NOMEM, "memory for the node preparation is not available");
-    unsigned char *pd = static_cast<unsigned char *>(T.dev), *ph = static_cast<unsigned char *>(T.pin);
-    for (DevSide &d : sd) {
-        d.sort_tmp = pd;
-        d.counts = reinterpret_cast<int32_t *>(pd + d.sort_b);
-        d.flag = reinterpret_cast<int32_t *>(pd + d.sort_b + d.cnt_b);
-        d.sidx_dev = reinterpret_cast<int64_t *>(pd + d.sort_b + d.cnt_b + 256);
-        d.svals_dev = reinterpret_cast<double *>(pd + d.sort_b + d.cnt_b + 256 + d.smp_b);
-        pd += d.sort_b + d.cnt_b + 256 + 2 * d.smp_b;
-        d.counts_h = reinterpret_cast<int32_t *>(ph);
-        d.flag_h = reinterpret_cast<int32_t *>(ph + d.cnt_b);
-        d.sidx_h = reinterpret_cast<int64_t *>(ph + d.cnt_b + 256);
-        d.svals_h = reinterpret_cast<double *>(ph + d.cnt_b + 256 + d.smp_b);
-        ph += d.cnt_b + 256 + 2 * d.smp_b;
-        std::copy(d.sidx.begin(), d.sidx.end(), d.sidx_h);
+    auto sort_side = [&](DevSide &d) {
+        return SortSide{d.x, d.M, d.scale, d.off, d.nbins, d.L.block, d.counts, d.flag};
+    };
+    // both sides in one sort where their keys fit 31 bits: one set of
+    // launches and one read-back each for the counts and the samples.
+    // Device: [sort scratch][counts 0][counts 1][flags][samples 0][samples 1]
+    // [values 0][values 1]; pinned: the same from the counts on.
+    const bool pair = device_sort_pair_fits(sort_side(sd[0]), sort_side(sd[1]));
+    size_t dev_need = 0, pin_need = 0;
+    if (pair) {
+        const size_t tmp_b = al256(device_sort_tmp_bytes(sd[0].M + sd[1].M));
+        pin_need = sd[0].cnt_b + sd[1].cnt_b + 256 + 2 * (sd[0].smp_b + sd[1].smp_b);
+        dev_need = tmp_b + pin_need;
+        if (!T.reserve(dev_need, pin_need))
+            return fail(NNFFT_ERR_NOMEM, "memory for the node preparation is not available");
+        unsigned char *pd = static_cast<unsigned char *>(T.dev), *ph = static_cast<unsigned char *>(T.pin);
+        size_t o = 0;
+        for (DevSide &d : sd) {
+            d.sort_tmp = pd;   // shared; each side's records use it in turn (plan_create)
+            d.counts = reinterpret_cast<int32_t *>(pd + tmp_b + o);
+            d.counts_h = reinterpret_cast<int32_t *>(ph + o);
+            o += d.cnt_b;
+        }
+        for (int i = 0; i < 2; ++i) {
+            sd[i].flag = reinterpret_cast<int32_t *>(pd + tmp_b + o) + i;
+            sd[i].flag_h = reinterpret_cast<int32_t *>(ph + o) + i;
+        }
+        o += 256;
+        for (DevSide &d : sd) {
+            d.sidx_dev = reinterpret_cast<int64_t *>(pd + tmp_b + o);
+            d.sidx_h = reinterpret_cast<int64_t *>(ph + o);
+            o += d.smp_b;
+        }
+        for (DevSide &d : sd) {
+            d.svals_dev = reinterpret_cast<double *>(pd + tmp_b + o);
+            d.svals_h = reinterpret_cast<double *>(ph + o);
+            o += d.smp_b;
+        }
+        for (DevSide &d : sd) std::copy(d.sidx.begin(), d.sidx.end(), d.sidx_h);
+    } else {
+        for (DevSide &d : sd) {
+            dev_need += d.sort_b + d.cnt_b + 256 + 2 * d.smp_b;
+            pin_need += d.cnt_b + 256 + 2 * d.smp_b;
+        }
+        if (!T.reserve(dev_need, pin_need))
+            return fail(NNFFT_ERR_NOMEM, "memory for the node preparation is not available");
+        unsigned char *pd = static_cast<unsigned char *>(T.dev), *ph = static_cast<unsigned char *>(T.pin);
+        for (DevSide &d : sd) {
+            d.sort_tmp = pd;
+            d.counts = reinterpret_cast<int32_t *>(pd + d.sort_b);
+            d.flag = reinterpret_cast<int32_t *>(pd + d.sort_b + d.cnt_b);
+            d.sidx_dev = reinterpret_cast<int64_t *>(pd + d.sort_b + d.cnt_b + 256);
+            d.svals_dev = reinterpret_cast<double *>(pd + d.sort_b + d.cnt_b + 256 + d.smp_b);
+            pd += d.sort_b + d.cnt_b + 256 + 2 * d.smp_b;
+            d.counts_h = reinterpret_cast<int32_t *>(ph);
+            d.flag_h = reinterpret_cast<int32_t *>(ph + d.cnt_b);
+            d.sidx_h = reinterpret_cast<int64_t *>(ph + d.cnt_b + 256);
+            d.svals_h = reinterpret_cast<double *>(ph + d.cnt_b + 256 + d.smp_b);
+            ph += d.cnt_b + 256 + 2 * d.smp_b;
+            std::copy(d.sidx.begin(), d.sidx.end(), d.sidx_h);
+        }
     }
     // device work of both sides, then the tables on the host meanwhile
-    for (DevSide &d : sd) {
-        hip_check(hipMemsetAsync(d.counts, 0, d.cnt_b + 256, s), "hipMemsetAsync");
-        hip_check(device_sort_nodes(d.x, d.M, d.scale, d.off, d.nbins, d.L.block, d.counts, d.flag, d.sort_tmp,
-                                    &d.sorted, s),
+    if (pair) {
+        const size_t cnt_all = sd[0].cnt_b + sd[1].cnt_b + 256, smp_all = sd[0].smp_b + sd[1].smp_b;
+        hip_check(hipMemsetAsync(sd[0].counts, 0, cnt_all, s), "hipMemsetAsync");
+        hip_check(device_sort_node_pair(sort_side(sd[0]), sort_side(sd[1]), sd[0].sort_tmp, &sd[0].sorted,
+                                        &sd[1].sorted, s),
                   "node sort");
-        if (!d.sidx.empty()) {
-            hip_check(hipMemcpyAsync(d.sidx_dev, d.sidx_h, d.sidx.size() * 8, hipMemcpyHostToDevice, s),
+        if (!sd[0].sidx.empty() || !sd[1].sidx.empty()) {
+            hip_check(hipMemcpyAsync(sd[0].sidx_dev, sd[0].sidx_h, smp_all, hipMemcpyHostToDevice, s),
                       "hipMemcpyAsync");
-            hip_check(device_gather(d.x, d.sidx_dev, (int64_t)d.sidx.size(), d.svals_dev, s), "density samples");
-            hip_check(hipMemcpyAsync(d.svals_h, d.svals_dev, d.sidx.size() * 8, hipMemcpyDeviceToHost, s),
+            for (DevSide &d : sd)
+                if (!d.sidx.empty())
+                    hip_check(device_gather(d.x, d.sidx_dev, (int64_t)d.sidx.size(), d.svals_dev, s),
+                              "density samples");
+            hip_check(hipMemcpyAsync(sd[0].svals_h, sd[0].svals_dev, smp_all, hipMemcpyDeviceToHost, s),
                       "hipMemcpyAsync");
         }
-        hip_check(hipMemcpyAsync(d.counts_h, d.counts, d.cnt_b + 256, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+        hip_check(hipMemcpyAsync(sd[0].counts_h, sd[0].counts, cnt_all, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+    } else {
+        for (DevSide &d : sd) {
+            hip_check(hipMemsetAsync(d.counts, 0, d.cnt_b + 256, s), "hipMemsetAsync");
+            hip_check(device_sort_nodes(d.x, d.M, d.scale, d.off, d.nbins, d.L.block, d.counts, d.flag, d.sort_tmp,
+                                        &d.sorted, s),
+                      "node sort");
+            if (!d.sidx.empty()) {
+                hip_check(hipMemcpyAsync(d.sidx_dev, d.sidx_h, d.sidx.size() * 8, hipMemcpyHostToDevice, s),
+                          "hipMemcpyAsync");
+                hip_check(device_gather(d.x, d.sidx_dev, (int64_t)d.sidx.size(), d.svals_dev, s), "density samples");
+                hip_check(hipMemcpyAsync(d.svals_h, d.svals_dev, d.sidx.size() * 8, hipMemcpyDeviceToHost, s),
+                          "hipMemcpyAsync");
+            }
+            hip_check(hipMemcpyAsync(d.counts_h, d.counts, d.cnt_b + 256, hipMemcpyDeviceToHost, s),
+                      "hipMemcpyAsync");
+        }
     }
     st = plan_tables(H);
     hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");

@@ -44,12 +44,12 @@ __device__ __forceinline__ double cell_floor(double t)
     return tr > t ? tr - 1.0 : tr;
 }
 
-// keys[k] = (block << bbits) | bin, vals[k] = k; flag bit 0: a node
+// keys[k] = keyor | (block << bbits) | bin, vals[k] = k; flag bit 0: a node
 // outside [-1/2, 1/2] (or NaN), bit 1: a bin outside [0, nbins) (then the key
 // uses bin 0 and the plan is refused)
 __global__ void k_node_keys(const double *__restrict__ x, int64_t M, double scale, int64_t off, int64_t nbins,
-                            int64_t block, int bbits, uint32_t *__restrict__ keys, int32_t *__restrict__ vals,
-                            int32_t *__restrict__ flag)
+                            int64_t block, int bbits, uint32_t keyor, uint32_t *__restrict__ keys,
+                            int32_t *__restrict__ vals, int32_t *__restrict__ flag)
 {
 #pragma clang fp contract(off)
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < M; k += (int64_t)gridDim.x * blockDim.x) {
@@ -67,7 +67,7 @@ __global__ void k_node_keys(const double *__restrict__ x, int64_t M, double scal
             bin = 0;
         }
         const int64_t blk = k / block;
-        keys[k] = ((uint32_t)blk << bbits) | (uint32_t)bin;
+        keys[k] = keyor | ((uint32_t)blk << bbits) | (uint32_t)bin;
         vals[k] = (int32_t)k;
     }
 }
@@ -92,6 +92,43 @@ __global__ void k_run_ends(const uint32_t *__restrict__ keys, int64_t M, int bbi
         const uint32_t k = keys[p];
         if (p == M - 1 || keys[p + 1] != k) {
             int32_t *c = &counts[(int64_t)(k >> bbits) * nbins + (k & ((1u << bbits) - 1u))];
+            *c = (int32_t)(p + 1) - *c;
+        }
+    }
+}
+
+// Both sides sorted together: side i's keys carry i at bit kb above its own
+// (block << bbits_i) | bin; the count of a run goes to that side's array.
+struct RunPair {
+    int32_t *counts[2];
+    int64_t nbins[2];
+    int bbits[2];
+    int kb;
+};
+
+__device__ __forceinline__ int32_t *pair_cell(const RunPair &R, uint32_t k)
+{
+    const bool one = (k >> R.kb) != 0u;
+    const uint32_t rest = k & ((1u << R.kb) - 1u);
+    const int bb = one ? R.bbits[1] : R.bbits[0];
+    int32_t *const c = one ? R.counts[1] : R.counts[0];
+    return c + (int64_t)(rest >> bb) * (one ? R.nbins[1] : R.nbins[0]) + (rest & ((1u << bb) - 1u));
+}
+
+__global__ void k_run_starts_pair(const uint32_t *__restrict__ keys, int64_t M, RunPair R)
+{
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < M; p += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t k = keys[p];
+        if (p == 0 || keys[p - 1] != k) *pair_cell(R, k) = (int32_t)p;
+    }
+}
+
+__global__ void k_run_ends_pair(const uint32_t *__restrict__ keys, int64_t M, RunPair R)
+{
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < M; p += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t k = keys[p];
+        if (p == M - 1 || keys[p + 1] != k) {
+            int32_t *c = pair_cell(R, k);
             *c = (int32_t)(p + 1) - *c;
         }
     }
@@ -328,7 +365,7 @@ hipError_t device_sort_nodes(const double *x, int64_t M, double scale, int64_t o
     p += al256((size_t)kRadix * ntiles * 4);
     uint32_t *tot = reinterpret_cast<uint32_t *>(p);
     hipLaunchKernelGGL(k_node_keys, dim3(grid_for(M, 256)), dim3(256), 0, s, x, M, scale, off, nbins, block, bbits,
-                       keys[0], vals[0], flag);
+                       0u, keys[0], vals[0], flag);
     int cur = 0;
     for (int shift = 0; shift < kbits; shift += 8) {
         hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)ntiles), dim3(kSortThreads), 0, s, keys[cur], M, shift,
@@ -341,6 +378,73 @@ hipError_t device_sort_nodes(const double *x, int64_t M, double scale, int64_t o
     hipLaunchKernelGGL(k_run_starts, dim3(grid_for(M, 256)), dim3(256), 0, s, keys[cur], M, bbits, nbins, counts);
     hipLaunchKernelGGL(k_run_ends, dim3(grid_for(M, 256)), dim3(256), 0, s, keys[cur], M, bbits, nbins, counts);
     *sorted_idx = vals[cur];
+    return hipGetLastError();
+}
+
+static int key_bits(int64_t M, int64_t nbins, int64_t block, int *bbits)
+{
+    const int64_t nblocks = (M + block - 1) / block;
+    *bbits = std::max(1, bit_width((uint64_t)(nbins - 1)));
+    return *bbits + bit_width((uint64_t)(nblocks - 1));
+}
+
+bool device_sort_pair_fits(const SortSide &a, const SortSide &b)
+{
+    int ba, bb;
+    const int kb = std::max(key_bits(a.M, a.nbins, a.block, &ba), key_bits(b.M, b.nbins, b.block, &bb));
+    return kb + 1 <= 32 && a.M + b.M < ((int64_t)1 << 31);
+}
+
+hipError_t device_sort_node_pair(const SortSide &a, const SortSide &b, void *tmp, int32_t **sorted_a,
+                                 int32_t **sorted_b, hipStream_t s)
+{
+    const SortSide *sd[2] = {&a, &b};
+    RunPair R{};
+    int kb = 0;
+    for (int i = 0; i < 2; ++i) {
+        kb = std::max(kb, key_bits(sd[i]->M, sd[i]->nbins, sd[i]->block, &R.bbits[i]));
+        R.counts[i] = sd[i]->counts;
+        R.nbins[i] = sd[i]->nbins;
+    }
+    R.kb = kb;
+    const int kbits = kb + 1;
+    const int64_t M = a.M + b.M;
+    const int64_t ntiles = (M + kTile - 1) / kTile;
+    unsigned char *p = static_cast<unsigned char *>(tmp);
+    uint32_t *keys[2];
+    int32_t *vals[2];
+    keys[0] = reinterpret_cast<uint32_t *>(p);
+    p += al256((size_t)M * 4);
+    keys[1] = reinterpret_cast<uint32_t *>(p);
+    p += al256((size_t)M * 4);
+    vals[0] = reinterpret_cast<int32_t *>(p);
+    p += al256((size_t)M * 4);
+    vals[1] = reinterpret_cast<int32_t *>(p);
+    p += al256((size_t)M * 4);
+    uint32_t *hist = reinterpret_cast<uint32_t *>(p);
+    p += al256((size_t)kRadix * ntiles * 4);
+    uint32_t *tot = reinterpret_cast<uint32_t *>(p);
+    int64_t at = 0;
+    for (int i = 0; i < 2; ++i) {
+        const SortSide &d = *sd[i];
+        if (d.M > 0)
+            hipLaunchKernelGGL(k_node_keys, dim3(grid_for(d.M, 256)), dim3(256), 0, s, d.x, d.M, d.scale, d.off, d.nbins,
+                               d.block, R.bbits[i], (uint32_t)i << kb, keys[0] + at, vals[0] + at, d.flag);
+        at += d.M;
+    }
+    int cur = 0;
+    for (int shift = 0; shift < kbits; shift += 8) {
+        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)ntiles), dim3(kSortThreads), 0, s, keys[cur], M, shift,
+                           ntiles, hist);
+        hipLaunchKernelGGL(k_radix_scan_rows, dim3(kRadix), dim3(kSortThreads), 0, s, hist, ntiles, tot);
+        hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)ntiles), dim3(kSortThreads), 0, s, keys[cur], vals[cur],
+                           M, shift, ntiles, hist, tot, keys[1 - cur], vals[1 - cur]);
+        cur = 1 - cur;
+    }
+    hipLaunchKernelGGL(k_run_starts_pair, dim3(grid_for(M, 256)), dim3(256), 0, s, keys[cur], M, R);
+    hipLaunchKernelGGL(k_run_ends_pair, dim3(grid_for(M, 256)), dim3(256), 0, s, keys[cur], M, R);
+    *sorted_a = vals[cur];
+    *sorted_b = vals[cur] + a.M;
     return hipGetLastError();
 }
 

@@ -41,4 +41,9 @@ hipError_t device_transpose_records(const PtRec *, const Item *, int64_t, int, P
     std::abort();
 }
 hipError_t device_gather(const double *, const int64_t *, int64_t, double *, hipStream_t) { std::abort(); }
+bool device_sort_pair_fits(const SortSide &, const SortSide &) { std::abort(); }
+hipError_t device_sort_node_pair(const SortSide &, const SortSide &, void *, int32_t **, int32_t **, hipStream_t)
+{
+    std::abort();
+}
 }  // namespace nnfft
