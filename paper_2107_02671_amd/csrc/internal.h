@@ -242,9 +242,11 @@ hipError_t device_sort_node_pair(const SortSide &a, const SortSide &b, void *tmp
 // FP32 (index, offset) records in sorted order.
 hipError_t device_sorted_records(const double *x, const int32_t *sorted_idx, int64_t M, double scale, bool fp32,
                                  int32_t *perm, double *frac64, PtRec *rec32, hipStream_t s);
-// FP32 records in per-slot transposed blocks from the sorted records.
-hipError_t device_transpose_records(const PtRec *rec32, const Item *launch_items, int64_t nslot, int rows,
-                                    PtRec *trec32, hipStream_t s);
+// The FP32 records in per-slot transposed blocks directly from the sorted
+// indices: point q of item t of launch slot g at (g rows + q) 64 + t, rows
+// past an item's end repeating its last record, empty items zero.
+hipError_t device_transposed_records(const double *x, const int32_t *sorted_idx, double scale, const Item *launch_items,
+                                     int64_t nslot, int rows, PtRec *trec32, hipStream_t s);
 hipError_t device_gather(const double *x, const int64_t *idx, int64_t n, double *out, hipStream_t s);
 
 // Per-exec working memory of a plan (window planes and overflow windows, the

@@ -1624,20 +1624,23 @@ nnfft_status plan_create(const HostPlan &H, const DevMem &mem, hipStream_t s, nn
         const size_t up = dev ? dev_start : upload_end;   // device-written records follow dev_start
         if (stage.size() < up) stage.resize(up);
         hip_check(hipMemcpyAsync(base, stage.data(), up, hipMemcpyHostToDevice, s), "hipMemcpyAsync");
+        // plane cells that no window covers are read as zeros by every exec;
+        // the planes follow the device-written records (layout_plan), so one
+        // fill clears both where the records are written on the device
+        const size_t part_off = (size_t)(static_cast<const char *>(pl->desc.sp.partial) - static_cast<char *>(base));
+        const size_t part_end = part_off + (size_t)H.sp.part_cells * 16;
         if (dev) {
-            // the gaps between the device-written arrays (alignment) read as zeros, as in the host image
-            hip_check(hipMemsetAsync(static_cast<char *>(base) + dev_start, 0, upload_end - dev_start, s),
+            // the gaps between the device-written arrays (alignment) read as
+            // zeros, as in the host image; the record kernels fill the rest
+            hip_check(hipMemsetAsync(static_cast<char *>(base) + dev_start, 0, part_end - dev_start, s),
                       "hipMemsetAsync");
             const PlanDev &D = pl->desc;
             auto side = [&](const SideHost &S, const DevSideRecords &R, const Item *items, const PtRec *rec32,
                             const int32_t *perm, const double *frac) {
                 if (!S.dev) return;
                 if (H.fp32) {
-                    PtRec *tmp = static_cast<PtRec *>(R.rec_tmp);
-                    hip_check(device_sorted_records(R.x, R.sorted, S.npts, R.scale, true, nullptr, nullptr, tmp, s),
-                              "sorted records");
-                    hip_check(device_transpose_records(tmp, items, (int64_t)S.launch.size(), S.rows,
-                                                       const_cast<PtRec *>(rec32), s),
+                    hip_check(device_transposed_records(R.x, R.sorted, R.scale, items, (int64_t)S.launch.size(),
+                                                        S.rows, const_cast<PtRec *>(rec32), s),
                               "transposed records");
                 } else {
                     hip_check(device_sorted_records(R.x, R.sorted, S.npts, R.scale, false, const_cast<int32_t *>(perm),
@@ -1650,8 +1653,7 @@ nnfft_status plan_create(const HostPlan &H, const DevMem &mem, hipStream_t s, nn
         }
         hip_check(hipMemcpyAsync(pl->ddesc, &pl->desc, sizeof(PlanDev), hipMemcpyHostToDevice, s),
                   "hipMemcpyAsync");
-        // plane cells that no window covers are read as zeros by every exec
-        hip_check(hipMemsetAsync(pl->desc.sp.partial, 0, (size_t)H.sp.part_cells * 16, s), "hipMemsetAsync");
+        if (!dev) hip_check(hipMemsetAsync(pl->desc.sp.partial, 0, (size_t)H.sp.part_cells * 16, s), "hipMemsetAsync");
         hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
     } catch (const HipError &e) {
         (void)hipStreamSynchronize(s);   // nothing queued may still write into the released block
@@ -1821,7 +1823,7 @@ nnfft_status plan_device_nodes(HostPlan &H, DevRecords &R, NodePrepScratch &T, i
         unsigned char *pd = static_cast<unsigned char *>(T.dev), *ph = static_cast<unsigned char *>(T.pin);
         size_t o = 0;
         for (DevSide &d : sd) {
-            d.sort_tmp = pd;   // shared; each side's records use it in turn (plan_create)
+            d.sort_tmp = pd;   // shared by both sides' sort
             d.counts = reinterpret_cast<int32_t *>(pd + tmp_b + o);
             d.counts_h = reinterpret_cast<int32_t *>(ph + o);
             o += d.cnt_b;
@@ -1936,8 +1938,8 @@ nnfft_status plan_device_nodes(HostPlan &H, DevRecords &R, NodePrepScratch &T, i
         return fail(NNFFT_ERR_ARG, err);
     st = plan_finish(H);
     if (st != NNFFT_OK) return st;
-    R.sp = DevSideRecords{v, sd[0].sorted, sd[0].scale, sd[0].sort_tmp};
-    R.ip = DevSideRecords{x, sd[1].sorted, sd[1].scale, sd[1].sort_tmp};
+    R.sp = DevSideRecords{v, sd[0].sorted, sd[0].scale};
+    R.ip = DevSideRecords{x, sd[1].sorted, sd[1].scale};
     return NNFFT_OK;
 }
 

@@ -192,13 +192,11 @@ nnfft_status nfft_plan_host(HostPlan &H, int64_t N, int64_t M, double sigma, int
                             const std::vector<double> &x);
 
 // The records of a side whose nodes were sorted on the device: the nodes,
-// the sorted caller indices, the grid scale, and device memory of at least
-// 8 M bytes for the FP32 sorted records.
+// the sorted caller indices and the grid scale.
 struct DevSideRecords {
     const double *x = nullptr;
     const int32_t *sorted = nullptr;
     double scale = 0.0;
-    void *rec_tmp = nullptr;
 };
 struct DevRecords {
     DevSideRecords sp, ip;

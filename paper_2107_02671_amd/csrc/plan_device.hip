@@ -257,36 +257,51 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t *
 }
 
 // sorted records: p-th point of the sorted order is node k = idx[p]
+// the FP64 cell offset of node k: the product and the difference rounded
+// separately, as on the host (a fused multiply-subtract would give another
+// offset)
+__device__ __forceinline__ double node_offset(const double *__restrict__ x, int32_t k, double scale)
+{
+#pragma clang fp contract(off)
+    const double t = scale * x[k];
+    return t - cell_floor(t);
+}
+
+// the FP32 record of sorted point p
+__device__ __forceinline__ PtRec node_rec32(const double *__restrict__ x, const int32_t *__restrict__ idx, int64_t p,
+                                            double scale)
+{
+    const int32_t k = idx[p];
+    float f = (float)node_offset(x, k, scale);
+    if (!(f < 1.0f)) f = 0.99999994f;   // keep the offset inside [0, 1)
+    PtRec r;
+    r.perm = k;
+    r.frac = f;
+    return r;
+}
+
 __global__ void k_sorted_records(const double *__restrict__ x, const int32_t *__restrict__ idx, int64_t M,
                                  double scale, int fp32, int32_t *__restrict__ perm, double *__restrict__ frac64,
                                  PtRec *__restrict__ rec32)
 {
-    // the product and the difference rounded separately, as on the host (a
-    // fused multiply-subtract would give another offset in FP64)
-#pragma clang fp contract(off)
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < M; p += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t k = idx[p];
-        const double t = scale * x[k];
-        const double fr = t - cell_floor(t);
         if (fp32) {
-            float f = (float)fr;
-            if (!(f < 1.0f)) f = 0.99999994f;   // keep the offset inside [0, 1)
-            PtRec r;
-            r.perm = k;
-            r.frac = f;
-            rec32[p] = r;
+            rec32[p] = node_rec32(x, idx, p, scale);
         } else {
+            const int32_t k = idx[p];
             perm[p] = k;
-            frac64[p] = fr;
+            frac64[p] = node_offset(x, k, scale);
         }
     }
 }
 
-// FP32 records in per-slot transposed blocks: point q of item t of slot g at
-// (g rows + q) 64 + t; rows past an item's end repeat its last record; empty
-// items hold zeros
-__global__ void k_transpose_records(const PtRec *__restrict__ rec, const Item *__restrict__ items, int64_t nslot,
-                                    int rows, PtRec *__restrict__ out)
+// FP32 records in per-slot transposed blocks, formed directly from the
+// sorted indices: point q of item t of slot g at (g rows + q) 64 + t holds
+// the record of its sorted point; rows past an item's end repeat its last
+// record; empty items hold zeros
+__global__ void k_transposed_records(const double *__restrict__ x, const int32_t *__restrict__ idx, double scale,
+                                     const Item *__restrict__ items, int64_t nslot, int rows,
+                                     PtRec *__restrict__ out)
 {
     const int64_t total = nslot * rows * kItemsPerWg;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
@@ -298,7 +313,7 @@ __global__ void k_transpose_records(const PtRec *__restrict__ rec, const Item *_
         PtRec r;
         r.perm = 0;
         r.frac = 0.f;
-        if (it.n > 0) r = rec[it.p0 + std::min<int64_t>(q, it.n - 1)];
+        if (it.n > 0) r = node_rec32(x, idx, it.p0 + std::min<int64_t>(q, it.n - 1), scale);
         out[i] = r;
     }
 }
@@ -456,12 +471,12 @@ hipError_t device_sorted_records(const double *x, const int32_t *sorted_idx, int
     return hipGetLastError();
 }
 
-hipError_t device_transpose_records(const PtRec *rec32, const Item *launch_items, int64_t nslot, int rows,
-                                    PtRec *trec32, hipStream_t s)
+hipError_t device_transposed_records(const double *x, const int32_t *sorted_idx, double scale, const Item *launch_items,
+                                     int64_t nslot, int rows, PtRec *trec32, hipStream_t s)
 {
     const int64_t total = nslot * rows * kItemsPerWg;
-    hipLaunchKernelGGL(k_transpose_records, dim3(grid_for(total, 256)), dim3(256), 0, s, rec32, launch_items, nslot,
-                       rows, trec32);
+    hipLaunchKernelGGL(k_transposed_records, dim3(grid_for(total, 256)), dim3(256), 0, s, x, sorted_idx, scale,
+                       launch_items, nslot, rows, trec32);
     return hipGetLastError();
 }
 

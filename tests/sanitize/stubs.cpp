@@ -36,11 +36,12 @@ hipError_t device_sorted_records(const double *, const int32_t *, int64_t, doubl
 {
     std::abort();
 }
-hipError_t device_transpose_records(const PtRec *, const Item *, int64_t, int, PtRec *, hipStream_t)
+hipError_t device_gather(const double *, const int64_t *, int64_t, double *, hipStream_t) { std::abort(); }
+hipError_t device_transposed_records(const double *, const int32_t *, double, const Item *, int64_t, int, PtRec *,
+                                     hipStream_t)
 {
     std::abort();
 }
-hipError_t device_gather(const double *, const int64_t *, int64_t, double *, hipStream_t) { std::abort(); }
 bool device_sort_pair_fits(const SortSide &, const SortSide &) { std::abort(); }
 hipError_t device_sort_node_pair(const SortSide &, const SortSide &, void *, int32_t **, int32_t **, hipStream_t)
 {
