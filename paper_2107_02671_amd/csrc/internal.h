@@ -248,6 +248,24 @@ hipError_t device_sorted_records(const double *x, const int32_t *sorted_idx, int
 hipError_t device_transposed_records(const double *x, const int32_t *sorted_idx, double scale, const Item *launch_items,
                                      int64_t nslot, int rows, PtRec *trec32, hipStream_t s);
 hipError_t device_gather(const double *x, const int64_t *idx, int64_t n, double *out, hipStream_t s);
+// Both sides of a plan in one launch each: the records (FP32: transposed
+// slot blocks into trec; FP64: perm and frac in sorted order) and the
+// density samples.
+struct RecSide {
+    const double *x;
+    const int32_t *idx;
+    double scale;
+    int64_t M;            // FP64: points
+    const Item *items;    // FP32: launch slots' items
+    int64_t nslot;
+    int32_t rows;
+    PtRec *trec;
+    int32_t *perm;
+    double *frac;
+};
+hipError_t device_records_pair(bool fp32, const RecSide &a, const RecSide &b, hipStream_t s);
+hipError_t device_gather_pair(const double *x0, const int64_t *idx0, int64_t n0, double *out0, const double *x1,
+                              const int64_t *idx1, int64_t n1, double *out1, hipStream_t s);
 
 // Per-exec working memory of a plan (window planes and overflow windows, the
 // four-step intermediate, the consumed FFT outputs), in bytes; the planes

@@ -1635,21 +1635,35 @@ nnfft_status plan_create(const HostPlan &H, const DevMem &mem, hipStream_t s, nn
             hip_check(hipMemsetAsync(static_cast<char *>(base) + dev_start, 0, part_end - dev_start, s),
                       "hipMemsetAsync");
             const PlanDev &D = pl->desc;
-            auto side = [&](const SideHost &S, const DevSideRecords &R, const Item *items, const PtRec *rec32,
-                            const int32_t *perm, const double *frac) {
-                if (!S.dev) return;
-                if (H.fp32) {
-                    hip_check(device_transposed_records(R.x, R.sorted, R.scale, items, (int64_t)S.launch.size(),
-                                                        S.rows, const_cast<PtRec *>(rec32), s),
-                              "transposed records");
-                } else {
-                    hip_check(device_sorted_records(R.x, R.sorted, S.npts, R.scale, false, const_cast<int32_t *>(perm),
-                                                    const_cast<double *>(frac), nullptr, s),
-                              "sorted records");
-                }
+            auto rec_side = [&](const SideHost &S, const DevSideRecords &R, const Item *items, const PtRec *rec32,
+                                const int32_t *perm, const double *frac) {
+                return RecSide{R.x, R.sorted, R.scale, S.npts, items, (int64_t)S.launch.size(), S.rows,
+                               const_cast<PtRec *>(rec32), const_cast<int32_t *>(perm), const_cast<double *>(frac)};
             };
-            side(H.sp, dev->sp, D.sp.items, D.sp.rec32, D.sp.perm, D.sp.frac64);
-            side(H.ip, dev->ip, D.ip.items, D.ip.rec32, D.ip.perm, D.ip.frac64);
+            if (H.sp.dev && H.ip.dev) {   // both sides in one launch
+                hip_check(device_records_pair(H.fp32, rec_side(H.sp, dev->sp, D.sp.items, D.sp.rec32, D.sp.perm,
+                                                               D.sp.frac64),
+                                              rec_side(H.ip, dev->ip, D.ip.items, D.ip.rec32, D.ip.perm, D.ip.frac64),
+                                              s),
+                          "records");
+            } else {
+                auto side = [&](const SideHost &S, const DevSideRecords &R, const Item *items, const PtRec *rec32,
+                                const int32_t *perm, const double *frac) {
+                    if (!S.dev) return;
+                    if (H.fp32) {
+                        hip_check(device_transposed_records(R.x, R.sorted, R.scale, items, (int64_t)S.launch.size(),
+                                                            S.rows, const_cast<PtRec *>(rec32), s),
+                                  "transposed records");
+                    } else {
+                        hip_check(device_sorted_records(R.x, R.sorted, S.npts, R.scale, false,
+                                                        const_cast<int32_t *>(perm), const_cast<double *>(frac),
+                                                        nullptr, s),
+                                  "sorted records");
+                    }
+                };
+                side(H.sp, dev->sp, D.sp.items, D.sp.rec32, D.sp.perm, D.sp.frac64);
+                side(H.ip, dev->ip, D.ip.items, D.ip.rec32, D.ip.perm, D.ip.frac64);
+            }
         }
         hip_check(hipMemcpyAsync(pl->ddesc, &pl->desc, sizeof(PlanDev), hipMemcpyHostToDevice, s),
                   "hipMemcpyAsync");
@@ -1877,10 +1891,9 @@ nnfft_status plan_device_nodes(HostPlan &H, DevRecords &R, NodePrepScratch &T, i
         if (!sd[0].sidx.empty() || !sd[1].sidx.empty()) {
             hip_check(hipMemcpyAsync(sd[0].sidx_dev, sd[0].sidx_h, smp_all, hipMemcpyHostToDevice, s),
                       "hipMemcpyAsync");
-            for (DevSide &d : sd)
-                if (!d.sidx.empty())
-                    hip_check(device_gather(d.x, d.sidx_dev, (int64_t)d.sidx.size(), d.svals_dev, s),
-                              "density samples");
+            hip_check(device_gather_pair(sd[0].x, sd[0].sidx_dev, (int64_t)sd[0].sidx.size(), sd[0].svals_dev, sd[1].x,
+                                         sd[1].sidx_dev, (int64_t)sd[1].sidx.size(), sd[1].svals_dev, s),
+                      "density samples");
             hip_check(hipMemcpyAsync(sd[0].svals_h, sd[0].svals_dev, smp_all, hipMemcpyDeviceToHost, s),
                       "hipMemcpyAsync");
         }

@@ -47,28 +47,57 @@ __device__ __forceinline__ double cell_floor(double t)
 // keys[k] = keyor | (block << bbits) | bin, vals[k] = k; flag bit 0: a node
 // outside [-1/2, 1/2] (or NaN), bit 1: a bin outside [0, nbins) (then the key
 // uses bin 0 and the plan is refused)
+__device__ __forceinline__ void node_key(const double *__restrict__ x, int64_t k, double scale, int64_t off,
+                                         int64_t nbins, int64_t block, int bbits, uint32_t keyor,
+                                         uint32_t *__restrict__ key, int32_t *__restrict__ val,
+                                         int32_t *__restrict__ flag)
+{
+#pragma clang fp contract(off)
+    const double v = x[k];
+    int fl = 0;
+    if (!(fabs(v) <= 0.5)) fl |= 1;
+    const double t = scale * v;
+    int64_t bin = 0;
+    if (fl == 0) {
+        bin = (int64_t)cell_floor(t) + off;
+        if (bin < 0 || bin >= nbins) fl |= 2;
+    }
+    if (fl != 0) {
+        atomicOr(flag, fl);
+        bin = 0;
+    }
+    const int64_t blk = k / block;
+    *key = keyor | ((uint32_t)blk << bbits) | (uint32_t)bin;
+    *val = (int32_t)k;
+}
+
 __global__ void k_node_keys(const double *__restrict__ x, int64_t M, double scale, int64_t off, int64_t nbins,
                             int64_t block, int bbits, uint32_t keyor, uint32_t *__restrict__ keys,
                             int32_t *__restrict__ vals, int32_t *__restrict__ flag)
 {
-#pragma clang fp contract(off)
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < M; k += (int64_t)gridDim.x * blockDim.x) {
-        const double v = x[k];
-        int fl = 0;
-        if (!(fabs(v) <= 0.5)) fl |= 1;
-        const double t = scale * v;
-        int64_t bin = 0;
-        if (fl == 0) {
-            bin = (int64_t)cell_floor(t) + off;
-            if (bin < 0 || bin >= nbins) fl |= 2;
-        }
-        if (fl != 0) {
-            atomicOr(flag, fl);
-            bin = 0;
-        }
-        const int64_t blk = k / block;
-        keys[k] = keyor | ((uint32_t)blk << bbits) | (uint32_t)bin;
-        vals[k] = (int32_t)k;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < M; k += (int64_t)gridDim.x * blockDim.x)
+        node_key(x, k, scale, off, nbins, block, bbits, keyor, keys + k, vals + k, flag);
+}
+
+// the keys of both sides of a plan in one launch: side 1's at [a.M, a.M + b.M)
+struct KeySide {
+    const double *x;
+    int64_t M;
+    double scale;
+    int64_t off, nbins, block;
+    int bbits;
+    uint32_t keyor;
+    int32_t *flag;
+};
+
+__global__ void k_node_keys_pair(KeySide a, KeySide b, uint32_t *__restrict__ keys, int32_t *__restrict__ vals)
+{
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < a.M + b.M;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        if (p < a.M)
+            node_key(a.x, p, a.scale, a.off, a.nbins, a.block, a.bbits, a.keyor, keys + p, vals + p, a.flag);
+        else
+            node_key(b.x, p - a.M, b.scale, b.off, b.nbins, b.block, b.bbits, b.keyor, keys + p, vals + p, b.flag);
     }
 }
 
@@ -115,21 +144,18 @@ __device__ __forceinline__ int32_t *pair_cell(const RunPair &R, uint32_t k)
     return c + (int64_t)(rest >> bb) * (one ? R.nbins[1] : R.nbins[0]) + (rest & ((1u << bb) - 1u));
 }
 
-__global__ void k_run_starts_pair(const uint32_t *__restrict__ keys, int64_t M, RunPair R)
+// the run lengths in one pass: the run's first position subtracts its
+// index, its last adds its index + 1 (integer adds: the order of the two
+// does not matter; counts zeroed by the caller)
+__global__ void k_run_counts_pair(const uint32_t *__restrict__ keys, int64_t M, RunPair R)
 {
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < M; p += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t k = keys[p];
-        if (p == 0 || keys[p - 1] != k) *pair_cell(R, k) = (int32_t)p;
-    }
-}
-
-__global__ void k_run_ends_pair(const uint32_t *__restrict__ keys, int64_t M, RunPair R)
-{
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < M; p += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t k = keys[p];
-        if (p == M - 1 || keys[p + 1] != k) {
+        const bool first = p == 0 || keys[p - 1] != k, last = p == M - 1 || keys[p + 1] != k;
+        if (first || last) {
             int32_t *c = pair_cell(R, k);
-            *c = (int32_t)(p + 1) - *c;
+            if (first) atomicAdd(c, -(int32_t)p);
+            if (last) atomicAdd(c, (int32_t)(p + 1));
         }
     }
 }
@@ -299,22 +325,59 @@ __global__ void k_sorted_records(const double *__restrict__ x, const int32_t *__
 // sorted indices: point q of item t of slot g at (g rows + q) 64 + t holds
 // the record of its sorted point; rows past an item's end repeat its last
 // record; empty items hold zeros
+__device__ __forceinline__ void transposed_record(const double *__restrict__ x, const int32_t *__restrict__ idx,
+                                                  double scale, const Item *__restrict__ items, int rows, int64_t i,
+                                                  PtRec *__restrict__ out)
+{
+    const int t = (int)(i % kItemsPerWg);
+    const int64_t gq = i / kItemsPerWg;
+    const int64_t g = gq / rows, q = gq % rows;
+    const Item it = items[g * kItemsPerWg + t];
+    PtRec r;
+    r.perm = 0;
+    r.frac = 0.f;
+    if (it.n > 0) r = node_rec32(x, idx, it.p0 + std::min<int64_t>(q, it.n - 1), scale);
+    out[i] = r;
+}
+
 __global__ void k_transposed_records(const double *__restrict__ x, const int32_t *__restrict__ idx, double scale,
                                      const Item *__restrict__ items, int64_t nslot, int rows,
                                      PtRec *__restrict__ out)
 {
     const int64_t total = nslot * rows * kItemsPerWg;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x)
+        transposed_record(x, idx, scale, items, rows, i, out);
+}
+
+// both sides' records in one launch (side b's entries after side a's)
+__global__ void k_records_pair(RecSide a, RecSide b, int fp32)
+{
+    const int64_t na = fp32 ? a.nslot * a.rows * kItemsPerWg : a.M;
+    const int64_t nb = fp32 ? b.nslot * b.rows * kItemsPerWg : b.M;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < na + nb;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const int t = (int)(i % kItemsPerWg);
-        const int64_t gq = i / kItemsPerWg;
-        const int64_t g = gq / rows, q = gq % rows;
-        const Item it = items[g * kItemsPerWg + t];
-        PtRec r;
-        r.perm = 0;
-        r.frac = 0.f;
-        if (it.n > 0) r = node_rec32(x, idx, it.p0 + std::min<int64_t>(q, it.n - 1), scale);
-        out[i] = r;
+        const bool second = i >= na;
+        const RecSide &S = second ? b : a;
+        const int64_t j = second ? i - na : i;
+        if (fp32) {
+            transposed_record(S.x, S.idx, S.scale, S.items, S.rows, j, S.trec);
+        } else {
+            const int32_t k = S.idx[j];
+            S.perm[j] = k;
+            S.frac[j] = node_offset(S.x, k, S.scale);
+        }
+    }
+}
+
+__global__ void k_gather_pair(const double *__restrict__ x0, const int64_t *__restrict__ idx0, int64_t n0,
+                              double *__restrict__ out0, const double *__restrict__ x1,
+                              const int64_t *__restrict__ idx1, int64_t n1, double *__restrict__ out1)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n0 + n1;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        if (i < n0) out0[i] = x0[idx0[i]];
+        else out1[i - n0] = x1[idx1[i - n0]];
     }
 }
 
@@ -439,14 +502,12 @@ hipError_t device_sort_node_pair(const SortSide &a, const SortSide &b, void *tmp
     uint32_t *hist = reinterpret_cast<uint32_t *>(p);
     p += al256((size_t)kRadix * ntiles * 4);
     uint32_t *tot = reinterpret_cast<uint32_t *>(p);
-    int64_t at = 0;
+    KeySide ks[2];
     for (int i = 0; i < 2; ++i) {
         const SortSide &d = *sd[i];
-        if (d.M > 0)
-            hipLaunchKernelGGL(k_node_keys, dim3(grid_for(d.M, 256)), dim3(256), 0, s, d.x, d.M, d.scale, d.off, d.nbins,
-                               d.block, R.bbits[i], (uint32_t)i << kb, keys[0] + at, vals[0] + at, d.flag);
-        at += d.M;
+        ks[i] = KeySide{d.x, d.M, d.scale, d.off, d.nbins, d.block, R.bbits[i], (uint32_t)i << kb, d.flag};
     }
+    hipLaunchKernelGGL(k_node_keys_pair, dim3(grid_for(M, 256)), dim3(256), 0, s, ks[0], ks[1], keys[0], vals[0]);
     int cur = 0;
     for (int shift = 0; shift < kbits; shift += 8) {
         hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)ntiles), dim3(kSortThreads), 0, s, keys[cur], M, shift,
@@ -456,8 +517,7 @@ hipError_t device_sort_node_pair(const SortSide &a, const SortSide &b, void *tmp
                            M, shift, ntiles, hist, tot, keys[1 - cur], vals[1 - cur]);
         cur = 1 - cur;
     }
-    hipLaunchKernelGGL(k_run_starts_pair, dim3(grid_for(M, 256)), dim3(256), 0, s, keys[cur], M, R);
-    hipLaunchKernelGGL(k_run_ends_pair, dim3(grid_for(M, 256)), dim3(256), 0, s, keys[cur], M, R);
+    hipLaunchKernelGGL(k_run_counts_pair, dim3(grid_for(M, 256)), dim3(256), 0, s, keys[cur], M, R);
     *sorted_a = vals[cur];
     *sorted_b = vals[cur] + a.M;
     return hipGetLastError();
@@ -477,6 +537,21 @@ hipError_t device_transposed_records(const double *x, const int32_t *sorted_idx,
     const int64_t total = nslot * rows * kItemsPerWg;
     hipLaunchKernelGGL(k_transposed_records, dim3(grid_for(total, 256)), dim3(256), 0, s, x, sorted_idx, scale,
                        launch_items, nslot, rows, trec32);
+    return hipGetLastError();
+}
+
+hipError_t device_records_pair(bool fp32, const RecSide &a, const RecSide &b, hipStream_t s)
+{
+    const int64_t n = fp32 ? (a.nslot * a.rows + b.nslot * b.rows) * kItemsPerWg : a.M + b.M;
+    hipLaunchKernelGGL(k_records_pair, dim3(grid_for(n, 256)), dim3(256), 0, s, a, b, fp32 ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t device_gather_pair(const double *x0, const int64_t *idx0, int64_t n0, double *out0, const double *x1,
+                              const int64_t *idx1, int64_t n1, double *out1, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gather_pair, dim3(grid_for(n0 + n1, 256)), dim3(256), 0, s, x0, idx0, n0, out0, x1, idx1, n1,
+                       out1);
     return hipGetLastError();
 }
 

@@ -43,6 +43,12 @@ hipError_t device_transposed_records(const double *, const int32_t *, double, co
     std::abort();
 }
 bool device_sort_pair_fits(const SortSide &, const SortSide &) { std::abort(); }
+hipError_t device_records_pair(bool, const RecSide &, const RecSide &, hipStream_t) { std::abort(); }
+hipError_t device_gather_pair(const double *, const int64_t *, int64_t, double *, const double *, const int64_t *,
+                              int64_t, double *, hipStream_t)
+{
+    std::abort();
+}
 hipError_t device_sort_node_pair(const SortSide &, const SortSide &, void *, int32_t **, int32_t **, hipStream_t)
 {
     std::abort();
