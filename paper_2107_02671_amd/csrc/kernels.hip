@@ -323,11 +323,18 @@ __device__ __forceinline__ int wave_row(int row0, int j, int rpw, int rows)
 // LDS arrays are indexed [moment or tap][item or bin] so that the lanes of a
 // wave (consecutive items or bins) touch consecutive 8-byte words: no bank
 // conflicts in any phase.
-template <int TM>   // TM >= 2 m
+template <int TM>   // TM >= 2 m, a multiple of kWaves32
+struct Spread32Cells {
+    static_assert(TM % kWaves32 == 0, "taps are split evenly over the waves");
+    cx<float> sbin[TM][kItemsPerWg];               // 2m taps of each bin (B2, C)
+    double cre[kWaves32][kItemsPerWg + TM];        // wave w's FP64 sum of taps r = w mod 4 of each cell (C)
+    double cim[kWaves32][kItemsPerWg + TM];
+};
+template <int TM>
 struct Spread32Lds {
     union {
         cx<float> mom[kWaves32][kDeg + 1][kItemsPerWg];   // each wave's share of the item moments (A, B1)
-        cx<float> sbin[TM][kItemsPerWg];                  // 2m taps of each bin (B2, C)
+        Spread32Cells<TM> cs;                             // (B2, C)
     };
     cx<float> bmom[kDeg + 1][kItemsPerWg];                // moments of each bin
     float C[TM * (kDeg + 1)];                         // tap coefficients
@@ -562,31 +569,34 @@ __device__ __forceinline__ void spread32_cells(const SpreadArgs &A, const Chunk 
                 ar = fmaf(c[k], Mr[k], ar);
                 ai = fmaf(c[k], Mi[k], ai);
             }
-            L.sbin[r0][t] = cxmk(ar, ai);
+            L.cs.sbin[r0][t] = cxmk(ar, ai);
         }
     }
     lds_barrier();
-    const int W = ch.nbin + tm - 1;
-    float4 *part = reinterpret_cast<float4 *>(A.partial);
-    for (int wc = threadIdx.x; wc < W; wc += blockDim.x) {
-        cx<float> v[TM];
-#pragma unroll
-        for (int rr = 0; rr < TM; ++rr) {
-            const int b = min(max(wc - rr, 0), ch.nbin - 1);
-            v[rr] = L.sbin[rr][b];
-        }
-        // the at most 2m taps of the cell added in FP64 (exact for FP32
-        // terms of similar size, far below FP32 rounding otherwise), then
-        // split into the (hi, lo) FP32 pair the merge adds with two-sum
+    // C1: wave w adds taps r = w, w + 4, ... of every cell in FP64
+    const int W = ch.nbin + tm - 1;   // <= kItemsPerWg + TM - 1
+    for (int wc = t; wc < W; wc += kItemsPerWg) {
         double sr = 0.0, si = 0.0;
 #pragma unroll
-        for (int rr = 0; rr < TM; ++rr) {
-            const int b = wc - rr;
+        for (int j = 0; j < TM / kWaves32; ++j) {
+            const int rr = w + kWaves32 * j, b = wc - rr;
+            const cx<float> v = L.cs.sbin[rr][min(max(b, 0), ch.nbin - 1)];
             if (rr < tm && b >= 0 && b < ch.nbin) {
-                sr += (double)v[rr].re;
-                si += (double)v[rr].im;
+                sr += (double)v.re;
+                si += (double)v.im;
             }
         }
+        L.cs.cre[w][wc] = sr;
+        L.cs.cim[w][wc] = si;
+    }
+    lds_barrier();
+    // C2: the cell's four partial sums added in FP64 (exact for FP32 taps of
+    // similar size, far below FP32 rounding otherwise), then split into the
+    // (hi, lo) FP32 pair the merge adds with two-sum
+    float4 *part = reinterpret_cast<float4 *>(A.partial);
+    for (int wc = threadIdx.x; wc < W; wc += blockDim.x) {
+        const double sr = ((L.cs.cre[0][wc] + L.cs.cre[1][wc]) + L.cs.cre[2][wc]) + L.cs.cre[3][wc];
+        const double si = ((L.cs.cim[0][wc] + L.cs.cim[1][wc]) + L.cs.cim[2][wc]) + L.cs.cim[3][wc];
         const float hr = (float)sr, hi = (float)si;
         part[window_index(ch, wc, m, A.slotT, A.slotP)] =
             make_float4(hr, hi, (float)(sr - (double)hr), (float)(si - (double)hi));
